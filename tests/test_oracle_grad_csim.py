@@ -1,0 +1,213 @@
+"""Pins of the oracle's gradients, conditional simulation and convergence behaviour (CPU only)."""
+import os
+
+import numpy as np
+import pytest
+
+from oracle import csim, philox
+from oracle.exact import ExactKriging, gp_draw
+from oracle.grad import corr_image_direct, dlag_direct, dlag_entry, grad_coef, loss_masked_square
+from oracle.matern import Matern
+from oracle.rapid import (Grid, RapidPredictor, conv_lag_direct, grid_unit, lag_quadrant, fill_distance_of_grid)
+
+GOLD = os.path.join(os.path.dirname(__file__), "golden")
+
+
+def _problem(seed=0, m1=8, m2=10, L=2, n=12, tau2=1e-2):
+    rng = np.random.default_rng(seed)
+    g = Grid(m1, m2, 0.0, 0.0, 1.0 / (m1 - 1), 1.2 / (m2 - 1), L)
+    k = Matern(1.0, 0.35, 1.5, tau2)
+    s = np.stack([rng.uniform(0, 1, n), rng.uniform(0, 1.2, n)], 1)
+    return g, k, s, rng
+
+
+def _forward(g, rp, ek, lag, y):
+    return conv_lag_direct(g, lag, rp.cstar(ek.coef(y)))
+
+
+def test_adjoint_dot_product_and_finite_differences():
+    g, k, s, rng = _problem()
+    ek = ExactKriging(s, k)
+    rp = RapidPredictor(g, k, s)
+    lag = lag_quadrant(g, k)
+    y = rng.standard_normal(len(s))
+    mask = rng.uniform(0, 1, (g.m1, g.m2))
+    yhat = _forward(g, rp, ek, lag, y)
+    gup = 2 * mask * yhat                                    # d loss / d yhat for loss = sum m yhat^2
+    corr = corr_image_direct(g, lag, gup)
+    dalpha = grad_coef(rp.A, corr)
+    dy = ek.coef(dalpha)                                     # M symmetric
+    dlag = dlag_direct(g, gup, rp.cstar(ek.coef(y)))
+    # dot-product test of the linear map y -> yhat
+    v = rng.standard_normal(len(s))
+    w = rng.standard_normal((g.m1, g.m2))
+    lhs = np.sum(w * _forward(g, rp, ek, lag, v))
+    rhs = np.dot(v, ek.coef(grad_coef(rp.A, corr_image_direct(g, lag, w))))
+    assert abs(lhs - rhs) < 1e-12 * abs(lhs)
+    # central finite differences: the loss is quadratic in y and in lag separately,
+    # so the central difference is exact up to rounding
+    h = 1e-3
+    L0 = lambda yy, ll: loss_masked_square(_forward(g, rp, ek, ll, yy), mask)
+    for i in (0, 5, 11):
+        e = np.zeros(len(s))
+        e[i] = h
+        fd = (L0(y + e, lag) - L0(y - e, lag)) / (2 * h)
+        assert abs(fd - dy[i]) < 1e-8 * max(1.0, abs(dy[i]))
+    for (u, w_) in ((0, 0), (1, 3), (4, 0), (7, 9), (9, 11)):
+        E = np.zeros_like(lag)
+        E[u, w_] = h
+        fd = (L0(y, lag + E) - L0(y, lag - E)) / (2 * h)
+        assert abs(fd - dlag[u, w_]) < 1e-8 * max(1.0, abs(fd))
+    # single-entry formula agrees with the full fold
+    cimg = rp.cstar(ek.coef(y))
+    for (u, w_) in ((0, 0), (2, 0), (0, 5), (3, 4)):
+        assert np.isclose(dlag_entry(g, gup, cimg, u, w_), dlag[u, w_], rtol=1e-12, atol=1e-12)
+
+
+def test_exact_gradient_is_rapid_gradient_on_nodes():
+    # with sites on grid nodes A is a selection, so the rapid gradient equals
+    # the exact one M^{-1} K(obs, grid) g
+    g = grid_unit(14, 12, 2)
+    k = Matern(1.0, 0.25, 1.5, 1e-2)
+    rng = np.random.default_rng(3)
+    ia = rng.choice(np.arange(2, 12), 10)
+    ib = rng.choice(np.arange(2, 10), 10)
+    s = np.unique(np.stack([ia * g.dx, ib * g.dy], 1), axis=0)
+    ek = ExactKriging(s, k)
+    rp = RapidPredictor(g, k, s)
+    gup = rng.standard_normal((g.m1, g.m2))
+    dy = ek.coef(grad_coef(rp.A, corr_image_direct(g, lag_quadrant(g, k), gup)))
+    dy_exact = ek.grad_y(g.nodes(), gup.ravel())
+    assert np.abs(dy - dy_exact).max() < 1e-10 * np.abs(dy_exact).max()
+
+
+def test_table2_convergence_slopes():
+    """Figure 5 / Table 2 set-up: range 0.25, L = 2, site in the centre of the central box;
+    Lambda = sup over the domain of |k_approx(s, s*) - k(s, s*)| against 1/delta."""
+    exp = {}
+    for line in open(os.path.join(GOLD, "table2_slopes.txt")):
+        if line.strip() and not line.startswith("#"):
+            a, b = line.split()
+            exp[float(a)] = float(b)
+    ms = [20, 30, 40, 60, 80, 100, 140]
+    for nu, kappa in exp.items():
+        errs, inv = [], []
+        for m in ms:
+            g = grid_unit(m, m, 2)
+            k = Matern(1.0, 0.25, nu)
+            h = g.dx
+            c = (m - 1) // 2
+            s = np.array([[(c + 0.5) * h, (c + 0.5) * h]])
+            rp = RapidPredictor(g, k, s)
+            a = np.linspace(0, 1, 121)
+            X, Y = np.meshgrid(a, a, indexing="ij")
+            b = np.linspace(-3 * h, 3 * h, 81)
+            U, V = np.meshgrid(b, b, indexing="ij")
+            pts = np.concatenate([np.stack([X.ravel(), Y.ravel()], 1), s + np.stack([U.ravel(), V.ravel()], 1)])
+            errs.append(np.abs(rp.approx_kernel(0, pts) - k.cross(pts, s)[:, 0]).max())
+            inv.append(1.0 / fill_distance_of_grid(g))
+        slope = -np.polyfit(np.log10(inv), np.log10(errs), 1)[0]
+        assert abs(slope - kappa) < 0.2, (nu, slope, kappa)
+
+
+def test_tableA2_error_magnitudes_within_a_decade():
+    """Approx-vs-exact mean absolute error against the fitted model of Table A2 for a few
+    factor combinations (sigma^2 and the evaluation points are not stated in the paper:
+    sigma^2 = 1 and five grid nodes from centre to corner are used; partly unpinned)."""
+    coef = {}
+    for line in open(os.path.join(GOLD, "tableA2_coef.txt")):
+        if line.strip() and not line.startswith("#"):
+            a, b = line.split()
+            coef[a] = float(b)
+    from scipy.optimize import brentq
+    from oracle.matern import phi
+
+    def predicted(nu, L, m, tau2):
+        t = coef["(Intercept)"]
+        sn = {0.5: None, 1.0: "smoothness1", 1.5: "smoothness1.5"}[nu]
+        if sn:
+            t += coef[sn]
+        if L != 2:
+            t += coef[f"NN{L}"]
+            if sn:
+                t += coef[f"{sn}:NN{L}"]
+        if m != 100:
+            t += coef[f"nGrid{m}"]
+        if tau2 != 0.01:
+            t += coef[f"nugget{tau2}"]
+        return t
+
+    rng = np.random.default_rng(8)
+    for nu, L, m, tau2, n in ((0.5, 2, 100, 0.01, 200), (1.5, 4, 100, 0.1, 200), (1.0, 2, 100, 0.5, 500)):
+        rho = brentq(lambda r: phi(np.array([0.4 / r]), nu)[0] - 0.7, 1e-3, 10.0)
+        k = Matern(1.0, rho, nu, tau2)
+        g = grid_unit(m, m, L)
+        pts_ab = [(m // 2, m // 2), (m // 4, m // 4), (0, 0), (m // 2, 0), (m - 1, m // 2)]
+        idx = np.array([a * m + b for a, b in pts_ab])
+        errs = []
+        for rep in range(6):
+            s = rng.uniform(0, 1, (n, 2))
+            ek = ExactKriging(s, k)
+            rp = RapidPredictor(g, k, s)
+            c = ek.coef(gp_draw(s, k, rng))
+            errs.append(np.abs(rp.predict_direct(c, idx) - ek.predict_at(g.nodes()[idx], c)))
+        got = np.log10(np.mean(errs))
+        assert abs(got - predicted(nu, L, m, tau2)) < 1.0, (nu, L, m, tau2, got, predicted(nu, L, m, tau2))
+
+
+# ---------------------------------------------------------------------- conditional simulation
+def test_ce_eigs_and_field_covariance():
+    g = grid_unit(10, 12, 2)
+    k = Matern(1.0, 0.15, 1.5, 0.0)
+    lam, ncl, ratio = csim.ce_eigs(g, k, 32, 36)
+    assert ratio > -1e-6
+    # the embedded covariance restricted to the padded grid is the true covariance:
+    # E[u u^T] computed from the spectrum equals K on that grid (exact identity)
+    Fs1, Fs2 = lam.shape
+    cov = np.fft.ifft2(lam).real             # first row of the circulant
+    P = np.array([[a, b] for a in range(g.P1) for b in range(g.P2)])
+    d1 = (P[:, None, 0] - P[None, :, 0]) % Fs1
+    d2 = (P[:, None, 1] - P[None, :, 1]) % Fs2
+    C = cov[d1, d2]
+    X = (P[:, 0] - g.L) * g.dx
+    Y = (P[:, 1] - g.L) * g.dy
+    K = k.cross(np.stack([X, Y], 1), np.stack([X, Y], 1))
+    assert np.abs(C - K).max() < 1e-12
+    # too small a torus is rejected
+    with pytest.raises(ValueError):
+        csim.ce_eigs(g, k, 2 * (g.P1 - 1) - 2, 36)
+
+
+def test_ce_fields_empirical_variance():
+    g = grid_unit(8, 8, 2)
+    k = Matern(2.0, 0.2, 0.5)
+    lam, _, _ = csim.ce_eigs(g, k, 24, 24)
+    us = []
+    for p in range(400):
+        a, b = csim.ce_pair(lam, 99, p, g.P1, g.P2)
+        us += [a, b]
+    us = np.array(us)
+    var = us.var(0)
+    assert abs(var.mean() - 2.0) < 0.1
+    # lag-1 correlation along x matches k(dx)/sigma^2
+    c1 = np.mean(us[:, 3, 4] * us[:, 4, 4]) / 2.0
+    assert abs(c1 - k.of_dist(g.dx) / 2.0) < 0.06
+
+
+def test_conditional_simulation_reproduces_kriging_se():
+    g = grid_unit(16, 16, 2)
+    k = Matern(1.0, 0.2, 1.5, 0.01)
+    rng = np.random.default_rng(0)
+    s = rng.uniform(0, 1, (25, 2))
+    cs = csim.ConditionalSimulator(g, k, s, 64, 64)
+    y = gp_draw(s, k, rng)
+    R = 300
+    f = np.array([cs.realisation(7, r, y) for r in range(R)])
+    sd = f.std(0)
+    se = cs.ek.std_error(g.nodes()).reshape(g.m1, g.m2)
+    ratio = sd / se
+    assert abs(np.mean(ratio) - 1.0) < 0.05
+    # the ensemble mean is the kriging prediction (up to Monte Carlo error)
+    mean = f.mean(0)
+    pred = cs.rp.predict_direct(cs.ek.coef(y)).reshape(g.m1, g.m2)
+    assert np.max(np.abs(mean - pred) / se) < 5 / np.sqrt(R) * 3
