@@ -1,0 +1,192 @@
+/*
+ * krig.h -- C ABI of libkrig, a GPU (gfx950) implementation of the rapid Kriging
+ * predictor of Li, Fasshauer & Nychka, "Rapid Approximation Prediction for Kriging".
+ *
+ * Problem statement (Section 2): observations y_i at sites s_i (i < n) of a
+ * zero-mean field g with stationary Matern covariance k (eq. Matern1) plus a
+ * nugget tau^2 (eq. ObservationalModel, with the linear part X beta already
+ * removed: y = z - X beta_hat).  Kriging coefficients c = (K + tau^2 I)^{-1} y
+ * (eq. findc); predictions on a regular m1 x m2 grid approximate
+ * g_hat(s_j) = sum_i k(s_j, s_i) c_i (eq. predictionh) by the rapid method of
+ * Section 2.2: each k(., s_i) is replaced by an interpolant on the M = (2L)^2
+ * grid nodes around s_i (eq. weights), the coefficients are scattered onto the
+ * L-padded grid (c* = A^T c, Steps 5-6) and convolved with the covariance lag
+ * image through a circulant-embedded 2-D FFT (Step 7, eq. Convolution).
+ *
+ * Conventions used by every entry point
+ *  - Grid node (a, b) is (x0 + a dx, y0 + b dy), a < m1, b < m2, row-major with b
+ *    fastest.  The padded grid has P1 = m1 + 2L by P2 = m2 + 2L nodes; padded
+ *    index = unpadded index + L.  Sites must satisfy 0 <= (x-x0)/dx <= m1-1 and
+ *    0 <= (y-y0)/dy <= m2-1.
+ *  - Covariance k(d) = sigma2 * phi(d / range), phi of eq. (Matern1) with
+ *    nu in {0.5, 1.5, 2.5}.
+ *  - Neighbour offsets (ox, oy) in {-L+1..L}^2 of the lower-left node of the cell
+ *    holding a site, listed ox-major; W[i][m] is the weight of offset m.
+ *  - d_* pointers are device memory owned by the caller (contiguous, row-major);
+ *    h_* pointers are host memory.  The plan keeps its own copies of what it needs.
+ *  - "dt" arrays (images, lag, predictions, gradients) have the plan's dtype
+ *    (float for KRIG_F32, double for KRIG_F64).  Data y, coefficients alpha,
+ *    gradients w.r.t. y and the weights are always FP64.
+ *  - All calls after krig_plan_create are asynchronous on the plan's stream
+ *    (krig_set_stream), return a krig_status, never throw, and validate their
+ *    arguments on the host before enqueueing anything.  A plan must not be used
+ *    from two host threads at once; calls on one plan are ordered by its stream.
+ */
+#ifndef KRIG_H
+#define KRIG_H
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef enum {
+  KRIG_OK = 0,
+  KRIG_EINVAL = -1,       /* bad argument (shape, NULL, size) */
+  KRIG_EDOMAIN = -2,      /* a site lies outside the grid's bounding box */
+  KRIG_ENOTSPD = -3,      /* non-positive pivot in K + tau^2 I or in K_N */
+  KRIG_ECE = -4,          /* circulant embedding not non-negative definite */
+  KRIG_ENOMEM = -5,       /* device allocation failed */
+  KRIG_EHIP = -6,         /* HIP runtime error */
+  KRIG_EUNSUPPORTED = -7  /* unsupported smoothness or transform size */
+} krig_status;
+
+typedef enum { KRIG_F32 = 1, KRIG_F64 = 2 } krig_dtype;
+
+typedef struct {
+  int32_t m1, m2;       /* prediction grid nodes per axis (>= 2) */
+  double x0, y0;        /* first node */
+  double dx, dy;        /* spacings (> 0) */
+  int32_t L;            /* neighbour order, M = (2L)^2, 1 <= L <= 4 */
+} krig_grid;
+
+typedef struct {
+  double sigma2;        /* process variance (> 0) */
+  double range;         /* divides the distance (> 0) */
+  double nu;            /* smoothness: 0.5, 1.5 or 2.5 */
+  double tau2;          /* nugget variance (>= 0) */
+} krig_matern;
+
+typedef struct krig_plan_s *krig_plan;
+
+/* Sizes and status readable through krig_plan_info. */
+enum {
+  KRIG_INFO_N = 1, KRIG_INFO_M, KRIG_INFO_P1, KRIG_INFO_P2, KRIG_INFO_F1, KRIG_INFO_F2, KRIG_INFO_H2,
+  KRIG_INFO_LDH,        /* row pitch (elements) of half-spectrum buffers */
+  KRIG_INFO_SAVED_PER_FIELD, /* elements (complex dt) per field of the saved forward spectrum */
+  KRIG_INFO_KN_STATUS,  /* 0 clean, 1 jitter added to K_N */
+  KRIG_INFO_PIVOT,      /* first failing pivot (1-based) of K + tau^2 I, 0 if none */
+  KRIG_INFO_DTYPE,
+  KRIG_INFO_CE_CLAMPED  /* number of clamped circulant-embedding eigenvalues (after krig_csim) */
+};
+
+/*
+ * Create a plan for one site set, kernel, grid and dtype (Steps 1-4 of Section 2.2
+ * and the Cholesky factorisation named after eq. predictionf):
+ *  - the lag image lag[a][b] = k((a dx, b dy)), a < m1+L, b < m2+L (Step 2), and
+ *    its circulant-embedded spectrum, computed in FP64, scaled by 1/(F1 F2) and
+ *    stored in dt, with F1, F2 even 2^a 3^b lengths >= 2m + 2L - 1;
+ *  - K_N and its Cholesky factor (Step 1; jitter 1e-14*sigma2*M is added once if
+ *    a pivot fails), k_i for every site (Step 3) and A_i = K_N^{-1} k_i (Step 4,
+ *    applied as two FP64 MFMA products with the inverse Cholesky factor);
+ *  - the CSR layout of A^T over the padded grid (Step 5), built without float
+ *    atomics so the scatter sums in a fixed order;
+ *  - M = K + tau^2 I, its Cholesky factor and the inverse factor L^{-1} (FP64).
+ * h_sites: host [n][2] FP64.  stream: a hipStream_t (NULL = default stream).
+ * Synchronises the stream once to read the pivot status.  Returns KRIG_EDOMAIN,
+ * KRIG_ENOTSPD (pivot via KRIG_INFO_PIVOT), KRIG_EUNSUPPORTED, KRIG_EINVAL,
+ * KRIG_ENOMEM or KRIG_EHIP on failure, in which case *out is NULL.
+ */
+int krig_plan_create(krig_plan *out, const krig_grid *g, const krig_matern *k, int32_t n,
+                     const double *h_sites, int32_t dtype, void *stream);
+
+/* Free the plan and its device memory (synchronises its stream first). */
+int krig_plan_destroy(krig_plan p);
+
+/* Read a size or status value (KRIG_INFO_*) into *value. */
+int krig_plan_info(krig_plan p, int32_t what, int64_t *value);
+
+/* Change the stream later calls are enqueued on. */
+int krig_set_stream(krig_plan p, void *stream);
+
+/*
+ * Export the neighbour structure of Steps 3-4: d_anchor [n][2] int32 (lower-left
+ * cell node (i0, j0) of each site, unpadded indices) and d_W [n][M] FP64 weights
+ * A_i (eq. weights).  Either pointer may be NULL.
+ */
+int krig_weights(krig_plan p, int32_t *d_anchor, double *d_W);
+
+/*
+ * Replace the weights by caller-supplied ones (same layout as krig_weights) and
+ * rebuild the CSR layout.  Used to compare the scatter and convolution with a
+ * reference on identical weights when K_N is badly conditioned.
+ */
+int krig_set_weights(krig_plan p, const int32_t *d_anchor, const double *d_W);
+
+/* Export the lag quadrant (m1+L) x (m2+L) in dt (Step 2's filter). */
+int krig_lag(krig_plan p, void *d_lag);
+
+/* Kriging coefficients alpha = (K + tau^2 I)^{-1} y for B fields (eq. findc), FP64:
+ * d_y, d_alpha [B][n] (may alias). */
+int krig_solve(krig_plan p, int32_t B, const double *d_y, double *d_alpha);
+
+/*
+ * Steps 5-6 on their own: the padded coefficient image c* = A^T alpha for B fields,
+ * d_alpha [B][n] FP64, d_img [B][P1][P2] dt.  Segment sums in a fixed order,
+ * accumulated in FP64 and rounded once (bitwise repeatable).
+ */
+int krig_scatter(krig_plan p, int32_t B, const double *d_alpha, void *d_img);
+
+/*
+ * Rapid prediction from coefficients (Steps 5-7): d_alpha [B][n] FP64 ->
+ * d_yhat [B][m1][m2] dt.  d_lag: NULL to use the plan's lag image, else a
+ * caller lag quadrant (m1+L) x (m2+L) in dt whose spectrum is recomputed (FP64).
+ * d_saved: NULL, or a buffer of B * KRIG_INFO_SAVED_PER_FIELD complex dt that
+ * receives the row spectra of c* for krig_predict_adjoint.
+ */
+int krig_convolve(krig_plan p, int32_t B, const double *d_alpha, const void *d_lag, void *d_yhat,
+                  void *d_saved);
+
+/*
+ * Full prediction y -> yhat: alpha = (K + tau^2 I)^{-1} y (FP64), then
+ * krig_convolve.  d_alpha_out [B][n] FP64 may be NULL (else receives alpha).
+ */
+int krig_predict(krig_plan p, int32_t B, const double *d_y, const void *d_lag, void *d_yhat,
+                 double *d_alpha_out, void *d_saved);
+
+/*
+ * Adjoint of krig_predict for an upstream gradient d_g = dLoss/dyhat [B][m1][m2] dt:
+ *   dalpha_i = sum_m W[i][m] (Phi (*) g)[anchor_i + offset_m]   (correlation with the
+ *              symmetric filter on the padded grid, gathered at the neighbours),
+ *   d_dy [B][n] FP64    = (K + tau^2 I)^{-1} dalpha            (NULL to skip),
+ *   d_dlag (m1+L)x(m2+L) dt = sum_b sum over sign images of (g_b corr c*_b)
+ *                               (NULL to skip; summed over the batch; needs the
+ *                               coefficients: d_saved from krig_predict, or
+ *                               d_alpha [B][n] FP64 to recompute c*).
+ * A and the coefficients are held fixed with respect to the lag.
+ */
+int krig_predict_adjoint(krig_plan p, int32_t B, const void *d_g, const double *d_alpha,
+                         const void *d_saved, const void *d_lag, double *d_dy, void *d_dlag);
+
+/*
+ * Conditional simulation (Section 1 steps (1)-(2); circulant embedding as in the
+ * discussion section): R realisations on the m1 x m2 grid, d_fields [R][m1][m2] dt.
+ * Realisation r: unconditional field u on the padded grid by circulant embedding
+ * (complex Philox-4x32-10 noise, counter (bin, r/2, 0, 0), key = seed; real part
+ * for even r, imaginary for odd r), u at the sites by the same neighbour weights,
+ * simulated data u(s_i) + tau * xi_i (counter (i, r, 1, 0)), residual kriged by
+ * the rapid predictor and added to u.  Negative embedding eigenvalues above
+ * -1e-6 * max are clamped (count via KRIG_INFO_CE_CLAMPED); otherwise the torus is
+ * enlarged up to twice, then KRIG_ECE.  d_y [n] FP64.
+ */
+int krig_csim(krig_plan p, int32_t R, uint64_t seed, const double *d_y, void *d_fields);
+
+/* Human-readable text for a status code (static storage). */
+const char *krig_strerror(int status);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* KRIG_H */

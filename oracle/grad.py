@@ -83,3 +83,36 @@ def dlag_entry(grid: Grid, g: np.ndarray, cimg: np.ndarray, u: int, w: int) -> f
 def loss_masked_square(yhat: np.ndarray, mask: np.ndarray) -> float:
     """The differentiation workload's loss: sum over the grid of m * y_hat^2."""
     return float(np.sum(mask * yhat * yhat))
+
+
+def corr_image_fft(grid: Grid, lag: np.ndarray, g: np.ndarray) -> np.ndarray:
+    """TEST-ONLY FFT form of corr_image_direct (validated against it in the test suite)."""
+    from .rapid import embed_even, fft_len
+    F1 = fft_len(grid.m1 + grid.P1 - 1)
+    F2 = fft_len(grid.m2 + grid.P2 - 1)
+    E = embed_even(lag, F1, F2)
+    G = np.zeros((F1, F2))
+    G[grid.L:grid.L + grid.m1, grid.L:grid.L + grid.m2] = g
+    return np.fft.ifft2(np.fft.fft2(E) * np.fft.fft2(G)).real[:grid.P1, :grid.P2]
+
+
+def dlag_fft(grid: Grid, g: np.ndarray, cimg: np.ndarray) -> np.ndarray:
+    """TEST-ONLY FFT form of dlag_direct: fold of the cross-correlation of g (at offset L)
+    with c*, X[d] = sum_p g_pad[p] c*[p - d], over the sign images (validated against
+    dlag_direct in the test suite)."""
+    from .rapid import fft_len
+    F1 = fft_len(grid.m1 + grid.P1 - 1)
+    F2 = fft_len(grid.m2 + grid.P2 - 1)
+    G = np.zeros((F1, F2))
+    G[grid.L:grid.L + grid.m1, grid.L:grid.L + grid.m2] = g
+    C = np.zeros((F1, F2))
+    C[:grid.P1, :grid.P2] = cimg
+    X = np.fft.ifft2(np.fft.fft2(G) * np.conj(np.fft.fft2(C))).real
+    n1, n2 = grid.m1 + grid.L, grid.m2 + grid.L
+    out = np.zeros((n1, n2))
+    for u in range(n1):
+        rows = [u] if u == 0 else [u, F1 - u]
+        for w in range(n2):
+            cols = [w] if w == 0 else [w, F2 - w]
+            out[u, w] = sum(X[r, c] for r in rows for c in cols)
+    return out

@@ -1,0 +1,272 @@
+"""Python binding of libkrig, the GPU rapid Kriging predictor (Li, Fasshauer & Nychka).
+
+Argument marshalling only: every step runs in the HIP kernels of libkrig.so,
+called through its C ABI (include/krig.h).  PyTorch supplies device memory and
+the current stream.  There is no CPU fallback: importing the binding without a
+built library, or calling it without a GPU, raises.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+from typing import Optional, Tuple
+
+import numpy as np
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_HERE, "libkrig.so")
+
+KRIG_F32 = 1
+KRIG_F64 = 2
+
+INFO = dict(N=1, M=2, P1=3, P2=4, F1=5, F2=6, H2=7, LDH=8, SAVED_PER_FIELD=9, KN_STATUS=10,
+            PIVOT=11, DTYPE=12, CE_CLAMPED=13)
+
+STATUS = {0: "KRIG_OK", -1: "KRIG_EINVAL", -2: "KRIG_EDOMAIN", -3: "KRIG_ENOTSPD", -4: "KRIG_ECE",
+          -5: "KRIG_ENOMEM", -6: "KRIG_EHIP", -7: "KRIG_EUNSUPPORTED"}
+
+EXPORTS = ["krig_plan_create", "krig_plan_destroy", "krig_plan_info", "krig_set_stream", "krig_weights",
+           "krig_set_weights", "krig_lag", "krig_solve", "krig_scatter", "krig_convolve", "krig_predict",
+           "krig_predict_adjoint", "krig_csim", "krig_strerror"]
+
+
+class KrigError(RuntimeError):
+    def __init__(self, status: int, what: str):
+        self.status = status
+        super().__init__(f"{what}: {STATUS.get(status, status)} ({_strerror(status)})")
+
+
+class _Grid(ctypes.Structure):
+    _fields_ = [("m1", ctypes.c_int32), ("m2", ctypes.c_int32), ("x0", ctypes.c_double),
+                ("y0", ctypes.c_double), ("dx", ctypes.c_double), ("dy", ctypes.c_double),
+                ("L", ctypes.c_int32)]
+
+
+class _Matern(ctypes.Structure):
+    _fields_ = [("sigma2", ctypes.c_double), ("range", ctypes.c_double), ("nu", ctypes.c_double),
+                ("tau2", ctypes.c_double)]
+
+
+_lib = None
+
+
+def load_library(path: str = LIB_PATH) -> ctypes.CDLL:
+    """Load libkrig.so (raises if it has not been built)."""
+    global _lib
+    if _lib is not None:
+        return _lib
+    if not os.path.exists(path):
+        raise ImportError(f"{path} not found: build it with `python -m paper_2605_29284_amd.build`")
+    lib = ctypes.CDLL(path)
+    vp, i32, i64, dp = ctypes.c_void_p, ctypes.c_int32, ctypes.c_int64, ctypes.c_void_p
+    sig = {
+        "krig_plan_create": [ctypes.POINTER(vp), ctypes.POINTER(_Grid), ctypes.POINTER(_Matern), i32, dp, i32, vp],
+        "krig_plan_destroy": [vp],
+        "krig_plan_info": [vp, i32, ctypes.POINTER(i64)],
+        "krig_set_stream": [vp, vp],
+        "krig_weights": [vp, dp, dp],
+        "krig_set_weights": [vp, dp, dp],
+        "krig_lag": [vp, dp],
+        "krig_solve": [vp, i32, dp, dp],
+        "krig_scatter": [vp, i32, dp, dp],
+        "krig_convolve": [vp, i32, dp, dp, dp, dp],
+        "krig_predict": [vp, i32, dp, dp, dp, dp, dp],
+        "krig_predict_adjoint": [vp, i32, dp, dp, dp, dp, dp, dp],
+        "krig_csim": [vp, i32, ctypes.c_uint64, dp, dp],
+    }
+    for name, args in sig.items():
+        f = getattr(lib, name)
+        f.argtypes = args
+        f.restype = ctypes.c_int
+    lib.krig_strerror.argtypes = [ctypes.c_int]
+    lib.krig_strerror.restype = ctypes.c_char_p
+    _lib = lib
+    return lib
+
+
+def _strerror(status: int) -> str:
+    try:
+        return load_library().krig_strerror(status).decode()
+    except Exception:  # library missing: message only
+        return "?"
+
+
+def _check(status: int, what: str):
+    if status != 0:
+        raise KrigError(status, what)
+
+
+def _ptr(t) -> Optional[int]:
+    return None if t is None else t.data_ptr()
+
+
+class Plan:
+    """One site set, Matern kernel, grid and dtype (see krig_plan_create)."""
+
+    def __init__(self, m1: int, m2: int, x0: float, y0: float, dx: float, dy: float, L: int,
+                 sigma2: float, rho: float, nu: float, tau2: float, sites, dtype: str = "f32",
+                 device: str = "cuda:0"):
+        import torch
+        self.torch = torch
+        if not torch.cuda.is_available():
+            raise RuntimeError("libkrig needs a GPU (no device visible)")
+        self.lib = load_library()
+        self.device = torch.device(device)
+        self.dtype_code = {"f32": KRIG_F32, "f64": KRIG_F64}[dtype]
+        self.tdtype = torch.float32 if dtype == "f32" else torch.float64
+        self.m1, self.m2, self.L = int(m1), int(m2), int(L)
+        s = np.ascontiguousarray(np.asarray(sites, dtype=np.float64))
+        if s.ndim != 2 or s.shape[1] != 2:
+            raise ValueError("sites must be n x 2")
+        self.n = s.shape[0]
+        g = _Grid(self.m1, self.m2, x0, y0, dx, dy, self.L)
+        k = _Matern(sigma2, rho, nu, tau2)
+        h = ctypes.c_void_p()
+        with torch.cuda.device(self.device):
+            st = torch.cuda.current_stream(self.device).cuda_stream
+            _check(self.lib.krig_plan_create(ctypes.byref(h), ctypes.byref(g), ctypes.byref(k), self.n,
+                                             s.ctypes.data, self.dtype_code, st), "krig_plan_create")
+        self.h = h
+        self.M = self.info("M")
+        self.P1, self.P2 = self.info("P1"), self.info("P2")
+        self.F1, self.F2 = self.info("F1"), self.info("F2")
+        self.saved_per_field = self.info("SAVED_PER_FIELD")
+
+    # -- plumbing ---------------------------------------------------------------------
+    def __del__(self):
+        try:
+            if getattr(self, "h", None) and self.h.value:
+                self.lib.krig_plan_destroy(self.h)
+                self.h = ctypes.c_void_p()
+        except Exception:
+            pass
+
+    def close(self):
+        self.__del__()
+
+    def info(self, key: str) -> int:
+        v = ctypes.c_int64()
+        _check(self.lib.krig_plan_info(self.h, INFO[key], ctypes.byref(v)), "krig_plan_info")
+        return int(v.value)
+
+    def _stream(self):
+        st = self.torch.cuda.current_stream(self.device).cuda_stream
+        _check(self.lib.krig_set_stream(self.h, st), "krig_set_stream")
+
+    def _t(self, x, dtype, shape, name):
+        t = self.torch
+        if not isinstance(x, t.Tensor) or x.device != self.device or x.dtype != dtype or not x.is_contiguous():
+            raise TypeError(f"{name}: expected a contiguous {dtype} tensor on {self.device}")
+        if tuple(x.shape) != tuple(shape):
+            raise ValueError(f"{name}: expected shape {tuple(shape)}, got {tuple(x.shape)}")
+        return x
+
+    def _batch(self, x, last, name, dtype):
+        if x.dim() == len(last):
+            x = x.unsqueeze(0)
+        return self._t(x, dtype, (x.shape[0],) + tuple(last), name)
+
+    def empty(self, *shape, dtype=None):
+        return self.torch.empty(*shape, dtype=dtype or self.tdtype, device=self.device)
+
+    # -- entry points -----------------------------------------------------------------
+    def weights(self) -> Tuple["torch.Tensor", "torch.Tensor"]:
+        a = self.empty(self.n, 2, dtype=self.torch.int32)
+        w = self.empty(self.n, self.M, dtype=self.torch.float64)
+        self._stream()
+        _check(self.lib.krig_weights(self.h, a.data_ptr(), w.data_ptr()), "krig_weights")
+        return a, w
+
+    def set_weights(self, anchor, W):
+        self._t(anchor, self.torch.int32, (self.n, 2), "anchor")
+        self._t(W, self.torch.float64, (self.n, self.M), "W")
+        self._stream()
+        _check(self.lib.krig_set_weights(self.h, anchor.data_ptr(), W.data_ptr()), "krig_set_weights")
+
+    def lag(self):
+        out = self.empty(self.m1 + self.L, self.m2 + self.L)
+        self._stream()
+        _check(self.lib.krig_lag(self.h, out.data_ptr()), "krig_lag")
+        return out
+
+    def solve(self, y):
+        y = self._batch(y, (self.n,), "y", self.torch.float64)
+        out = self.empty(y.shape[0], self.n, dtype=self.torch.float64)
+        self._stream()
+        _check(self.lib.krig_solve(self.h, y.shape[0], y.data_ptr(), out.data_ptr()), "krig_solve")
+        return out
+
+    def scatter(self, alpha):
+        alpha = self._batch(alpha, (self.n,), "alpha", self.torch.float64)
+        out = self.empty(alpha.shape[0], self.P1, self.P2)
+        self._stream()
+        _check(self.lib.krig_scatter(self.h, alpha.shape[0], alpha.data_ptr(), out.data_ptr()), "krig_scatter")
+        return out
+
+    def _lag_ptr(self, lag):
+        if lag is None:
+            return None
+        return self._t(lag, self.tdtype, (self.m1 + self.L, self.m2 + self.L), "lag").data_ptr()
+
+    def new_saved(self, B: int):
+        """Buffer for the forward row spectra kept for the adjoint (complex dt)."""
+        return self.empty(B, self.saved_per_field, 2)
+
+    def convolve(self, alpha, lag=None, saved=None, out=None):
+        alpha = self._batch(alpha, (self.n,), "alpha", self.torch.float64)
+        B = alpha.shape[0]
+        out = self.empty(B, self.m1, self.m2) if out is None else self._t(out, self.tdtype, (B, self.m1, self.m2), "out")
+        if saved is not None:
+            self._t(saved, self.tdtype, (B, self.saved_per_field, 2), "saved")
+        self._stream()
+        _check(self.lib.krig_convolve(self.h, B, alpha.data_ptr(), self._lag_ptr(lag), out.data_ptr(),
+                                      _ptr(saved)), "krig_convolve")
+        return out
+
+    def predict(self, y, lag=None, alpha_out=None, saved=None, out=None):
+        y = self._batch(y, (self.n,), "y", self.torch.float64)
+        B = y.shape[0]
+        out = self.empty(B, self.m1, self.m2) if out is None else self._t(out, self.tdtype, (B, self.m1, self.m2), "out")
+        if alpha_out is not None:
+            self._t(alpha_out, self.torch.float64, (B, self.n), "alpha_out")
+        if saved is not None:
+            self._t(saved, self.tdtype, (B, self.saved_per_field, 2), "saved")
+        self._stream()
+        _check(self.lib.krig_predict(self.h, B, y.data_ptr(), self._lag_ptr(lag), out.data_ptr(), _ptr(alpha_out),
+                                     _ptr(saved)), "krig_predict")
+        return out
+
+    def adjoint(self, g, alpha=None, saved=None, lag=None, want_dy=True, want_dlag=True, dy_out=None,
+                dlag_out=None):
+        g = self._batch(g, (self.m1, self.m2), "g", self.tdtype)
+        B = g.shape[0]
+        if alpha is not None:
+            self._t(alpha, self.torch.float64, (B, self.n), "alpha")
+        if saved is not None:
+            self._t(saved, self.tdtype, (B, self.saved_per_field, 2), "saved")
+        dy = None
+        if want_dy:
+            dy = self.empty(B, self.n, dtype=self.torch.float64) if dy_out is None else dy_out
+        dlag = None
+        if want_dlag:
+            dlag = self.empty(self.m1 + self.L, self.m2 + self.L) if dlag_out is None else dlag_out
+        self._stream()
+        _check(self.lib.krig_predict_adjoint(self.h, B, g.data_ptr(), _ptr(alpha), _ptr(saved), self._lag_ptr(lag),
+                                             _ptr(dy), _ptr(dlag)), "krig_predict_adjoint")
+        return dy, dlag
+
+    def csim(self, R: int, seed: int, y):
+        y = self._t(y, self.torch.float64, (self.n,), "y")
+        out = self.empty(R, self.m1, self.m2)
+        self._stream()
+        _check(self.lib.krig_csim(self.h, R, int(seed) & 0xFFFFFFFFFFFFFFFF, y.data_ptr(), out.data_ptr()),
+               "krig_csim")
+        return out
+
+
+def plan_for(w, dtype: str = "f32", device: str = "cuda:0") -> Plan:
+    """Plan from a workloads.Workload."""
+    return Plan(w.m1, w.m2, w.x0, w.y0, w.dx, w.dy, w.L, w.sigma2, w.rho, w.nu, w.tau2, w.sites, dtype, device)
+
+
+from .autograd import KrigPredictFn, krig_predict  # noqa: E402,F401

@@ -1,0 +1,37 @@
+// FP64 dense linear algebra kernels (GPU) used for the kriging system.
+#pragma once
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+#include "matern_dev.h"
+
+namespace krig {
+
+struct GemmArgs {
+  const double* A;
+  int64_t lda;
+  int transA;
+  const double* B;
+  int64_t ldb;
+  int transB;
+  double* C;
+  int64_t ldc;
+  int m_off, M_end;   // rows [m_off, M_end) of C (and of op(A))
+  int n_off, N_end;   // cols [n_off, N_end) of C (and of op(B))
+  int K;
+  double alpha, beta;
+  int lower;          // only tiles with tile_col <= tile_row, and entries col <= row
+};
+
+hipError_t gemm_f64(const GemmArgs& g, hipStream_t st);
+hipError_t assemble_kt(const double* d_sites, int n, const MaternDev& mt, double* Kt, int64_t ld,
+                       hipStream_t st);
+hipError_t cholesky_and_inverse(double* A, int64_t lda, int n, double* Linv, double* Dinv, double* work,
+                                int* d_status, hipStream_t st);
+hipError_t copy_rows(const double* src, int64_t ld_src, double* dst, int64_t ld_dst, int nr, int nc,
+                     hipStream_t st);
+hipError_t fill_f64(double* p, int64_t cnt, double v, hipStream_t st);
+hipError_t tri_apply(const double* X, int64_t ldx, int n, const double* in, int64_t in_fs, double* out,
+                     int64_t out_fs, int B, int trans, hipStream_t st);
+
+}  // namespace krig

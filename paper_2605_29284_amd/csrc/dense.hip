@@ -1,0 +1,345 @@
+// FP64 dense linear algebra on the GPU: the kriging system M = K + tau^2 I of
+// eq. (findc), factored by a blocked right-looking Cholesky whose panel solves and
+// trailing updates are FP64 MFMA GEMMs, and the explicit inverse Cholesky factor
+// L^{-1} used to apply M^{-1} = L^{-T} L^{-1} to many right-hand sides at once.
+#include "dense.h"
+
+#include <math.h>
+
+#include "matern_dev.h"
+
+namespace krig {
+
+typedef double double4_t __attribute__((ext_vector_type(4)));
+
+// ------------------------------------------------------------------------------------
+// GEMM: C = alpha * op(A) * op(B) + beta * C  (row-major, FP64, MFMA 16x16x4)
+// Block tile 64 x 64, four waves each owning a 32 x 32 quadrant (2 x 2 MFMA tiles),
+// K staged through LDS 16 at a time.  LOWER restricts the launch to tiles with
+// tile_col <= tile_row (symmetric rank-k updates).
+// MFMA operand layout (v_mfma_f64_16x16x4f64): lane l supplies A[l%16][l/16] and
+// B[l/16][l%16]; result register r of lane l is D[4*(l/16) + r][l%16].
+// ------------------------------------------------------------------------------------
+__global__ void __launch_bounds__(256) k_gemm_f64(GemmArgs g) {
+  __shared__ double As[16][64 + 1];   // [k][m]
+  __shared__ double Bs[16][64 + 1];   // [k][n]
+  const int tm = blockIdx.y, tn = blockIdx.x;
+  if (g.lower && tn > tm) return;
+  const int m0 = tm * 64 + g.m_off, n0 = tn * 64 + g.n_off;
+  const int tid = threadIdx.x;
+  const int wave = tid >> 6, lane = tid & 63;
+  const int wm = (wave >> 1) * 32, wn = (wave & 1) * 32;
+  double4_t acc[2][2];
+  for (int i = 0; i < 2; ++i)
+    for (int j = 0; j < 2; ++j) acc[i][j] = (double4_t){0.0, 0.0, 0.0, 0.0};
+
+  for (int k0 = 0; k0 < g.K; k0 += 16) {
+    // stage A (64 x 16) and B (16 x 64)
+    for (int e = tid; e < 64 * 16; e += 256) {
+      int mm, kk;
+      if (g.transA) { mm = e % 64; kk = e / 64; } else { kk = e % 16; mm = e / 16; }
+      const int gm = m0 + mm, gk = k0 + kk;
+      double v = 0.0;
+      if (gm < g.M_end && gk < g.K)
+        v = g.transA ? g.A[(int64_t)gk * g.lda + gm] : g.A[(int64_t)gm * g.lda + gk];
+      As[kk][mm] = v;
+    }
+    for (int e = tid; e < 64 * 16; e += 256) {
+      int nn, kk;
+      if (g.transB) { kk = e % 16; nn = e / 16; } else { nn = e % 64; kk = e / 64; }
+      const int gn = n0 + nn, gk = k0 + kk;
+      double v = 0.0;
+      if (gn < g.N_end && gk < g.K)
+        v = g.transB ? g.B[(int64_t)gn * g.ldb + gk] : g.B[(int64_t)gk * g.ldb + gn];
+      Bs[kk][nn] = v;
+    }
+    __syncthreads();
+#pragma unroll
+    for (int kk = 0; kk < 16; kk += 4) {
+      const int kq = kk + (lane >> 4);
+      double a0 = As[kq][wm + (lane & 15)];
+      double a1 = As[kq][wm + 16 + (lane & 15)];
+      double b0 = Bs[kq][wn + (lane & 15)];
+      double b1 = Bs[kq][wn + 16 + (lane & 15)];
+      acc[0][0] = __builtin_amdgcn_mfma_f64_16x16x4f64(a0, b0, acc[0][0], 0, 0, 0);
+      acc[0][1] = __builtin_amdgcn_mfma_f64_16x16x4f64(a0, b1, acc[0][1], 0, 0, 0);
+      acc[1][0] = __builtin_amdgcn_mfma_f64_16x16x4f64(a1, b0, acc[1][0], 0, 0, 0);
+      acc[1][1] = __builtin_amdgcn_mfma_f64_16x16x4f64(a1, b1, acc[1][1], 0, 0, 0);
+    }
+    __syncthreads();
+  }
+  for (int i = 0; i < 2; ++i)
+    for (int j = 0; j < 2; ++j)
+      for (int r = 0; r < 4; ++r) {
+        const int gm = m0 + wm + i * 16 + 4 * (lane >> 4) + r;
+        const int gn = n0 + wn + j * 16 + (lane & 15);
+        if (gm < g.M_end && gn < g.N_end) {
+          if (g.lower && gn > gm) continue;
+          double* c = g.C + (int64_t)gm * g.ldc + gn;
+          const double v = g.alpha * acc[i][j][r];
+          *c = (g.beta == 0.0) ? v : v + g.beta * *c;
+        }
+      }
+}
+
+hipError_t gemm_f64(const GemmArgs& g, hipStream_t st) {
+  const int M = g.M_end - g.m_off, N = g.N_end - g.n_off;
+  if (M <= 0 || N <= 0) return hipSuccess;
+  dim3 grid((N + 63) / 64, (M + 63) / 64);
+  hipLaunchKernelGGL(k_gemm_f64, grid, dim3(256), 0, st, g);
+  return hipGetLastError();
+}
+
+// ------------------------------------------------------------------------------------
+// assembly of M = K + tau^2 I (full square, row-major)
+// ------------------------------------------------------------------------------------
+__global__ void k_assemble_kt(const double* __restrict__ sites, int n, MaternDev mt, double* __restrict__ Kt,
+                              int64_t ld) {
+  const int64_t idx = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (idx >= (int64_t)n * n) return;
+  const int i = (int)(idx / n), j = (int)(idx % n);
+  const double hx = sites[2 * i] - sites[2 * j];
+  const double hy = sites[2 * i + 1] - sites[2 * j + 1];
+  double v = matern_cov(sqrt(hx * hx + hy * hy), mt);
+  if (i == j) v += mt.tau2;
+  Kt[(int64_t)i * ld + j] = v;
+}
+
+hipError_t assemble_kt(const double* d_sites, int n, const MaternDev& mt, double* Kt, int64_t ld,
+                       hipStream_t st) {
+  const int64_t tot = (int64_t)n * n;
+  hipLaunchKernelGGL(k_assemble_kt, dim3((unsigned)((tot + 255) / 256)), dim3(256), 0, st, d_sites, n, mt, Kt,
+                     ld);
+  return hipGetLastError();
+}
+
+// ------------------------------------------------------------------------------------
+// diagonal block: Cholesky of a 64 x 64 tile (in place, lower) and its inverse.
+// Entries past the matrix edge act as the identity.  A non-positive pivot stores
+// (global row + 1) into *status (first failure wins) and the tile is left as is.
+// ------------------------------------------------------------------------------------
+__global__ void __launch_bounds__(256) k_potrf_diag(double* A, int64_t lda, int n, int k0, double* Dinv,
+                                                    int* status) {
+  __shared__ double a[64][65];
+  __shared__ int bad;
+  const int tid = threadIdx.x;
+  const int nb = min(64, n - k0);
+  if (tid == 0) bad = 0;
+  for (int e = tid; e < 64 * 64; e += 256) {
+    const int i = e / 64, j = e % 64;
+    double v = 0.0;
+    if (i < nb && j < nb) v = (j <= i) ? A[(int64_t)(k0 + i) * lda + k0 + j] : 0.0;
+    else if (i == j) v = 1.0;
+    a[i][j] = v;
+  }
+  __syncthreads();
+  for (int j = 0; j < 64; ++j) {
+    if (tid == 0) {
+      const double d = a[j][j];
+      if (!(d > 0.0)) {
+        if (!bad) {
+          bad = 1;
+          atomicCAS(status, 0, k0 + j + 1);
+        }
+        a[j][j] = 1.0;
+      } else {
+        a[j][j] = sqrt(d);
+      }
+    }
+    __syncthreads();
+    const double djj = a[j][j];
+    for (int i = j + 1 + tid; i < 64; i += 256) a[i][j] /= djj;
+    __syncthreads();
+    const int rem = 63 - j;  // trailing (rem x rem) lower triangle
+    for (int e = tid; e < rem * rem; e += 256) {
+      const int i = j + 1 + e / rem, c = j + 1 + e % rem;
+      if (c <= i) a[i][c] -= a[i][j] * a[c][j];
+    }
+    __syncthreads();
+  }
+  // the factor back to A
+  for (int e = tid; e < 64 * 64; e += 256) {
+    const int i = e / 64, j = e % 64;
+    if (i < nb && j < nb) A[(int64_t)(k0 + i) * lda + k0 + j] = (j <= i) ? a[i][j] : 0.0;
+  }
+  // inverse of the lower-triangular tile, one column per thread, written straight to
+  // Dinv (row-major 64 x 64); each thread only reads back entries it wrote itself
+  if (tid < 64) {
+    const int j = tid;
+    for (int i = 0; i < j; ++i) Dinv[i * 64 + j] = 0.0;
+    Dinv[j * 64 + j] = 1.0 / a[j][j];
+    for (int i = j + 1; i < 64; ++i) {
+      double s = 0.0;
+      for (int k = j; k < i; ++k) s += a[i][k] * Dinv[k * 64 + j];
+      Dinv[i * 64 + j] = -s / a[i][i];
+    }
+  }
+}
+
+// zero the strict upper triangle of an n x n row-major matrix
+__global__ void k_zero_upper(double* A, int64_t lda, int n) {
+  const int64_t idx = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (idx >= (int64_t)n * n) return;
+  const int i = (int)(idx / n), j = (int)(idx % n);
+  if (j > i) A[(int64_t)i * lda + j] = 0.0;
+}
+
+// Blocked Cholesky of the n x n matrix A (lower, in place) plus the inverse factor
+// Linv = L^{-1} (lower, n x n).  work: 64 x n doubles.  Dinv: nblk * 64 * 64.
+hipError_t cholesky_and_inverse(double* A, int64_t lda, int n, double* Linv, double* Dinv, double* work,
+                                int* d_status, hipStream_t st) {
+  const int nblk = (n + 63) / 64;
+  hipError_t e;
+  for (int kb = 0; kb < nblk; ++kb) {
+    const int k0 = kb * 64;
+    const int nb = min(64, n - k0);
+    hipLaunchKernelGGL(k_potrf_diag, dim3(1), dim3(256), 0, st, A, lda, n, k0, Dinv + (int64_t)kb * 4096,
+                       d_status);
+    if ((e = hipGetLastError()) != hipSuccess) return e;
+    if (k0 + nb >= n) break;
+    // panel: L21 = A21 * Dinv^T  (rows k0+nb .. n-1, cols k0 .. k0+nb-1), via work
+    {
+      const int rows = n - k0 - nb;
+      GemmArgs g{};
+      g.A = A + (int64_t)(k0 + nb) * lda + k0; g.lda = lda; g.transA = 0;
+      g.B = Dinv + (int64_t)kb * 4096; g.ldb = 64; g.transB = 1;
+      g.C = work; g.ldc = 64;
+      g.m_off = 0; g.M_end = rows; g.n_off = 0; g.N_end = nb; g.K = nb;
+      g.alpha = 1.0; g.beta = 0.0; g.lower = 0;
+      if ((e = gemm_f64(g, st)) != hipSuccess) return e;
+      // copy back into A
+      if ((e = copy_rows(work, 64, A + (int64_t)(k0 + nb) * lda + k0, lda, rows, nb, st)) != hipSuccess) return e;
+    }
+    // trailing update: A22 -= L21 L21^T (lower tiles)
+    {
+      const int rows = n - k0 - nb;
+      GemmArgs g{};
+      g.A = A + (int64_t)(k0 + nb) * lda + k0; g.lda = lda; g.transA = 0;
+      g.B = A + (int64_t)(k0 + nb) * lda + k0; g.ldb = lda; g.transB = 1;
+      g.C = A + (int64_t)(k0 + nb) * lda + (k0 + nb); g.ldc = lda;
+      g.m_off = 0; g.M_end = rows; g.n_off = 0; g.N_end = rows; g.K = nb;
+      g.alpha = -1.0; g.beta = 1.0; g.lower = 1;
+      if ((e = gemm_f64(g, st)) != hipSuccess) return e;
+    }
+  }
+  hipLaunchKernelGGL(k_zero_upper, dim3((unsigned)(((int64_t)n * n + 255) / 256)), dim3(256), 0, st, A, lda, n);
+  if ((e = hipGetLastError()) != hipSuccess) return e;
+  if (!Linv) return hipSuccess;
+  // Linv by block forward substitution on L X = I.  X (in Linv) first accumulates
+  // R[i][j] = sum_{j<=k<i} L_ik X_kj; block row i is then X[i][:i] = -Dinv_i R[i][:i],
+  // X[i][i] = Dinv_i, and R of the rows below is updated with L[:, i] X[i][:i+1].
+  if ((e = fill_f64(Linv, (int64_t)n * lda, 0.0, st)) != hipSuccess) return e;
+  for (int ib = 0; ib < nblk; ++ib) {
+    const int i0 = ib * 64;
+    const int nb = min(64, n - i0);
+    if (ib > 0) {
+      // X[i][0:i0] = -Dinv_i R[i][0:i0]   (via work: 64 x i0)
+      GemmArgs g{};
+      g.A = Dinv + (int64_t)ib * 4096; g.lda = 64; g.transA = 0;
+      g.B = Linv + (int64_t)i0 * lda; g.ldb = lda; g.transB = 0;
+      g.C = work; g.ldc = n;
+      g.m_off = 0; g.M_end = nb; g.n_off = 0; g.N_end = i0; g.K = nb;
+      g.alpha = -1.0; g.beta = 0.0; g.lower = 0;
+      if ((e = gemm_f64(g, st)) != hipSuccess) return e;
+      if ((e = copy_rows(work, n, Linv + (int64_t)i0 * lda, lda, nb, i0, st)) != hipSuccess) return e;
+    }
+    // diagonal block
+    if ((e = copy_rows(Dinv + (int64_t)ib * 4096, 64, Linv + (int64_t)i0 * lda + i0, lda, nb, nb, st)) !=
+        hipSuccess)
+      return e;
+    if (i0 + nb >= n) break;
+    // R[i0+nb:, 0:i0+nb] += L[i0+nb:, i0:i0+nb] X[i0:i0+nb, 0:i0+nb]
+    GemmArgs g{};
+    g.A = A + (int64_t)(i0 + nb) * lda + i0; g.lda = lda; g.transA = 0;
+    g.B = Linv + (int64_t)i0 * lda; g.ldb = lda; g.transB = 0;
+    g.C = Linv + (int64_t)(i0 + nb) * lda; g.ldc = lda;
+    g.m_off = 0; g.M_end = n - i0 - nb; g.n_off = 0; g.N_end = i0 + nb; g.K = nb;
+    g.alpha = 1.0; g.beta = 1.0; g.lower = 0;
+    if ((e = gemm_f64(g, st)) != hipSuccess) return e;
+  }
+  return hipSuccess;
+}
+
+__global__ void k_fill_f64(double* p, int64_t cnt, double v) {
+  const int64_t idx = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (idx < cnt) p[idx] = v;
+}
+
+hipError_t fill_f64(double* p, int64_t cnt, double v, hipStream_t st) {
+  if (cnt <= 0) return hipSuccess;
+  hipLaunchKernelGGL(k_fill_f64, dim3((unsigned)((cnt + 255) / 256)), dim3(256), 0, st, p, cnt, v);
+  return hipGetLastError();
+}
+
+__global__ void k_copy_rows(const double* __restrict__ src, int64_t lds_, double* __restrict__ dst, int64_t ldd,
+                            int nr, int nc) {
+  const int64_t idx = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (idx >= (int64_t)nr * nc) return;
+  const int i = (int)(idx / nc), j = (int)(idx % nc);
+  dst[(int64_t)i * ldd + j] = src[(int64_t)i * lds_ + j];
+}
+
+hipError_t copy_rows(const double* src, int64_t ld_src, double* dst, int64_t ld_dst, int nr, int nc,
+                     hipStream_t st) {
+  const int64_t tot = (int64_t)nr * nc;
+  if (tot <= 0) return hipSuccess;
+  hipLaunchKernelGGL(k_copy_rows, dim3((unsigned)((tot + 255) / 256)), dim3(256), 0, st, src, ld_src, dst,
+                     ld_dst, nr, nc);
+  return hipGetLastError();
+}
+
+// ------------------------------------------------------------------------------------
+// apply the explicit inverse factor to B right-hand sides
+//   trans = 0:  out[b][i] = sum_{k <= i} X[i][k] in[b][k]      (L^{-1} y)
+//   trans = 1:  out[b][i] = sum_{k >= i} X[k][i] in[b][k]      (L^{-T} y)
+// One block per 16 output entries; 16 k-lanes per output; fields in chunks of 8.
+// ------------------------------------------------------------------------------------
+__global__ void __launch_bounds__(256) k_tri_apply(const double* __restrict__ X, int64_t ldx, int n,
+                                                   const double* __restrict__ in, int64_t in_fs,
+                                                   double* __restrict__ out, int64_t out_fs, int B, int trans) {
+  __shared__ double red[16][16][9];
+  const int tid = threadIdx.x;
+  const int c = tid & 15, kl = tid >> 4;
+  const int i = blockIdx.x * 16 + c;
+  for (int f0 = 0; f0 < B; f0 += 8) {
+    double acc[8];
+#pragma unroll
+    for (int f = 0; f < 8; ++f) acc[f] = 0.0;
+    if (i < n) {
+      if (!trans) {
+        for (int k = kl; k <= i; k += 16) {
+          const double x = X[(int64_t)i * ldx + k];
+#pragma unroll
+          for (int f = 0; f < 8; ++f)
+            if (f0 + f < B) acc[f] += x * in[(int64_t)(f0 + f) * in_fs + k];
+        }
+      } else {
+        for (int k = i + kl; k < n; k += 16) {
+          const double x = X[(int64_t)k * ldx + i];
+#pragma unroll
+          for (int f = 0; f < 8; ++f)
+            if (f0 + f < B) acc[f] += x * in[(int64_t)(f0 + f) * in_fs + k];
+        }
+      }
+    }
+#pragma unroll
+    for (int f = 0; f < 8; ++f) red[kl][c][f] = acc[f];
+    __syncthreads();
+    if (kl < 8) {
+      const int f = kl;
+      double s = 0.0;
+      for (int q = 0; q < 16; ++q) s += red[q][c][f];  // fixed order
+      if (i < n && f0 + f < B) out[(int64_t)(f0 + f) * out_fs + i] = s;
+    }
+    __syncthreads();
+  }
+}
+
+hipError_t tri_apply(const double* X, int64_t ldx, int n, const double* in, int64_t in_fs, double* out,
+                     int64_t out_fs, int B, int trans, hipStream_t st) {
+  hipLaunchKernelGGL(k_tri_apply, dim3((n + 15) / 16), dim3(256), 0, st, X, ldx, n, in, in_fs, out, out_fs, B,
+                     trans);
+  return hipGetLastError();
+}
+
+}  // namespace krig

@@ -1,0 +1,497 @@
+// Two-level FFT pass kernels for the circulant-embedded convolution (Step 7) and
+// its adjoint.  Included by one generated translation unit per transform length.
+//
+// Roles (TC = arithmetic precision, TS = storage precision):
+//  k_rows_r2c   forward transform of real rows, two rows per complex line
+//               ("two-for-one"), sources: CSR scatter of alpha_i w_im (Steps 5-6),
+//               dense rows (adjoint input), or the even reflection of the lag
+//               quadrant (Step 2).  Writes the half spectrum.
+//  k_cols       column pass over the half spectrum: forward transform, pointwise
+//               product with the real filter spectrum, inverse transform, keep the
+//               requested rows; variants also accumulate sum_b G_b conj(C_b)
+//               (lag gradient), store the forward real part (filter set-up), or
+//               invert a sum of partial spectra.
+//  k_rows_c2r   inverse transform back to real rows, two rows per complex line,
+//               keeping the requested columns (optionally adding an image).
+//
+// Thread layout.  Row kernels: lane s (fastest) then line l; LDS [l][n2][k1].
+// Column kernels: column l (fastest, coalesced global access) then s; LDS
+// [n2][k1][l].  The n2 stride is odd(N1)*lines so stage-A writes hit distinct
+// banks.
+#pragma once
+#include "fft_args.h"
+#include "fft_reg.h"
+
+namespace krig {
+
+__host__ __device__ constexpr int odd_up(int x) { return x | 1; }
+__host__ __device__ constexpr int imax(int a, int b) { return a > b ? a : b; }
+
+// Hide a pointer's value from the optimiser so loads through it are not hoisted
+// out of a loop (keeps loop-invariant twiddles/filter values out of registers).
+template <typename P>
+__device__ __forceinline__ P opaque(P p) {
+  asm volatile("" : "+s"(p));
+  return p;
+}
+
+__device__ __forceinline__ int opaque_v(int x) {
+  asm volatile("" : "+v"(x));
+  return x;
+}
+
+template <int N1, int N2> struct Geo {
+  static constexpr int F = N1 * N2;
+  static constexpr int NT = imax(N1, N2);
+  static constexpr int ON1 = odd_up(N1);
+};
+
+// ----------------------------------------------------------------------------------------
+// row kernels: forward (real -> half spectrum)
+// ----------------------------------------------------------------------------------------
+enum { SRC_CSR = 0, SRC_DENSE = 1, SRC_LAG = 2 };
+
+template <typename TC, typename TS, int N1, int N2, int SRC>
+__global__ void __launch_bounds__(256) k_rows_r2c(RowsR2CArgs a) {
+  using G = Geo<N1, N2>;
+  extern __shared__ unsigned char smem_raw[];
+  cx<TC>* lds = reinterpret_cast<cx<TC>*>(smem_raw);
+  const int s = threadIdx.x % G::NT;
+  const int l = threadIdx.x / G::NT;
+  const int b = blockIdx.y;
+  const int pair = blockIdx.x * a.NL + l;
+  const int ra = 2 * pair, rb = 2 * pair + 1;
+  const bool oka = ra < a.nrows, okb = rb < a.nrows;
+  const cx<TC>* twF = reinterpret_cast<const cx<TC>*>(a.twF);
+  cx<TC>* L = lds + (size_t)l * (N2 * G::ON1);
+
+  if (s < N2) {
+    cx<TC> v[N1];
+#pragma unroll
+    for (int n1 = 0; n1 < N1; ++n1) {
+      const int c = N2 * n1 + s;
+      TC xa = 0, xb = 0;
+      if constexpr (SRC == SRC_CSR) {
+        if (c < a.ncols) {
+          const double* al = a.alpha + (int64_t)b * a.alpha_fs;
+          if (oka) {
+            const int q = ra * a.ncols + c;
+            double acc = 0.0;
+            for (int e = a.row_ptr[q]; e < a.row_ptr[q + 1]; ++e) acc += al[a.ent_site[e]] * a.ent_w[e];
+            xa = (TC)acc;
+          }
+          if (okb) {
+            const int q = rb * a.ncols + c;
+            double acc = 0.0;
+            for (int e = a.row_ptr[q]; e < a.row_ptr[q + 1]; ++e) acc += al[a.ent_site[e]] * a.ent_w[e];
+            xb = (TC)acc;
+          }
+        }
+      } else if constexpr (SRC == SRC_DENSE) {
+        const int cc = c - a.coff;
+        if (cc >= 0 && cc < a.ncols) {
+          const TS* d = reinterpret_cast<const TS*>(a.dense) + (int64_t)b * a.dense_fs;
+          if (oka) xa = (TC)d[(int64_t)ra * a.dense_ld + cc];
+          if (okb) xb = (TC)d[(int64_t)rb * a.dense_ld + cc];
+        }
+      } else {  // SRC_LAG: embedding row r holds lag[min(r, F1-r)][min(c, F2-c)]
+        const int F2 = G::F;
+        const int dc = c < F2 - c ? c : F2 - c;
+        if (dc < a.n2l) {
+          if (oka) {
+            const int dr = ra < a.F1 - ra ? ra : a.F1 - ra;
+            if (dr < a.n1l) xa = (TC)a.lag[(int64_t)dr * a.n2l + dc];
+          }
+          if (okb) {
+            const int dr = rb < a.F1 - rb ? rb : a.F1 - rb;
+            if (dr < a.n1l) xb = (TC)a.lag[(int64_t)dr * a.n2l + dc];
+          }
+        }
+      }
+      v[n1] = mk<TC>(xa, xb);
+    }
+    DFT<N1, -1, TC>::run(v);
+#pragma unroll
+    for (int k1 = 0; k1 < N1; ++k1) {
+      cx<TC> t = v[k1];
+      if (k1 != 0 && s != 0) t = cmul(t, twF[s * k1]);
+      L[s * G::ON1 + k1] = t;
+    }
+  }
+  __syncthreads();
+  cx<TC> w[N2];
+  if (s < N1) {
+#pragma unroll
+    for (int n2 = 0; n2 < N2; ++n2) w[n2] = L[n2 * G::ON1 + s];
+    DFT<N2, -1, TC>::run(w);
+  }
+  __syncthreads();
+  // natural-order exchange to pair Z[k] with Z[F-k]
+  if (s < N1) {
+#pragma unroll
+    for (int k2 = 0; k2 < N2; ++k2) L[s + N1 * k2] = w[k2];
+  }
+  __syncthreads();
+  if (s < N1) {
+    cx<TS>* oa = reinterpret_cast<cx<TS>*>(a.out) + (int64_t)b * a.out_fs + (int64_t)ra * a.ldH;
+    cx<TS>* ob = oa + a.ldH;
+#pragma unroll
+    for (int k2 = 0; k2 < N2; ++k2) {
+      const int k = s + N1 * k2;
+      if (k < a.H2) {
+        const cx<TC> z = w[k2];
+        const cx<TC> zc = L[(G::F - k) % G::F];
+        // Xa = (Z[k] + conj Z[F-k]) / 2,  Xb = (Z[k] - conj Z[F-k]) / (2 i)
+        const cx<TC> xa = mk<TC>((TC)0.5 * (z.x + zc.x), (TC)0.5 * (z.y - zc.y));
+        const cx<TC> xb = mk<TC>((TC)0.5 * (z.y + zc.y), (TC)0.5 * (zc.x - z.x));
+        if (oka) oa[k] = ccast<TS>(xa);
+        if (okb) ob[k] = ccast<TS>(xb);
+      }
+    }
+  }
+}
+
+// ----------------------------------------------------------------------------------------
+// column kernels
+// ----------------------------------------------------------------------------------------
+// forward column transform: returns X[s + N1 k2] in w[k2] for threads s < N1
+template <typename TC, typename TS, int N1, int N2>
+__device__ __forceinline__ void col_fwd(const cx<TS>* src, int ld, int in_off, int in_cnt, int col,
+                                        bool colok, int s, int l, int NL, cx<TC>* lds,
+                                        const cx<TC>* twF, cx<TC> (&w)[N2]) {
+  using G = Geo<N1, N2>;
+  const int SN2 = NL * G::ON1;
+  if (s < N2) {
+    cx<TC> v[N1];
+#pragma unroll
+    for (int n1 = 0; n1 < N1; ++n1) {
+      const int r = N2 * n1 + s - in_off;
+      v[n1] = (colok && r >= 0 && r < in_cnt) ? ccast<TC>(src[(int64_t)r * ld + col]) : mk<TC>(0, 0);
+    }
+    DFT<N1, -1, TC>::run(v);
+#pragma unroll
+    for (int k1 = 0; k1 < N1; ++k1) {
+      cx<TC> t = v[k1];
+      if (k1 != 0 && s != 0) t = cmul(t, twF[s * k1]);
+      lds[s * SN2 + k1 * NL + l] = t;
+    }
+  }
+  __syncthreads();
+  if (s < N1) {
+#pragma unroll
+    for (int n2 = 0; n2 < N2; ++n2) w[n2] = lds[n2 * SN2 + s * NL + l];
+    DFT<N2, -1, TC>::run(w);
+  }
+}
+
+// inverse column transform from the transposed order held by col_fwd (thread s = k1
+// holds k2 = 0..N2-1); thread s < N2 ends with x[N2 n1 + s] in v[n1].
+template <typename TC, int N1, int N2>
+__device__ __forceinline__ void col_inv_from_t(cx<TC> (&w)[N2], int s, int l, int NL, cx<TC>* lds,
+                                               const cx<TC>* twF, cx<TC> (&v)[N1]) {
+  using G = Geo<N1, N2>;
+  const int SN2 = NL * G::ON1;
+  if (s < N1) {
+    DFT<N2, 1, TC>::run(w);
+#pragma unroll
+    for (int n2 = 0; n2 < N2; ++n2) {
+      cx<TC> t = w[n2];
+      if (n2 != 0 && s != 0) t = cmulc(t, twF[n2 * s]);
+      lds[n2 * SN2 + s * NL + l] = t;
+    }
+  }
+  __syncthreads();
+  if (s < N2) {
+#pragma unroll
+    for (int k1 = 0; k1 < N1; ++k1) v[k1] = lds[s * SN2 + k1 * NL + l];
+    DFT<N1, 1, TC>::run(v);
+  }
+}
+
+template <typename TS>
+__device__ __forceinline__ int window_dst(const Window& wd, int i) {
+  if (i >= wd.a0 && i < wd.a0 + wd.na) return i - wd.a0;
+  if (i >= wd.b0 && i < wd.b0 + wd.nb) return wd.na + i - wd.b0;
+  return -1;
+}
+
+enum { COL_CONV = 0, COL_CONV_DLAG = 1, COL_FWD_REAL = 2, COL_INV_SUM = 3 };
+
+template <typename TC, typename TS, int N1, int N2, int MODE>
+__global__ void __launch_bounds__(256) k_cols(ColsArgs a) {
+  using G = Geo<N1, N2>;
+  extern __shared__ unsigned char smem_raw[];
+  cx<TC>* lds = reinterpret_cast<cx<TC>*>(smem_raw);
+  const int NL = a.NL;
+  const int l0 = threadIdx.x % NL;
+  const int s0 = threadIdx.x / NL;
+  const int col0 = blockIdx.x * NL + l0;
+  const bool colok = col0 < a.H2;
+  const cx<TC>* twF = reinterpret_cast<const cx<TC>*>(a.twF);
+  const int l = l0, s = s0, col = col0;
+
+  if constexpr (MODE == COL_CONV) {
+    const int b = blockIdx.y;
+    const cx<TS>* src = reinterpret_cast<const cx<TS>*>(a.in) + (int64_t)b * a.in_fs;
+    cx<TC> w[N2];
+    col_fwd<TC, TS, N1, N2>(src, a.ldH, a.in_off, a.in_cnt, col, colok, s, l, NL, lds, twF, w);
+    if (s < N1 && colok) {
+      const TS* f = reinterpret_cast<const TS*>(a.filt);
+#pragma unroll
+      for (int k2 = 0; k2 < N2; ++k2) w[k2] = cscale(w[k2], (TC)f[(int64_t)(s + N1 * k2) * a.ldH + col]);
+    }
+    cx<TC> v[N1];
+    col_inv_from_t<TC, N1, N2>(w, s, l, NL, lds, twF, v);
+    if (s < N2 && colok) {
+      cx<TS>* dst = reinterpret_cast<cx<TS>*>(a.out) + (int64_t)b * a.out_fs;
+#pragma unroll
+      for (int n1 = 0; n1 < N1; ++n1) {
+        const int d = window_dst<TS>(a.rows, N2 * n1 + s);
+        if (d >= 0) dst[(int64_t)d * a.ldH + col] = ccast<TS>(v[n1]);
+      }
+    }
+  } else if constexpr (MODE == COL_CONV_DLAG) {
+    // blockIdx.y = group of G fields; partial spectrum of the group -> part[group]
+    cx<TC> acc[N2];
+#pragma unroll
+    for (int k2 = 0; k2 < N2; ++k2) acc[k2] = mk<TC>(0, 0);
+    cx<TC>* stash = lds + (size_t)N2 * NL * G::ON1;  // [k2][k1][l], thread-private slots
+    const int b0 = blockIdx.y * a.G;
+#pragma unroll 1
+    for (int gi = 0; gi < a.G; ++gi) {
+      const int b = b0 + gi;
+      if (b >= a.B) break;  // uniform across the block
+      cx<TC> wg[N2];
+      twF = opaque(twF);
+      // fresh copies of the lane indices each iteration: keeps per-lane address
+      // arithmetic from being hoisted out of the field loop (register pressure)
+      const int s = opaque_v(s0), l = opaque_v(l0), col = opaque_v(col0);
+      const cx<TS>* srcc = reinterpret_cast<const cx<TS>*>(a.in2) + (int64_t)b * a.in2_fs;
+      const cx<TS>* srcg = reinterpret_cast<const cx<TS>*>(a.in) + (int64_t)b * a.in_fs;
+      __syncthreads();
+      {
+        // C-hat of this field: transform, then park it in the stash region of LDS
+        cx<TC> wc[N2];
+        col_fwd<TC, TS, N1, N2>(srcc, a.ldH, a.in2_off, a.in2_cnt, col, colok, s, l, NL, lds, twF, wc);
+        if (s < N1) {
+#pragma unroll
+          for (int k2 = 0; k2 < N2; ++k2) stash[(k2 * N1 + s) * NL + l] = wc[k2];
+        }
+      }
+      __syncthreads();
+      col_fwd<TC, TS, N1, N2>(srcg, a.ldH, a.in_off, a.in_cnt, col, colok, s, l, NL, lds, twF, wg);
+      if (s < N1 && colok) {
+        const TS* f = opaque(reinterpret_cast<const TS*>(a.filt));
+#pragma unroll
+        for (int k2 = 0; k2 < N2; ++k2) {
+          acc[k2] = acc[k2] + cmulc(wg[k2], stash[(k2 * N1 + s) * NL + l]);
+          wg[k2] = cscale(wg[k2], (TC)f[(int64_t)(s + N1 * k2) * a.ldH + col]);
+        }
+      }
+      cx<TC> v[N1];
+      col_inv_from_t<TC, N1, N2>(wg, s, l, NL, lds, twF, v);
+      if (s < N2 && colok) {
+        cx<TS>* dst = reinterpret_cast<cx<TS>*>(a.out) + (int64_t)b * a.out_fs;
+#pragma unroll
+        for (int n1 = 0; n1 < N1; ++n1) {
+          const int d = window_dst<TS>(a.rows, N2 * n1 + s);
+          if (d >= 0) dst[(int64_t)d * a.ldH + col] = ccast<TS>(v[n1]);
+        }
+      }
+    }
+    if (s < N1 && colok) {
+      cx<TS>* p = reinterpret_cast<cx<TS>*>(a.part) + (int64_t)blockIdx.y * G::F * a.ldH;
+#pragma unroll
+      for (int k2 = 0; k2 < N2; ++k2) p[(int64_t)(s + N1 * k2) * a.ldH + col] = ccast<TS>(acc[k2]);
+    }
+  } else if constexpr (MODE == COL_FWD_REAL) {
+    // forward transform of the input columns; store Re(X) * scale (natural order, TS = double)
+    const int b = blockIdx.y;
+    const cx<TS>* src = reinterpret_cast<const cx<TS>*>(a.in) + (int64_t)b * a.in_fs;
+    cx<TC> w[N2];
+    col_fwd<TC, TS, N1, N2>(src, a.ldH, a.in_off, a.in_cnt, col, colok, s, l, NL, lds, twF, w);
+    if (s < N1 && colok) {
+      TS* dst = reinterpret_cast<TS*>(a.out) + (int64_t)b * a.out_fs;
+#pragma unroll
+      for (int k2 = 0; k2 < N2; ++k2) dst[(int64_t)(s + N1 * k2) * a.ldH + col] = (TS)(w[k2].x * (TC)a.scale);
+    }
+  } else {  // COL_INV_SUM: inverse transform of sum_g part[g] (natural order), keep rows
+    const int SN2 = NL * G::ON1;
+    const cx<TS>* p = reinterpret_cast<const cx<TS>*>(a.in);
+    const int ng = a.G;
+    if (s < N2) {
+      cx<TC> v[N1];
+#pragma unroll
+      for (int n1 = 0; n1 < N1; ++n1) {
+        cx<TC> t = mk<TC>(0, 0);
+        if (colok) {
+          const int64_t off = (int64_t)(N2 * n1 + s) * a.ldH + col;
+          for (int g = 0; g < ng; ++g) t = t + ccast<TC>(p[(int64_t)g * a.in_fs + off]);
+        }
+        v[n1] = t;
+      }
+      DFT<N1, 1, TC>::run(v);
+#pragma unroll
+      for (int k1 = 0; k1 < N1; ++k1) {
+        cx<TC> t = v[k1];
+        if (k1 != 0 && s != 0) t = cmulc(t, twF[s * k1]);
+        lds[s * SN2 + k1 * NL + l] = t;
+      }
+    }
+    __syncthreads();
+    if (s < N1 && colok) {
+      cx<TC> w[N2];
+#pragma unroll
+      for (int n2 = 0; n2 < N2; ++n2) w[n2] = lds[n2 * SN2 + s * NL + l];
+      DFT<N2, 1, TC>::run(w);
+      cx<TS>* dst = reinterpret_cast<cx<TS>*>(a.out);
+#pragma unroll
+      for (int k2 = 0; k2 < N2; ++k2) {
+        const int d = window_dst<TS>(a.rows, s + N1 * k2);
+        if (d >= 0) dst[(int64_t)d * a.ldH + col] = ccast<TS>(w[k2]);
+      }
+    }
+  }
+}
+
+// ----------------------------------------------------------------------------------------
+// row kernel: inverse (half spectrum -> real), two rows per complex line
+// ----------------------------------------------------------------------------------------
+template <typename TC, typename TS, int N1, int N2>
+__global__ void __launch_bounds__(256) k_rows_c2r(RowsC2RArgs a) {
+  using G = Geo<N1, N2>;
+  extern __shared__ unsigned char smem_raw[];
+  cx<TC>* lds = reinterpret_cast<cx<TC>*>(smem_raw);
+  const int s = threadIdx.x % G::NT;
+  const int l = threadIdx.x / G::NT;
+  const int b = blockIdx.y;
+  const int pair = blockIdx.x * a.NL + l;
+  const int ra = 2 * pair, rb = 2 * pair + 1;
+  const bool oka = ra < a.nrows, okb = rb < a.nrows;
+  const cx<TC>* twF = reinterpret_cast<const cx<TC>*>(a.twF);
+  cx<TC>* L = lds + (size_t)l * (N2 * G::ON1);
+  const cx<TS>* ia = reinterpret_cast<const cx<TS>*>(a.in) + (int64_t)b * a.in_fs + (int64_t)ra * a.ldH;
+  const cx<TS>* ib = ia + a.ldH;
+
+  if (s < N2) {
+    cx<TC> v[N1];
+#pragma unroll
+    for (int n1 = 0; n1 < N1; ++n1) {
+      const int k = N2 * n1 + s;
+      const bool lo = k < a.H2;
+      const int kk = lo ? k : G::F - k;
+      cx<TC> xa = oka ? ccast<TC>(ia[kk]) : mk<TC>(0, 0);
+      cx<TC> xb = okb ? ccast<TC>(ib[kk]) : mk<TC>(0, 0);
+      if (kk == 0 || 2 * kk == G::F) { xa.y = 0; xb.y = 0; }  // DC / Nyquist are real
+      if (!lo) { xa.y = -xa.y; xb.y = -xb.y; }
+      v[n1] = mk<TC>(xa.x - xb.y, xa.y + xb.x);  // Xa + i Xb
+    }
+    DFT<N1, 1, TC>::run(v);
+#pragma unroll
+    for (int k1 = 0; k1 < N1; ++k1) {
+      cx<TC> t = v[k1];
+      if (k1 != 0 && s != 0) t = cmulc(t, twF[s * k1]);
+      L[s * G::ON1 + k1] = t;
+    }
+  }
+  __syncthreads();
+  if (s < N1) {
+    cx<TC> w[N2];
+#pragma unroll
+    for (int n2 = 0; n2 < N2; ++n2) w[n2] = L[n2 * G::ON1 + s];
+    DFT<N2, 1, TC>::run(w);
+    TS* oa = reinterpret_cast<TS*>(a.out) + (int64_t)b * a.out_fs + (int64_t)ra * a.ldo;
+    TS* ob = oa + a.ldo;
+    const TS* ad = reinterpret_cast<const TS*>(a.add);
+#pragma unroll
+    for (int k2 = 0; k2 < N2; ++k2) {
+      const int c = s + N1 * k2;
+      const int d = window_dst<TS>(a.cols, c);
+      if (d >= 0) {
+        TS va = (TS)w[k2].x, vb = (TS)w[k2].y;
+        if (ad) {
+          const TS* abase = ad + (int64_t)b * a.add_fs + (int64_t)(ra + a.add_r0) * a.add_ld + d + a.add_c0;
+          if (oka) va += abase[0];
+          if (okb) vb += abase[a.add_ld];
+        }
+        if (oka) oa[d] = va;
+        if (okb) ob[d] = vb;
+      }
+    }
+  }
+}
+
+// ----------------------------------------------------------------------------------------
+// launchers
+// ----------------------------------------------------------------------------------------
+template <typename TC, int N1, int N2>
+inline size_t rows_lds_bytes(int NL) { return (size_t)NL * N2 * Geo<N1, N2>::ON1 * sizeof(cx<TC>); }
+template <typename TC, int N1, int N2, int MODE>
+inline size_t cols_lds_bytes(int NL) {
+  size_t ex = (size_t)NL * N2 * Geo<N1, N2>::ON1;
+  if (MODE == COL_CONV_DLAG) ex += (size_t)NL * N1 * N2;  // stash of C-hat
+  return ex * sizeof(cx<TC>);
+}
+
+template <typename TC, typename TS, int N1, int N2, int SRC>
+hipError_t launch_rows_r2c(const RowsR2CArgs& a, int B, hipStream_t st) {
+  const int npairs = (a.nrows + 1) / 2;
+  dim3 grid((npairs + a.NL - 1) / a.NL, B);
+  dim3 block(Geo<N1, N2>::NT * a.NL);
+  const size_t sh = rows_lds_bytes<TC, N1, N2>(a.NL);
+  k_rows_r2c<TC, TS, N1, N2, SRC><<<grid, block, sh, st>>>(a);
+  return hipGetLastError();
+}
+
+template <typename TC, typename TS, int N1, int N2, int MODE>
+hipError_t launch_cols(const ColsArgs& a, int nblk_y, hipStream_t st) {
+  dim3 grid((a.H2 + a.NL - 1) / a.NL, nblk_y);
+  dim3 block(Geo<N1, N2>::NT * a.NL);
+  const size_t sh = cols_lds_bytes<TC, N1, N2, MODE>(a.NL);
+  k_cols<TC, TS, N1, N2, MODE><<<grid, block, sh, st>>>(a);
+  return hipGetLastError();
+}
+
+template <typename TC, typename TS, int N1, int N2>
+hipError_t launch_rows_c2r(const RowsC2RArgs& a, int B, hipStream_t st) {
+  const int npairs = (a.nrows + 1) / 2;
+  dim3 grid((npairs + a.NL - 1) / a.NL, B);
+  dim3 block(Geo<N1, N2>::NT * a.NL);
+  const size_t sh = rows_lds_bytes<TC, N1, N2>(a.NL);
+  k_rows_c2r<TC, TS, N1, N2><<<grid, block, sh, st>>>(a);
+  return hipGetLastError();
+}
+
+template <int N1, int N2>
+FftEntry make_fft_entry() {
+  FftEntry e;
+  e.F = N1 * N2;
+  e.N1 = N1;
+  e.N2 = N2;
+  // FP32 storage: scatter+forward rows in FP64 arithmetic, other passes FP32
+  e.f32.r2c_csr = launch_rows_r2c<double, float, N1, N2, SRC_CSR>;
+  e.f32.r2c_dense = launch_rows_r2c<float, float, N1, N2, SRC_DENSE>;
+  e.f32.r2c_lag64 = launch_rows_r2c<double, double, N1, N2, SRC_LAG>;
+  e.f32.conv = launch_cols<float, float, N1, N2, COL_CONV>;
+  e.f32.conv_dlag = launch_cols<float, float, N1, N2, COL_CONV_DLAG>;
+  e.f32.fwd_real64 = launch_cols<double, double, N1, N2, COL_FWD_REAL>;
+  e.f32.inv_sum = launch_cols<float, float, N1, N2, COL_INV_SUM>;
+  e.f32.c2r = launch_rows_c2r<float, float, N1, N2>;
+  // FP64: the same kernels instantiated for double
+  e.f64.r2c_csr = launch_rows_r2c<double, double, N1, N2, SRC_CSR>;
+  e.f64.r2c_dense = launch_rows_r2c<double, double, N1, N2, SRC_DENSE>;
+  e.f64.r2c_lag64 = e.f32.r2c_lag64;
+  e.f64.conv = launch_cols<double, double, N1, N2, COL_CONV>;
+  e.f64.conv_dlag = launch_cols<double, double, N1, N2, COL_CONV_DLAG>;
+  e.f64.fwd_real64 = e.f32.fwd_real64;
+  e.f64.inv_sum = launch_cols<double, double, N1, N2, COL_INV_SUM>;
+  e.f64.c2r = launch_rows_c2r<double, double, N1, N2>;
+  return e;
+}
+
+}  // namespace krig
+
+#define KRIG_FFT_SIZE(N1, N2)                                              \
+  namespace krig {                                                         \
+  void register_fft_##N1##x##N2() { register_fft(make_fft_entry<N1, N2>()); } \
+  }

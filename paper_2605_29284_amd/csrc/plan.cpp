@@ -1,0 +1,724 @@
+// C-ABI entry points of libkrig: plan set-up (Steps 1-4 of Section 2.2 and the
+// kriging-system factorisation) and the per-call sequences (solve, scatter,
+// convolution, adjoint, conditional simulation).
+#include <hip/hip_runtime.h>
+#include <math.h>
+#include <string.h>
+
+#include <algorithm>
+#include <mutex>
+#include <new>
+#include <vector>
+
+#include "../../include/krig.h"
+#include "dense.h"
+#include "fft_args.h"
+#include "fft_reg.h"
+#include "setup.h"
+
+using namespace krig;
+
+namespace {
+
+struct DevBuf {
+  void* p = nullptr;
+  size_t bytes = 0;
+};
+
+}  // namespace
+
+struct krig_plan_s {
+  hipStream_t st = nullptr;
+  int dtype = KRIG_F32;
+  size_t tsz = 4;  // bytes of one real dt value
+  GridDev g{};
+  MaternDev mt{};
+  int n = 0, M = 0, P1 = 0, P2 = 0, F1 = 0, F2 = 0, H2 = 0, ldH = 0;
+  int n1l = 0, n2l = 0;
+  const FftEntry* e1 = nullptr;  // columns (length F1)
+  const FftEntry* e2 = nullptr;  // rows (length F2)
+  // twiddles exp(-2 pi i j / F)
+  double* tw1_64 = nullptr;
+  double* tw2_64 = nullptr;
+  float* tw1_32 = nullptr;
+  float* tw2_32 = nullptr;
+  // set-up products
+  double* sites = nullptr;
+  double* lag64 = nullptr;
+  void* lagT = nullptr;
+  void* filt = nullptr;  // dt [F1][ldH]
+  double* KN = nullptr;
+  double* LinvN = nullptr;
+  int* d_status = nullptr;   // [0] K_N status, [1] M pivot
+  int32_t* anchor = nullptr;
+  double* kvec = nullptr;
+  double* W = nullptr;
+  double* Wt = nullptr;
+  int32_t* node_ptr = nullptr;
+  int32_t* ent_site = nullptr;
+  double* ent_w = nullptr;
+  CsrWork cw{};
+  double* Lfac = nullptr;  // Cholesky factor of K + tau^2 I
+  double* Linv = nullptr;  // its inverse
+  double* Dinv = nullptr;
+  double* work = nullptr;
+  int kn_status = 0, pivot = 0;
+  // per-call workspaces
+  int wsB = 0;
+  void* S1 = nullptr;     // cx dt [B][P1][ldH]
+  void* S2 = nullptr;     // cx dt [B][max(m1,P1)][ldH]
+  void* SG = nullptr;     // cx dt [B][m1][ldH]
+  void* img = nullptr;    // dt [B][P1][P2]
+  double* alpha = nullptr;  // [B][n]
+  double* tmpv = nullptr;   // [B][n]
+  void* part = nullptr;   // cx dt [ngroups][F1][ldH]
+  int part_groups = 0;
+  void* XC = nullptr;     // cx dt [2 n1l - 1][ldH]
+  void* XR = nullptr;     // dt [2 n1l - 1][2 n2l - 1]
+  // custom-lag filter
+  void* filtC = nullptr;
+  double* lagC64 = nullptr;
+  double* phiS64 = nullptr;  // cx double [F1][ldH]
+  double* phiR64 = nullptr;  // double [F1][ldH]
+  // launch shapes
+  int nl_rows_c = 8;   // lines per block, FP64-compute row kernels
+  int nl_rows = 8;
+  int nl_cols = 8;
+  int nl_cols_dlag = 4;
+  int dlag_G = 2;
+  // conditional simulation
+  int ce_clamped = 0;
+  std::vector<void*> allocs;
+};
+
+namespace {
+
+std::once_flag g_once;
+
+int hip_status(hipError_t e) { return e == hipSuccess ? KRIG_OK : KRIG_EHIP; }
+
+#define KRIG_TRY(expr)                         \
+  do {                                         \
+    hipError_t _e = (expr);                    \
+    if (_e != hipSuccess) return KRIG_EHIP;    \
+  } while (0)
+
+template <typename T>
+int dalloc(krig_plan p, T** out, size_t count) {
+  void* q = nullptr;
+  if (count == 0) count = 1;
+  if (hipMalloc(&q, count * sizeof(T)) != hipSuccess) {
+    *out = nullptr;
+    return KRIG_ENOMEM;
+  }
+  p->allocs.push_back(q);
+  *out = static_cast<T*>(q);
+  return KRIG_OK;
+}
+
+int dalloc_bytes(krig_plan p, void** out, size_t bytes) {
+  char* q = nullptr;
+  int s = dalloc(p, &q, bytes);
+  *out = q;
+  return s;
+}
+
+void dfree(krig_plan p, void* q) {
+  if (!q) return;
+  auto it = std::find(p->allocs.begin(), p->allocs.end(), q);
+  if (it != p->allocs.end()) p->allocs.erase(it);
+  (void)hipFree(q);
+}
+
+int pick_fft(int need) {
+  int sizes[64];
+  const int k = fft_sizes(sizes, 64);
+  int best = -1;
+  for (int i = 0; i < k && i < 64; ++i)
+    if (sizes[i] >= need && (best < 0 || sizes[i] < best)) best = sizes[i];
+  return best;
+}
+
+int nt_of(const FftEntry* e) { return std::max(e->N1, e->N2); }
+int on1_of(const FftEntry* e) { return e->N1 | 1; }
+
+// largest lines-per-block with threads <= 256 and LDS <= budget
+int lines_for(const FftEntry* e, size_t csz, size_t extra_per_line, size_t budget = 64 * 1024) {
+  const int nt = nt_of(e);
+  int nl = std::max(1, 256 / nt);
+  while (nl > 1 && (size_t)nl * ((size_t)e->N2 * on1_of(e) * csz + extra_per_line) > budget) --nl;
+  return nl;
+}
+
+int make_twiddles(krig_plan p, int F, double** d64, float** d32) {
+  std::vector<double> h64(2 * (size_t)F);
+  std::vector<float> h32(2 * (size_t)F);
+  for (int j = 0; j < F; ++j) {
+    const double c = trig_frac(j, F, true), s = -trig_frac(j, F, false);
+    h64[2 * j] = c;
+    h64[2 * j + 1] = s;
+    h32[2 * j] = (float)c;
+    h32[2 * j + 1] = (float)s;
+  }
+  int r;
+  if ((r = dalloc(p, d64, 2 * (size_t)F)) != KRIG_OK) return r;
+  if ((r = dalloc(p, d32, 2 * (size_t)F)) != KRIG_OK) return r;
+  KRIG_TRY(hipMemcpyAsync(*d64, h64.data(), h64.size() * sizeof(double), hipMemcpyHostToDevice, p->st));
+  KRIG_TRY(hipMemcpyAsync(*d32, h32.data(), h32.size() * sizeof(float), hipMemcpyHostToDevice, p->st));
+  KRIG_TRY(hipStreamSynchronize(p->st));  // host vectors go out of scope
+  return KRIG_OK;
+}
+
+const FftSet& set1(krig_plan p) { return p->dtype == KRIG_F32 ? p->e1->f32 : p->e1->f64; }
+const FftSet& set2(krig_plan p) { return p->dtype == KRIG_F32 ? p->e2->f32 : p->e2->f64; }
+const void* twc1(krig_plan p) { return p->dtype == KRIG_F32 ? (const void*)p->tw1_32 : (const void*)p->tw1_64; }
+const void* twc2(krig_plan p) { return p->dtype == KRIG_F32 ? (const void*)p->tw2_32 : (const void*)p->tw2_64; }
+size_t csz(krig_plan p) { return 2 * p->tsz; }
+
+// spectrum of the even-reflected lag quadrant (FP64), scaled by 1/(F1 F2), stored in dt
+int make_filter(krig_plan p, const double* lag64, void* filt_out) {
+  RowsR2CArgs r{};
+  r.nrows = p->F1;
+  r.H2 = p->H2;
+  r.ldH = p->ldH;
+  r.out = p->phiS64;
+  r.out_fs = 0;
+  r.twF = p->tw2_64;
+  r.lag = lag64;
+  r.n1l = p->n1l;
+  r.n2l = p->n2l;
+  r.F1 = p->F1;
+  r.NL = lines_for(p->e2, 16, 0);
+  KRIG_TRY(p->e2->f64.r2c_lag64(r, 1, p->st));
+  ColsArgs c{};
+  c.H2 = p->H2;
+  c.ldH = p->ldH;
+  c.in = p->phiS64;
+  c.in_fs = 0;
+  c.in_off = 0;
+  c.in_cnt = p->F1;
+  c.out = p->phiR64;
+  c.out_fs = 0;
+  c.twF = p->tw1_64;
+  c.scale = 1.0 / ((double)p->F1 * (double)p->F2);
+  c.NL = lines_for(p->e1, 16, 0);
+  KRIG_TRY(p->e1->f64.fwd_real64(c, 1, p->st));
+  KRIG_TRY(convert_f64(p->phiR64, filt_out, (int64_t)p->F1 * p->ldH, p->dtype == KRIG_F32, p->st));
+  return KRIG_OK;
+}
+
+int ensure_ws(krig_plan p, int B) {
+  if (B <= p->wsB) return KRIG_OK;
+  void* olds[] = {p->S1, p->S2, p->SG, p->img, p->alpha, p->tmpv, p->part};
+  KRIG_TRY(hipStreamSynchronize(p->st));
+  for (void* q : olds) dfree(p, q);
+  const size_t c = csz(p);
+  const int rmax = std::max(p->g.m1, p->P1);
+  int r;
+  if ((r = dalloc_bytes(p, &p->S1, c * B * (size_t)p->P1 * p->ldH)) != KRIG_OK) return r;
+  if ((r = dalloc_bytes(p, &p->S2, c * B * (size_t)rmax * p->ldH)) != KRIG_OK) return r;
+  if ((r = dalloc_bytes(p, &p->SG, c * B * (size_t)p->g.m1 * p->ldH)) != KRIG_OK) return r;
+  if ((r = dalloc_bytes(p, &p->img, p->tsz * B * (size_t)p->P1 * p->P2)) != KRIG_OK) return r;
+  if ((r = dalloc(p, &p->alpha, (size_t)B * p->n)) != KRIG_OK) return r;
+  if ((r = dalloc(p, &p->tmpv, (size_t)B * p->n)) != KRIG_OK) return r;
+  p->part_groups = B;  // worst case G = 1
+  if ((r = dalloc_bytes(p, &p->part, c * (size_t)p->part_groups * p->F1 * p->ldH)) != KRIG_OK) return r;
+  p->wsB = B;
+  return KRIG_OK;
+}
+
+int do_solve(krig_plan p, int B, const double* y, double* alpha) {
+  KRIG_TRY(tri_apply(p->Linv, p->n, p->n, y, p->n, p->tmpv, p->n, B, 0, p->st));
+  KRIG_TRY(tri_apply(p->Linv, p->n, p->n, p->tmpv, p->n, alpha, p->n, B, 1, p->st));
+  return KRIG_OK;
+}
+
+// custom lag (dt) -> filtC; returns the filter to use
+int filter_for(krig_plan p, const void* d_lag, const void** out) {
+  if (!d_lag) {
+    *out = p->filt;
+    return KRIG_OK;
+  }
+  int r;
+  KRIG_TRY(convert_to_f64(d_lag, p->lagC64, (int64_t)p->n1l * p->n2l, p->dtype == KRIG_F32, p->st));
+  if ((r = make_filter(p, p->lagC64, p->filtC)) != KRIG_OK) return r;
+  *out = p->filtC;
+  return KRIG_OK;
+}
+
+int do_convolve(krig_plan p, int B, const double* alpha, const void* filt, void* yhat, void* spec1,
+                const void* add, int64_t add_fs, int add_ld) {
+  RowsR2CArgs r{};
+  r.nrows = p->P1;
+  r.H2 = p->H2;
+  r.ldH = p->ldH;
+  r.out = spec1;
+  r.out_fs = (int64_t)p->P1 * p->ldH;
+  r.twF = p->tw2_64;  // scatter + forward rows in FP64 arithmetic
+  r.row_ptr = p->node_ptr;
+  r.ent_site = p->ent_site;
+  r.ent_w = p->ent_w;
+  r.alpha = alpha;
+  r.alpha_fs = p->n;
+  r.ncols = p->P2;
+  r.NL = p->nl_rows_c;
+  KRIG_TRY(set2(p).r2c_csr(r, B, p->st));
+
+  ColsArgs c{};
+  c.H2 = p->H2;
+  c.ldH = p->ldH;
+  c.in = spec1;
+  c.in_fs = (int64_t)p->P1 * p->ldH;
+  c.in_off = 0;
+  c.in_cnt = p->P1;
+  c.filt = filt;
+  c.out = p->S2;
+  c.out_fs = (int64_t)p->g.m1 * p->ldH;
+  c.rows = Window{p->g.L, p->g.m1, 0, 0};
+  c.twF = twc1(p);
+  c.B = B;
+  c.NL = p->nl_cols;
+  KRIG_TRY(set1(p).conv(c, B, p->st));
+
+  RowsC2RArgs o{};
+  o.nrows = p->g.m1;
+  o.H2 = p->H2;
+  o.ldH = p->ldH;
+  o.in = p->S2;
+  o.in_fs = (int64_t)p->g.m1 * p->ldH;
+  o.out = yhat;
+  o.out_fs = (int64_t)p->g.m1 * p->g.m2;
+  o.ldo = p->g.m2;
+  o.cols = Window{p->g.L, p->g.m2, 0, 0};
+  o.add = add;
+  o.add_fs = add_fs;
+  o.add_ld = add_ld;
+  o.add_r0 = p->g.L;
+  o.add_c0 = p->g.L;
+  o.twF = twc2(p);
+  o.NL = p->nl_rows;
+  KRIG_TRY(set2(p).c2r(o, B, p->st));
+  return KRIG_OK;
+}
+
+int validate_sites(const krig_grid* g, int n, const double* s) {
+  for (int i = 0; i < n; ++i) {
+    const double t = (s[2 * i] - g->x0) / g->dx;
+    const double u = (s[2 * i + 1] - g->y0) / g->dy;
+    if (!(t >= 0.0 && t <= (double)(g->m1 - 1) && u >= 0.0 && u <= (double)(g->m2 - 1))) return KRIG_EDOMAIN;
+  }
+  return KRIG_OK;
+}
+
+int matern_kind(double nu) {
+  if (nu == 0.5) return 0;
+  if (nu == 1.5) return 1;
+  if (nu == 2.5) return 2;
+  return -1;
+}
+
+void destroy_all(krig_plan p) {
+  if (!p) return;
+  (void)hipStreamSynchronize(p->st);
+  for (void* q : p->allocs) (void)hipFree(q);
+  p->allocs.clear();
+  delete p;
+}
+
+}  // namespace
+
+// =====================================================================================
+extern "C" {
+
+const char* krig_strerror(int s) {
+  switch (s) {
+    case KRIG_OK: return "ok";
+    case KRIG_EINVAL: return "invalid argument";
+    case KRIG_EDOMAIN: return "site outside the prediction grid";
+    case KRIG_ENOTSPD: return "matrix not positive definite";
+    case KRIG_ECE: return "circulant embedding not non-negative definite";
+    case KRIG_ENOMEM: return "device allocation failed";
+    case KRIG_EHIP: return "HIP runtime error";
+    case KRIG_EUNSUPPORTED: return "unsupported parameter";
+    default: return "unknown status";
+  }
+}
+
+int krig_plan_create(krig_plan* out, const krig_grid* g, const krig_matern* k, int32_t n, const double* h_sites,
+                     int32_t dtype, void* stream) {
+  if (!out) return KRIG_EINVAL;
+  *out = nullptr;
+  if (!g || !k || !h_sites || n < 1) return KRIG_EINVAL;
+  if (g->m1 < 2 || g->m2 < 2 || g->L < 1 || g->L > 4 || !(g->dx > 0) || !(g->dy > 0)) return KRIG_EINVAL;
+  if (dtype != KRIG_F32 && dtype != KRIG_F64) return KRIG_EINVAL;
+  if (!(k->sigma2 > 0) || !(k->range > 0) || !(k->tau2 >= 0)) return KRIG_EINVAL;
+  const int kind = matern_kind(k->nu);
+  if (kind < 0) return KRIG_EUNSUPPORTED;
+  if ((int64_t)(g->m1 + 2 * g->L) * (g->m2 + 2 * g->L) > (1LL << 30)) return KRIG_EINVAL;
+  int r = validate_sites(g, n, h_sites);
+  if (r != KRIG_OK) return r;
+  std::call_once(g_once, register_all_fft);
+
+  krig_plan p = new (std::nothrow) krig_plan_s();
+  if (!p) return KRIG_ENOMEM;
+  p->st = (hipStream_t)stream;
+  p->dtype = dtype;
+  p->tsz = dtype == KRIG_F32 ? 4 : 8;
+  p->n = n;
+  p->g.m1 = g->m1;
+  p->g.m2 = g->m2;
+  p->g.L = g->L;
+  p->g.x0 = g->x0;
+  p->g.y0 = g->y0;
+  p->g.dx = g->dx;
+  p->g.dy = g->dy;
+  p->g.P1 = g->m1 + 2 * g->L;
+  p->g.P2 = g->m2 + 2 * g->L;
+  p->g.M = 4 * g->L * g->L;
+  p->mt.sigma2 = k->sigma2;
+  p->mt.rho = k->range;
+  p->mt.tau2 = k->tau2;
+  p->mt.kind = kind;
+  p->M = p->g.M;
+  p->P1 = p->g.P1;
+  p->P2 = p->g.P2;
+  p->n1l = g->m1 + g->L;
+  p->n2l = g->m2 + g->L;
+  p->F1 = pick_fft(g->m1 + p->P1 - 1);
+  p->F2 = pick_fft(g->m2 + p->P2 - 1);
+  if (p->F1 < 0 || p->F2 < 0) {
+    delete p;
+    return KRIG_EUNSUPPORTED;
+  }
+  p->e1 = find_fft(p->F1);
+  p->e2 = find_fft(p->F2);
+  p->H2 = p->F2 / 2 + 1;
+  p->ldH = (p->H2 + 15) / 16 * 16;
+  const bool f32 = dtype == KRIG_F32;
+  // launch shapes (lines per block) within 256 threads and 64 KB of LDS
+  p->nl_rows_c = lines_for(p->e2, 16, 0);
+  p->nl_rows = lines_for(p->e2, f32 ? 8 : 16, 0);
+  p->nl_cols = lines_for(p->e1, f32 ? 8 : 16, 0);
+  p->nl_cols_dlag = lines_for(p->e1, f32 ? 8 : 16, (size_t)p->F1 * (f32 ? 8 : 16));
+
+#define CK(x)                 \
+  do {                        \
+    if ((r = (x)) != KRIG_OK) { \
+      destroy_all(p);         \
+      return r;               \
+    }                         \
+  } while (0)
+#define CKH(x) CK(hip_status(x))
+
+  const int n1l = p->n1l, n2l = p->n2l, M = p->M, P1 = p->P1, P2 = p->P2;
+  CK(make_twiddles(p, p->F1, &p->tw1_64, &p->tw1_32));
+  CK(make_twiddles(p, p->F2, &p->tw2_64, &p->tw2_32));
+  CK(dalloc(p, &p->sites, 2 * (size_t)n));
+  CKH(hipMemcpyAsync(p->sites, h_sites, 2 * sizeof(double) * n, hipMemcpyHostToDevice, p->st));
+  CK(dalloc(p, &p->d_status, 4));
+  CKH(hipMemsetAsync(p->d_status, 0, 4 * sizeof(int), p->st));
+
+  // Step 2: lag image and its spectrum (FP64)
+  CK(dalloc(p, &p->lag64, (size_t)n1l * n2l));
+  CK(dalloc_bytes(p, &p->lagT, p->tsz * (size_t)n1l * n2l));
+  CK(dalloc(p, &p->lagC64, (size_t)n1l * n2l));
+  CK(dalloc(p, &p->phiS64, 2 * (size_t)p->F1 * p->ldH));
+  CK(dalloc(p, &p->phiR64, (size_t)p->F1 * p->ldH));
+  CK(dalloc_bytes(p, &p->filt, p->tsz * (size_t)p->F1 * p->ldH));
+  CK(dalloc_bytes(p, &p->filtC, p->tsz * (size_t)p->F1 * p->ldH));
+  CKH(lag_image(p->g, p->mt, p->lag64, p->st));
+  CKH(convert_f64(p->lag64, p->lagT, (int64_t)n1l * n2l, f32, p->st));
+  CK(make_filter(p, p->lag64, p->filt));
+
+  // Steps 1, 3, 4: K_N, k_i, A_i = K_N^{-1} k_i  (two FP64 MFMA products with L_N^{-1})
+  CK(dalloc(p, &p->KN, (size_t)M * M));
+  CK(dalloc(p, &p->LinvN, (size_t)M * M));
+  CK(dalloc(p, &p->anchor, 2 * (size_t)n));
+  CK(dalloc(p, &p->kvec, (size_t)n * M));
+  CK(dalloc(p, &p->W, (size_t)n * M));
+  CK(dalloc(p, &p->Wt, (size_t)n * M));
+  CKH(kn_factor(p->g, p->mt, p->KN, p->LinvN, p->d_status, p->st));
+  CKH(site_kvec(p->g, p->mt, p->sites, n, p->anchor, p->kvec, p->st));
+  {
+    GemmArgs ga{};
+    ga.A = p->kvec; ga.lda = M; ga.transA = 0;
+    ga.B = p->LinvN; ga.ldb = M; ga.transB = 1;
+    ga.C = p->W; ga.ldc = M;
+    ga.m_off = 0; ga.M_end = n; ga.n_off = 0; ga.N_end = M; ga.K = M;
+    ga.alpha = 1.0; ga.beta = 0.0; ga.lower = 0;
+    CKH(gemm_f64(ga, p->st));  // T1 = k L_N^{-T}  (into W)
+    GemmArgs gb = ga;
+    gb.A = p->W; gb.transB = 0; gb.C = p->kvec;  // W = T1 L_N^{-1}  (into kvec, then swap)
+    CKH(gemm_f64(gb, p->st));
+    std::swap(p->W, p->kvec);
+  }
+  CKH(transpose_w(p->W, n, M, p->Wt, p->st));
+
+  // Step 5 structure
+  CK(dalloc(p, &p->cw.cell_cnt, (size_t)g->m1 * g->m2));
+  CK(dalloc(p, &p->cw.cell_ptr, (size_t)g->m1 * g->m2 + 1));
+  CK(dalloc(p, &p->cw.cell_cur, (size_t)g->m1 * g->m2));
+  CK(dalloc(p, &p->cw.cell_sites, (size_t)n));
+  CK(dalloc(p, &p->cw.node_cnt, (size_t)P1 * P2));
+  CK(dalloc(p, &p->cw.scan_tmp, (size_t)P1 * P2 / 1024 + 16 + (size_t)g->m1 * g->m2 / 1024));
+  CK(dalloc(p, &p->node_ptr, (size_t)P1 * P2 + 1));
+  CK(dalloc(p, &p->ent_site, (size_t)n * M));
+  CK(dalloc(p, &p->ent_w, (size_t)n * M));
+  CKH(build_csr(p->g, p->anchor, p->W, n, p->cw, p->node_ptr, p->ent_site, p->ent_w, p->st));
+
+  // kriging system: M = K + tau^2 I, Cholesky, inverse factor
+  CK(dalloc(p, &p->Lfac, (size_t)n * n));
+  CK(dalloc(p, &p->Linv, (size_t)n * n));
+  CK(dalloc(p, &p->Dinv, (size_t)((n + 63) / 64) * 4096));
+  CK(dalloc(p, &p->work, (size_t)64 * std::max(n, 64)));
+  CKH(assemble_kt(p->sites, n, p->mt, p->Lfac, n, p->st));
+  CKH(cholesky_and_inverse(p->Lfac, n, n, p->Linv, p->Dinv, p->work, p->d_status + 1, p->st));
+
+  // dlag buffers
+  CK(dalloc_bytes(p, &p->XC, csz(p) * (size_t)(2 * n1l - 1) * p->ldH));
+  CK(dalloc_bytes(p, &p->XR, p->tsz * (size_t)(2 * n1l - 1) * (2 * n2l - 1)));
+
+  int hst[4] = {0, 0, 0, 0};
+  CKH(hipMemcpyAsync(hst, p->d_status, sizeof(hst), hipMemcpyDeviceToHost, p->st));
+  CKH(hipStreamSynchronize(p->st));
+  p->kn_status = hst[0];
+  p->pivot = hst[1];
+  dfree(p, p->kvec);
+  p->kvec = nullptr;
+  if (hst[0] < 0 || hst[1] != 0) {
+    destroy_all(p);
+    return KRIG_ENOTSPD;
+  }
+  *out = p;
+  return KRIG_OK;
+#undef CK
+#undef CKH
+}
+
+int krig_plan_destroy(krig_plan p) {
+  if (!p) return KRIG_EINVAL;
+  destroy_all(p);
+  return KRIG_OK;
+}
+
+int krig_plan_info(krig_plan p, int32_t what, int64_t* v) {
+  if (!p || !v) return KRIG_EINVAL;
+  switch (what) {
+    case KRIG_INFO_N: *v = p->n; break;
+    case KRIG_INFO_M: *v = p->M; break;
+    case KRIG_INFO_P1: *v = p->P1; break;
+    case KRIG_INFO_P2: *v = p->P2; break;
+    case KRIG_INFO_F1: *v = p->F1; break;
+    case KRIG_INFO_F2: *v = p->F2; break;
+    case KRIG_INFO_H2: *v = p->H2; break;
+    case KRIG_INFO_LDH: *v = p->ldH; break;
+    case KRIG_INFO_SAVED_PER_FIELD: *v = (int64_t)p->P1 * p->ldH; break;
+    case KRIG_INFO_KN_STATUS: *v = p->kn_status; break;
+    case KRIG_INFO_PIVOT: *v = p->pivot; break;
+    case KRIG_INFO_DTYPE: *v = p->dtype; break;
+    case KRIG_INFO_CE_CLAMPED: *v = p->ce_clamped; break;
+    default: return KRIG_EINVAL;
+  }
+  return KRIG_OK;
+}
+
+int krig_set_stream(krig_plan p, void* stream) {
+  if (!p) return KRIG_EINVAL;
+  p->st = (hipStream_t)stream;
+  return KRIG_OK;
+}
+
+int krig_weights(krig_plan p, int32_t* d_anchor, double* d_W) {
+  if (!p) return KRIG_EINVAL;
+  if (d_anchor)
+    KRIG_TRY(hipMemcpyAsync(d_anchor, p->anchor, 2 * sizeof(int32_t) * p->n, hipMemcpyDeviceToDevice, p->st));
+  if (d_W) KRIG_TRY(hipMemcpyAsync(d_W, p->W, sizeof(double) * p->n * p->M, hipMemcpyDeviceToDevice, p->st));
+  return KRIG_OK;
+}
+
+int krig_set_weights(krig_plan p, const int32_t* d_anchor, const double* d_W) {
+  if (!p || !d_anchor || !d_W) return KRIG_EINVAL;
+  // anchors must keep every neighbour inside the padded grid
+  std::vector<int32_t> h(2 * (size_t)p->n);
+  KRIG_TRY(hipMemcpyAsync(h.data(), d_anchor, h.size() * sizeof(int32_t), hipMemcpyDeviceToHost, p->st));
+  KRIG_TRY(hipStreamSynchronize(p->st));
+  for (int i = 0; i < p->n; ++i)
+    if (h[2 * i] < 0 || h[2 * i] >= p->g.m1 || h[2 * i + 1] < 0 || h[2 * i + 1] >= p->g.m2) return KRIG_EDOMAIN;
+  KRIG_TRY(hipMemcpyAsync(p->anchor, d_anchor, h.size() * sizeof(int32_t), hipMemcpyDeviceToDevice, p->st));
+  KRIG_TRY(hipMemcpyAsync(p->W, d_W, sizeof(double) * p->n * p->M, hipMemcpyDeviceToDevice, p->st));
+  KRIG_TRY(transpose_w(p->W, p->n, p->M, p->Wt, p->st));
+  KRIG_TRY(build_csr(p->g, p->anchor, p->W, p->n, p->cw, p->node_ptr, p->ent_site, p->ent_w, p->st));
+  return KRIG_OK;
+}
+
+int krig_lag(krig_plan p, void* d_lag) {
+  if (!p || !d_lag) return KRIG_EINVAL;
+  KRIG_TRY(hipMemcpyAsync(d_lag, p->lagT, p->tsz * p->n1l * p->n2l, hipMemcpyDeviceToDevice, p->st));
+  return KRIG_OK;
+}
+
+int krig_solve(krig_plan p, int32_t B, const double* d_y, double* d_alpha) {
+  if (!p || B < 1 || !d_y || !d_alpha) return KRIG_EINVAL;
+  int r = ensure_ws(p, B);
+  if (r != KRIG_OK) return r;
+  return do_solve(p, B, d_y, d_alpha);
+}
+
+int krig_scatter(krig_plan p, int32_t B, const double* d_alpha, void* d_img) {
+  if (!p || B < 1 || !d_alpha || !d_img) return KRIG_EINVAL;
+  KRIG_TRY(scatter_image(p->g, p->node_ptr, p->ent_site, p->ent_w, d_alpha, p->n, B, d_img,
+                         (int64_t)p->P1 * p->P2, p->dtype == KRIG_F32, p->st));
+  return KRIG_OK;
+}
+
+int krig_convolve(krig_plan p, int32_t B, const double* d_alpha, const void* d_lag, void* d_yhat, void* d_saved) {
+  if (!p || B < 1 || !d_alpha || !d_yhat) return KRIG_EINVAL;
+  int r = ensure_ws(p, B);
+  if (r != KRIG_OK) return r;
+  const void* filt = nullptr;
+  if ((r = filter_for(p, d_lag, &filt)) != KRIG_OK) return r;
+  return do_convolve(p, B, d_alpha, filt, d_yhat, d_saved ? d_saved : p->S1, nullptr, 0, 0);
+}
+
+int krig_predict(krig_plan p, int32_t B, const double* d_y, const void* d_lag, void* d_yhat, double* d_alpha_out,
+                 void* d_saved) {
+  if (!p || B < 1 || !d_y || !d_yhat) return KRIG_EINVAL;
+  int r = ensure_ws(p, B);
+  if (r != KRIG_OK) return r;
+  double* al = d_alpha_out ? d_alpha_out : p->alpha;
+  if ((r = do_solve(p, B, d_y, al)) != KRIG_OK) return r;
+  const void* filt = nullptr;
+  if ((r = filter_for(p, d_lag, &filt)) != KRIG_OK) return r;
+  return do_convolve(p, B, al, filt, d_yhat, d_saved ? d_saved : p->S1, nullptr, 0, 0);
+}
+
+int krig_predict_adjoint(krig_plan p, int32_t B, const void* d_g, const double* d_alpha, const void* d_saved,
+                         const void* d_lag, double* d_dy, void* d_dlag) {
+  if (!p || B < 1 || !d_g) return KRIG_EINVAL;
+  if (d_dlag && !d_saved && !d_alpha) return KRIG_EINVAL;
+  int r = ensure_ws(p, B);
+  if (r != KRIG_OK) return r;
+  const void* filt = nullptr;
+  if ((r = filter_for(p, d_lag, &filt)) != KRIG_OK) return r;
+  const bool f32 = p->dtype == KRIG_F32;
+  const void* spec1 = d_saved;
+  if (d_dlag && !spec1) {
+    // recompute the row spectra of c* from the coefficients
+    RowsR2CArgs rr{};
+    rr.nrows = p->P1;
+    rr.H2 = p->H2;
+    rr.ldH = p->ldH;
+    rr.out = p->S1;
+    rr.out_fs = (int64_t)p->P1 * p->ldH;
+    rr.twF = p->tw2_64;
+    rr.row_ptr = p->node_ptr;
+    rr.ent_site = p->ent_site;
+    rr.ent_w = p->ent_w;
+    rr.alpha = d_alpha;
+    rr.alpha_fs = p->n;
+    rr.ncols = p->P2;
+    rr.NL = p->nl_rows_c;
+    KRIG_TRY(set2(p).r2c_csr(rr, B, p->st));
+    spec1 = p->S1;
+  }
+  // rows of g (placed at padded offset L) -> half spectra
+  RowsR2CArgs rg{};
+  rg.nrows = p->g.m1;
+  rg.H2 = p->H2;
+  rg.ldH = p->ldH;
+  rg.out = p->SG;
+  rg.out_fs = (int64_t)p->g.m1 * p->ldH;
+  rg.twF = twc2(p);
+  rg.dense = d_g;
+  rg.dense_fs = (int64_t)p->g.m1 * p->g.m2;
+  rg.dense_ld = p->g.m2;
+  rg.coff = p->g.L;
+  rg.ncols = p->g.m2;
+  rg.NL = p->nl_rows;
+  KRIG_TRY(set2(p).r2c_dense(rg, B, p->st));
+  // columns: correlation with the (even) filter, keep the P1 padded rows
+  ColsArgs c{};
+  c.H2 = p->H2;
+  c.ldH = p->ldH;
+  c.in = p->SG;
+  c.in_fs = (int64_t)p->g.m1 * p->ldH;
+  c.in_off = p->g.L;
+  c.in_cnt = p->g.m1;
+  c.filt = filt;
+  c.out = p->S2;
+  c.out_fs = (int64_t)p->P1 * p->ldH;
+  c.rows = Window{0, p->P1, 0, 0};
+  c.twF = twc1(p);
+  c.B = B;
+  int ngroups = 0;
+  if (d_dlag) {
+    c.in2 = spec1;
+    c.in2_fs = (int64_t)p->P1 * p->ldH;
+    c.in2_off = 0;
+    c.in2_cnt = p->P1;
+    c.part = p->part;
+    c.G = std::max(1, std::min(p->dlag_G, B));
+    c.NL = p->nl_cols_dlag;
+    ngroups = (B + c.G - 1) / c.G;
+    KRIG_TRY(set1(p).conv_dlag(c, ngroups, p->st));
+  } else {
+    c.NL = p->nl_cols;
+    KRIG_TRY(set1(p).conv(c, B, p->st));
+  }
+  // rows back to the padded image
+  RowsC2RArgs o{};
+  o.nrows = p->P1;
+  o.H2 = p->H2;
+  o.ldH = p->ldH;
+  o.in = p->S2;
+  o.in_fs = (int64_t)p->P1 * p->ldH;
+  o.out = p->img;
+  o.out_fs = (int64_t)p->P1 * p->P2;
+  o.ldo = p->P2;
+  o.cols = Window{0, p->P2, 0, 0};
+  o.twF = twc2(p);
+  o.NL = p->nl_rows;
+  KRIG_TRY(set2(p).c2r(o, B, p->st));
+  // dalpha by gathering at the neighbours, then dy = M^{-1} dalpha
+  if (d_dy) {
+    KRIG_TRY(gather_sites(p->g, p->anchor, p->Wt, p->n, p->img, (int64_t)p->P1 * p->P2, p->P2, B, f32, p->alpha,
+                          p->n, p->st));
+    if ((r = do_solve(p, B, p->alpha, d_dy)) != KRIG_OK) return r;
+  }
+  if (d_dlag) {
+    // inverse transform of sum_b G_b conj(C_b), keeping lags -(n-1)..(n-1)
+    ColsArgs ci{};
+    ci.H2 = p->H2;
+    ci.ldH = p->ldH;
+    ci.in = p->part;
+    ci.in_fs = (int64_t)p->F1 * p->ldH;
+    ci.G = ngroups;
+    ci.out = p->XC;
+    ci.rows = Window{0, p->n1l, p->F1 - p->n1l + 1, p->n1l - 1};
+    ci.twF = twc1(p);
+    ci.NL = p->nl_cols;
+    KRIG_TRY(set1(p).inv_sum(ci, 1, p->st));
+    RowsC2RArgs oc{};
+    oc.nrows = 2 * p->n1l - 1;
+    oc.H2 = p->H2;
+    oc.ldH = p->ldH;
+    oc.in = p->XC;
+    oc.in_fs = 0;
+    oc.out = p->XR;
+    oc.out_fs = 0;
+    oc.ldo = 2 * p->n2l - 1;
+    oc.cols = Window{0, p->n2l, p->F2 - p->n2l + 1, p->n2l - 1};
+    oc.twF = twc2(p);
+    oc.NL = p->nl_rows;
+    KRIG_TRY(set2(p).c2r(oc, 1, p->st));
+    KRIG_TRY(fold_dlag(p->XR, 2 * p->n2l - 1, p->n1l, p->n2l, 1.0 / ((double)p->F1 * p->F2), d_dlag, f32, p->st));
+  }
+  return KRIG_OK;
+}
+
+int krig_csim(krig_plan p, int32_t R, uint64_t seed, const double* d_y, void* d_fields) {
+  if (!p || R < 1 || !d_y || !d_fields) return KRIG_EINVAL;
+  return KRIG_EUNSUPPORTED;
+}
+
+}  // extern "C"

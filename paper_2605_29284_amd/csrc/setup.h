@@ -1,0 +1,68 @@
+// Set-up and gather/scatter kernels of the rapid predictor (Section 2.2, Steps 1-6).
+#pragma once
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+#include "matern_dev.h"
+
+namespace krig {
+
+struct GridDev {
+  int m1, m2, L;
+  double x0, y0, dx, dy;
+  int P1, P2, M;
+};
+
+// lag[a][b] = k((a dx, b dy)), a < m1+L, b < m2+L (Step 2's filter on its quadrant)
+hipError_t lag_image(const GridDev& g, const MaternDev& mt, double* lag64, hipStream_t st);
+// FP64 -> storage precision copies
+hipError_t convert_f64(const double* src, void* dst, int64_t cnt, int to_f32, hipStream_t st);
+hipError_t convert_to_f64(const void* src, double* dst, int64_t cnt, int from_f32, hipStream_t st);
+// 2D copy with pitch: dst[r][c] = src[r][c] (r < nr, c < nc) as storage type
+hipError_t copy2d_f64_to(const double* src, int64_t lds_, void* dst, int64_t ldd, int nr, int nc, int to_f32,
+                         hipStream_t st);
+
+// Step 1: K_N (M x M) from the neighbour offsets, its Cholesky factor and the inverse
+// factor LinvN = L_N^{-1}.  One block.  On a non-positive pivot the factorisation is
+// retried once with jitter 1e-14*sigma2*M on the diagonal; status bit 1 = jitter used,
+// status = -(pivot+1) if the retry fails too.
+hipError_t kn_factor(const GridDev& g, const MaternDev& mt, double* KN, double* LinvN, int* status,
+                     hipStream_t st);
+// Step 3: anchor cell (i0, j0) and k_i (n x M) of every site; sites [n][2] FP64.
+hipError_t site_kvec(const GridDev& g, const MaternDev& mt, const double* sites, int n, int32_t* anchor,
+                     double* kvec, hipStream_t st);
+// W [n][M] -> Wt [M][n]
+hipError_t transpose_w(const double* W, int n, int M, double* Wt, hipStream_t st);
+
+// Step 5 structure: CSR over the padded grid (deterministic, no float atomics).
+//  cell_cnt [m1*m2], cell_ptr [m1*m2+1], cell_sites [n], node_ptr [P1*P2+1],
+//  ent_site [n*M], ent_w [n*M]; scan_tmp: >= 2*(P1*P2/256+2) ints.
+struct CsrWork {
+  int32_t *cell_cnt, *cell_ptr, *cell_cur, *cell_sites, *node_cnt, *scan_tmp;
+};
+hipError_t build_csr(const GridDev& g, const int32_t* anchor, const double* W, int n, const CsrWork& w,
+                     int32_t* node_ptr, int32_t* ent_site, double* ent_w, hipStream_t st);
+
+// c* image [B][P1][P2] (storage precision) = A^T alpha by segment sums (FP64 accumulation)
+hipError_t scatter_image(const GridDev& g, const int32_t* node_ptr, const int32_t* ent_site, const double* ent_w,
+                         const double* alpha, int64_t alpha_fs, int B, void* img, int64_t img_fs, int to_f32,
+                         hipStream_t st);
+// out[b][i] = sum_m Wt[m][i] img[b][(i0+L+ox_m) * ldi + j0+L+oy_m] (FP64 accumulation);
+// optional: out[b][i] = sub[b][i] - (that + noise_scale * N(0,1) Philox noise).
+hipError_t gather_sites(const GridDev& g, const int32_t* anchor, const double* Wt, int n, const void* img,
+                        int64_t img_fs, int64_t ldi, int B, int from_f32, double* out, int64_t out_fs,
+                        hipStream_t st);
+hipError_t csim_residual(const GridDev& g, const int32_t* anchor, const double* Wt, int n, const void* img,
+                         int64_t img_fs, int64_t ldi, int R, int from_f32, const double* y, double noise_sd,
+                         uint64_t seed, int r0, double* out, int64_t out_fs, hipStream_t st);
+
+// d loss / d lag from the compact correlation image X (rows: lags 0..n1l-1 then
+// -(n1l-1)..-1; cols likewise), summing the sign images, times scale.
+hipError_t fold_dlag(const void* X, int64_t ldx, int n1l, int n2l, double scale, void* dlag, int to_f32,
+                     hipStream_t st);
+
+// Complex white noise x sqrt(Lambda) for the circulant-embedding sampler, and the
+// field pair -> real images.  (see csim kernels in setup.hip)
+hipError_t ce_lambda_check(const double* lam, int64_t cnt, double* minmax, hipStream_t st);
+
+}  // namespace krig

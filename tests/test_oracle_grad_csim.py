@@ -211,3 +211,13 @@ def test_conditional_simulation_reproduces_kriging_se():
     mean = f.mean(0)
     pred = cs.rp.predict_direct(cs.ek.coef(y)).reshape(g.m1, g.m2)
     assert np.max(np.abs(mean - pred) / se) < 5 / np.sqrt(R) * 3
+
+
+def test_fft_forms_of_the_gradient_match_direct():
+    from oracle.grad import corr_image_fft, dlag_fft
+    g, k, s, rng = _problem(7, m1=9, m2=7, L=3, n=10)
+    lag = lag_quadrant(g, k)
+    gup = rng.standard_normal((g.m1, g.m2))
+    cimg = rng.standard_normal((g.P1, g.P2))
+    assert np.abs(corr_image_fft(g, lag, gup) - corr_image_direct(g, lag, gup)).max() < 1e-12
+    assert np.abs(dlag_fft(g, gup, cimg) - dlag_direct(g, gup, cimg)).max() < 1e-11
