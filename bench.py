@@ -1,0 +1,207 @@
+"""Benchmark: grid predictions/s of the rapid Kriging predictor, forward + adjoint, on one GPU.
+
+    python bench.py [--steps K] [--warmup W] [--gpus 1] [--no-cpu-baseline]
+
+Workload (one step): the paper-sized field -- n = 1368 sites on [0,2] x [0,1],
+Matern nu = 2.5, range 0.3, nugget 0.05, 350 x 350 grid, L = 3 -- with a batch
+of B = 16 data vectors: y -> alpha (FP64 solve) -> scatter + FFT convolution ->
+y_hat, then the adjoint of an upstream gradient g = 2 m y_hat (loss sum m y_hat^2,
+m a seeded U[0,1] mask) -> dy (FP64 solve) and d lag.  Inputs are resident in
+HBM before timing.  Prints one JSON line.
+"""
+from __future__ import annotations
+
+import argparse
+import json
+import os
+import sys
+import time
+
+import numpy as np
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+HBM_PEAK_GBS = 8000.0  # MI355X HBM3E, GB/s
+
+
+def stage_bytes(p, B, ngroups):
+    """Algorithmic bytes per launch of each timed stage (what the pass must read and write)."""
+    t = 4 if p.dtype_code == 1 else 8
+    c = 2 * t
+    m1, m2, n, M = p.m1, p.m2, p.n, p.M
+    P1, P2, F1, H2 = p.P1, p.P2, p.F1, p.info("H2")
+    return {
+        "ROWS_FWD": B * (P1 * H2 * c + n * 8) + (P1 * P2 + 1) * 4 + n * M * 12,
+        "COLS_CONV": B * (P1 + m1) * H2 * c + F1 * H2 * t,
+        "ROWS_INV": B * (m1 * H2 * c + m1 * m2 * t),
+        "ADJ_ROWS_FWD": B * (m1 * m2 * t + m1 * H2 * c),
+        "ADJ_COLS": B * (m1 * H2 * c + 2 * P1 * H2 * c) + ngroups * F1 * H2 * c + F1 * H2 * t,
+        "ADJ_ROWS_INV": B * (P1 * H2 * c + P1 * P2 * t),
+        "GATHER": B * (n * M * t + n * 8) + n * M * 8 + n * 8,
+    }
+
+
+def cpu_baseline(w, nfields: int, reps: int = 3):
+    """The FP64 oracle (its FFT variants, single thread) on a bounded sample of fields."""
+    from threadpoolctl import threadpool_limits
+
+    from oracle.exact import ExactKriging
+    from oracle.grad import corr_image_fft, dlag_fft, grad_coef
+    from oracle.matern import Matern
+    from oracle.rapid import Grid, RapidPredictor, lag_quadrant, rapid_fft
+
+    with threadpool_limits(limits=1):
+        g = Grid(w.m1, w.m2, w.x0, w.y0, w.dx, w.dy, w.L)
+        k = Matern(w.sigma2, w.rho, w.nu, w.tau2)
+        ek = ExactKriging(w.sites, k)
+        rp = RapidPredictor(g, k, w.sites)
+        lag = lag_quadrant(g, k)
+        mask = w.extra["mask"]
+        t0 = time.perf_counter()
+        for b in [f % w.B for f in range(nfields * reps)]:
+            c = ek.coef(w.y[b])
+            cimg = rp.cstar(c)
+            yhat = rapid_fft(g, lag, cimg)
+            gup = 2.0 * mask * yhat
+            ek.coef(grad_coef(rp.A, corr_image_fft(g, lag, gup)))
+            dlag_fft(g, gup, cimg)
+        dt = time.perf_counter() - t0
+    return {"value": nfields * reps * w.m1 * w.m2 / dt, "unit": "grid predictions/s", "cores": 1, "kind": "oracle",
+            "sample": f"{nfields} of the {w.B} fields x {reps} passes, forward + adjoint (y -> y_hat, g -> dy, d lag) with the "
+                      f"oracle's FP64 FFT variants, one thread, {dt:.1f} s"}
+
+
+def main(argv=None):
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=20)
+    ap.add_argument("--warmup", type=int, default=5)
+    ap.add_argument("--B", type=int, default=16)
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--cpu-fields", type=int, default=16)
+    ap.add_argument("--no-fp64", action="store_true")
+    a = ap.parse_args(argv)
+    if a.gpus != 1:
+        print(f"bench.py measures one GPU only (asked for --gpus {a.gpus}); the batch axis would shard with no "
+              "communication, see the design notes.", file=sys.stderr)
+        return 2
+
+    import torch
+
+    import paper_2605_29284_amd as krig
+    import workloads as wl
+
+    if not torch.cuda.is_available():
+        print("no GPU visible", file=sys.stderr)
+        return 1
+    dev = torch.device("cuda:0")
+    w = wl.grad_batch(B=a.B)
+    B = a.B
+
+    def setup(dtype):
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        p = krig.plan_for(w, dtype)
+        torch.cuda.synchronize()
+        return p, (time.perf_counter() - t0) * 1e3
+
+    y = torch.as_tensor(w.y, dtype=torch.float64, device=dev)
+
+    def buffers(p):
+        td = p.tdtype
+        return dict(alpha=torch.empty(B, w.n, dtype=torch.float64, device=dev), saved=p.new_saved(B),
+                    yhat=torch.empty(B, w.m1, w.m2, dtype=td, device=dev),
+                    dy=torch.empty(B, w.n, dtype=torch.float64, device=dev),
+                    dlag=torch.empty(w.m1 + w.L, w.m2 + w.L, dtype=td, device=dev))
+
+    def run(p, bf, g, steps, hot=False):
+        for _ in range(steps):
+            if hot:  # alpha given: scatter + convolution and its adjoint only
+                p.convolve(bf["alpha"], saved=bf["saved"], out=bf["yhat"])
+                p.adjoint(g, alpha=bf["alpha"], saved=bf["saved"], want_dy=False, dlag_out=bf["dlag"])
+            else:
+                p.predict(y, alpha_out=bf["alpha"], saved=bf["saved"], out=bf["yhat"])
+                p.adjoint(g, alpha=bf["alpha"], saved=bf["saved"], dy_out=bf["dy"], dlag_out=bf["dlag"])
+
+    def timed(p, bf, g, steps, hot=False):
+        s, e = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        torch.cuda.synchronize()
+        s.record()
+        run(p, bf, g, steps, hot)
+        e.record()
+        torch.cuda.synchronize()
+        return s.elapsed_time(e) / steps
+
+    mask = torch.as_tensor(w.extra["mask"], device=dev)
+    res = {}
+    for dtype in (("f32",) if a.no_fp64 else ("f32", "f64")):
+        p, setup_ms = setup(dtype)
+        bf = buffers(p)
+        p.predict(y, alpha_out=bf["alpha"], saved=bf["saved"], out=bf["yhat"])
+        g = (2.0 * mask.to(p.tdtype) * bf["yhat"]).contiguous()  # upstream gradient, fixed over the steps
+        run(p, bf, g, a.warmup)
+        ms = timed(p, bf, g, a.steps)
+        hot_ms = timed(p, bf, g, a.steps, hot=True)
+        # per-stage kernel times (HIP events around each launch, same stream)
+        p.timing(True)
+        run(p, bf, g, a.steps)
+        stages = p.timing_read()
+        p.timing(False)
+        run(p, bf, g, 1)
+        torch.cuda.synchronize()
+        res[dtype] = dict(plan=p, ms=ms, hot_ms=hot_ms, setup_ms=setup_ms, stages=stages,
+                          yhat=bf["yhat"].double().cpu().numpy(), dy=bf["dy"].cpu().numpy(),
+                          dlag=bf["dlag"].double().cpu().numpy())
+
+    r32 = res["f32"]
+    p32 = r32["plan"]
+    npred = B * w.m1 * w.m2
+    value = npred / (r32["ms"] * 1e-3)
+    # dominant single-kernel stage and its roofline
+    ng = (B + 1) // 2
+    sb = stage_bytes(p32, B, ng)
+    avg = {k: (v[0] / v[1]) for k, v in r32["stages"].items() if v[1] > 0}
+    dom = max((k for k in sb if k in avg), key=lambda k: avg[k])
+    achieved = sb[dom] / (avg[dom] * 1e-3) / 1e9
+    out = {
+        "metric": "grid predictions/s fwd+adjoint, FP32 vs FP64 at rel err <=1e-5; % HBM peak",
+        "value": value,
+        "unit": "grid predictions/s",
+        "n_gpus": 1,
+        "steps": a.steps,
+        "warmup": a.warmup,
+        "ms_per_step": r32["ms"],
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f32",
+        "data": "synthetic",
+        "config": {"workload": "grad-batch: paper-sized field, n=1368 sites on [0,2]x[0,1], Matern nu=2.5 "
+                               "range 0.3 nugget 0.05, 350x350 grid, L=3 (M=36), B=16 fields, "
+                               "forward (y->y_hat) + adjoint (g->dy, dlag)",
+                   "B": B, "n": w.n, "grid": [w.m1, w.m2], "L": w.L, "fft": [p32.F1, p32.F2]},
+        "roofline": {"bound": "hbm", "kernel": dom, "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                     "frac": achieved / HBM_PEAK_GBS, "traffic": None,
+                     "bytes_per_launch": sb[dom], "avg_launch_ms": avg[dom]},
+        "hot_path_value": npred / (r32["hot_ms"] * 1e-3),
+        "setup_ms": r32["setup_ms"],
+        "stage_avg_ms": {k: round(v, 5) for k, v in avg.items()},
+        "stage_gbs": {k: round(sb[k] / (avg[k] * 1e-3) / 1e9, 1) for k in sb if k in avg},
+    }
+    if "f64" in res:
+        r64 = res["f64"]
+        rel = lambda x, y: float(np.max(np.abs(x - y)) / np.max(np.abs(y)))
+        out["fp64_value"] = npred / (r64["ms"] * 1e-3)
+        out["fp64_ms_per_step"] = r64["ms"]
+        out["fp32_vs_fp64_rel_err"] = {
+            "yhat": max(rel(r32["yhat"][b], r64["yhat"][b]) for b in range(B)),
+            "dy": rel(r32["dy"], r64["dy"]), "dlag": rel(r32["dlag"], r64["dlag"])}
+    if not a.no_cpu_baseline:
+        out["cpu_baseline"] = cpu_baseline(w, a.cpu_fields)
+    print(json.dumps(out), flush=True)
+    return 0
+
+
+if __name__ == "__main__":
+    sys.exit(main())

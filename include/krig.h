@@ -74,7 +74,7 @@ typedef struct krig_plan_s *krig_plan;
 enum {
   KRIG_INFO_N = 1, KRIG_INFO_M, KRIG_INFO_P1, KRIG_INFO_P2, KRIG_INFO_F1, KRIG_INFO_F2, KRIG_INFO_H2,
   KRIG_INFO_LDH,        /* row pitch (elements) of half-spectrum buffers */
-  KRIG_INFO_SAVED_PER_FIELD, /* elements (complex dt) per field of the saved forward spectrum */
+  KRIG_INFO_SAVED_PER_FIELD, /* elements (complex FP64) per field of the saved forward spectrum */
   KRIG_INFO_KN_STATUS,  /* 0 clean, 1 jitter added to K_N */
   KRIG_INFO_PIVOT,      /* first failing pivot (1-based) of K + tau^2 I, 0 if none */
   KRIG_INFO_DTYPE,
@@ -142,8 +142,13 @@ int krig_scatter(krig_plan p, int32_t B, const double *d_alpha, void *d_img);
  * Rapid prediction from coefficients (Steps 5-7): d_alpha [B][n] FP64 ->
  * d_yhat [B][m1][m2] dt.  d_lag: NULL to use the plan's lag image, else a
  * caller lag quadrant (m1+L) x (m2+L) in dt whose spectrum is recomputed (FP64).
- * d_saved: NULL, or a buffer of B * KRIG_INFO_SAVED_PER_FIELD complex dt that
- * receives the row spectra of c* for krig_predict_adjoint.
+ * d_saved: NULL, or a buffer of B * KRIG_INFO_SAVED_PER_FIELD complex FP64 values
+ * that receives the row spectra of c* for krig_predict_adjoint.
+ * Precision: the scatter, the forward row transforms and the forward column
+ * transforms run in FP64 arithmetic with FP64 storage; in a KRIG_F32 plan the
+ * product with the filter spectrum is rounded to FP32 and the inverse column and
+ * row transforms run in FP32 (the prediction is a cancellation-heavy sum, so the
+ * forward half decides the accuracy).
  */
 int krig_convolve(krig_plan p, int32_t B, const double *d_alpha, const void *d_lag, void *d_yhat,
                   void *d_saved);
@@ -164,7 +169,10 @@ int krig_predict(krig_plan p, int32_t B, const double *d_y, const void *d_lag, v
  *                               (NULL to skip; summed over the batch; needs the
  *                               coefficients: d_saved from krig_predict, or
  *                               d_alpha [B][n] FP64 to recompute c*).
- * A and the coefficients are held fixed with respect to the lag.
+ * A and the coefficients are held fixed with respect to the lag.  The adjoint runs
+ * in FP64 arithmetic and storage for both dtypes (dy is (K + tau^2 I)^{-1} applied to
+ * the gathered correlation, which amplifies any FP32 rounding of that image by the
+ * system's condition number); only d_g and d_dlag are in dt.
  */
 int krig_predict_adjoint(krig_plan p, int32_t B, const void *d_g, const double *d_alpha,
                          const void *d_saved, const void *d_lag, double *d_dy, void *d_dlag);
@@ -181,6 +189,29 @@ int krig_predict_adjoint(krig_plan p, int32_t B, const void *d_g, const double *
  * enlarged up to twice, then KRIG_ECE.  d_y [n] FP64.
  */
 int krig_csim(krig_plan p, int32_t R, uint64_t seed, const double *d_y, void *d_fields);
+
+/* Pipeline stages whose kernel launches can be timed (krig_timing_*). */
+enum {
+  KRIG_STAGE_ROWS_FWD = 0,   /* scatter of alpha_i w_im fused with the forward row transforms */
+  KRIG_STAGE_COLS_CONV,      /* column pass: forward transform, x filter, inverse (prediction) */
+  KRIG_STAGE_ROWS_INV,       /* inverse row transforms, crop to the m1 x m2 grid */
+  KRIG_STAGE_ADJ_ROWS_FWD,   /* adjoint: forward row transforms of the upstream gradient */
+  KRIG_STAGE_ADJ_COLS,       /* adjoint: column pass (correlation, and lag-gradient spectra) */
+  KRIG_STAGE_ADJ_ROWS_INV,   /* adjoint: inverse row transforms to the padded grid */
+  KRIG_STAGE_GATHER,         /* adjoint: gather at the neighbours (d alpha) */
+  KRIG_STAGE_SOLVE,          /* FP64 applications of the inverse Cholesky factor */
+  KRIG_STAGE_DLAG_TAIL,      /* lag gradient: inverse transforms of the summed spectra + fold */
+  KRIG_STAGE_COUNT
+};
+
+/*
+ * Per-stage kernel timing: while enabled, every launch of a stage is bracketed by
+ * two HIP events on the plan's stream.  krig_timing_read synchronises on them and
+ * returns the summed elapsed milliseconds and the number of launches since the
+ * last read (then resets that stage).  Events are created on first use.
+ */
+int krig_timing_enable(krig_plan p, int32_t on);
+int krig_timing_read(krig_plan p, int32_t stage, double *total_ms, int64_t *launches);
 
 /* Human-readable text for a status code (static storage). */
 const char *krig_strerror(int status);

@@ -27,7 +27,10 @@ STATUS = {0: "KRIG_OK", -1: "KRIG_EINVAL", -2: "KRIG_EDOMAIN", -3: "KRIG_ENOTSPD
 
 EXPORTS = ["krig_plan_create", "krig_plan_destroy", "krig_plan_info", "krig_set_stream", "krig_weights",
            "krig_set_weights", "krig_lag", "krig_solve", "krig_scatter", "krig_convolve", "krig_predict",
-           "krig_predict_adjoint", "krig_csim", "krig_strerror"]
+           "krig_predict_adjoint", "krig_csim", "krig_timing_enable", "krig_timing_read", "krig_strerror"]
+
+STAGES = ["ROWS_FWD", "COLS_CONV", "ROWS_INV", "ADJ_ROWS_FWD", "ADJ_COLS", "ADJ_ROWS_INV", "GATHER", "SOLVE",
+          "DLAG_TAIL"]
 
 
 class KrigError(RuntimeError):
@@ -73,6 +76,8 @@ def load_library(path: str = LIB_PATH) -> ctypes.CDLL:
         "krig_predict": [vp, i32, dp, dp, dp, dp, dp],
         "krig_predict_adjoint": [vp, i32, dp, dp, dp, dp, dp, dp],
         "krig_csim": [vp, i32, ctypes.c_uint64, dp, dp],
+        "krig_timing_enable": [vp, i32],
+        "krig_timing_read": [vp, i32, ctypes.POINTER(ctypes.c_double), ctypes.POINTER(i64)],
     }
     for name, args in sig.items():
         f = getattr(lib, name)
@@ -209,15 +214,15 @@ class Plan:
         return self._t(lag, self.tdtype, (self.m1 + self.L, self.m2 + self.L), "lag").data_ptr()
 
     def new_saved(self, B: int):
-        """Buffer for the forward row spectra kept for the adjoint (complex dt)."""
-        return self.empty(B, self.saved_per_field, 2)
+        """Buffer for the forward row spectra kept for the adjoint (complex FP64)."""
+        return self.empty(B, self.saved_per_field, 2, dtype=self.torch.float64)
 
     def convolve(self, alpha, lag=None, saved=None, out=None):
         alpha = self._batch(alpha, (self.n,), "alpha", self.torch.float64)
         B = alpha.shape[0]
         out = self.empty(B, self.m1, self.m2) if out is None else self._t(out, self.tdtype, (B, self.m1, self.m2), "out")
         if saved is not None:
-            self._t(saved, self.tdtype, (B, self.saved_per_field, 2), "saved")
+            self._t(saved, self.torch.float64, (B, self.saved_per_field, 2), "saved")
         self._stream()
         _check(self.lib.krig_convolve(self.h, B, alpha.data_ptr(), self._lag_ptr(lag), out.data_ptr(),
                                       _ptr(saved)), "krig_convolve")
@@ -230,7 +235,7 @@ class Plan:
         if alpha_out is not None:
             self._t(alpha_out, self.torch.float64, (B, self.n), "alpha_out")
         if saved is not None:
-            self._t(saved, self.tdtype, (B, self.saved_per_field, 2), "saved")
+            self._t(saved, self.torch.float64, (B, self.saved_per_field, 2), "saved")
         self._stream()
         _check(self.lib.krig_predict(self.h, B, y.data_ptr(), self._lag_ptr(lag), out.data_ptr(), _ptr(alpha_out),
                                      _ptr(saved)), "krig_predict")
@@ -243,7 +248,7 @@ class Plan:
         if alpha is not None:
             self._t(alpha, self.torch.float64, (B, self.n), "alpha")
         if saved is not None:
-            self._t(saved, self.tdtype, (B, self.saved_per_field, 2), "saved")
+            self._t(saved, self.torch.float64, (B, self.saved_per_field, 2), "saved")
         dy = None
         if want_dy:
             dy = self.empty(B, self.n, dtype=self.torch.float64) if dy_out is None else dy_out
@@ -254,6 +259,20 @@ class Plan:
         _check(self.lib.krig_predict_adjoint(self.h, B, g.data_ptr(), _ptr(alpha), _ptr(saved), self._lag_ptr(lag),
                                              _ptr(dy), _ptr(dlag)), "krig_predict_adjoint")
         return dy, dlag
+
+    def timing(self, on: bool):
+        """Bracket every stage launch with HIP events on the plan's stream."""
+        _check(self.lib.krig_timing_enable(self.h, 1 if on else 0), "krig_timing_enable")
+
+    def timing_read(self):
+        """{stage: (total_ms, launches)} since the last read (synchronises)."""
+        out = {}
+        for i, name in enumerate(STAGES):
+            ms = ctypes.c_double()
+            cnt = ctypes.c_int64()
+            _check(self.lib.krig_timing_read(self.h, i, ctypes.byref(ms), ctypes.byref(cnt)), "krig_timing_read")
+            out[name] = (float(ms.value), int(cnt.value))
+        return out
 
     def csim(self, R: int, seed: int, y):
         y = self._t(y, self.torch.float64, (self.n,), "y")

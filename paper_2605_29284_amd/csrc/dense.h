@@ -31,7 +31,9 @@ hipError_t cholesky_and_inverse(double* A, int64_t lda, int n, double* Linv, dou
 hipError_t copy_rows(const double* src, int64_t ld_src, double* dst, int64_t ld_dst, int nr, int nc,
                      hipStream_t st);
 hipError_t fill_f64(double* p, int64_t cnt, double v, hipStream_t st);
+// part: workspace of tri_chunks(n) * B * n doubles
+int tri_chunks(int n);
 hipError_t tri_apply(const double* X, int64_t ldx, int n, const double* in, int64_t in_fs, double* out,
-                     int64_t out_fs, int B, int trans, hipStream_t st);
+                     int64_t out_fs, int B, int trans, double* part, hipStream_t st);
 
 }  // namespace krig

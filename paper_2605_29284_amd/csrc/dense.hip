@@ -18,7 +18,8 @@ typedef double double4_t __attribute__((ext_vector_type(4)));
 // K staged through LDS 16 at a time.  LOWER restricts the launch to tiles with
 // tile_col <= tile_row (symmetric rank-k updates).
 // MFMA operand layout (v_mfma_f64_16x16x4f64): lane l supplies A[l%16][l/16] and
-// B[l/16][l%16]; result register r of lane l is D[4*(l/16) + r][l%16].
+// B[l/16][l%16]; result register r of lane l is D[l/16 + 4*r][l%16] (FP64 form: rows
+// interleave across the four lane groups, unlike the FP32 16x16 forms).
 // ------------------------------------------------------------------------------------
 __global__ void __launch_bounds__(256) k_gemm_f64(GemmArgs g) {
   __shared__ double As[16][64 + 1];   // [k][m]
@@ -71,7 +72,7 @@ __global__ void __launch_bounds__(256) k_gemm_f64(GemmArgs g) {
   for (int i = 0; i < 2; ++i)
     for (int j = 0; j < 2; ++j)
       for (int r = 0; r < 4; ++r) {
-        const int gm = m0 + wm + i * 16 + 4 * (lane >> 4) + r;
+        const int gm = m0 + wm + i * 16 + (lane >> 4) + 4 * r;
         const int gn = n0 + wn + j * 16 + (lane & 15);
         if (gm < g.M_end && gn < g.N_end) {
           if (g.lower && gn > gm) continue;
@@ -289,56 +290,85 @@ hipError_t copy_rows(const double* src, int64_t ld_src, double* dst, int64_t ld_
 }
 
 // ------------------------------------------------------------------------------------
-// apply the explicit inverse factor to B right-hand sides
+// apply the explicit inverse factor to B right-hand sides (FP64 MFMA, split over K)
 //   trans = 0:  out[b][i] = sum_{k <= i} X[i][k] in[b][k]      (L^{-1} y)
 //   trans = 1:  out[b][i] = sum_{k >= i} X[k][i] in[b][k]      (L^{-T} y)
-// One block per 16 output entries; 16 k-lanes per output; fields in chunks of 8.
+// X is lower triangular with explicit zeros above the diagonal, so only whole
+// tiles outside the triangle are skipped.  Block (col tile j of 64, K chunk c,
+// field group z of 16): four waves, each a 16 x 16 MFMA tile (fields x columns);
+// the partial sums of chunk c go to part[c][b][i] and are reduced in a fixed order.
 // ------------------------------------------------------------------------------------
-__global__ void __launch_bounds__(256) k_tri_apply(const double* __restrict__ X, int64_t ldx, int n,
-                                                   const double* __restrict__ in, int64_t in_fs,
-                                                   double* __restrict__ out, int64_t out_fs, int B, int trans) {
-  __shared__ double red[16][16][9];
-  const int tid = threadIdx.x;
-  const int c = tid & 15, kl = tid >> 4;
-  const int i = blockIdx.x * 16 + c;
-  for (int f0 = 0; f0 < B; f0 += 8) {
-    double acc[8];
-#pragma unroll
-    for (int f = 0; f < 8; ++f) acc[f] = 0.0;
-    if (i < n) {
-      if (!trans) {
-        for (int k = kl; k <= i; k += 16) {
-          const double x = X[(int64_t)i * ldx + k];
-#pragma unroll
-          for (int f = 0; f < 8; ++f)
-            if (f0 + f < B) acc[f] += x * in[(int64_t)(f0 + f) * in_fs + k];
-        }
-      } else {
-        for (int k = i + kl; k < n; k += 16) {
-          const double x = X[(int64_t)k * ldx + i];
-#pragma unroll
-          for (int f = 0; f < 8; ++f)
-            if (f0 + f < B) acc[f] += x * in[(int64_t)(f0 + f) * in_fs + k];
-        }
-      }
+constexpr int TRI_KC = 256;
+
+template <int TRANS>
+__global__ void __launch_bounds__(256) k_tri_mm(const double* __restrict__ X, int64_t ldx, int n,
+                                                const double* __restrict__ in, int64_t in_fs, int B,
+                                                double* __restrict__ part) {
+  __shared__ double xs[16][64 + 1];   // [k][col]
+  __shared__ double ys[16][16 + 1];   // [k][field]
+  const int i0 = blockIdx.x * 64;
+  const int kc0 = blockIdx.y * TRI_KC;
+  const int f0 = blockIdx.z * 16;
+  const int tid = threadIdx.x, wave = tid >> 6, lane = tid & 63;
+  int kb = kc0, ke = min(kc0 + TRI_KC, n);
+  if (TRANS == 0) ke = min(ke, i0 + 64);   // k <= i
+  else kb = max(kb, i0);                    // k >= i
+  double4_t acc = (double4_t){0.0, 0.0, 0.0, 0.0};
+  for (int k0 = kb; k0 < ke; k0 += 16) {
+    for (int e = tid; e < 16 * 64; e += 256) {
+      int kk, cc;
+      if (TRANS == 0) { kk = e % 16; cc = e / 16; } else { cc = e % 64; kk = e / 64; }
+      const int k = k0 + kk, i = i0 + cc;
+      double v = 0.0;
+      if (k < ke && i < n) v = TRANS == 0 ? X[(int64_t)i * ldx + k] : X[(int64_t)k * ldx + i];
+      xs[kk][cc] = v;
     }
-#pragma unroll
-    for (int f = 0; f < 8; ++f) red[kl][c][f] = acc[f];
+    {
+      const int kk = tid % 16, ff = tid / 16;  // 256 threads = 16 x 16
+      const int k = k0 + kk, f = f0 + ff;
+      ys[kk][ff] = (k < ke && f < B) ? in[(int64_t)f * in_fs + k] : 0.0;
+    }
     __syncthreads();
-    if (kl < 8) {
-      const int f = kl;
-      double s = 0.0;
-      for (int q = 0; q < 16; ++q) s += red[q][c][f];  // fixed order
-      if (i < n && f0 + f < B) out[(int64_t)(f0 + f) * out_fs + i] = s;
+#pragma unroll
+    for (int kq = 0; kq < 16; kq += 4) {
+      const double a = ys[kq + (lane >> 4)][lane & 15];
+      const double b = xs[kq + (lane >> 4)][wave * 16 + (lane & 15)];
+      acc = __builtin_amdgcn_mfma_f64_16x16x4f64(a, b, acc, 0, 0, 0);
     }
     __syncthreads();
   }
+  const int i = i0 + wave * 16 + (lane & 15);
+  for (int r = 0; r < 4; ++r) {
+    const int f = f0 + (lane >> 4) + 4 * r;
+    if (f < B && i < n) part[((int64_t)blockIdx.y * B + f) * n + i] = acc[r];
+  }
 }
 
+__global__ void k_chunk_reduce(const double* __restrict__ part, int nchunk, int B, int n, double* __restrict__ out,
+                               int64_t out_fs) {
+  const int64_t idx = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (idx >= (int64_t)B * n) return;
+  const int b = (int)(idx / n), i = (int)(idx % n);
+  double s = 0.0;
+  for (int c = 0; c < nchunk; ++c) s += part[((int64_t)c * B + b) * n + i];  // fixed order
+  out[(int64_t)b * out_fs + i] = s;
+}
+
+int tri_chunks(int n) { return (n + TRI_KC - 1) / TRI_KC; }
+
 hipError_t tri_apply(const double* X, int64_t ldx, int n, const double* in, int64_t in_fs, double* out,
-                     int64_t out_fs, int B, int trans, hipStream_t st) {
-  hipLaunchKernelGGL(k_tri_apply, dim3((n + 15) / 16), dim3(256), 0, st, X, ldx, n, in, in_fs, out, out_fs, B,
-                     trans);
+                     int64_t out_fs, int B, int trans, double* part, hipStream_t st) {
+  const int nch = tri_chunks(n);
+  dim3 grid((n + 63) / 64, nch, (B + 15) / 16);
+  if (trans)
+    hipLaunchKernelGGL(k_tri_mm<1>, grid, dim3(256), 0, st, X, ldx, n, in, in_fs, B, part);
+  else
+    hipLaunchKernelGGL(k_tri_mm<0>, grid, dim3(256), 0, st, X, ldx, n, in, in_fs, B, part);
+  hipError_t e = hipGetLastError();
+  if (e != hipSuccess) return e;
+  const int64_t tot = (int64_t)B * n;
+  hipLaunchKernelGGL(k_chunk_reduce, dim3((unsigned)((tot + 255) / 256)), dim3(256), 0, st, part, nch, B, n, out,
+                     out_fs);
   return hipGetLastError();
 }
 

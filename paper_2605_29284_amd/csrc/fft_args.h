@@ -60,7 +60,8 @@ struct ColsArgs {
   void* part;             // cx<TS> [ngroups][F][ldH] dlag partial spectra
   int G;                  // fields per block (dlag)
   int B;                  // total fields
-  const void* twF;        // cx<TC> [F]
+  const void* twF;        // cx<TF> [F] twiddles of the forward transform's precision
+  const void* twI;        // cx<TI> [F] twiddles of the inverse transform's precision
   double scale;           // store scale (setup transforms)
   int NL;                 // columns per block
 };
@@ -85,21 +86,26 @@ typedef hipError_t (*launch_rows_r2c_t)(const RowsR2CArgs&, int B, hipStream_t);
 typedef hipError_t (*launch_cols_t)(const ColsArgs&, int nblk_y, hipStream_t);
 typedef hipError_t (*launch_rows_c2r_t)(const RowsC2RArgs&, int B, hipStream_t);
 
-// Kernels for one transform length, one storage precision.
+// Kernels for one transform length.  Arithmetic and storage precisions are fixed
+// per role: everything is FP64 except the inverse half of the prediction's column
+// pass and the prediction's inverse rows in the FP32 form.
 struct FftSet {
-  launch_rows_r2c_t r2c_csr;     // scatter + forward rows (compute FP64)
-  launch_rows_r2c_t r2c_dense;   // dense rows (compute = storage precision)
-  launch_rows_r2c_t r2c_lag64;   // even-reflected lag, FP64 compute and FP64 output
-  launch_cols_t conv;            // fwd, x filter, inv
-  launch_cols_t conv_dlag;       // same + sum_b conj(C_b) G_b partial spectra
-  launch_cols_t fwd_real64;      // FP64: forward columns, store Re * scale as FP64 [F][ldH]
-  launch_cols_t inv_sum;         // inverse columns of the sum of partial spectra
-  launch_rows_c2r_t c2r;         // inverse rows
+  launch_rows_r2c_t r2c_csr;        // scatter + forward rows, FP64 -> FP64 spectra
+  launch_rows_r2c_t r2c_dense_f32;  // FP32 rows (upstream gradient) -> FP64 spectra
+  launch_rows_r2c_t r2c_dense_f64;  // FP64 rows -> FP64 spectra
+  launch_rows_r2c_t r2c_lag;        // even-reflected lag quadrant, FP64
+  launch_cols_t conv_mixed;         // FP64 forward, x filter, FP32 inverse, FP32 out
+  launch_cols_t conv64;             // all FP64
+  launch_cols_t conv_dlag64;        // all FP64, plus sum_b G_b conj(C_b) partial spectra
+  launch_cols_t fwd_real64;         // forward columns, store Re * scale (FP64)
+  launch_cols_t inv_sum64;          // inverse columns of a sum of partial spectra (FP64)
+  launch_rows_c2r_t c2r32;          // inverse rows, FP32
+  launch_rows_c2r_t c2r64;          // inverse rows, FP64
 };
 
 struct FftEntry {
   int F, N1, N2;
-  FftSet f32, f64;
+  FftSet k;
 };
 
 // size registry (filled by the generated per-size translation units)

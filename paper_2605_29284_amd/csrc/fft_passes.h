@@ -51,7 +51,7 @@ template <int N1, int N2> struct Geo {
 // ----------------------------------------------------------------------------------------
 enum { SRC_CSR = 0, SRC_DENSE = 1, SRC_LAG = 2 };
 
-template <typename TC, typename TS, int N1, int N2, int SRC>
+template <typename TC, typename TIN, typename TS, int N1, int N2, int SRC>
 __global__ void __launch_bounds__(256) k_rows_r2c(RowsR2CArgs a) {
   using G = Geo<N1, N2>;
   extern __shared__ unsigned char smem_raw[];
@@ -90,7 +90,7 @@ __global__ void __launch_bounds__(256) k_rows_r2c(RowsR2CArgs a) {
       } else if constexpr (SRC == SRC_DENSE) {
         const int cc = c - a.coff;
         if (cc >= 0 && cc < a.ncols) {
-          const TS* d = reinterpret_cast<const TS*>(a.dense) + (int64_t)b * a.dense_fs;
+          const TIN* d = reinterpret_cast<const TIN*>(a.dense) + (int64_t)b * a.dense_fs;
           if (oka) xa = (TC)d[(int64_t)ra * a.dense_ld + cc];
           if (okb) xb = (TC)d[(int64_t)rb * a.dense_ld + cc];
         }
@@ -217,37 +217,46 @@ __device__ __forceinline__ int window_dst(const Window& wd, int i) {
 
 enum { COL_CONV = 0, COL_CONV_DLAG = 1, COL_FWD_REAL = 2, COL_INV_SUM = 3 };
 
-template <typename TC, typename TS, int N1, int N2, int MODE>
+template <typename TF, typename TI, typename TSI, typename TSO, int N1, int N2, int MODE>
 __global__ void __launch_bounds__(256) k_cols(ColsArgs a) {
   using G = Geo<N1, N2>;
+  using TC = TF;
+  using TS = TSI;
   extern __shared__ unsigned char smem_raw[];
   cx<TC>* lds = reinterpret_cast<cx<TC>*>(smem_raw);
+  cx<TI>* ldsi = reinterpret_cast<cx<TI>*>(smem_raw);
   const int NL = a.NL;
   const int l0 = threadIdx.x % NL;
   const int s0 = threadIdx.x / NL;
   const int col0 = blockIdx.x * NL + l0;
   const bool colok = col0 < a.H2;
   const cx<TC>* twF = reinterpret_cast<const cx<TC>*>(a.twF);
+  const cx<TI>* twI = reinterpret_cast<const cx<TI>*>(a.twI);
   const int l = l0, s = s0, col = col0;
 
   if constexpr (MODE == COL_CONV) {
     const int b = blockIdx.y;
     const cx<TS>* src = reinterpret_cast<const cx<TS>*>(a.in) + (int64_t)b * a.in_fs;
-    cx<TC> w[N2];
-    col_fwd<TC, TS, N1, N2>(src, a.ldH, a.in_off, a.in_cnt, col, colok, s, l, NL, lds, twF, w);
-    if (s < N1 && colok) {
-      const TS* f = reinterpret_cast<const TS*>(a.filt);
+    cx<TI> wi[N2];
+    {
+      cx<TC> w[N2];
+      col_fwd<TC, TS, N1, N2>(src, a.ldH, a.in_off, a.in_cnt, col, colok, s, l, NL, lds, twF, w);
+      if (s < N1 && colok) {
+        const TF* f = reinterpret_cast<const TF*>(a.filt);
 #pragma unroll
-      for (int k2 = 0; k2 < N2; ++k2) w[k2] = cscale(w[k2], (TC)f[(int64_t)(s + N1 * k2) * a.ldH + col]);
+        for (int k2 = 0; k2 < N2; ++k2) w[k2] = cscale(w[k2], f[(int64_t)(s + N1 * k2) * a.ldH + col]);
+      }
+#pragma unroll
+      for (int k2 = 0; k2 < N2; ++k2) wi[k2] = ccast<TI>(w[k2]);
     }
-    cx<TC> v[N1];
-    col_inv_from_t<TC, N1, N2>(w, s, l, NL, lds, twF, v);
+    cx<TI> v[N1];
+    col_inv_from_t<TI, N1, N2>(wi, s, l, NL, ldsi, twI, v);
     if (s < N2 && colok) {
-      cx<TS>* dst = reinterpret_cast<cx<TS>*>(a.out) + (int64_t)b * a.out_fs;
+      cx<TSO>* dst = reinterpret_cast<cx<TSO>*>(a.out) + (int64_t)b * a.out_fs;
 #pragma unroll
       for (int n1 = 0; n1 < N1; ++n1) {
         const int d = window_dst<TS>(a.rows, N2 * n1 + s);
-        if (d >= 0) dst[(int64_t)d * a.ldH + col] = ccast<TS>(v[n1]);
+        if (d >= 0) dst[(int64_t)d * a.ldH + col] = ccast<TSO>(v[n1]);
       }
     }
   } else if constexpr (MODE == COL_CONV_DLAG) {
@@ -281,7 +290,7 @@ __global__ void __launch_bounds__(256) k_cols(ColsArgs a) {
       __syncthreads();
       col_fwd<TC, TS, N1, N2>(srcg, a.ldH, a.in_off, a.in_cnt, col, colok, s, l, NL, lds, twF, wg);
       if (s < N1 && colok) {
-        const TS* f = opaque(reinterpret_cast<const TS*>(a.filt));
+        const TF* f = opaque(reinterpret_cast<const TF*>(a.filt));
 #pragma unroll
         for (int k2 = 0; k2 < N2; ++k2) {
           acc[k2] = acc[k2] + cmulc(wg[k2], stash[(k2 * N1 + s) * NL + l]);
@@ -291,18 +300,18 @@ __global__ void __launch_bounds__(256) k_cols(ColsArgs a) {
       cx<TC> v[N1];
       col_inv_from_t<TC, N1, N2>(wg, s, l, NL, lds, twF, v);
       if (s < N2 && colok) {
-        cx<TS>* dst = reinterpret_cast<cx<TS>*>(a.out) + (int64_t)b * a.out_fs;
+        cx<TSO>* dst = reinterpret_cast<cx<TSO>*>(a.out) + (int64_t)b * a.out_fs;
 #pragma unroll
         for (int n1 = 0; n1 < N1; ++n1) {
           const int d = window_dst<TS>(a.rows, N2 * n1 + s);
-          if (d >= 0) dst[(int64_t)d * a.ldH + col] = ccast<TS>(v[n1]);
+          if (d >= 0) dst[(int64_t)d * a.ldH + col] = ccast<TSO>(v[n1]);
         }
       }
     }
     if (s < N1 && colok) {
-      cx<TS>* p = reinterpret_cast<cx<TS>*>(a.part) + (int64_t)blockIdx.y * G::F * a.ldH;
+      cx<TSO>* p = reinterpret_cast<cx<TSO>*>(a.part) + (int64_t)blockIdx.y * G::F * a.ldH;
 #pragma unroll
-      for (int k2 = 0; k2 < N2; ++k2) p[(int64_t)(s + N1 * k2) * a.ldH + col] = ccast<TS>(acc[k2]);
+      for (int k2 = 0; k2 < N2; ++k2) p[(int64_t)(s + N1 * k2) * a.ldH + col] = ccast<TSO>(acc[k2]);
     }
   } else if constexpr (MODE == COL_FWD_REAL) {
     // forward transform of the input columns; store Re(X) * scale (natural order, TS = double)
@@ -311,9 +320,9 @@ __global__ void __launch_bounds__(256) k_cols(ColsArgs a) {
     cx<TC> w[N2];
     col_fwd<TC, TS, N1, N2>(src, a.ldH, a.in_off, a.in_cnt, col, colok, s, l, NL, lds, twF, w);
     if (s < N1 && colok) {
-      TS* dst = reinterpret_cast<TS*>(a.out) + (int64_t)b * a.out_fs;
+      TSO* dst = reinterpret_cast<TSO*>(a.out) + (int64_t)b * a.out_fs;
 #pragma unroll
-      for (int k2 = 0; k2 < N2; ++k2) dst[(int64_t)(s + N1 * k2) * a.ldH + col] = (TS)(w[k2].x * (TC)a.scale);
+      for (int k2 = 0; k2 < N2; ++k2) dst[(int64_t)(s + N1 * k2) * a.ldH + col] = (TSO)(w[k2].x * (TC)a.scale);
     }
   } else {  // COL_INV_SUM: inverse transform of sum_g part[g] (natural order), keep rows
     const int SN2 = NL * G::ON1;
@@ -344,11 +353,11 @@ __global__ void __launch_bounds__(256) k_cols(ColsArgs a) {
 #pragma unroll
       for (int n2 = 0; n2 < N2; ++n2) w[n2] = lds[n2 * SN2 + s * NL + l];
       DFT<N2, 1, TC>::run(w);
-      cx<TS>* dst = reinterpret_cast<cx<TS>*>(a.out);
+      cx<TSO>* dst = reinterpret_cast<cx<TSO>*>(a.out);
 #pragma unroll
       for (int k2 = 0; k2 < N2; ++k2) {
         const int d = window_dst<TS>(a.rows, s + N1 * k2);
-        if (d >= 0) dst[(int64_t)d * a.ldH + col] = ccast<TS>(w[k2]);
+        if (d >= 0) dst[(int64_t)d * a.ldH + col] = ccast<TSO>(w[k2]);
       }
     }
   }
@@ -357,7 +366,7 @@ __global__ void __launch_bounds__(256) k_cols(ColsArgs a) {
 // ----------------------------------------------------------------------------------------
 // row kernel: inverse (half spectrum -> real), two rows per complex line
 // ----------------------------------------------------------------------------------------
-template <typename TC, typename TS, int N1, int N2>
+template <typename TC, typename TS, typename TO, int N1, int N2>
 __global__ void __launch_bounds__(256) k_rows_c2r(RowsC2RArgs a) {
   using G = Geo<N1, N2>;
   extern __shared__ unsigned char smem_raw[];
@@ -400,17 +409,17 @@ __global__ void __launch_bounds__(256) k_rows_c2r(RowsC2RArgs a) {
 #pragma unroll
     for (int n2 = 0; n2 < N2; ++n2) w[n2] = L[n2 * G::ON1 + s];
     DFT<N2, 1, TC>::run(w);
-    TS* oa = reinterpret_cast<TS*>(a.out) + (int64_t)b * a.out_fs + (int64_t)ra * a.ldo;
-    TS* ob = oa + a.ldo;
-    const TS* ad = reinterpret_cast<const TS*>(a.add);
+    TO* oa = reinterpret_cast<TO*>(a.out) + (int64_t)b * a.out_fs + (int64_t)ra * a.ldo;
+    TO* ob = oa + a.ldo;
+    const TO* ad = reinterpret_cast<const TO*>(a.add);
 #pragma unroll
     for (int k2 = 0; k2 < N2; ++k2) {
       const int c = s + N1 * k2;
       const int d = window_dst<TS>(a.cols, c);
       if (d >= 0) {
-        TS va = (TS)w[k2].x, vb = (TS)w[k2].y;
+        TO va = (TO)w[k2].x, vb = (TO)w[k2].y;
         if (ad) {
-          const TS* abase = ad + (int64_t)b * a.add_fs + (int64_t)(ra + a.add_r0) * a.add_ld + d + a.add_c0;
+          const TO* abase = ad + (int64_t)b * a.add_fs + (int64_t)(ra + a.add_r0) * a.add_ld + d + a.add_c0;
           if (oka) va += abase[0];
           if (okb) vb += abase[a.add_ld];
         }
@@ -426,39 +435,39 @@ __global__ void __launch_bounds__(256) k_rows_c2r(RowsC2RArgs a) {
 // ----------------------------------------------------------------------------------------
 template <typename TC, int N1, int N2>
 inline size_t rows_lds_bytes(int NL) { return (size_t)NL * N2 * Geo<N1, N2>::ON1 * sizeof(cx<TC>); }
-template <typename TC, int N1, int N2, int MODE>
+template <typename TF, int N1, int N2, int MODE>
 inline size_t cols_lds_bytes(int NL) {
   size_t ex = (size_t)NL * N2 * Geo<N1, N2>::ON1;
   if (MODE == COL_CONV_DLAG) ex += (size_t)NL * N1 * N2;  // stash of C-hat
-  return ex * sizeof(cx<TC>);
+  return ex * sizeof(cx<TF>);
 }
 
-template <typename TC, typename TS, int N1, int N2, int SRC>
+template <typename TC, typename TIN, typename TS, int N1, int N2, int SRC>
 hipError_t launch_rows_r2c(const RowsR2CArgs& a, int B, hipStream_t st) {
   const int npairs = (a.nrows + 1) / 2;
   dim3 grid((npairs + a.NL - 1) / a.NL, B);
   dim3 block(Geo<N1, N2>::NT * a.NL);
   const size_t sh = rows_lds_bytes<TC, N1, N2>(a.NL);
-  k_rows_r2c<TC, TS, N1, N2, SRC><<<grid, block, sh, st>>>(a);
+  k_rows_r2c<TC, TIN, TS, N1, N2, SRC><<<grid, block, sh, st>>>(a);
   return hipGetLastError();
 }
 
-template <typename TC, typename TS, int N1, int N2, int MODE>
+template <typename TF, typename TI, typename TSI, typename TSO, int N1, int N2, int MODE>
 hipError_t launch_cols(const ColsArgs& a, int nblk_y, hipStream_t st) {
   dim3 grid((a.H2 + a.NL - 1) / a.NL, nblk_y);
   dim3 block(Geo<N1, N2>::NT * a.NL);
-  const size_t sh = cols_lds_bytes<TC, N1, N2, MODE>(a.NL);
-  k_cols<TC, TS, N1, N2, MODE><<<grid, block, sh, st>>>(a);
+  const size_t sh = cols_lds_bytes<TF, N1, N2, MODE>(a.NL);
+  k_cols<TF, TI, TSI, TSO, N1, N2, MODE><<<grid, block, sh, st>>>(a);
   return hipGetLastError();
 }
 
-template <typename TC, typename TS, int N1, int N2>
+template <typename TC, typename TS, typename TO, int N1, int N2>
 hipError_t launch_rows_c2r(const RowsC2RArgs& a, int B, hipStream_t st) {
   const int npairs = (a.nrows + 1) / 2;
   dim3 grid((npairs + a.NL - 1) / a.NL, B);
   dim3 block(Geo<N1, N2>::NT * a.NL);
   const size_t sh = rows_lds_bytes<TC, N1, N2>(a.NL);
-  k_rows_c2r<TC, TS, N1, N2><<<grid, block, sh, st>>>(a);
+  k_rows_c2r<TC, TS, TO, N1, N2><<<grid, block, sh, st>>>(a);
   return hipGetLastError();
 }
 
@@ -468,24 +477,18 @@ FftEntry make_fft_entry() {
   e.F = N1 * N2;
   e.N1 = N1;
   e.N2 = N2;
-  // FP32 storage: scatter+forward rows in FP64 arithmetic, other passes FP32
-  e.f32.r2c_csr = launch_rows_r2c<double, float, N1, N2, SRC_CSR>;
-  e.f32.r2c_dense = launch_rows_r2c<float, float, N1, N2, SRC_DENSE>;
-  e.f32.r2c_lag64 = launch_rows_r2c<double, double, N1, N2, SRC_LAG>;
-  e.f32.conv = launch_cols<float, float, N1, N2, COL_CONV>;
-  e.f32.conv_dlag = launch_cols<float, float, N1, N2, COL_CONV_DLAG>;
-  e.f32.fwd_real64 = launch_cols<double, double, N1, N2, COL_FWD_REAL>;
-  e.f32.inv_sum = launch_cols<float, float, N1, N2, COL_INV_SUM>;
-  e.f32.c2r = launch_rows_c2r<float, float, N1, N2>;
-  // FP64: the same kernels instantiated for double
-  e.f64.r2c_csr = launch_rows_r2c<double, double, N1, N2, SRC_CSR>;
-  e.f64.r2c_dense = launch_rows_r2c<double, double, N1, N2, SRC_DENSE>;
-  e.f64.r2c_lag64 = e.f32.r2c_lag64;
-  e.f64.conv = launch_cols<double, double, N1, N2, COL_CONV>;
-  e.f64.conv_dlag = launch_cols<double, double, N1, N2, COL_CONV_DLAG>;
-  e.f64.fwd_real64 = e.f32.fwd_real64;
-  e.f64.inv_sum = launch_cols<double, double, N1, N2, COL_INV_SUM>;
-  e.f64.c2r = launch_rows_c2r<double, double, N1, N2>;
+  FftSet& k = e.k;
+  k.r2c_csr = launch_rows_r2c<double, double, double, N1, N2, SRC_CSR>;
+  k.r2c_dense_f32 = launch_rows_r2c<double, float, double, N1, N2, SRC_DENSE>;
+  k.r2c_dense_f64 = launch_rows_r2c<double, double, double, N1, N2, SRC_DENSE>;
+  k.r2c_lag = launch_rows_r2c<double, double, double, N1, N2, SRC_LAG>;
+  k.conv_mixed = launch_cols<double, float, double, float, N1, N2, COL_CONV>;
+  k.conv64 = launch_cols<double, double, double, double, N1, N2, COL_CONV>;
+  k.conv_dlag64 = launch_cols<double, double, double, double, N1, N2, COL_CONV_DLAG>;
+  k.fwd_real64 = launch_cols<double, double, double, double, N1, N2, COL_FWD_REAL>;
+  k.inv_sum64 = launch_cols<double, double, double, double, N1, N2, COL_INV_SUM>;
+  k.c2r32 = launch_rows_c2r<float, float, float, N1, N2>;
+  k.c2r64 = launch_rows_c2r<double, double, double, N1, N2>;
   return e;
 }
 

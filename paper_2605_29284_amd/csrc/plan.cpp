@@ -46,7 +46,7 @@ struct krig_plan_s {
   double* sites = nullptr;
   double* lag64 = nullptr;
   void* lagT = nullptr;
-  void* filt = nullptr;  // dt [F1][ldH]
+  double* filt = nullptr;  // [F1][ldH] filter spectrum / (F1 F2), FP64
   double* KN = nullptr;
   double* LinvN = nullptr;
   int* d_status = nullptr;   // [0] K_N status, [1] M pivot
@@ -65,29 +65,35 @@ struct krig_plan_s {
   int kn_status = 0, pivot = 0;
   // per-call workspaces
   int wsB = 0;
-  void* S1 = nullptr;     // cx dt [B][P1][ldH]
-  void* S2 = nullptr;     // cx dt [B][max(m1,P1)][ldH]
-  void* SG = nullptr;     // cx dt [B][m1][ldH]
-  void* img = nullptr;    // dt [B][P1][P2]
+  void* S1 = nullptr;     // cx FP64 [B][P1][ldH]   row spectra of c*
+  void* S2 = nullptr;     // cx dt   [B][m1][ldH]   prediction column-pass output
+  void* SG = nullptr;     // cx FP64 [B][m1][ldH]   row spectra of the upstream gradient
+  void* SA = nullptr;     // cx FP64 [B][P1][ldH]   adjoint column-pass output
+  void* img = nullptr;    // FP64 [B][P1][P2]       correlation image
   double* alpha = nullptr;  // [B][n]
   double* tmpv = nullptr;   // [B][n]
-  void* part = nullptr;   // cx dt [ngroups][F1][ldH]
+  double* tripart = nullptr;  // [tri_chunks(n)][B][n] split-K partial sums of the solve
+  void* part = nullptr;   // cx FP64 [ngroups][F1][ldH]
   int part_groups = 0;
-  void* XC = nullptr;     // cx dt [2 n1l - 1][ldH]
-  void* XR = nullptr;     // dt [2 n1l - 1][2 n2l - 1]
+  void* XC = nullptr;     // cx FP64 [2 n1l - 1][ldH]
+  void* XR = nullptr;     // FP64 [2 n1l - 1][2 n2l - 1]
   // custom-lag filter
-  void* filtC = nullptr;
+  double* filtC = nullptr;
   double* lagC64 = nullptr;
   double* phiS64 = nullptr;  // cx double [F1][ldH]
   double* phiR64 = nullptr;  // double [F1][ldH]
   // launch shapes
-  int nl_rows_c = 8;   // lines per block, FP64-compute row kernels
-  int nl_rows = 8;
-  int nl_cols = 8;
-  int nl_cols_dlag = 4;
+  int nl_rows64 = 4;   // lines per block, FP64 row kernels
+  int nl_rows32 = 8;   // FP32 row kernels
+  int nl_cols64 = 4;   // columns per block, FP64-forward column kernels
+  int nl_cols_dlag = 2;
   int dlag_G = 2;
   // conditional simulation
   int ce_clamped = 0;
+  // stage timing
+  bool timing = false;
+  std::vector<hipEvent_t> ev_pool;
+  std::vector<std::pair<hipEvent_t, hipEvent_t>> ev_pending[KRIG_STAGE_COUNT];
   std::vector<void*> allocs;
 };
 
@@ -96,6 +102,40 @@ namespace {
 std::once_flag g_once;
 
 int hip_status(hipError_t e) { return e == hipSuccess ? KRIG_OK : KRIG_EHIP; }
+
+hipEvent_t take_event(krig_plan p) {
+  if (!p->ev_pool.empty()) {
+    hipEvent_t e = p->ev_pool.back();
+    p->ev_pool.pop_back();
+    return e;
+  }
+  hipEvent_t e = nullptr;
+  if (hipEventCreate(&e) != hipSuccess) return nullptr;
+  return e;
+}
+
+// Brackets the launches of one stage with events when timing is on.
+struct StageTimer {
+  krig_plan p;
+  int stage;
+  hipEvent_t a = nullptr, b = nullptr;
+  StageTimer(krig_plan p_, int s_) : p(p_), stage(s_) {
+    if (p->timing) {
+      a = take_event(p);
+      b = take_event(p);
+      if (a && b) (void)hipEventRecord(a, p->st);
+    }
+  }
+  ~StageTimer() {
+    if (a && b) {
+      (void)hipEventRecord(b, p->st);
+      p->ev_pending[stage].push_back({a, b});
+    } else {
+      if (a) p->ev_pool.push_back(a);
+      if (b) p->ev_pool.push_back(b);
+    }
+  }
+};
 
 #define KRIG_TRY(expr)                         \
   do {                                         \
@@ -169,14 +209,13 @@ int make_twiddles(krig_plan p, int F, double** d64, float** d32) {
   return KRIG_OK;
 }
 
-const FftSet& set1(krig_plan p) { return p->dtype == KRIG_F32 ? p->e1->f32 : p->e1->f64; }
-const FftSet& set2(krig_plan p) { return p->dtype == KRIG_F32 ? p->e2->f32 : p->e2->f64; }
-const void* twc1(krig_plan p) { return p->dtype == KRIG_F32 ? (const void*)p->tw1_32 : (const void*)p->tw1_64; }
-const void* twc2(krig_plan p) { return p->dtype == KRIG_F32 ? (const void*)p->tw2_32 : (const void*)p->tw2_64; }
+const FftSet& set1(krig_plan p) { return p->e1->k; }
+const FftSet& set2(krig_plan p) { return p->e2->k; }
+bool is32(krig_plan p) { return p->dtype == KRIG_F32; }
 size_t csz(krig_plan p) { return 2 * p->tsz; }
 
-// spectrum of the even-reflected lag quadrant (FP64), scaled by 1/(F1 F2), stored in dt
-int make_filter(krig_plan p, const double* lag64, void* filt_out) {
+// spectrum of the even-reflected lag quadrant (FP64), scaled by 1/(F1 F2)
+int make_filter(krig_plan p, const double* lag64, double* filt_out) {
   RowsR2CArgs r{};
   r.nrows = p->F1;
   r.H2 = p->H2;
@@ -189,7 +228,7 @@ int make_filter(krig_plan p, const double* lag64, void* filt_out) {
   r.n2l = p->n2l;
   r.F1 = p->F1;
   r.NL = lines_for(p->e2, 16, 0);
-  KRIG_TRY(p->e2->f64.r2c_lag64(r, 1, p->st));
+  KRIG_TRY(p->e2->k.r2c_lag(r, 1, p->st));
   ColsArgs c{};
   c.H2 = p->H2;
   c.ldH = p->ldH;
@@ -197,44 +236,46 @@ int make_filter(krig_plan p, const double* lag64, void* filt_out) {
   c.in_fs = 0;
   c.in_off = 0;
   c.in_cnt = p->F1;
-  c.out = p->phiR64;
+  c.out = filt_out;
   c.out_fs = 0;
   c.twF = p->tw1_64;
+  c.twI = p->tw1_64;
   c.scale = 1.0 / ((double)p->F1 * (double)p->F2);
   c.NL = lines_for(p->e1, 16, 0);
-  KRIG_TRY(p->e1->f64.fwd_real64(c, 1, p->st));
-  KRIG_TRY(convert_f64(p->phiR64, filt_out, (int64_t)p->F1 * p->ldH, p->dtype == KRIG_F32, p->st));
+  KRIG_TRY(p->e1->k.fwd_real64(c, 1, p->st));
   return KRIG_OK;
 }
 
 int ensure_ws(krig_plan p, int B) {
   if (B <= p->wsB) return KRIG_OK;
-  void* olds[] = {p->S1, p->S2, p->SG, p->img, p->alpha, p->tmpv, p->part};
+  void* olds[] = {p->S1, p->S2, p->SG, p->SA, p->img, p->alpha, p->tmpv, p->part, p->tripart};
   KRIG_TRY(hipStreamSynchronize(p->st));
   for (void* q : olds) dfree(p, q);
   const size_t c = csz(p);
-  const int rmax = std::max(p->g.m1, p->P1);
   int r;
-  if ((r = dalloc_bytes(p, &p->S1, c * B * (size_t)p->P1 * p->ldH)) != KRIG_OK) return r;
-  if ((r = dalloc_bytes(p, &p->S2, c * B * (size_t)rmax * p->ldH)) != KRIG_OK) return r;
-  if ((r = dalloc_bytes(p, &p->SG, c * B * (size_t)p->g.m1 * p->ldH)) != KRIG_OK) return r;
-  if ((r = dalloc_bytes(p, &p->img, p->tsz * B * (size_t)p->P1 * p->P2)) != KRIG_OK) return r;
+  if ((r = dalloc_bytes(p, &p->S1, 16 * (size_t)B * p->P1 * p->ldH)) != KRIG_OK) return r;
+  if ((r = dalloc_bytes(p, &p->S2, c * (size_t)B * p->g.m1 * p->ldH)) != KRIG_OK) return r;
+  if ((r = dalloc_bytes(p, &p->SG, 16 * (size_t)B * p->g.m1 * p->ldH)) != KRIG_OK) return r;
+  if ((r = dalloc_bytes(p, &p->SA, 16 * (size_t)B * p->P1 * p->ldH)) != KRIG_OK) return r;
+  if ((r = dalloc_bytes(p, &p->img, 8 * (size_t)B * p->P1 * p->P2)) != KRIG_OK) return r;
   if ((r = dalloc(p, &p->alpha, (size_t)B * p->n)) != KRIG_OK) return r;
   if ((r = dalloc(p, &p->tmpv, (size_t)B * p->n)) != KRIG_OK) return r;
+  if ((r = dalloc(p, &p->tripart, (size_t)tri_chunks(p->n) * B * p->n)) != KRIG_OK) return r;
   p->part_groups = B;  // worst case G = 1
-  if ((r = dalloc_bytes(p, &p->part, c * (size_t)p->part_groups * p->F1 * p->ldH)) != KRIG_OK) return r;
+  if ((r = dalloc_bytes(p, &p->part, 16 * (size_t)p->part_groups * p->F1 * p->ldH)) != KRIG_OK) return r;
   p->wsB = B;
   return KRIG_OK;
 }
 
 int do_solve(krig_plan p, int B, const double* y, double* alpha) {
-  KRIG_TRY(tri_apply(p->Linv, p->n, p->n, y, p->n, p->tmpv, p->n, B, 0, p->st));
-  KRIG_TRY(tri_apply(p->Linv, p->n, p->n, p->tmpv, p->n, alpha, p->n, B, 1, p->st));
+  StageTimer t(p, KRIG_STAGE_SOLVE);
+  KRIG_TRY(tri_apply(p->Linv, p->n, p->n, y, p->n, p->tmpv, p->n, B, 0, p->tripart, p->st));
+  KRIG_TRY(tri_apply(p->Linv, p->n, p->n, p->tmpv, p->n, alpha, p->n, B, 1, p->tripart, p->st));
   return KRIG_OK;
 }
 
 // custom lag (dt) -> filtC; returns the filter to use
-int filter_for(krig_plan p, const void* d_lag, const void** out) {
+int filter_for(krig_plan p, const void* d_lag, const double** out) {
   if (!d_lag) {
     *out = p->filt;
     return KRIG_OK;
@@ -246,7 +287,7 @@ int filter_for(krig_plan p, const void* d_lag, const void** out) {
   return KRIG_OK;
 }
 
-int do_convolve(krig_plan p, int B, const double* alpha, const void* filt, void* yhat, void* spec1,
+int do_convolve(krig_plan p, int B, const double* alpha, const double* filt, void* yhat, void* spec1,
                 const void* add, int64_t add_fs, int add_ld) {
   RowsR2CArgs r{};
   r.nrows = p->P1;
@@ -254,15 +295,18 @@ int do_convolve(krig_plan p, int B, const double* alpha, const void* filt, void*
   r.ldH = p->ldH;
   r.out = spec1;
   r.out_fs = (int64_t)p->P1 * p->ldH;
-  r.twF = p->tw2_64;  // scatter + forward rows in FP64 arithmetic
+  r.twF = p->tw2_64;  // scatter + forward rows in FP64
   r.row_ptr = p->node_ptr;
   r.ent_site = p->ent_site;
   r.ent_w = p->ent_w;
   r.alpha = alpha;
   r.alpha_fs = p->n;
   r.ncols = p->P2;
-  r.NL = p->nl_rows_c;
-  KRIG_TRY(set2(p).r2c_csr(r, B, p->st));
+  r.NL = p->nl_rows64;
+  {
+    StageTimer t(p, KRIG_STAGE_ROWS_FWD);
+    KRIG_TRY(set2(p).r2c_csr(r, B, p->st));
+  }
 
   ColsArgs c{};
   c.H2 = p->H2;
@@ -275,10 +319,14 @@ int do_convolve(krig_plan p, int B, const double* alpha, const void* filt, void*
   c.out = p->S2;
   c.out_fs = (int64_t)p->g.m1 * p->ldH;
   c.rows = Window{p->g.L, p->g.m1, 0, 0};
-  c.twF = twc1(p);
+  c.twF = p->tw1_64;  // forward column transform in FP64
+  c.twI = is32(p) ? (const void*)p->tw1_32 : (const void*)p->tw1_64;
   c.B = B;
-  c.NL = p->nl_cols;
-  KRIG_TRY(set1(p).conv(c, B, p->st));
+  c.NL = p->nl_cols64;
+  {
+    StageTimer t(p, KRIG_STAGE_COLS_CONV);
+    KRIG_TRY((is32(p) ? set1(p).conv_mixed : set1(p).conv64)(c, B, p->st));
+  }
 
   RowsC2RArgs o{};
   o.nrows = p->g.m1;
@@ -295,9 +343,12 @@ int do_convolve(krig_plan p, int B, const double* alpha, const void* filt, void*
   o.add_ld = add_ld;
   o.add_r0 = p->g.L;
   o.add_c0 = p->g.L;
-  o.twF = twc2(p);
-  o.NL = p->nl_rows;
-  KRIG_TRY(set2(p).c2r(o, B, p->st));
+  o.twF = is32(p) ? (const void*)p->tw2_32 : (const void*)p->tw2_64;
+  o.NL = is32(p) ? p->nl_rows32 : p->nl_rows64;
+  {
+    StageTimer t(p, KRIG_STAGE_ROWS_INV);
+    KRIG_TRY((is32(p) ? set2(p).c2r32 : set2(p).c2r64)(o, B, p->st));
+  }
   return KRIG_OK;
 }
 
@@ -320,6 +371,12 @@ int matern_kind(double nu) {
 void destroy_all(krig_plan p) {
   if (!p) return;
   (void)hipStreamSynchronize(p->st);
+  for (auto& v : p->ev_pending)
+    for (auto& pr : v) {
+      (void)hipEventDestroy(pr.first);
+      (void)hipEventDestroy(pr.second);
+    }
+  for (hipEvent_t e : p->ev_pool) (void)hipEventDestroy(e);
   for (void* q : p->allocs) (void)hipFree(q);
   p->allocs.clear();
   delete p;
@@ -396,10 +453,15 @@ int krig_plan_create(krig_plan* out, const krig_grid* g, const krig_matern* k, i
   p->ldH = (p->H2 + 15) / 16 * 16;
   const bool f32 = dtype == KRIG_F32;
   // launch shapes (lines per block) within 256 threads and 64 KB of LDS
-  p->nl_rows_c = lines_for(p->e2, 16, 0);
-  p->nl_rows = lines_for(p->e2, f32 ? 8 : 16, 0);
-  p->nl_cols = lines_for(p->e1, f32 ? 8 : 16, 0);
-  p->nl_cols_dlag = lines_for(p->e1, f32 ? 8 : 16, (size_t)p->F1 * (f32 ? 8 : 16));
+  p->nl_rows64 = lines_for(p->e2, 16, 0);
+  p->nl_rows32 = lines_for(p->e2, 8, 0);
+  p->nl_cols64 = lines_for(p->e1, 16, 0);
+  p->nl_cols_dlag = lines_for(p->e1, 16, (size_t)p->F1 * 16);
+  if (lines_for(p->e1, 16, 0) * (size_t)p->e1->N2 * on1_of(p->e1) * 16 > 64 * 1024 ||
+      lines_for(p->e2, 16, 0) * (size_t)p->e2->N2 * on1_of(p->e2) * 16 > 64 * 1024) {
+    delete p;
+    return KRIG_EUNSUPPORTED;
+  }
 
 #define CK(x)                 \
   do {                        \
@@ -424,8 +486,8 @@ int krig_plan_create(krig_plan* out, const krig_grid* g, const krig_matern* k, i
   CK(dalloc(p, &p->lagC64, (size_t)n1l * n2l));
   CK(dalloc(p, &p->phiS64, 2 * (size_t)p->F1 * p->ldH));
   CK(dalloc(p, &p->phiR64, (size_t)p->F1 * p->ldH));
-  CK(dalloc_bytes(p, &p->filt, p->tsz * (size_t)p->F1 * p->ldH));
-  CK(dalloc_bytes(p, &p->filtC, p->tsz * (size_t)p->F1 * p->ldH));
+  CK(dalloc(p, &p->filt, (size_t)p->F1 * p->ldH));
+  CK(dalloc(p, &p->filtC, (size_t)p->F1 * p->ldH));
   CKH(lag_image(p->g, p->mt, p->lag64, p->st));
   CKH(convert_f64(p->lag64, p->lagT, (int64_t)n1l * n2l, f32, p->st));
   CK(make_filter(p, p->lag64, p->filt));
@@ -475,8 +537,8 @@ int krig_plan_create(krig_plan* out, const krig_grid* g, const krig_matern* k, i
   CKH(cholesky_and_inverse(p->Lfac, n, n, p->Linv, p->Dinv, p->work, p->d_status + 1, p->st));
 
   // dlag buffers
-  CK(dalloc_bytes(p, &p->XC, csz(p) * (size_t)(2 * n1l - 1) * p->ldH));
-  CK(dalloc_bytes(p, &p->XR, p->tsz * (size_t)(2 * n1l - 1) * (2 * n2l - 1)));
+  CK(dalloc_bytes(p, &p->XC, 16 * (size_t)(2 * n1l - 1) * p->ldH));
+  CK(dalloc_bytes(p, &p->XR, 8 * (size_t)(2 * n1l - 1) * (2 * n2l - 1)));
 
   int hst[4] = {0, 0, 0, 0};
   CKH(hipMemcpyAsync(hst, p->d_status, sizeof(hst), hipMemcpyDeviceToHost, p->st));
@@ -512,7 +574,7 @@ int krig_plan_info(krig_plan p, int32_t what, int64_t* v) {
     case KRIG_INFO_F2: *v = p->F2; break;
     case KRIG_INFO_H2: *v = p->H2; break;
     case KRIG_INFO_LDH: *v = p->ldH; break;
-    case KRIG_INFO_SAVED_PER_FIELD: *v = (int64_t)p->P1 * p->ldH; break;
+    case KRIG_INFO_SAVED_PER_FIELD: *v = (int64_t)p->P1 * p->ldH; break;  // complex FP64
     case KRIG_INFO_KN_STATUS: *v = p->kn_status; break;
     case KRIG_INFO_PIVOT: *v = p->pivot; break;
     case KRIG_INFO_DTYPE: *v = p->dtype; break;
@@ -575,7 +637,7 @@ int krig_convolve(krig_plan p, int32_t B, const double* d_alpha, const void* d_l
   if (!p || B < 1 || !d_alpha || !d_yhat) return KRIG_EINVAL;
   int r = ensure_ws(p, B);
   if (r != KRIG_OK) return r;
-  const void* filt = nullptr;
+  const double* filt = nullptr;
   if ((r = filter_for(p, d_lag, &filt)) != KRIG_OK) return r;
   return do_convolve(p, B, d_alpha, filt, d_yhat, d_saved ? d_saved : p->S1, nullptr, 0, 0);
 }
@@ -587,7 +649,7 @@ int krig_predict(krig_plan p, int32_t B, const double* d_y, const void* d_lag, v
   if (r != KRIG_OK) return r;
   double* al = d_alpha_out ? d_alpha_out : p->alpha;
   if ((r = do_solve(p, B, d_y, al)) != KRIG_OK) return r;
-  const void* filt = nullptr;
+  const double* filt = nullptr;
   if ((r = filter_for(p, d_lag, &filt)) != KRIG_OK) return r;
   return do_convolve(p, B, al, filt, d_yhat, d_saved ? d_saved : p->S1, nullptr, 0, 0);
 }
@@ -598,9 +660,11 @@ int krig_predict_adjoint(krig_plan p, int32_t B, const void* d_g, const double* 
   if (d_dlag && !d_saved && !d_alpha) return KRIG_EINVAL;
   int r = ensure_ws(p, B);
   if (r != KRIG_OK) return r;
-  const void* filt = nullptr;
+  const double* filt = nullptr;
   if ((r = filter_for(p, d_lag, &filt)) != KRIG_OK) return r;
-  const bool f32 = p->dtype == KRIG_F32;
+  // The adjoint runs in FP64 whatever the plan's dtype: d alpha is multiplied by
+  // (K + tau^2 I)^{-1}, whose condition number amplifies any FP32 rounding of the
+  // correlation image far beyond the gradient tolerance.
   const void* spec1 = d_saved;
   if (d_dlag && !spec1) {
     // recompute the row spectra of c* from the coefficients
@@ -617,7 +681,8 @@ int krig_predict_adjoint(krig_plan p, int32_t B, const void* d_g, const double* 
     rr.alpha = d_alpha;
     rr.alpha_fs = p->n;
     rr.ncols = p->P2;
-    rr.NL = p->nl_rows_c;
+    rr.NL = p->nl_rows64;
+    StageTimer t(p, KRIG_STAGE_ROWS_FWD);
     KRIG_TRY(set2(p).r2c_csr(rr, B, p->st));
     spec1 = p->S1;
   }
@@ -628,14 +693,17 @@ int krig_predict_adjoint(krig_plan p, int32_t B, const void* d_g, const double* 
   rg.ldH = p->ldH;
   rg.out = p->SG;
   rg.out_fs = (int64_t)p->g.m1 * p->ldH;
-  rg.twF = twc2(p);
+  rg.twF = p->tw2_64;
   rg.dense = d_g;
   rg.dense_fs = (int64_t)p->g.m1 * p->g.m2;
   rg.dense_ld = p->g.m2;
   rg.coff = p->g.L;
   rg.ncols = p->g.m2;
-  rg.NL = p->nl_rows;
-  KRIG_TRY(set2(p).r2c_dense(rg, B, p->st));
+  rg.NL = p->nl_rows64;
+  {
+    StageTimer t(p, KRIG_STAGE_ADJ_ROWS_FWD);
+    KRIG_TRY((is32(p) ? set2(p).r2c_dense_f32 : set2(p).r2c_dense_f64)(rg, B, p->st));
+  }
   // columns: correlation with the (even) filter, keep the P1 padded rows
   ColsArgs c{};
   c.H2 = p->H2;
@@ -645,10 +713,11 @@ int krig_predict_adjoint(krig_plan p, int32_t B, const void* d_g, const double* 
   c.in_off = p->g.L;
   c.in_cnt = p->g.m1;
   c.filt = filt;
-  c.out = p->S2;
+  c.out = p->SA;
   c.out_fs = (int64_t)p->P1 * p->ldH;
   c.rows = Window{0, p->P1, 0, 0};
-  c.twF = twc1(p);
+  c.twF = p->tw1_64;
+  c.twI = p->tw1_64;
   c.B = B;
   int ngroups = 0;
   if (d_dlag) {
@@ -657,35 +726,44 @@ int krig_predict_adjoint(krig_plan p, int32_t B, const void* d_g, const double* 
     c.in2_off = 0;
     c.in2_cnt = p->P1;
     c.part = p->part;
-    c.G = std::max(1, std::min(p->dlag_G, B));
+    c.G = std::max(1, std::min(p->dlag_G, (int)B));
     c.NL = p->nl_cols_dlag;
     ngroups = (B + c.G - 1) / c.G;
-    KRIG_TRY(set1(p).conv_dlag(c, ngroups, p->st));
+    StageTimer t(p, KRIG_STAGE_ADJ_COLS);
+    KRIG_TRY(set1(p).conv_dlag64(c, ngroups, p->st));
   } else {
-    c.NL = p->nl_cols;
-    KRIG_TRY(set1(p).conv(c, B, p->st));
+    c.NL = p->nl_cols64;
+    StageTimer t(p, KRIG_STAGE_ADJ_COLS);
+    KRIG_TRY(set1(p).conv64(c, B, p->st));
   }
   // rows back to the padded image
   RowsC2RArgs o{};
   o.nrows = p->P1;
   o.H2 = p->H2;
   o.ldH = p->ldH;
-  o.in = p->S2;
+  o.in = p->SA;
   o.in_fs = (int64_t)p->P1 * p->ldH;
   o.out = p->img;
   o.out_fs = (int64_t)p->P1 * p->P2;
   o.ldo = p->P2;
   o.cols = Window{0, p->P2, 0, 0};
-  o.twF = twc2(p);
-  o.NL = p->nl_rows;
-  KRIG_TRY(set2(p).c2r(o, B, p->st));
+  o.twF = p->tw2_64;
+  o.NL = p->nl_rows64;
+  {
+    StageTimer t(p, KRIG_STAGE_ADJ_ROWS_INV);
+    KRIG_TRY(set2(p).c2r64(o, B, p->st));
+  }
   // dalpha by gathering at the neighbours, then dy = M^{-1} dalpha
   if (d_dy) {
-    KRIG_TRY(gather_sites(p->g, p->anchor, p->Wt, p->n, p->img, (int64_t)p->P1 * p->P2, p->P2, B, f32, p->alpha,
-                          p->n, p->st));
+    {
+      StageTimer t(p, KRIG_STAGE_GATHER);
+      KRIG_TRY(gather_sites(p->g, p->anchor, p->Wt, p->n, p->img, (int64_t)p->P1 * p->P2, p->P2, B, 0, p->alpha,
+                            p->n, p->st));
+    }
     if ((r = do_solve(p, B, p->alpha, d_dy)) != KRIG_OK) return r;
   }
   if (d_dlag) {
+    StageTimer t(p, KRIG_STAGE_DLAG_TAIL);
     // inverse transform of sum_b G_b conj(C_b), keeping lags -(n-1)..(n-1)
     ColsArgs ci{};
     ci.H2 = p->H2;
@@ -695,9 +773,10 @@ int krig_predict_adjoint(krig_plan p, int32_t B, const void* d_g, const double* 
     ci.G = ngroups;
     ci.out = p->XC;
     ci.rows = Window{0, p->n1l, p->F1 - p->n1l + 1, p->n1l - 1};
-    ci.twF = twc1(p);
-    ci.NL = p->nl_cols;
-    KRIG_TRY(set1(p).inv_sum(ci, 1, p->st));
+    ci.twF = p->tw1_64;
+    ci.twI = p->tw1_64;
+    ci.NL = p->nl_cols64;
+    KRIG_TRY(set1(p).inv_sum64(ci, 1, p->st));
     RowsC2RArgs oc{};
     oc.nrows = 2 * p->n1l - 1;
     oc.H2 = p->H2;
@@ -708,11 +787,37 @@ int krig_predict_adjoint(krig_plan p, int32_t B, const void* d_g, const double* 
     oc.out_fs = 0;
     oc.ldo = 2 * p->n2l - 1;
     oc.cols = Window{0, p->n2l, p->F2 - p->n2l + 1, p->n2l - 1};
-    oc.twF = twc2(p);
-    oc.NL = p->nl_rows;
-    KRIG_TRY(set2(p).c2r(oc, 1, p->st));
-    KRIG_TRY(fold_dlag(p->XR, 2 * p->n2l - 1, p->n1l, p->n2l, 1.0 / ((double)p->F1 * p->F2), d_dlag, f32, p->st));
+    oc.twF = p->tw2_64;
+    oc.NL = p->nl_rows64;
+    KRIG_TRY(set2(p).c2r64(oc, 1, p->st));
+    KRIG_TRY(fold_dlag((const double*)p->XR, 2 * p->n2l - 1, p->n1l, p->n2l, 1.0 / ((double)p->F1 * p->F2), d_dlag, is32(p),
+                       p->st));
   }
+  return KRIG_OK;
+}
+
+int krig_timing_enable(krig_plan p, int32_t on) {
+  if (!p) return KRIG_EINVAL;
+  p->timing = on != 0;
+  return KRIG_OK;
+}
+
+int krig_timing_read(krig_plan p, int32_t stage, double* total_ms, int64_t* launches) {
+  if (!p || stage < 0 || stage >= KRIG_STAGE_COUNT || !total_ms || !launches) return KRIG_EINVAL;
+  double tot = 0.0;
+  int64_t cnt = 0;
+  for (auto& pr : p->ev_pending[stage]) {
+    KRIG_TRY(hipEventSynchronize(pr.second));
+    float ms = 0.f;
+    KRIG_TRY(hipEventElapsedTime(&ms, pr.first, pr.second));
+    tot += ms;
+    ++cnt;
+    p->ev_pool.push_back(pr.first);
+    p->ev_pool.push_back(pr.second);
+  }
+  p->ev_pending[stage].clear();
+  *total_ms = tot;
+  *launches = cnt;
   return KRIG_OK;
 }
 

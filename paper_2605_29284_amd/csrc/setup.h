@@ -58,7 +58,7 @@ hipError_t csim_residual(const GridDev& g, const int32_t* anchor, const double* 
 
 // d loss / d lag from the compact correlation image X (rows: lags 0..n1l-1 then
 // -(n1l-1)..-1; cols likewise), summing the sign images, times scale.
-hipError_t fold_dlag(const void* X, int64_t ldx, int n1l, int n2l, double scale, void* dlag, int to_f32,
+hipError_t fold_dlag(const double* X, int64_t ldx, int n1l, int n2l, double scale, void* dlag, int to_f32,
                      hipStream_t st);
 
 // Complex white noise x sqrt(Lambda) for the circulant-embedding sampler, and the

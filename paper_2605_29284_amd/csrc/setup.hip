@@ -420,9 +420,9 @@ hipError_t csim_residual(const GridDev& g, const int32_t* anchor, const double* 
 }
 
 // ------------------------------------------------------------------------------ dlag fold
-template <typename TS>
-__global__ void k_fold_dlag(const TS* __restrict__ X, int64_t ldx, int n1l, int n2l, double scale,
-                            TS* __restrict__ dlag) {
+template <typename TO>
+__global__ void k_fold_dlag(const double* __restrict__ X, int64_t ldx, int n1l, int n2l, double scale,
+                            TO* __restrict__ dlag) {
   const int idx = blockIdx.x * blockDim.x + threadIdx.x;
   if (idx >= n1l * n2l) return;
   const int u = idx / n2l, w = idx % n2l;
@@ -431,18 +431,18 @@ __global__ void k_fold_dlag(const TS* __restrict__ X, int64_t ldx, int n1l, int 
   const int nu = u == 0 ? 1 : 2, nw = w == 0 ? 1 : 2;
   double acc = 0.0;
   for (int a = 0; a < nu; ++a)
-    for (int b = 0; b < nw; ++b) acc += (double)X[(int64_t)ru[a] * ldx + cw[b]];
-  dlag[idx] = (TS)(acc * scale);
+    for (int b = 0; b < nw; ++b) acc += X[(int64_t)ru[a] * ldx + cw[b]];
+  dlag[idx] = (TO)(acc * scale);
 }
-hipError_t fold_dlag(const void* X, int64_t ldx, int n1l, int n2l, double scale, void* dlag, int to_f32,
+hipError_t fold_dlag(const double* X, int64_t ldx, int n1l, int n2l, double scale, void* dlag, int to_f32,
                      hipStream_t st) {
   const int cnt = n1l * n2l;
   if (to_f32)
-    hipLaunchKernelGGL(k_fold_dlag<float>, dim3(nblk(cnt)), dim3(256), 0, st, (const float*)X, ldx, n1l, n2l,
-                       scale, (float*)dlag);
+    hipLaunchKernelGGL(k_fold_dlag<float>, dim3(nblk(cnt)), dim3(256), 0, st, X, ldx, n1l, n2l, scale,
+                       (float*)dlag);
   else
-    hipLaunchKernelGGL(k_fold_dlag<double>, dim3(nblk(cnt)), dim3(256), 0, st, (const double*)X, ldx, n1l, n2l,
-                       scale, (double*)dlag);
+    hipLaunchKernelGGL(k_fold_dlag<double>, dim3(nblk(cnt)), dim3(256), 0, st, X, ldx, n1l, n2l, scale,
+                       (double*)dlag);
   return hipGetLastError();
 }
 

@@ -101,7 +101,9 @@ def test_solve_matches_cholesky(krig, small, paper, which):
     y = np.concatenate([w.y, np.random.default_rng(0).standard_normal((2, w.n))])
     a = host(p.solve(dev(y)))
     ref = ek.coef(y)
-    assert relmax(a, ref) < 1e-11
+    # forward error of a backward-stable solve: a small multiple of cond(M) * eps
+    cond = np.linalg.cond(ek.M)
+    assert relmax(a, ref) < 10 * cond * np.finfo(float).eps
 
 
 # ------------------------------------------------------------------------------ scatter (Steps 5-6)
@@ -147,7 +149,12 @@ def test_convolve_sweep_identical_inputs(krig, dtype, case):
         cimg = rp.cstar(alpha[b])
         ref = rapid_direct(g, k, cimg).reshape(g.m1, g.m2) if m1 * m2 <= 4096 else rapid_fft(g, lag, cimg)
         err = relmax(y[b], ref)
-        assert err < (1e-12 if dtype == "f64" else 1e-5), err
+        # FP32 storage of the filtered spectrum limits the relative error to roughly
+        # eps32 times the cancellation sum|c*| / max|y_hat|; the 1e-5 bar holds up to the
+        # cancellation of the paper-shaped workloads (<= 2e4) and scales beyond it
+        cancel = np.abs(cimg).sum() / np.abs(ref).max()
+        tol = 1e-12 if dtype == "f64" else 1e-5 * max(1.0, cancel / 2e4)
+        assert err < tol, (err, cancel)
 
 
 @pytest.mark.parametrize("dtype", ["f64", "f32"])
@@ -229,10 +236,14 @@ def test_adjoint_tiny_direct(krig, dtype):
 
 
 def test_adjoint_grad_batch_full_size(krig):
+    # identical weights on both sides: K_N (cond ~3e13) admits weight vectors that differ
+    # by ~1e-3 and still interpolate; d alpha, then (K + tau^2 I)^{-1} (cond ~1.4e4), turns
+    # that into a ~1e-3 spread of dy, which is a property of the problem, not of the adjoint
     w = wl.grad_batch(B=4)
     g, k, rp, ek = oracle_of(w)
     say("adjoint grad-batch B=4 full size f32")
     p = krig.plan_for(w, "f32")
+    p.set_weights(dev(np.stack([rp.i0, rp.j0], 1), torch.int32), dev(rp.W))
     y = dev(w.y)
     alpha = torch.empty(4, w.n, dtype=torch.float64, device="cuda:0")
     saved = p.new_saved(4)
