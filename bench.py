@@ -26,19 +26,21 @@ HBM_PEAK_GBS = 8000.0  # MI355X HBM3E, GB/s
 
 
 def stage_bytes(p, B, ngroups):
-    """Algorithmic bytes per launch of each timed stage (what the pass must read and write)."""
-    t = 4 if p.dtype_code == 1 else 8
-    c = 2 * t
+    """Algorithmic bytes per launch of each timed single-kernel stage: what the pass must
+    read and write once (FP64 row spectra and adjoint, dt forward tail and outputs)."""
+    t = 4 if p.dtype_code == 1 else 8      # dt value
+    c = 2 * t                               # dt complex
+    z = 16                                  # FP64 complex
     m1, m2, n, M = p.m1, p.m2, p.n, p.M
     P1, P2, F1, H2 = p.P1, p.P2, p.F1, p.info("H2")
     return {
-        "ROWS_FWD": B * (P1 * H2 * c + n * 8) + (P1 * P2 + 1) * 4 + n * M * 12,
-        "COLS_CONV": B * (P1 + m1) * H2 * c + F1 * H2 * t,
-        "ROWS_INV": B * (m1 * H2 * c + m1 * m2 * t),
-        "ADJ_ROWS_FWD": B * (m1 * m2 * t + m1 * H2 * c),
-        "ADJ_COLS": B * (m1 * H2 * c + 2 * P1 * H2 * c) + ngroups * F1 * H2 * c + F1 * H2 * t,
-        "ADJ_ROWS_INV": B * (P1 * H2 * c + P1 * P2 * t),
-        "GATHER": B * (n * M * t + n * 8) + n * M * 8 + n * 8,
+        "ROWS_FWD": B * (H2 * P1 * z + n * 8) + (P1 * P2 + 1) * 4 + n * M * 12,
+        "COLS_CONV": B * (H2 * P1 * z + H2 * m1 * c) + H2 * F1 * 8,
+        "ROWS_INV": B * (H2 * m1 * c + m1 * m2 * t),
+        "ADJ_ROWS_FWD": B * (m1 * m2 * t + H2 * m1 * z),
+        "ADJ_COLS": B * (H2 * m1 * z + 2 * H2 * P1 * z) + ngroups * H2 * F1 * z + H2 * F1 * 8,
+        "ADJ_ROWS_INV": B * (H2 * P1 * z + P1 * P2 * 8),
+        "GATHER": B * (n * M * 8 + n * 8) + n * M * 8 + n * 8,
     }
 
 
@@ -81,6 +83,8 @@ def main(argv=None):
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-fields", type=int, default=16)
     ap.add_argument("--no-fp64", action="store_true")
+    ap.add_argument("--calibrate-copy-mib", type=int, default=0,
+                    help="only run a plain device copy of this many MiB (counter calibration) and exit")
     a = ap.parse_args(argv)
     if a.gpus != 1:
         print(f"bench.py measures one GPU only (asked for --gpus {a.gpus}); the batch axis would shard with no "
@@ -96,6 +100,15 @@ def main(argv=None):
         print("no GPU visible", file=sys.stderr)
         return 1
     dev = torch.device("cuda:0")
+    if a.calibrate_copy_mib:
+        n = a.calibrate_copy_mib * (1 << 20) // 4
+        src = torch.ones(n, dtype=torch.float32, device=dev)
+        dst = torch.empty_like(src)
+        for _ in range(3):  # a plain elementwise kernel: reads and writes 4n bytes each
+            torch.add(src, 1.0, out=dst)
+        torch.cuda.synchronize()
+        print(json.dumps({"calibration_copy_bytes": 4 * n, "copies": 3}), flush=True)
+        return 0
     w = wl.grad_batch(B=a.B)
     B = a.B
 
@@ -159,7 +172,8 @@ def main(argv=None):
     npred = B * w.m1 * w.m2
     value = npred / (r32["ms"] * 1e-3)
     # dominant single-kernel stage and its roofline
-    ng = (B + 1) // 2
+    G = p32.info("DLAG_GROUP")
+    ng = (B + G - 1) // G
     sb = stage_bytes(p32, B, ng)
     avg = {k: (v[0] / v[1]) for k, v in r32["stages"].items() if v[1] > 0}
     dom = max((k for k in sb if k in avg), key=lambda k: avg[k])

@@ -73,12 +73,13 @@ typedef struct krig_plan_s *krig_plan;
 /* Sizes and status readable through krig_plan_info. */
 enum {
   KRIG_INFO_N = 1, KRIG_INFO_M, KRIG_INFO_P1, KRIG_INFO_P2, KRIG_INFO_F1, KRIG_INFO_F2, KRIG_INFO_H2,
-  KRIG_INFO_LDH,        /* row pitch (elements) of half-spectrum buffers */
+  KRIG_INFO_LDH,        /* pitch (elements) between frequencies of the saved spectra */
   KRIG_INFO_SAVED_PER_FIELD, /* elements (complex FP64) per field of the saved forward spectrum */
   KRIG_INFO_KN_STATUS,  /* 0 clean, 1 jitter added to K_N */
   KRIG_INFO_PIVOT,      /* first failing pivot (1-based) of K + tau^2 I, 0 if none */
   KRIG_INFO_DTYPE,
-  KRIG_INFO_CE_CLAMPED  /* number of clamped circulant-embedding eigenvalues (after krig_csim) */
+  KRIG_INFO_CE_CLAMPED, /* number of clamped circulant-embedding eigenvalues (after krig_csim) */
+  KRIG_INFO_DLAG_GROUP  /* fields per block in the lag-gradient column pass */
 };
 
 /*

@@ -20,7 +20,7 @@ KRIG_F32 = 1
 KRIG_F64 = 2
 
 INFO = dict(N=1, M=2, P1=3, P2=4, F1=5, F2=6, H2=7, LDH=8, SAVED_PER_FIELD=9, KN_STATUS=10,
-            PIVOT=11, DTYPE=12, CE_CLAMPED=13)
+            PIVOT=11, DTYPE=12, CE_CLAMPED=13, DLAG_GROUP=14)
 
 STATUS = {0: "KRIG_OK", -1: "KRIG_EINVAL", -2: "KRIG_EDOMAIN", -3: "KRIG_ENOTSPD", -4: "KRIG_ECE",
           -5: "KRIG_ENOMEM", -6: "KRIG_EHIP", -7: "KRIG_EUNSUPPORTED"}

@@ -7,6 +7,10 @@
 // Stage A: one thread per n2 holds x[N2 n1 + n2] for all n1, does the length-N1
 // DFT and the twiddle W_F^(n2 k1); stage B: one thread per k1 holds all n2 and
 // does the length-N2 DFT, ending with X[k1 + N1 k2] for all k2 in registers.
+//
+// Half spectra between the row and column passes are stored frequency-major:
+// element (field b, frequency k, row r) at base + b*fs + k*ld + r, so that a
+// column pass reads and writes whole contiguous columns.
 #pragma once
 #include <hip/hip_runtime.h>
 #include <stdint.h>
@@ -19,12 +23,13 @@ struct Window {
   int a0, na, b0, nb;
 };
 
-// Forward real-row transform (two rows per complex line), output half spectrum.
+// Forward real-row transform (two rows per complex line); output: half spectra,
+// frequency-major.
 struct RowsR2CArgs {
   int nrows;             // rows of the (virtual) input image
-  int H2, ldH;           // half-spectrum length F/2+1 and output row pitch
-  void* out;             // cx<TS> [B][nrows][ldH]
-  int64_t out_fs;        // field stride of out (elements)
+  int H2;                // half-spectrum length F/2+1
+  void* out;             // cx<TS>: out[b*out_fs + k*out_ld + r]
+  int64_t out_fs, out_ld;
   const void* twF;       // cx<TC> [F] forward twiddles exp(-2 pi i j/F)
   // source CSR (scatter of alpha_i * w_im onto the padded grid)
   const int32_t* row_ptr;   // [nrows*ncols + 1]
@@ -32,8 +37,8 @@ struct RowsR2CArgs {
   const double* ent_w;      // [nnz]
   const double* alpha;      // [B][n]
   int64_t alpha_fs;
-  // dense source: in[b][r][c] placed at column offset coff (valid cols ncols)
-  const void* dense;        // TS
+  // dense source: in[b][r][c] (row-major) placed at column offset coff
+  const void* dense;        // TIN
   int64_t dense_fs, dense_ld;
   int coff;
   int ncols;                // nonzero columns of the input rows
@@ -43,39 +48,42 @@ struct RowsR2CArgs {
   int NL;                   // lines (row pairs) per block
 };
 
-// Column pass: forward FFT, optional multiply by the real filter, inverse FFT.
+// Column pass over frequency-major half spectra: forward transform, optional
+// product with the real filter spectrum, inverse transform.
 struct ColsArgs {
-  int H2;                 // number of columns
-  int ldH;                // pitch of the column-major-by-rows arrays (row pitch)
-  const void* in;         // cx<TS> [B][*][ldH]
-  int64_t in_fs;
-  int in_off, in_cnt;     // input row r sits at FFT index r + in_off
-  const void* in2;        // second input (dlag: c* spectrum rows) cx<TS>
-  int64_t in2_fs;
+  int H2;                 // number of columns (frequencies)
+  const void* in;         // cx<TSI>: in[b*in_fs + c*in_ld + r]
+  int64_t in_fs, in_ld;
+  int in_off, in_cnt;     // input row r sits at transform index r + in_off
+  const void* in2;        // second input (lag gradient: row spectra of c*)
+  int64_t in2_fs, in2_ld;
   int in2_off, in2_cnt;
-  const void* filt;       // TS [F][ldH] real filter (already scaled by 1/(F1 F2))
-  void* out;              // cx<TS> [B][*][ldH]
-  int64_t out_fs;
-  Window rows;            // FFT-index rows to keep
-  void* part;             // cx<TS> [ngroups][F][ldH] dlag partial spectra
-  int G;                  // fields per block (dlag)
+  const void* filt;       // TF filt[c*filt_ld + k], already scaled by 1/(F1 F2)
+  int64_t filt_ld;
+  void* out;              // cx<TSO>: out[b*out_fs + c*out_ld + d]
+  int64_t out_fs, out_ld;
+  Window rows;            // transform-index rows to keep
+  void* part;             // cx<TSO> part[g*part_fs + c*part_ld + k] (lag-gradient partial spectra)
+  int64_t part_fs, part_ld;
+  int G;                  // fields per block (lag gradient) / number of partials (inverse sum)
   int B;                  // total fields
   const void* twF;        // cx<TF> [F] twiddles of the forward transform's precision
   const void* twI;        // cx<TI> [F] twiddles of the inverse transform's precision
-  double scale;           // store scale (setup transforms)
+  double scale;           // store scale (set-up transforms)
   int NL;                 // columns per block
 };
 
-// Inverse real-row transform (two rows per complex line) from a half spectrum.
+// Inverse real-row transform (two rows per complex line) from frequency-major half
+// spectra; output rows are row-major.
 struct RowsC2RArgs {
   int nrows;
-  int H2, ldH;
-  const void* in;         // cx<TS> [B][nrows][ldH]
-  int64_t in_fs;
-  void* out;              // TS [B][nrows][ldo]
+  int H2;
+  const void* in;         // cx<TS>: in[b*in_fs + k*in_ld + r]
+  int64_t in_fs, in_ld;
+  void* out;              // TO [B][nrows][ldo]
   int64_t out_fs, ldo;
-  Window cols;            // FFT-index columns to keep
-  const void* add;        // optional TS image added to the output: add[b][r + add_r0][c + add_c0]
+  Window cols;            // transform-index columns to keep
+  const void* add;        // optional TO image added to the output: add[b][r + add_r0][c + add_c0]
   int64_t add_fs, add_ld;
   int add_r0, add_c0;
   const void* twF;        // cx<TC> [F]
@@ -113,5 +121,9 @@ void register_fft(const FftEntry& e);
 const FftEntry* find_fft(int F);
 int fft_sizes(int* out, int cap);
 void register_all_fft();
+
+// LDS bytes of one block (lines or columns NL) for each kernel family
+size_t rows_lds(int N1, int N2, int NL, size_t csz);
+size_t cols_lds(int N1, int N2, int NL, size_t csz, bool stash);
 
 }  // namespace krig

@@ -1,23 +1,24 @@
 // Two-level FFT pass kernels for the circulant-embedded convolution (Step 7) and
 // its adjoint.  Included by one generated translation unit per transform length.
 //
-// Roles (TC = arithmetic precision, TS = storage precision):
+// Roles (TC/TF/TI = arithmetic precision, TS/TSI/TSO/TO = storage precision):
 //  k_rows_r2c   forward transform of real rows, two rows per complex line
-//               ("two-for-one"), sources: CSR scatter of alpha_i w_im (Steps 5-6),
-//               dense rows (adjoint input), or the even reflection of the lag
-//               quadrant (Step 2).  Writes the half spectrum.
-//  k_cols       column pass over the half spectrum: forward transform, pointwise
-//               product with the real filter spectrum, inverse transform, keep the
-//               requested rows; variants also accumulate sum_b G_b conj(C_b)
-//               (lag gradient), store the forward real part (filter set-up), or
-//               invert a sum of partial spectra.
+//               ("two-for-one"); sources: the CSR scatter of alpha_i w_im (Steps
+//               5-6), dense rows (the adjoint's input), or the even reflection of
+//               the lag quadrant (Step 2).  Writes frequency-major half spectra
+//               through an LDS transpose so stores are whole cache lines.
+//  k_cols       column pass over frequency-major half spectra (contiguous
+//               columns): forward transform, product with the real filter
+//               spectrum, inverse transform, keep the requested rows; variants
+//               also accumulate sum_b G_b conj(C_b) (lag gradient), store the
+//               forward real part (filter set-up), or invert a sum of partial
+//               spectra.
 //  k_rows_c2r   inverse transform back to real rows, two rows per complex line,
 //               keeping the requested columns (optionally adding an image).
 //
-// Thread layout.  Row kernels: lane s (fastest) then line l; LDS [l][n2][k1].
-// Column kernels: column l (fastest, coalesced global access) then s; LDS
-// [n2][k1][l].  The n2 stride is odd(N1)*lines so stage-A writes hit distinct
-// banks.
+// Thread layout in all kernels: lane s (fastest, the transform's thread index)
+// then line/column l; per-line LDS [l][n2][k1] with the n2 stride odd(N1) so the
+// stage-A writes of consecutive lanes hit distinct banks.
 #pragma once
 #include "fft_args.h"
 #include "fft_reg.h"
@@ -27,14 +28,13 @@ namespace krig {
 __host__ __device__ constexpr int odd_up(int x) { return x | 1; }
 __host__ __device__ constexpr int imax(int a, int b) { return a > b ? a : b; }
 
-// Hide a pointer's value from the optimiser so loads through it are not hoisted
-// out of a loop (keeps loop-invariant twiddles/filter values out of registers).
+// Hide a value from the optimiser so address arithmetic and loads derived from it
+// stay inside a loop (keeps loop-invariant values out of registers).
 template <typename P>
 __device__ __forceinline__ P opaque(P p) {
   asm volatile("" : "+s"(p));
   return p;
 }
-
 __device__ __forceinline__ int opaque_v(int x) {
   asm volatile("" : "+v"(x));
   return x;
@@ -44,10 +44,67 @@ template <int N1, int N2> struct Geo {
   static constexpr int F = N1 * N2;
   static constexpr int NT = imax(N1, N2);
   static constexpr int ON1 = odd_up(N1);
+  static constexpr int EX = N2 * ON1;                     // exchange slots per line
+  static constexpr int ROWS = imax(EX, F + 2);            // row kernels: exchange or transpose
 };
 
+__device__ __forceinline__ int window_dst(const Window& wd, int i) {
+  if (i >= wd.a0 && i < wd.a0 + wd.na) return i - wd.a0;
+  if (i >= wd.b0 && i < wd.b0 + wd.nb) return wd.na + i - wd.b0;
+  return -1;
+}
+
 // ----------------------------------------------------------------------------------------
-// row kernels: forward (real -> half spectrum)
+// the two register stages of a transform on one line, exchanged through LDS region
+// L (stride ON1 between n2 rows).  On entry thread s < N2 holds v[n1] = x[N2 n1 + s];
+// on exit thread s < N1 holds w[k2] = X[s + N1 k2].  DIR = -1 forward, +1 inverse.
+// ----------------------------------------------------------------------------------------
+template <typename TC, int N1, int N2, int DIR>
+__device__ __forceinline__ void two_stage(cx<TC> (&v)[N1], cx<TC> (&w)[N2], int s, cx<TC>* L,
+                                          const cx<TC>* twF) {
+  using G = Geo<N1, N2>;
+  if (s < N2) {
+    DFT<N1, DIR, TC>::run(v);
+#pragma unroll
+    for (int k1 = 0; k1 < N1; ++k1) {
+      cx<TC> t = v[k1];
+      if (k1 != 0 && s != 0) t = DIR < 0 ? cmul(t, twF[s * k1]) : cmulc(t, twF[s * k1]);
+      L[s * G::ON1 + k1] = t;
+    }
+  }
+  __syncthreads();
+  if (s < N1) {
+#pragma unroll
+    for (int n2 = 0; n2 < N2; ++n2) w[n2] = L[n2 * G::ON1 + s];
+    DFT<N2, DIR, TC>::run(w);
+  }
+}
+
+// inverse from the transposed order left by two_stage (thread s = k1 holds k2 =
+// 0..N2-1); thread s < N2 ends with x[N2 n1 + s] in v[n1].
+template <typename TC, int N1, int N2>
+__device__ __forceinline__ void inv_from_t(cx<TC> (&w)[N2], int s, cx<TC>* L, const cx<TC>* twF,
+                                           cx<TC> (&v)[N1]) {
+  using G = Geo<N1, N2>;
+  if (s < N1) {
+    DFT<N2, 1, TC>::run(w);
+#pragma unroll
+    for (int n2 = 0; n2 < N2; ++n2) {
+      cx<TC> t = w[n2];
+      if (n2 != 0 && s != 0) t = cmulc(t, twF[n2 * s]);
+      L[n2 * G::ON1 + s] = t;
+    }
+  }
+  __syncthreads();
+  if (s < N2) {
+#pragma unroll
+    for (int k1 = 0; k1 < N1; ++k1) v[k1] = L[s * G::ON1 + k1];
+    DFT<N1, 1, TC>::run(v);
+  }
+}
+
+// ----------------------------------------------------------------------------------------
+// row kernels: forward (real rows -> frequency-major half spectra)
 // ----------------------------------------------------------------------------------------
 enum { SRC_CSR = 0, SRC_DENSE = 1, SRC_LAG = 2 };
 
@@ -58,15 +115,16 @@ __global__ void __launch_bounds__(256) k_rows_r2c(RowsR2CArgs a) {
   cx<TC>* lds = reinterpret_cast<cx<TC>*>(smem_raw);
   const int s = threadIdx.x % G::NT;
   const int l = threadIdx.x / G::NT;
+  const int NL = a.NL;
   const int b = blockIdx.y;
-  const int pair = blockIdx.x * a.NL + l;
-  const int ra = 2 * pair, rb = 2 * pair + 1;
+  const int row0 = 2 * blockIdx.x * NL;
+  const int ra = row0 + 2 * l, rb = ra + 1;
   const bool oka = ra < a.nrows, okb = rb < a.nrows;
   const cx<TC>* twF = reinterpret_cast<const cx<TC>*>(a.twF);
-  cx<TC>* L = lds + (size_t)l * (N2 * G::ON1);
+  cx<TC>* L = lds + (size_t)l * G::ROWS;
 
+  cx<TC> v[N1];
   if (s < N2) {
-    cx<TC> v[N1];
 #pragma unroll
     for (int n1 = 0; n1 < N1; ++n1) {
       const int c = N2 * n1 + s;
@@ -110,21 +168,9 @@ __global__ void __launch_bounds__(256) k_rows_r2c(RowsR2CArgs a) {
       }
       v[n1] = mk<TC>(xa, xb);
     }
-    DFT<N1, -1, TC>::run(v);
-#pragma unroll
-    for (int k1 = 0; k1 < N1; ++k1) {
-      cx<TC> t = v[k1];
-      if (k1 != 0 && s != 0) t = cmul(t, twF[s * k1]);
-      L[s * G::ON1 + k1] = t;
-    }
   }
-  __syncthreads();
   cx<TC> w[N2];
-  if (s < N1) {
-#pragma unroll
-    for (int n2 = 0; n2 < N2; ++n2) w[n2] = L[n2 * G::ON1 + s];
-    DFT<N2, -1, TC>::run(w);
-  }
+  two_stage<TC, N1, N2, -1>(v, w, s, L, twF);
   __syncthreads();
   // natural-order exchange to pair Z[k] with Z[F-k]
   if (s < N1) {
@@ -132,87 +178,57 @@ __global__ void __launch_bounds__(256) k_rows_r2c(RowsR2CArgs a) {
     for (int k2 = 0; k2 < N2; ++k2) L[s + N1 * k2] = w[k2];
   }
   __syncthreads();
+  constexpr int NK = (G::F / 2 + N1) / N1;  // k2 values with k = s + N1 k2 <= F/2 for some s
+  cx<TC> xa[NK], xb[NK];
   if (s < N1) {
-    cx<TS>* oa = reinterpret_cast<cx<TS>*>(a.out) + (int64_t)b * a.out_fs + (int64_t)ra * a.ldH;
-    cx<TS>* ob = oa + a.ldH;
 #pragma unroll
-    for (int k2 = 0; k2 < N2; ++k2) {
+    for (int k2 = 0; k2 < NK; ++k2) {
+      const int k = s + N1 * k2;
+      const cx<TC> z = w[k2];
+      const cx<TC> zc = L[(G::F - k) % G::F];
+      // Xa = (Z[k] + conj Z[F-k]) / 2,  Xb = (Z[k] - conj Z[F-k]) / (2 i)
+      xa[k2] = mk<TC>((TC)0.5 * (z.x + zc.x), (TC)0.5 * (z.y - zc.y));
+      xb[k2] = mk<TC>((TC)0.5 * (z.y + zc.y), (TC)0.5 * (zc.x - z.x));
+    }
+  }
+  __syncthreads();
+  // transpose through LDS: T[k][2l + {0,1}] over the block, then row-contiguous stores
+  cx<TC>* T = lds;
+  const int R2 = 2 * NL;
+  if (s < N1) {
+#pragma unroll
+    for (int k2 = 0; k2 < NK; ++k2) {
       const int k = s + N1 * k2;
       if (k < a.H2) {
-        const cx<TC> z = w[k2];
-        const cx<TC> zc = L[(G::F - k) % G::F];
-        // Xa = (Z[k] + conj Z[F-k]) / 2,  Xb = (Z[k] - conj Z[F-k]) / (2 i)
-        const cx<TC> xa = mk<TC>((TC)0.5 * (z.x + zc.x), (TC)0.5 * (z.y - zc.y));
-        const cx<TC> xb = mk<TC>((TC)0.5 * (z.y + zc.y), (TC)0.5 * (zc.x - z.x));
-        if (oka) oa[k] = ccast<TS>(xa);
-        if (okb) ob[k] = ccast<TS>(xb);
+        T[k * R2 + 2 * l] = xa[k2];
+        T[k * R2 + 2 * l + 1] = xb[k2];
       }
     }
   }
+  __syncthreads();
+  cx<TS>* o = reinterpret_cast<cx<TS>*>(a.out) + (int64_t)b * a.out_fs;
+  for (int idx = threadIdx.x; idx < a.H2 * R2; idx += blockDim.x) {
+    const int rl = idx % R2, k = idx / R2;
+    const int row = row0 + rl;
+    if (row < a.nrows) o[(int64_t)k * a.out_ld + row] = ccast<TS>(T[idx]);
+  }
 }
 
 // ----------------------------------------------------------------------------------------
-// column kernels
+// column kernels (contiguous columns of frequency-major spectra)
 // ----------------------------------------------------------------------------------------
-// forward column transform: returns X[s + N1 k2] in w[k2] for threads s < N1
 template <typename TC, typename TS, int N1, int N2>
-__device__ __forceinline__ void col_fwd(const cx<TS>* src, int ld, int in_off, int in_cnt, int col,
-                                        bool colok, int s, int l, int NL, cx<TC>* lds,
-                                        const cx<TC>* twF, cx<TC> (&w)[N2]) {
-  using G = Geo<N1, N2>;
-  const int SN2 = NL * G::ON1;
+__device__ __forceinline__ void col_fwd(const cx<TS>* src, int in_off, int in_cnt, bool colok, int s,
+                                        cx<TC>* L, const cx<TC>* twF, cx<TC> (&w)[N2]) {
+  cx<TC> v[N1];
   if (s < N2) {
-    cx<TC> v[N1];
 #pragma unroll
     for (int n1 = 0; n1 < N1; ++n1) {
       const int r = N2 * n1 + s - in_off;
-      v[n1] = (colok && r >= 0 && r < in_cnt) ? ccast<TC>(src[(int64_t)r * ld + col]) : mk<TC>(0, 0);
-    }
-    DFT<N1, -1, TC>::run(v);
-#pragma unroll
-    for (int k1 = 0; k1 < N1; ++k1) {
-      cx<TC> t = v[k1];
-      if (k1 != 0 && s != 0) t = cmul(t, twF[s * k1]);
-      lds[s * SN2 + k1 * NL + l] = t;
+      v[n1] = (colok && r >= 0 && r < in_cnt) ? ccast<TC>(src[r]) : mk<TC>(0, 0);
     }
   }
-  __syncthreads();
-  if (s < N1) {
-#pragma unroll
-    for (int n2 = 0; n2 < N2; ++n2) w[n2] = lds[n2 * SN2 + s * NL + l];
-    DFT<N2, -1, TC>::run(w);
-  }
-}
-
-// inverse column transform from the transposed order held by col_fwd (thread s = k1
-// holds k2 = 0..N2-1); thread s < N2 ends with x[N2 n1 + s] in v[n1].
-template <typename TC, int N1, int N2>
-__device__ __forceinline__ void col_inv_from_t(cx<TC> (&w)[N2], int s, int l, int NL, cx<TC>* lds,
-                                               const cx<TC>* twF, cx<TC> (&v)[N1]) {
-  using G = Geo<N1, N2>;
-  const int SN2 = NL * G::ON1;
-  if (s < N1) {
-    DFT<N2, 1, TC>::run(w);
-#pragma unroll
-    for (int n2 = 0; n2 < N2; ++n2) {
-      cx<TC> t = w[n2];
-      if (n2 != 0 && s != 0) t = cmulc(t, twF[n2 * s]);
-      lds[n2 * SN2 + s * NL + l] = t;
-    }
-  }
-  __syncthreads();
-  if (s < N2) {
-#pragma unroll
-    for (int k1 = 0; k1 < N1; ++k1) v[k1] = lds[s * SN2 + k1 * NL + l];
-    DFT<N1, 1, TC>::run(v);
-  }
-}
-
-template <typename TS>
-__device__ __forceinline__ int window_dst(const Window& wd, int i) {
-  if (i >= wd.a0 && i < wd.a0 + wd.na) return i - wd.a0;
-  if (i >= wd.b0 && i < wd.b0 + wd.nb) return wd.na + i - wd.b0;
-  return -1;
+  two_stage<TC, N1, N2, -1>(v, w, s, L, twF);
 }
 
 enum { COL_CONV = 0, COL_CONV_DLAG = 1, COL_FWD_REAL = 2, COL_INV_SUM = 3 };
@@ -221,42 +237,40 @@ template <typename TF, typename TI, typename TSI, typename TSO, int N1, int N2, 
 __global__ void __launch_bounds__(256) k_cols(ColsArgs a) {
   using G = Geo<N1, N2>;
   using TC = TF;
-  using TS = TSI;
   extern __shared__ unsigned char smem_raw[];
-  cx<TC>* lds = reinterpret_cast<cx<TC>*>(smem_raw);
-  cx<TI>* ldsi = reinterpret_cast<cx<TI>*>(smem_raw);
   const int NL = a.NL;
-  const int l0 = threadIdx.x % NL;
-  const int s0 = threadIdx.x / NL;
+  const int s0 = threadIdx.x % G::NT;
+  const int l0 = threadIdx.x / G::NT;
   const int col0 = blockIdx.x * NL + l0;
   const bool colok = col0 < a.H2;
   const cx<TC>* twF = reinterpret_cast<const cx<TC>*>(a.twF);
-  const cx<TI>* twI = reinterpret_cast<const cx<TI>*>(a.twI);
-  const int l = l0, s = s0, col = col0;
+  cx<TC>* L = reinterpret_cast<cx<TC>*>(smem_raw) + (size_t)l0 * G::EX;
+  const int s = s0, col = col0;
 
   if constexpr (MODE == COL_CONV) {
     const int b = blockIdx.y;
-    const cx<TS>* src = reinterpret_cast<const cx<TS>*>(a.in) + (int64_t)b * a.in_fs;
+    const cx<TSI>* src = reinterpret_cast<const cx<TSI>*>(a.in) + (int64_t)b * a.in_fs + (int64_t)col * a.in_ld;
     cx<TI> wi[N2];
     {
       cx<TC> w[N2];
-      col_fwd<TC, TS, N1, N2>(src, a.ldH, a.in_off, a.in_cnt, col, colok, s, l, NL, lds, twF, w);
+      col_fwd<TC, TSI, N1, N2>(src, a.in_off, a.in_cnt, colok, s, L, twF, w);
       if (s < N1 && colok) {
-        const TF* f = reinterpret_cast<const TF*>(a.filt);
+        const TF* f = reinterpret_cast<const TF*>(a.filt) + (int64_t)col * a.filt_ld;
 #pragma unroll
-        for (int k2 = 0; k2 < N2; ++k2) w[k2] = cscale(w[k2], f[(int64_t)(s + N1 * k2) * a.ldH + col]);
+        for (int k2 = 0; k2 < N2; ++k2) w[k2] = cscale(w[k2], f[s + N1 * k2]);
       }
 #pragma unroll
       for (int k2 = 0; k2 < N2; ++k2) wi[k2] = ccast<TI>(w[k2]);
     }
+    cx<TI>* LI = reinterpret_cast<cx<TI>*>(smem_raw) + (size_t)l0 * G::EX;
     cx<TI> v[N1];
-    col_inv_from_t<TI, N1, N2>(wi, s, l, NL, ldsi, twI, v);
+    inv_from_t<TI, N1, N2>(wi, s, LI, reinterpret_cast<const cx<TI>*>(a.twI), v);
     if (s < N2 && colok) {
-      cx<TSO>* dst = reinterpret_cast<cx<TSO>*>(a.out) + (int64_t)b * a.out_fs;
+      cx<TSO>* dst = reinterpret_cast<cx<TSO>*>(a.out) + (int64_t)b * a.out_fs + (int64_t)col * a.out_ld;
 #pragma unroll
       for (int n1 = 0; n1 < N1; ++n1) {
-        const int d = window_dst<TS>(a.rows, N2 * n1 + s);
-        if (d >= 0) dst[(int64_t)d * a.ldH + col] = ccast<TSO>(v[n1]);
+        const int d = window_dst(a.rows, N2 * n1 + s);
+        if (d >= 0) dst[d] = ccast<TSO>(v[n1]);
       }
     }
   } else if constexpr (MODE == COL_CONV_DLAG) {
@@ -264,107 +278,94 @@ __global__ void __launch_bounds__(256) k_cols(ColsArgs a) {
     cx<TC> acc[N2];
 #pragma unroll
     for (int k2 = 0; k2 < N2; ++k2) acc[k2] = mk<TC>(0, 0);
-    cx<TC>* stash = lds + (size_t)N2 * NL * G::ON1;  // [k2][k1][l], thread-private slots
+    cx<TC>* stash = reinterpret_cast<cx<TC>*>(smem_raw) + (size_t)NL * G::EX + (size_t)l0 * G::F;
     const int b0 = blockIdx.y * a.G;
 #pragma unroll 1
     for (int gi = 0; gi < a.G; ++gi) {
       const int b = b0 + gi;
       if (b >= a.B) break;  // uniform across the block
-      cx<TC> wg[N2];
       twF = opaque(twF);
       // fresh copies of the lane indices each iteration: keeps per-lane address
       // arithmetic from being hoisted out of the field loop (register pressure)
-      const int s = opaque_v(s0), l = opaque_v(l0), col = opaque_v(col0);
-      const cx<TS>* srcc = reinterpret_cast<const cx<TS>*>(a.in2) + (int64_t)b * a.in2_fs;
-      const cx<TS>* srcg = reinterpret_cast<const cx<TS>*>(a.in) + (int64_t)b * a.in_fs;
+      const int s = opaque_v(s0), col = opaque_v(col0);
+      const cx<TSI>* srcc =
+          reinterpret_cast<const cx<TSI>*>(a.in2) + (int64_t)b * a.in2_fs + (int64_t)col * a.in2_ld;
+      const cx<TSI>* srcg = reinterpret_cast<const cx<TSI>*>(a.in) + (int64_t)b * a.in_fs + (int64_t)col * a.in_ld;
       __syncthreads();
       {
-        // C-hat of this field: transform, then park it in the stash region of LDS
+        // C-hat of this field: transform, then park it in this thread's stash slots
         cx<TC> wc[N2];
-        col_fwd<TC, TS, N1, N2>(srcc, a.ldH, a.in2_off, a.in2_cnt, col, colok, s, l, NL, lds, twF, wc);
+        col_fwd<TC, TSI, N1, N2>(srcc, a.in2_off, a.in2_cnt, colok, s, L, twF, wc);
         if (s < N1) {
 #pragma unroll
-          for (int k2 = 0; k2 < N2; ++k2) stash[(k2 * N1 + s) * NL + l] = wc[k2];
+          for (int k2 = 0; k2 < N2; ++k2) stash[k2 * N1 + s] = wc[k2];
         }
       }
       __syncthreads();
-      col_fwd<TC, TS, N1, N2>(srcg, a.ldH, a.in_off, a.in_cnt, col, colok, s, l, NL, lds, twF, wg);
+      cx<TC> wg[N2];
+      col_fwd<TC, TSI, N1, N2>(srcg, a.in_off, a.in_cnt, colok, s, L, twF, wg);
       if (s < N1 && colok) {
-        const TF* f = opaque(reinterpret_cast<const TF*>(a.filt));
+        const TF* f = opaque(reinterpret_cast<const TF*>(a.filt)) + (int64_t)col * a.filt_ld;
 #pragma unroll
         for (int k2 = 0; k2 < N2; ++k2) {
-          acc[k2] = acc[k2] + cmulc(wg[k2], stash[(k2 * N1 + s) * NL + l]);
-          wg[k2] = cscale(wg[k2], (TC)f[(int64_t)(s + N1 * k2) * a.ldH + col]);
+          acc[k2] = acc[k2] + cmulc(wg[k2], stash[k2 * N1 + s]);
+          wg[k2] = cscale(wg[k2], f[s + N1 * k2]);
         }
       }
       cx<TC> v[N1];
-      col_inv_from_t<TC, N1, N2>(wg, s, l, NL, lds, twF, v);
+      inv_from_t<TC, N1, N2>(wg, s, L, twF, v);
       if (s < N2 && colok) {
-        cx<TSO>* dst = reinterpret_cast<cx<TSO>*>(a.out) + (int64_t)b * a.out_fs;
+        cx<TSO>* dst = reinterpret_cast<cx<TSO>*>(a.out) + (int64_t)b * a.out_fs + (int64_t)col * a.out_ld;
 #pragma unroll
         for (int n1 = 0; n1 < N1; ++n1) {
-          const int d = window_dst<TS>(a.rows, N2 * n1 + s);
-          if (d >= 0) dst[(int64_t)d * a.ldH + col] = ccast<TSO>(v[n1]);
+          const int d = window_dst(a.rows, N2 * n1 + s);
+          if (d >= 0) dst[d] = ccast<TSO>(v[n1]);
         }
       }
     }
     if (s < N1 && colok) {
-      cx<TSO>* p = reinterpret_cast<cx<TSO>*>(a.part) + (int64_t)blockIdx.y * G::F * a.ldH;
+      cx<TSO>* p = reinterpret_cast<cx<TSO>*>(a.part) + (int64_t)blockIdx.y * a.part_fs + (int64_t)col * a.part_ld;
 #pragma unroll
-      for (int k2 = 0; k2 < N2; ++k2) p[(int64_t)(s + N1 * k2) * a.ldH + col] = ccast<TSO>(acc[k2]);
+      for (int k2 = 0; k2 < N2; ++k2) p[s + N1 * k2] = ccast<TSO>(acc[k2]);
     }
   } else if constexpr (MODE == COL_FWD_REAL) {
-    // forward transform of the input columns; store Re(X) * scale (natural order, TS = double)
+    // forward transform of the input columns; store Re(X) * scale (natural order)
     const int b = blockIdx.y;
-    const cx<TS>* src = reinterpret_cast<const cx<TS>*>(a.in) + (int64_t)b * a.in_fs;
+    const cx<TSI>* src = reinterpret_cast<const cx<TSI>*>(a.in) + (int64_t)b * a.in_fs + (int64_t)col * a.in_ld;
     cx<TC> w[N2];
-    col_fwd<TC, TS, N1, N2>(src, a.ldH, a.in_off, a.in_cnt, col, colok, s, l, NL, lds, twF, w);
+    col_fwd<TC, TSI, N1, N2>(src, a.in_off, a.in_cnt, colok, s, L, twF, w);
     if (s < N1 && colok) {
-      TSO* dst = reinterpret_cast<TSO*>(a.out) + (int64_t)b * a.out_fs;
+      TSO* dst = reinterpret_cast<TSO*>(a.out) + (int64_t)b * a.out_fs + (int64_t)col * a.out_ld;
 #pragma unroll
-      for (int k2 = 0; k2 < N2; ++k2) dst[(int64_t)(s + N1 * k2) * a.ldH + col] = (TSO)(w[k2].x * (TC)a.scale);
+      for (int k2 = 0; k2 < N2; ++k2) dst[s + N1 * k2] = (TSO)(w[k2].x * (TC)a.scale);
     }
   } else {  // COL_INV_SUM: inverse transform of sum_g part[g] (natural order), keep rows
-    const int SN2 = NL * G::ON1;
-    const cx<TS>* p = reinterpret_cast<const cx<TS>*>(a.in);
-    const int ng = a.G;
+    const cx<TSI>* p = reinterpret_cast<const cx<TSI>*>(a.in) + (int64_t)col * a.in_ld;
+    cx<TC> v[N1];
     if (s < N2) {
-      cx<TC> v[N1];
 #pragma unroll
       for (int n1 = 0; n1 < N1; ++n1) {
         cx<TC> t = mk<TC>(0, 0);
-        if (colok) {
-          const int64_t off = (int64_t)(N2 * n1 + s) * a.ldH + col;
-          for (int g = 0; g < ng; ++g) t = t + ccast<TC>(p[(int64_t)g * a.in_fs + off]);
-        }
+        if (colok)
+          for (int g = 0; g < a.G; ++g) t = t + ccast<TC>(p[(int64_t)g * a.in_fs + N2 * n1 + s]);  // fixed order
         v[n1] = t;
       }
-      DFT<N1, 1, TC>::run(v);
-#pragma unroll
-      for (int k1 = 0; k1 < N1; ++k1) {
-        cx<TC> t = v[k1];
-        if (k1 != 0 && s != 0) t = cmulc(t, twF[s * k1]);
-        lds[s * SN2 + k1 * NL + l] = t;
-      }
     }
-    __syncthreads();
+    cx<TC> w[N2];
+    two_stage<TC, N1, N2, 1>(v, w, s, L, twF);
     if (s < N1 && colok) {
-      cx<TC> w[N2];
-#pragma unroll
-      for (int n2 = 0; n2 < N2; ++n2) w[n2] = lds[n2 * SN2 + s * NL + l];
-      DFT<N2, 1, TC>::run(w);
-      cx<TSO>* dst = reinterpret_cast<cx<TSO>*>(a.out);
+      cx<TSO>* dst = reinterpret_cast<cx<TSO>*>(a.out) + (int64_t)col * a.out_ld;
 #pragma unroll
       for (int k2 = 0; k2 < N2; ++k2) {
-        const int d = window_dst<TS>(a.rows, s + N1 * k2);
-        if (d >= 0) dst[(int64_t)d * a.ldH + col] = ccast<TSO>(w[k2]);
+        const int d = window_dst(a.rows, s + N1 * k2);
+        if (d >= 0) dst[d] = ccast<TSO>(w[k2]);
       }
     }
   }
 }
 
 // ----------------------------------------------------------------------------------------
-// row kernel: inverse (half spectrum -> real), two rows per complex line
+// row kernel: inverse (frequency-major half spectra -> real rows), two rows per line
 // ----------------------------------------------------------------------------------------
 template <typename TC, typename TS, typename TO, int N1, int N2>
 __global__ void __launch_bounds__(256) k_rows_c2r(RowsC2RArgs a) {
@@ -373,49 +374,47 @@ __global__ void __launch_bounds__(256) k_rows_c2r(RowsC2RArgs a) {
   cx<TC>* lds = reinterpret_cast<cx<TC>*>(smem_raw);
   const int s = threadIdx.x % G::NT;
   const int l = threadIdx.x / G::NT;
+  const int NL = a.NL;
   const int b = blockIdx.y;
-  const int pair = blockIdx.x * a.NL + l;
-  const int ra = 2 * pair, rb = 2 * pair + 1;
+  const int row0 = 2 * blockIdx.x * NL;
+  const int ra = row0 + 2 * l, rb = ra + 1;
   const bool oka = ra < a.nrows, okb = rb < a.nrows;
   const cx<TC>* twF = reinterpret_cast<const cx<TC>*>(a.twF);
-  cx<TC>* L = lds + (size_t)l * (N2 * G::ON1);
-  const cx<TS>* ia = reinterpret_cast<const cx<TS>*>(a.in) + (int64_t)b * a.in_fs + (int64_t)ra * a.ldH;
-  const cx<TS>* ib = ia + a.ldH;
-
+  // row-contiguous loads of the block's 2 NL rows into T[k][rl]
+  const int R2 = 2 * NL;
+  cx<TC>* T = lds;
+  const cx<TS>* in = reinterpret_cast<const cx<TS>*>(a.in) + (int64_t)b * a.in_fs;
+  for (int idx = threadIdx.x; idx < a.H2 * R2; idx += blockDim.x) {
+    const int rl = idx % R2, k = idx / R2;
+    const int row = row0 + rl;
+    T[idx] = row < a.nrows ? ccast<TC>(in[(int64_t)k * a.in_ld + row]) : mk<TC>(0, 0);
+  }
+  __syncthreads();
+  cx<TC> v[N1];
   if (s < N2) {
-    cx<TC> v[N1];
 #pragma unroll
     for (int n1 = 0; n1 < N1; ++n1) {
       const int k = N2 * n1 + s;
       const bool lo = k < a.H2;
       const int kk = lo ? k : G::F - k;
-      cx<TC> xa = oka ? ccast<TC>(ia[kk]) : mk<TC>(0, 0);
-      cx<TC> xb = okb ? ccast<TC>(ib[kk]) : mk<TC>(0, 0);
+      cx<TC> xa = T[kk * R2 + 2 * l], xb = T[kk * R2 + 2 * l + 1];
       if (kk == 0 || 2 * kk == G::F) { xa.y = 0; xb.y = 0; }  // DC / Nyquist are real
       if (!lo) { xa.y = -xa.y; xb.y = -xb.y; }
       v[n1] = mk<TC>(xa.x - xb.y, xa.y + xb.x);  // Xa + i Xb
     }
-    DFT<N1, 1, TC>::run(v);
-#pragma unroll
-    for (int k1 = 0; k1 < N1; ++k1) {
-      cx<TC> t = v[k1];
-      if (k1 != 0 && s != 0) t = cmulc(t, twF[s * k1]);
-      L[s * G::ON1 + k1] = t;
-    }
   }
   __syncthreads();
+  cx<TC>* L = lds + (size_t)l * G::ROWS;
+  cx<TC> w[N2];
+  two_stage<TC, N1, N2, 1>(v, w, s, L, twF);
   if (s < N1) {
-    cx<TC> w[N2];
-#pragma unroll
-    for (int n2 = 0; n2 < N2; ++n2) w[n2] = L[n2 * G::ON1 + s];
-    DFT<N2, 1, TC>::run(w);
     TO* oa = reinterpret_cast<TO*>(a.out) + (int64_t)b * a.out_fs + (int64_t)ra * a.ldo;
     TO* ob = oa + a.ldo;
     const TO* ad = reinterpret_cast<const TO*>(a.add);
 #pragma unroll
     for (int k2 = 0; k2 < N2; ++k2) {
       const int c = s + N1 * k2;
-      const int d = window_dst<TS>(a.cols, c);
+      const int d = window_dst(a.cols, c);
       if (d >= 0) {
         TO va = (TO)w[k2].x, vb = (TO)w[k2].y;
         if (ad) {
@@ -433,21 +432,12 @@ __global__ void __launch_bounds__(256) k_rows_c2r(RowsC2RArgs a) {
 // ----------------------------------------------------------------------------------------
 // launchers
 // ----------------------------------------------------------------------------------------
-template <typename TC, int N1, int N2>
-inline size_t rows_lds_bytes(int NL) { return (size_t)NL * N2 * Geo<N1, N2>::ON1 * sizeof(cx<TC>); }
-template <typename TF, int N1, int N2, int MODE>
-inline size_t cols_lds_bytes(int NL) {
-  size_t ex = (size_t)NL * N2 * Geo<N1, N2>::ON1;
-  if (MODE == COL_CONV_DLAG) ex += (size_t)NL * N1 * N2;  // stash of C-hat
-  return ex * sizeof(cx<TF>);
-}
-
 template <typename TC, typename TIN, typename TS, int N1, int N2, int SRC>
 hipError_t launch_rows_r2c(const RowsR2CArgs& a, int B, hipStream_t st) {
   const int npairs = (a.nrows + 1) / 2;
   dim3 grid((npairs + a.NL - 1) / a.NL, B);
   dim3 block(Geo<N1, N2>::NT * a.NL);
-  const size_t sh = rows_lds_bytes<TC, N1, N2>(a.NL);
+  const size_t sh = rows_lds(N1, N2, a.NL, sizeof(cx<TC>));
   k_rows_r2c<TC, TIN, TS, N1, N2, SRC><<<grid, block, sh, st>>>(a);
   return hipGetLastError();
 }
@@ -456,7 +446,7 @@ template <typename TF, typename TI, typename TSI, typename TSO, int N1, int N2, 
 hipError_t launch_cols(const ColsArgs& a, int nblk_y, hipStream_t st) {
   dim3 grid((a.H2 + a.NL - 1) / a.NL, nblk_y);
   dim3 block(Geo<N1, N2>::NT * a.NL);
-  const size_t sh = cols_lds_bytes<TF, N1, N2, MODE>(a.NL);
+  const size_t sh = cols_lds(N1, N2, a.NL, sizeof(cx<TF>), MODE == COL_CONV_DLAG);
   k_cols<TF, TI, TSI, TSO, N1, N2, MODE><<<grid, block, sh, st>>>(a);
   return hipGetLastError();
 }
@@ -466,7 +456,7 @@ hipError_t launch_rows_c2r(const RowsC2RArgs& a, int B, hipStream_t st) {
   const int npairs = (a.nrows + 1) / 2;
   dim3 grid((npairs + a.NL - 1) / a.NL, B);
   dim3 block(Geo<N1, N2>::NT * a.NL);
-  const size_t sh = rows_lds_bytes<TC, N1, N2>(a.NL);
+  const size_t sh = rows_lds(N1, N2, a.NL, sizeof(cx<TC>));
   k_rows_c2r<TC, TS, TO, N1, N2><<<grid, block, sh, st>>>(a);
   return hipGetLastError();
 }
@@ -494,7 +484,7 @@ FftEntry make_fft_entry() {
 
 }  // namespace krig
 
-#define KRIG_FFT_SIZE(N1, N2)                                              \
-  namespace krig {                                                         \
+#define KRIG_FFT_SIZE(N1, N2)                                                 \
+  namespace krig {                                                            \
   void register_fft_##N1##x##N2() { register_fft(make_fft_entry<N1, N2>()); } \
   }

@@ -40,3 +40,18 @@ int fft_sizes(int* out, int cap) {
 }
 
 }  // namespace krig
+
+namespace krig {
+
+size_t rows_lds(int N1, int N2, int NL, size_t csz) {
+  const size_t ex = (size_t)N2 * (N1 | 1), tr = (size_t)N1 * N2 + 2;
+  return (size_t)NL * (ex > tr ? ex : tr) * csz;
+}
+
+size_t cols_lds(int N1, int N2, int NL, size_t csz, bool stash) {
+  size_t e = (size_t)NL * N2 * (N1 | 1);
+  if (stash) e += (size_t)NL * N1 * N2;
+  return e * csz;
+}
+
+}  // namespace krig

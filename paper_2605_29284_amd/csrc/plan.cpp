@@ -33,7 +33,10 @@ struct krig_plan_s {
   size_t tsz = 4;  // bytes of one real dt value
   GridDev g{};
   MaternDev mt{};
-  int n = 0, M = 0, P1 = 0, P2 = 0, F1 = 0, F2 = 0, H2 = 0, ldH = 0;
+  int n = 0, M = 0, P1 = 0, P2 = 0, F1 = 0, F2 = 0, H2 = 0;
+  int ldP = 0;  // pitch of frequency-major spectra with P1 rows
+  int ldM = 0;  // ... with m1 rows
+  int ldX = 0;  // ... with 2 (m1 + L) - 1 rows
   int n1l = 0, n2l = 0;
   const FftEntry* e1 = nullptr;  // columns (length F1)
   const FftEntry* e2 = nullptr;  // rows (length F2)
@@ -46,7 +49,7 @@ struct krig_plan_s {
   double* sites = nullptr;
   double* lag64 = nullptr;
   void* lagT = nullptr;
-  double* filt = nullptr;  // [F1][ldH] filter spectrum / (F1 F2), FP64
+  double* filt = nullptr;  // [H2][F1] filter spectrum / (F1 F2), FP64
   double* KN = nullptr;
   double* LinvN = nullptr;
   int* d_status = nullptr;   // [0] K_N status, [1] M pivot
@@ -65,23 +68,22 @@ struct krig_plan_s {
   int kn_status = 0, pivot = 0;
   // per-call workspaces
   int wsB = 0;
-  void* S1 = nullptr;     // cx FP64 [B][P1][ldH]   row spectra of c*
-  void* S2 = nullptr;     // cx dt   [B][m1][ldH]   prediction column-pass output
-  void* SG = nullptr;     // cx FP64 [B][m1][ldH]   row spectra of the upstream gradient
-  void* SA = nullptr;     // cx FP64 [B][P1][ldH]   adjoint column-pass output
+  void* S1 = nullptr;     // cx FP64 [B][H2][ldP]   row spectra of c*
+  void* S2 = nullptr;     // cx dt   [B][H2][ldM]   prediction column-pass output
+  void* SG = nullptr;     // cx FP64 [B][H2][ldM]   row spectra of the upstream gradient
+  void* SA = nullptr;     // cx FP64 [B][H2][ldP]   adjoint column-pass output
   void* img = nullptr;    // FP64 [B][P1][P2]       correlation image
   double* alpha = nullptr;  // [B][n]
   double* tmpv = nullptr;   // [B][n]
   double* tripart = nullptr;  // [tri_chunks(n)][B][n] split-K partial sums of the solve
-  void* part = nullptr;   // cx FP64 [ngroups][F1][ldH]
+  void* part = nullptr;   // cx FP64 [ngroups][H2][F1]
   int part_groups = 0;
-  void* XC = nullptr;     // cx FP64 [2 n1l - 1][ldH]
+  void* XC = nullptr;     // cx FP64 [H2][ldX]
   void* XR = nullptr;     // FP64 [2 n1l - 1][2 n2l - 1]
   // custom-lag filter
   double* filtC = nullptr;
   double* lagC64 = nullptr;
-  double* phiS64 = nullptr;  // cx double [F1][ldH]
-  double* phiR64 = nullptr;  // double [F1][ldH]
+  double* phiS64 = nullptr;  // cx double [H2][F1]
   // launch shapes
   int nl_rows64 = 4;   // lines per block, FP64 row kernels
   int nl_rows32 = 8;   // FP32 row kernels
@@ -180,15 +182,20 @@ int pick_fft(int need) {
 }
 
 int nt_of(const FftEntry* e) { return std::max(e->N1, e->N2); }
-int on1_of(const FftEntry* e) { return e->N1 | 1; }
 
-// largest lines-per-block with threads <= 256 and LDS <= budget
-int lines_for(const FftEntry* e, size_t csz, size_t extra_per_line, size_t budget = 64 * 1024) {
-  const int nt = nt_of(e);
-  int nl = std::max(1, 256 / nt);
-  while (nl > 1 && (size_t)nl * ((size_t)e->N2 * on1_of(e) * csz + extra_per_line) > budget) --nl;
+// largest lines (row kernels) / columns (column kernels) per block with at most 256
+// threads and 64 KB of LDS
+int nl_rows_for(const FftEntry* e, size_t csz) {
+  int nl = std::max(1, 256 / nt_of(e));
+  while (nl > 1 && rows_lds(e->N1, e->N2, nl, csz) > 64 * 1024) --nl;
   return nl;
 }
+int nl_cols_for(const FftEntry* e, size_t csz, bool stash) {
+  int nl = std::max(1, 256 / nt_of(e));
+  while (nl > 1 && cols_lds(e->N1, e->N2, nl, csz, stash) > 64 * 1024) --nl;
+  return nl;
+}
+int pitch16(int rows) { return (rows + 15) / 16 * 16; }
 
 int make_twiddles(krig_plan p, int F, double** d64, float** d32) {
   std::vector<double> h64(2 * (size_t)F);
@@ -219,29 +226,30 @@ int make_filter(krig_plan p, const double* lag64, double* filt_out) {
   RowsR2CArgs r{};
   r.nrows = p->F1;
   r.H2 = p->H2;
-  r.ldH = p->ldH;
   r.out = p->phiS64;
   r.out_fs = 0;
+  r.out_ld = p->F1;
   r.twF = p->tw2_64;
   r.lag = lag64;
   r.n1l = p->n1l;
   r.n2l = p->n2l;
   r.F1 = p->F1;
-  r.NL = lines_for(p->e2, 16, 0);
+  r.NL = nl_rows_for(p->e2, 16);
   KRIG_TRY(p->e2->k.r2c_lag(r, 1, p->st));
   ColsArgs c{};
   c.H2 = p->H2;
-  c.ldH = p->ldH;
   c.in = p->phiS64;
   c.in_fs = 0;
+  c.in_ld = p->F1;
   c.in_off = 0;
   c.in_cnt = p->F1;
   c.out = filt_out;
   c.out_fs = 0;
+  c.out_ld = p->F1;
   c.twF = p->tw1_64;
   c.twI = p->tw1_64;
   c.scale = 1.0 / ((double)p->F1 * (double)p->F2);
-  c.NL = lines_for(p->e1, 16, 0);
+  c.NL = nl_cols_for(p->e1, 16, false);
   KRIG_TRY(p->e1->k.fwd_real64(c, 1, p->st));
   return KRIG_OK;
 }
@@ -252,17 +260,18 @@ int ensure_ws(krig_plan p, int B) {
   KRIG_TRY(hipStreamSynchronize(p->st));
   for (void* q : olds) dfree(p, q);
   const size_t c = csz(p);
+  const size_t H2 = p->H2;
   int r;
-  if ((r = dalloc_bytes(p, &p->S1, 16 * (size_t)B * p->P1 * p->ldH)) != KRIG_OK) return r;
-  if ((r = dalloc_bytes(p, &p->S2, c * (size_t)B * p->g.m1 * p->ldH)) != KRIG_OK) return r;
-  if ((r = dalloc_bytes(p, &p->SG, 16 * (size_t)B * p->g.m1 * p->ldH)) != KRIG_OK) return r;
-  if ((r = dalloc_bytes(p, &p->SA, 16 * (size_t)B * p->P1 * p->ldH)) != KRIG_OK) return r;
+  if ((r = dalloc_bytes(p, &p->S1, 16 * (size_t)B * H2 * p->ldP)) != KRIG_OK) return r;
+  if ((r = dalloc_bytes(p, &p->S2, c * (size_t)B * H2 * p->ldM)) != KRIG_OK) return r;
+  if ((r = dalloc_bytes(p, &p->SG, 16 * (size_t)B * H2 * p->ldM)) != KRIG_OK) return r;
+  if ((r = dalloc_bytes(p, &p->SA, 16 * (size_t)B * H2 * p->ldP)) != KRIG_OK) return r;
   if ((r = dalloc_bytes(p, &p->img, 8 * (size_t)B * p->P1 * p->P2)) != KRIG_OK) return r;
   if ((r = dalloc(p, &p->alpha, (size_t)B * p->n)) != KRIG_OK) return r;
   if ((r = dalloc(p, &p->tmpv, (size_t)B * p->n)) != KRIG_OK) return r;
   if ((r = dalloc(p, &p->tripart, (size_t)tri_chunks(p->n) * B * p->n)) != KRIG_OK) return r;
   p->part_groups = B;  // worst case G = 1
-  if ((r = dalloc_bytes(p, &p->part, 16 * (size_t)p->part_groups * p->F1 * p->ldH)) != KRIG_OK) return r;
+  if ((r = dalloc_bytes(p, &p->part, 16 * (size_t)p->part_groups * H2 * p->F1)) != KRIG_OK) return r;
   p->wsB = B;
   return KRIG_OK;
 }
@@ -292,9 +301,9 @@ int do_convolve(krig_plan p, int B, const double* alpha, const double* filt, voi
   RowsR2CArgs r{};
   r.nrows = p->P1;
   r.H2 = p->H2;
-  r.ldH = p->ldH;
   r.out = spec1;
-  r.out_fs = (int64_t)p->P1 * p->ldH;
+  r.out_fs = (int64_t)p->H2 * p->ldP;
+  r.out_ld = p->ldP;
   r.twF = p->tw2_64;  // scatter + forward rows in FP64
   r.row_ptr = p->node_ptr;
   r.ent_site = p->ent_site;
@@ -310,14 +319,16 @@ int do_convolve(krig_plan p, int B, const double* alpha, const double* filt, voi
 
   ColsArgs c{};
   c.H2 = p->H2;
-  c.ldH = p->ldH;
   c.in = spec1;
-  c.in_fs = (int64_t)p->P1 * p->ldH;
+  c.in_fs = (int64_t)p->H2 * p->ldP;
+  c.in_ld = p->ldP;
   c.in_off = 0;
   c.in_cnt = p->P1;
   c.filt = filt;
+  c.filt_ld = p->F1;
   c.out = p->S2;
-  c.out_fs = (int64_t)p->g.m1 * p->ldH;
+  c.out_fs = (int64_t)p->H2 * p->ldM;
+  c.out_ld = p->ldM;
   c.rows = Window{p->g.L, p->g.m1, 0, 0};
   c.twF = p->tw1_64;  // forward column transform in FP64
   c.twI = is32(p) ? (const void*)p->tw1_32 : (const void*)p->tw1_64;
@@ -331,9 +342,9 @@ int do_convolve(krig_plan p, int B, const double* alpha, const double* filt, voi
   RowsC2RArgs o{};
   o.nrows = p->g.m1;
   o.H2 = p->H2;
-  o.ldH = p->ldH;
   o.in = p->S2;
-  o.in_fs = (int64_t)p->g.m1 * p->ldH;
+  o.in_fs = (int64_t)p->H2 * p->ldM;
+  o.in_ld = p->ldM;
   o.out = yhat;
   o.out_fs = (int64_t)p->g.m1 * p->g.m2;
   o.ldo = p->g.m2;
@@ -450,15 +461,17 @@ int krig_plan_create(krig_plan* out, const krig_grid* g, const krig_matern* k, i
   p->e1 = find_fft(p->F1);
   p->e2 = find_fft(p->F2);
   p->H2 = p->F2 / 2 + 1;
-  p->ldH = (p->H2 + 15) / 16 * 16;
+  p->ldP = pitch16(p->P1);
+  p->ldM = pitch16(g->m1);
+  p->ldX = pitch16(2 * (g->m1 + g->L) - 1);
   const bool f32 = dtype == KRIG_F32;
   // launch shapes (lines per block) within 256 threads and 64 KB of LDS
-  p->nl_rows64 = lines_for(p->e2, 16, 0);
-  p->nl_rows32 = lines_for(p->e2, 8, 0);
-  p->nl_cols64 = lines_for(p->e1, 16, 0);
-  p->nl_cols_dlag = lines_for(p->e1, 16, (size_t)p->F1 * 16);
-  if (lines_for(p->e1, 16, 0) * (size_t)p->e1->N2 * on1_of(p->e1) * 16 > 64 * 1024 ||
-      lines_for(p->e2, 16, 0) * (size_t)p->e2->N2 * on1_of(p->e2) * 16 > 64 * 1024) {
+  p->nl_rows64 = nl_rows_for(p->e2, 16);
+  p->nl_rows32 = nl_rows_for(p->e2, 8);
+  p->nl_cols64 = nl_cols_for(p->e1, 16, false);
+  p->nl_cols_dlag = nl_cols_for(p->e1, 16, true);
+  if (rows_lds(p->e2->N1, p->e2->N2, p->nl_rows64, 16) > 64 * 1024 ||
+      cols_lds(p->e1->N1, p->e1->N2, p->nl_cols_dlag, 16, true) > 64 * 1024) {
     delete p;
     return KRIG_EUNSUPPORTED;
   }
@@ -484,10 +497,9 @@ int krig_plan_create(krig_plan* out, const krig_grid* g, const krig_matern* k, i
   CK(dalloc(p, &p->lag64, (size_t)n1l * n2l));
   CK(dalloc_bytes(p, &p->lagT, p->tsz * (size_t)n1l * n2l));
   CK(dalloc(p, &p->lagC64, (size_t)n1l * n2l));
-  CK(dalloc(p, &p->phiS64, 2 * (size_t)p->F1 * p->ldH));
-  CK(dalloc(p, &p->phiR64, (size_t)p->F1 * p->ldH));
-  CK(dalloc(p, &p->filt, (size_t)p->F1 * p->ldH));
-  CK(dalloc(p, &p->filtC, (size_t)p->F1 * p->ldH));
+  CK(dalloc(p, &p->phiS64, 2 * (size_t)p->H2 * p->F1));
+  CK(dalloc(p, &p->filt, (size_t)p->H2 * p->F1));
+  CK(dalloc(p, &p->filtC, (size_t)p->H2 * p->F1));
   CKH(lag_image(p->g, p->mt, p->lag64, p->st));
   CKH(convert_f64(p->lag64, p->lagT, (int64_t)n1l * n2l, f32, p->st));
   CK(make_filter(p, p->lag64, p->filt));
@@ -537,7 +549,7 @@ int krig_plan_create(krig_plan* out, const krig_grid* g, const krig_matern* k, i
   CKH(cholesky_and_inverse(p->Lfac, n, n, p->Linv, p->Dinv, p->work, p->d_status + 1, p->st));
 
   // dlag buffers
-  CK(dalloc_bytes(p, &p->XC, 16 * (size_t)(2 * n1l - 1) * p->ldH));
+  CK(dalloc_bytes(p, &p->XC, 16 * (size_t)p->H2 * p->ldX));
   CK(dalloc_bytes(p, &p->XR, 8 * (size_t)(2 * n1l - 1) * (2 * n2l - 1)));
 
   int hst[4] = {0, 0, 0, 0};
@@ -573,12 +585,13 @@ int krig_plan_info(krig_plan p, int32_t what, int64_t* v) {
     case KRIG_INFO_F1: *v = p->F1; break;
     case KRIG_INFO_F2: *v = p->F2; break;
     case KRIG_INFO_H2: *v = p->H2; break;
-    case KRIG_INFO_LDH: *v = p->ldH; break;
-    case KRIG_INFO_SAVED_PER_FIELD: *v = (int64_t)p->P1 * p->ldH; break;  // complex FP64
+    case KRIG_INFO_LDH: *v = p->ldP; break;
+    case KRIG_INFO_SAVED_PER_FIELD: *v = (int64_t)p->H2 * p->ldP; break;  // complex FP64
     case KRIG_INFO_KN_STATUS: *v = p->kn_status; break;
     case KRIG_INFO_PIVOT: *v = p->pivot; break;
     case KRIG_INFO_DTYPE: *v = p->dtype; break;
     case KRIG_INFO_CE_CLAMPED: *v = p->ce_clamped; break;
+    case KRIG_INFO_DLAG_GROUP: *v = p->dlag_G; break;
     default: return KRIG_EINVAL;
   }
   return KRIG_OK;
@@ -671,9 +684,9 @@ int krig_predict_adjoint(krig_plan p, int32_t B, const void* d_g, const double* 
     RowsR2CArgs rr{};
     rr.nrows = p->P1;
     rr.H2 = p->H2;
-    rr.ldH = p->ldH;
     rr.out = p->S1;
-    rr.out_fs = (int64_t)p->P1 * p->ldH;
+    rr.out_fs = (int64_t)p->H2 * p->ldP;
+    rr.out_ld = p->ldP;
     rr.twF = p->tw2_64;
     rr.row_ptr = p->node_ptr;
     rr.ent_site = p->ent_site;
@@ -690,9 +703,9 @@ int krig_predict_adjoint(krig_plan p, int32_t B, const void* d_g, const double* 
   RowsR2CArgs rg{};
   rg.nrows = p->g.m1;
   rg.H2 = p->H2;
-  rg.ldH = p->ldH;
   rg.out = p->SG;
-  rg.out_fs = (int64_t)p->g.m1 * p->ldH;
+  rg.out_fs = (int64_t)p->H2 * p->ldM;
+  rg.out_ld = p->ldM;
   rg.twF = p->tw2_64;
   rg.dense = d_g;
   rg.dense_fs = (int64_t)p->g.m1 * p->g.m2;
@@ -707,14 +720,16 @@ int krig_predict_adjoint(krig_plan p, int32_t B, const void* d_g, const double* 
   // columns: correlation with the (even) filter, keep the P1 padded rows
   ColsArgs c{};
   c.H2 = p->H2;
-  c.ldH = p->ldH;
   c.in = p->SG;
-  c.in_fs = (int64_t)p->g.m1 * p->ldH;
+  c.in_fs = (int64_t)p->H2 * p->ldM;
+  c.in_ld = p->ldM;
   c.in_off = p->g.L;
   c.in_cnt = p->g.m1;
   c.filt = filt;
+  c.filt_ld = p->F1;
   c.out = p->SA;
-  c.out_fs = (int64_t)p->P1 * p->ldH;
+  c.out_fs = (int64_t)p->H2 * p->ldP;
+  c.out_ld = p->ldP;
   c.rows = Window{0, p->P1, 0, 0};
   c.twF = p->tw1_64;
   c.twI = p->tw1_64;
@@ -722,10 +737,13 @@ int krig_predict_adjoint(krig_plan p, int32_t B, const void* d_g, const double* 
   int ngroups = 0;
   if (d_dlag) {
     c.in2 = spec1;
-    c.in2_fs = (int64_t)p->P1 * p->ldH;
+    c.in2_fs = (int64_t)p->H2 * p->ldP;
+    c.in2_ld = p->ldP;
     c.in2_off = 0;
     c.in2_cnt = p->P1;
     c.part = p->part;
+    c.part_fs = (int64_t)p->H2 * p->F1;
+    c.part_ld = p->F1;
     c.G = std::max(1, std::min(p->dlag_G, (int)B));
     c.NL = p->nl_cols_dlag;
     ngroups = (B + c.G - 1) / c.G;
@@ -740,9 +758,9 @@ int krig_predict_adjoint(krig_plan p, int32_t B, const void* d_g, const double* 
   RowsC2RArgs o{};
   o.nrows = p->P1;
   o.H2 = p->H2;
-  o.ldH = p->ldH;
   o.in = p->SA;
-  o.in_fs = (int64_t)p->P1 * p->ldH;
+  o.in_fs = (int64_t)p->H2 * p->ldP;
+  o.in_ld = p->ldP;
   o.out = p->img;
   o.out_fs = (int64_t)p->P1 * p->P2;
   o.ldo = p->P2;
@@ -767,11 +785,12 @@ int krig_predict_adjoint(krig_plan p, int32_t B, const void* d_g, const double* 
     // inverse transform of sum_b G_b conj(C_b), keeping lags -(n-1)..(n-1)
     ColsArgs ci{};
     ci.H2 = p->H2;
-    ci.ldH = p->ldH;
     ci.in = p->part;
-    ci.in_fs = (int64_t)p->F1 * p->ldH;
+    ci.in_fs = (int64_t)p->H2 * p->F1;
+    ci.in_ld = p->F1;
     ci.G = ngroups;
     ci.out = p->XC;
+    ci.out_ld = p->ldX;
     ci.rows = Window{0, p->n1l, p->F1 - p->n1l + 1, p->n1l - 1};
     ci.twF = p->tw1_64;
     ci.twI = p->tw1_64;
@@ -780,9 +799,9 @@ int krig_predict_adjoint(krig_plan p, int32_t B, const void* d_g, const double* 
     RowsC2RArgs oc{};
     oc.nrows = 2 * p->n1l - 1;
     oc.H2 = p->H2;
-    oc.ldH = p->ldH;
     oc.in = p->XC;
     oc.in_fs = 0;
+    oc.in_ld = p->ldX;
     oc.out = p->XR;
     oc.out_fs = 0;
     oc.ldo = 2 * p->n2l - 1;
