@@ -79,7 +79,9 @@ enum {
   KRIG_INFO_PIVOT,      /* first failing pivot (1-based) of K + tau^2 I, 0 if none */
   KRIG_INFO_DTYPE,
   KRIG_INFO_CE_CLAMPED, /* number of clamped circulant-embedding eigenvalues (after krig_csim) */
-  KRIG_INFO_DLAG_GROUP  /* fields per block in the lag-gradient column pass */
+  KRIG_INFO_DLAG_GROUP, /* fields per block in the lag-gradient column pass */
+  KRIG_INFO_CE_F1,      /* circulant-embedding torus size (0 before the first krig_csim) */
+  KRIG_INFO_CE_F2
 };
 
 /*
@@ -202,6 +204,7 @@ enum {
   KRIG_STAGE_GATHER,         /* adjoint: gather at the neighbours (d alpha) */
   KRIG_STAGE_SOLVE,          /* FP64 applications of the inverse Cholesky factor */
   KRIG_STAGE_DLAG_TAIL,      /* lag gradient: inverse transforms of the summed spectra + fold */
+  KRIG_STAGE_CSIM_CE,        /* conditional simulation: circulant-embedding sampler (2 passes) */
   KRIG_STAGE_COUNT
 };
 

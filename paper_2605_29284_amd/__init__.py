@@ -20,7 +20,7 @@ KRIG_F32 = 1
 KRIG_F64 = 2
 
 INFO = dict(N=1, M=2, P1=3, P2=4, F1=5, F2=6, H2=7, LDH=8, SAVED_PER_FIELD=9, KN_STATUS=10,
-            PIVOT=11, DTYPE=12, CE_CLAMPED=13, DLAG_GROUP=14)
+            PIVOT=11, DTYPE=12, CE_CLAMPED=13, DLAG_GROUP=14, CE_F1=15, CE_F2=16)
 
 STATUS = {0: "KRIG_OK", -1: "KRIG_EINVAL", -2: "KRIG_EDOMAIN", -3: "KRIG_ENOTSPD", -4: "KRIG_ECE",
           -5: "KRIG_ENOMEM", -6: "KRIG_EHIP", -7: "KRIG_EUNSUPPORTED"}
@@ -30,7 +30,7 @@ EXPORTS = ["krig_plan_create", "krig_plan_destroy", "krig_plan_info", "krig_set_
            "krig_predict_adjoint", "krig_csim", "krig_timing_enable", "krig_timing_read", "krig_strerror"]
 
 STAGES = ["ROWS_FWD", "COLS_CONV", "ROWS_INV", "ADJ_ROWS_FWD", "ADJ_COLS", "ADJ_ROWS_INV", "GATHER", "SOLVE",
-          "DLAG_TAIL"]
+          "DLAG_TAIL", "CSIM_CE"]
 
 
 class KrigError(RuntimeError):

@@ -45,6 +45,9 @@ struct RowsR2CArgs {
   // even-reflected lag source: row r of the F1 x F2 embedding of lag[n1l][n2l]
   const double* lag;
   int n1l, n2l, F1;
+  // covariance on the F1 x F2 torus (minimal-image lags) for circulant embedding
+  double cov_sigma2, cov_rho, cov_dx, cov_dy;
+  int cov_kind;
   int NL;                   // lines (row pairs) per block
 };
 
@@ -70,7 +73,26 @@ struct ColsArgs {
   const void* twF;        // cx<TF> [F] twiddles of the forward transform's precision
   const void* twI;        // cx<TI> [F] twiddles of the inverse transform's precision
   double scale;           // store scale (set-up transforms)
+  // circulant-embedding sampler: complex Philox noise x sqrt(Lambda / N) on the torus
+  uint32_t key0, key1;    // Philox key (seed)
+  int pair0;              // first realisation pair of this launch
+  int ncol_full;          // torus length along the columns' index (all frequencies)
   int NL;                 // columns per block
+};
+
+// Circulant-embedding sampler, second pass: complex transforms of torus rows
+// (frequency-major input) -> realisations 2p (real part) and 2p+1 (imaginary part).
+struct RowsCEArgs {
+  int nrows;              // rows kept (P1)
+  int ncols;              // torus row length (all frequencies)
+  const void* in;         // cx<TS>: in[pair*in_fs + k*in_ld + r]
+  int64_t in_fs, in_ld;
+  void* out;              // TO [R][nrows][ldo]
+  int64_t out_fs, ldo;
+  int keep;               // columns kept (P2)
+  int R, pair0;
+  const void* twF;
+  int NL;
 };
 
 // Inverse real-row transform (two rows per complex line) from frequency-major half
@@ -93,6 +115,7 @@ struct RowsC2RArgs {
 typedef hipError_t (*launch_rows_r2c_t)(const RowsR2CArgs&, int B, hipStream_t);
 typedef hipError_t (*launch_cols_t)(const ColsArgs&, int nblk_y, hipStream_t);
 typedef hipError_t (*launch_rows_c2r_t)(const RowsC2RArgs&, int B, hipStream_t);
+typedef hipError_t (*launch_rows_ce_t)(const RowsCEArgs&, int npairs, hipStream_t);
 
 // Kernels for one transform length.  Arithmetic and storage precisions are fixed
 // per role: everything is FP64 except the inverse half of the prediction's column
@@ -109,6 +132,9 @@ struct FftSet {
   launch_cols_t inv_sum64;          // inverse columns of a sum of partial spectra (FP64)
   launch_rows_c2r_t c2r32;          // inverse rows, FP32
   launch_rows_c2r_t c2r64;          // inverse rows, FP64
+  launch_rows_r2c_t r2c_cov;        // covariance on the embedding torus, FP64
+  launch_cols_t ce_cols32, ce_cols64;    // sampler pass 1 (noise x sqrt(Lambda), column transforms)
+  launch_rows_ce_t ce_rows32, ce_rows64; // sampler pass 2 (row transforms -> two realisations)
 };
 
 struct FftEntry {
@@ -125,5 +151,6 @@ void register_all_fft();
 // LDS bytes of one block (lines or columns NL) for each kernel family
 size_t rows_lds(int N1, int N2, int NL, size_t csz);
 size_t cols_lds(int N1, int N2, int NL, size_t csz, bool stash);
+size_t ce_rows_lds(int N1, int N2, int NL, size_t csz);
 
 }  // namespace krig

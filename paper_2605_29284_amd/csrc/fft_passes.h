@@ -22,6 +22,8 @@
 #pragma once
 #include "fft_args.h"
 #include "fft_reg.h"
+#include "matern_dev.h"
+#include "philox_dev.h"
 
 namespace krig {
 
@@ -106,7 +108,7 @@ __device__ __forceinline__ void inv_from_t(cx<TC> (&w)[N2], int s, cx<TC>* L, co
 // ----------------------------------------------------------------------------------------
 // row kernels: forward (real rows -> frequency-major half spectra)
 // ----------------------------------------------------------------------------------------
-enum { SRC_CSR = 0, SRC_DENSE = 1, SRC_LAG = 2 };
+enum { SRC_CSR = 0, SRC_DENSE = 1, SRC_LAG = 2, SRC_COV = 3 };
 
 template <typename TC, typename TIN, typename TS, int N1, int N2, int SRC>
 __global__ void __launch_bounds__(256) k_rows_r2c(RowsR2CArgs a) {
@@ -151,6 +153,22 @@ __global__ void __launch_bounds__(256) k_rows_r2c(RowsR2CArgs a) {
           const TIN* d = reinterpret_cast<const TIN*>(a.dense) + (int64_t)b * a.dense_fs;
           if (oka) xa = (TC)d[(int64_t)ra * a.dense_ld + cc];
           if (okb) xb = (TC)d[(int64_t)rb * a.dense_ld + cc];
+        }
+      } else if constexpr (SRC == SRC_COV) {  // torus covariance with minimal-image lags
+        const int F2 = G::F;
+        MaternDev mt;
+        mt.sigma2 = a.cov_sigma2;
+        mt.rho = a.cov_rho;
+        mt.tau2 = 0.0;
+        mt.kind = a.cov_kind;
+        const double hw = (double)(c < F2 - c ? c : F2 - c) * a.cov_dy;
+        if (oka) {
+          const double hu = (double)(ra < a.F1 - ra ? ra : a.F1 - ra) * a.cov_dx;
+          xa = (TC)matern_cov(sqrt(hu * hu + hw * hw), mt);
+        }
+        if (okb) {
+          const double hu = (double)(rb < a.F1 - rb ? rb : a.F1 - rb) * a.cov_dx;
+          xb = (TC)matern_cov(sqrt(hu * hu + hw * hw), mt);
         }
       } else {  // SRC_LAG: embedding row r holds lag[min(r, F1-r)][min(c, F2-c)]
         const int F2 = G::F;
@@ -231,7 +249,7 @@ __device__ __forceinline__ void col_fwd(const cx<TS>* src, int in_off, int in_cn
   two_stage<TC, N1, N2, -1>(v, w, s, L, twF);
 }
 
-enum { COL_CONV = 0, COL_CONV_DLAG = 1, COL_FWD_REAL = 2, COL_INV_SUM = 3 };
+enum { COL_CONV = 0, COL_CONV_DLAG = 1, COL_FWD_REAL = 2, COL_INV_SUM = 3, COL_CE = 4 };
 
 template <typename TF, typename TI, typename TSI, typename TSO, int N1, int N2, int MODE>
 __global__ void __launch_bounds__(256) k_cols(ColsArgs a) {
@@ -339,6 +357,44 @@ __global__ void __launch_bounds__(256) k_cols(ColsArgs a) {
 #pragma unroll
       for (int k2 = 0; k2 < N2; ++k2) dst[s + N1 * k2] = (TSO)(w[k2].x * (TC)a.scale);
     }
+  } else if constexpr (MODE == COL_CE) {
+    // sampler pass 1: column k2 (all ncol_full frequencies) of sqrt(Lambda/N) (xi1 + i xi2),
+    // xi from Philox counter (k1 * ncol_full + k2, pair, STREAM_CE, 0); forward transform
+    // over k1; keep rows [0, rows.na) -> out[pair][k2][r]
+    const int pair = a.pair0 + blockIdx.y;
+    const int kk2 = col < a.ncol_full - col ? col : a.ncol_full - col;  // Lambda is even
+    const double* lam = reinterpret_cast<const double*>(a.filt) + (int64_t)kk2 * a.filt_ld;
+    cx<TC> v[N1];
+    if (s < N2) {
+#pragma unroll
+      for (int n1 = 0; n1 < N1; ++n1) {
+        const int k1 = N2 * n1 + s;
+        cx<TC> z = mk<TC>(0, 0);
+        if (colok) {
+          u32x4 cn;
+          cn.v[0] = (uint32_t)(k1 * a.ncol_full + col);
+          cn.v[1] = (uint32_t)pair;
+          cn.v[2] = STREAM_CE;
+          cn.v[3] = 0;
+          const u32x4 r = philox4x32_10(cn, a.key0, a.key1);
+          double x0, x1;
+          box_muller_f64(r.v[0], r.v[1], x0, x1);
+          const double sl = lam[k1];
+          z = mk<TC>((TC)(sl * x0), (TC)(sl * x1));
+        }
+        v[n1] = z;
+      }
+    }
+    cx<TC> w[N2];
+    two_stage<TC, N1, N2, -1>(v, w, s, L, twF);
+    if (s < N1 && colok) {
+      cx<TSO>* dst = reinterpret_cast<cx<TSO>*>(a.out) + (int64_t)blockIdx.y * a.out_fs + (int64_t)col * a.out_ld;
+#pragma unroll
+      for (int k2 = 0; k2 < N2; ++k2) {
+        const int d = window_dst(a.rows, s + N1 * k2);
+        if (d >= 0) dst[d] = ccast<TSO>(w[k2]);
+      }
+    }
   } else {  // COL_INV_SUM: inverse transform of sum_g part[g] (natural order), keep rows
     const cx<TSI>* p = reinterpret_cast<const cx<TSI>*>(a.in) + (int64_t)col * a.in_ld;
     cx<TC> v[N1];
@@ -430,6 +486,54 @@ __global__ void __launch_bounds__(256) k_rows_c2r(RowsC2RArgs a) {
 }
 
 // ----------------------------------------------------------------------------------------
+// sampler pass 2: complex forward transform of torus rows r < nrows (frequency-major
+// input), keep columns < keep; real part -> realisation 2 pair, imaginary -> 2 pair + 1
+// ----------------------------------------------------------------------------------------
+template <typename TC, typename TS, typename TO, int N1, int N2>
+__global__ void __launch_bounds__(256) k_rows_ce(RowsCEArgs a) {
+  using G = Geo<N1, N2>;
+  extern __shared__ unsigned char smem_raw[];
+  cx<TC>* lds = reinterpret_cast<cx<TC>*>(smem_raw);
+  const int s = threadIdx.x % G::NT;
+  const int l = threadIdx.x / G::NT;
+  const int NL = a.NL;
+  const int pair = a.pair0 + blockIdx.y;
+  const int row0 = blockIdx.x * NL;
+  const int row = row0 + l;
+  const cx<TC>* twF = reinterpret_cast<const cx<TC>*>(a.twF);
+  const cx<TS>* in = reinterpret_cast<const cx<TS>*>(a.in) + (int64_t)blockIdx.y * a.in_fs;
+  cx<TC>* T = lds;  // [k][l]
+  for (int idx = threadIdx.x; idx < G::F * NL; idx += blockDim.x) {
+    const int rl = idx % NL, k = idx / NL;
+    const int r = row0 + rl;
+    T[idx] = r < a.nrows ? ccast<TC>(in[(int64_t)k * a.in_ld + r]) : mk<TC>(0, 0);
+  }
+  __syncthreads();
+  cx<TC> v[N1];
+  if (s < N2) {
+#pragma unroll
+    for (int n1 = 0; n1 < N1; ++n1) v[n1] = T[(N2 * n1 + s) * NL + l];
+  }
+  __syncthreads();
+  cx<TC>* L = lds + (size_t)l * G::EX;
+  cx<TC> w[N2];
+  two_stage<TC, N1, N2, -1>(v, w, s, L, twF);
+  if (s < N1 && row < a.nrows) {
+    const int re = 2 * pair, im = 2 * pair + 1;
+    TO* o1 = reinterpret_cast<TO*>(a.out) + (int64_t)re * a.out_fs + (int64_t)row * a.ldo;
+    TO* o2 = reinterpret_cast<TO*>(a.out) + (int64_t)im * a.out_fs + (int64_t)row * a.ldo;
+#pragma unroll
+    for (int k2 = 0; k2 < N2; ++k2) {
+      const int c = s + N1 * k2;
+      if (c < a.keep) {
+        if (re < a.R) o1[c] = (TO)w[k2].x;
+        if (im < a.R) o2[c] = (TO)w[k2].y;
+      }
+    }
+  }
+}
+
+// ----------------------------------------------------------------------------------------
 // launchers
 // ----------------------------------------------------------------------------------------
 template <typename TC, typename TIN, typename TS, int N1, int N2, int SRC>
@@ -461,6 +565,15 @@ hipError_t launch_rows_c2r(const RowsC2RArgs& a, int B, hipStream_t st) {
   return hipGetLastError();
 }
 
+template <typename TC, typename TS, typename TO, int N1, int N2>
+hipError_t launch_rows_ce(const RowsCEArgs& a, int npairs, hipStream_t st) {
+  dim3 grid((a.nrows + a.NL - 1) / a.NL, npairs);
+  dim3 block(Geo<N1, N2>::NT * a.NL);
+  const size_t sh = ce_rows_lds(N1, N2, a.NL, sizeof(cx<TC>));
+  k_rows_ce<TC, TS, TO, N1, N2><<<grid, block, sh, st>>>(a);
+  return hipGetLastError();
+}
+
 template <int N1, int N2>
 FftEntry make_fft_entry() {
   FftEntry e;
@@ -479,6 +592,11 @@ FftEntry make_fft_entry() {
   k.inv_sum64 = launch_cols<double, double, double, double, N1, N2, COL_INV_SUM>;
   k.c2r32 = launch_rows_c2r<float, float, float, N1, N2>;
   k.c2r64 = launch_rows_c2r<double, double, double, N1, N2>;
+  k.r2c_cov = launch_rows_r2c<double, double, double, N1, N2, SRC_COV>;
+  k.ce_cols32 = launch_cols<float, float, float, float, N1, N2, COL_CE>;
+  k.ce_cols64 = launch_cols<double, double, double, double, N1, N2, COL_CE>;
+  k.ce_rows32 = launch_rows_ce<float, float, float, N1, N2>;
+  k.ce_rows64 = launch_rows_ce<double, double, double, N1, N2>;
   return e;
 }
 

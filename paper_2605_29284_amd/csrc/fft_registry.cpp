@@ -48,6 +48,11 @@ size_t rows_lds(int N1, int N2, int NL, size_t csz) {
   return (size_t)NL * (ex > tr ? ex : tr) * csz;
 }
 
+size_t ce_rows_lds(int N1, int N2, int NL, size_t csz) {
+  const size_t ex = (size_t)N2 * (N1 | 1), tr = (size_t)N1 * N2;
+  return (size_t)NL * (ex > tr ? ex : tr) * csz;
+}
+
 size_t cols_lds(int N1, int N2, int NL, size_t csz, bool stash) {
   size_t e = (size_t)NL * N2 * (N1 | 1);
   if (stash) e += (size_t)NL * N1 * N2;

@@ -90,8 +90,20 @@ struct krig_plan_s {
   int nl_cols64 = 4;   // columns per block, FP64-forward column kernels
   int nl_cols_dlag = 2;
   int dlag_G = 2;
-  // conditional simulation
+  // conditional simulation (set up on the first krig_csim call)
   int ce_clamped = 0;
+  int Fs1 = 0, Fs2 = 0, Hs2 = 0;
+  const FftEntry* es1 = nullptr;  // torus columns (length Fs1)
+  const FftEntry* es2 = nullptr;  // torus rows (length Fs2)
+  double *tws1_64 = nullptr, *tws2_64 = nullptr;
+  float *tws1_32 = nullptr, *tws2_32 = nullptr;
+  double* lamS = nullptr;   // sqrt(Lambda / (Fs1 Fs2)), [Hs2][Fs1]
+  int csR = 0;
+  void* csT = nullptr;      // cx dt [pairs][Fs2][ldP]
+  void* csU = nullptr;      // dt [R][P1][P2] unconditional fields
+  double* csRes = nullptr;  // [R][n]
+  double* csAl = nullptr;   // [R][n]
+  int wsB_adj = 0;
   // stage timing
   bool timing = false;
   std::vector<hipEvent_t> ev_pool;
@@ -254,9 +266,10 @@ int make_filter(krig_plan p, const double* lag64, double* filt_out) {
   return KRIG_OK;
 }
 
+// forward workspaces (prediction and solves) for B fields
 int ensure_ws(krig_plan p, int B) {
   if (B <= p->wsB) return KRIG_OK;
-  void* olds[] = {p->S1, p->S2, p->SG, p->SA, p->img, p->alpha, p->tmpv, p->part, p->tripart};
+  void* olds[] = {p->S1, p->S2, p->alpha, p->tmpv, p->tripart};
   KRIG_TRY(hipStreamSynchronize(p->st));
   for (void* q : olds) dfree(p, q);
   const size_t c = csz(p);
@@ -264,15 +277,27 @@ int ensure_ws(krig_plan p, int B) {
   int r;
   if ((r = dalloc_bytes(p, &p->S1, 16 * (size_t)B * H2 * p->ldP)) != KRIG_OK) return r;
   if ((r = dalloc_bytes(p, &p->S2, c * (size_t)B * H2 * p->ldM)) != KRIG_OK) return r;
-  if ((r = dalloc_bytes(p, &p->SG, 16 * (size_t)B * H2 * p->ldM)) != KRIG_OK) return r;
-  if ((r = dalloc_bytes(p, &p->SA, 16 * (size_t)B * H2 * p->ldP)) != KRIG_OK) return r;
-  if ((r = dalloc_bytes(p, &p->img, 8 * (size_t)B * p->P1 * p->P2)) != KRIG_OK) return r;
   if ((r = dalloc(p, &p->alpha, (size_t)B * p->n)) != KRIG_OK) return r;
   if ((r = dalloc(p, &p->tmpv, (size_t)B * p->n)) != KRIG_OK) return r;
   if ((r = dalloc(p, &p->tripart, (size_t)tri_chunks(p->n) * B * p->n)) != KRIG_OK) return r;
+  p->wsB = B;
+  return KRIG_OK;
+}
+
+// adjoint workspaces for B fields
+int ensure_ws_adj(krig_plan p, int B) {
+  if (B <= p->wsB_adj) return KRIG_OK;
+  void* olds[] = {p->SG, p->SA, p->img, p->part};
+  KRIG_TRY(hipStreamSynchronize(p->st));
+  for (void* q : olds) dfree(p, q);
+  const size_t H2 = p->H2;
+  int r;
+  if ((r = dalloc_bytes(p, &p->SG, 16 * (size_t)B * H2 * p->ldM)) != KRIG_OK) return r;
+  if ((r = dalloc_bytes(p, &p->SA, 16 * (size_t)B * H2 * p->ldP)) != KRIG_OK) return r;
+  if ((r = dalloc_bytes(p, &p->img, 8 * (size_t)B * p->P1 * p->P2)) != KRIG_OK) return r;
   p->part_groups = B;  // worst case G = 1
   if ((r = dalloc_bytes(p, &p->part, 16 * (size_t)p->part_groups * H2 * p->F1)) != KRIG_OK) return r;
-  p->wsB = B;
+  p->wsB_adj = B;
   return KRIG_OK;
 }
 
@@ -391,6 +416,104 @@ void destroy_all(krig_plan p) {
   for (void* q : p->allocs) (void)hipFree(q);
   p->allocs.clear();
   delete p;
+}
+
+int nl_ce_rows_for(const FftEntry* e, size_t csz) {
+  int nl = std::max(1, 256 / nt_of(e));
+  while (nl > 1 && ce_rows_lds(e->N1, e->N2, nl, csz) > 64 * 1024) --nl;
+  return nl;
+}
+
+// Circulant embedding of the padded-grid covariance (discussion section): torus
+// Fs >= 2 (P - 1) from the length ladder, eigenvalues Lambda = FFT2 of the
+// minimal-image covariance (FP64).  Negative eigenvalues down to -1e-6 max are
+// clamped; otherwise the torus grows (up to twice the first choice); else KRIG_ECE.
+int ce_setup(krig_plan p) {
+  int r;
+  const int f1_0 = pick_fft(2 * (p->P1 - 1)), f2_0 = pick_fft(2 * (p->P2 - 1));
+  if (f1_0 < 0 || f2_0 < 0) return KRIG_EUNSUPPORTED;
+  int f1 = f1_0, f2 = f2_0;
+  for (;;) {
+    const FftEntry* e1 = find_fft(f1);
+    const FftEntry* e2 = find_fft(f2);
+    if (rows_lds(e2->N1, e2->N2, nl_rows_for(e2, 16), 16) > 64 * 1024 ||
+        cols_lds(e1->N1, e1->N2, nl_cols_for(e1, 16, false), 16, false) > 64 * 1024)
+      return KRIG_EUNSUPPORTED;
+    const int h2 = f2 / 2 + 1;
+    double* lam = nullptr;
+    double* spec = nullptr;
+    double *t1_64 = nullptr, *t2_64 = nullptr;
+    float *t1_32 = nullptr, *t2_32 = nullptr;
+    if ((r = dalloc(p, &lam, (size_t)h2 * f1)) != KRIG_OK) return r;
+    if ((r = dalloc(p, &spec, 2 * (size_t)h2 * f1)) != KRIG_OK) return r;
+    if ((r = make_twiddles(p, f1, &t1_64, &t1_32)) != KRIG_OK) return r;
+    if ((r = make_twiddles(p, f2, &t2_64, &t2_32)) != KRIG_OK) return r;
+    RowsR2CArgs a{};
+    a.nrows = f1;
+    a.H2 = h2;
+    a.out = spec;
+    a.out_fs = 0;
+    a.out_ld = f1;
+    a.twF = t2_64;
+    a.F1 = f1;
+    a.cov_sigma2 = p->mt.sigma2;
+    a.cov_rho = p->mt.rho;
+    a.cov_dx = p->g.dx;
+    a.cov_dy = p->g.dy;
+    a.cov_kind = p->mt.kind;
+    a.NL = nl_rows_for(e2, 16);
+    KRIG_TRY(e2->k.r2c_cov(a, 1, p->st));
+    ColsArgs c{};
+    c.H2 = h2;
+    c.in = spec;
+    c.in_ld = f1;
+    c.in_off = 0;
+    c.in_cnt = f1;
+    c.out = lam;
+    c.out_ld = f1;
+    c.twF = t1_64;
+    c.twI = t1_64;
+    c.scale = 1.0;
+    c.NL = nl_cols_for(e1, 16, false);
+    KRIG_TRY(e1->k.fwd_real64(c, 1, p->st));
+    const int nb = 256;
+    double* bm = nullptr;
+    if ((r = dalloc(p, &bm, 3 * (size_t)nb)) != KRIG_OK) return r;
+    KRIG_TRY(minmax_blocks(lam, (int64_t)h2 * f1, bm, bm + nb, (int*)(bm + 2 * nb), nb, p->st));
+    std::vector<double> hb(3 * (size_t)nb);
+    KRIG_TRY(hipMemcpyAsync(hb.data(), bm, hb.size() * sizeof(double), hipMemcpyDeviceToHost, p->st));
+    KRIG_TRY(hipStreamSynchronize(p->st));
+    double lmin = 1e300, lmax = -1e300;
+    int64_t nneg = 0;
+    const int* hn = reinterpret_cast<const int*>(hb.data() + 2 * nb);
+    for (int i = 0; i < nb; ++i) {
+      lmin = std::min(lmin, hb[i]);
+      lmax = std::max(lmax, hb[nb + i]);
+      nneg += hn[i];
+    }
+    dfree(p, bm);
+    dfree(p, spec);
+    if (lmin >= -1e-6 * lmax) {
+      KRIG_TRY(sqrt_clamp(lam, (int64_t)h2 * f1, 1.0 / ((double)f1 * f2), p->st));
+      p->lamS = lam;
+      p->Fs1 = f1;
+      p->Fs2 = f2;
+      p->Hs2 = h2;
+      p->es1 = e1;
+      p->es2 = e2;
+      p->tws1_64 = t1_64;
+      p->tws1_32 = t1_32;
+      p->tws2_64 = t2_64;
+      p->tws2_32 = t2_32;
+      p->ce_clamped = (int)nneg;
+      return KRIG_OK;
+    }
+    dfree(p, lam);
+    const int n1 = pick_fft(f1 + 1), n2 = pick_fft(f2 + 1);
+    if (n1 < 0 || n2 < 0 || n1 > 2 * f1_0 || n2 > 2 * f2_0) return KRIG_ECE;
+    f1 = n1;
+    f2 = n2;
+  }
 }
 
 }  // namespace
@@ -592,6 +715,8 @@ int krig_plan_info(krig_plan p, int32_t what, int64_t* v) {
     case KRIG_INFO_DTYPE: *v = p->dtype; break;
     case KRIG_INFO_CE_CLAMPED: *v = p->ce_clamped; break;
     case KRIG_INFO_DLAG_GROUP: *v = p->dlag_G; break;
+    case KRIG_INFO_CE_F1: *v = p->Fs1; break;
+    case KRIG_INFO_CE_F2: *v = p->Fs2; break;
     default: return KRIG_EINVAL;
   }
   return KRIG_OK;
@@ -673,6 +798,7 @@ int krig_predict_adjoint(krig_plan p, int32_t B, const void* d_g, const double* 
   if (d_dlag && !d_saved && !d_alpha) return KRIG_EINVAL;
   int r = ensure_ws(p, B);
   if (r != KRIG_OK) return r;
+  if ((r = ensure_ws_adj(p, B)) != KRIG_OK) return r;
   const double* filt = nullptr;
   if ((r = filter_for(p, d_lag, &filt)) != KRIG_OK) return r;
   // The adjoint runs in FP64 whatever the plan's dtype: d alpha is multiplied by
@@ -842,7 +968,67 @@ int krig_timing_read(krig_plan p, int32_t stage, double* total_ms, int64_t* laun
 
 int krig_csim(krig_plan p, int32_t R, uint64_t seed, const double* d_y, void* d_fields) {
   if (!p || R < 1 || !d_y || !d_fields) return KRIG_EINVAL;
-  return KRIG_EUNSUPPORTED;
+  int r;
+  if (!p->lamS && (r = ce_setup(p)) != KRIG_OK) return r;
+  if ((r = ensure_ws(p, R)) != KRIG_OK) return r;
+  const bool f32 = is32(p);
+  const int npairs = (R + 1) / 2;
+  if (R > p->csR) {
+    KRIG_TRY(hipStreamSynchronize(p->st));
+    dfree(p, p->csT);
+    dfree(p, p->csU);
+    dfree(p, p->csRes);
+    dfree(p, p->csAl);
+    if ((r = dalloc_bytes(p, &p->csT, csz(p) * (size_t)npairs * p->Fs2 * p->ldP)) != KRIG_OK) return r;
+    if ((r = dalloc_bytes(p, &p->csU, p->tsz * (size_t)2 * npairs * p->P1 * p->P2)) != KRIG_OK) return r;
+    if ((r = dalloc(p, &p->csRes, (size_t)R * p->n)) != KRIG_OK) return r;
+    if ((r = dalloc(p, &p->csAl, (size_t)R * p->n)) != KRIG_OK) return r;
+    p->csR = R;
+  }
+  {
+    StageTimer t(p, KRIG_STAGE_CSIM_CE);
+    // pass 1: noise x sqrt(Lambda/N) and transforms over the torus columns
+    ColsArgs c{};
+    c.H2 = p->Fs2;
+    c.filt = p->lamS;
+    c.filt_ld = p->Fs1;
+    c.out = p->csT;
+    c.out_fs = (int64_t)p->Fs2 * p->ldP;
+    c.out_ld = p->ldP;
+    c.rows = Window{0, p->P1, 0, 0};
+    c.key0 = (uint32_t)(seed & 0xFFFFFFFFu);
+    c.key1 = (uint32_t)(seed >> 32);
+    c.pair0 = 0;
+    c.ncol_full = p->Fs2;
+    c.twF = f32 ? (const void*)p->tws1_32 : (const void*)p->tws1_64;
+    c.NL = nl_cols_for(p->es1, csz(p), false);
+    KRIG_TRY((f32 ? p->es1->k.ce_cols32 : p->es1->k.ce_cols64)(c, npairs, p->st));
+    // pass 2: transforms over the torus rows -> two realisations per pair
+    RowsCEArgs o{};
+    o.nrows = p->P1;
+    o.ncols = p->Fs2;
+    o.in = p->csT;
+    o.in_fs = (int64_t)p->Fs2 * p->ldP;
+    o.in_ld = p->ldP;
+    o.out = p->csU;
+    o.out_fs = (int64_t)p->P1 * p->P2;
+    o.ldo = p->P2;
+    o.keep = p->P2;
+    o.R = R;
+    o.pair0 = 0;
+    o.twF = f32 ? (const void*)p->tws2_32 : (const void*)p->tws2_64;
+    o.NL = nl_ce_rows_for(p->es2, csz(p));
+    KRIG_TRY((f32 ? p->es2->k.ce_rows32 : p->es2->k.ce_rows64)(o, npairs, p->st));
+  }
+  // residual of the data against the simulated data at the sites
+  {
+    StageTimer t(p, KRIG_STAGE_GATHER);
+    KRIG_TRY(csim_residual(p->g, p->anchor, p->Wt, p->n, p->csU, (int64_t)p->P1 * p->P2, p->P2, R, f32, d_y,
+                           sqrt(p->mt.tau2), seed, 0, p->csRes, p->n, p->st));
+  }
+  if ((r = do_solve(p, R, p->csRes, p->csAl)) != KRIG_OK) return r;
+  // krige the residual and add the unconditional field (last pass of the convolution)
+  return do_convolve(p, R, p->csAl, p->filt, d_fields, p->S1, p->csU, (int64_t)p->P1 * p->P2, p->P2);
 }
 
 }  // extern "C"

@@ -61,8 +61,10 @@ hipError_t csim_residual(const GridDev& g, const int32_t* anchor, const double* 
 hipError_t fold_dlag(const double* X, int64_t ldx, int n1l, int n2l, double scale, void* dlag, int to_f32,
                      hipStream_t st);
 
-// Complex white noise x sqrt(Lambda) for the circulant-embedding sampler, and the
-// field pair -> real images.  (see csim kernels in setup.hip)
-hipError_t ce_lambda_check(const double* lam, int64_t cnt, double* minmax, hipStream_t st);
+// circulant-embedding eigenvalues: per-block min / max / negative count (the host
+// finishes the reduction), then x <- sqrt(max(x, 0) * scale)
+hipError_t minmax_blocks(const double* x, int64_t cnt, double* bmin, double* bmax, int* bneg, int nblocks,
+                         hipStream_t st);
+hipError_t sqrt_clamp(double* x, int64_t cnt, double scale, hipStream_t st);
 
 }  // namespace krig

@@ -447,3 +447,56 @@ hipError_t fold_dlag(const double* X, int64_t ldx, int n1l, int n2l, double scal
 }
 
 }  // namespace krig
+
+namespace krig {
+
+// per-block min, max and count of negatives of a FP64 array (host finishes)
+__global__ void __launch_bounds__(256) k_minmax(const double* __restrict__ x, int64_t cnt, double* bmin,
+                                                double* bmax, int* bneg) {
+  __shared__ double smin[256], smax[256];
+  __shared__ int sneg[256];
+  double mn = 1e300, mx = -1e300;
+  int ng = 0;
+  for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < cnt; i += (int64_t)gridDim.x * blockDim.x) {
+    const double v = x[i];
+    mn = fmin(mn, v);
+    mx = fmax(mx, v);
+    ng += v < 0.0;
+  }
+  smin[threadIdx.x] = mn;
+  smax[threadIdx.x] = mx;
+  sneg[threadIdx.x] = ng;
+  __syncthreads();
+  for (int o = 128; o > 0; o >>= 1) {
+    if ((int)threadIdx.x < o) {
+      smin[threadIdx.x] = fmin(smin[threadIdx.x], smin[threadIdx.x + o]);
+      smax[threadIdx.x] = fmax(smax[threadIdx.x], smax[threadIdx.x + o]);
+      sneg[threadIdx.x] += sneg[threadIdx.x + o];
+    }
+    __syncthreads();
+  }
+  if (threadIdx.x == 0) {
+    bmin[blockIdx.x] = smin[0];
+    bmax[blockIdx.x] = smax[0];
+    bneg[blockIdx.x] = sneg[0];
+  }
+}
+
+hipError_t minmax_blocks(const double* x, int64_t cnt, double* bmin, double* bmax, int* bneg, int nblocks,
+                         hipStream_t st) {
+  hipLaunchKernelGGL(k_minmax, dim3(nblocks), dim3(256), 0, st, x, cnt, bmin, bmax, bneg);
+  return hipGetLastError();
+}
+
+// x <- sqrt(max(x, 0) * scale)
+__global__ void k_sqrt_clamp(double* x, int64_t cnt, double scale) {
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < cnt) x[i] = sqrt(fmax(x[i], 0.0) * scale);
+}
+
+hipError_t sqrt_clamp(double* x, int64_t cnt, double scale, hipStream_t st) {
+  hipLaunchKernelGGL(k_sqrt_clamp, dim3(nblk(cnt)), dim3(256), 0, st, x, cnt, scale);
+  return hipGetLastError();
+}
+
+}  // namespace krig

@@ -348,3 +348,48 @@ def test_error_paths(krig):
     y = host(p.predict(dev(np.array([[1.0, -2.0, 0.5, 3.0]]))))[0]
     ref = rp.predict_direct(ek.coef(np.array([1.0, -2.0, 0.5, 3.0]))).reshape(10, 10)
     assert relmax(y, ref) < 1e-12
+
+
+# ------------------------------------------------------------------------------ conditional simulation
+@pytest.mark.parametrize("dtype", ["f64", "f32"])
+def test_csim_realisation_parity(krig, dtype):
+    from oracle.csim import ConditionalSimulator
+    w = wl.tiny(seed=21, m1=20, m2=18, L=2, n=25, nu=1.5, rho=0.15, tau2=0.01, ylen=0.9)
+    g, k, rp, ek = oracle_of(w)
+    say("csim realisation parity", dtype)
+    p = krig.plan_for(w, dtype)
+    p.set_weights(dev(np.stack([rp.i0, rp.j0], 1), torch.int32), dev(rp.W))
+    R, seed = 5, 12345
+    f = host(p.csim(R, seed, dev(w.y[0])))
+    Fs1, Fs2 = p.info("CE_F1"), p.info("CE_F2")
+    assert Fs1 >= 2 * (g.P1 - 1) and Fs2 >= 2 * (g.P2 - 1)
+    cs = ConditionalSimulator(g, k, w.sites, Fs1, Fs2)
+    assert p.info("CE_CLAMPED") == cs.nclamp
+    for r in range(R):
+        ref = cs.realisation(seed, r, w.y[0])
+        err = relmax(f[r], ref)
+        # FP32: u is stored in FP32 and the residual solve amplifies its rounding by
+        # at most cond(M) (~2e3 here)
+        assert err < (1e-9 if dtype == "f64" else 1e-4), (r, err)
+    f2 = host(p.csim(R, seed, dev(w.y[0])))
+    assert np.array_equal(f, f2)  # same seed, same fields
+
+
+def test_csim_batch_matches_kriging_standard_errors(krig):
+    w = wl.csim_batch()
+    g, k, rp, ek = oracle_of(w)
+    say("csim batch R=256 512x512 statistics")
+    p = krig.plan_for(w, "f32")
+    R = w.extra["R"]
+    f = p.csim(R, w.extra["ce_seed"], dev(w.y[0]))
+    idx = np.random.default_rng(7).choice(g.m1 * g.m2, 1024, replace=False)
+    fs = host(f.reshape(R, -1)[:, torch.as_tensor(idx, device="cuda:0")])
+    sd = fs.std(0, ddof=1)
+    se = ek.std_error(g.nodes()[idx])
+    ratio = sd / se
+    assert abs(ratio.mean() - 1.0) < 0.03, ratio.mean()
+    assert np.mean(np.abs(ratio - 1.0) < 0.15) > 0.99
+    pred = rp.predict_direct(ek.coef(w.y[0]), idx)
+    z = np.abs(fs.mean(0) - pred) / (se / np.sqrt(R))
+    assert np.mean(z < 4.0) > 0.99
+    assert p.info("CE_F1") == 1152 and p.info("CE_CLAMPED") >= 0
