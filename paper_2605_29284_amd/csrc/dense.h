@@ -31,9 +31,12 @@ hipError_t cholesky_and_inverse(double* A, int64_t lda, int n, double* Linv, dou
 hipError_t copy_rows(const double* src, int64_t ld_src, double* dst, int64_t ld_dst, int nr, int nc,
                      hipStream_t st);
 hipError_t fill_f64(double* p, int64_t cnt, double v, hipStream_t st);
-// part: workspace of tri_chunks(n) * B * n doubles
-int tri_chunks(int n);
-hipError_t tri_apply(const double* X, int64_t ldx, int n, const double* in, int64_t in_fs, double* out,
-                     int64_t out_fs, int B, int trans, double* part, hipStream_t st);
+// dst = src^T for an n x n matrix
+hipError_t transpose_f64(const double* src, int64_t ld_src, double* dst, int64_t ld_dst, int n, hipStream_t st);
+// out[b] = T in[b] for a triangular T (upper = 0: lower, 1: upper); T row-major with a
+// pitch ldt that is a multiple of 4 and >= n rounded up to 16, 32-byte aligned, zeros
+// outside the triangle and in the padding.  hipErrorInvalidValue otherwise.
+hipError_t tri_apply(const double* T, int64_t ldt, int n, int upper, const double* in, int64_t in_fs, double* out,
+                     int64_t out_fs, int B, hipStream_t st);
 
 }  // namespace krig

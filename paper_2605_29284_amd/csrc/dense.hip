@@ -290,85 +290,102 @@ hipError_t copy_rows(const double* src, int64_t ld_src, double* dst, int64_t ld_
 }
 
 // ------------------------------------------------------------------------------------
-// apply the explicit inverse factor to B right-hand sides (FP64 MFMA, split over K)
-//   trans = 0:  out[b][i] = sum_{k <= i} X[i][k] in[b][k]      (L^{-1} y)
-//   trans = 1:  out[b][i] = sum_{k >= i} X[k][i] in[b][k]      (L^{-T} y)
-// X is lower triangular with explicit zeros above the diagonal, so only whole
-// tiles outside the triangle are skipped.  Block (col tile j of 64, K chunk c,
-// field group z of 16): four waves, each a 16 x 16 MFMA tile (fields x columns);
-// the partial sums of chunk c go to part[c][b][i] and are reduced in a fixed order.
+// transpose of an n x n row-major matrix into dst (pitch ldd), through 32 x 32 LDS tiles
 // ------------------------------------------------------------------------------------
-constexpr int TRI_KC = 256;
+__global__ void __launch_bounds__(256) k_transpose_f64(const double* __restrict__ src, int64_t lds_,
+                                                       double* __restrict__ dst, int64_t ldd, int n) {
+  __shared__ double t[32][33];
+  const int r0 = blockIdx.y * 32, c0 = blockIdx.x * 32;
+  const int tx = threadIdx.x & 31, ty = threadIdx.x >> 5;  // 32 x 8
+  for (int k = ty; k < 32; k += 8) {
+    const int r = r0 + k, c = c0 + tx;
+    t[k][tx] = (r < n && c < n) ? src[(int64_t)r * lds_ + c] : 0.0;
+  }
+  __syncthreads();
+  for (int k = ty; k < 32; k += 8) {
+    const int r = c0 + k, c = r0 + tx;
+    if (r < n && c < n) dst[(int64_t)r * ldd + c] = t[tx][k];
+  }
+}
 
-template <int TRANS>
-__global__ void __launch_bounds__(256) k_tri_mm(const double* __restrict__ X, int64_t ldx, int n,
-                                                const double* __restrict__ in, int64_t in_fs, int B,
-                                                double* __restrict__ part) {
-  __shared__ double xs[16][64 + 1];   // [k][col]
-  __shared__ double ys[16][16 + 1];   // [k][field]
-  const int i0 = blockIdx.x * 64;
-  const int kc0 = blockIdx.y * TRI_KC;
-  const int f0 = blockIdx.z * 16;
-  const int tid = threadIdx.x, wave = tid >> 6, lane = tid & 63;
-  int kb = kc0, ke = min(kc0 + TRI_KC, n);
-  if (TRANS == 0) ke = min(ke, i0 + 64);   // k <= i
-  else kb = max(kb, i0);                    // k >= i
+hipError_t transpose_f64(const double* src, int64_t ld_src, double* dst, int64_t ld_dst, int n, hipStream_t st) {
+  if (n <= 0) return hipSuccess;
+  dim3 grid((n + 31) / 32, (n + 31) / 32);
+  hipLaunchKernelGGL(k_transpose_f64, grid, dim3(256), 0, st, src, ld_src, dst, ld_dst, n);
+  return hipGetLastError();
+}
+
+// ------------------------------------------------------------------------------------
+// triangular product with an explicit triangular factor T (row-major, pitch ldt,
+// zeros outside the triangle and in the pitch padding):
+//   UPPER = 0:  out[b][i] = sum_{k <= i} T[i][k] in[b][k]      (T = L^{-1})
+//   UPPER = 1:  out[b][i] = sum_{k >= i} T[i][k] in[b][k]      (T = L^{-T})
+// One block per 16 output rows x 16 fields; its 16 waves take interleaved K chunks of
+// 16, four chunks per round.  Per chunk, lane (r = l%16, g = l/16) loads T[i0+r][16c + 4g .. +3] as one
+// 32-byte vector (a wave reads whole 128-byte row segments) and in[f0+r][same k];
+// four MFMA 16x16x4 steps take element s of each, i.e. the K order inside a chunk is
+// permuted identically for both operands.  The waves' tiles are summed through LDS
+// in a fixed order, so results do not depend on scheduling.
+// ------------------------------------------------------------------------------------
+constexpr int TRI_WAVES = 16;
+constexpr int TRI_U = 4;
+
+template <int UPPER>
+__global__ void __launch_bounds__(64 * TRI_WAVES) k_tri_apply(const double* __restrict__ T, int64_t ldt, int n,
+                                                              const double* __restrict__ in, int64_t in_fs, int B,
+                                                              double* __restrict__ out, int64_t out_fs) {
+  __shared__ double red[TRI_WAVES][4][64];
+  const int i0 = blockIdx.x * 16, f0 = blockIdx.y * 16;
+  const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
+  const int r = lane & 15, g = lane >> 4;
+  const int nch = (n + 15) / 16;
+  const int c_lo = UPPER ? i0 / 16 : 0;
+  const int c_hi = UPPER ? nch : min(nch, i0 / 16 + 1);
+  const bool rok = i0 + r < n, fok = f0 + r < B;
+  const double* trow = T + (int64_t)(rok ? i0 + r : 0) * ldt;
+  const double* irow = in + (int64_t)(fok ? f0 + r : 0) * in_fs;
   double4_t acc = (double4_t){0.0, 0.0, 0.0, 0.0};
-  for (int k0 = kb; k0 < ke; k0 += 16) {
-    for (int e = tid; e < 16 * 64; e += 256) {
-      int kk, cc;
-      if (TRANS == 0) { kk = e % 16; cc = e / 16; } else { cc = e % 64; kk = e / 64; }
-      const int k = k0 + kk, i = i0 + cc;
-      double v = 0.0;
-      if (k < ke && i < n) v = TRANS == 0 ? X[(int64_t)i * ldx + k] : X[(int64_t)k * ldx + i];
-      xs[kk][cc] = v;
-    }
-    {
-      const int kk = tid % 16, ff = tid / 16;  // 256 threads = 16 x 16
-      const int k = k0 + kk, f = f0 + ff;
-      ys[kk][ff] = (k < ke && f < B) ? in[(int64_t)f * in_fs + k] : 0.0;
-    }
-    __syncthreads();
+  // TRI_U chunks per round: all their loads are in flight before the first MFMA
+  for (int c0 = c_lo + wave; c0 < c_hi; c0 += TRI_U * TRI_WAVES) {
+    double4_t x[TRI_U];
+    double a[TRI_U][4];
 #pragma unroll
-    for (int kq = 0; kq < 16; kq += 4) {
-      const double a = ys[kq + (lane >> 4)][lane & 15];
-      const double b = xs[kq + (lane >> 4)][wave * 16 + (lane & 15)];
-      acc = __builtin_amdgcn_mfma_f64_16x16x4f64(a, b, acc, 0, 0, 0);
+    for (int u = 0; u < TRI_U; ++u) {
+      const int c = c0 + u * TRI_WAVES;
+      const int k = 16 * c + 4 * g;
+      x[u] = (double4_t){0.0, 0.0, 0.0, 0.0};
+      if (rok && c < c_hi) x[u] = *reinterpret_cast<const double4_t*>(trow + k);
+#pragma unroll
+      for (int s = 0; s < 4; ++s) a[u][s] = (fok && c < c_hi && k + s < n) ? irow[k + s] : 0.0;
     }
-    __syncthreads();
+#pragma unroll
+    for (int u = 0; u < TRI_U; ++u)
+#pragma unroll
+      for (int s = 0; s < 4; ++s) acc = __builtin_amdgcn_mfma_f64_16x16x4f64(a[u][s], x[u][s], acc, 0, 0, 0);
   }
-  const int i = i0 + wave * 16 + (lane & 15);
-  for (int r = 0; r < 4; ++r) {
-    const int f = f0 + (lane >> 4) + 4 * r;
-    if (f < B && i < n) part[((int64_t)blockIdx.y * B + f) * n + i] = acc[r];
+#pragma unroll
+  for (int q = 0; q < 4; ++q) red[wave][q][lane] = acc[q];
+  __syncthreads();
+  if (threadIdx.x < 256) {
+    const int q = threadIdx.x >> 6, l = threadIdx.x & 63;
+    double s = 0.0;
+    for (int w = 0; w < TRI_WAVES; ++w) s += red[w][q][l];  // fixed order
+    // D[l/16 + 4q][l%16]: field f0 + l/16 + 4q, row i0 + l%16
+    const int f = f0 + (l >> 4) + 4 * q, i = i0 + (l & 15);
+    if (f < B && i < n) out[(int64_t)f * out_fs + i] = s;
   }
 }
 
-__global__ void k_chunk_reduce(const double* __restrict__ part, int nchunk, int B, int n, double* __restrict__ out,
-                               int64_t out_fs) {
-  const int64_t idx = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  if (idx >= (int64_t)B * n) return;
-  const int b = (int)(idx / n), i = (int)(idx % n);
-  double s = 0.0;
-  for (int c = 0; c < nchunk; ++c) s += part[((int64_t)c * B + b) * n + i];  // fixed order
-  out[(int64_t)b * out_fs + i] = s;
-}
-
-int tri_chunks(int n) { return (n + TRI_KC - 1) / TRI_KC; }
-
-hipError_t tri_apply(const double* X, int64_t ldx, int n, const double* in, int64_t in_fs, double* out,
-                     int64_t out_fs, int B, int trans, double* part, hipStream_t st) {
-  const int nch = tri_chunks(n);
-  dim3 grid((n + 63) / 64, nch, (B + 15) / 16);
-  if (trans)
-    hipLaunchKernelGGL(k_tri_mm<1>, grid, dim3(256), 0, st, X, ldx, n, in, in_fs, B, part);
+hipError_t tri_apply(const double* T, int64_t ldt, int n, int upper, const double* in, int64_t in_fs, double* out,
+                     int64_t out_fs, int B, hipStream_t st) {
+  if (n <= 0 || B <= 0) return hipSuccess;
+  if ((ldt & 3) || ldt < (int64_t)(n + 15) / 16 * 16 || (reinterpret_cast<uintptr_t>(T) & 31))
+    return hipErrorInvalidValue;
+  dim3 grid((n + 15) / 16, (B + 15) / 16);
+  if (upper)
+    hipLaunchKernelGGL(k_tri_apply<1>, grid, dim3(64 * TRI_WAVES), 0, st, T, ldt, n, in, in_fs, B, out, out_fs);
   else
-    hipLaunchKernelGGL(k_tri_mm<0>, grid, dim3(256), 0, st, X, ldx, n, in, in_fs, B, part);
-  hipError_t e = hipGetLastError();
-  if (e != hipSuccess) return e;
-  const int64_t tot = (int64_t)B * n;
-  hipLaunchKernelGGL(k_chunk_reduce, dim3((unsigned)((tot + 255) / 256)), dim3(256), 0, st, part, nch, B, n, out,
-                     out_fs);
+    hipLaunchKernelGGL(k_tri_apply<0>, grid, dim3(64 * TRI_WAVES), 0, st, T, ldt, n, in, in_fs, B, out, out_fs);
   return hipGetLastError();
 }
 

@@ -109,6 +109,7 @@ struct RowsC2RArgs {
   int64_t add_fs, add_ld;
   int add_r0, add_c0;
   const void* twF;        // cx<TC> [F]
+  double scale;           // output scale (folded form)
   int NL;
 };
 
@@ -132,6 +133,8 @@ struct FftSet {
   launch_cols_t inv_sum64;          // inverse columns of a sum of partial spectra (FP64)
   launch_rows_c2r_t c2r32;          // inverse rows, FP32
   launch_rows_c2r_t c2r64;          // inverse rows, FP64
+  launch_rows_c2r_t c2r_fold32;     // inverse rows of the compact correlation, sign images
+  launch_rows_c2r_t c2r_fold64;     //   folded, FP64 arithmetic -> FP32 / FP64 lag gradient
   launch_rows_r2c_t r2c_cov;        // covariance on the embedding torus, FP64
   launch_cols_t ce_cols32, ce_cols64;    // sampler pass 1 (noise x sqrt(Lambda), column transforms)
   launch_rows_ce_t ce_rows32, ce_rows64; // sampler pass 2 (row transforms -> two realisations)

@@ -50,6 +50,11 @@ template <int N1, int N2> struct Geo {
   static constexpr int ROWS = imax(EX, F + 2);            // row kernels: exchange or transpose
 };
 
+// LDS transposes [k][R] with the column rotated by k: lanes that differ in k (the
+// fast lane index on one side of the transpose) fall on distinct banks, and a row
+// stays a permutation of itself so the other side still reads whole rows.
+__device__ __forceinline__ int rot(int k, int c, int R) { return k * R + (c + k) % R; }
+
 __device__ __forceinline__ int window_dst(const Window& wd, int i) {
   if (i >= wd.a0 && i < wd.a0 + wd.na) return i - wd.a0;
   if (i >= wd.b0 && i < wd.b0 + wd.nb) return wd.na + i - wd.b0;
@@ -218,8 +223,8 @@ __global__ void __launch_bounds__(256) k_rows_r2c(RowsR2CArgs a) {
     for (int k2 = 0; k2 < NK; ++k2) {
       const int k = s + N1 * k2;
       if (k < a.H2) {
-        T[k * R2 + 2 * l] = xa[k2];
-        T[k * R2 + 2 * l + 1] = xb[k2];
+        T[rot(k, 2 * l, R2)] = xa[k2];
+        T[rot(k, 2 * l + 1, R2)] = xb[k2];
       }
     }
   }
@@ -228,7 +233,7 @@ __global__ void __launch_bounds__(256) k_rows_r2c(RowsR2CArgs a) {
   for (int idx = threadIdx.x; idx < a.H2 * R2; idx += blockDim.x) {
     const int rl = idx % R2, k = idx / R2;
     const int row = row0 + rl;
-    if (row < a.nrows) o[(int64_t)k * a.out_ld + row] = ccast<TS>(T[idx]);
+    if (row < a.nrows) o[(int64_t)k * a.out_ld + row] = ccast<TS>(T[rot(k, rl, R2)]);
   }
 }
 
@@ -398,13 +403,15 @@ __global__ void __launch_bounds__(256) k_cols(ColsArgs a) {
   } else {  // COL_INV_SUM: inverse transform of sum_g part[g] (natural order), keep rows
     const cx<TSI>* p = reinterpret_cast<const cx<TSI>*>(a.in) + (int64_t)col * a.in_ld;
     cx<TC> v[N1];
-    if (s < N2) {
 #pragma unroll
-      for (int n1 = 0; n1 < N1; ++n1) {
-        cx<TC> t = mk<TC>(0, 0);
-        if (colok)
-          for (int g = 0; g < a.G; ++g) t = t + ccast<TC>(p[(int64_t)g * a.in_fs + N2 * n1 + s]);  // fixed order
-        v[n1] = t;
+    for (int n1 = 0; n1 < N1; ++n1) v[n1] = mk<TC>(0, 0);
+    if (s < N2 && colok) {
+      // partial g outermost: each round issues the N1 loads of one partial together;
+      // every element is still summed in the order g = 0, 1, ...
+      for (int g = 0; g < a.G; ++g) {
+        const cx<TSI>* pg = p + (int64_t)g * a.in_fs + s;
+#pragma unroll
+        for (int n1 = 0; n1 < N1; ++n1) v[n1] = v[n1] + ccast<TC>(pg[N2 * n1]);
       }
     }
     cx<TC> w[N2];
@@ -443,7 +450,7 @@ __global__ void __launch_bounds__(256) k_rows_c2r(RowsC2RArgs a) {
   for (int idx = threadIdx.x; idx < a.H2 * R2; idx += blockDim.x) {
     const int rl = idx % R2, k = idx / R2;
     const int row = row0 + rl;
-    T[idx] = row < a.nrows ? ccast<TC>(in[(int64_t)k * a.in_ld + row]) : mk<TC>(0, 0);
+    T[rot(k, rl, R2)] = row < a.nrows ? ccast<TC>(in[(int64_t)k * a.in_ld + row]) : mk<TC>(0, 0);
   }
   __syncthreads();
   cx<TC> v[N1];
@@ -453,7 +460,7 @@ __global__ void __launch_bounds__(256) k_rows_c2r(RowsC2RArgs a) {
       const int k = N2 * n1 + s;
       const bool lo = k < a.H2;
       const int kk = lo ? k : G::F - k;
-      cx<TC> xa = T[kk * R2 + 2 * l], xb = T[kk * R2 + 2 * l + 1];
+      cx<TC> xa = T[rot(kk, 2 * l, R2)], xb = T[rot(kk, 2 * l + 1, R2)];
       if (kk == 0 || 2 * kk == G::F) { xa.y = 0; xb.y = 0; }  // DC / Nyquist are real
       if (!lo) { xa.y = -xa.y; xb.y = -xb.y; }
       v[n1] = mk<TC>(xa.x - xb.y, xa.y + xb.x);  // Xa + i Xb
@@ -486,6 +493,75 @@ __global__ void __launch_bounds__(256) k_rows_c2r(RowsC2RArgs a) {
 }
 
 // ----------------------------------------------------------------------------------------
+// inverse rows of the compact correlation image with the sign images folded in:
+// input rows (frequency-major) hold lags 0..n1l-1 then -(n1l-1)..-1 (compact row
+// 2 n1l - 1 - u is lag -u); output row u < n1l, column w < n2l is
+//   scale * sum over the sign images (+-u, +-w) of the correlation,
+// each distinct image once (u = 0 or w = 0 has fewer).  The row fold is done on the
+// input spectra (the row transform is linear), the column fold on the transformed
+// line in LDS.
+// ----------------------------------------------------------------------------------------
+template <typename TC, typename TO, int N1, int N2>
+__global__ void __launch_bounds__(256) k_rows_c2r_fold(RowsC2RArgs a) {
+  using G = Geo<N1, N2>;
+  extern __shared__ unsigned char smem_raw[];
+  cx<TC>* lds = reinterpret_cast<cx<TC>*>(smem_raw);
+  const int s = threadIdx.x % G::NT;
+  const int l = threadIdx.x / G::NT;
+  const int NL = a.NL;
+  const int n1l = a.nrows, n2l = a.cols.na;
+  const int row0 = 2 * blockIdx.x * NL;
+  const int ra = row0 + 2 * l, rb = ra + 1;
+  const cx<TC>* twF = reinterpret_cast<const cx<TC>*>(a.twF);
+  const int R2 = 2 * NL;
+  cx<TC>* T = lds;
+  const cx<TC>* in = reinterpret_cast<const cx<TC>*>(a.in);
+  for (int idx = threadIdx.x; idx < a.H2 * R2; idx += blockDim.x) {
+    const int rl = idx % R2, k = idx / R2;
+    const int u = row0 + rl;
+    cx<TC> t = mk<TC>(0, 0);
+    if (u < n1l) {
+      t = in[(int64_t)k * a.in_ld + u];
+      if (u > 0) t = t + in[(int64_t)k * a.in_ld + 2 * n1l - 1 - u];
+    }
+    T[rot(k, rl, R2)] = t;
+  }
+  __syncthreads();
+  cx<TC> v[N1];
+  if (s < N2) {
+#pragma unroll
+    for (int n1 = 0; n1 < N1; ++n1) {
+      const int k = N2 * n1 + s;
+      const bool lo = k < a.H2;
+      const int kk = lo ? k : G::F - k;
+      cx<TC> xa = T[rot(kk, 2 * l, R2)], xb = T[rot(kk, 2 * l + 1, R2)];
+      if (kk == 0 || 2 * kk == G::F) { xa.y = 0; xb.y = 0; }  // DC / Nyquist are real
+      if (!lo) { xa.y = -xa.y; xb.y = -xb.y; }
+      v[n1] = mk<TC>(xa.x - xb.y, xa.y + xb.x);  // Xa + i Xb
+    }
+  }
+  __syncthreads();
+  cx<TC>* L = lds + (size_t)l * G::ROWS;
+  cx<TC> w[N2];
+  two_stage<TC, N1, N2, 1>(v, w, s, L, twF);
+  __syncthreads();
+  if (s < N1) {
+#pragma unroll
+    for (int k2 = 0; k2 < N2; ++k2) L[s + N1 * k2] = w[k2];  // natural column order
+  }
+  __syncthreads();
+  TO* oa = reinterpret_cast<TO*>(a.out) + (int64_t)ra * a.ldo;
+  TO* ob = oa + a.ldo;
+  const TC sc = (TC)a.scale;
+  for (int c = s; c < n2l; c += G::NT) {
+    cx<TC> y = L[c];
+    if (c > 0) y = y + L[G::F - c];
+    if (ra < n1l) oa[c] = (TO)(y.x * sc);
+    if (rb < n1l) ob[c] = (TO)(y.y * sc);
+  }
+}
+
+// ----------------------------------------------------------------------------------------
 // sampler pass 2: complex forward transform of torus rows r < nrows (frequency-major
 // input), keep columns < keep; real part -> realisation 2 pair, imaginary -> 2 pair + 1
 // ----------------------------------------------------------------------------------------
@@ -506,13 +582,13 @@ __global__ void __launch_bounds__(256) k_rows_ce(RowsCEArgs a) {
   for (int idx = threadIdx.x; idx < G::F * NL; idx += blockDim.x) {
     const int rl = idx % NL, k = idx / NL;
     const int r = row0 + rl;
-    T[idx] = r < a.nrows ? ccast<TC>(in[(int64_t)k * a.in_ld + r]) : mk<TC>(0, 0);
+    T[rot(k, rl, NL)] = r < a.nrows ? ccast<TC>(in[(int64_t)k * a.in_ld + r]) : mk<TC>(0, 0);
   }
   __syncthreads();
   cx<TC> v[N1];
   if (s < N2) {
 #pragma unroll
-    for (int n1 = 0; n1 < N1; ++n1) v[n1] = T[(N2 * n1 + s) * NL + l];
+    for (int n1 = 0; n1 < N1; ++n1) v[n1] = T[rot(N2 * n1 + s, l, NL)];
   }
   __syncthreads();
   cx<TC>* L = lds + (size_t)l * G::EX;
@@ -565,6 +641,17 @@ hipError_t launch_rows_c2r(const RowsC2RArgs& a, int B, hipStream_t st) {
   return hipGetLastError();
 }
 
+template <typename TC, typename TO, int N1, int N2>
+hipError_t launch_rows_c2r_fold(const RowsC2RArgs& a, int B, hipStream_t st) {
+  const int npairs = (a.nrows + 1) / 2;
+  dim3 grid((npairs + a.NL - 1) / a.NL, 1);
+  dim3 block(Geo<N1, N2>::NT * a.NL);
+  const size_t sh = rows_lds(N1, N2, a.NL, sizeof(cx<TC>));
+  (void)B;
+  k_rows_c2r_fold<TC, TO, N1, N2><<<grid, block, sh, st>>>(a);
+  return hipGetLastError();
+}
+
 template <typename TC, typename TS, typename TO, int N1, int N2>
 hipError_t launch_rows_ce(const RowsCEArgs& a, int npairs, hipStream_t st) {
   dim3 grid((a.nrows + a.NL - 1) / a.NL, npairs);
@@ -592,6 +679,8 @@ FftEntry make_fft_entry() {
   k.inv_sum64 = launch_cols<double, double, double, double, N1, N2, COL_INV_SUM>;
   k.c2r32 = launch_rows_c2r<float, float, float, N1, N2>;
   k.c2r64 = launch_rows_c2r<double, double, double, N1, N2>;
+  k.c2r_fold32 = launch_rows_c2r_fold<double, float, N1, N2>;
+  k.c2r_fold64 = launch_rows_c2r_fold<double, double, N1, N2>;
   k.r2c_cov = launch_rows_r2c<double, double, double, N1, N2, SRC_COV>;
   k.ce_cols32 = launch_cols<float, float, float, float, N1, N2, COL_CE>;
   k.ce_cols64 = launch_cols<double, double, double, double, N1, N2, COL_CE>;

@@ -63,6 +63,8 @@ struct krig_plan_s {
   CsrWork cw{};
   double* Lfac = nullptr;  // Cholesky factor of K + tau^2 I
   double* Linv = nullptr;  // its inverse
+  double* LinvT = nullptr;  // and the transpose of that
+  int64_t ldL = 0;  // pitch of Lfac, Linv, LinvT (n rounded up to 16)
   double* Dinv = nullptr;
   double* work = nullptr;
   int kn_status = 0, pivot = 0;
@@ -75,11 +77,9 @@ struct krig_plan_s {
   void* img = nullptr;    // FP64 [B][P1][P2]       correlation image
   double* alpha = nullptr;  // [B][n]
   double* tmpv = nullptr;   // [B][n]
-  double* tripart = nullptr;  // [tri_chunks(n)][B][n] split-K partial sums of the solve
   void* part = nullptr;   // cx FP64 [ngroups][H2][F1]
   int part_groups = 0;
   void* XC = nullptr;     // cx FP64 [H2][ldX]
-  void* XR = nullptr;     // FP64 [2 n1l - 1][2 n2l - 1]
   // custom-lag filter
   double* filtC = nullptr;
   double* lagC64 = nullptr;
@@ -269,7 +269,7 @@ int make_filter(krig_plan p, const double* lag64, double* filt_out) {
 // forward workspaces (prediction and solves) for B fields
 int ensure_ws(krig_plan p, int B) {
   if (B <= p->wsB) return KRIG_OK;
-  void* olds[] = {p->S1, p->S2, p->alpha, p->tmpv, p->tripart};
+  void* olds[] = {p->S1, p->S2, p->alpha, p->tmpv};
   KRIG_TRY(hipStreamSynchronize(p->st));
   for (void* q : olds) dfree(p, q);
   const size_t c = csz(p);
@@ -279,7 +279,6 @@ int ensure_ws(krig_plan p, int B) {
   if ((r = dalloc_bytes(p, &p->S2, c * (size_t)B * H2 * p->ldM)) != KRIG_OK) return r;
   if ((r = dalloc(p, &p->alpha, (size_t)B * p->n)) != KRIG_OK) return r;
   if ((r = dalloc(p, &p->tmpv, (size_t)B * p->n)) != KRIG_OK) return r;
-  if ((r = dalloc(p, &p->tripart, (size_t)tri_chunks(p->n) * B * p->n)) != KRIG_OK) return r;
   p->wsB = B;
   return KRIG_OK;
 }
@@ -303,8 +302,8 @@ int ensure_ws_adj(krig_plan p, int B) {
 
 int do_solve(krig_plan p, int B, const double* y, double* alpha) {
   StageTimer t(p, KRIG_STAGE_SOLVE);
-  KRIG_TRY(tri_apply(p->Linv, p->n, p->n, y, p->n, p->tmpv, p->n, B, 0, p->tripart, p->st));
-  KRIG_TRY(tri_apply(p->Linv, p->n, p->n, p->tmpv, p->n, alpha, p->n, B, 1, p->tripart, p->st));
+  KRIG_TRY(tri_apply(p->Linv, p->ldL, p->n, 0, y, p->n, p->tmpv, p->n, B, p->st));
+  KRIG_TRY(tri_apply(p->LinvT, p->ldL, p->n, 1, p->tmpv, p->n, alpha, p->n, B, p->st));
   return KRIG_OK;
 }
 
@@ -664,16 +663,19 @@ int krig_plan_create(krig_plan* out, const krig_grid* g, const krig_matern* k, i
   CKH(build_csr(p->g, p->anchor, p->W, n, p->cw, p->node_ptr, p->ent_site, p->ent_w, p->st));
 
   // kriging system: M = K + tau^2 I, Cholesky, inverse factor
-  CK(dalloc(p, &p->Lfac, (size_t)n * n));
-  CK(dalloc(p, &p->Linv, (size_t)n * n));
+  p->ldL = (n + 15) / 16 * 16;
+  CK(dalloc(p, &p->Lfac, (size_t)n * p->ldL));
+  CK(dalloc(p, &p->Linv, (size_t)n * p->ldL));
+  CK(dalloc(p, &p->LinvT, (size_t)n * p->ldL));
   CK(dalloc(p, &p->Dinv, (size_t)((n + 63) / 64) * 4096));
   CK(dalloc(p, &p->work, (size_t)64 * std::max(n, 64)));
-  CKH(assemble_kt(p->sites, n, p->mt, p->Lfac, n, p->st));
-  CKH(cholesky_and_inverse(p->Lfac, n, n, p->Linv, p->Dinv, p->work, p->d_status + 1, p->st));
+  CKH(assemble_kt(p->sites, n, p->mt, p->Lfac, p->ldL, p->st));
+  CKH(cholesky_and_inverse(p->Lfac, p->ldL, n, p->Linv, p->Dinv, p->work, p->d_status + 1, p->st));
+  CKH(fill_f64(p->LinvT, (int64_t)n * p->ldL, 0.0, p->st));
+  CKH(transpose_f64(p->Linv, p->ldL, p->LinvT, p->ldL, n, p->st));
 
   // dlag buffers
   CK(dalloc_bytes(p, &p->XC, 16 * (size_t)p->H2 * p->ldX));
-  CK(dalloc_bytes(p, &p->XR, 8 * (size_t)(2 * n1l - 1) * (2 * n2l - 1)));
 
   int hst[4] = {0, 0, 0, 0};
   CKH(hipMemcpyAsync(hst, p->d_status, sizeof(hst), hipMemcpyDeviceToHost, p->st));
@@ -923,20 +925,19 @@ int krig_predict_adjoint(krig_plan p, int32_t B, const void* d_g, const double* 
     ci.NL = p->nl_cols64;
     KRIG_TRY(set1(p).inv_sum64(ci, 1, p->st));
     RowsC2RArgs oc{};
-    oc.nrows = 2 * p->n1l - 1;
+    oc.nrows = p->n1l;
     oc.H2 = p->H2;
     oc.in = p->XC;
     oc.in_fs = 0;
     oc.in_ld = p->ldX;
-    oc.out = p->XR;
+    oc.out = d_dlag;
     oc.out_fs = 0;
-    oc.ldo = 2 * p->n2l - 1;
-    oc.cols = Window{0, p->n2l, p->F2 - p->n2l + 1, p->n2l - 1};
+    oc.ldo = p->n2l;
+    oc.cols = Window{0, p->n2l, 0, 0};
     oc.twF = p->tw2_64;
+    oc.scale = 1.0 / ((double)p->F1 * p->F2);
     oc.NL = p->nl_rows64;
-    KRIG_TRY(set2(p).c2r64(oc, 1, p->st));
-    KRIG_TRY(fold_dlag((const double*)p->XR, 2 * p->n2l - 1, p->n1l, p->n2l, 1.0 / ((double)p->F1 * p->F2), d_dlag, is32(p),
-                       p->st));
+    KRIG_TRY((is32(p) ? set2(p).c2r_fold32 : set2(p).c2r_fold64)(oc, 1, p->st));
   }
   return KRIG_OK;
 }

@@ -56,11 +56,6 @@ hipError_t csim_residual(const GridDev& g, const int32_t* anchor, const double* 
                          int64_t img_fs, int64_t ldi, int R, int from_f32, const double* y, double noise_sd,
                          uint64_t seed, int r0, double* out, int64_t out_fs, hipStream_t st);
 
-// d loss / d lag from the compact correlation image X (rows: lags 0..n1l-1 then
-// -(n1l-1)..-1; cols likewise), summing the sign images, times scale.
-hipError_t fold_dlag(const double* X, int64_t ldx, int n1l, int n2l, double scale, void* dlag, int to_f32,
-                     hipStream_t st);
-
 // circulant-embedding eigenvalues: per-block min / max / negative count (the host
 // finishes the reduction), then x <- sqrt(max(x, 0) * scale)
 hipError_t minmax_blocks(const double* x, int64_t cnt, double* bmin, double* bmax, int* bneg, int nblocks,

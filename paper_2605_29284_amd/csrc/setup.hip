@@ -1,6 +1,6 @@
 // Set-up kernels (Steps 1-4 and the structure of Step 5), the deterministic scatter
 // (Steps 5-6, unfused form), the site gather of the adjoint and of conditional
-// simulation, and the lag-gradient fold.
+// simulation.
 #include "setup.h"
 
 #include "philox_dev.h"
@@ -416,33 +416,6 @@ hipError_t csim_residual(const GridDev& g, const int32_t* anchor, const double* 
   else
     hipLaunchKernelGGL(k_csim_residual<double>, grid, dim3(256), 0, st, g, anchor, Wt, n, (const double*)img,
                        img_fs, ldi, y, noise_sd, k0, k1, r0, out, out_fs);
-  return hipGetLastError();
-}
-
-// ------------------------------------------------------------------------------ dlag fold
-template <typename TO>
-__global__ void k_fold_dlag(const double* __restrict__ X, int64_t ldx, int n1l, int n2l, double scale,
-                            TO* __restrict__ dlag) {
-  const int idx = blockIdx.x * blockDim.x + threadIdx.x;
-  if (idx >= n1l * n2l) return;
-  const int u = idx / n2l, w = idx % n2l;
-  const int ru[2] = {u, 2 * n1l - 1 - u};  // compact rows of lags +u and -u
-  const int cw[2] = {w, 2 * n2l - 1 - w};
-  const int nu = u == 0 ? 1 : 2, nw = w == 0 ? 1 : 2;
-  double acc = 0.0;
-  for (int a = 0; a < nu; ++a)
-    for (int b = 0; b < nw; ++b) acc += X[(int64_t)ru[a] * ldx + cw[b]];
-  dlag[idx] = (TO)(acc * scale);
-}
-hipError_t fold_dlag(const double* X, int64_t ldx, int n1l, int n2l, double scale, void* dlag, int to_f32,
-                     hipStream_t st) {
-  const int cnt = n1l * n2l;
-  if (to_f32)
-    hipLaunchKernelGGL(k_fold_dlag<float>, dim3(nblk(cnt)), dim3(256), 0, st, X, ldx, n1l, n2l, scale,
-                       (float*)dlag);
-  else
-    hipLaunchKernelGGL(k_fold_dlag<double>, dim3(nblk(cnt)), dim3(256), 0, st, X, ldx, n1l, n2l, scale,
-                       (double*)dlag);
   return hipGetLastError();
 }
 
