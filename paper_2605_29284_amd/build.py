@@ -33,7 +33,7 @@ FLAGS = [
 
 def fft_sizes():
     txt = open(os.path.join(CSRC, "fft_sizes.h")).read()
-    return [(int(a), int(b)) for a, b in re.findall(r"X\((\d+),\s*(\d+)\)", txt)]
+    return [tuple(int(v) for v in m) for m in re.findall(r"X\((\d+),\s*(\d+),\s*(\d+)\)", txt)]
 
 
 def hipcc():
@@ -54,9 +54,9 @@ def build(jobs: int = 8, verbose: bool = False) -> str:
     os.makedirs(os.path.join(BUILD, "gen"), exist_ok=True)
     cc = hipcc()
     units = []
-    for a, b in fft_sizes():
-        src = os.path.join(BUILD, "gen", f"fft_{a}x{b}.hip")
-        body = f'#include "{CSRC}/fft_passes.h"\nKRIG_FFT_SIZE({a}, {b})\n'
+    for a, b, c in fft_sizes():
+        src = os.path.join(BUILD, "gen", f"fft_{a}x{b}x{c}.hip")
+        body = f'#include "{CSRC}/fft_passes.h"\nKRIG_FFT_SIZE({a}, {b}, {c})\n'
         if not os.path.exists(src) or open(src).read() != body:
             with open(src, "w") as f:
                 f.write(body)

@@ -1,12 +1,18 @@
-// Argument blocks and the per-size kernel table of the two-level FFT passes.
+// Argument blocks, geometry and the per-size kernel table of the FFT passes.
 //
-// A transform of length F = N1 * N2 is done in two register stages joined by one
-// LDS exchange (Cooley-Tukey "four-step" split): with n = N2*n1 + n2 and
-// k = k1 + N1*k2,
-//   X[k1 + N1 k2] = sum_n2 W_N2^(n2 k2) W_F^(n2 k1) sum_n1 x[N2 n1 + n2] W_N1^(n1 k1).
-// Stage A: one thread per n2 holds x[N2 n1 + n2] for all n1, does the length-N1
-// DFT and the twiddle W_F^(n2 k1); stage B: one thread per k1 holds all n2 and
-// does the length-N2 DFT, ending with X[k1 + N1 k2] for all k2 in registers.
+// A transform of length F = R1 * R2 * R3 runs in up to three register stages joined
+// by LDS exchanges.  With M = R2 * R3, n = m + M j and k = k1 + R1 k',
+//   X[k1 + R1 k'] = sum_m W_M^(m k') W_F^(m k1) sum_j x[m + M j] W_R1^(j k1)
+// (pass 1: one thread per m does the length-R1 DFT over j and the twiddle), and each
+// of the R1 inner length-M transforms is split again as M = R2 * R3 (Cooley-Tukey
+// "four-step"): with m = R3 n1 + s and k' = s' + R2 k2,
+//   Z[s' + R2 k2] = sum_s W_R3^(s k2) W_M^(s s') sum_n1 z[R3 n1 + s] W_R2^(n1 s').
+// R1 = 1 is the two-stage form.  Between passes the data cross lanes through LDS.
+//
+// Register layouts:  input  thread t < TIN  holds x[t + TIN j],  j < NIN;
+//                    output thread t < TOUT holds X[t + TOUT k], k < NOUT = R3.
+// The inverse transform can start from the output layout and end in the input
+// layout, so a forward/inverse pair needs no reordering in between.
 //
 // Half spectra between the row and column passes are stored frequency-major:
 // element (field b, frequency k, row r) at base + b*fs + k*ld + r, so that a
@@ -140,8 +146,47 @@ struct FftSet {
   launch_rows_ce_t ce_rows32, ce_rows64; // sampler pass 2 (row transforms -> two realisations)
 };
 
+__host__ __device__ constexpr int odd_up(int x) { return x | 1; }
+__host__ __device__ constexpr int imax(int a, int b) { return a > b ? a : b; }
+
+struct FftGeo {
+  int R1, R2, R3;
+  int F, M;         // length and inner length R2 * R3
+  int NIN, TIN;     // input layout
+  int NOUT, TOUT;   // output layout
+  int T2;           // threads of the middle pass (R1 * R3)
+  int NT;           // threads per line
+  int ON2;          // odd stride between the R3 rows of an inner exchange
+  int RS;           // odd size of one inner exchange region
+  int P1;           // row stride of the pass-1 exchange (M + 1)
+  int EX;           // LDS slots per line for the exchanges
+  int ROWS;         // row kernels: exchanges, natural-order pairing or transpose
+};
+
+__host__ __device__ constexpr FftGeo fft_geo(int R1, int R2, int R3) {
+  FftGeo g{};
+  g.R1 = R1;
+  g.R2 = R2;
+  g.R3 = R3;
+  g.F = R1 * R2 * R3;
+  g.M = R2 * R3;
+  g.NIN = R1 > 1 ? R1 : R2;
+  g.TIN = R1 > 1 ? g.M : R3;
+  g.NOUT = R3;
+  g.TOUT = R1 * R2;
+  g.T2 = R1 * R3;
+  g.NT = imax(imax(g.TIN, g.T2), g.TOUT);
+  g.ON2 = odd_up(R2);
+  g.RS = odd_up(R3 * g.ON2);
+  g.P1 = g.M + 1;
+  g.EX = R1 > 1 ? imax(R1 * g.P1, R1 * g.RS) : g.RS;
+  g.ROWS = imax(g.EX, g.F + 2);
+  return g;
+}
+
 struct FftEntry {
-  int F, N1, N2;
+  int F;
+  FftGeo geo;
   FftSet k;
 };
 
@@ -152,8 +197,8 @@ int fft_sizes(int* out, int cap);
 void register_all_fft();
 
 // LDS bytes of one block (lines or columns NL) for each kernel family
-size_t rows_lds(int N1, int N2, int NL, size_t csz);
-size_t cols_lds(int N1, int N2, int NL, size_t csz, bool stash);
-size_t ce_rows_lds(int N1, int N2, int NL, size_t csz);
+inline size_t rows_lds(const FftGeo& g, int NL, size_t csz) { return (size_t)NL * g.ROWS * csz; }
+inline size_t cols_lds(const FftGeo& g, int NL, size_t csz) { return (size_t)NL * g.EX * csz; }
+inline size_t ce_rows_lds(const FftGeo& g, int NL, size_t csz) { return (size_t)NL * imax(g.EX, g.F) * csz; }
 
 }  // namespace krig

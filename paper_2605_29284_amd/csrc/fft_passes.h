@@ -1,24 +1,29 @@
-// Two-level FFT pass kernels for the circulant-embedded convolution (Step 7) and
-// its adjoint.  Included by one generated translation unit per transform length.
+// FFT pass kernels for the circulant-embedded convolution (Step 7) and its adjoint,
+// and the circulant-embedding sampler.  Included by one generated translation unit
+// per transform length F = R1 * R2 * R3 (factorisation and register layouts: see
+// fft_args.h).
 //
 // Roles (TC/TF/TI = arithmetic precision, TS/TSI/TSO/TO = storage precision):
 //  k_rows_r2c   forward transform of real rows, two rows per complex line
 //               ("two-for-one"); sources: the CSR scatter of alpha_i w_im (Steps
-//               5-6), dense rows (the adjoint's input), or the even reflection of
-//               the lag quadrant (Step 2).  Writes frequency-major half spectra
-//               through an LDS transpose so stores are whole cache lines.
+//               5-6), dense rows (the adjoint's input), the even reflection of the
+//               lag quadrant (Step 2), or the covariance on the sampler's torus.
+//               Writes frequency-major half spectra through an LDS transpose so
+//               stores are whole cache lines.
 //  k_cols       column pass over frequency-major half spectra (contiguous
 //               columns): forward transform, product with the real filter
 //               spectrum, inverse transform, keep the requested rows; variants
 //               also accumulate sum_b G_b conj(C_b) (lag gradient), store the
-//               forward real part (filter set-up), or invert a sum of partial
-//               spectra.
+//               forward real part (filter set-up), invert a sum of partial
+//               spectra, or draw the sampler's noise.
 //  k_rows_c2r   inverse transform back to real rows, two rows per complex line,
-//               keeping the requested columns (optionally adding an image).
+//               keeping the requested columns (optionally adding an image); a
+//               folded form for the lag gradient.
+//  k_rows_ce    the sampler's complex row transforms.
 //
-// Thread layout in all kernels: lane s (fastest, the transform's thread index)
-// then line/column l; per-line LDS [l][n2][k1] with the n2 stride odd(N1) so the
-// stage-A writes of consecutive lanes hit distinct banks.
+// Thread layout in all kernels: lane s (fastest, the transform's thread index, NT
+// per line) then line/column l.  Every transform begins with a block barrier, since
+// a line may span two waves and reuses the LDS of the previous step.
 #pragma once
 #include "fft_args.h"
 #include "fft_reg.h"
@@ -27,11 +32,16 @@
 
 namespace krig {
 
-__host__ __device__ constexpr int odd_up(int x) { return x | 1; }
-__host__ __device__ constexpr int imax(int a, int b) { return a > b ? a : b; }
+template <int R1_, int R2_, int R3_> struct Geo {
+  static constexpr FftGeo g = fft_geo(R1_, R2_, R3_);
+  static constexpr int R1 = R1_, R2 = R2_, R3 = R3_;
+  static constexpr int F = g.F, M = g.M, NIN = g.NIN, TIN = g.TIN, NOUT = g.NOUT, TOUT = g.TOUT, T2 = g.T2;
+  static constexpr int NT = g.NT, ON2 = g.ON2, RS = g.RS, P1 = g.P1, EX = g.EX, ROWS = g.ROWS;
+  static constexpr bool THREE = R1_ > 1;
+};
 
-// Hide a value from the optimiser so address arithmetic and loads derived from it
-// stay inside a loop (keeps loop-invariant values out of registers).
+// Hide a value from the optimiser so address arithmetic derived from it stays
+// inside a loop (keeps loop-invariant values out of registers).
 template <typename P>
 __device__ __forceinline__ P opaque(P p) {
   asm volatile("" : "+s"(p));
@@ -42,13 +52,11 @@ __device__ __forceinline__ int opaque_v(int x) {
   return x;
 }
 
-template <int N1, int N2> struct Geo {
-  static constexpr int F = N1 * N2;
-  static constexpr int NT = imax(N1, N2);
-  static constexpr int ON1 = odd_up(N1);
-  static constexpr int EX = N2 * ON1;                     // exchange slots per line
-  static constexpr int ROWS = imax(EX, F + 2);            // row kernels: exchange or transpose
-};
+// a * tw (DIR < 0) or a * conj(tw) (DIR > 0)
+template <int DIR, typename T>
+__device__ __forceinline__ cx<T> twm(cx<T> a, cx<T> tw) {
+  return DIR < 0 ? cmul(a, tw) : cmulc(a, tw);
+}
 
 // LDS transposes [k][R] with the column rotated by k: lanes that differ in k (the
 // fast lane index on one side of the transpose) fall on distinct banks, and a row
@@ -62,51 +70,114 @@ __device__ __forceinline__ int window_dst(const Window& wd, int i) {
 }
 
 // ----------------------------------------------------------------------------------------
-// the two register stages of a transform on one line, exchanged through LDS region
-// L (stride ON1 between n2 rows).  On entry thread s < N2 holds v[n1] = x[N2 n1 + s];
-// on exit thread s < N1 holds w[k2] = X[s + N1 k2].  DIR = -1 forward, +1 inverse.
+// One transform per line, input layout -> output layout (DIR = -1 forward, +1
+// inverse, unnormalised).  L: the line's EX LDS slots; tw: exp(-2 pi i j / F), j < F.
+//  pass 1 (R1 > 1): thread m < M: DFT_R1 over j of x[m + M j], times W_F^(m k1),
+//                   to L[k1 P1 + m]
+//  pass 2: thread (k1, s), t = k1 R3 + s: DFT_R2 over n1 of z_k1[R3 n1 + s], times
+//          W_M^(s s'), to L[k1 RS + s ON2 + s']
+//  pass 3: thread (k1, s'), t = s' R1 + k1: DFT_R3 over s -> X[k1 + R1 s' + R1 R2 k2]
+//          = X[t + TOUT k2]
 // ----------------------------------------------------------------------------------------
-template <typename TC, int N1, int N2, int DIR>
-__device__ __forceinline__ void two_stage(cx<TC> (&v)[N1], cx<TC> (&w)[N2], int s, cx<TC>* L,
-                                          const cx<TC>* twF) {
-  using G = Geo<N1, N2>;
-  if (s < N2) {
-    DFT<N1, DIR, TC>::run(v);
+template <typename TC, int R1, int R2, int R3, int DIR>
+__device__ __forceinline__ void xf_fwd(cx<TC> (&v)[(Geo<R1, R2, R3>::NIN)], cx<TC> (&w)[R3], int t, cx<TC>* L,
+                                       const cx<TC>* tw) {
+  using G = Geo<R1, R2, R3>;
+  __syncthreads();
+  cx<TC> u[R2];
+  if constexpr (G::THREE) {
+    if (t < G::TIN) {
+      DFT<R1, DIR, TC>::run(v);
 #pragma unroll
-    for (int k1 = 0; k1 < N1; ++k1) {
-      cx<TC> t = v[k1];
-      if (k1 != 0 && s != 0) t = DIR < 0 ? cmul(t, twF[s * k1]) : cmulc(t, twF[s * k1]);
-      L[s * G::ON1 + k1] = t;
+      for (int k1 = 0; k1 < R1; ++k1) {
+        cx<TC> a = v[k1];
+        if (k1 != 0 && t != 0) a = twm<DIR>(a, tw[t * k1]);
+        L[k1 * G::P1 + t] = a;
+      }
+    }
+    __syncthreads();
+    if (t < G::T2) {
+      const int k1 = t / R3, s = t % R3;
+#pragma unroll
+      for (int n1 = 0; n1 < R2; ++n1) u[n1] = L[k1 * G::P1 + R3 * n1 + s];
+    }
+    __syncthreads();
+  } else {
+#pragma unroll
+    for (int n1 = 0; n1 < R2; ++n1) u[n1] = v[n1];
+  }
+  if (t < G::T2) {
+    const int k1 = t / R3, s = t % R3;
+    DFT<R2, DIR, TC>::run(u);
+    cx<TC>* Lk = L + k1 * G::RS;
+#pragma unroll
+    for (int q = 0; q < R2; ++q) {
+      cx<TC> a = u[q];
+      if (q != 0 && s != 0) a = twm<DIR>(a, tw[R1 * s * q]);
+      Lk[s * G::ON2 + q] = a;
     }
   }
   __syncthreads();
-  if (s < N1) {
+  if (t < G::TOUT) {
+    const int k1 = t % R1, sp = t / R1;
+    const cx<TC>* Lk = L + k1 * G::RS;
 #pragma unroll
-    for (int n2 = 0; n2 < N2; ++n2) w[n2] = L[n2 * G::ON1 + s];
-    DFT<N2, DIR, TC>::run(w);
+    for (int n2 = 0; n2 < R3; ++n2) w[n2] = Lk[n2 * G::ON2 + sp];
+    DFT<R3, DIR, TC>::run(w);
   }
 }
 
-// inverse from the transposed order left by two_stage (thread s = k1 holds k2 =
-// 0..N2-1); thread s < N2 ends with x[N2 n1 + s] in v[n1].
-template <typename TC, int N1, int N2>
-__device__ __forceinline__ void inv_from_t(cx<TC> (&w)[N2], int s, cx<TC>* L, const cx<TC>* twF,
-                                           cx<TC> (&v)[N1]) {
-  using G = Geo<N1, N2>;
-  if (s < N1) {
-    DFT<N2, 1, TC>::run(w);
+// Inverse transform from the output layout (thread t < TOUT holds X[t + TOUT k2])
+// back to the input layout (thread t < TIN ends with x[t + TIN j] in v[j]): the
+// passes of xf_fwd in reverse with conjugate twiddles.
+template <typename TC, int R1, int R2, int R3>
+__device__ __forceinline__ void xf_inv(cx<TC> (&w)[R3], int t, cx<TC>* L, const cx<TC>* tw,
+                                       cx<TC> (&v)[(Geo<R1, R2, R3>::NIN)]) {
+  using G = Geo<R1, R2, R3>;
+  __syncthreads();
+  if (t < G::TOUT) {
+    const int k1 = t % R1, sp = t / R1;
+    DFT<R3, 1, TC>::run(w);
+    cx<TC>* Lk = L + k1 * G::RS;
 #pragma unroll
-    for (int n2 = 0; n2 < N2; ++n2) {
-      cx<TC> t = w[n2];
-      if (n2 != 0 && s != 0) t = cmulc(t, twF[n2 * s]);
-      L[n2 * G::ON1 + s] = t;
+    for (int n2 = 0; n2 < R3; ++n2) {
+      cx<TC> a = w[n2];
+      if (n2 != 0 && sp != 0) a = cmulc(a, tw[R1 * n2 * sp]);
+      Lk[n2 * G::ON2 + sp] = a;
     }
   }
   __syncthreads();
-  if (s < N2) {
+  cx<TC> u[R2];
+  if (t < G::T2) {
+    const int k1 = t / R3, n2 = t % R3;
 #pragma unroll
-    for (int k1 = 0; k1 < N1; ++k1) v[k1] = L[s * G::ON1 + k1];
-    DFT<N1, 1, TC>::run(v);
+    for (int q = 0; q < R2; ++q) u[q] = L[k1 * G::RS + n2 * G::ON2 + q];
+  }
+  if constexpr (G::THREE) {
+    __syncthreads();
+    if (t < G::T2) {
+      const int k1 = t / R3, n2 = t % R3;
+      DFT<R2, 1, TC>::run(u);
+#pragma unroll
+      for (int n1 = 0; n1 < R2; ++n1) {
+        const int m = R3 * n1 + n2;
+        cx<TC> a = u[n1];
+        if (k1 != 0 && m != 0) a = cmulc(a, tw[m * k1]);
+        L[k1 * G::P1 + m] = a;
+      }
+    }
+    __syncthreads();
+    if (t < G::TIN) {
+#pragma unroll
+      for (int k1 = 0; k1 < R1; ++k1) v[k1] = L[k1 * G::P1 + t];
+      DFT<R1, 1, TC>::run(v);
+    }
+  } else {
+    if (t < G::T2) {
+      DFT<R2, 1, TC>::run(u);
+#pragma unroll
+      for (int n1 = 0; n1 < R2; ++n1) v[n1] = u[n1];
+    }
   }
 }
 
@@ -115,9 +186,9 @@ __device__ __forceinline__ void inv_from_t(cx<TC> (&w)[N2], int s, cx<TC>* L, co
 // ----------------------------------------------------------------------------------------
 enum { SRC_CSR = 0, SRC_DENSE = 1, SRC_LAG = 2, SRC_COV = 3 };
 
-template <typename TC, typename TIN, typename TS, int N1, int N2, int SRC>
+template <typename TC, typename TIN, typename TS, int R1, int R2, int R3, int SRC>
 __global__ void __launch_bounds__(256) k_rows_r2c(RowsR2CArgs a) {
-  using G = Geo<N1, N2>;
+  using G = Geo<R1, R2, R3>;
   extern __shared__ unsigned char smem_raw[];
   cx<TC>* lds = reinterpret_cast<cx<TC>*>(smem_raw);
   const int s = threadIdx.x % G::NT;
@@ -130,11 +201,11 @@ __global__ void __launch_bounds__(256) k_rows_r2c(RowsR2CArgs a) {
   const cx<TC>* twF = reinterpret_cast<const cx<TC>*>(a.twF);
   cx<TC>* L = lds + (size_t)l * G::ROWS;
 
-  cx<TC> v[N1];
-  if (s < N2) {
+  cx<TC> v[G::NIN];
+  if (s < G::TIN) {
 #pragma unroll
-    for (int n1 = 0; n1 < N1; ++n1) {
-      const int c = N2 * n1 + s;
+    for (int j = 0; j < G::NIN; ++j) {
+      const int c = G::TIN * j + s;
       TC xa = 0, xb = 0;
       if constexpr (SRC == SRC_CSR) {
         if (c < a.ncols) {
@@ -189,24 +260,24 @@ __global__ void __launch_bounds__(256) k_rows_r2c(RowsR2CArgs a) {
           }
         }
       }
-      v[n1] = mk<TC>(xa, xb);
+      v[j] = mk<TC>(xa, xb);
     }
   }
-  cx<TC> w[N2];
-  two_stage<TC, N1, N2, -1>(v, w, s, L, twF);
+  cx<TC> w[G::NOUT];
+  xf_fwd<TC, R1, R2, R3, -1>(v, w, s, L, twF);
   __syncthreads();
   // natural-order exchange to pair Z[k] with Z[F-k]
-  if (s < N1) {
+  if (s < G::TOUT) {
 #pragma unroll
-    for (int k2 = 0; k2 < N2; ++k2) L[s + N1 * k2] = w[k2];
+    for (int k2 = 0; k2 < G::NOUT; ++k2) L[s + G::TOUT * k2] = w[k2];
   }
   __syncthreads();
-  constexpr int NK = (G::F / 2 + N1) / N1;  // k2 values with k = s + N1 k2 <= F/2 for some s
+  constexpr int NK = (G::F / 2 + G::TOUT) / G::TOUT;  // k2 with k = s + TOUT k2 <= F/2 for some s
   cx<TC> xa[NK], xb[NK];
-  if (s < N1) {
+  if (s < G::TOUT) {
 #pragma unroll
     for (int k2 = 0; k2 < NK; ++k2) {
-      const int k = s + N1 * k2;
+      const int k = s + G::TOUT * k2;
       const cx<TC> z = w[k2];
       const cx<TC> zc = L[(G::F - k) % G::F];
       // Xa = (Z[k] + conj Z[F-k]) / 2,  Xb = (Z[k] - conj Z[F-k]) / (2 i)
@@ -217,150 +288,139 @@ __global__ void __launch_bounds__(256) k_rows_r2c(RowsR2CArgs a) {
   __syncthreads();
   // transpose through LDS: T[k][2l + {0,1}] over the block, then row-contiguous stores
   cx<TC>* T = lds;
-  const int R2 = 2 * NL;
-  if (s < N1) {
+  const int R2b = 2 * NL;
+  if (s < G::TOUT) {
 #pragma unroll
     for (int k2 = 0; k2 < NK; ++k2) {
-      const int k = s + N1 * k2;
+      const int k = s + G::TOUT * k2;
       if (k < a.H2) {
-        T[rot(k, 2 * l, R2)] = xa[k2];
-        T[rot(k, 2 * l + 1, R2)] = xb[k2];
+        T[rot(k, 2 * l, R2b)] = xa[k2];
+        T[rot(k, 2 * l + 1, R2b)] = xb[k2];
       }
     }
   }
   __syncthreads();
   cx<TS>* o = reinterpret_cast<cx<TS>*>(a.out) + (int64_t)b * a.out_fs;
-  for (int idx = threadIdx.x; idx < a.H2 * R2; idx += blockDim.x) {
-    const int rl = idx % R2, k = idx / R2;
+  for (int idx = threadIdx.x; idx < a.H2 * R2b; idx += blockDim.x) {
+    const int rl = idx % R2b, k = idx / R2b;
     const int row = row0 + rl;
-    if (row < a.nrows) o[(int64_t)k * a.out_ld + row] = ccast<TS>(T[rot(k, rl, R2)]);
+    if (row < a.nrows) o[(int64_t)k * a.out_ld + row] = ccast<TS>(T[rot(k, rl, R2b)]);
   }
 }
 
 // ----------------------------------------------------------------------------------------
 // column kernels (contiguous columns of frequency-major spectra)
 // ----------------------------------------------------------------------------------------
-template <typename TC, typename TS, int N1, int N2>
+template <typename TC, typename TS, int R1, int R2, int R3>
 __device__ __forceinline__ void col_fwd(const cx<TS>* src, int in_off, int in_cnt, bool colok, int s,
-                                        cx<TC>* L, const cx<TC>* twF, cx<TC> (&w)[N2]) {
-  cx<TC> v[N1];
-  if (s < N2) {
+                                        cx<TC>* L, const cx<TC>* twF, cx<TC> (&w)[R3]) {
+  using G = Geo<R1, R2, R3>;
+  cx<TC> v[G::NIN];
+  if (s < G::TIN) {
 #pragma unroll
-    for (int n1 = 0; n1 < N1; ++n1) {
-      const int r = N2 * n1 + s - in_off;
-      v[n1] = (colok && r >= 0 && r < in_cnt) ? ccast<TC>(src[r]) : mk<TC>(0, 0);
+    for (int j = 0; j < G::NIN; ++j) {
+      const int r = G::TIN * j + s - in_off;
+      v[j] = (colok && r >= 0 && r < in_cnt) ? ccast<TC>(src[r]) : mk<TC>(0, 0);
     }
   }
-  two_stage<TC, N1, N2, -1>(v, w, s, L, twF);
+  xf_fwd<TC, R1, R2, R3, -1>(v, w, s, L, twF);
 }
 
 enum { COL_CONV = 0, COL_CONV_DLAG = 1, COL_FWD_REAL = 2, COL_INV_SUM = 3, COL_CE = 4 };
 
-template <typename TF, typename TI, typename TSI, typename TSO, int N1, int N2, int MODE>
+template <typename TF, typename TI, typename TSI, typename TSO, int R1, int R2, int R3, int MODE>
 __global__ void __launch_bounds__(256) k_cols(ColsArgs a) {
-  using G = Geo<N1, N2>;
+  using G = Geo<R1, R2, R3>;
   using TC = TF;
   extern __shared__ unsigned char smem_raw[];
   const int NL = a.NL;
-  const int s0 = threadIdx.x % G::NT;
+  const int s = threadIdx.x % G::NT;
   const int l0 = threadIdx.x / G::NT;
-  const int col0 = blockIdx.x * NL + l0;
-  const bool colok = col0 < a.H2;
+  const int col = blockIdx.x * NL + l0;
+  const bool colok = col < a.H2;
   const cx<TC>* twF = reinterpret_cast<const cx<TC>*>(a.twF);
   cx<TC>* L = reinterpret_cast<cx<TC>*>(smem_raw) + (size_t)l0 * G::EX;
-  const int s = s0, col = col0;
 
   if constexpr (MODE == COL_CONV) {
     const int b = blockIdx.y;
     const cx<TSI>* src = reinterpret_cast<const cx<TSI>*>(a.in) + (int64_t)b * a.in_fs + (int64_t)col * a.in_ld;
-    cx<TI> wi[N2];
+    cx<TI> wi[R3];
     {
-      cx<TC> w[N2];
-      col_fwd<TC, TSI, N1, N2>(src, a.in_off, a.in_cnt, colok, s, L, twF, w);
-      if (s < N1 && colok) {
+      cx<TC> w[R3];
+      col_fwd<TC, TSI, R1, R2, R3>(src, a.in_off, a.in_cnt, colok, s, L, twF, w);
+      if (s < G::TOUT && colok) {
         const TF* f = reinterpret_cast<const TF*>(a.filt) + (int64_t)col * a.filt_ld;
 #pragma unroll
-        for (int k2 = 0; k2 < N2; ++k2) w[k2] = cscale(w[k2], f[s + N1 * k2]);
+        for (int k2 = 0; k2 < R3; ++k2) w[k2] = cscale(w[k2], f[s + G::TOUT * k2]);
       }
 #pragma unroll
-      for (int k2 = 0; k2 < N2; ++k2) wi[k2] = ccast<TI>(w[k2]);
+      for (int k2 = 0; k2 < R3; ++k2) wi[k2] = ccast<TI>(w[k2]);
     }
     cx<TI>* LI = reinterpret_cast<cx<TI>*>(smem_raw) + (size_t)l0 * G::EX;
-    cx<TI> v[N1];
-    inv_from_t<TI, N1, N2>(wi, s, LI, reinterpret_cast<const cx<TI>*>(a.twI), v);
-    if (s < N2 && colok) {
+    cx<TI> v[G::NIN];
+    xf_inv<TI, R1, R2, R3>(wi, s, LI, reinterpret_cast<const cx<TI>*>(a.twI), v);
+    if (s < G::TIN && colok) {
       cx<TSO>* dst = reinterpret_cast<cx<TSO>*>(a.out) + (int64_t)b * a.out_fs + (int64_t)col * a.out_ld;
 #pragma unroll
-      for (int n1 = 0; n1 < N1; ++n1) {
-        const int d = window_dst(a.rows, N2 * n1 + s);
-        if (d >= 0) dst[d] = ccast<TSO>(v[n1]);
+      for (int j = 0; j < G::NIN; ++j) {
+        const int d = window_dst(a.rows, G::TIN * j + s);
+        if (d >= 0) dst[d] = ccast<TSO>(v[j]);
       }
     }
   } else if constexpr (MODE == COL_CONV_DLAG) {
     // blockIdx.y = group of G fields; partial spectrum of the group -> part[group]
-    cx<TC> acc[N2];
+    cx<TC> acc[R3];
 #pragma unroll
-    for (int k2 = 0; k2 < N2; ++k2) acc[k2] = mk<TC>(0, 0);
-    cx<TC>* stash = reinterpret_cast<cx<TC>*>(smem_raw) + (size_t)NL * G::EX + (size_t)l0 * G::F;
+    for (int k2 = 0; k2 < R3; ++k2) acc[k2] = mk<TC>(0, 0);
     const int b0 = blockIdx.y * a.G;
+    const int s0 = s, col0 = col;
 #pragma unroll 1
     for (int gi = 0; gi < a.G; ++gi) {
       const int b = b0 + gi;
       if (b >= a.B) break;  // uniform across the block
-      twF = opaque(twF);
-      // fresh copies of the lane indices each iteration: keeps per-lane address
-      // arithmetic from being hoisted out of the field loop (register pressure)
+      // fresh copies of the lane indices each iteration: keeps per-lane addresses
+      // and twiddles from being hoisted out of the field loop
       const int s = opaque_v(s0), col = opaque_v(col0);
       const cx<TSI>* srcc =
           reinterpret_cast<const cx<TSI>*>(a.in2) + (int64_t)b * a.in2_fs + (int64_t)col * a.in2_ld;
       const cx<TSI>* srcg = reinterpret_cast<const cx<TSI>*>(a.in) + (int64_t)b * a.in_fs + (int64_t)col * a.in_ld;
-      __syncthreads();
-      {
-        // C-hat of this field: transform, then park it in this thread's stash slots
-        cx<TC> wc[N2];
-        col_fwd<TC, TSI, N1, N2>(srcc, a.in2_off, a.in2_cnt, colok, s, L, twF, wc);
-        if (s < N1) {
+      cx<TC> wc[R3], wg[R3];
+      col_fwd<TC, TSI, R1, R2, R3>(srcc, a.in2_off, a.in2_cnt, colok, s, L, twF, wc);  // C-hat
+      col_fwd<TC, TSI, R1, R2, R3>(srcg, a.in_off, a.in_cnt, colok, s, L, twF, wg);    // G-hat
+      if (s < G::TOUT && colok) {
+        const TF* f = reinterpret_cast<const TF*>(a.filt) + (int64_t)col * a.filt_ld;
 #pragma unroll
-          for (int k2 = 0; k2 < N2; ++k2) stash[k2 * N1 + s] = wc[k2];
+        for (int k2 = 0; k2 < R3; ++k2) {
+          acc[k2] = acc[k2] + cmulc(wg[k2], wc[k2]);
+          wg[k2] = cscale(wg[k2], f[s + G::TOUT * k2]);
         }
       }
-      __syncthreads();
-      cx<TC> wg[N2];
-      col_fwd<TC, TSI, N1, N2>(srcg, a.in_off, a.in_cnt, colok, s, L, twF, wg);
-      if (s < N1 && colok) {
-        const TF* f = opaque(reinterpret_cast<const TF*>(a.filt)) + (int64_t)col * a.filt_ld;
-#pragma unroll
-        for (int k2 = 0; k2 < N2; ++k2) {
-          acc[k2] = acc[k2] + cmulc(wg[k2], stash[k2 * N1 + s]);
-          wg[k2] = cscale(wg[k2], f[s + N1 * k2]);
-        }
-      }
-      cx<TC> v[N1];
-      inv_from_t<TC, N1, N2>(wg, s, L, twF, v);
-      if (s < N2 && colok) {
+      cx<TC> v[G::NIN];
+      xf_inv<TC, R1, R2, R3>(wg, s, L, twF, v);
+      if (s < G::TIN && colok) {
         cx<TSO>* dst = reinterpret_cast<cx<TSO>*>(a.out) + (int64_t)b * a.out_fs + (int64_t)col * a.out_ld;
 #pragma unroll
-        for (int n1 = 0; n1 < N1; ++n1) {
-          const int d = window_dst(a.rows, N2 * n1 + s);
-          if (d >= 0) dst[d] = ccast<TSO>(v[n1]);
+        for (int j = 0; j < G::NIN; ++j) {
+          const int d = window_dst(a.rows, G::TIN * j + s);
+          if (d >= 0) dst[d] = ccast<TSO>(v[j]);
         }
       }
     }
-    if (s < N1 && colok) {
+    if (s < G::TOUT && colok) {
       cx<TSO>* p = reinterpret_cast<cx<TSO>*>(a.part) + (int64_t)blockIdx.y * a.part_fs + (int64_t)col * a.part_ld;
 #pragma unroll
-      for (int k2 = 0; k2 < N2; ++k2) p[s + N1 * k2] = ccast<TSO>(acc[k2]);
+      for (int k2 = 0; k2 < R3; ++k2) p[s + G::TOUT * k2] = ccast<TSO>(acc[k2]);
     }
   } else if constexpr (MODE == COL_FWD_REAL) {
     // forward transform of the input columns; store Re(X) * scale (natural order)
     const int b = blockIdx.y;
     const cx<TSI>* src = reinterpret_cast<const cx<TSI>*>(a.in) + (int64_t)b * a.in_fs + (int64_t)col * a.in_ld;
-    cx<TC> w[N2];
-    col_fwd<TC, TSI, N1, N2>(src, a.in_off, a.in_cnt, colok, s, L, twF, w);
-    if (s < N1 && colok) {
+    cx<TC> w[R3];
+    col_fwd<TC, TSI, R1, R2, R3>(src, a.in_off, a.in_cnt, colok, s, L, twF, w);
+    if (s < G::TOUT && colok) {
       TSO* dst = reinterpret_cast<TSO*>(a.out) + (int64_t)b * a.out_fs + (int64_t)col * a.out_ld;
 #pragma unroll
-      for (int k2 = 0; k2 < N2; ++k2) dst[s + N1 * k2] = (TSO)(w[k2].x * (TC)a.scale);
+      for (int k2 = 0; k2 < R3; ++k2) dst[s + G::TOUT * k2] = (TSO)(w[k2].x * (TC)a.scale);
     }
   } else if constexpr (MODE == COL_CE) {
     // sampler pass 1: column k2 (all ncol_full frequencies) of sqrt(Lambda/N) (xi1 + i xi2),
@@ -369,11 +429,11 @@ __global__ void __launch_bounds__(256) k_cols(ColsArgs a) {
     const int pair = a.pair0 + blockIdx.y;
     const int kk2 = col < a.ncol_full - col ? col : a.ncol_full - col;  // Lambda is even
     const double* lam = reinterpret_cast<const double*>(a.filt) + (int64_t)kk2 * a.filt_ld;
-    cx<TC> v[N1];
-    if (s < N2) {
+    cx<TC> v[G::NIN];
+    if (s < G::TIN) {
 #pragma unroll
-      for (int n1 = 0; n1 < N1; ++n1) {
-        const int k1 = N2 * n1 + s;
+      for (int j = 0; j < G::NIN; ++j) {
+        const int k1 = G::TIN * j + s;
         cx<TC> z = mk<TC>(0, 0);
         if (colok) {
           u32x4 cn;
@@ -387,40 +447,40 @@ __global__ void __launch_bounds__(256) k_cols(ColsArgs a) {
           const double sl = lam[k1];
           z = mk<TC>((TC)(sl * x0), (TC)(sl * x1));
         }
-        v[n1] = z;
+        v[j] = z;
       }
     }
-    cx<TC> w[N2];
-    two_stage<TC, N1, N2, -1>(v, w, s, L, twF);
-    if (s < N1 && colok) {
+    cx<TC> w[R3];
+    xf_fwd<TC, R1, R2, R3, -1>(v, w, s, L, twF);
+    if (s < G::TOUT && colok) {
       cx<TSO>* dst = reinterpret_cast<cx<TSO>*>(a.out) + (int64_t)blockIdx.y * a.out_fs + (int64_t)col * a.out_ld;
 #pragma unroll
-      for (int k2 = 0; k2 < N2; ++k2) {
-        const int d = window_dst(a.rows, s + N1 * k2);
+      for (int k2 = 0; k2 < R3; ++k2) {
+        const int d = window_dst(a.rows, s + G::TOUT * k2);
         if (d >= 0) dst[d] = ccast<TSO>(w[k2]);
       }
     }
   } else {  // COL_INV_SUM: inverse transform of sum_g part[g] (natural order), keep rows
     const cx<TSI>* p = reinterpret_cast<const cx<TSI>*>(a.in) + (int64_t)col * a.in_ld;
-    cx<TC> v[N1];
+    cx<TC> v[G::NIN];
 #pragma unroll
-    for (int n1 = 0; n1 < N1; ++n1) v[n1] = mk<TC>(0, 0);
-    if (s < N2 && colok) {
-      // partial g outermost: each round issues the N1 loads of one partial together;
+    for (int j = 0; j < G::NIN; ++j) v[j] = mk<TC>(0, 0);
+    if (s < G::TIN && colok) {
+      // partial g outermost: each round issues the NIN loads of one partial together;
       // every element is still summed in the order g = 0, 1, ...
       for (int g = 0; g < a.G; ++g) {
         const cx<TSI>* pg = p + (int64_t)g * a.in_fs + s;
 #pragma unroll
-        for (int n1 = 0; n1 < N1; ++n1) v[n1] = v[n1] + ccast<TC>(pg[N2 * n1]);
+        for (int j = 0; j < G::NIN; ++j) v[j] = v[j] + ccast<TC>(pg[G::TIN * j]);
       }
     }
-    cx<TC> w[N2];
-    two_stage<TC, N1, N2, 1>(v, w, s, L, twF);
-    if (s < N1 && colok) {
+    cx<TC> w[R3];
+    xf_fwd<TC, R1, R2, R3, 1>(v, w, s, L, twF);
+    if (s < G::TOUT && colok) {
       cx<TSO>* dst = reinterpret_cast<cx<TSO>*>(a.out) + (int64_t)col * a.out_ld;
 #pragma unroll
-      for (int k2 = 0; k2 < N2; ++k2) {
-        const int d = window_dst(a.rows, s + N1 * k2);
+      for (int k2 = 0; k2 < R3; ++k2) {
+        const int d = window_dst(a.rows, s + G::TOUT * k2);
         if (d >= 0) dst[d] = ccast<TSO>(w[k2]);
       }
     }
@@ -430,9 +490,29 @@ __global__ void __launch_bounds__(256) k_cols(ColsArgs a) {
 // ----------------------------------------------------------------------------------------
 // row kernel: inverse (frequency-major half spectra -> real rows), two rows per line
 // ----------------------------------------------------------------------------------------
-template <typename TC, typename TS, typename TO, int N1, int N2>
+// Loads the block's rows (transposed through LDS) and forms line l's complex input
+// Xa + i Xb from the half spectra (conjugate symmetry for k > F/2).
+template <typename TC, int R1, int R2, int R3>
+__device__ __forceinline__ void c2r_line_input(const cx<TC>* T, int R2b, int l, int s, int H2,
+                                               cx<TC> (&v)[(Geo<R1, R2, R3>::NIN)]) {
+  using G = Geo<R1, R2, R3>;
+  if (s < G::TIN) {
+#pragma unroll
+    for (int j = 0; j < G::NIN; ++j) {
+      const int k = G::TIN * j + s;
+      const bool lo = k < H2;
+      const int kk = lo ? k : G::F - k;
+      cx<TC> xa = T[rot(kk, 2 * l, R2b)], xb = T[rot(kk, 2 * l + 1, R2b)];
+      if (kk == 0 || 2 * kk == G::F) { xa.y = 0; xb.y = 0; }  // DC / Nyquist are real
+      if (!lo) { xa.y = -xa.y; xb.y = -xb.y; }
+      v[j] = mk<TC>(xa.x - xb.y, xa.y + xb.x);  // Xa + i Xb
+    }
+  }
+}
+
+template <typename TC, typename TS, typename TO, int R1, int R2, int R3>
 __global__ void __launch_bounds__(256) k_rows_c2r(RowsC2RArgs a) {
-  using G = Geo<N1, N2>;
+  using G = Geo<R1, R2, R3>;
   extern __shared__ unsigned char smem_raw[];
   cx<TC>* lds = reinterpret_cast<cx<TC>*>(smem_raw);
   const int s = threadIdx.x % G::NT;
@@ -444,39 +524,27 @@ __global__ void __launch_bounds__(256) k_rows_c2r(RowsC2RArgs a) {
   const bool oka = ra < a.nrows, okb = rb < a.nrows;
   const cx<TC>* twF = reinterpret_cast<const cx<TC>*>(a.twF);
   // row-contiguous loads of the block's 2 NL rows into T[k][rl]
-  const int R2 = 2 * NL;
+  const int R2b = 2 * NL;
   cx<TC>* T = lds;
   const cx<TS>* in = reinterpret_cast<const cx<TS>*>(a.in) + (int64_t)b * a.in_fs;
-  for (int idx = threadIdx.x; idx < a.H2 * R2; idx += blockDim.x) {
-    const int rl = idx % R2, k = idx / R2;
+  for (int idx = threadIdx.x; idx < a.H2 * R2b; idx += blockDim.x) {
+    const int rl = idx % R2b, k = idx / R2b;
     const int row = row0 + rl;
-    T[rot(k, rl, R2)] = row < a.nrows ? ccast<TC>(in[(int64_t)k * a.in_ld + row]) : mk<TC>(0, 0);
+    T[rot(k, rl, R2b)] = row < a.nrows ? ccast<TC>(in[(int64_t)k * a.in_ld + row]) : mk<TC>(0, 0);
   }
   __syncthreads();
-  cx<TC> v[N1];
-  if (s < N2) {
-#pragma unroll
-    for (int n1 = 0; n1 < N1; ++n1) {
-      const int k = N2 * n1 + s;
-      const bool lo = k < a.H2;
-      const int kk = lo ? k : G::F - k;
-      cx<TC> xa = T[rot(kk, 2 * l, R2)], xb = T[rot(kk, 2 * l + 1, R2)];
-      if (kk == 0 || 2 * kk == G::F) { xa.y = 0; xb.y = 0; }  // DC / Nyquist are real
-      if (!lo) { xa.y = -xa.y; xb.y = -xb.y; }
-      v[n1] = mk<TC>(xa.x - xb.y, xa.y + xb.x);  // Xa + i Xb
-    }
-  }
-  __syncthreads();
+  cx<TC> v[G::NIN];
+  c2r_line_input<TC, R1, R2, R3>(T, R2b, l, s, a.H2, v);
   cx<TC>* L = lds + (size_t)l * G::ROWS;
-  cx<TC> w[N2];
-  two_stage<TC, N1, N2, 1>(v, w, s, L, twF);
-  if (s < N1) {
+  cx<TC> w[R3];
+  xf_fwd<TC, R1, R2, R3, 1>(v, w, s, L, twF);
+  if (s < G::TOUT) {
     TO* oa = reinterpret_cast<TO*>(a.out) + (int64_t)b * a.out_fs + (int64_t)ra * a.ldo;
     TO* ob = oa + a.ldo;
     const TO* ad = reinterpret_cast<const TO*>(a.add);
 #pragma unroll
-    for (int k2 = 0; k2 < N2; ++k2) {
-      const int c = s + N1 * k2;
+    for (int k2 = 0; k2 < R3; ++k2) {
+      const int c = s + G::TOUT * k2;
       const int d = window_dst(a.cols, c);
       if (d >= 0) {
         TO va = (TO)w[k2].x, vb = (TO)w[k2].y;
@@ -501,9 +569,9 @@ __global__ void __launch_bounds__(256) k_rows_c2r(RowsC2RArgs a) {
 // input spectra (the row transform is linear), the column fold on the transformed
 // line in LDS.
 // ----------------------------------------------------------------------------------------
-template <typename TC, typename TO, int N1, int N2>
+template <typename TC, typename TO, int R1, int R2, int R3>
 __global__ void __launch_bounds__(256) k_rows_c2r_fold(RowsC2RArgs a) {
-  using G = Geo<N1, N2>;
+  using G = Geo<R1, R2, R3>;
   extern __shared__ unsigned char smem_raw[];
   cx<TC>* lds = reinterpret_cast<cx<TC>*>(smem_raw);
   const int s = threadIdx.x % G::NT;
@@ -513,41 +581,29 @@ __global__ void __launch_bounds__(256) k_rows_c2r_fold(RowsC2RArgs a) {
   const int row0 = 2 * blockIdx.x * NL;
   const int ra = row0 + 2 * l, rb = ra + 1;
   const cx<TC>* twF = reinterpret_cast<const cx<TC>*>(a.twF);
-  const int R2 = 2 * NL;
+  const int R2b = 2 * NL;
   cx<TC>* T = lds;
   const cx<TC>* in = reinterpret_cast<const cx<TC>*>(a.in);
-  for (int idx = threadIdx.x; idx < a.H2 * R2; idx += blockDim.x) {
-    const int rl = idx % R2, k = idx / R2;
+  for (int idx = threadIdx.x; idx < a.H2 * R2b; idx += blockDim.x) {
+    const int rl = idx % R2b, k = idx / R2b;
     const int u = row0 + rl;
     cx<TC> t = mk<TC>(0, 0);
     if (u < n1l) {
       t = in[(int64_t)k * a.in_ld + u];
       if (u > 0) t = t + in[(int64_t)k * a.in_ld + 2 * n1l - 1 - u];
     }
-    T[rot(k, rl, R2)] = t;
+    T[rot(k, rl, R2b)] = t;
   }
   __syncthreads();
-  cx<TC> v[N1];
-  if (s < N2) {
-#pragma unroll
-    for (int n1 = 0; n1 < N1; ++n1) {
-      const int k = N2 * n1 + s;
-      const bool lo = k < a.H2;
-      const int kk = lo ? k : G::F - k;
-      cx<TC> xa = T[rot(kk, 2 * l, R2)], xb = T[rot(kk, 2 * l + 1, R2)];
-      if (kk == 0 || 2 * kk == G::F) { xa.y = 0; xb.y = 0; }  // DC / Nyquist are real
-      if (!lo) { xa.y = -xa.y; xb.y = -xb.y; }
-      v[n1] = mk<TC>(xa.x - xb.y, xa.y + xb.x);  // Xa + i Xb
-    }
-  }
-  __syncthreads();
+  cx<TC> v[G::NIN];
+  c2r_line_input<TC, R1, R2, R3>(T, R2b, l, s, a.H2, v);
   cx<TC>* L = lds + (size_t)l * G::ROWS;
-  cx<TC> w[N2];
-  two_stage<TC, N1, N2, 1>(v, w, s, L, twF);
+  cx<TC> w[R3];
+  xf_fwd<TC, R1, R2, R3, 1>(v, w, s, L, twF);
   __syncthreads();
-  if (s < N1) {
+  if (s < G::TOUT) {
 #pragma unroll
-    for (int k2 = 0; k2 < N2; ++k2) L[s + N1 * k2] = w[k2];  // natural column order
+    for (int k2 = 0; k2 < R3; ++k2) L[s + G::TOUT * k2] = w[k2];  // natural column order
   }
   __syncthreads();
   TO* oa = reinterpret_cast<TO*>(a.out) + (int64_t)ra * a.ldo;
@@ -565,9 +621,9 @@ __global__ void __launch_bounds__(256) k_rows_c2r_fold(RowsC2RArgs a) {
 // sampler pass 2: complex forward transform of torus rows r < nrows (frequency-major
 // input), keep columns < keep; real part -> realisation 2 pair, imaginary -> 2 pair + 1
 // ----------------------------------------------------------------------------------------
-template <typename TC, typename TS, typename TO, int N1, int N2>
+template <typename TC, typename TS, typename TO, int R1, int R2, int R3>
 __global__ void __launch_bounds__(256) k_rows_ce(RowsCEArgs a) {
-  using G = Geo<N1, N2>;
+  using G = Geo<R1, R2, R3>;
   extern __shared__ unsigned char smem_raw[];
   cx<TC>* lds = reinterpret_cast<cx<TC>*>(smem_raw);
   const int s = threadIdx.x % G::NT;
@@ -585,22 +641,21 @@ __global__ void __launch_bounds__(256) k_rows_ce(RowsCEArgs a) {
     T[rot(k, rl, NL)] = r < a.nrows ? ccast<TC>(in[(int64_t)k * a.in_ld + r]) : mk<TC>(0, 0);
   }
   __syncthreads();
-  cx<TC> v[N1];
-  if (s < N2) {
+  cx<TC> v[G::NIN];
+  if (s < G::TIN) {
 #pragma unroll
-    for (int n1 = 0; n1 < N1; ++n1) v[n1] = T[rot(N2 * n1 + s, l, NL)];
+    for (int j = 0; j < G::NIN; ++j) v[j] = T[rot(G::TIN * j + s, l, NL)];
   }
-  __syncthreads();
   cx<TC>* L = lds + (size_t)l * G::EX;
-  cx<TC> w[N2];
-  two_stage<TC, N1, N2, -1>(v, w, s, L, twF);
-  if (s < N1 && row < a.nrows) {
+  cx<TC> w[R3];
+  xf_fwd<TC, R1, R2, R3, -1>(v, w, s, L, twF);
+  if (s < G::TOUT && row < a.nrows) {
     const int re = 2 * pair, im = 2 * pair + 1;
     TO* o1 = reinterpret_cast<TO*>(a.out) + (int64_t)re * a.out_fs + (int64_t)row * a.ldo;
     TO* o2 = reinterpret_cast<TO*>(a.out) + (int64_t)im * a.out_fs + (int64_t)row * a.ldo;
 #pragma unroll
-    for (int k2 = 0; k2 < N2; ++k2) {
-      const int c = s + N1 * k2;
+    for (int k2 = 0; k2 < R3; ++k2) {
+      const int c = s + G::TOUT * k2;
       if (c < a.keep) {
         if (re < a.R) o1[c] = (TO)w[k2].x;
         if (im < a.R) o2[c] = (TO)w[k2].y;
@@ -612,86 +667,90 @@ __global__ void __launch_bounds__(256) k_rows_ce(RowsCEArgs a) {
 // ----------------------------------------------------------------------------------------
 // launchers
 // ----------------------------------------------------------------------------------------
-template <typename TC, typename TIN, typename TS, int N1, int N2, int SRC>
+template <typename TC, typename TIN, typename TS, int R1, int R2, int R3, int SRC>
 hipError_t launch_rows_r2c(const RowsR2CArgs& a, int B, hipStream_t st) {
+  using G = Geo<R1, R2, R3>;
   const int npairs = (a.nrows + 1) / 2;
   dim3 grid((npairs + a.NL - 1) / a.NL, B);
-  dim3 block(Geo<N1, N2>::NT * a.NL);
-  const size_t sh = rows_lds(N1, N2, a.NL, sizeof(cx<TC>));
-  k_rows_r2c<TC, TIN, TS, N1, N2, SRC><<<grid, block, sh, st>>>(a);
+  dim3 block(G::NT * a.NL);
+  const size_t sh = rows_lds(G::g, a.NL, sizeof(cx<TC>));
+  k_rows_r2c<TC, TIN, TS, R1, R2, R3, SRC><<<grid, block, sh, st>>>(a);
   return hipGetLastError();
 }
 
-template <typename TF, typename TI, typename TSI, typename TSO, int N1, int N2, int MODE>
+template <typename TF, typename TI, typename TSI, typename TSO, int R1, int R2, int R3, int MODE>
 hipError_t launch_cols(const ColsArgs& a, int nblk_y, hipStream_t st) {
+  using G = Geo<R1, R2, R3>;
   dim3 grid((a.H2 + a.NL - 1) / a.NL, nblk_y);
-  dim3 block(Geo<N1, N2>::NT * a.NL);
-  const size_t sh = cols_lds(N1, N2, a.NL, sizeof(cx<TF>), MODE == COL_CONV_DLAG);
-  k_cols<TF, TI, TSI, TSO, N1, N2, MODE><<<grid, block, sh, st>>>(a);
+  dim3 block(G::NT * a.NL);
+  const size_t sh = cols_lds(G::g, a.NL, sizeof(cx<TF>));
+  k_cols<TF, TI, TSI, TSO, R1, R2, R3, MODE><<<grid, block, sh, st>>>(a);
   return hipGetLastError();
 }
 
-template <typename TC, typename TS, typename TO, int N1, int N2>
+template <typename TC, typename TS, typename TO, int R1, int R2, int R3>
 hipError_t launch_rows_c2r(const RowsC2RArgs& a, int B, hipStream_t st) {
+  using G = Geo<R1, R2, R3>;
   const int npairs = (a.nrows + 1) / 2;
   dim3 grid((npairs + a.NL - 1) / a.NL, B);
-  dim3 block(Geo<N1, N2>::NT * a.NL);
-  const size_t sh = rows_lds(N1, N2, a.NL, sizeof(cx<TC>));
-  k_rows_c2r<TC, TS, TO, N1, N2><<<grid, block, sh, st>>>(a);
+  dim3 block(G::NT * a.NL);
+  const size_t sh = rows_lds(G::g, a.NL, sizeof(cx<TC>));
+  k_rows_c2r<TC, TS, TO, R1, R2, R3><<<grid, block, sh, st>>>(a);
   return hipGetLastError();
 }
 
-template <typename TC, typename TO, int N1, int N2>
+template <typename TC, typename TO, int R1, int R2, int R3>
 hipError_t launch_rows_c2r_fold(const RowsC2RArgs& a, int B, hipStream_t st) {
+  using G = Geo<R1, R2, R3>;
   const int npairs = (a.nrows + 1) / 2;
   dim3 grid((npairs + a.NL - 1) / a.NL, 1);
-  dim3 block(Geo<N1, N2>::NT * a.NL);
-  const size_t sh = rows_lds(N1, N2, a.NL, sizeof(cx<TC>));
+  dim3 block(G::NT * a.NL);
+  const size_t sh = rows_lds(G::g, a.NL, sizeof(cx<TC>));
   (void)B;
-  k_rows_c2r_fold<TC, TO, N1, N2><<<grid, block, sh, st>>>(a);
+  k_rows_c2r_fold<TC, TO, R1, R2, R3><<<grid, block, sh, st>>>(a);
   return hipGetLastError();
 }
 
-template <typename TC, typename TS, typename TO, int N1, int N2>
+template <typename TC, typename TS, typename TO, int R1, int R2, int R3>
 hipError_t launch_rows_ce(const RowsCEArgs& a, int npairs, hipStream_t st) {
+  using G = Geo<R1, R2, R3>;
   dim3 grid((a.nrows + a.NL - 1) / a.NL, npairs);
-  dim3 block(Geo<N1, N2>::NT * a.NL);
-  const size_t sh = ce_rows_lds(N1, N2, a.NL, sizeof(cx<TC>));
-  k_rows_ce<TC, TS, TO, N1, N2><<<grid, block, sh, st>>>(a);
+  dim3 block(G::NT * a.NL);
+  const size_t sh = ce_rows_lds(G::g, a.NL, sizeof(cx<TC>));
+  k_rows_ce<TC, TS, TO, R1, R2, R3><<<grid, block, sh, st>>>(a);
   return hipGetLastError();
 }
 
-template <int N1, int N2>
+template <int R1, int R2, int R3>
 FftEntry make_fft_entry() {
   FftEntry e;
-  e.F = N1 * N2;
-  e.N1 = N1;
-  e.N2 = N2;
+  e.F = R1 * R2 * R3;
+  e.geo = fft_geo(R1, R2, R3);
   FftSet& k = e.k;
-  k.r2c_csr = launch_rows_r2c<double, double, double, N1, N2, SRC_CSR>;
-  k.r2c_dense_f32 = launch_rows_r2c<double, float, double, N1, N2, SRC_DENSE>;
-  k.r2c_dense_f64 = launch_rows_r2c<double, double, double, N1, N2, SRC_DENSE>;
-  k.r2c_lag = launch_rows_r2c<double, double, double, N1, N2, SRC_LAG>;
-  k.conv_mixed = launch_cols<double, float, double, float, N1, N2, COL_CONV>;
-  k.conv64 = launch_cols<double, double, double, double, N1, N2, COL_CONV>;
-  k.conv_dlag64 = launch_cols<double, double, double, double, N1, N2, COL_CONV_DLAG>;
-  k.fwd_real64 = launch_cols<double, double, double, double, N1, N2, COL_FWD_REAL>;
-  k.inv_sum64 = launch_cols<double, double, double, double, N1, N2, COL_INV_SUM>;
-  k.c2r32 = launch_rows_c2r<float, float, float, N1, N2>;
-  k.c2r64 = launch_rows_c2r<double, double, double, N1, N2>;
-  k.c2r_fold32 = launch_rows_c2r_fold<double, float, N1, N2>;
-  k.c2r_fold64 = launch_rows_c2r_fold<double, double, N1, N2>;
-  k.r2c_cov = launch_rows_r2c<double, double, double, N1, N2, SRC_COV>;
-  k.ce_cols32 = launch_cols<float, float, float, float, N1, N2, COL_CE>;
-  k.ce_cols64 = launch_cols<double, double, double, double, N1, N2, COL_CE>;
-  k.ce_rows32 = launch_rows_ce<float, float, float, N1, N2>;
-  k.ce_rows64 = launch_rows_ce<double, double, double, N1, N2>;
+  k.r2c_csr = launch_rows_r2c<double, double, double, R1, R2, R3, SRC_CSR>;
+  k.r2c_dense_f32 = launch_rows_r2c<double, float, double, R1, R2, R3, SRC_DENSE>;
+  k.r2c_dense_f64 = launch_rows_r2c<double, double, double, R1, R2, R3, SRC_DENSE>;
+  k.r2c_lag = launch_rows_r2c<double, double, double, R1, R2, R3, SRC_LAG>;
+  k.conv_mixed = launch_cols<double, float, double, float, R1, R2, R3, COL_CONV>;
+  k.conv64 = launch_cols<double, double, double, double, R1, R2, R3, COL_CONV>;
+  k.conv_dlag64 = launch_cols<double, double, double, double, R1, R2, R3, COL_CONV_DLAG>;
+  k.fwd_real64 = launch_cols<double, double, double, double, R1, R2, R3, COL_FWD_REAL>;
+  k.inv_sum64 = launch_cols<double, double, double, double, R1, R2, R3, COL_INV_SUM>;
+  k.c2r32 = launch_rows_c2r<float, float, float, R1, R2, R3>;
+  k.c2r64 = launch_rows_c2r<double, double, double, R1, R2, R3>;
+  k.c2r_fold32 = launch_rows_c2r_fold<double, float, R1, R2, R3>;
+  k.c2r_fold64 = launch_rows_c2r_fold<double, double, R1, R2, R3>;
+  k.r2c_cov = launch_rows_r2c<double, double, double, R1, R2, R3, SRC_COV>;
+  k.ce_cols32 = launch_cols<float, float, float, float, R1, R2, R3, COL_CE>;
+  k.ce_cols64 = launch_cols<double, double, double, double, R1, R2, R3, COL_CE>;
+  k.ce_rows32 = launch_rows_ce<float, float, float, R1, R2, R3>;
+  k.ce_rows64 = launch_rows_ce<double, double, double, R1, R2, R3>;
   return e;
 }
 
 }  // namespace krig
 
-#define KRIG_FFT_SIZE(N1, N2)                                                 \
-  namespace krig {                                                            \
-  void register_fft_##N1##x##N2() { register_fft(make_fft_entry<N1, N2>()); } \
+#define KRIG_FFT_SIZE(R1, R2, R3)                                                               \
+  namespace krig {                                                                              \
+  void register_fft_##R1##x##R2##x##R3() { register_fft(make_fft_entry<R1, R2, R3>()); }        \
   }

@@ -6,7 +6,7 @@
 
 namespace krig {
 
-#define KRIG_DECL(a, b) void register_fft_##a##x##b();
+#define KRIG_DECL(a, b, c) void register_fft_##a##x##b##x##c();
 KRIG_FFT_SIZES(KRIG_DECL)
 #undef KRIG_DECL
 
@@ -19,7 +19,7 @@ void register_fft(const FftEntry& e) { table().push_back(e); }
 
 void register_all_fft() {
   if (!table().empty()) return;
-#define KRIG_CALL(a, b) register_fft_##a##x##b();
+#define KRIG_CALL(a, b, c) register_fft_##a##x##b##x##c();
   KRIG_FFT_SIZES(KRIG_CALL)
 #undef KRIG_CALL
 }
@@ -42,21 +42,5 @@ int fft_sizes(int* out, int cap) {
 }  // namespace krig
 
 namespace krig {
-
-size_t rows_lds(int N1, int N2, int NL, size_t csz) {
-  const size_t ex = (size_t)N2 * (N1 | 1), tr = (size_t)N1 * N2 + 2;
-  return (size_t)NL * (ex > tr ? ex : tr) * csz;
-}
-
-size_t ce_rows_lds(int N1, int N2, int NL, size_t csz) {
-  const size_t ex = (size_t)N2 * (N1 | 1), tr = (size_t)N1 * N2;
-  return (size_t)NL * (ex > tr ? ex : tr) * csz;
-}
-
-size_t cols_lds(int N1, int N2, int NL, size_t csz, bool stash) {
-  size_t e = (size_t)NL * N2 * (N1 | 1);
-  if (stash) e += (size_t)NL * N1 * N2;
-  return e * csz;
-}
 
 }  // namespace krig

@@ -193,18 +193,18 @@ int pick_fft(int need) {
   return best;
 }
 
-int nt_of(const FftEntry* e) { return std::max(e->N1, e->N2); }
+int nt_of(const FftEntry* e) { return e->geo.NT; }
 
 // largest lines (row kernels) / columns (column kernels) per block with at most 256
 // threads and 64 KB of LDS
 int nl_rows_for(const FftEntry* e, size_t csz) {
   int nl = std::max(1, 256 / nt_of(e));
-  while (nl > 1 && rows_lds(e->N1, e->N2, nl, csz) > 64 * 1024) --nl;
+  while (nl > 1 && rows_lds(e->geo, nl, csz) > 64 * 1024) --nl;
   return nl;
 }
-int nl_cols_for(const FftEntry* e, size_t csz, bool stash) {
+int nl_cols_for(const FftEntry* e, size_t csz) {
   int nl = std::max(1, 256 / nt_of(e));
-  while (nl > 1 && cols_lds(e->N1, e->N2, nl, csz, stash) > 64 * 1024) --nl;
+  while (nl > 1 && cols_lds(e->geo, nl, csz) > 64 * 1024) --nl;
   return nl;
 }
 int pitch16(int rows) { return (rows + 15) / 16 * 16; }
@@ -261,7 +261,7 @@ int make_filter(krig_plan p, const double* lag64, double* filt_out) {
   c.twF = p->tw1_64;
   c.twI = p->tw1_64;
   c.scale = 1.0 / ((double)p->F1 * (double)p->F2);
-  c.NL = nl_cols_for(p->e1, 16, false);
+  c.NL = nl_cols_for(p->e1, 16);
   KRIG_TRY(p->e1->k.fwd_real64(c, 1, p->st));
   return KRIG_OK;
 }
@@ -419,7 +419,7 @@ void destroy_all(krig_plan p) {
 
 int nl_ce_rows_for(const FftEntry* e, size_t csz) {
   int nl = std::max(1, 256 / nt_of(e));
-  while (nl > 1 && ce_rows_lds(e->N1, e->N2, nl, csz) > 64 * 1024) --nl;
+  while (nl > 1 && ce_rows_lds(e->geo, nl, csz) > 64 * 1024) --nl;
   return nl;
 }
 
@@ -435,8 +435,8 @@ int ce_setup(krig_plan p) {
   for (;;) {
     const FftEntry* e1 = find_fft(f1);
     const FftEntry* e2 = find_fft(f2);
-    if (rows_lds(e2->N1, e2->N2, nl_rows_for(e2, 16), 16) > 64 * 1024 ||
-        cols_lds(e1->N1, e1->N2, nl_cols_for(e1, 16, false), 16, false) > 64 * 1024)
+    if (rows_lds(e2->geo, nl_rows_for(e2, 16), 16) > 64 * 1024 ||
+        cols_lds(e1->geo, nl_cols_for(e1, 16), 16) > 64 * 1024)
       return KRIG_EUNSUPPORTED;
     const int h2 = f2 / 2 + 1;
     double* lam = nullptr;
@@ -473,7 +473,7 @@ int ce_setup(krig_plan p) {
     c.twF = t1_64;
     c.twI = t1_64;
     c.scale = 1.0;
-    c.NL = nl_cols_for(e1, 16, false);
+    c.NL = nl_cols_for(e1, 16);
     KRIG_TRY(e1->k.fwd_real64(c, 1, p->st));
     const int nb = 256;
     double* bm = nullptr;
@@ -590,10 +590,9 @@ int krig_plan_create(krig_plan* out, const krig_grid* g, const krig_matern* k, i
   // launch shapes (lines per block) within 256 threads and 64 KB of LDS
   p->nl_rows64 = nl_rows_for(p->e2, 16);
   p->nl_rows32 = nl_rows_for(p->e2, 8);
-  p->nl_cols64 = nl_cols_for(p->e1, 16, false);
-  p->nl_cols_dlag = nl_cols_for(p->e1, 16, true);
-  if (rows_lds(p->e2->N1, p->e2->N2, p->nl_rows64, 16) > 64 * 1024 ||
-      cols_lds(p->e1->N1, p->e1->N2, p->nl_cols_dlag, 16, true) > 64 * 1024) {
+  p->nl_cols64 = nl_cols_for(p->e1, 16);
+  p->nl_cols_dlag = p->nl_cols64;
+  if (rows_lds(p->e2->geo, p->nl_rows64, 16) > 64 * 1024 || cols_lds(p->e1->geo, p->nl_cols64, 16) > 64 * 1024) {
     delete p;
     return KRIG_EUNSUPPORTED;
   }
@@ -1002,7 +1001,7 @@ int krig_csim(krig_plan p, int32_t R, uint64_t seed, const double* d_y, void* d_
     c.pair0 = 0;
     c.ncol_full = p->Fs2;
     c.twF = f32 ? (const void*)p->tws1_32 : (const void*)p->tws1_64;
-    c.NL = nl_cols_for(p->es1, csz(p), false);
+    c.NL = nl_cols_for(p->es1, csz(p));
     KRIG_TRY((f32 ? p->es1->k.ce_cols32 : p->es1->k.ce_cols64)(c, npairs, p->st));
     // pass 2: transforms over the torus rows -> two realisations per pair
     RowsCEArgs o{};
