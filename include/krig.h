@@ -81,7 +81,13 @@ enum {
   KRIG_INFO_CE_CLAMPED, /* number of clamped circulant-embedding eigenvalues (after krig_csim) */
   KRIG_INFO_DLAG_GROUP, /* fields per block in the lag-gradient column pass */
   KRIG_INFO_CE_F1,      /* circulant-embedding torus size (0 before the first krig_csim) */
-  KRIG_INFO_CE_F2
+  KRIG_INFO_CE_F2,
+  KRIG_INFO_NL_ROWS64,  /* lines (row pairs) per block of the FP64 row passes */
+  KRIG_INFO_NL_ROWS32,  /* lines per block of the FP32 row passes */
+  KRIG_INFO_NL_COLS64,  /* columns per block of the prediction and adjoint column passes */
+  KRIG_INFO_FFT_R1,     /* factorisation F2 = R1 * R2 * R3 of the row transforms (R1 = 1: two stages) */
+  KRIG_INFO_FFT_R2,
+  KRIG_INFO_FFT_R3
 };
 
 /*
@@ -216,6 +222,27 @@ enum {
  */
 int krig_timing_enable(krig_plan p, int32_t on);
 int krig_timing_read(krig_plan p, int32_t stage, double *total_ms, int64_t *launches);
+
+/*
+ * Launch shapes.  plan_create picks defaults; a caller or an autotuner may change
+ * them between calls.
+ *   KRIG_TUNE_NL_ROWS64 / _ROWS32 / _COLS64: lines or columns per block, >= 1, with
+ *     at most 256 threads and 64 KB of LDS per block.  Every line's arithmetic is
+ *     unchanged, so results are bitwise the same for any value.
+ *   KRIG_TUNE_DLAG_GROUP: fields per block in the lag-gradient column pass, >= 1
+ *     (1 selects the one-field kernel); more fields per block means fewer partial
+ *     spectra to write and sum, less parallelism.  It sets how the sum over fields
+ *     of the lag gradient is grouped, and the one-field kernel is compiled apart
+ *     from the grouped one, so the adjoint's outputs change by rounding only.
+ * Returns KRIG_EINVAL for an unknown key or a value outside those limits.
+ */
+typedef enum {
+  KRIG_TUNE_DLAG_GROUP = 1,
+  KRIG_TUNE_NL_ROWS64,
+  KRIG_TUNE_NL_ROWS32,
+  KRIG_TUNE_NL_COLS64
+} krig_tune_key;
+int krig_plan_tune(krig_plan p, int32_t key, int64_t value);
 
 /* Human-readable text for a status code (static storage). */
 const char *krig_strerror(int status);

@@ -20,14 +20,17 @@ KRIG_F32 = 1
 KRIG_F64 = 2
 
 INFO = dict(N=1, M=2, P1=3, P2=4, F1=5, F2=6, H2=7, LDH=8, SAVED_PER_FIELD=9, KN_STATUS=10,
-            PIVOT=11, DTYPE=12, CE_CLAMPED=13, DLAG_GROUP=14, CE_F1=15, CE_F2=16)
+            PIVOT=11, DTYPE=12, CE_CLAMPED=13, DLAG_GROUP=14, CE_F1=15, CE_F2=16, NL_ROWS64=17,
+            NL_ROWS32=18, NL_COLS64=19, FFT_R1=20, FFT_R2=21, FFT_R3=22)
+TUNE = dict(DLAG_GROUP=1, NL_ROWS64=2, NL_ROWS32=3, NL_COLS64=4)
 
 STATUS = {0: "KRIG_OK", -1: "KRIG_EINVAL", -2: "KRIG_EDOMAIN", -3: "KRIG_ENOTSPD", -4: "KRIG_ECE",
           -5: "KRIG_ENOMEM", -6: "KRIG_EHIP", -7: "KRIG_EUNSUPPORTED"}
 
 EXPORTS = ["krig_plan_create", "krig_plan_destroy", "krig_plan_info", "krig_set_stream", "krig_weights",
            "krig_set_weights", "krig_lag", "krig_solve", "krig_scatter", "krig_convolve", "krig_predict",
-           "krig_predict_adjoint", "krig_csim", "krig_timing_enable", "krig_timing_read", "krig_strerror"]
+           "krig_predict_adjoint", "krig_csim", "krig_plan_tune", "krig_timing_enable", "krig_timing_read",
+           "krig_strerror"]
 
 STAGES = ["ROWS_FWD", "COLS_CONV", "ROWS_INV", "ADJ_ROWS_FWD", "ADJ_COLS", "ADJ_ROWS_INV", "GATHER", "SOLVE",
           "DLAG_TAIL", "CSIM_CE"]
@@ -76,6 +79,7 @@ def load_library(path: str = LIB_PATH) -> ctypes.CDLL:
         "krig_predict": [vp, i32, dp, dp, dp, dp, dp],
         "krig_predict_adjoint": [vp, i32, dp, dp, dp, dp, dp, dp],
         "krig_csim": [vp, i32, ctypes.c_uint64, dp, dp],
+        "krig_plan_tune": [vp, i32, i64],
         "krig_timing_enable": [vp, i32],
         "krig_timing_read": [vp, i32, ctypes.POINTER(ctypes.c_double), ctypes.POINTER(i64)],
     }
@@ -259,6 +263,11 @@ class Plan:
         _check(self.lib.krig_predict_adjoint(self.h, B, g.data_ptr(), _ptr(alpha), _ptr(saved), self._lag_ptr(lag),
                                              _ptr(dy), _ptr(dlag)), "krig_predict_adjoint")
         return dy, dlag
+
+    def tune(self, key: str, value: int):
+        """Set a launch shape (TUNE key): speed only, apart from DLAG_GROUP, which changes the
+        adjoint's outputs by rounding."""
+        _check(self.lib.krig_plan_tune(self.h, TUNE[key], ctypes.c_int64(int(value))), "krig_plan_tune")
 
     def timing(self, on: bool):
         """Bracket every stage launch with HIP events on the plan's stream."""

@@ -36,7 +36,10 @@ hipError_t transpose_f64(const double* src, int64_t ld_src, double* dst, int64_t
 // out[b] = T in[b] for a triangular T (upper = 0: lower, 1: upper); T row-major with a
 // pitch ldt that is a multiple of 4 and >= n rounded up to 16, 32-byte aligned, zeros
 // outside the triangle and in the padding.  hipErrorInvalidValue otherwise.
+// part: tri_part_size(n, B) doubles of workspace.
+int tri_max_splits(int n);
+inline size_t tri_part_size(int n, int B) { return (size_t)((n + 15) / 16) * tri_max_splits(n) * ((B + 15) / 16) * 256; }
 hipError_t tri_apply(const double* T, int64_t ldt, int n, int upper, const double* in, int64_t in_fs, double* out,
-                     int64_t out_fs, int B, hipStream_t st);
+                     int64_t out_fs, int B, double* part, hipStream_t st);
 
 }  // namespace krig

@@ -318,74 +318,96 @@ hipError_t transpose_f64(const double* src, int64_t ld_src, double* dst, int64_t
 // ------------------------------------------------------------------------------------
 // triangular product with an explicit triangular factor T (row-major, pitch ldt,
 // zeros outside the triangle and in the pitch padding):
-//   UPPER = 0:  out[b][i] = sum_{k <= i} T[i][k] in[b][k]      (T = L^{-1})
-//   UPPER = 1:  out[b][i] = sum_{k >= i} T[i][k] in[b][k]      (T = L^{-T})
-// One block per 16 output rows x 16 fields; its 16 waves take interleaved K chunks of
-// 16, four chunks per round.  Per chunk, lane (r = l%16, g = l/16) loads T[i0+r][16c + 4g .. +3] as one
-// 32-byte vector (a wave reads whole 128-byte row segments) and in[f0+r][same k];
-// four MFMA 16x16x4 steps take element s of each, i.e. the K order inside a chunk is
-// permuted identically for both operands.  The waves' tiles are summed through LDS
-// in a fixed order, so results do not depend on scheduling.
+//   upper = 0:  out[b][i] = sum_{k <= i} T[i][k] in[b][k]      (T = L^{-1})
+//   upper = 1:  out[b][i] = sum_{k >= i} T[i][k] in[b][k]      (T = L^{-T})
+// Work unit (one wave): 16 output rows (row tile t) x 16 fields x TRI_KS chunks of 16
+// columns.  A row tile's chunks are split over many waves so that no compute unit
+// streams a long row block alone (a single unit's share of memory bandwidth is
+// small).  Per chunk, lane (r = l%16, g = l/16) loads T[16t+r][16c + 4g .. +3] as
+// one 32-byte vector (whole 128-byte row segments per wave) and in[f0+r][same k];
+// four MFMA 16x16x4 steps take element s of each, i.e. the K order inside a chunk
+// is permuted identically for both operands.  Each wave stores its 16 x 16 partial
+// tile; a second kernel sums a tile's partials in the order of the split index.
 // ------------------------------------------------------------------------------------
-constexpr int TRI_WAVES = 16;
-constexpr int TRI_U = 4;
+constexpr int TRI_KS = 8;
+
+__host__ __device__ inline int tri_splits(int n, int t, int upper) {
+  const int nch = (n + 15) / 16;
+  const int len = upper ? nch - t : t + 1;
+  return (len + TRI_KS - 1) / TRI_KS;
+}
+int tri_max_splits(int n) { return tri_splits(n, 0, 1); }
 
 template <int UPPER>
-__global__ void __launch_bounds__(64 * TRI_WAVES) k_tri_apply(const double* __restrict__ T, int64_t ldt, int n,
-                                                              const double* __restrict__ in, int64_t in_fs, int B,
-                                                              double* __restrict__ out, int64_t out_fs) {
-  __shared__ double red[TRI_WAVES][4][64];
-  const int i0 = blockIdx.x * 16, f0 = blockIdx.y * 16;
-  const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
-  const int r = lane & 15, g = lane >> 4;
+__global__ void __launch_bounds__(64) k_tri_part(const double* __restrict__ T, int64_t ldt, int n,
+                                                 const double* __restrict__ in, int64_t in_fs, int B,
+                                                 double* __restrict__ part, int qmax) {
+  const int t = blockIdx.x, q = blockIdx.y, z = blockIdx.z, nfz = gridDim.z;
+  if (q >= tri_splits(n, t, UPPER)) return;  // the whole wave
+  const int lane = threadIdx.x, r = lane & 15, g = lane >> 4;
+  const int i0 = 16 * t, f0 = 16 * z;
   const int nch = (n + 15) / 16;
-  const int c_lo = UPPER ? i0 / 16 : 0;
-  const int c_hi = UPPER ? nch : min(nch, i0 / 16 + 1);
+  const int cb = (UPPER ? t : 0) + q * TRI_KS;
+  const int ce = min(cb + TRI_KS, UPPER ? nch : t + 1);
   const bool rok = i0 + r < n, fok = f0 + r < B;
   const double* trow = T + (int64_t)(rok ? i0 + r : 0) * ldt;
   const double* irow = in + (int64_t)(fok ? f0 + r : 0) * in_fs;
+  double4_t x[TRI_KS];
+  double a[TRI_KS][4];
+#pragma unroll
+  for (int u = 0; u < TRI_KS; ++u) {
+    const int c = cb + u;
+    const int k = 16 * c + 4 * g;
+    x[u] = (double4_t){0.0, 0.0, 0.0, 0.0};
+    if (rok && c < ce) x[u] = *reinterpret_cast<const double4_t*>(trow + k);
+#pragma unroll
+    for (int s = 0; s < 4; ++s) a[u][s] = (fok && c < ce && k + s < n) ? irow[k + s] : 0.0;
+  }
   double4_t acc = (double4_t){0.0, 0.0, 0.0, 0.0};
-  // TRI_U chunks per round: all their loads are in flight before the first MFMA
-  for (int c0 = c_lo + wave; c0 < c_hi; c0 += TRI_U * TRI_WAVES) {
-    double4_t x[TRI_U];
-    double a[TRI_U][4];
 #pragma unroll
-    for (int u = 0; u < TRI_U; ++u) {
-      const int c = c0 + u * TRI_WAVES;
-      const int k = 16 * c + 4 * g;
-      x[u] = (double4_t){0.0, 0.0, 0.0, 0.0};
-      if (rok && c < c_hi) x[u] = *reinterpret_cast<const double4_t*>(trow + k);
+  for (int u = 0; u < TRI_KS; ++u)
 #pragma unroll
-      for (int s = 0; s < 4; ++s) a[u][s] = (fok && c < c_hi && k + s < n) ? irow[k + s] : 0.0;
-    }
+    for (int s = 0; s < 4; ++s) acc = __builtin_amdgcn_mfma_f64_16x16x4f64(a[u][s], x[u][s], acc, 0, 0, 0);
+  double* pp = part + ((int64_t)(t * qmax + q) * nfz + z) * 256;
 #pragma unroll
-    for (int u = 0; u < TRI_U; ++u)
+  for (int j = 0; j < 4; ++j) pp[j * 64 + lane] = acc[j];
+}
+
+// out = sum of a tile's partials (split index order); element e of a partial tile is
+// MFMA result register e/64 of lane e%64: field f0 + (e%64)/16 + 4 (e/64), row i0 + e%16
+template <int UPPER>
+__global__ void __launch_bounds__(256) k_tri_sum(const double* __restrict__ part, int n, int B, int qmax,
+                                                 double* __restrict__ out, int64_t out_fs) {
+  const int t = blockIdx.x, z = blockIdx.y, nfz = gridDim.y;
+  const int e = threadIdx.x, lane = e & 63, j = e >> 6;
+  const int f = 16 * z + (lane >> 4) + 4 * j, i = 16 * t + (lane & 15);
+  const int ns = tri_splits(n, t, UPPER);
+  double s = 0.0;
+  for (int q0 = 0; q0 < ns; q0 += 8) {  // eight loads in flight, summed in split order
+    double v[8];
 #pragma unroll
-      for (int s = 0; s < 4; ++s) acc = __builtin_amdgcn_mfma_f64_16x16x4f64(a[u][s], x[u][s], acc, 0, 0, 0);
+    for (int u = 0; u < 8; ++u) v[u] = q0 + u < ns ? part[((int64_t)(t * qmax + q0 + u) * nfz + z) * 256 + e] : 0.0;
+#pragma unroll
+    for (int u = 0; u < 8; ++u)
+      if (q0 + u < ns) s += v[u];
   }
-#pragma unroll
-  for (int q = 0; q < 4; ++q) red[wave][q][lane] = acc[q];
-  __syncthreads();
-  if (threadIdx.x < 256) {
-    const int q = threadIdx.x >> 6, l = threadIdx.x & 63;
-    double s = 0.0;
-    for (int w = 0; w < TRI_WAVES; ++w) s += red[w][q][l];  // fixed order
-    // D[l/16 + 4q][l%16]: field f0 + l/16 + 4q, row i0 + l%16
-    const int f = f0 + (l >> 4) + 4 * q, i = i0 + (l & 15);
-    if (f < B && i < n) out[(int64_t)f * out_fs + i] = s;
-  }
+  if (f < B && i < n) out[(int64_t)f * out_fs + i] = s;
 }
 
 hipError_t tri_apply(const double* T, int64_t ldt, int n, int upper, const double* in, int64_t in_fs, double* out,
-                     int64_t out_fs, int B, hipStream_t st) {
+                     int64_t out_fs, int B, double* part, hipStream_t st) {
   if (n <= 0 || B <= 0) return hipSuccess;
   if ((ldt & 3) || ldt < (int64_t)(n + 15) / 16 * 16 || (reinterpret_cast<uintptr_t>(T) & 31))
     return hipErrorInvalidValue;
-  dim3 grid((n + 15) / 16, (B + 15) / 16);
-  if (upper)
-    hipLaunchKernelGGL(k_tri_apply<1>, grid, dim3(64 * TRI_WAVES), 0, st, T, ldt, n, in, in_fs, B, out, out_fs);
-  else
-    hipLaunchKernelGGL(k_tri_apply<0>, grid, dim3(64 * TRI_WAVES), 0, st, T, ldt, n, in, in_fs, B, out, out_fs);
+  const int qmax = tri_max_splits(n), nt = (n + 15) / 16, nfz = (B + 15) / 16;
+  dim3 grid(nt, qmax, nfz);
+  if (upper) {
+    hipLaunchKernelGGL(k_tri_part<1>, grid, dim3(64), 0, st, T, ldt, n, in, in_fs, B, part, qmax);
+    hipLaunchKernelGGL(k_tri_sum<1>, dim3(nt, nfz), dim3(256), 0, st, part, n, B, qmax, out, out_fs);
+  } else {
+    hipLaunchKernelGGL(k_tri_part<0>, grid, dim3(64), 0, st, T, ldt, n, in, in_fs, B, part, qmax);
+    hipLaunchKernelGGL(k_tri_sum<0>, dim3(nt, nfz), dim3(256), 0, st, part, n, B, qmax, out, out_fs);
+  }
   return hipGetLastError();
 }
 

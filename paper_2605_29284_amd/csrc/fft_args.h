@@ -135,6 +135,7 @@ struct FftSet {
   launch_cols_t conv_mixed;         // FP64 forward, x filter, FP32 inverse, FP32 out
   launch_cols_t conv64;             // all FP64
   launch_cols_t conv_dlag64;        // all FP64, plus sum_b G_b conj(C_b) partial spectra
+  launch_cols_t conv_dlag64_1;      //   the same with one field per block (one partial per field)
   launch_cols_t fwd_real64;         // forward columns, store Re * scale (FP64)
   launch_cols_t inv_sum64;          // inverse columns of a sum of partial spectra (FP64)
   launch_rows_c2r_t c2r32;          // inverse rows, FP32

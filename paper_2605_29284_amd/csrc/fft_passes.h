@@ -202,27 +202,54 @@ __global__ void __launch_bounds__(256) k_rows_r2c(RowsR2CArgs a) {
   cx<TC>* L = lds + (size_t)l * G::ROWS;
 
   cx<TC> v[G::NIN];
+  // CSR scatter (Steps 5-6): node (r, c) = sum over its segment of alpha[site] * w, in
+  // segment order.  For each of the line's two rows the loads of its NIN nodes go out
+  // in three batches (segment bounds, first entries, their alphas) instead of one
+  // dependent chain per node; later entries of a segment (rare) follow in a loop.
+  double sc[2][G::NIN];
+  if constexpr (SRC == SRC_CSR) {
+    if (s < G::TIN) {
+      const double* al = a.alpha + (int64_t)b * a.alpha_fs;
+#pragma unroll
+      for (int h = 0; h < 2; ++h) {
+        const int rr = h ? rb : ra;
+        const bool okr = h ? okb : oka;
+        int e0[G::NIN], e1[G::NIN];
+#pragma unroll
+        for (int j = 0; j < G::NIN; ++j) {
+          const int c = G::TIN * j + s;
+          const bool ok = okr && c < a.ncols;
+          const int q = rr * a.ncols + c;
+          e0[j] = ok ? a.row_ptr[q] : 0;
+          e1[j] = ok ? a.row_ptr[q + 1] : 0;
+        }
+        int site[G::NIN];
+        double w0[G::NIN];
+#pragma unroll
+        for (int j = 0; j < G::NIN; ++j) {
+          const bool has = e0[j] < e1[j];
+          site[j] = has ? a.ent_site[e0[j]] : 0;
+          w0[j] = has ? a.ent_w[e0[j]] : 0.0;
+        }
+#pragma unroll
+        for (int j = 0; j < G::NIN; ++j) {
+          sc[h][j] = 0.0;
+          if (e0[j] < e1[j]) sc[h][j] += al[site[j]] * w0[j];
+        }
+#pragma unroll
+        for (int j = 0; j < G::NIN; ++j)
+          for (int e = e0[j] + 1; e < e1[j]; ++e) sc[h][j] += al[a.ent_site[e]] * a.ent_w[e];
+      }
+    }
+  }
   if (s < G::TIN) {
 #pragma unroll
     for (int j = 0; j < G::NIN; ++j) {
       const int c = G::TIN * j + s;
       TC xa = 0, xb = 0;
       if constexpr (SRC == SRC_CSR) {
-        if (c < a.ncols) {
-          const double* al = a.alpha + (int64_t)b * a.alpha_fs;
-          if (oka) {
-            const int q = ra * a.ncols + c;
-            double acc = 0.0;
-            for (int e = a.row_ptr[q]; e < a.row_ptr[q + 1]; ++e) acc += al[a.ent_site[e]] * a.ent_w[e];
-            xa = (TC)acc;
-          }
-          if (okb) {
-            const int q = rb * a.ncols + c;
-            double acc = 0.0;
-            for (int e = a.row_ptr[q]; e < a.row_ptr[q + 1]; ++e) acc += al[a.ent_site[e]] * a.ent_w[e];
-            xb = (TC)acc;
-          }
-        }
+        xa = (TC)sc[0][j];
+        xb = (TC)sc[1][j];
       } else if constexpr (SRC == SRC_DENSE) {
         const int cc = c - a.coff;
         if (cc >= 0 && cc < a.ncols) {
@@ -326,7 +353,7 @@ __device__ __forceinline__ void col_fwd(const cx<TS>* src, int in_off, int in_cn
   xf_fwd<TC, R1, R2, R3, -1>(v, w, s, L, twF);
 }
 
-enum { COL_CONV = 0, COL_CONV_DLAG = 1, COL_FWD_REAL = 2, COL_INV_SUM = 3, COL_CE = 4 };
+enum { COL_CONV = 0, COL_CONV_DLAG = 1, COL_FWD_REAL = 2, COL_INV_SUM = 3, COL_CE = 4, COL_CONV_DLAG1 = 5 };
 
 template <typename TF, typename TI, typename TSI, typename TSO, int R1, int R2, int R3, int MODE>
 __global__ void __launch_bounds__(256) k_cols(ColsArgs a) {
@@ -411,6 +438,33 @@ __global__ void __launch_bounds__(256) k_cols(ColsArgs a) {
 #pragma unroll
       for (int k2 = 0; k2 < R3; ++k2) p[s + G::TOUT * k2] = ccast<TSO>(acc[k2]);
     }
+  } else if constexpr (MODE == COL_CONV_DLAG1) {
+    // one field per block (blockIdx.y): its product G-hat conj(C-hat) -> part[field]
+    const int b = blockIdx.y;
+    const cx<TSI>* srcc = reinterpret_cast<const cx<TSI>*>(a.in2) + (int64_t)b * a.in2_fs + (int64_t)col * a.in2_ld;
+    const cx<TSI>* srcg = reinterpret_cast<const cx<TSI>*>(a.in) + (int64_t)b * a.in_fs + (int64_t)col * a.in_ld;
+    cx<TC> wc[R3], wg[R3];
+    col_fwd<TC, TSI, R1, R2, R3>(srcc, a.in2_off, a.in2_cnt, colok, s, L, twF, wc);  // C-hat
+    col_fwd<TC, TSI, R1, R2, R3>(srcg, a.in_off, a.in_cnt, colok, s, L, twF, wg);    // G-hat
+    if (s < G::TOUT && colok) {
+      const TF* f = reinterpret_cast<const TF*>(a.filt) + (int64_t)col * a.filt_ld;
+      cx<TSO>* p = reinterpret_cast<cx<TSO>*>(a.part) + (int64_t)b * a.part_fs + (int64_t)col * a.part_ld;
+#pragma unroll
+      for (int k2 = 0; k2 < R3; ++k2) {
+        p[s + G::TOUT * k2] = ccast<TSO>(cmulc(wg[k2], wc[k2]));
+        wg[k2] = cscale(wg[k2], f[s + G::TOUT * k2]);
+      }
+    }
+    cx<TC> v[G::NIN];
+    xf_inv<TC, R1, R2, R3>(wg, s, L, twF, v);
+    if (s < G::TIN && colok) {
+      cx<TSO>* dst = reinterpret_cast<cx<TSO>*>(a.out) + (int64_t)b * a.out_fs + (int64_t)col * a.out_ld;
+#pragma unroll
+      for (int j = 0; j < G::NIN; ++j) {
+        const int d = window_dst(a.rows, G::TIN * j + s);
+        if (d >= 0) dst[d] = ccast<TSO>(v[j]);
+      }
+    }
   } else if constexpr (MODE == COL_FWD_REAL) {
     // forward transform of the input columns; store Re(X) * scale (natural order)
     const int b = blockIdx.y;
@@ -466,12 +520,22 @@ __global__ void __launch_bounds__(256) k_cols(ColsArgs a) {
 #pragma unroll
     for (int j = 0; j < G::NIN; ++j) v[j] = mk<TC>(0, 0);
     if (s < G::TIN && colok) {
-      // partial g outermost: each round issues the NIN loads of one partial together;
-      // every element is still summed in the order g = 0, 1, ...
-      for (int g = 0; g < a.G; ++g) {
-        const cx<TSI>* pg = p + (int64_t)g * a.in_fs + s;
+      // four partials per round: their 4 NIN loads go out together; every element is
+      // still summed in the order g = 0, 1, ...
+      for (int g0 = 0; g0 < a.G; g0 += 4) {
+        cx<TSI> t[4][G::NIN];
 #pragma unroll
-        for (int j = 0; j < G::NIN; ++j) v[j] = v[j] + ccast<TC>(pg[G::TIN * j]);
+        for (int u = 0; u < 4; ++u) {
+          const cx<TSI>* pg = p + (int64_t)(g0 + u < a.G ? g0 + u : g0) * a.in_fs + s;
+#pragma unroll
+          for (int j = 0; j < G::NIN; ++j) t[u][j] = pg[G::TIN * j];
+        }
+#pragma unroll
+        for (int u = 0; u < 4; ++u)
+          if (g0 + u < a.G) {
+#pragma unroll
+            for (int j = 0; j < G::NIN; ++j) v[j] = v[j] + ccast<TC>(t[u][j]);
+          }
       }
     }
     cx<TC> w[R3];
@@ -734,6 +798,7 @@ FftEntry make_fft_entry() {
   k.conv_mixed = launch_cols<double, float, double, float, R1, R2, R3, COL_CONV>;
   k.conv64 = launch_cols<double, double, double, double, R1, R2, R3, COL_CONV>;
   k.conv_dlag64 = launch_cols<double, double, double, double, R1, R2, R3, COL_CONV_DLAG>;
+  k.conv_dlag64_1 = launch_cols<double, double, double, double, R1, R2, R3, COL_CONV_DLAG1>;
   k.fwd_real64 = launch_cols<double, double, double, double, R1, R2, R3, COL_FWD_REAL>;
   k.inv_sum64 = launch_cols<double, double, double, double, R1, R2, R3, COL_INV_SUM>;
   k.c2r32 = launch_rows_c2r<float, float, float, R1, R2, R3>;

@@ -77,6 +77,7 @@ struct krig_plan_s {
   void* img = nullptr;    // FP64 [B][P1][P2]       correlation image
   double* alpha = nullptr;  // [B][n]
   double* tmpv = nullptr;   // [B][n]
+  double* tripart = nullptr;  // partial tiles of the split triangular products
   void* part = nullptr;   // cx FP64 [ngroups][H2][F1]
   int part_groups = 0;
   void* XC = nullptr;     // cx FP64 [H2][ldX]
@@ -88,8 +89,7 @@ struct krig_plan_s {
   int nl_rows64 = 4;   // lines per block, FP64 row kernels
   int nl_rows32 = 8;   // FP32 row kernels
   int nl_cols64 = 4;   // columns per block, FP64-forward column kernels
-  int nl_cols_dlag = 2;
-  int dlag_G = 2;
+  int dlag_G = 1;       // fields per block of the lag-gradient column pass (1: one-field kernel)
   // conditional simulation (set up on the first krig_csim call)
   int ce_clamped = 0;
   int Fs1 = 0, Fs2 = 0, Hs2 = 0;
@@ -269,7 +269,7 @@ int make_filter(krig_plan p, const double* lag64, double* filt_out) {
 // forward workspaces (prediction and solves) for B fields
 int ensure_ws(krig_plan p, int B) {
   if (B <= p->wsB) return KRIG_OK;
-  void* olds[] = {p->S1, p->S2, p->alpha, p->tmpv};
+  void* olds[] = {p->S1, p->S2, p->alpha, p->tmpv, p->tripart};
   KRIG_TRY(hipStreamSynchronize(p->st));
   for (void* q : olds) dfree(p, q);
   const size_t c = csz(p);
@@ -279,6 +279,7 @@ int ensure_ws(krig_plan p, int B) {
   if ((r = dalloc_bytes(p, &p->S2, c * (size_t)B * H2 * p->ldM)) != KRIG_OK) return r;
   if ((r = dalloc(p, &p->alpha, (size_t)B * p->n)) != KRIG_OK) return r;
   if ((r = dalloc(p, &p->tmpv, (size_t)B * p->n)) != KRIG_OK) return r;
+  if ((r = dalloc(p, &p->tripart, tri_part_size(p->n, B))) != KRIG_OK) return r;
   p->wsB = B;
   return KRIG_OK;
 }
@@ -302,8 +303,8 @@ int ensure_ws_adj(krig_plan p, int B) {
 
 int do_solve(krig_plan p, int B, const double* y, double* alpha) {
   StageTimer t(p, KRIG_STAGE_SOLVE);
-  KRIG_TRY(tri_apply(p->Linv, p->ldL, p->n, 0, y, p->n, p->tmpv, p->n, B, p->st));
-  KRIG_TRY(tri_apply(p->LinvT, p->ldL, p->n, 1, p->tmpv, p->n, alpha, p->n, B, p->st));
+  KRIG_TRY(tri_apply(p->Linv, p->ldL, p->n, 0, y, p->n, p->tmpv, p->n, B, p->tripart, p->st));
+  KRIG_TRY(tri_apply(p->LinvT, p->ldL, p->n, 1, p->tmpv, p->n, alpha, p->n, B, p->tripart, p->st));
   return KRIG_OK;
 }
 
@@ -591,7 +592,6 @@ int krig_plan_create(krig_plan* out, const krig_grid* g, const krig_matern* k, i
   p->nl_rows64 = nl_rows_for(p->e2, 16);
   p->nl_rows32 = nl_rows_for(p->e2, 8);
   p->nl_cols64 = nl_cols_for(p->e1, 16);
-  p->nl_cols_dlag = p->nl_cols64;
   if (rows_lds(p->e2->geo, p->nl_rows64, 16) > 64 * 1024 || cols_lds(p->e1->geo, p->nl_cols64, 16) > 64 * 1024) {
     delete p;
     return KRIG_EUNSUPPORTED;
@@ -716,6 +716,12 @@ int krig_plan_info(krig_plan p, int32_t what, int64_t* v) {
     case KRIG_INFO_DTYPE: *v = p->dtype; break;
     case KRIG_INFO_CE_CLAMPED: *v = p->ce_clamped; break;
     case KRIG_INFO_DLAG_GROUP: *v = p->dlag_G; break;
+    case KRIG_INFO_NL_ROWS64: *v = p->nl_rows64; break;
+    case KRIG_INFO_NL_ROWS32: *v = p->nl_rows32; break;
+    case KRIG_INFO_NL_COLS64: *v = p->nl_cols64; break;
+    case KRIG_INFO_FFT_R1: *v = p->e2->geo.R1; break;
+    case KRIG_INFO_FFT_R2: *v = p->e2->geo.R2; break;
+    case KRIG_INFO_FFT_R3: *v = p->e2->geo.R3; break;
     case KRIG_INFO_CE_F1: *v = p->Fs1; break;
     case KRIG_INFO_CE_F2: *v = p->Fs2; break;
     default: return KRIG_EINVAL;
@@ -872,10 +878,10 @@ int krig_predict_adjoint(krig_plan p, int32_t B, const void* d_g, const double* 
     c.part_fs = (int64_t)p->H2 * p->F1;
     c.part_ld = p->F1;
     c.G = std::max(1, std::min(p->dlag_G, (int)B));
-    c.NL = p->nl_cols_dlag;
+    c.NL = p->nl_cols64;
     ngroups = (B + c.G - 1) / c.G;
     StageTimer t(p, KRIG_STAGE_ADJ_COLS);
-    KRIG_TRY(set1(p).conv_dlag64(c, ngroups, p->st));
+    KRIG_TRY((c.G == 1 ? set1(p).conv_dlag64_1 : set1(p).conv_dlag64)(c, ngroups, p->st));
   } else {
     c.NL = p->nl_cols64;
     StageTimer t(p, KRIG_STAGE_ADJ_COLS);
@@ -939,6 +945,27 @@ int krig_predict_adjoint(krig_plan p, int32_t B, const void* d_g, const double* 
     KRIG_TRY((is32(p) ? set2(p).c2r_fold32 : set2(p).c2r_fold64)(oc, 1, p->st));
   }
   return KRIG_OK;
+}
+
+int krig_plan_tune(krig_plan p, int32_t key, int64_t value) {
+  if (!p || value < 1 || value > 256) return KRIG_EINVAL;
+  const int v = (int)value;
+  switch (key) {
+    case KRIG_TUNE_DLAG_GROUP: p->dlag_G = v; return KRIG_OK;
+    case KRIG_TUNE_NL_ROWS64:
+      if (v * nt_of(p->e2) > 256 || rows_lds(p->e2->geo, v, 16) > 64 * 1024) return KRIG_EINVAL;
+      p->nl_rows64 = v;
+      return KRIG_OK;
+    case KRIG_TUNE_NL_ROWS32:
+      if (v * nt_of(p->e2) > 256 || rows_lds(p->e2->geo, v, 8) > 64 * 1024) return KRIG_EINVAL;
+      p->nl_rows32 = v;
+      return KRIG_OK;
+    case KRIG_TUNE_NL_COLS64:
+      if (v * nt_of(p->e1) > 256 || cols_lds(p->e1->geo, v, 16) > 64 * 1024) return KRIG_EINVAL;
+      p->nl_cols64 = v;
+      return KRIG_OK;
+    default: return KRIG_EINVAL;
+  }
 }
 
 int krig_timing_enable(krig_plan p, int32_t on) {

@@ -356,9 +356,23 @@ __device__ inline double gather_one(const GridDev& g, const int32_t* anchor, con
   const int i0 = anchor[2 * i], j0 = anchor[2 * i + 1];
   const int L2 = 2 * g.L;
   double acc = 0.0;
-  for (int m = 0; m < g.M; ++m) {
-    const int ox = m / L2 - g.L + 1, oy = m % L2 - g.L + 1;
-    acc += Wt[(int64_t)m * n + i] * (double)im[(int64_t)(i0 + g.L + ox) * ldi + (j0 + g.L + oy)];
+  // loads of sixteen neighbours are issued together; the sum runs in the order of m
+  for (int m0 = 0; m0 < g.M; m0 += 16) {
+    double wv[16], iv[16];
+#pragma unroll
+    for (int u = 0; u < 16; ++u) {
+      const int m = m0 + u;
+      wv[u] = 0.0;
+      iv[u] = 0.0;
+      if (m < g.M) {
+        const int ox = m / L2 - g.L + 1, oy = m % L2 - g.L + 1;
+        wv[u] = Wt[(int64_t)m * n + i];
+        iv[u] = (double)im[(int64_t)(i0 + g.L + ox) * ldi + (j0 + g.L + oy)];
+      }
+    }
+#pragma unroll
+    for (int u = 0; u < 16; ++u)
+      if (m0 + u < g.M) acc += wv[u] * iv[u];
   }
   return acc;
 }

@@ -328,6 +328,53 @@ def test_bitwise_repeatable(krig, paper):
     assert np.array_equal(d1[0], d2[0]) and np.array_equal(d1[1], d2[1])
 
 
+@pytest.mark.parametrize("dtype", ["f64", "f32"])
+def test_launch_shapes(krig, paper, dtype):
+    """Lines per block leave every result bitwise unchanged; the lag-gradient field
+    grouping regroups only the sum over fields of d lag (rounding-level change)."""
+    w, _ = paper
+    say("launch shapes", dtype)
+    p = krig.plan_for(w, dtype)
+    B = 5
+    y = dev(np.concatenate([w.y] * B)[:B] * np.linspace(1.0, 2.0, B)[:, None])
+    gup = dev(np.random.default_rng(7).standard_normal((B, w.m1, w.m2)), p.tdtype)
+
+    def run():
+        saved = p.new_saved(B)
+        alpha = torch.empty(B, w.n, dtype=torch.float64, device=y.device)
+        yh = p.predict(y, alpha_out=alpha, saved=saved)
+        dy, dlag = p.adjoint(gup, alpha=alpha, saved=saved)
+        return host(yh), host(dy), host(dlag)
+
+    g0 = p.info("DLAG_GROUP")
+    p.tune("DLAG_GROUP", 2)
+    ref = run()
+    for key, vals in (("NL_ROWS64", (1, 2)), ("NL_ROWS32", (1, 2)), ("NL_COLS64", (1, 2))):
+        old = p.info(key)
+        for v in vals:
+            p.tune(key, v)
+            out = run()
+            for a_, b_ in zip(out, ref):
+                assert np.array_equal(a_, b_), (key, v)
+        p.tune(key, old)
+    tol = 1e-13 if dtype == "f64" else 1e-6
+    for gv in (1, 3, 16):
+        p.tune("DLAG_GROUP", gv)
+        out = run()
+        assert np.array_equal(out[0], ref[0]), gv
+        if gv >= 2:  # the same grouped kernel: the per-field arithmetic is unchanged
+            assert np.array_equal(out[1], ref[1]), gv
+        else:  # the one-field kernel is compiled separately: dy agrees to rounding,
+            # amplified by cond(K + tau^2 I) (~1e4 here)
+            assert relmax(out[1], ref[1]) < 1e-11, gv
+        assert relmax(out[2], ref[2]) < tol, gv
+    p.tune("DLAG_GROUP", g0)
+    for key, v in (("NL_COLS64", 1000), ("NL_ROWS64", 0), ("DLAG_GROUP", 0)):
+        with pytest.raises(krig.KrigError) as e:
+            p.tune(key, v)
+        assert e.value.status == -1
+
+
 def test_error_paths(krig):
     say("error paths")
     w = wl.tiny(seed=1, m1=10, m2=10, L=2, n=5)
