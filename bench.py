@@ -12,8 +12,10 @@ HBM before timing.  Prints one JSON line.
 from __future__ import annotations
 
 import argparse
+import hashlib
 import json
 import os
+import re
 import sys
 import time
 
@@ -23,6 +25,34 @@ ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
 HBM_PEAK_GBS = 8000.0  # MI355X HBM3E, GB/s
+PROFILES = os.path.join(ROOT, "profiles")
+# sources of the FFT pass kernels: a recorded traffic figure holds only while they are unchanged
+KERNEL_SOURCES = ["fft_passes.h", "fft_args.h", "fft_reg.h", "krig_internal.h", "matern_dev.h", "philox_dev.h"]
+
+
+def kernel_source_hash():
+    h = hashlib.sha256()
+    for name in KERNEL_SOURCES:
+        with open(os.path.join(ROOT, "paper_2605_29284_amd", "csrc", name), "rb") as f:
+            h.update(f.read())
+    return h.hexdigest()[:16]
+
+
+def recorded_traffic(stage):
+    """HBM bytes per launch of a stage's kernel from the committed rocprofv3 counter
+    summary (FETCH_SIZE + WRITE_SIZE, copy-calibrated), or None when there is none or
+    the kernel sources have changed since it was taken."""
+    if not os.path.isdir(PROFILES):
+        return None
+    for name in sorted(os.listdir(PROFILES)):
+        if not name.startswith(stage + "_") or not name.endswith(".md"):
+            continue
+        txt = open(os.path.join(PROFILES, name)).read()
+        m = re.search(r"^traffic_bytes_per_launch:\s*([0-9.eE+]+)\s*$", txt, re.M)
+        h = re.search(r"^kernel_source_hash:\s*([0-9a-f]+)\s*$", txt, re.M)
+        if m and h and h.group(1) == kernel_source_hash():
+            return float(m.group(1))
+    return None
 
 
 def stage_bytes(p, B, ngroups):
@@ -38,13 +68,14 @@ def stage_bytes(p, B, ngroups):
         "COLS_CONV": B * (H2 * P1 * z + H2 * m1 * c) + H2 * F1 * 8,
         "ROWS_INV": B * (H2 * m1 * c + m1 * m2 * t),
         "ADJ_ROWS_FWD": B * (m1 * m2 * t + H2 * m1 * z),
-        "ADJ_COLS": B * (H2 * m1 * z + 2 * H2 * P1 * z) + ngroups * H2 * F1 * z + H2 * F1 * 8,
+        # the summed lag-gradient spectrum once (per-group partials are an implementation choice)
+        "ADJ_COLS": B * (H2 * m1 * z + 2 * H2 * P1 * z) + H2 * F1 * z + H2 * F1 * 8,
         "ADJ_ROWS_INV": B * (H2 * P1 * z + P1 * P2 * 8),
         "GATHER": B * (n * M * 8 + n * 8) + n * M * 8 + n * 8,
     }
 
 
-def cpu_baseline(w, nfields: int, reps: int = 3):
+def cpu_baseline(w, nfields: int, reps: int = 6):
     """The FP64 oracle (its FFT variants, single thread) on a bounded sample of fields."""
     from threadpoolctl import threadpool_limits
 
@@ -196,7 +227,7 @@ def main(argv=None):
                                "forward (y->y_hat) + adjoint (g->dy, dlag)",
                    "B": B, "n": w.n, "grid": [w.m1, w.m2], "L": w.L, "fft": [p32.F1, p32.F2]},
         "roofline": {"bound": "hbm", "kernel": dom, "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
-                     "frac": achieved / HBM_PEAK_GBS, "traffic": None,
+                     "frac": achieved / HBM_PEAK_GBS, "traffic": recorded_traffic(dom),
                      "bytes_per_launch": sb[dom], "avg_launch_ms": avg[dom]},
         "hot_path_value": npred / (r32["hot_ms"] * 1e-3),
         "setup_ms": r32["setup_ms"],

@@ -229,11 +229,11 @@ int krig_timing_read(krig_plan p, int32_t stage, double *total_ms, int64_t *laun
  *   KRIG_TUNE_NL_ROWS64 / _ROWS32 / _COLS64: lines or columns per block, >= 1, with
  *     at most 256 threads and 64 KB of LDS per block.  Every line's arithmetic is
  *     unchanged, so results are bitwise the same for any value.
- *   KRIG_TUNE_DLAG_GROUP: fields per block in the lag-gradient column pass, >= 1
- *     (1 selects the one-field kernel); more fields per block means fewer partial
- *     spectra to write and sum, less parallelism.  It sets how the sum over fields
- *     of the lag gradient is grouped, and the one-field kernel is compiled apart
- *     from the grouped one, so the adjoint's outputs change by rounding only.
+ *   KRIG_TUNE_DLAG_GROUP: fields per block in the lag-gradient column pass (one
+ *     field per line of one column), >= 1, with the same thread and LDS limits; more
+ *     fields per block means fewer partial spectra to write and sum.  It sets how the
+ *     sum over fields of the lag gradient is grouped, so d lag changes by rounding
+ *     only; the other outputs are bitwise the same.
  * Returns KRIG_EINVAL for an unknown key or a value outside those limits.
  */
 typedef enum {

@@ -265,8 +265,8 @@ class Plan:
         return dy, dlag
 
     def tune(self, key: str, value: int):
-        """Set a launch shape (TUNE key): speed only, apart from DLAG_GROUP, which changes the
-        adjoint's outputs by rounding."""
+        """Set a launch shape (TUNE key): speed only, apart from DLAG_GROUP, which regroups the
+        sum over fields of d lag (rounding-level change)."""
         _check(self.lib.krig_plan_tune(self.h, TUNE[key], ctypes.c_int64(int(value))), "krig_plan_tune")
 
     def timing(self, on: bool):

@@ -74,7 +74,7 @@ struct ColsArgs {
   Window rows;            // transform-index rows to keep
   void* part;             // cx<TSO> part[g*part_fs + c*part_ld + k] (lag-gradient partial spectra)
   int64_t part_fs, part_ld;
-  int G;                  // fields per block (lag gradient) / number of partials (inverse sum)
+  int G;                  // number of partials (inverse sum)
   int B;                  // total fields
   const void* twF;        // cx<TF> [F] twiddles of the forward transform's precision
   const void* twI;        // cx<TI> [F] twiddles of the inverse transform's precision
@@ -134,8 +134,8 @@ struct FftSet {
   launch_rows_r2c_t r2c_lag;        // even-reflected lag quadrant, FP64
   launch_cols_t conv_mixed;         // FP64 forward, x filter, FP32 inverse, FP32 out
   launch_cols_t conv64;             // all FP64
-  launch_cols_t conv_dlag64;        // all FP64, plus sum_b G_b conj(C_b) partial spectra
-  launch_cols_t conv_dlag64_1;      //   the same with one field per block (one partial per field)
+  launch_cols_t conv_dlag64;        // all FP64, plus sum_b G_b conj(C_b) partial spectra (NL fields
+                                    // of one column per block, one partial per block row)
   launch_cols_t fwd_real64;         // forward columns, store Re * scale (FP64)
   launch_cols_t inv_sum64;          // inverse columns of a sum of partial spectra (FP64)
   launch_rows_c2r_t c2r32;          // inverse rows, FP32

@@ -353,7 +353,7 @@ __device__ __forceinline__ void col_fwd(const cx<TS>* src, int in_off, int in_cn
   xf_fwd<TC, R1, R2, R3, -1>(v, w, s, L, twF);
 }
 
-enum { COL_CONV = 0, COL_CONV_DLAG = 1, COL_FWD_REAL = 2, COL_INV_SUM = 3, COL_CE = 4, COL_CONV_DLAG1 = 5 };
+enum { COL_CONV = 0, COL_CONV_DLAG = 1, COL_FWD_REAL = 2, COL_INV_SUM = 3, COL_CE = 4 };
 
 template <typename TF, typename TI, typename TSI, typename TSO, int R1, int R2, int R3, int MODE>
 __global__ void __launch_bounds__(256) k_cols(ColsArgs a) {
@@ -395,70 +395,44 @@ __global__ void __launch_bounds__(256) k_cols(ColsArgs a) {
       }
     }
   } else if constexpr (MODE == COL_CONV_DLAG) {
-    // blockIdx.y = group of G fields; partial spectrum of the group -> part[group]
-    cx<TC> acc[R3];
-#pragma unroll
-    for (int k2 = 0; k2 < R3; ++k2) acc[k2] = mk<TC>(0, 0);
-    const int b0 = blockIdx.y * a.G;
-    const int s0 = s, col0 = col;
-#pragma unroll 1
-    for (int gi = 0; gi < a.G; ++gi) {
-      const int b = b0 + gi;
-      if (b >= a.B) break;  // uniform across the block
-      // fresh copies of the lane indices each iteration: keeps per-lane addresses
-      // and twiddles from being hoisted out of the field loop
-      const int s = opaque_v(s0), col = opaque_v(col0);
-      const cx<TSI>* srcc =
-          reinterpret_cast<const cx<TSI>*>(a.in2) + (int64_t)b * a.in2_fs + (int64_t)col * a.in2_ld;
-      const cx<TSI>* srcg = reinterpret_cast<const cx<TSI>*>(a.in) + (int64_t)b * a.in_fs + (int64_t)col * a.in_ld;
-      cx<TC> wc[R3], wg[R3];
-      col_fwd<TC, TSI, R1, R2, R3>(srcc, a.in2_off, a.in2_cnt, colok, s, L, twF, wc);  // C-hat
-      col_fwd<TC, TSI, R1, R2, R3>(srcg, a.in_off, a.in_cnt, colok, s, L, twF, wg);    // G-hat
-      if (s < G::TOUT && colok) {
-        const TF* f = reinterpret_cast<const TF*>(a.filt) + (int64_t)col * a.filt_ld;
-#pragma unroll
-        for (int k2 = 0; k2 < R3; ++k2) {
-          acc[k2] = acc[k2] + cmulc(wg[k2], wc[k2]);
-          wg[k2] = cscale(wg[k2], f[s + G::TOUT * k2]);
-        }
-      }
-      cx<TC> v[G::NIN];
-      xf_inv<TC, R1, R2, R3>(wg, s, L, twF, v);
-      if (s < G::TIN && colok) {
-        cx<TSO>* dst = reinterpret_cast<cx<TSO>*>(a.out) + (int64_t)b * a.out_fs + (int64_t)col * a.out_ld;
-#pragma unroll
-        for (int j = 0; j < G::NIN; ++j) {
-          const int d = window_dst(a.rows, G::TIN * j + s);
-          if (d >= 0) dst[d] = ccast<TSO>(v[j]);
-        }
-      }
-    }
-    if (s < G::TOUT && colok) {
-      cx<TSO>* p = reinterpret_cast<cx<TSO>*>(a.part) + (int64_t)blockIdx.y * a.part_fs + (int64_t)col * a.part_ld;
-#pragma unroll
-      for (int k2 = 0; k2 < R3; ++k2) p[s + G::TOUT * k2] = ccast<TSO>(acc[k2]);
-    }
-  } else if constexpr (MODE == COL_CONV_DLAG1) {
-    // one field per block (blockIdx.y): its product G-hat conj(C-hat) -> part[field]
-    const int b = blockIdx.y;
-    const cx<TSI>* srcc = reinterpret_cast<const cx<TSI>*>(a.in2) + (int64_t)b * a.in2_fs + (int64_t)col * a.in2_ld;
-    const cx<TSI>* srcg = reinterpret_cast<const cx<TSI>*>(a.in) + (int64_t)b * a.in_fs + (int64_t)col * a.in_ld;
+    // one column per block (blockIdx.x); line l0 takes field blockIdx.y * NL + l0.  The
+    // lines' products G-hat conj(C-hat) are summed through LDS in line order into the
+    // block's partial spectrum part[blockIdx.y]; each field's correlation with the
+    // filter goes to out as in COL_CONV.
+    const int colb = blockIdx.x;
+    const bool colokb = colb < a.H2;
+    const int b = blockIdx.y * NL + l0;
+    const bool fok = colokb && b < a.B;
+    const int bb = b < a.B ? b : 0;
+    const cx<TSI>* srcc = reinterpret_cast<const cx<TSI>*>(a.in2) + (int64_t)bb * a.in2_fs + (int64_t)colb * a.in2_ld;
+    const cx<TSI>* srcg = reinterpret_cast<const cx<TSI>*>(a.in) + (int64_t)bb * a.in_fs + (int64_t)colb * a.in_ld;
     cx<TC> wc[R3], wg[R3];
-    col_fwd<TC, TSI, R1, R2, R3>(srcc, a.in2_off, a.in2_cnt, colok, s, L, twF, wc);  // C-hat
-    col_fwd<TC, TSI, R1, R2, R3>(srcg, a.in_off, a.in_cnt, colok, s, L, twF, wg);    // G-hat
-    if (s < G::TOUT && colok) {
-      const TF* f = reinterpret_cast<const TF*>(a.filt) + (int64_t)col * a.filt_ld;
-      cx<TSO>* p = reinterpret_cast<cx<TSO>*>(a.part) + (int64_t)b * a.part_fs + (int64_t)col * a.part_ld;
+    col_fwd<TC, TSI, R1, R2, R3>(srcc, a.in2_off, a.in2_cnt, fok, s, L, twF, wc);  // C-hat
+    col_fwd<TC, TSI, R1, R2, R3>(srcg, a.in_off, a.in_cnt, fok, s, L, twF, wg);    // G-hat
+    __syncthreads();
+    if (s < G::TOUT) {
+      const TF* f = reinterpret_cast<const TF*>(a.filt) + (int64_t)(colokb ? colb : 0) * a.filt_ld;
 #pragma unroll
       for (int k2 = 0; k2 < R3; ++k2) {
-        p[s + G::TOUT * k2] = ccast<TSO>(cmulc(wg[k2], wc[k2]));
-        wg[k2] = cscale(wg[k2], f[s + G::TOUT * k2]);
+        L[s + G::TOUT * k2] = fok ? cmulc(wg[k2], wc[k2]) : mk<TC>(0, 0);
+        if (fok) wg[k2] = cscale(wg[k2], f[s + G::TOUT * k2]);
+      }
+    }
+    __syncthreads();
+    if (l0 == 0 && s < G::TOUT && colokb) {
+      const cx<TC>* L0 = reinterpret_cast<const cx<TC>*>(smem_raw);
+      cx<TSO>* p = reinterpret_cast<cx<TSO>*>(a.part) + (int64_t)blockIdx.y * a.part_fs + (int64_t)colb * a.part_ld;
+#pragma unroll
+      for (int k2 = 0; k2 < R3; ++k2) {
+        cx<TC> acc = L0[s + G::TOUT * k2];
+        for (int li = 1; li < NL; ++li) acc = acc + L0[(size_t)li * G::EX + s + G::TOUT * k2];
+        p[s + G::TOUT * k2] = ccast<TSO>(acc);
       }
     }
     cx<TC> v[G::NIN];
     xf_inv<TC, R1, R2, R3>(wg, s, L, twF, v);
-    if (s < G::TIN && colok) {
-      cx<TSO>* dst = reinterpret_cast<cx<TSO>*>(a.out) + (int64_t)b * a.out_fs + (int64_t)col * a.out_ld;
+    if (s < G::TIN && fok) {
+      cx<TSO>* dst = reinterpret_cast<cx<TSO>*>(a.out) + (int64_t)b * a.out_fs + (int64_t)colb * a.out_ld;
 #pragma unroll
       for (int j = 0; j < G::NIN; ++j) {
         const int d = window_dst(a.rows, G::TIN * j + s);
@@ -745,7 +719,8 @@ hipError_t launch_rows_r2c(const RowsR2CArgs& a, int B, hipStream_t st) {
 template <typename TF, typename TI, typename TSI, typename TSO, int R1, int R2, int R3, int MODE>
 hipError_t launch_cols(const ColsArgs& a, int nblk_y, hipStream_t st) {
   using G = Geo<R1, R2, R3>;
-  dim3 grid((a.H2 + a.NL - 1) / a.NL, nblk_y);
+  // the lag-gradient pass: one column per block, its NL lines are fields
+  dim3 grid(MODE == COL_CONV_DLAG ? a.H2 : (a.H2 + a.NL - 1) / a.NL, nblk_y);
   dim3 block(G::NT * a.NL);
   const size_t sh = cols_lds(G::g, a.NL, sizeof(cx<TF>));
   k_cols<TF, TI, TSI, TSO, R1, R2, R3, MODE><<<grid, block, sh, st>>>(a);
@@ -798,7 +773,6 @@ FftEntry make_fft_entry() {
   k.conv_mixed = launch_cols<double, float, double, float, R1, R2, R3, COL_CONV>;
   k.conv64 = launch_cols<double, double, double, double, R1, R2, R3, COL_CONV>;
   k.conv_dlag64 = launch_cols<double, double, double, double, R1, R2, R3, COL_CONV_DLAG>;
-  k.conv_dlag64_1 = launch_cols<double, double, double, double, R1, R2, R3, COL_CONV_DLAG1>;
   k.fwd_real64 = launch_cols<double, double, double, double, R1, R2, R3, COL_FWD_REAL>;
   k.inv_sum64 = launch_cols<double, double, double, double, R1, R2, R3, COL_INV_SUM>;
   k.c2r32 = launch_rows_c2r<float, float, float, R1, R2, R3>;

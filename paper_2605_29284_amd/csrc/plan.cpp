@@ -89,7 +89,7 @@ struct krig_plan_s {
   int nl_rows64 = 4;   // lines per block, FP64 row kernels
   int nl_rows32 = 8;   // FP32 row kernels
   int nl_cols64 = 4;   // columns per block, FP64-forward column kernels
-  int dlag_G = 1;       // fields per block of the lag-gradient column pass (1: one-field kernel)
+  int dlag_G = 1;       // fields per block of the lag-gradient column pass
   // conditional simulation (set up on the first krig_csim call)
   int ce_clamped = 0;
   int Fs1 = 0, Fs2 = 0, Hs2 = 0;
@@ -592,6 +592,7 @@ int krig_plan_create(krig_plan* out, const krig_grid* g, const krig_matern* k, i
   p->nl_rows64 = nl_rows_for(p->e2, 16);
   p->nl_rows32 = nl_rows_for(p->e2, 8);
   p->nl_cols64 = nl_cols_for(p->e1, 16);
+  p->dlag_G = p->nl_cols64;
   if (rows_lds(p->e2->geo, p->nl_rows64, 16) > 64 * 1024 || cols_lds(p->e1->geo, p->nl_cols64, 16) > 64 * 1024) {
     delete p;
     return KRIG_EUNSUPPORTED;
@@ -877,11 +878,10 @@ int krig_predict_adjoint(krig_plan p, int32_t B, const void* d_g, const double* 
     c.part = p->part;
     c.part_fs = (int64_t)p->H2 * p->F1;
     c.part_ld = p->F1;
-    c.G = std::max(1, std::min(p->dlag_G, (int)B));
-    c.NL = p->nl_cols64;
-    ngroups = (B + c.G - 1) / c.G;
+    c.NL = std::max(1, std::min(p->dlag_G, (int)B));  // fields (lines) per block
+    ngroups = (B + c.NL - 1) / c.NL;
     StageTimer t(p, KRIG_STAGE_ADJ_COLS);
-    KRIG_TRY((c.G == 1 ? set1(p).conv_dlag64_1 : set1(p).conv_dlag64)(c, ngroups, p->st));
+    KRIG_TRY(set1(p).conv_dlag64(c, ngroups, p->st));
   } else {
     c.NL = p->nl_cols64;
     StageTimer t(p, KRIG_STAGE_ADJ_COLS);
@@ -951,7 +951,10 @@ int krig_plan_tune(krig_plan p, int32_t key, int64_t value) {
   if (!p || value < 1 || value > 256) return KRIG_EINVAL;
   const int v = (int)value;
   switch (key) {
-    case KRIG_TUNE_DLAG_GROUP: p->dlag_G = v; return KRIG_OK;
+    case KRIG_TUNE_DLAG_GROUP:
+      if (v * nt_of(p->e1) > 256 || cols_lds(p->e1->geo, v, 16) > 64 * 1024) return KRIG_EINVAL;
+      p->dlag_G = v;
+      return KRIG_OK;
     case KRIG_TUNE_NL_ROWS64:
       if (v * nt_of(p->e2) > 256 || rows_lds(p->e2->geo, v, 16) > 64 * 1024) return KRIG_EINVAL;
       p->nl_rows64 = v;

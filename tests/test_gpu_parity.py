@@ -358,18 +358,13 @@ def test_launch_shapes(krig, paper, dtype):
                 assert np.array_equal(a_, b_), (key, v)
         p.tune(key, old)
     tol = 1e-13 if dtype == "f64" else 1e-6
-    for gv in (1, 3, 16):
+    for gv in (1,):  # at most 256 threads per block: two 96-thread lines at length 768
         p.tune("DLAG_GROUP", gv)
         out = run()
-        assert np.array_equal(out[0], ref[0]), gv
-        if gv >= 2:  # the same grouped kernel: the per-field arithmetic is unchanged
-            assert np.array_equal(out[1], ref[1]), gv
-        else:  # the one-field kernel is compiled separately: dy agrees to rounding,
-            # amplified by cond(K + tau^2 I) (~1e4 here)
-            assert relmax(out[1], ref[1]) < 1e-11, gv
+        assert np.array_equal(out[0], ref[0]) and np.array_equal(out[1], ref[1]), gv
         assert relmax(out[2], ref[2]) < tol, gv
     p.tune("DLAG_GROUP", g0)
-    for key, v in (("NL_COLS64", 1000), ("NL_ROWS64", 0), ("DLAG_GROUP", 0)):
+    for key, v in (("NL_COLS64", 1000), ("NL_ROWS64", 0), ("DLAG_GROUP", 0), ("DLAG_GROUP", 3)):
         with pytest.raises(krig.KrigError) as e:
             p.tune(key, v)
         assert e.value.status == -1
