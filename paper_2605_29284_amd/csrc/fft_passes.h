@@ -63,6 +63,31 @@ __device__ __forceinline__ cx<T> twm(cx<T> a, cx<T> tw) {
 // stays a permutation of itself so the other side still reads whole rows.
 __device__ __forceinline__ int rot(int k, int c, int R) { return k * R + (c + k) % R; }
 
+// Workgroups go to the 8 XCDs (each with its own L2) round-robin by linear block id.
+// xcd_block maps the hardware id to a logical id so that each XCD runs one contiguous
+// range of logical blocks; blocks that share cache lines (neighbouring row blocks of a
+// frequency-major spectrum) or a filter column (the fields of one column) then share
+// an L2 instead of fetching the same lines once per XCD.
+constexpr int KRIG_XCDS = 8;
+__device__ __forceinline__ int xcd_block(int bid, int nb) {
+  const int per = nb / KRIG_XCDS, rem = nb % KRIG_XCDS;
+  const int x = bid % KRIG_XCDS, k = bid / KRIG_XCDS;
+  return x * per + (x < rem ? x : rem) + k;
+}
+// logical (bx, by) of this block: rows kernels order bx fastest (row blocks of a field
+// contiguous), column kernels order by fastest (the fields of a column contiguous)
+template <bool Y_FAST>
+__device__ __forceinline__ void logical_block(int& bx, int& by) {
+  const int lb = xcd_block(blockIdx.x + gridDim.x * blockIdx.y, gridDim.x * gridDim.y);
+  if (Y_FAST) {
+    by = lb % gridDim.y;
+    bx = lb / gridDim.y;
+  } else {
+    bx = lb % gridDim.x;
+    by = lb / gridDim.x;
+  }
+}
+
 __device__ __forceinline__ int window_dst(const Window& wd, int i) {
   if (i >= wd.a0 && i < wd.a0 + wd.na) return i - wd.a0;
   if (i >= wd.b0 && i < wd.b0 + wd.nb) return wd.na + i - wd.b0;
@@ -188,14 +213,16 @@ enum { SRC_CSR = 0, SRC_DENSE = 1, SRC_LAG = 2, SRC_COV = 3 };
 
 template <typename TC, typename TIN, typename TS, int R1, int R2, int R3, int SRC>
 __global__ void __launch_bounds__(256) k_rows_r2c(RowsR2CArgs a) {
+  int bx, by;
+  logical_block<false>(bx, by);
   using G = Geo<R1, R2, R3>;
   extern __shared__ unsigned char smem_raw[];
   cx<TC>* lds = reinterpret_cast<cx<TC>*>(smem_raw);
   const int s = threadIdx.x % G::NT;
   const int l = threadIdx.x / G::NT;
   const int NL = a.NL;
-  const int b = blockIdx.y;
-  const int row0 = 2 * blockIdx.x * NL;
+  const int b = by;
+  const int row0 = 2 * bx * NL;
   const int ra = row0 + 2 * l, rb = ra + 1;
   const bool oka = ra < a.nrows, okb = rb < a.nrows;
   const cx<TC>* twF = reinterpret_cast<const cx<TC>*>(a.twF);
@@ -357,19 +384,21 @@ enum { COL_CONV = 0, COL_CONV_DLAG = 1, COL_FWD_REAL = 2, COL_INV_SUM = 3, COL_C
 
 template <typename TF, typename TI, typename TSI, typename TSO, int R1, int R2, int R3, int MODE>
 __global__ void __launch_bounds__(256) k_cols(ColsArgs a) {
+  int bx, by;
+  logical_block<true>(bx, by);
   using G = Geo<R1, R2, R3>;
   using TC = TF;
   extern __shared__ unsigned char smem_raw[];
   const int NL = a.NL;
   const int s = threadIdx.x % G::NT;
   const int l0 = threadIdx.x / G::NT;
-  const int col = blockIdx.x * NL + l0;
+  const int col = bx * NL + l0;
   const bool colok = col < a.H2;
   const cx<TC>* twF = reinterpret_cast<const cx<TC>*>(a.twF);
   cx<TC>* L = reinterpret_cast<cx<TC>*>(smem_raw) + (size_t)l0 * G::EX;
 
   if constexpr (MODE == COL_CONV) {
-    const int b = blockIdx.y;
+    const int b = by;
     const cx<TSI>* src = reinterpret_cast<const cx<TSI>*>(a.in) + (int64_t)b * a.in_fs + (int64_t)col * a.in_ld;
     cx<TI> wi[R3];
     {
@@ -395,13 +424,13 @@ __global__ void __launch_bounds__(256) k_cols(ColsArgs a) {
       }
     }
   } else if constexpr (MODE == COL_CONV_DLAG) {
-    // one column per block (blockIdx.x); line l0 takes field blockIdx.y * NL + l0.  The
+    // one column per block (bx); line l0 takes field by * NL + l0.  The
     // lines' products G-hat conj(C-hat) are summed through LDS in line order into the
-    // block's partial spectrum part[blockIdx.y]; each field's correlation with the
+    // block's partial spectrum part[by]; each field's correlation with the
     // filter goes to out as in COL_CONV.
-    const int colb = blockIdx.x;
+    const int colb = bx;
     const bool colokb = colb < a.H2;
-    const int b = blockIdx.y * NL + l0;
+    const int b = by * NL + l0;
     const bool fok = colokb && b < a.B;
     const int bb = b < a.B ? b : 0;
     const cx<TSI>* srcc = reinterpret_cast<const cx<TSI>*>(a.in2) + (int64_t)bb * a.in2_fs + (int64_t)colb * a.in2_ld;
@@ -421,7 +450,7 @@ __global__ void __launch_bounds__(256) k_cols(ColsArgs a) {
     __syncthreads();
     if (l0 == 0 && s < G::TOUT && colokb) {
       const cx<TC>* L0 = reinterpret_cast<const cx<TC>*>(smem_raw);
-      cx<TSO>* p = reinterpret_cast<cx<TSO>*>(a.part) + (int64_t)blockIdx.y * a.part_fs + (int64_t)colb * a.part_ld;
+      cx<TSO>* p = reinterpret_cast<cx<TSO>*>(a.part) + (int64_t)by * a.part_fs + (int64_t)colb * a.part_ld;
 #pragma unroll
       for (int k2 = 0; k2 < R3; ++k2) {
         cx<TC> acc = L0[s + G::TOUT * k2];
@@ -441,7 +470,7 @@ __global__ void __launch_bounds__(256) k_cols(ColsArgs a) {
     }
   } else if constexpr (MODE == COL_FWD_REAL) {
     // forward transform of the input columns; store Re(X) * scale (natural order)
-    const int b = blockIdx.y;
+    const int b = by;
     const cx<TSI>* src = reinterpret_cast<const cx<TSI>*>(a.in) + (int64_t)b * a.in_fs + (int64_t)col * a.in_ld;
     cx<TC> w[R3];
     col_fwd<TC, TSI, R1, R2, R3>(src, a.in_off, a.in_cnt, colok, s, L, twF, w);
@@ -454,7 +483,7 @@ __global__ void __launch_bounds__(256) k_cols(ColsArgs a) {
     // sampler pass 1: column k2 (all ncol_full frequencies) of sqrt(Lambda/N) (xi1 + i xi2),
     // xi from Philox counter (k1 * ncol_full + k2, pair, STREAM_CE, 0); forward transform
     // over k1; keep rows [0, rows.na) -> out[pair][k2][r]
-    const int pair = a.pair0 + blockIdx.y;
+    const int pair = a.pair0 + by;
     const int kk2 = col < a.ncol_full - col ? col : a.ncol_full - col;  // Lambda is even
     const double* lam = reinterpret_cast<const double*>(a.filt) + (int64_t)kk2 * a.filt_ld;
     cx<TC> v[G::NIN];
@@ -481,7 +510,7 @@ __global__ void __launch_bounds__(256) k_cols(ColsArgs a) {
     cx<TC> w[R3];
     xf_fwd<TC, R1, R2, R3, -1>(v, w, s, L, twF);
     if (s < G::TOUT && colok) {
-      cx<TSO>* dst = reinterpret_cast<cx<TSO>*>(a.out) + (int64_t)blockIdx.y * a.out_fs + (int64_t)col * a.out_ld;
+      cx<TSO>* dst = reinterpret_cast<cx<TSO>*>(a.out) + (int64_t)by * a.out_fs + (int64_t)col * a.out_ld;
 #pragma unroll
       for (int k2 = 0; k2 < R3; ++k2) {
         const int d = window_dst(a.rows, s + G::TOUT * k2);
@@ -550,14 +579,16 @@ __device__ __forceinline__ void c2r_line_input(const cx<TC>* T, int R2b, int l, 
 
 template <typename TC, typename TS, typename TO, int R1, int R2, int R3>
 __global__ void __launch_bounds__(256) k_rows_c2r(RowsC2RArgs a) {
+  int bx, by;
+  logical_block<false>(bx, by);
   using G = Geo<R1, R2, R3>;
   extern __shared__ unsigned char smem_raw[];
   cx<TC>* lds = reinterpret_cast<cx<TC>*>(smem_raw);
   const int s = threadIdx.x % G::NT;
   const int l = threadIdx.x / G::NT;
   const int NL = a.NL;
-  const int b = blockIdx.y;
-  const int row0 = 2 * blockIdx.x * NL;
+  const int b = by;
+  const int row0 = 2 * bx * NL;
   const int ra = row0 + 2 * l, rb = ra + 1;
   const bool oka = ra < a.nrows, okb = rb < a.nrows;
   const cx<TC>* twF = reinterpret_cast<const cx<TC>*>(a.twF);
@@ -609,6 +640,8 @@ __global__ void __launch_bounds__(256) k_rows_c2r(RowsC2RArgs a) {
 // ----------------------------------------------------------------------------------------
 template <typename TC, typename TO, int R1, int R2, int R3>
 __global__ void __launch_bounds__(256) k_rows_c2r_fold(RowsC2RArgs a) {
+  int bx, by;
+  logical_block<false>(bx, by);
   using G = Geo<R1, R2, R3>;
   extern __shared__ unsigned char smem_raw[];
   cx<TC>* lds = reinterpret_cast<cx<TC>*>(smem_raw);
@@ -616,7 +649,7 @@ __global__ void __launch_bounds__(256) k_rows_c2r_fold(RowsC2RArgs a) {
   const int l = threadIdx.x / G::NT;
   const int NL = a.NL;
   const int n1l = a.nrows, n2l = a.cols.na;
-  const int row0 = 2 * blockIdx.x * NL;
+  const int row0 = 2 * bx * NL;
   const int ra = row0 + 2 * l, rb = ra + 1;
   const cx<TC>* twF = reinterpret_cast<const cx<TC>*>(a.twF);
   const int R2b = 2 * NL;
@@ -661,17 +694,19 @@ __global__ void __launch_bounds__(256) k_rows_c2r_fold(RowsC2RArgs a) {
 // ----------------------------------------------------------------------------------------
 template <typename TC, typename TS, typename TO, int R1, int R2, int R3>
 __global__ void __launch_bounds__(256) k_rows_ce(RowsCEArgs a) {
+  int bx, by;
+  logical_block<false>(bx, by);
   using G = Geo<R1, R2, R3>;
   extern __shared__ unsigned char smem_raw[];
   cx<TC>* lds = reinterpret_cast<cx<TC>*>(smem_raw);
   const int s = threadIdx.x % G::NT;
   const int l = threadIdx.x / G::NT;
   const int NL = a.NL;
-  const int pair = a.pair0 + blockIdx.y;
-  const int row0 = blockIdx.x * NL;
+  const int pair = a.pair0 + by;
+  const int row0 = bx * NL;
   const int row = row0 + l;
   const cx<TC>* twF = reinterpret_cast<const cx<TC>*>(a.twF);
-  const cx<TS>* in = reinterpret_cast<const cx<TS>*>(a.in) + (int64_t)blockIdx.y * a.in_fs;
+  const cx<TS>* in = reinterpret_cast<const cx<TS>*>(a.in) + (int64_t)by * a.in_fs;
   cx<TC>* T = lds;  // [k][l]
   for (int idx = threadIdx.x; idx < G::F * NL; idx += blockDim.x) {
     const int rl = idx % NL, k = idx / NL;
