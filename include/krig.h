@@ -244,6 +244,37 @@ typedef enum {
 } krig_tune_key;
 int krig_plan_tune(krig_plan p, int32_t key, int64_t value);
 
+/*
+ * Uneven batch: predictions for several plans at once (different grids, sites,
+ * kernels or dtypes; Section 2.2's predictor applied to each problem).  Problem i is
+ * krig_predict(plans[i], h_B[i], h_y[i], NULL, h_yhat[i], NULL, NULL) (h_B NULL: one
+ * field each); h_B, h_y and h_yhat are host arrays of count entries, the last two
+ * holding device pointers.  stream NULL runs each problem on its plan's own stream;
+ * otherwise every problem is enqueued on `stream` and the plans keep their streams.
+ * Every argument is checked before anything is enqueued.
+ */
+int krig_predict_many(const krig_plan *plans, int32_t count, const int32_t *h_B, const double *const *h_y,
+                      void *const *h_yhat, void *stream);
+
+/*
+ * The same batch recorded once as a HIP graph and replayed by one launch.
+ * krig_batch_create grows every plan's workspaces for its B, then captures the
+ * batch's kernel launches on `stream` (NULL: a stream of the batch's own), spread
+ * over `lanes` (1..16) parallel branches so that small problems run side by side
+ * (largest problem first, each to the least-loaded branch).  The device pointers in
+ * h_y / h_yhat are recorded: a replay reads and writes those buffers.
+ * krig_batch_launch replays the graph on `stream` (NULL: the capture stream).
+ * While a batch exists its plans refuse krig_plan_destroy and any call that would
+ * regrow their workspaces (KRIG_EINVAL); a replay must not overlap other calls on the
+ * same plans.  krig_batch_create fails with KRIG_EINVAL while stage timing is on for
+ * any of the plans.
+ */
+typedef struct krig_batch_s *krig_batch;
+int krig_batch_create(krig_batch *out, const krig_plan *plans, int32_t count, const int32_t *h_B,
+                      const double *const *h_y, void *const *h_yhat, int32_t lanes, void *stream);
+int krig_batch_launch(krig_batch b, void *stream);
+int krig_batch_destroy(krig_batch b);
+
 /* Human-readable text for a status code (static storage). */
 const char *krig_strerror(int status);
 

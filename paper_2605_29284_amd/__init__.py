@@ -29,8 +29,8 @@ STATUS = {0: "KRIG_OK", -1: "KRIG_EINVAL", -2: "KRIG_EDOMAIN", -3: "KRIG_ENOTSPD
 
 EXPORTS = ["krig_plan_create", "krig_plan_destroy", "krig_plan_info", "krig_set_stream", "krig_weights",
            "krig_set_weights", "krig_lag", "krig_solve", "krig_scatter", "krig_convolve", "krig_predict",
-           "krig_predict_adjoint", "krig_csim", "krig_plan_tune", "krig_timing_enable", "krig_timing_read",
-           "krig_strerror"]
+           "krig_predict_adjoint", "krig_csim", "krig_plan_tune", "krig_predict_many", "krig_batch_create",
+           "krig_batch_launch", "krig_batch_destroy", "krig_timing_enable", "krig_timing_read", "krig_strerror"]
 
 STAGES = ["ROWS_FWD", "COLS_CONV", "ROWS_INV", "ADJ_ROWS_FWD", "ADJ_COLS", "ADJ_ROWS_INV", "GATHER", "SOLVE",
           "DLAG_TAIL", "CSIM_CE"]
@@ -80,6 +80,11 @@ def load_library(path: str = LIB_PATH) -> ctypes.CDLL:
         "krig_predict_adjoint": [vp, i32, dp, dp, dp, dp, dp, dp],
         "krig_csim": [vp, i32, ctypes.c_uint64, dp, dp],
         "krig_plan_tune": [vp, i32, i64],
+        "krig_predict_many": [ctypes.POINTER(vp), i32, ctypes.POINTER(i32), ctypes.POINTER(vp), ctypes.POINTER(vp), vp],
+        "krig_batch_create": [ctypes.POINTER(vp), ctypes.POINTER(vp), i32, ctypes.POINTER(i32), ctypes.POINTER(vp),
+                              ctypes.POINTER(vp), i32, vp],
+        "krig_batch_launch": [vp, vp],
+        "krig_batch_destroy": [vp],
         "krig_timing_enable": [vp, i32],
         "krig_timing_read": [vp, i32, ctypes.POINTER(ctypes.c_double), ctypes.POINTER(i64)],
     }
@@ -290,6 +295,64 @@ class Plan:
         _check(self.lib.krig_csim(self.h, R, int(seed) & 0xFFFFFFFFFFFFFFFF, y.data_ptr(), out.data_ptr()),
                "krig_csim")
         return out
+
+
+def _many_args(plans, ys, outs):
+    """Host arrays for the uneven-batch entry points; checks each problem's tensors."""
+    if not (len(plans) == len(ys) == len(outs)) or not plans:
+        raise ValueError("plans, ys and outs must be non-empty lists of equal length")
+    Bs = []
+    for p, y, o in zip(plans, ys, outs):
+        y = p._batch(y, (p.n,), "y", p.torch.float64)
+        p._t(o, p.tdtype, (y.shape[0], p.m1, p.m2), "out")
+        Bs.append(y.shape[0])
+    k = len(plans)
+    hp = (ctypes.c_void_p * k)(*[p.h for p in plans])
+    hb = (ctypes.c_int32 * k)(*Bs)
+    hy = (ctypes.c_void_p * k)(*[y.data_ptr() for y in ys])
+    ho = (ctypes.c_void_p * k)(*[o.data_ptr() for o in outs])
+    return k, hp, hb, hy, ho
+
+
+def predict_many(plans, ys, outs):
+    """Uneven batch: plans[i].predict(ys[i], out=outs[i]) for every i, all on torch's
+    current stream (krig_predict_many)."""
+    k, hp, hb, hy, ho = _many_args(plans, ys, outs)
+    st = plans[0].torch.cuda.current_stream(plans[0].device).cuda_stream
+    _check(plans[0].lib.krig_predict_many(hp, k, hb, hy, ho, st), "krig_predict_many")
+    return outs
+
+
+class Batch:
+    """The same uneven batch recorded once as a HIP graph (krig_batch_create) and
+    replayed by launch(); ys / outs are the buffers every replay reads and writes."""
+
+    def __init__(self, plans, ys, outs, lanes: int = 4):
+        k, hp, hb, hy, ho = _many_args(plans, ys, outs)
+        self.plans, self.ys, self.outs = list(plans), list(ys), list(outs)  # keep them alive
+        self.lib = plans[0].lib
+        self.torch = plans[0].torch
+        self.device = plans[0].device
+        st = self.torch.cuda.current_stream(self.device).cuda_stream
+        h = ctypes.c_void_p()
+        _check(self.lib.krig_batch_create(ctypes.byref(h), hp, k, hb, hy, ho, int(lanes), st), "krig_batch_create")
+        self.h = h
+
+    def launch(self):
+        st = self.torch.cuda.current_stream(self.device).cuda_stream
+        _check(self.lib.krig_batch_launch(self.h, st), "krig_batch_launch")
+        return self.outs
+
+    def close(self):
+        if getattr(self, "h", None):
+            _check(self.lib.krig_batch_destroy(self.h), "krig_batch_destroy")
+            self.h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
 
 
 def plan_for(w, dtype: str = "f32", device: str = "cuda:0") -> Plan:

@@ -106,6 +106,7 @@ struct krig_plan_s {
   int wsB_adj = 0;
   // stage timing
   bool timing = false;
+  int batch_refs = 0;  // recorded batches (graphs) holding pointers into the workspaces
   std::vector<hipEvent_t> ev_pool;
   std::vector<std::pair<hipEvent_t, hipEvent_t>> ev_pending[KRIG_STAGE_COUNT];
   std::vector<void*> allocs;
@@ -269,6 +270,7 @@ int make_filter(krig_plan p, const double* lag64, double* filt_out) {
 // forward workspaces (prediction and solves) for B fields
 int ensure_ws(krig_plan p, int B) {
   if (B <= p->wsB) return KRIG_OK;
+  if (p->batch_refs > 0) return KRIG_EINVAL;  // a recorded graph uses the current buffers
   void* olds[] = {p->S1, p->S2, p->alpha, p->tmpv, p->tripart};
   KRIG_TRY(hipStreamSynchronize(p->st));
   for (void* q : olds) dfree(p, q);
@@ -287,6 +289,7 @@ int ensure_ws(krig_plan p, int B) {
 // adjoint workspaces for B fields
 int ensure_ws_adj(krig_plan p, int B) {
   if (B <= p->wsB_adj) return KRIG_OK;
+  if (p->batch_refs > 0) return KRIG_EINVAL;
   void* olds[] = {p->SG, p->SA, p->img, p->part};
   KRIG_TRY(hipStreamSynchronize(p->st));
   for (void* q : olds) dfree(p, q);
@@ -695,7 +698,7 @@ int krig_plan_create(krig_plan* out, const krig_grid* g, const krig_matern* k, i
 }
 
 int krig_plan_destroy(krig_plan p) {
-  if (!p) return KRIG_EINVAL;
+  if (!p || p->batch_refs > 0) return KRIG_EINVAL;
   destroy_all(p);
   return KRIG_OK;
 }
@@ -1059,6 +1062,158 @@ int krig_csim(krig_plan p, int32_t R, uint64_t seed, const double* d_y, void* d_
   if ((r = do_solve(p, R, p->csRes, p->csAl)) != KRIG_OK) return r;
   // krige the residual and add the unconditional field (last pass of the convolution)
   return do_convolve(p, R, p->csAl, p->filt, d_fields, p->S1, p->csU, (int64_t)p->P1 * p->P2, p->P2);
+}
+
+
+// ------------------------------------------------------------------------------ uneven batch
+static int check_many(const krig_plan* plans, int32_t count, const int32_t* h_B, const double* const* h_y,
+                      void* const* h_yhat) {
+  if (!plans || count < 1 || !h_y || !h_yhat) return KRIG_EINVAL;
+  for (int i = 0; i < count; ++i)
+    if (!plans[i] || !h_y[i] || !h_yhat[i] || (h_B && h_B[i] < 1)) return KRIG_EINVAL;
+  return KRIG_OK;
+}
+
+int krig_predict_many(const krig_plan* plans, int32_t count, const int32_t* h_B, const double* const* h_y,
+                      void* const* h_yhat, void* stream) {
+  int r = check_many(plans, count, h_B, h_y, h_yhat);
+  if (r != KRIG_OK) return r;
+  for (int i = 0; i < count; ++i) {
+    krig_plan p = plans[i];
+    const hipStream_t old = p->st;
+    if (stream) p->st = (hipStream_t)stream;
+    r = krig_predict(p, h_B ? h_B[i] : 1, h_y[i], nullptr, h_yhat[i], nullptr, nullptr);
+    p->st = old;
+    if (r != KRIG_OK) return r;
+  }
+  return KRIG_OK;
+}
+
+struct krig_batch_s {
+  std::vector<krig_plan> plans;
+  hipGraph_t graph = nullptr;
+  hipGraphExec_t exec = nullptr;
+  hipStream_t own = nullptr;   // capture stream created by the batch (stream NULL)
+  hipStream_t cap = nullptr;   // the capture stream
+};
+
+static void batch_free(krig_batch b) {
+  if (b->exec) (void)hipGraphExecDestroy(b->exec);
+  if (b->graph) (void)hipGraphDestroy(b->graph);
+  if (b->own) (void)hipStreamDestroy(b->own);
+  for (krig_plan p : b->plans) --p->batch_refs;
+  delete b;
+}
+
+int krig_batch_create(krig_batch* out, const krig_plan* plans, int32_t count, const int32_t* h_B,
+                      const double* const* h_y, void* const* h_yhat, int32_t lanes, void* stream) {
+  if (!out || lanes < 1 || lanes > 16) return KRIG_EINVAL;
+  int r = check_many(plans, count, h_B, h_y, h_yhat);
+  if (r != KRIG_OK) return r;
+  for (int i = 0; i < count; ++i)
+    if (plans[i]->timing) return KRIG_EINVAL;
+  // workspaces at their final size before anything is recorded
+  for (int i = 0; i < count; ++i)
+    if ((r = ensure_ws(plans[i], h_B ? h_B[i] : 1)) != KRIG_OK) return r;
+  krig_batch b = new krig_batch_s();
+  if (!stream) {
+    if (hipStreamCreateWithFlags(&b->own, hipStreamNonBlocking) != hipSuccess) {
+      delete b;
+      return KRIG_EHIP;
+    }
+    b->cap = b->own;
+  } else {
+    b->cap = (hipStream_t)stream;
+  }
+  for (int i = 0; i < count; ++i) {
+    b->plans.push_back(plans[i]);
+    ++plans[i]->batch_refs;
+  }
+  // problems to branches: the problems of one plan share its workspaces, so they stay
+  // on one branch (in order); plans go largest first to the least-loaded branch
+  std::vector<krig_plan> uniq;
+  std::vector<int> grp(count);
+  for (int i = 0; i < count; ++i) {
+    const auto it = std::find(uniq.begin(), uniq.end(), plans[i]);
+    grp[i] = (int)(it - uniq.begin());
+    if (it == uniq.end()) uniq.push_back(plans[i]);
+  }
+  const int ng = (int)uniq.size();
+  std::vector<double> cost(ng, 0.0);
+  for (int i = 0; i < count; ++i) {
+    const krig_plan p = plans[i];
+    const double Bi = h_B ? h_B[i] : 1;
+    cost[grp[i]] += Bi * ((double)p->F1 * p->F2 * 2.0 + (double)p->n * p->n);
+  }
+  std::vector<int> order(ng);
+  for (int g = 0; g < ng; ++g) order[g] = g;
+  std::stable_sort(order.begin(), order.end(), [&](int a, int c) { return cost[a] > cost[c]; });
+  const int nl = std::min<int>(lanes, ng);
+  std::vector<double> load(nl, 0.0);
+  std::vector<int> lane_of_grp(ng, 0), lane_of(count, 0);
+  for (int g : order) {
+    const int k = (int)(std::min_element(load.begin(), load.end()) - load.begin());
+    lane_of_grp[g] = k;
+    load[k] += cost[g];
+  }
+  for (int i = 0; i < count; ++i) lane_of[i] = lane_of_grp[grp[i]];
+  std::vector<hipStream_t> ls(nl, nullptr);
+  std::vector<hipEvent_t> ev(nl + 1, nullptr);
+  std::vector<hipStream_t> old(count);
+  for (int i = 0; i < count; ++i) old[i] = plans[i]->st;
+  hipError_t e = hipSuccess;
+  bool capturing = false;
+  for (int k = 0; k < nl && e == hipSuccess; ++k) e = hipStreamCreateWithFlags(&ls[k], hipStreamNonBlocking);
+  for (int k = 0; k <= nl && e == hipSuccess; ++k) e = hipEventCreateWithFlags(&ev[k], hipEventDisableTiming);
+  if (e == hipSuccess) e = hipStreamBeginCapture(b->cap, hipStreamCaptureModeThreadLocal);
+  if (e == hipSuccess) {
+    capturing = true;
+    e = hipEventRecord(ev[nl], b->cap);  // fork
+    for (int k = 0; k < nl && e == hipSuccess; ++k) e = hipStreamWaitEvent(ls[k], ev[nl], 0);
+  }
+  r = e == hipSuccess ? KRIG_OK : KRIG_EHIP;
+  for (int i = 0; i < count && r == KRIG_OK; ++i) {
+    plans[i]->st = ls[lane_of[i]];
+    r = krig_predict(plans[i], h_B ? h_B[i] : 1, h_y[i], nullptr, h_yhat[i], nullptr, nullptr);
+    plans[i]->st = old[i];
+  }
+  for (int k = 0; k < nl && r == KRIG_OK; ++k) {  // join
+    if (hipEventRecord(ev[k], ls[k]) != hipSuccess || hipStreamWaitEvent(b->cap, ev[k], 0) != hipSuccess) r = KRIG_EHIP;
+  }
+  if (capturing) {
+    hipGraph_t g = nullptr;
+    const hipError_t ee = hipStreamEndCapture(b->cap, &g);
+    if (r == KRIG_OK && ee != hipSuccess) r = KRIG_EHIP;
+    if (r == KRIG_OK) {
+      b->graph = g;
+      if (hipGraphInstantiate(&b->exec, b->graph, nullptr, nullptr, 0) != hipSuccess) r = KRIG_EHIP;
+    } else if (g) {
+      (void)hipGraphDestroy(g);
+    }
+  }
+  for (int i = 0; i < count; ++i) plans[i]->st = old[i];
+  for (auto s_ : ls)
+    if (s_) (void)hipStreamDestroy(s_);
+  for (auto v : ev)
+    if (v) (void)hipEventDestroy(v);
+  if (r != KRIG_OK) {
+    batch_free(b);
+    return r;
+  }
+  *out = b;
+  return KRIG_OK;
+}
+
+int krig_batch_launch(krig_batch b, void* stream) {
+  if (!b || !b->exec) return KRIG_EINVAL;
+  KRIG_TRY(hipGraphLaunch(b->exec, stream ? (hipStream_t)stream : b->cap));
+  return KRIG_OK;
+}
+
+int krig_batch_destroy(krig_batch b) {
+  if (!b) return KRIG_EINVAL;
+  batch_free(b);
+  return KRIG_OK;
 }
 
 }  // extern "C"

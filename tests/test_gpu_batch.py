@@ -1,0 +1,137 @@
+"""GPU: the uneven batch (krig_predict_many and the graph-recorded krig_batch).
+
+Problems of different grids, site sets, kernels, neighbour orders and dtypes, drawn
+like the 64-problem uneven workload at reduced n.  A batch must reproduce each plan's
+own krig_predict bit for bit (same kernels, same inputs), on every replay of the
+recorded graph, and each problem must match the FP64 oracle (with the oracle's
+neighbour weights injected, so both sides start from identical inputs).
+"""
+import sys
+
+import numpy as np
+import pytest
+
+import workloads as wl
+from oracle.exact import ExactKriging
+from oracle.matern import Matern
+from oracle.rapid import Grid, RapidPredictor, lag_quadrant, rapid_fft
+
+pytestmark = pytest.mark.gpu
+
+torch = pytest.importorskip("torch")
+
+
+def say(*a):
+    print("[gpu-case]", *a, flush=True)
+    sys.stdout.flush()
+
+
+def relmax(a, b):
+    a = np.asarray(a, dtype=np.float64)
+    b = np.asarray(b, dtype=np.float64)
+    return float(np.abs(a - b).max() / max(np.abs(b).max(), 1e-300))
+
+
+def dev(x, dtype=torch.float64):
+    return torch.as_tensor(np.ascontiguousarray(x), dtype=dtype, device="cuda:0")
+
+
+def host(t):
+    torch.cuda.synchronize()
+    return t.detach().cpu().numpy().astype(np.float64)
+
+
+@pytest.fixture(scope="module")
+def problems(krig):
+    """Eight uneven problems (n <= 2500), alternating FP32 / FP64 plans; problem 3
+    has two fields and the last problem reuses plan 0 with other data."""
+    ws = wl.uneven_batch(seed=4, count=7, nmax=2500)
+    out = []
+    for i, w in enumerate(ws):
+        dtype = "f32" if i % 2 == 0 else "f64"
+        say("uneven batch plan", i, w.name, dtype)
+        g = Grid(w.m1, w.m2, w.x0, w.y0, w.dx, w.dy, w.L)
+        k = Matern(w.sigma2, w.rho, w.nu, w.tau2)
+        rp = RapidPredictor(g, k, w.sites)
+        ek = ExactKriging(w.sites, k)
+        p = krig.plan_for(w, dtype)
+        p.set_weights(dev(np.stack([rp.i0, rp.j0], 1), torch.int32), dev(rp.W))
+        y = w.y if i != 3 else np.concatenate([w.y, -0.5 * w.y])
+        out.append(dict(w=w, g=g, k=k, rp=rp, ek=ek, p=p, y=dev(y), dtype=dtype))
+    last = dict(out[0])
+    last["y"] = dev(0.25 * out[0]["w"].y[::-1].copy())
+    out.append(last)
+    return out
+
+
+def reference(problems):
+    return [host(q["p"].predict(q["y"])) for q in problems]
+
+
+def test_problems_match_oracle(problems):
+    for i, q in enumerate(problems[:-1]):
+        say("uneven batch oracle", i, q["w"].name, q["dtype"])
+        yhat = host(q["p"].predict(q["y"]))
+        lag = lag_quadrant(q["g"], q["k"])
+        for b in range(yhat.shape[0]):
+            c = q["ek"].coef(host(q["y"])[b])
+            cimg = q["rp"].cstar(c)
+            ref = rapid_fft(q["g"], lag, cimg)
+            cancel = np.abs(cimg).sum() / np.abs(ref).max()
+            tol = (1e-12 if q["dtype"] == "f64" else 1e-5) * max(1.0, cancel / 2e4)
+            assert relmax(yhat[b], ref) < tol, (i, relmax(yhat[b], ref), cancel)
+
+
+def test_predict_many_bitwise(krig, problems):
+    say("predict_many")
+    ref = reference(problems)
+    outs = [q["p"].empty(q["y"].shape[0], q["w"].m1, q["w"].m2) for q in problems]
+    krig.predict_many([q["p"] for q in problems], [q["y"] for q in problems], outs)
+    for i, (o, r) in enumerate(zip(outs, ref)):
+        assert np.array_equal(host(o), r), i
+
+
+@pytest.mark.parametrize("lanes", [1, 3])
+def test_batch_graph_replays(krig, problems, lanes):
+    say("batch graph, lanes", lanes)
+    ref = reference(problems)
+    outs = [q["p"].empty(q["y"].shape[0], q["w"].m1, q["w"].m2) for q in problems]
+    bt = krig.Batch([q["p"] for q in problems], [q["y"] for q in problems], outs, lanes=lanes)
+    try:
+        for rep in range(3):
+            for o in outs:
+                o.fill_(float("nan"))  # a replay must write every output
+            torch.cuda.synchronize()
+            bt.launch()
+            torch.cuda.synchronize()
+            for i, (o, r) in enumerate(zip(outs, ref)):
+                assert np.array_equal(host(o), r), (rep, i)
+            # eager work on the same plans between replays
+            host(problems[1]["p"].predict(problems[1]["y"]))
+    finally:
+        bt.close()
+
+
+def test_batch_guards(krig, problems):
+    """While a batch exists its plans refuse destruction and workspace growth."""
+    say("batch guards")
+    q = problems[2]
+    p = q["p"]
+    outs = [p.empty(1, q["w"].m1, q["w"].m2)]
+    bt = krig.Batch([p], [q["y"]], outs, lanes=1)
+    try:
+        big = torch.zeros(64, p.n, dtype=torch.float64, device="cuda:0")
+        with pytest.raises(krig.KrigError) as e:
+            p.predict(big)
+        assert e.value.status == -1
+        assert p.lib.krig_plan_destroy(p.h) == -1
+        p.timing(True)
+        try:
+            with pytest.raises(krig.KrigError) as e:
+                krig.Batch([p], [q["y"]], outs, lanes=1)
+            assert e.value.status == -1
+        finally:
+            p.timing(False)
+    finally:
+        bt.close()
+    host(p.predict(torch.zeros(64, p.n, dtype=torch.float64, device="cuda:0")))  # grows now
