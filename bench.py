@@ -114,6 +114,7 @@ def main(argv=None):
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-fields", type=int, default=16)
     ap.add_argument("--no-fp64", action="store_true")
+    ap.add_argument("--no-autotune", action="store_true", help="keep plan_create's launch shapes")
     ap.add_argument("--calibrate-copy-mib", type=int, default=0,
                     help="only run a plain device copy of this many MiB (counter calibration) and exit")
     a = ap.parse_args(argv)
@@ -148,7 +149,10 @@ def main(argv=None):
         t0 = time.perf_counter()
         p = krig.plan_for(w, dtype)
         torch.cuda.synchronize()
-        return p, (time.perf_counter() - t0) * 1e3
+        t1 = time.perf_counter()
+        tuned = None if a.no_autotune else p.autotune(B, with_adjoint=True)
+        torch.cuda.synchronize()
+        return p, (t1 - t0) * 1e3, (time.perf_counter() - t1) * 1e3, tuned
 
     y = torch.as_tensor(w.y, dtype=torch.float64, device=dev)
 
@@ -180,7 +184,7 @@ def main(argv=None):
     mask = torch.as_tensor(w.extra["mask"], device=dev)
     res = {}
     for dtype in (("f32",) if a.no_fp64 else ("f32", "f64")):
-        p, setup_ms = setup(dtype)
+        p, setup_ms, tune_ms, tuned = setup(dtype)
         bf = buffers(p)
         p.predict(y, alpha_out=bf["alpha"], saved=bf["saved"], out=bf["yhat"])
         g = (2.0 * mask.to(p.tdtype) * bf["yhat"]).contiguous()  # upstream gradient, fixed over the steps
@@ -194,7 +198,7 @@ def main(argv=None):
         p.timing(False)
         run(p, bf, g, 1)
         torch.cuda.synchronize()
-        res[dtype] = dict(plan=p, ms=ms, hot_ms=hot_ms, setup_ms=setup_ms, stages=stages,
+        res[dtype] = dict(plan=p, ms=ms, hot_ms=hot_ms, setup_ms=setup_ms, tune_ms=tune_ms, tuned=tuned, stages=stages,
                           yhat=bf["yhat"].double().cpu().numpy(), dy=bf["dy"].cpu().numpy(),
                           dlag=bf["dlag"].double().cpu().numpy())
 
@@ -231,6 +235,8 @@ def main(argv=None):
                      "bytes_per_launch": sb[dom], "avg_launch_ms": avg[dom]},
         "hot_path_value": npred / (r32["hot_ms"] * 1e-3),
         "setup_ms": r32["setup_ms"],
+        "autotune_ms": r32["tune_ms"],
+        "launch_shapes": r32["tuned"],
         "stage_avg_ms": {k: round(v, 5) for k, v in avg.items()},
         "stage_gbs": {k: round(sb[k] / (avg[k] * 1e-3) / 1e9, 1) for k in sb if k in avg},
     }

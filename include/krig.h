@@ -87,7 +87,11 @@ enum {
   KRIG_INFO_NL_COLS64,  /* columns per block of the prediction and adjoint column passes */
   KRIG_INFO_FFT_R1,     /* factorisation F2 = R1 * R2 * R3 of the row transforms (R1 = 1: two stages) */
   KRIG_INFO_FFT_R2,
-  KRIG_INFO_FFT_R3
+  KRIG_INFO_FFT_R3,
+  KRIG_INFO_FFT_VARIANTS_ROWS, /* compiled forms of the row / column transform length */
+  KRIG_INFO_FFT_VARIANTS_COLS,
+  KRIG_INFO_FFT_VARIANT_ROWS,  /* form in use, 1-based (1: the default form) */
+  KRIG_INFO_FFT_VARIANT_COLS
 };
 
 /*
@@ -234,15 +238,36 @@ int krig_timing_read(krig_plan p, int32_t stage, double *total_ms, int64_t *laun
  *     fields per block means fewer partial spectra to write and sum.  It sets how the
  *     sum over fields of the lag gradient is grouped, so d lag changes by rounding
  *     only; the other outputs are bitwise the same.
- * Returns KRIG_EINVAL for an unknown key or a value outside those limits.
+ *   KRIG_TUNE_FFT_ROWS / _COLS: which compiled factorisation of the row / column
+ *     transform length to use, 1-based (1: the default; count via
+ *     KRIG_INFO_FFT_VARIANTS_*).  Resets that side's lines per block (and the field
+ *     grouping, for columns) to the form's defaults.  Outputs change by rounding.
+ * Returns KRIG_EINVAL for an unknown key, a value outside those limits, or while a
+ * recorded batch (krig_batch) holds the plan.
  */
 typedef enum {
   KRIG_TUNE_DLAG_GROUP = 1,
   KRIG_TUNE_NL_ROWS64,
   KRIG_TUNE_NL_ROWS32,
-  KRIG_TUNE_NL_COLS64
+  KRIG_TUNE_NL_COLS64,
+  KRIG_TUNE_FFT_ROWS,
+  KRIG_TUNE_FFT_COLS
 } krig_tune_key;
 int krig_plan_tune(krig_plan p, int32_t key, int64_t value);
+
+/*
+ * Autotuner: with B fields of synthetic data in temporary buffers, times
+ * krig_predict (and, if with_adjoint, krig_predict_adjoint with the saved spectra)
+ * on the plan's stream for each candidate value of every KRIG_TUNE_* key in turn
+ * (transform forms first, then lines per block and field grouping; candidates are
+ * the powers of two up to each key's limit and the limit itself).  Each timing is
+ * the median of three windows of ten calls; a candidate replaces the current value
+ * only when it is more than 1% faster.  The choice is recorded in a process-wide table keyed by grid, neighbour
+ * order, transform lengths and dtype; plans created later with the same key start
+ * from it.  Synchronises the plan's stream.  KRIG_EINVAL while stage timing is on or
+ * a recorded batch holds the plan.
+ */
+int krig_plan_autotune(krig_plan p, int32_t B, int32_t with_adjoint);
 
 /*
  * Uneven batch: predictions for several plans at once (different grids, sites,

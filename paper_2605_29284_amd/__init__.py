@@ -21,15 +21,16 @@ KRIG_F64 = 2
 
 INFO = dict(N=1, M=2, P1=3, P2=4, F1=5, F2=6, H2=7, LDH=8, SAVED_PER_FIELD=9, KN_STATUS=10,
             PIVOT=11, DTYPE=12, CE_CLAMPED=13, DLAG_GROUP=14, CE_F1=15, CE_F2=16, NL_ROWS64=17,
-            NL_ROWS32=18, NL_COLS64=19, FFT_R1=20, FFT_R2=21, FFT_R3=22)
-TUNE = dict(DLAG_GROUP=1, NL_ROWS64=2, NL_ROWS32=3, NL_COLS64=4)
+            NL_ROWS32=18, NL_COLS64=19, FFT_R1=20, FFT_R2=21, FFT_R3=22, FFT_VARIANTS_ROWS=23,
+            FFT_VARIANTS_COLS=24, FFT_VARIANT_ROWS=25, FFT_VARIANT_COLS=26)
+TUNE = dict(DLAG_GROUP=1, NL_ROWS64=2, NL_ROWS32=3, NL_COLS64=4, FFT_ROWS=5, FFT_COLS=6)
 
 STATUS = {0: "KRIG_OK", -1: "KRIG_EINVAL", -2: "KRIG_EDOMAIN", -3: "KRIG_ENOTSPD", -4: "KRIG_ECE",
           -5: "KRIG_ENOMEM", -6: "KRIG_EHIP", -7: "KRIG_EUNSUPPORTED"}
 
 EXPORTS = ["krig_plan_create", "krig_plan_destroy", "krig_plan_info", "krig_set_stream", "krig_weights",
            "krig_set_weights", "krig_lag", "krig_solve", "krig_scatter", "krig_convolve", "krig_predict",
-           "krig_predict_adjoint", "krig_csim", "krig_plan_tune", "krig_predict_many", "krig_batch_create",
+           "krig_predict_adjoint", "krig_csim", "krig_plan_tune", "krig_plan_autotune", "krig_predict_many", "krig_batch_create",
            "krig_batch_launch", "krig_batch_destroy", "krig_timing_enable", "krig_timing_read", "krig_strerror"]
 
 STAGES = ["ROWS_FWD", "COLS_CONV", "ROWS_INV", "ADJ_ROWS_FWD", "ADJ_COLS", "ADJ_ROWS_INV", "GATHER", "SOLVE",
@@ -80,6 +81,7 @@ def load_library(path: str = LIB_PATH) -> ctypes.CDLL:
         "krig_predict_adjoint": [vp, i32, dp, dp, dp, dp, dp, dp],
         "krig_csim": [vp, i32, ctypes.c_uint64, dp, dp],
         "krig_plan_tune": [vp, i32, i64],
+        "krig_plan_autotune": [vp, i32, i32],
         "krig_predict_many": [ctypes.POINTER(vp), i32, ctypes.POINTER(i32), ctypes.POINTER(vp), ctypes.POINTER(vp), vp],
         "krig_batch_create": [ctypes.POINTER(vp), ctypes.POINTER(vp), i32, ctypes.POINTER(i32), ctypes.POINTER(vp),
                               ctypes.POINTER(vp), i32, vp],
@@ -273,6 +275,14 @@ class Plan:
         """Set a launch shape (TUNE key): speed only, apart from DLAG_GROUP, which regroups the
         sum over fields of d lag (rounding-level change)."""
         _check(self.lib.krig_plan_tune(self.h, TUNE[key], ctypes.c_int64(int(value))), "krig_plan_tune")
+
+    def autotune(self, B: int, with_adjoint: bool = True):
+        """Time the launch-shape candidates on B synthetic fields and keep the fastest
+        (krig_plan_autotune); later plans of the same shape start from the choice."""
+        self._stream()
+        _check(self.lib.krig_plan_autotune(self.h, int(B), 1 if with_adjoint else 0), "krig_plan_autotune")
+        return {k: self.info(k) for k in ("FFT_VARIANT_ROWS", "FFT_VARIANT_COLS", "NL_ROWS64", "NL_ROWS32",
+                                          "NL_COLS64", "DLAG_GROUP")}
 
     def timing(self, on: bool):
         """Bracket every stage launch with HIP events on the plan's stream."""

@@ -194,6 +194,8 @@ struct FftEntry {
 // size registry (filled by the generated per-size translation units)
 void register_fft(const FftEntry& e);
 const FftEntry* find_fft(int F);
+// every compiled form of length F, the default first; returns the count
+int fft_variants(int F, const FftEntry** out, int cap);
 int fft_sizes(int* out, int cap);
 void register_all_fft();
 

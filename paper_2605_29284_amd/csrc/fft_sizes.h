@@ -9,3 +9,10 @@
   X(1, 16, 8) X(1, 12, 12) X(1, 16, 12) X(1, 16, 16) X(1, 18, 16) X(8, 8, 6) X(8, 8, 8)      \
   X(8, 9, 8) X(8, 12, 8) X(8, 12, 9) X(8, 16, 8) X(8, 12, 12) X(8, 16, 12) X(16, 16, 8)      \
   X(16, 12, 12) X(16, 16, 12)
+
+// Further factorisations of some lengths, compiled as well: the default (first) form
+// of each length comes from the list above; krig_plan_tune / krig_plan_autotune may
+// switch a plan's row or column transforms to one of these.
+#define KRIG_FFT_VARIANTS(X)                                                                  \
+  X(1, 24, 16) X(1, 32, 16) X(1, 24, 24) X(12, 8, 8) X(8, 8, 12) X(1, 32, 24) X(1, 36, 24)   \
+  X(16, 8, 8) X(12, 12, 8) X(1, 36, 32) X(12, 16, 12)

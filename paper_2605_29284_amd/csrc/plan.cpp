@@ -6,6 +6,8 @@
 #include <string.h>
 
 #include <algorithm>
+#include <map>
+#include <tuple>
 #include <mutex>
 #include <new>
 #include <vector>
@@ -40,6 +42,7 @@ struct krig_plan_s {
   int n1l = 0, n2l = 0;
   const FftEntry* e1 = nullptr;  // columns (length F1)
   const FftEntry* e2 = nullptr;  // rows (length F2)
+  int var_cols = 0, var_rows = 0;  // which compiled form of F1 / F2 (0: the default)
   // twiddles exp(-2 pi i j / F)
   double* tw1_64 = nullptr;
   double* tw2_64 = nullptr;
@@ -519,6 +522,73 @@ int ce_setup(krig_plan p) {
   }
 }
 
+// default launch shapes for the current row / column transform forms
+void default_rows_shapes(krig_plan p) {
+  p->nl_rows64 = nl_rows_for(p->e2, 16);
+  p->nl_rows32 = nl_rows_for(p->e2, 8);
+}
+void default_cols_shapes(krig_plan p) {
+  p->nl_cols64 = nl_cols_for(p->e1, 16);
+  p->dlag_G = p->nl_cols64;
+}
+
+// switch the row (rows = true) or column transforms to compiled form idx of their
+// length; the launch shapes of that side return to the form's defaults
+int set_variant(krig_plan p, bool rows, int idx) {
+  const FftEntry* v[16];
+  const int F = rows ? p->F2 : p->F1;
+  const int k = fft_variants(F, v, 16);
+  if (idx < 0 || idx >= k || idx >= 16) return KRIG_EINVAL;
+  if (rows) {
+    if (rows_lds(v[idx]->geo, nl_rows_for(v[idx], 16), 16) > 64 * 1024) return KRIG_EINVAL;
+    p->e2 = v[idx];
+    p->var_rows = idx;
+    default_rows_shapes(p);
+  } else {
+    if (cols_lds(v[idx]->geo, nl_cols_for(v[idx], 16), 16) > 64 * 1024) return KRIG_EINVAL;
+    p->e1 = v[idx];
+    p->var_cols = idx;
+    default_cols_shapes(p);
+  }
+  return KRIG_OK;
+}
+
+// Process-wide table of autotuned launch shapes, keyed by what the kernels depend on:
+// grid, neighbour order, transform lengths and dtype.
+struct TuneKey {
+  int m1, m2, L, F1, F2, dtype;
+  bool operator<(const TuneKey& o) const {
+    return std::tie(m1, m2, L, F1, F2, dtype) < std::tie(o.m1, o.m2, o.L, o.F1, o.F2, o.dtype);
+  }
+};
+struct TuneRec {
+  int var_rows, var_cols, nl_rows64, nl_rows32, nl_cols64, dlag_G;
+};
+std::mutex& tune_mutex() {
+  static std::mutex m;
+  return m;
+}
+std::map<TuneKey, TuneRec>& tune_table() {
+  static std::map<TuneKey, TuneRec> t;
+  return t;
+}
+TuneKey tune_key(krig_plan p) { return TuneKey{p->g.m1, p->g.m2, p->g.L, p->F1, p->F2, p->dtype}; }
+
+void tuned_lookup(krig_plan p) {
+  TuneRec r;
+  {
+    std::lock_guard<std::mutex> lk(tune_mutex());
+    auto it = tune_table().find(tune_key(p));
+    if (it == tune_table().end()) return;
+    r = it->second;
+  }
+  if (set_variant(p, true, r.var_rows) != KRIG_OK || set_variant(p, false, r.var_cols) != KRIG_OK) return;
+  p->nl_rows64 = r.nl_rows64;
+  p->nl_rows32 = r.nl_rows32;
+  p->nl_cols64 = r.nl_cols64;
+  p->dlag_G = r.dlag_G;
+}
+
 }  // namespace
 
 // =====================================================================================
@@ -592,10 +662,9 @@ int krig_plan_create(krig_plan* out, const krig_grid* g, const krig_matern* k, i
   p->ldX = pitch16(2 * (g->m1 + g->L) - 1);
   const bool f32 = dtype == KRIG_F32;
   // launch shapes (lines per block) within 256 threads and 64 KB of LDS
-  p->nl_rows64 = nl_rows_for(p->e2, 16);
-  p->nl_rows32 = nl_rows_for(p->e2, 8);
-  p->nl_cols64 = nl_cols_for(p->e1, 16);
-  p->dlag_G = p->nl_cols64;
+  default_rows_shapes(p);
+  default_cols_shapes(p);
+  tuned_lookup(p);
   if (rows_lds(p->e2->geo, p->nl_rows64, 16) > 64 * 1024 || cols_lds(p->e1->geo, p->nl_cols64, 16) > 64 * 1024) {
     delete p;
     return KRIG_EUNSUPPORTED;
@@ -691,6 +760,11 @@ int krig_plan_create(krig_plan* out, const krig_grid* g, const krig_matern* k, i
     destroy_all(p);
     return KRIG_ENOTSPD;
   }
+  // the factor itself and its panel workspaces are not needed after set-up
+  dfree(p, p->Lfac);
+  dfree(p, p->Dinv);
+  dfree(p, p->work);
+  p->Lfac = p->Dinv = p->work = nullptr;
   *out = p;
   return KRIG_OK;
 #undef CK
@@ -723,6 +797,10 @@ int krig_plan_info(krig_plan p, int32_t what, int64_t* v) {
     case KRIG_INFO_NL_ROWS64: *v = p->nl_rows64; break;
     case KRIG_INFO_NL_ROWS32: *v = p->nl_rows32; break;
     case KRIG_INFO_NL_COLS64: *v = p->nl_cols64; break;
+    case KRIG_INFO_FFT_VARIANTS_ROWS: *v = fft_variants(p->F2, nullptr, 0); break;
+    case KRIG_INFO_FFT_VARIANTS_COLS: *v = fft_variants(p->F1, nullptr, 0); break;
+    case KRIG_INFO_FFT_VARIANT_ROWS: *v = p->var_rows + 1; break;
+    case KRIG_INFO_FFT_VARIANT_COLS: *v = p->var_cols + 1; break;
     case KRIG_INFO_FFT_R1: *v = p->e2->geo.R1; break;
     case KRIG_INFO_FFT_R2: *v = p->e2->geo.R2; break;
     case KRIG_INFO_FFT_R3: *v = p->e2->geo.R3; break;
@@ -952,6 +1030,7 @@ int krig_predict_adjoint(krig_plan p, int32_t B, const void* d_g, const double* 
 
 int krig_plan_tune(krig_plan p, int32_t key, int64_t value) {
   if (!p || value < 1 || value > 256) return KRIG_EINVAL;
+  if (p->batch_refs > 0) return KRIG_EINVAL;  // a recorded graph holds the current launches
   const int v = (int)value;
   switch (key) {
     case KRIG_TUNE_DLAG_GROUP:
@@ -970,8 +1049,128 @@ int krig_plan_tune(krig_plan p, int32_t key, int64_t value) {
       if (v * nt_of(p->e1) > 256 || cols_lds(p->e1->geo, v, 16) > 64 * 1024) return KRIG_EINVAL;
       p->nl_cols64 = v;
       return KRIG_OK;
+    case KRIG_TUNE_FFT_ROWS:
+    case KRIG_TUNE_FFT_COLS: return set_variant(p, key == KRIG_TUNE_FFT_ROWS, (int)value - 1);
     default: return KRIG_EINVAL;
   }
+}
+
+int krig_plan_autotune(krig_plan p, int32_t B, int32_t with_adjoint) {
+  if (!p || B < 1 || p->timing || p->batch_refs > 0) return KRIG_EINVAL;
+  int r;
+  if ((r = ensure_ws(p, B)) != KRIG_OK) return r;
+  if (with_adjoint && (r = ensure_ws_adj(p, B)) != KRIG_OK) return r;
+  const size_t npix = (size_t)B * p->g.m1 * p->g.m2;
+  double *y = nullptr, *alpha = nullptr, *dy = nullptr;
+  void *yhat = nullptr, *gup = nullptr, *dlag = nullptr;
+  hipEvent_t e0 = nullptr, e1 = nullptr;
+  auto cleanup = [&]() {
+    for (void* q : {(void*)y, (void*)alpha, (void*)dy, yhat, gup, dlag}) dfree(p, q);
+    if (e0) (void)hipEventDestroy(e0);
+    if (e1) (void)hipEventDestroy(e1);
+  };
+  if ((r = dalloc(p, &y, (size_t)B * p->n)) != KRIG_OK || (r = dalloc(p, &alpha, (size_t)B * p->n)) != KRIG_OK ||
+      (r = dalloc(p, &dy, (size_t)B * p->n)) != KRIG_OK || (r = dalloc_bytes(p, &yhat, p->tsz * npix)) != KRIG_OK ||
+      (r = dalloc_bytes(p, &gup, p->tsz * npix)) != KRIG_OK ||
+      (r = dalloc_bytes(p, &dlag, p->tsz * (size_t)p->n1l * p->n2l)) != KRIG_OK) {
+    cleanup();
+    return r;
+  }
+  if (fill_f64(y, (int64_t)B * p->n, 1.0, p->st) != hipSuccess || hipMemsetAsync(gup, 0, p->tsz * npix, p->st) != hipSuccess ||
+      hipEventCreate(&e0) != hipSuccess || hipEventCreate(&e1) != hipSuccess) {
+    cleanup();
+    return KRIG_EHIP;
+  }
+  auto step = [&]() -> int {
+    int q = krig_predict(p, B, y, nullptr, yhat, alpha, p->S1);
+    if (q == KRIG_OK && with_adjoint) q = krig_predict_adjoint(p, B, gup, alpha, p->S1, nullptr, dy, dlag);
+    return q;
+  };
+  // median of three windows of ten steps, after two warm-up steps
+  auto measure = [&](double* ms) -> int {
+    for (int i = 0; i < 2; ++i)
+      if (int q = step()) return q;
+    double w[3];
+    for (int j = 0; j < 3; ++j) {
+      if (hipEventRecord(e0, p->st) != hipSuccess) return KRIG_EHIP;
+      for (int i = 0; i < 10; ++i)
+        if (int q = step()) return q;
+      if (hipEventRecord(e1, p->st) != hipSuccess || hipEventSynchronize(e1) != hipSuccess) return KRIG_EHIP;
+      float t = 0.f;
+      if (hipEventElapsedTime(&t, e0, e1) != hipSuccess) return KRIG_EHIP;
+      w[j] = t / 10.0;
+    }
+    std::sort(w, w + 3);
+    *ms = w[1];
+    return KRIG_OK;
+  };
+  auto current = [&](int key) -> int {
+    switch (key) {
+      case KRIG_TUNE_FFT_ROWS: return p->var_rows + 1;
+      case KRIG_TUNE_FFT_COLS: return p->var_cols + 1;
+      case KRIG_TUNE_NL_ROWS64: return p->nl_rows64;
+      case KRIG_TUNE_NL_ROWS32: return p->nl_rows32;
+      case KRIG_TUNE_NL_COLS64: return p->nl_cols64;
+      default: return p->dlag_G;
+    }
+  };
+  const int keys[] = {KRIG_TUNE_FFT_ROWS, KRIG_TUNE_FFT_COLS, KRIG_TUNE_NL_ROWS64,
+                      KRIG_TUNE_NL_ROWS32, KRIG_TUNE_NL_COLS64, KRIG_TUNE_DLAG_GROUP};
+  for (int key : keys) {
+    if (key == KRIG_TUNE_DLAG_GROUP && !with_adjoint) continue;
+    std::vector<int> cand;
+    if (key == KRIG_TUNE_FFT_ROWS || key == KRIG_TUNE_FFT_COLS) {
+      const int k = fft_variants(key == KRIG_TUNE_FFT_ROWS ? p->F2 : p->F1, nullptr, 0);
+      for (int v = 1; v <= k; ++v) cand.push_back(v);
+    } else {
+      for (int v = 1; v <= 256; v *= 2) cand.push_back(v);
+      for (int v = 256; v >= 1; --v)  // the largest value the key accepts
+        if (krig_plan_tune(p, key, v) == KRIG_OK) {
+          if (std::find(cand.begin(), cand.end(), v) == cand.end()) cand.push_back(v);
+          break;
+        }
+    }
+    // a transform form resets its side's shapes: remember them with the form
+    const int keep = current(key);
+    const int s64 = p->nl_rows64, s32 = p->nl_rows32, sc = p->nl_cols64, sg = p->dlag_G;
+    // the current value first; another replaces it only if more than 1% faster
+    double keep_ms = 1e300;
+    if (krig_plan_tune(p, key, keep) == KRIG_OK && (r = measure(&keep_ms)) != KRIG_OK) {
+      cleanup();
+      return r;
+    }
+    int best = keep;
+    double best_ms = keep_ms;
+    for (int v : cand) {
+      if (v == keep || krig_plan_tune(p, key, v) != KRIG_OK) continue;
+      double ms = 0;
+      if ((r = measure(&ms)) != KRIG_OK) {
+        cleanup();
+        return r;
+      }
+      if (ms < 0.99 * best_ms) {
+        best_ms = ms;
+        best = v;
+      }
+    }
+    krig_plan_tune(p, key, best);
+    if ((key == KRIG_TUNE_FFT_ROWS || key == KRIG_TUNE_FFT_COLS) && best == keep) {
+      p->nl_rows64 = s64;
+      p->nl_rows32 = s32;
+      p->nl_cols64 = sc;
+      p->dlag_G = sg;
+    }
+  }
+  if (hipStreamSynchronize(p->st) != hipSuccess) {
+    cleanup();
+    return KRIG_EHIP;
+  }
+  cleanup();
+  {
+    std::lock_guard<std::mutex> lk(tune_mutex());
+    tune_table()[tune_key(p)] = TuneRec{p->var_rows, p->var_cols, p->nl_rows64, p->nl_rows32, p->nl_cols64, p->dlag_G};
+  }
+  return KRIG_OK;
 }
 
 int krig_timing_enable(krig_plan p, int32_t on) {

@@ -370,6 +370,48 @@ def test_launch_shapes(krig, paper, dtype):
         assert e.value.status == -1
 
 
+def test_fft_variants_match_oracle(krig, paper):
+    """Every compiled form of the 768-point transforms, on rows and on columns, gives
+    the FP64 oracle's prediction (oracle weights injected) and the same adjoint."""
+    w, (g, k, rp, ek) = paper
+    p = krig.plan_for(w, "f64")
+    p.set_weights(dev(np.stack([rp.i0, rp.j0], 1), torch.int32), dev(rp.W))
+    alpha = ek.coef(w.y)
+    cimg = rp.cstar(alpha[0])
+    ref = rapid_fft(g, lag_quadrant(g, k), cimg)
+    cancel = np.abs(cimg).sum() / np.abs(ref).max()
+    gup = dev(np.random.default_rng(3).standard_normal((1, w.m1, w.m2)))
+    base_dy, base_dlag = (host(t) for t in p.adjoint(gup, alpha=dev(alpha)))
+    nr, nc = p.info("FFT_VARIANTS_ROWS"), p.info("FFT_VARIANTS_COLS")
+    assert nr >= 2 and nc >= 2
+    for side, count in (("FFT_ROWS", nr), ("FFT_COLS", nc)):
+        for v in range(1, count + 1):
+            say("fft variant", side, v)
+            p.tune(side, v)
+            y = host(p.convolve(dev(alpha)))[0]
+            assert relmax(y, ref) < 1e-12 * max(1.0, cancel / 2e4), (side, v, relmax(y, ref))
+            dy, dlag = (host(t) for t in p.adjoint(gup, alpha=dev(alpha)))
+            # dy carries the rounding of the transforms times cond(K + tau^2 I) (~1e4 here)
+            assert relmax(dy, base_dy) < 1e-10 and relmax(dlag, base_dlag) < 1e-12, (side, v)
+        p.tune(side, 1)
+
+
+def test_autotune(krig, small):
+    """The autotuner keeps results within the plan's tolerance and later plans of the
+    same shape start from its choice."""
+    w, (g, k, rp, ek) = small
+    say("autotune small field f32")
+    p = krig.plan_for(w, "f32")
+    chosen = p.autotune(2, with_adjoint=True)
+    for key, v in chosen.items():
+        assert v >= 1, (key, v)
+    y = host(p.predict(dev(w.y)))[0]
+    ref = rp.predict_direct(ek.coef(w.y[0])).reshape(w.m1, w.m2)
+    assert relmax(y, ref) < 1e-5
+    q = krig.plan_for(w, "f32")
+    assert {key: q.info(key) for key in chosen} == chosen
+
+
 def test_error_paths(krig):
     say("error paths")
     w = wl.tiny(seed=1, m1=10, m2=10, L=2, n=5)
