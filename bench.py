@@ -57,16 +57,16 @@ def recorded_traffic(stage):
 
 def stage_bytes(p, B, ngroups):
     """Algorithmic bytes per launch of each timed single-kernel stage: what the pass must
-    read and write once (FP64 row spectra and adjoint, dt forward tail and outputs)."""
+    read and write once (FP64 spectra between the passes, the plan's dtype for the
+    caller's arrays)."""
     t = 4 if p.dtype_code == 1 else 8      # dt value
-    c = 2 * t                               # dt complex
     z = 16                                  # FP64 complex
     m1, m2, n, M = p.m1, p.m2, p.n, p.M
     P1, P2, F1, H2 = p.P1, p.P2, p.F1, p.info("H2")
     return {
         "ROWS_FWD": B * (H2 * P1 * z + n * 8) + (P1 * P2 + 1) * 4 + n * M * 12,
-        "COLS_CONV": B * (H2 * P1 * z + H2 * m1 * c) + H2 * F1 * 8,
-        "ROWS_INV": B * (H2 * m1 * c + m1 * m2 * t),
+        "COLS_CONV": B * (H2 * P1 * z + H2 * m1 * z) + H2 * F1 * 8,
+        "ROWS_INV": B * (H2 * m1 * z + m1 * m2 * t),
         "ADJ_ROWS_FWD": B * (m1 * m2 * t + H2 * m1 * z),
         # the summed lag-gradient spectrum once (per-group partials are an implementation choice)
         "ADJ_COLS": B * (H2 * m1 * z + 2 * H2 * P1 * z) + H2 * F1 * z + H2 * F1 * 8,
@@ -105,6 +105,82 @@ def cpu_baseline(w, nfields: int, reps: int = 6):
                       f"oracle's FP64 FFT variants, one thread, {dt:.1f} s"}
 
 
+def uneven(a, torch, krig, wl, dev):
+    """The 64-problem uneven batch (grids 128^2..1024^2, n 500..20000, L 2..4, nu 0.5..2.5),
+    recorded once as a HIP graph and replayed; FP32 plans against FP64 plans, one dtype at a
+    time (their inverse factors take tens of GB).  Prints one JSON line."""
+    ws = wl.uneven_batch(seed=4, count=a.uneven_count)
+    print(f"[uneven] {len(ws)} problems generated", file=sys.stderr, flush=True)
+    npred = sum(w.m1 * w.m2 for w in ws)
+    out = {"metric": "grid predictions/s, uneven batch of %d problems (one graph launch)" % len(ws),
+           "unit": "grid predictions/s", "n_gpus": 1, "higher_is_better": True, "data": "synthetic",
+           "config": {"workload": "uneven batch: grids from {128,256,384,512,1024}^2, n log-uniform in "
+                                  "[500, 20000], L in {2,3,4}, nu in {0.5,1.5,2.5}, range U[0.05,0.3], nugget 0.01",
+                      "problems": len(ws), "grid_points": npred, "n_max": max(w.sites.shape[0] for w in ws)}}
+    res = {}
+    for dtype in ("f32", "f64"):
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        plans = []
+        for i, w in enumerate(ws):
+            plans.append(krig.plan_for(w, dtype))
+            if i % 8 == 7:
+                torch.cuda.synchronize()
+                print(f"[uneven] {dtype}: {i + 1} plans, {time.perf_counter() - t0:.1f} s", file=sys.stderr, flush=True)
+        torch.cuda.synchronize()
+        t1 = time.perf_counter()
+        if not a.no_autotune:
+            for i, p in enumerate(plans):
+                p.autotune(1, with_adjoint=False)
+                if i % 8 == 7:
+                    print(f"[uneven] {dtype}: {i + 1} tuned, {time.perf_counter() - t1:.1f} s", file=sys.stderr, flush=True)
+        torch.cuda.synchronize()
+        t2 = time.perf_counter()
+        ys = [torch.as_tensor(w.y, dtype=torch.float64, device=dev) for w in ws]
+        outs = [p.empty(1, w.m1, w.m2) for p, w in zip(plans, ws)]
+        bt = krig.Batch(plans, ys, outs, lanes=4)
+        for _ in range(a.warmup):
+            bt.launch()
+        s, e = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        torch.cuda.synchronize()
+        s.record()
+        for _ in range(a.steps):
+            bt.launch()
+        e.record()
+        torch.cuda.synchronize()
+        ms = s.elapsed_time(e) / a.steps
+        # the same problems one plan after another, no graph
+        torch.cuda.synchronize()
+        s.record()
+        for _ in range(a.steps):
+            for p, y, o in zip(plans, ys, outs):
+                p.predict(y, out=o)
+        e.record()
+        torch.cuda.synchronize()
+        ms_eager = s.elapsed_time(e) / a.steps
+        res[dtype] = dict(ms=ms, ms_eager=ms_eager, setup_s=t1 - t0, tune_s=t2 - t1,
+                          y=[o.double().cpu().numpy() for o in outs])
+        bt.close()
+        del bt, plans, outs
+        torch.cuda.synchronize()
+        torch.cuda.empty_cache()
+    r32, r64 = res["f32"], res["f64"]
+    errs = [float(np.max(np.abs(a_ - b_)) / np.max(np.abs(b_))) for a_, b_ in zip(r32["y"], r64["y"])]
+    err = max(errs)
+    worst = sorted(range(len(ws)), key=lambda i: -errs[i])[:5]
+    out["worst_problems"] = [{"problem": ws[i].name, "rel_err": errs[i]} for i in worst]
+    out["problems_over_1e-5"] = sum(e > 1e-5 for e in errs)
+    out.update({"value": npred / (r32["ms"] * 1e-3), "ms_per_step": r32["ms"], "steps": a.steps,
+                "warmup": a.warmup, "dtype": "f64", "io_dtype": "f32", "scaling": "weak", "vs_baseline": None,
+                "fp64_value": npred / (r64["ms"] * 1e-3), "fp64_ms_per_step": r64["ms"],
+                "eager_ms_per_step": {"f32": r32["ms_eager"], "f64": r64["ms_eager"]},
+                "fp32_vs_fp64_rel_err": err,
+                "setup_s": {"f32": r32["setup_s"], "f64": r64["setup_s"]},
+                "autotune_s": {"f32": r32["tune_s"], "f64": r64["tune_s"]}})
+    print(json.dumps(out), flush=True)
+    return 0
+
+
 def main(argv=None):
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -115,6 +191,8 @@ def main(argv=None):
     ap.add_argument("--cpu-fields", type=int, default=16)
     ap.add_argument("--no-fp64", action="store_true")
     ap.add_argument("--no-autotune", action="store_true", help="keep plan_create's launch shapes")
+    ap.add_argument("--uneven", action="store_true", help="time the 64-problem uneven batch instead")
+    ap.add_argument("--uneven-count", type=int, default=64)
     ap.add_argument("--calibrate-copy-mib", type=int, default=0,
                     help="only run a plain device copy of this many MiB (counter calibration) and exit")
     a = ap.parse_args(argv)
@@ -141,6 +219,8 @@ def main(argv=None):
         torch.cuda.synchronize()
         print(json.dumps({"calibration_copy_bytes": 4 * n, "copies": 3}), flush=True)
         return 0
+    if a.uneven:
+        return uneven(a, torch, krig, wl, dev)
     w = wl.grad_batch(B=a.B)
     B = a.B
 
@@ -224,7 +304,9 @@ def main(argv=None):
         "higher_is_better": True,
         "scaling": "weak",
         "vs_baseline": None,
-        "dtype": "f32",
+        # both plans compute in FP64; the FP32 plan's lag, g, y_hat and d lag are FP32
+        "dtype": "f64",
+        "io_dtype": "f32",
         "data": "synthetic",
         "config": {"workload": "grad-batch: paper-sized field, n=1368 sites on [0,2]x[0,1], Matern nu=2.5 "
                                "range 0.3 nugget 0.05, 350x350 grid, L=3 (M=36), B=16 fields, "

@@ -82,8 +82,7 @@ enum {
   KRIG_INFO_DLAG_GROUP, /* fields per block in the lag-gradient column pass */
   KRIG_INFO_CE_F1,      /* circulant-embedding torus size (0 before the first krig_csim) */
   KRIG_INFO_CE_F2,
-  KRIG_INFO_NL_ROWS64,  /* lines (row pairs) per block of the FP64 row passes */
-  KRIG_INFO_NL_ROWS32,  /* lines per block of the FP32 row passes */
+  KRIG_INFO_NL_ROWS64,  /* lines (row pairs) per block of the row passes */
   KRIG_INFO_NL_COLS64,  /* columns per block of the prediction and adjoint column passes */
   KRIG_INFO_FFT_R1,     /* factorisation F2 = R1 * R2 * R3 of the row transforms (R1 = 1: two stages) */
   KRIG_INFO_FFT_R2,
@@ -230,7 +229,7 @@ int krig_timing_read(krig_plan p, int32_t stage, double *total_ms, int64_t *laun
 /*
  * Launch shapes.  plan_create picks defaults; a caller or an autotuner may change
  * them between calls.
- *   KRIG_TUNE_NL_ROWS64 / _ROWS32 / _COLS64: lines or columns per block, >= 1, with
+ *   KRIG_TUNE_NL_ROWS64 / _COLS64: lines or columns per block, >= 1, with
  *     at most 256 threads and 64 KB of LDS per block.  Every line's arithmetic is
  *     unchanged, so results are bitwise the same for any value.
  *   KRIG_TUNE_DLAG_GROUP: fields per block in the lag-gradient column pass (one
@@ -248,7 +247,6 @@ int krig_timing_read(krig_plan p, int32_t stage, double *total_ms, int64_t *laun
 typedef enum {
   KRIG_TUNE_DLAG_GROUP = 1,
   KRIG_TUNE_NL_ROWS64,
-  KRIG_TUNE_NL_ROWS32,
   KRIG_TUNE_NL_COLS64,
   KRIG_TUNE_FFT_ROWS,
   KRIG_TUNE_FFT_COLS

@@ -805,12 +805,11 @@ FftEntry make_fft_entry() {
   k.r2c_dense_f32 = launch_rows_r2c<double, float, double, R1, R2, R3, SRC_DENSE>;
   k.r2c_dense_f64 = launch_rows_r2c<double, double, double, R1, R2, R3, SRC_DENSE>;
   k.r2c_lag = launch_rows_r2c<double, double, double, R1, R2, R3, SRC_LAG>;
-  k.conv_mixed = launch_cols<double, float, double, float, R1, R2, R3, COL_CONV>;
   k.conv64 = launch_cols<double, double, double, double, R1, R2, R3, COL_CONV>;
   k.conv_dlag64 = launch_cols<double, double, double, double, R1, R2, R3, COL_CONV_DLAG>;
   k.fwd_real64 = launch_cols<double, double, double, double, R1, R2, R3, COL_FWD_REAL>;
   k.inv_sum64 = launch_cols<double, double, double, double, R1, R2, R3, COL_INV_SUM>;
-  k.c2r32 = launch_rows_c2r<float, float, float, R1, R2, R3>;
+  k.c2r64_32 = launch_rows_c2r<double, double, float, R1, R2, R3>;
   k.c2r64 = launch_rows_c2r<double, double, double, R1, R2, R3>;
   k.c2r_fold32 = launch_rows_c2r_fold<double, float, R1, R2, R3>;
   k.c2r_fold64 = launch_rows_c2r_fold<double, double, R1, R2, R3>;

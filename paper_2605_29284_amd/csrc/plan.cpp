@@ -90,7 +90,6 @@ struct krig_plan_s {
   double* phiS64 = nullptr;  // cx double [H2][F1]
   // launch shapes
   int nl_rows64 = 4;   // lines per block, FP64 row kernels
-  int nl_rows32 = 8;   // FP32 row kernels
   int nl_cols64 = 4;   // columns per block, FP64-forward column kernels
   int dlag_G = 1;       // fields per block of the lag-gradient column pass
   // conditional simulation (set up on the first krig_csim call)
@@ -277,11 +276,10 @@ int ensure_ws(krig_plan p, int B) {
   void* olds[] = {p->S1, p->S2, p->alpha, p->tmpv, p->tripart};
   KRIG_TRY(hipStreamSynchronize(p->st));
   for (void* q : olds) dfree(p, q);
-  const size_t c = csz(p);
   const size_t H2 = p->H2;
   int r;
   if ((r = dalloc_bytes(p, &p->S1, 16 * (size_t)B * H2 * p->ldP)) != KRIG_OK) return r;
-  if ((r = dalloc_bytes(p, &p->S2, c * (size_t)B * H2 * p->ldM)) != KRIG_OK) return r;
+  if ((r = dalloc_bytes(p, &p->S2, 16 * (size_t)B * H2 * p->ldM)) != KRIG_OK) return r;
   if ((r = dalloc(p, &p->alpha, (size_t)B * p->n)) != KRIG_OK) return r;
   if ((r = dalloc(p, &p->tmpv, (size_t)B * p->n)) != KRIG_OK) return r;
   if ((r = dalloc(p, &p->tripart, tri_part_size(p->n, B))) != KRIG_OK) return r;
@@ -361,13 +359,13 @@ int do_convolve(krig_plan p, int B, const double* alpha, const double* filt, voi
   c.out_fs = (int64_t)p->H2 * p->ldM;
   c.out_ld = p->ldM;
   c.rows = Window{p->g.L, p->g.m1, 0, 0};
-  c.twF = p->tw1_64;  // forward column transform in FP64
-  c.twI = is32(p) ? (const void*)p->tw1_32 : (const void*)p->tw1_64;
+  c.twF = p->tw1_64;  // FP64 column transforms for both dtypes
+  c.twI = p->tw1_64;
   c.B = B;
   c.NL = p->nl_cols64;
   {
     StageTimer t(p, KRIG_STAGE_COLS_CONV);
-    KRIG_TRY((is32(p) ? set1(p).conv_mixed : set1(p).conv64)(c, B, p->st));
+    KRIG_TRY(set1(p).conv64(c, B, p->st));
   }
 
   RowsC2RArgs o{};
@@ -385,11 +383,11 @@ int do_convolve(krig_plan p, int B, const double* alpha, const double* filt, voi
   o.add_ld = add_ld;
   o.add_r0 = p->g.L;
   o.add_c0 = p->g.L;
-  o.twF = is32(p) ? (const void*)p->tw2_32 : (const void*)p->tw2_64;
-  o.NL = is32(p) ? p->nl_rows32 : p->nl_rows64;
+  o.twF = p->tw2_64;  // FP64 arithmetic; the FP32 form only writes FP32
+  o.NL = p->nl_rows64;
   {
     StageTimer t(p, KRIG_STAGE_ROWS_INV);
-    KRIG_TRY((is32(p) ? set2(p).c2r32 : set2(p).c2r64)(o, B, p->st));
+    KRIG_TRY((is32(p) ? set2(p).c2r64_32 : set2(p).c2r64)(o, B, p->st));
   }
   return KRIG_OK;
 }
@@ -525,7 +523,6 @@ int ce_setup(krig_plan p) {
 // default launch shapes for the current row / column transform forms
 void default_rows_shapes(krig_plan p) {
   p->nl_rows64 = nl_rows_for(p->e2, 16);
-  p->nl_rows32 = nl_rows_for(p->e2, 8);
 }
 void default_cols_shapes(krig_plan p) {
   p->nl_cols64 = nl_cols_for(p->e1, 16);
@@ -562,7 +559,7 @@ struct TuneKey {
   }
 };
 struct TuneRec {
-  int var_rows, var_cols, nl_rows64, nl_rows32, nl_cols64, dlag_G;
+  int var_rows, var_cols, nl_rows64, nl_cols64, dlag_G;
 };
 std::mutex& tune_mutex() {
   static std::mutex m;
@@ -584,7 +581,6 @@ void tuned_lookup(krig_plan p) {
   }
   if (set_variant(p, true, r.var_rows) != KRIG_OK || set_variant(p, false, r.var_cols) != KRIG_OK) return;
   p->nl_rows64 = r.nl_rows64;
-  p->nl_rows32 = r.nl_rows32;
   p->nl_cols64 = r.nl_cols64;
   p->dlag_G = r.dlag_G;
 }
@@ -795,7 +791,6 @@ int krig_plan_info(krig_plan p, int32_t what, int64_t* v) {
     case KRIG_INFO_CE_CLAMPED: *v = p->ce_clamped; break;
     case KRIG_INFO_DLAG_GROUP: *v = p->dlag_G; break;
     case KRIG_INFO_NL_ROWS64: *v = p->nl_rows64; break;
-    case KRIG_INFO_NL_ROWS32: *v = p->nl_rows32; break;
     case KRIG_INFO_NL_COLS64: *v = p->nl_cols64; break;
     case KRIG_INFO_FFT_VARIANTS_ROWS: *v = fft_variants(p->F2, nullptr, 0); break;
     case KRIG_INFO_FFT_VARIANTS_COLS: *v = fft_variants(p->F1, nullptr, 0); break;
@@ -1041,10 +1036,6 @@ int krig_plan_tune(krig_plan p, int32_t key, int64_t value) {
       if (v * nt_of(p->e2) > 256 || rows_lds(p->e2->geo, v, 16) > 64 * 1024) return KRIG_EINVAL;
       p->nl_rows64 = v;
       return KRIG_OK;
-    case KRIG_TUNE_NL_ROWS32:
-      if (v * nt_of(p->e2) > 256 || rows_lds(p->e2->geo, v, 8) > 64 * 1024) return KRIG_EINVAL;
-      p->nl_rows32 = v;
-      return KRIG_OK;
     case KRIG_TUNE_NL_COLS64:
       if (v * nt_of(p->e1) > 256 || cols_lds(p->e1->geo, v, 16) > 64 * 1024) return KRIG_EINVAL;
       p->nl_cols64 = v;
@@ -1109,13 +1100,12 @@ int krig_plan_autotune(krig_plan p, int32_t B, int32_t with_adjoint) {
       case KRIG_TUNE_FFT_ROWS: return p->var_rows + 1;
       case KRIG_TUNE_FFT_COLS: return p->var_cols + 1;
       case KRIG_TUNE_NL_ROWS64: return p->nl_rows64;
-      case KRIG_TUNE_NL_ROWS32: return p->nl_rows32;
       case KRIG_TUNE_NL_COLS64: return p->nl_cols64;
       default: return p->dlag_G;
     }
   };
-  const int keys[] = {KRIG_TUNE_FFT_ROWS, KRIG_TUNE_FFT_COLS, KRIG_TUNE_NL_ROWS64,
-                      KRIG_TUNE_NL_ROWS32, KRIG_TUNE_NL_COLS64, KRIG_TUNE_DLAG_GROUP};
+  const int keys[] = {KRIG_TUNE_FFT_ROWS, KRIG_TUNE_FFT_COLS, KRIG_TUNE_NL_ROWS64, KRIG_TUNE_NL_COLS64,
+                      KRIG_TUNE_DLAG_GROUP};
   for (int key : keys) {
     if (key == KRIG_TUNE_DLAG_GROUP && !with_adjoint) continue;
     std::vector<int> cand;
@@ -1132,7 +1122,7 @@ int krig_plan_autotune(krig_plan p, int32_t B, int32_t with_adjoint) {
     }
     // a transform form resets its side's shapes: remember them with the form
     const int keep = current(key);
-    const int s64 = p->nl_rows64, s32 = p->nl_rows32, sc = p->nl_cols64, sg = p->dlag_G;
+    const int s64 = p->nl_rows64, sc = p->nl_cols64, sg = p->dlag_G;
     // the current value first; another replaces it only if more than 1% faster
     double keep_ms = 1e300;
     if (krig_plan_tune(p, key, keep) == KRIG_OK && (r = measure(&keep_ms)) != KRIG_OK) {
@@ -1156,7 +1146,6 @@ int krig_plan_autotune(krig_plan p, int32_t B, int32_t with_adjoint) {
     krig_plan_tune(p, key, best);
     if ((key == KRIG_TUNE_FFT_ROWS || key == KRIG_TUNE_FFT_COLS) && best == keep) {
       p->nl_rows64 = s64;
-      p->nl_rows32 = s32;
       p->nl_cols64 = sc;
       p->dlag_G = sg;
     }
@@ -1168,7 +1157,7 @@ int krig_plan_autotune(krig_plan p, int32_t B, int32_t with_adjoint) {
   cleanup();
   {
     std::lock_guard<std::mutex> lk(tune_mutex());
-    tune_table()[tune_key(p)] = TuneRec{p->var_rows, p->var_cols, p->nl_rows64, p->nl_rows32, p->nl_cols64, p->dlag_G};
+    tune_table()[tune_key(p)] = TuneRec{p->var_rows, p->var_cols, p->nl_rows64, p->nl_cols64, p->dlag_G};
   }
   return KRIG_OK;
 }

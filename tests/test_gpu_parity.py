@@ -2,7 +2,10 @@
 
 Every case prints its name before touching the GPU.  Tolerances: bit-exact for
 integer work (anchors), <= 1e-12 relative max error for the FP64 plan where the
-inputs are identical, <= 1e-5 for the FP32 plan, <= 1e-4 for FP32 gradients.
+inputs are identical.  FP32 plans compute in FP64 too and differ only by the rounding of
+their FP32 arrays (lag, upstream gradient, predictions, lag gradient): <= 1e-6 (the
+target for FP32 is 1e-5); the conditional-simulation sampler, FP32 arithmetic in the
+FP32 form, is held to 1e-4.
 """
 import sys
 
@@ -151,12 +154,12 @@ def test_convolve_sweep_identical_inputs(krig, dtype, case):
         cimg = rp.cstar(alpha[b])
         ref = rapid_direct(g, k, cimg).reshape(g.m1, g.m2) if m1 * m2 <= 4096 else rapid_fft(g, lag, cimg)
         err = relmax(y[b], ref)
-        # rounding in the transforms (FP64) or the FP32 storage of the filtered spectrum
-        # limits the relative error to roughly eps times the cancellation
-        # sum|c*| / max|y_hat|; the bars hold up to the cancellation of the
-        # paper-shaped workloads (<= 2e4) and scale beyond it
+        # FP64 rounding in the transforms limits the relative error to roughly eps times
+        # the cancellation sum|c*| / max|y_hat|: the FP64 bar holds up to the cancellation
+        # of the paper-shaped workloads (<= 2e4) and scales beyond it; the FP32 plan adds
+        # one rounding of y_hat
         cancel = np.abs(cimg).sum() / np.abs(ref).max()
-        tol = (1e-12 if dtype == "f64" else 1e-5) * max(1.0, cancel / 2e4)
+        tol = 1e-12 * max(1.0, cancel / 2e4) if dtype == "f64" else 1e-6
         assert err < tol, (err, cancel)
 
 
@@ -168,7 +171,7 @@ def test_predict_small_field_end_to_end(krig, small, dtype):
     y = host(p.predict(dev(w.y)))[0]
     ref = rp.predict_direct(ek.coef(w.y[0])).reshape(g.m1, g.m2)
     err = relmax(y, ref)
-    assert err < (1e-12 if dtype == "f64" else 1e-5), err
+    assert err < (1e-12 if dtype == "f64" else 1e-6), err
 
 
 @pytest.mark.parametrize("dtype", ["f64", "f32"])
@@ -181,12 +184,12 @@ def test_predict_paper_field_end_to_end(krig, paper, dtype):
     err = relmax(y, ref)
     # FP64: the ill-conditioned K_N (cond ~3e13) lets equally valid weight solves move the
     # prediction by ~1e-9; the 1e-12 FP64 bar is checked on identical weights below
-    assert err < (1e-8 if dtype == "f64" else 1e-5), err
+    assert err < (1e-8 if dtype == "f64" else 1e-6), err
     # sampled nodes against the direct sum (independent of the FFT variant)
     idx = np.random.default_rng(3).choice(g.m1 * g.m2, 64, replace=False)
     idx = np.concatenate([idx, [0, g.m2 - 1, (g.m1 - 1) * g.m2, g.m1 * g.m2 - 1]])
     d = rp.predict_direct(ek.coef(w.y[0]), idx)
-    assert relmax(y.ravel()[idx], d) < (1e-8 if dtype == "f64" else 1e-5)
+    assert relmax(y.ravel()[idx], d) < (1e-8 if dtype == "f64" else 1e-6)
 
 
 def test_predict_paper_field_f64_identical_weights(krig, paper):
@@ -225,13 +228,15 @@ def test_adjoint_tiny_direct(krig, dtype):
     saved = p.new_saved(3)
     p.convolve(alpha, saved=saved)
     gup = np.random.default_rng(5).standard_normal((3, g.m1, g.m2))
+    if dtype == "f32":  # the FP32 plan takes g in FP32: the reference starts from the same values
+        gup = gup.astype(np.float32).astype(np.float64)
     dy, dlag = p.adjoint(dev(gup, td), alpha=alpha, saved=saved)
     dy, dlag = host(dy), host(dlag)
     lag = lag_quadrant(g, k)
     ref_dy = np.stack([ek.coef(grad_coef(rp.A, corr_image_direct(g, lag, gup[b]))) for b in range(3)])
     ref_dlag = sum(dlag_direct(g, gup[b], rp.cstar(ek.coef(w.y[b]))) for b in range(3))
-    tol = 1e-11 if dtype == "f64" else 1e-4
-    assert relmax(dy, ref_dy) < tol
+    tol = 1e-11 if dtype == "f64" else 1e-6  # FP32: one rounding of d lag; dy is FP64
+    assert relmax(dy, ref_dy) < 1e-11
     assert relmax(dlag, ref_dlag) < tol
     # the same with the spectra recomputed from alpha
     dy2, dlag2 = p.adjoint(dev(gup, td), alpha=alpha)
@@ -259,8 +264,8 @@ def test_adjoint_grad_batch_full_size(krig):
     al = ek.coef(w.y)
     ref_dy = np.stack([ek.coef(grad_coef(rp.A, corr_image_fft(g, lag, gh[b]))) for b in range(4)])
     ref_dlag = sum(dlag_fft(g, gh[b], rp.cstar(al[b])) for b in range(4))
-    assert relmax(dy, ref_dy) < 1e-4
-    assert relmax(dlag, ref_dlag) < 1e-4
+    assert relmax(dy, ref_dy) < 1e-8
+    assert relmax(dlag, ref_dlag) < 1e-6
 
 
 def test_adjoint_finite_differences_f64(krig):
@@ -349,7 +354,7 @@ def test_launch_shapes(krig, paper, dtype):
     g0 = p.info("DLAG_GROUP")
     p.tune("DLAG_GROUP", 2)
     ref = run()
-    for key, vals in (("NL_ROWS64", (1, 2)), ("NL_ROWS32", (1, 2)), ("NL_COLS64", (1, 2))):
+    for key, vals in (("NL_ROWS64", (1, 2)), ("NL_COLS64", (1, 2))):
         old = p.info(key)
         for v in vals:
             p.tune(key, v)
