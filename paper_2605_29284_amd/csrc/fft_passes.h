@@ -596,10 +596,24 @@ __global__ void __launch_bounds__(256) k_rows_c2r(RowsC2RArgs a) {
   const int R2b = 2 * NL;
   cx<TC>* T = lds;
   const cx<TS>* in = reinterpret_cast<const cx<TS>*>(a.in) + (int64_t)b * a.in_fs;
-  for (int idx = threadIdx.x; idx < a.H2 * R2b; idx += blockDim.x) {
-    const int rl = idx % R2b, k = idx / R2b;
-    const int row = row0 + rl;
-    T[rot(k, rl, R2b)] = row < a.nrows ? ccast<TC>(in[(int64_t)k * a.in_ld + row]) : mk<TC>(0, 0);
+  {
+    // a thread's share is at most IT elements (blockDim = NT * NL, H2 = F/2 + 1): all
+    // its loads are issued before the first LDS store
+    constexpr int IT = (2 * (G::F / 2 + 1) + G::NT - 1) / G::NT;
+    const int tot = a.H2 * R2b;
+    cx<TS> buf[IT];
+#pragma unroll
+    for (int it = 0; it < IT; ++it) {
+      const int idx = threadIdx.x + it * blockDim.x;
+      const int rl = idx % R2b, k = idx / R2b;
+      const int row = row0 + rl;
+      buf[it] = (idx < tot && row < a.nrows) ? in[(int64_t)k * a.in_ld + row] : mk<TS>(0, 0);
+    }
+#pragma unroll
+    for (int it = 0; it < IT; ++it) {
+      const int idx = threadIdx.x + it * blockDim.x;
+      if (idx < tot) T[rot(idx / R2b, idx % R2b, R2b)] = ccast<TC>(buf[it]);
+    }
   }
   __syncthreads();
   cx<TC> v[G::NIN];
@@ -655,15 +669,25 @@ __global__ void __launch_bounds__(256) k_rows_c2r_fold(RowsC2RArgs a) {
   const int R2b = 2 * NL;
   cx<TC>* T = lds;
   const cx<TC>* in = reinterpret_cast<const cx<TC>*>(a.in);
-  for (int idx = threadIdx.x; idx < a.H2 * R2b; idx += blockDim.x) {
-    const int rl = idx % R2b, k = idx / R2b;
-    const int u = row0 + rl;
-    cx<TC> t = mk<TC>(0, 0);
-    if (u < n1l) {
-      t = in[(int64_t)k * a.in_ld + u];
-      if (u > 0) t = t + in[(int64_t)k * a.in_ld + 2 * n1l - 1 - u];
+  {
+    constexpr int IT = (2 * (G::F / 2 + 1) + G::NT - 1) / G::NT;  // as in k_rows_c2r
+    const int tot = a.H2 * R2b;
+    cx<TC> b0[IT], b1[IT];
+#pragma unroll
+    for (int it = 0; it < IT; ++it) {
+      const int idx = threadIdx.x + it * blockDim.x;
+      const int rl = idx % R2b, k = idx / R2b;
+      const int u = row0 + rl;
+      const bool ok = idx < tot && u < n1l;
+      b0[it] = ok ? in[(int64_t)k * a.in_ld + u] : mk<TC>(0, 0);
+      b1[it] = (ok && u > 0) ? in[(int64_t)k * a.in_ld + 2 * n1l - 1 - u] : mk<TC>(0, 0);
     }
-    T[rot(k, rl, R2b)] = t;
+#pragma unroll
+    for (int it = 0; it < IT; ++it) {
+      const int idx = threadIdx.x + it * blockDim.x;
+      const int u = row0 + idx % R2b;
+      if (idx < tot) T[rot(idx / R2b, idx % R2b, R2b)] = u > 0 ? b0[it] + b1[it] : b0[it];
+    }
   }
   __syncthreads();
   cx<TC> v[G::NIN];
@@ -708,10 +732,20 @@ __global__ void __launch_bounds__(256) k_rows_ce(RowsCEArgs a) {
   const cx<TC>* twF = reinterpret_cast<const cx<TC>*>(a.twF);
   const cx<TS>* in = reinterpret_cast<const cx<TS>*>(a.in) + (int64_t)by * a.in_fs;
   cx<TC>* T = lds;  // [k][l]
-  for (int idx = threadIdx.x; idx < G::F * NL; idx += blockDim.x) {
-    const int rl = idx % NL, k = idx / NL;
-    const int r = row0 + rl;
-    T[rot(k, rl, NL)] = r < a.nrows ? ccast<TC>(in[(int64_t)k * a.in_ld + r]) : mk<TC>(0, 0);
+  {
+    constexpr int IT = (G::F + G::NT - 1) / G::NT;  // blockDim = NT * NL
+    cx<TS> buf[IT];
+#pragma unroll
+    for (int it = 0; it < IT; ++it) {
+      const int idx = threadIdx.x + it * blockDim.x;
+      const int r = row0 + idx % NL;
+      buf[it] = (idx < G::F * NL && r < a.nrows) ? in[(int64_t)(idx / NL) * a.in_ld + r] : mk<TS>(0, 0);
+    }
+#pragma unroll
+    for (int it = 0; it < IT; ++it) {
+      const int idx = threadIdx.x + it * blockDim.x;
+      if (idx < G::F * NL) T[rot(idx / NL, idx % NL, NL)] = ccast<TC>(buf[it]);
+    }
   }
   __syncthreads();
   cx<TC> v[G::NIN];
@@ -765,6 +799,7 @@ hipError_t launch_cols(const ColsArgs& a, int nblk_y, hipStream_t st) {
 template <typename TC, typename TS, typename TO, int R1, int R2, int R3>
 hipError_t launch_rows_c2r(const RowsC2RArgs& a, int B, hipStream_t st) {
   using G = Geo<R1, R2, R3>;
+  if (a.H2 != G::F / 2 + 1 || a.NL < 1) return hipErrorInvalidValue;  // the load loop's bound
   const int npairs = (a.nrows + 1) / 2;
   dim3 grid((npairs + a.NL - 1) / a.NL, B);
   dim3 block(G::NT * a.NL);
@@ -776,6 +811,7 @@ hipError_t launch_rows_c2r(const RowsC2RArgs& a, int B, hipStream_t st) {
 template <typename TC, typename TO, int R1, int R2, int R3>
 hipError_t launch_rows_c2r_fold(const RowsC2RArgs& a, int B, hipStream_t st) {
   using G = Geo<R1, R2, R3>;
+  if (a.H2 != G::F / 2 + 1 || a.NL < 1) return hipErrorInvalidValue;
   const int npairs = (a.nrows + 1) / 2;
   dim3 grid((npairs + a.NL - 1) / a.NL, 1);
   dim3 block(G::NT * a.NL);

@@ -377,26 +377,60 @@ __device__ inline double gather_one(const GridDev& g, const int32_t* anchor, con
   return acc;
 }
 
-template <typename TS>
-__global__ void k_gather_sites(GridDev g, const int32_t* __restrict__ anchor, const double* __restrict__ Wt, int n,
-                               const TS* __restrict__ img, int64_t img_fs, int64_t ldi, double* __restrict__ out,
-                               int64_t out_fs) {
-  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+// Adjoint gather (the transpose of Steps 5-6): out[b][i] = sum_m W[i][m] img[b][node(i, m)].
+// Four lanes per site, lane q taking m = q, q+4, ... (M = 4 L^2, so L^2 terms each, with
+// L a compile-time constant so the neighbour offsets fold): every lane's loads go out
+// together, its partial runs in the order of m, and the four partials are added as
+// (q0 + q1) + (q2 + q3).
+template <typename TS, int L>
+__global__ void __launch_bounds__(256) k_gather_sites(GridDev g, const int32_t* __restrict__ anchor,
+                                                      const double* __restrict__ Wt, int n,
+                                                      const TS* __restrict__ img, int64_t img_fs, int64_t ldi,
+                                                      double* __restrict__ out, int64_t out_fs) {
+  constexpr int L2 = 2 * L, PER = L * L;
+  const int t = blockIdx.x * blockDim.x + threadIdx.x;
+  const int i = t >> 2, q = t & 3;
   const int b = blockIdx.y;
-  if (i >= n) return;
-  out[(int64_t)b * out_fs + i] = gather_one<TS>(g, anchor, Wt, n, i, img + (int64_t)b * img_fs, ldi);
+  const bool ok = i < n;  // all four lanes of a site agree; no early exit before the shuffles
+  const int ii = ok ? i : 0;
+  const TS* base = img + (int64_t)b * img_fs + (int64_t)(anchor[2 * ii] + L) * ldi + (anchor[2 * ii + 1] + L);
+  double wv[PER], iv[PER];
+#pragma unroll
+  for (int u = 0; u < PER; ++u) {
+    const int m = q + 4 * u;  // q is a lane value: the offsets below are q-dependent but cheap
+    const int ox = m / L2 - L + 1, oy = m % L2 - L + 1;
+    wv[u] = ok ? Wt[(int64_t)m * n + ii] : 0.0;
+    iv[u] = ok ? (double)base[(int64_t)ox * ldi + oy] : 0.0;
+  }
+  double acc = 0.0;
+#pragma unroll
+  for (int u = 0; u < PER; ++u) acc += wv[u] * iv[u];
+  const double o1 = __shfl_xor(acc, 1);
+  const double pair = (q & 1) ? o1 + acc : acc + o1;  // (q0 + q1) or (q2 + q3), on both lanes of a pair
+  const double o2 = __shfl_xor(pair, 2);
+  const double tot = (q & 2) ? o2 + pair : pair + o2;
+  if (ok && q == 0) out[(int64_t)b * out_fs + i] = tot;
 }
+
+template <typename TS>
+hipError_t gather_launch(const GridDev& g, const int32_t* anchor, const double* Wt, int n, const TS* img,
+                         int64_t img_fs, int64_t ldi, int B, double* out, int64_t out_fs, hipStream_t st) {
+  dim3 grid((unsigned)((4 * (int64_t)n + 255) / 256), B);
+  switch (g.L) {
+    case 1: hipLaunchKernelGGL((k_gather_sites<TS, 1>), grid, dim3(256), 0, st, g, anchor, Wt, n, img, img_fs, ldi, out, out_fs); break;
+    case 2: hipLaunchKernelGGL((k_gather_sites<TS, 2>), grid, dim3(256), 0, st, g, anchor, Wt, n, img, img_fs, ldi, out, out_fs); break;
+    case 3: hipLaunchKernelGGL((k_gather_sites<TS, 3>), grid, dim3(256), 0, st, g, anchor, Wt, n, img, img_fs, ldi, out, out_fs); break;
+    case 4: hipLaunchKernelGGL((k_gather_sites<TS, 4>), grid, dim3(256), 0, st, g, anchor, Wt, n, img, img_fs, ldi, out, out_fs); break;
+    default: return hipErrorInvalidValue;
+  }
+  return hipGetLastError();
+}
+
 hipError_t gather_sites(const GridDev& g, const int32_t* anchor, const double* Wt, int n, const void* img,
                         int64_t img_fs, int64_t ldi, int B, int from_f32, double* out, int64_t out_fs,
                         hipStream_t st) {
-  dim3 grid(nblk(n), B);
-  if (from_f32)
-    hipLaunchKernelGGL(k_gather_sites<float>, grid, dim3(256), 0, st, g, anchor, Wt, n, (const float*)img, img_fs,
-                       ldi, out, out_fs);
-  else
-    hipLaunchKernelGGL(k_gather_sites<double>, grid, dim3(256), 0, st, g, anchor, Wt, n, (const double*)img,
-                       img_fs, ldi, out, out_fs);
-  return hipGetLastError();
+  if (from_f32) return gather_launch<float>(g, anchor, Wt, n, (const float*)img, img_fs, ldi, B, out, out_fs, st);
+  return gather_launch<double>(g, anchor, Wt, n, (const double*)img, img_fs, ldi, B, out, out_fs, st);
 }
 
 // residual of conditional simulation: out[r][i] = y[i] - (u_r(s_i) + sd * xi_{r,i})
