@@ -58,6 +58,17 @@ __device__ __forceinline__ cx<T> twm(cx<T> a, cx<T> tw) {
   return DIR < 0 ? cmul(a, tw) : cmulc(a, tw);
 }
 
+// Three-pass row kernels with an outer radix of at most 8, a middle one of at most 12
+// and an inner one of at most 9 hold about 100 VGPRs; capped at 96 (five waves per
+// SIMD) they still need no scratch, and six 3-wave blocks (27 KB of LDS each at length
+// 768) then share a CU, so a pass over ~1,400 row blocks (16 fields) runs in one round
+// instead of 1.1.  Other forms keep the default: the cap would make them spill.
+template <int R1, int R2, int R3> struct RowCap {
+  static constexpr int waves = (R1 > 1 && R1 <= 8 && R2 <= 12 && R3 <= 9) ? 5 : 1;
+};
+#define KRIG_ROW_KERNEL \
+  __global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(RowCap<R1, R2, R3>::waves)))
+
 // LDS transposes [k][R] with the column rotated by k: lanes that differ in k (the
 // fast lane index on one side of the transpose) fall on distinct banks, and a row
 // stays a permutation of itself so the other side still reads whole rows.
@@ -212,7 +223,7 @@ __device__ __forceinline__ void xf_inv(cx<TC> (&w)[R3], int t, cx<TC>* L, const 
 enum { SRC_CSR = 0, SRC_DENSE = 1, SRC_LAG = 2, SRC_COV = 3 };
 
 template <typename TC, typename TIN, typename TS, int R1, int R2, int R3, int SRC>
-__global__ void __launch_bounds__(256) k_rows_r2c(RowsR2CArgs a) {
+KRIG_ROW_KERNEL k_rows_r2c(RowsR2CArgs a) {
   int bx, by;
   logical_block<false>(bx, by);
   using G = Geo<R1, R2, R3>;
@@ -578,7 +589,7 @@ __device__ __forceinline__ void c2r_line_input(const cx<TC>* T, int R2b, int l, 
 }
 
 template <typename TC, typename TS, typename TO, int R1, int R2, int R3>
-__global__ void __launch_bounds__(256) k_rows_c2r(RowsC2RArgs a) {
+KRIG_ROW_KERNEL k_rows_c2r(RowsC2RArgs a) {
   int bx, by;
   logical_block<false>(bx, by);
   using G = Geo<R1, R2, R3>;
