@@ -25,6 +25,8 @@
 // per line) then line/column l.  Every transform begins with a block barrier, since
 // a line may span two waves and reuses the LDS of the previous step.
 #pragma once
+#include <type_traits>
+
 #include "fft_args.h"
 #include "fft_reg.h"
 #include "matern_dev.h"
@@ -106,6 +108,53 @@ __device__ __forceinline__ int window_dst(const Window& wd, int i) {
 }
 
 // ----------------------------------------------------------------------------------------
+// Pass twiddles.  Each thread loads a few base powers b of W = exp(-2 pi i / F) once,
+// before its first transform, and forms the powers a pass needs by repeated
+// multiplication (loading them inside a pass put a memory latency after every barrier):
+//   f1 = W^t (pass 1), f2 = W^(R1 (t mod R3)) (pass 2); for the inverse from the output
+//   layout also i3 = W^(R1 floor(t / R1)), i4a = W^(floor(t / R3) (t mod R3)) and
+//   i4b = W^(R3 floor(t / R3)).
+// A table entry b = W^j (1 + d) carries a rounding d of about 2^-54, and b^k carries k d,
+// which for k up to 15 outweighed the rounding of the products and doubled the FP64
+// transform error.  The table stores d (FP32) after its F entries; every fourth step the
+// running power is multiplied by (1 + 4 d) (first order in d), so no power carries more
+// than 3 d.  Measured on the convolution sweep this matches direct table loads.
+// ----------------------------------------------------------------------------------------
+template <typename TC> struct TwB {
+  cx<TC> f1, f2, i3, i4a, i4b;
+  cx<float> d1, d2, d3, d4;  // relative rounding of f1, f2, i3, i4b
+};
+
+// Threads outside a pass's range read entry 0, which is exactly 1 (d = 0).
+template <typename TC, int R1, int R2, int R3, bool INV>
+__device__ __forceinline__ TwB<TC> tw_bases(const cx<TC>* tw, int t) {
+  using G = Geo<R1, R2, R3>;
+  const cx<float>* td = reinterpret_cast<const cx<float>*>(tw + G::F);
+  const int j1 = (G::THREE && t < G::TIN) ? t : 0;
+  const int j2 = t < G::T2 ? R1 * (t % R3) : 0;
+  const int j3 = (INV && t < G::TOUT) ? R1 * (t / R1) : 0;
+  const int j4 = (INV && G::THREE && t < G::T2) ? R3 * (t / R3) : 0;
+  TwB<TC> b;
+  b.f1 = tw[j1];
+  b.f2 = tw[j2];
+  b.i3 = tw[j3];
+  b.i4a = tw[(INV && G::THREE && t < G::T2) ? (t / R3) * (t % R3) : 0];
+  b.i4b = tw[j4];
+  b.d1 = td[j1];
+  b.d2 = td[j2];
+  b.d3 = td[j3];
+  b.d4 = td[j4];
+  return b;
+}
+
+// p (1 + k d): removes the rounding d of k table-entry factors from the product p.
+template <typename TC>
+__device__ __forceinline__ cx<TC> tw_fix(cx<TC> p, cx<float> d, int k) {
+  const TC er = (TC)(d.x * (float)k), ei = (TC)(d.y * (float)k);
+  return mk<TC>(fma(p.x, er, fma(-p.y, ei, p.x)), fma(p.x, ei, fma(p.y, er, p.y)));
+}
+
+// ----------------------------------------------------------------------------------------
 // One transform per line, input layout -> output layout (DIR = -1 forward, +1
 // inverse, unnormalised).  L: the line's EX LDS slots; tw: exp(-2 pi i j / F), j < F.
 //  pass 1 (R1 > 1): thread m < M: DFT_R1 over j of x[m + M j], times W_F^(m k1),
@@ -117,17 +166,22 @@ __device__ __forceinline__ int window_dst(const Window& wd, int i) {
 // ----------------------------------------------------------------------------------------
 template <typename TC, int R1, int R2, int R3, int DIR>
 __device__ __forceinline__ void xf_fwd(cx<TC> (&v)[(Geo<R1, R2, R3>::NIN)], cx<TC> (&w)[R3], int t, cx<TC>* L,
-                                       const cx<TC>* tw) {
+                                       const TwB<TC>& tb) {
   using G = Geo<R1, R2, R3>;
   __syncthreads();
   cx<TC> u[R2];
   if constexpr (G::THREE) {
     if (t < G::TIN) {
       DFT<R1, DIR, TC>::run(v);
+      cx<TC> wk = tb.f1;  // W^(t k1)
 #pragma unroll
       for (int k1 = 0; k1 < R1; ++k1) {
         cx<TC> a = v[k1];
-        if (k1 != 0 && t != 0) a = twm<DIR>(a, tw[t * k1]);
+        if (k1 != 0) {
+          if (k1 > 1) wk = cmul(wk, tb.f1);
+          if (k1 % 4 == 0) wk = tw_fix(wk, tb.d1, 4);
+          a = twm<DIR>(a, wk);
+        }
         L[k1 * G::P1 + t] = a;
       }
     }
@@ -146,10 +200,15 @@ __device__ __forceinline__ void xf_fwd(cx<TC> (&v)[(Geo<R1, R2, R3>::NIN)], cx<T
     const int k1 = t / R3, s = t % R3;
     DFT<R2, DIR, TC>::run(u);
     cx<TC>* Lk = L + k1 * G::RS;
+    cx<TC> wq = tb.f2;  // W^(R1 s q)
 #pragma unroll
     for (int q = 0; q < R2; ++q) {
       cx<TC> a = u[q];
-      if (q != 0 && s != 0) a = twm<DIR>(a, tw[R1 * s * q]);
+      if (q != 0) {
+        if (q > 1) wq = cmul(wq, tb.f2);
+        if (q % 4 == 0) wq = tw_fix(wq, tb.d2, 4);
+        a = twm<DIR>(a, wq);
+      }
       Lk[s * G::ON2 + q] = a;
     }
   }
@@ -167,7 +226,7 @@ __device__ __forceinline__ void xf_fwd(cx<TC> (&v)[(Geo<R1, R2, R3>::NIN)], cx<T
 // back to the input layout (thread t < TIN ends with x[t + TIN j] in v[j]): the
 // passes of xf_fwd in reverse with conjugate twiddles.
 template <typename TC, int R1, int R2, int R3>
-__device__ __forceinline__ void xf_inv(cx<TC> (&w)[R3], int t, cx<TC>* L, const cx<TC>* tw,
+__device__ __forceinline__ void xf_inv(cx<TC> (&w)[R3], int t, cx<TC>* L, const TwB<TC>& tb,
                                        cx<TC> (&v)[(Geo<R1, R2, R3>::NIN)]) {
   using G = Geo<R1, R2, R3>;
   __syncthreads();
@@ -175,10 +234,15 @@ __device__ __forceinline__ void xf_inv(cx<TC> (&w)[R3], int t, cx<TC>* L, const 
     const int k1 = t % R1, sp = t / R1;
     DFT<R3, 1, TC>::run(w);
     cx<TC>* Lk = L + k1 * G::RS;
+    cx<TC> wn = tb.i3;  // W^(R1 sp n2)
 #pragma unroll
     for (int n2 = 0; n2 < R3; ++n2) {
       cx<TC> a = w[n2];
-      if (n2 != 0 && sp != 0) a = cmulc(a, tw[R1 * n2 * sp]);
+      if (n2 != 0) {
+        if (n2 > 1) wn = cmul(wn, tb.i3);
+        if (n2 % 4 == 0) wn = tw_fix(wn, tb.d3, 4);
+        a = cmulc(a, wn);
+      }
       Lk[n2 * G::ON2 + sp] = a;
     }
   }
@@ -194,12 +258,13 @@ __device__ __forceinline__ void xf_inv(cx<TC> (&w)[R3], int t, cx<TC>* L, const 
     if (t < G::T2) {
       const int k1 = t / R3, n2 = t % R3;
       DFT<R2, 1, TC>::run(u);
+      cx<TC> wm = tb.i4a;  // W^(m k1), m = R3 n1 + n2
 #pragma unroll
       for (int n1 = 0; n1 < R2; ++n1) {
         const int m = R3 * n1 + n2;
-        cx<TC> a = u[n1];
-        if (k1 != 0 && m != 0) a = cmulc(a, tw[m * k1]);
-        L[k1 * G::P1 + m] = a;
+        if (n1 > 0) wm = cmul(wm, tb.i4b);
+        if (n1 > 0 && n1 % 4 == 0) wm = tw_fix(wm, tb.d4, 4);
+        L[k1 * G::P1 + m] = cmulc(u[n1], wm);
       }
     }
     __syncthreads();
@@ -237,6 +302,7 @@ KRIG_ROW_KERNEL k_rows_r2c(RowsR2CArgs a) {
   const int ra = row0 + 2 * l, rb = ra + 1;
   const bool oka = ra < a.nrows, okb = rb < a.nrows;
   const cx<TC>* twF = reinterpret_cast<const cx<TC>*>(a.twF);
+  const TwB<TC> tb = tw_bases<TC, R1, R2, R3, false>(twF, s);
   cx<TC>* L = lds + (size_t)l * G::ROWS;
 
   cx<TC> v[G::NIN];
@@ -329,7 +395,7 @@ KRIG_ROW_KERNEL k_rows_r2c(RowsR2CArgs a) {
     }
   }
   cx<TC> w[G::NOUT];
-  xf_fwd<TC, R1, R2, R3, -1>(v, w, s, L, twF);
+  xf_fwd<TC, R1, R2, R3, -1>(v, w, s, L, tb);
   __syncthreads();
   // natural-order exchange to pair Z[k] with Z[F-k]
   if (s < G::TOUT) {
@@ -378,7 +444,7 @@ KRIG_ROW_KERNEL k_rows_r2c(RowsR2CArgs a) {
 // ----------------------------------------------------------------------------------------
 template <typename TC, typename TS, int R1, int R2, int R3>
 __device__ __forceinline__ void col_fwd(const cx<TS>* src, int in_off, int in_cnt, bool colok, int s,
-                                        cx<TC>* L, const cx<TC>* twF, cx<TC> (&w)[R3]) {
+                                        cx<TC>* L, const TwB<TC>& tb, cx<TC> (&w)[R3]) {
   using G = Geo<R1, R2, R3>;
   cx<TC> v[G::NIN];
   if (s < G::TIN) {
@@ -388,13 +454,20 @@ __device__ __forceinline__ void col_fwd(const cx<TS>* src, int in_off, int in_cn
       v[j] = (colok && r >= 0 && r < in_cnt) ? ccast<TC>(src[r]) : mk<TC>(0, 0);
     }
   }
-  xf_fwd<TC, R1, R2, R3, -1>(v, w, s, L, twF);
+  xf_fwd<TC, R1, R2, R3, -1>(v, w, s, L, tb);
 }
 
 enum { COL_CONV = 0, COL_CONV_DLAG = 1, COL_FWD_REAL = 2, COL_INV_SUM = 3, COL_CE = 4 };
 
+// The lag-gradient column pass (two forward transforms and an inverse per line) of the
+// same forms holds just over 168 VGPRs: capped at three waves per SIMD it needs no scratch.
+template <int R1, int R2, int R3, int MODE> struct ColCap {
+  static constexpr int waves = (MODE == COL_CONV_DLAG && RowCap<R1, R2, R3>::waves > 1) ? 3 : 1;
+};
+
 template <typename TF, typename TI, typename TSI, typename TSO, int R1, int R2, int R3, int MODE>
-__global__ void __launch_bounds__(256) k_cols(ColsArgs a) {
+__global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(ColCap<R1, R2, R3, MODE>::waves)))
+k_cols(ColsArgs a) {
   int bx, by;
   logical_block<true>(bx, by);
   using G = Geo<R1, R2, R3>;
@@ -406,26 +479,34 @@ __global__ void __launch_bounds__(256) k_cols(ColsArgs a) {
   const int col = bx * NL + l0;
   const bool colok = col < a.H2;
   const cx<TC>* twF = reinterpret_cast<const cx<TC>*>(a.twF);
+  static_assert(std::is_same<TI, TF>::value, "one arithmetic type per column pass");
+  const TwB<TC> tb = tw_bases<TC, R1, R2, R3, (MODE == COL_CONV || MODE == COL_CONV_DLAG)>(twF, s);
   cx<TC>* L = reinterpret_cast<cx<TC>*>(smem_raw) + (size_t)l0 * G::EX;
 
   if constexpr (MODE == COL_CONV) {
     const int b = by;
     const cx<TSI>* src = reinterpret_cast<const cx<TSI>*>(a.in) + (int64_t)b * a.in_fs + (int64_t)col * a.in_ld;
+    // the filter values this thread needs, loaded before the transform hides their latency
+    TF fv[R3];
+    {
+      const TF* f = reinterpret_cast<const TF*>(a.filt) + (int64_t)(colok ? col : 0) * a.filt_ld;
+#pragma unroll
+      for (int k2 = 0; k2 < R3; ++k2) fv[k2] = (s < G::TOUT && colok) ? f[s + G::TOUT * k2] : (TF)0;
+    }
     cx<TI> wi[R3];
     {
       cx<TC> w[R3];
-      col_fwd<TC, TSI, R1, R2, R3>(src, a.in_off, a.in_cnt, colok, s, L, twF, w);
+      col_fwd<TC, TSI, R1, R2, R3>(src, a.in_off, a.in_cnt, colok, s, L, tb, w);
       if (s < G::TOUT && colok) {
-        const TF* f = reinterpret_cast<const TF*>(a.filt) + (int64_t)col * a.filt_ld;
 #pragma unroll
-        for (int k2 = 0; k2 < R3; ++k2) w[k2] = cscale(w[k2], f[s + G::TOUT * k2]);
+        for (int k2 = 0; k2 < R3; ++k2) w[k2] = cscale(w[k2], fv[k2]);
       }
 #pragma unroll
       for (int k2 = 0; k2 < R3; ++k2) wi[k2] = ccast<TI>(w[k2]);
     }
     cx<TI>* LI = reinterpret_cast<cx<TI>*>(smem_raw) + (size_t)l0 * G::EX;
     cx<TI> v[G::NIN];
-    xf_inv<TI, R1, R2, R3>(wi, s, LI, reinterpret_cast<const cx<TI>*>(a.twI), v);
+    xf_inv<TI, R1, R2, R3>(wi, s, LI, tb, v);
     if (s < G::TIN && colok) {
       cx<TSO>* dst = reinterpret_cast<cx<TSO>*>(a.out) + (int64_t)b * a.out_fs + (int64_t)col * a.out_ld;
 #pragma unroll
@@ -446,16 +527,21 @@ __global__ void __launch_bounds__(256) k_cols(ColsArgs a) {
     const int bb = b < a.B ? b : 0;
     const cx<TSI>* srcc = reinterpret_cast<const cx<TSI>*>(a.in2) + (int64_t)bb * a.in2_fs + (int64_t)colb * a.in2_ld;
     const cx<TSI>* srcg = reinterpret_cast<const cx<TSI>*>(a.in) + (int64_t)bb * a.in_fs + (int64_t)colb * a.in_ld;
+    TF fv[R3];  // filter values, loaded before the transforms
+    {
+      const TF* f = reinterpret_cast<const TF*>(a.filt) + (int64_t)(colokb ? colb : 0) * a.filt_ld;
+#pragma unroll
+      for (int k2 = 0; k2 < R3; ++k2) fv[k2] = (s < G::TOUT && fok) ? f[s + G::TOUT * k2] : (TF)0;
+    }
     cx<TC> wc[R3], wg[R3];
-    col_fwd<TC, TSI, R1, R2, R3>(srcc, a.in2_off, a.in2_cnt, fok, s, L, twF, wc);  // C-hat
-    col_fwd<TC, TSI, R1, R2, R3>(srcg, a.in_off, a.in_cnt, fok, s, L, twF, wg);    // G-hat
+    col_fwd<TC, TSI, R1, R2, R3>(srcc, a.in2_off, a.in2_cnt, fok, s, L, tb, wc);  // C-hat
+    col_fwd<TC, TSI, R1, R2, R3>(srcg, a.in_off, a.in_cnt, fok, s, L, tb, wg);    // G-hat
     __syncthreads();
     if (s < G::TOUT) {
-      const TF* f = reinterpret_cast<const TF*>(a.filt) + (int64_t)(colokb ? colb : 0) * a.filt_ld;
 #pragma unroll
       for (int k2 = 0; k2 < R3; ++k2) {
         L[s + G::TOUT * k2] = fok ? cmulc(wg[k2], wc[k2]) : mk<TC>(0, 0);
-        if (fok) wg[k2] = cscale(wg[k2], f[s + G::TOUT * k2]);
+        if (fok) wg[k2] = cscale(wg[k2], fv[k2]);
       }
     }
     __syncthreads();
@@ -470,7 +556,7 @@ __global__ void __launch_bounds__(256) k_cols(ColsArgs a) {
       }
     }
     cx<TC> v[G::NIN];
-    xf_inv<TC, R1, R2, R3>(wg, s, L, twF, v);
+    xf_inv<TC, R1, R2, R3>(wg, s, L, tb, v);
     if (s < G::TIN && fok) {
       cx<TSO>* dst = reinterpret_cast<cx<TSO>*>(a.out) + (int64_t)b * a.out_fs + (int64_t)colb * a.out_ld;
 #pragma unroll
@@ -484,7 +570,7 @@ __global__ void __launch_bounds__(256) k_cols(ColsArgs a) {
     const int b = by;
     const cx<TSI>* src = reinterpret_cast<const cx<TSI>*>(a.in) + (int64_t)b * a.in_fs + (int64_t)col * a.in_ld;
     cx<TC> w[R3];
-    col_fwd<TC, TSI, R1, R2, R3>(src, a.in_off, a.in_cnt, colok, s, L, twF, w);
+    col_fwd<TC, TSI, R1, R2, R3>(src, a.in_off, a.in_cnt, colok, s, L, tb, w);
     if (s < G::TOUT && colok) {
       TSO* dst = reinterpret_cast<TSO*>(a.out) + (int64_t)b * a.out_fs + (int64_t)col * a.out_ld;
 #pragma unroll
@@ -519,7 +605,7 @@ __global__ void __launch_bounds__(256) k_cols(ColsArgs a) {
       }
     }
     cx<TC> w[R3];
-    xf_fwd<TC, R1, R2, R3, -1>(v, w, s, L, twF);
+    xf_fwd<TC, R1, R2, R3, -1>(v, w, s, L, tb);
     if (s < G::TOUT && colok) {
       cx<TSO>* dst = reinterpret_cast<cx<TSO>*>(a.out) + (int64_t)by * a.out_fs + (int64_t)col * a.out_ld;
 #pragma unroll
@@ -553,7 +639,7 @@ __global__ void __launch_bounds__(256) k_cols(ColsArgs a) {
       }
     }
     cx<TC> w[R3];
-    xf_fwd<TC, R1, R2, R3, 1>(v, w, s, L, twF);
+    xf_fwd<TC, R1, R2, R3, 1>(v, w, s, L, tb);
     if (s < G::TOUT && colok) {
       cx<TSO>* dst = reinterpret_cast<cx<TSO>*>(a.out) + (int64_t)col * a.out_ld;
 #pragma unroll
@@ -603,6 +689,7 @@ KRIG_ROW_KERNEL k_rows_c2r(RowsC2RArgs a) {
   const int ra = row0 + 2 * l, rb = ra + 1;
   const bool oka = ra < a.nrows, okb = rb < a.nrows;
   const cx<TC>* twF = reinterpret_cast<const cx<TC>*>(a.twF);
+  const TwB<TC> tb = tw_bases<TC, R1, R2, R3, false>(twF, s);
   // row-contiguous loads of the block's 2 NL rows into T[k][rl]
   const int R2b = 2 * NL;
   cx<TC>* T = lds;
@@ -631,7 +718,7 @@ KRIG_ROW_KERNEL k_rows_c2r(RowsC2RArgs a) {
   c2r_line_input<TC, R1, R2, R3>(T, R2b, l, s, a.H2, v);
   cx<TC>* L = lds + (size_t)l * G::ROWS;
   cx<TC> w[R3];
-  xf_fwd<TC, R1, R2, R3, 1>(v, w, s, L, twF);
+  xf_fwd<TC, R1, R2, R3, 1>(v, w, s, L, tb);
   if (s < G::TOUT) {
     TO* oa = reinterpret_cast<TO*>(a.out) + (int64_t)b * a.out_fs + (int64_t)ra * a.ldo;
     TO* ob = oa + a.ldo;
@@ -677,6 +764,7 @@ __global__ void __launch_bounds__(256) k_rows_c2r_fold(RowsC2RArgs a) {
   const int row0 = 2 * bx * NL;
   const int ra = row0 + 2 * l, rb = ra + 1;
   const cx<TC>* twF = reinterpret_cast<const cx<TC>*>(a.twF);
+  const TwB<TC> tb = tw_bases<TC, R1, R2, R3, false>(twF, s);
   const int R2b = 2 * NL;
   cx<TC>* T = lds;
   const cx<TC>* in = reinterpret_cast<const cx<TC>*>(a.in);
@@ -705,7 +793,7 @@ __global__ void __launch_bounds__(256) k_rows_c2r_fold(RowsC2RArgs a) {
   c2r_line_input<TC, R1, R2, R3>(T, R2b, l, s, a.H2, v);
   cx<TC>* L = lds + (size_t)l * G::ROWS;
   cx<TC> w[R3];
-  xf_fwd<TC, R1, R2, R3, 1>(v, w, s, L, twF);
+  xf_fwd<TC, R1, R2, R3, 1>(v, w, s, L, tb);
   __syncthreads();
   if (s < G::TOUT) {
 #pragma unroll
@@ -741,6 +829,7 @@ __global__ void __launch_bounds__(256) k_rows_ce(RowsCEArgs a) {
   const int row0 = bx * NL;
   const int row = row0 + l;
   const cx<TC>* twF = reinterpret_cast<const cx<TC>*>(a.twF);
+  const TwB<TC> tb = tw_bases<TC, R1, R2, R3, false>(twF, s);
   const cx<TS>* in = reinterpret_cast<const cx<TS>*>(a.in) + (int64_t)by * a.in_fs;
   cx<TC>* T = lds;  // [k][l]
   {
@@ -766,7 +855,7 @@ __global__ void __launch_bounds__(256) k_rows_ce(RowsCEArgs a) {
   }
   cx<TC>* L = lds + (size_t)l * G::EX;
   cx<TC> w[R3];
-  xf_fwd<TC, R1, R2, R3, -1>(v, w, s, L, twF);
+  xf_fwd<TC, R1, R2, R3, -1>(v, w, s, L, tb);
   if (s < G::TOUT && row < a.nrows) {
     const int re = 2 * pair, im = 2 * pair + 1;
     TO* o1 = reinterpret_cast<TO*>(a.out) + (int64_t)re * a.out_fs + (int64_t)row * a.ldo;

@@ -10,6 +10,7 @@
 #include <tuple>
 #include <mutex>
 #include <new>
+#include <cmath>
 #include <vector>
 
 #include "../../include/krig.h"
@@ -212,19 +213,49 @@ int nl_cols_for(const FftEntry* e, size_t csz) {
 }
 int pitch16(int rows) { return (rows + 15) / 16 * 16; }
 
+// (cos, sin) of 2 pi j / F in x86 extended precision (64-bit significand), by the same
+// exact octant reduction as trig_frac; only used to measure the rounding of the tables.
+void trig_ext(long j, long F, long double* c, long double* s) {
+  const long double pi = 3.14159265358979323846264338327950288L;
+  long r = ((j % F) + F) % F, o = (8 * r) / F, num = 8 * r - o * F;
+  const long double x = (pi / 4) * ((long double)num / (long double)F), y = pi / 4 - x;
+  const long double sx = std::sin(x), cx_ = std::cos(x), sy = std::sin(y), cy = std::cos(y);
+  const long double C[8] = {cx_, sy, -sx, -cy, -cx_, -sy, sx, cy};
+  const long double S[8] = {sx, cy, cx_, sy, -sx, -cy, -cx_, -sy};
+  *c = C[o];
+  *s = S[o];
+}
+
+// Relative rounding error d = (exact - t) / t of a table entry t, as an FP32 complex pair.
+template <typename T>
+void rel_err(long double ec, long double es, T tc, T ts, float* d) {
+  const long double hr = tc, hi = ts, er = ec - hr, ei = es - hi, den = hr * hr + hi * hi;
+  d[0] = (float)((er * hr + ei * hi) / den);
+  d[1] = (float)((ei * hr - er * hi) / den);
+}
+
+// Twiddle tables exp(-2 pi i j / F), j < F, in FP64 and FP32.  Each table of F complex
+// entries is followed by F complex FP32 values d_j, the relative rounding error of entry
+// j: a kernel that forms W^(jk) as the k-th power of entry j corrects it by (1 + k d_j).
 int make_twiddles(krig_plan p, int F, double** d64, float** d32) {
-  std::vector<double> h64(2 * (size_t)F);
-  std::vector<float> h32(2 * (size_t)F);
+  std::vector<double> h64(3 * (size_t)F);  // 2F doubles, then 2F floats
+  std::vector<float> h32(4 * (size_t)F);
+  float* e64 = reinterpret_cast<float*>(h64.data() + 2 * (size_t)F);
   for (int j = 0; j < F; ++j) {
     const double c = trig_frac(j, F, true), s = -trig_frac(j, F, false);
     h64[2 * j] = c;
     h64[2 * j + 1] = s;
     h32[2 * j] = (float)c;
     h32[2 * j + 1] = (float)s;
+    long double ec, es;
+    trig_ext(j, F, &ec, &es);
+    es = -es;
+    rel_err(ec, es, c, s, e64 + 2 * j);
+    rel_err(ec, es, h32[2 * j], h32[2 * j + 1], h32.data() + 2 * (size_t)F + 2 * j);
   }
   int r;
-  if ((r = dalloc(p, d64, 2 * (size_t)F)) != KRIG_OK) return r;
-  if ((r = dalloc(p, d32, 2 * (size_t)F)) != KRIG_OK) return r;
+  if ((r = dalloc(p, d64, h64.size())) != KRIG_OK) return r;
+  if ((r = dalloc(p, d32, h32.size())) != KRIG_OK) return r;
   KRIG_TRY(hipMemcpyAsync(*d64, h64.data(), h64.size() * sizeof(double), hipMemcpyHostToDevice, p->st));
   KRIG_TRY(hipMemcpyAsync(*d32, h32.data(), h32.size() * sizeof(float), hipMemcpyHostToDevice, p->st));
   KRIG_TRY(hipStreamSynchronize(p->st));  // host vectors go out of scope
