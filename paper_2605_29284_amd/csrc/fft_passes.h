@@ -292,7 +292,7 @@ KRIG_ROW_KERNEL k_rows_r2c(RowsR2CArgs a) {
   int bx, by;
   logical_block<false>(bx, by);
   using G = Geo<R1, R2, R3>;
-  extern __shared__ unsigned char smem_raw[];
+  extern __shared__ __align__(16) unsigned char smem_raw[];
   cx<TC>* lds = reinterpret_cast<cx<TC>*>(smem_raw);
   const int s = threadIdx.x % G::NT;
   const int l = threadIdx.x / G::NT;
@@ -472,7 +472,7 @@ k_cols(ColsArgs a) {
   logical_block<true>(bx, by);
   using G = Geo<R1, R2, R3>;
   using TC = TF;
-  extern __shared__ unsigned char smem_raw[];
+  extern __shared__ __align__(16) unsigned char smem_raw[];
   const int NL = a.NL;
   const int s = threadIdx.x % G::NT;
   const int l0 = threadIdx.x / G::NT;
@@ -679,7 +679,7 @@ KRIG_ROW_KERNEL k_rows_c2r(RowsC2RArgs a) {
   int bx, by;
   logical_block<false>(bx, by);
   using G = Geo<R1, R2, R3>;
-  extern __shared__ unsigned char smem_raw[];
+  extern __shared__ __align__(16) unsigned char smem_raw[];
   cx<TC>* lds = reinterpret_cast<cx<TC>*>(smem_raw);
   const int s = threadIdx.x % G::NT;
   const int l = threadIdx.x / G::NT;
@@ -755,7 +755,7 @@ __global__ void __launch_bounds__(256) k_rows_c2r_fold(RowsC2RArgs a) {
   int bx, by;
   logical_block<false>(bx, by);
   using G = Geo<R1, R2, R3>;
-  extern __shared__ unsigned char smem_raw[];
+  extern __shared__ __align__(16) unsigned char smem_raw[];
   cx<TC>* lds = reinterpret_cast<cx<TC>*>(smem_raw);
   const int s = threadIdx.x % G::NT;
   const int l = threadIdx.x / G::NT;
@@ -820,7 +820,7 @@ __global__ void __launch_bounds__(256) k_rows_ce(RowsCEArgs a) {
   int bx, by;
   logical_block<false>(bx, by);
   using G = Geo<R1, R2, R3>;
-  extern __shared__ unsigned char smem_raw[];
+  extern __shared__ __align__(16) unsigned char smem_raw[];
   cx<TC>* lds = reinterpret_cast<cx<TC>*>(smem_raw);
   const int s = threadIdx.x % G::NT;
   const int l = threadIdx.x / G::NT;

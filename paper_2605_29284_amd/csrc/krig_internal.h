@@ -8,7 +8,10 @@
 namespace krig {
 
 // ---------------------------------------------------------------- complex numbers
-template <typename T> struct cx { T x, y; };
+// Aligned to its full size so that a complex value moves as one 16-byte (FP64) or 8-byte
+// (FP32) access: split into two halves, a wave's LDS accesses at a 16-byte stride
+// conflict in every bank pair.
+template <typename T> struct alignas(2 * sizeof(T)) cx { T x, y; };
 
 template <typename T> __host__ __device__ __forceinline__ cx<T> mk(T a, T b) { cx<T> r; r.x = a; r.y = b; return r; }
 template <typename T> __host__ __device__ __forceinline__ cx<T> operator+(cx<T> a, cx<T> b) { return mk<T>(a.x + b.x, a.y + b.y); }
