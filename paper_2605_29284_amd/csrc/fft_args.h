@@ -200,8 +200,17 @@ int fft_sizes(int* out, int cap);
 void register_all_fft();
 
 // LDS bytes of one block (lines or columns NL) for each kernel family
-inline size_t rows_lds(const FftGeo& g, int NL, size_t csz) { return (size_t)NL * g.ROWS * csz; }
+// Pitch of an LDS transpose with R values per k: R, padded by one where R is a multiple
+// of 4 (the bank-group reasoning is at the transposes in fft_passes.h).
+__host__ __device__ constexpr int tpitch(int R) { return R % 4 == 0 ? R + 1 : R; }
+// Row kernels hold either NL lines or the block's transpose [k][2 NL] (k <= F/2); the
+// circulant-embedding row kernel NL lines or a transpose [k][NL] (k < F).
+inline size_t rows_lds(const FftGeo& g, int NL, size_t csz) {
+  return (size_t)imax(NL * g.ROWS, (g.F / 2 + 1) * tpitch(2 * NL)) * csz;
+}
 inline size_t cols_lds(const FftGeo& g, int NL, size_t csz) { return (size_t)NL * g.EX * csz; }
-inline size_t ce_rows_lds(const FftGeo& g, int NL, size_t csz) { return (size_t)NL * imax(g.EX, g.F) * csz; }
+inline size_t ce_rows_lds(const FftGeo& g, int NL, size_t csz) {
+  return (size_t)imax(NL * imax(g.EX, g.F), g.F * tpitch(NL)) * csz;
+}
 
 }  // namespace krig

@@ -71,10 +71,12 @@ template <int R1, int R2, int R3> struct RowCap {
 #define KRIG_ROW_KERNEL \
   __global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(RowCap<R1, R2, R3>::waves)))
 
-// LDS transposes [k][R] with the column rotated by k: lanes that differ in k (the
-// fast lane index on one side of the transpose) fall on distinct banks, and a row
-// stays a permutation of itself so the other side still reads whole rows.
-__device__ __forceinline__ int rot(int k, int c, int R) { return k * R + (c + k) % R; }
+// LDS transposes [k][R] with the pitch tpitch(R).  A wave's 16-byte LDS accesses go
+// eight lanes at a time over 16 bank groups of 16 bytes, so eight lanes with
+// consecutive k (one side of the transpose) fall on distinct groups when the pitch is
+// not a multiple of 4; such pitches get one slot of padding.  Lanes with consecutive c
+// (the other side) read consecutive slots.
+__device__ __forceinline__ int tpos(int k, int c, int R) { return k * tpitch(R) + c; }
 
 // Workgroups go to the 8 XCDs (each with its own L2) round-robin by linear block id.
 // xcd_block maps the hardware id to a logical id so that each XCD runs one contiguous
@@ -425,8 +427,8 @@ KRIG_ROW_KERNEL k_rows_r2c(RowsR2CArgs a) {
     for (int k2 = 0; k2 < NK; ++k2) {
       const int k = s + G::TOUT * k2;
       if (k < a.H2) {
-        T[rot(k, 2 * l, R2b)] = xa[k2];
-        T[rot(k, 2 * l + 1, R2b)] = xb[k2];
+        T[tpos(k, 2 * l, R2b)] = xa[k2];
+        T[tpos(k, 2 * l + 1, R2b)] = xb[k2];
       }
     }
   }
@@ -435,7 +437,7 @@ KRIG_ROW_KERNEL k_rows_r2c(RowsR2CArgs a) {
   for (int idx = threadIdx.x; idx < a.H2 * R2b; idx += blockDim.x) {
     const int rl = idx % R2b, k = idx / R2b;
     const int row = row0 + rl;
-    if (row < a.nrows) o[(int64_t)k * a.out_ld + row] = ccast<TS>(T[rot(k, rl, R2b)]);
+    if (row < a.nrows) o[(int64_t)k * a.out_ld + row] = ccast<TS>(T[tpos(k, rl, R2b)]);
   }
 }
 
@@ -666,7 +668,7 @@ __device__ __forceinline__ void c2r_line_input(const cx<TC>* T, int R2b, int l, 
       const int k = G::TIN * j + s;
       const bool lo = k < H2;
       const int kk = lo ? k : G::F - k;
-      cx<TC> xa = T[rot(kk, 2 * l, R2b)], xb = T[rot(kk, 2 * l + 1, R2b)];
+      cx<TC> xa = T[tpos(kk, 2 * l, R2b)], xb = T[tpos(kk, 2 * l + 1, R2b)];
       if (kk == 0 || 2 * kk == G::F) { xa.y = 0; xb.y = 0; }  // DC / Nyquist are real
       if (!lo) { xa.y = -xa.y; xb.y = -xb.y; }
       v[j] = mk<TC>(xa.x - xb.y, xa.y + xb.x);  // Xa + i Xb
@@ -710,7 +712,7 @@ KRIG_ROW_KERNEL k_rows_c2r(RowsC2RArgs a) {
 #pragma unroll
     for (int it = 0; it < IT; ++it) {
       const int idx = threadIdx.x + it * blockDim.x;
-      if (idx < tot) T[rot(idx / R2b, idx % R2b, R2b)] = ccast<TC>(buf[it]);
+      if (idx < tot) T[tpos(idx / R2b, idx % R2b, R2b)] = ccast<TC>(buf[it]);
     }
   }
   __syncthreads();
@@ -785,7 +787,7 @@ __global__ void __launch_bounds__(256) k_rows_c2r_fold(RowsC2RArgs a) {
     for (int it = 0; it < IT; ++it) {
       const int idx = threadIdx.x + it * blockDim.x;
       const int u = row0 + idx % R2b;
-      if (idx < tot) T[rot(idx / R2b, idx % R2b, R2b)] = u > 0 ? b0[it] + b1[it] : b0[it];
+      if (idx < tot) T[tpos(idx / R2b, idx % R2b, R2b)] = u > 0 ? b0[it] + b1[it] : b0[it];
     }
   }
   __syncthreads();
@@ -844,14 +846,14 @@ __global__ void __launch_bounds__(256) k_rows_ce(RowsCEArgs a) {
 #pragma unroll
     for (int it = 0; it < IT; ++it) {
       const int idx = threadIdx.x + it * blockDim.x;
-      if (idx < G::F * NL) T[rot(idx / NL, idx % NL, NL)] = ccast<TC>(buf[it]);
+      if (idx < G::F * NL) T[tpos(idx / NL, idx % NL, NL)] = ccast<TC>(buf[it]);
     }
   }
   __syncthreads();
   cx<TC> v[G::NIN];
   if (s < G::TIN) {
 #pragma unroll
-    for (int j = 0; j < G::NIN; ++j) v[j] = T[rot(G::TIN * j + s, l, NL)];
+    for (int j = 0; j < G::NIN; ++j) v[j] = T[tpos(G::TIN * j + s, l, NL)];
   }
   cx<TC>* L = lds + (size_t)l * G::EX;
   cx<TC> w[R3];
