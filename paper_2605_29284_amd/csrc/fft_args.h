@@ -201,8 +201,9 @@ void register_all_fft();
 
 // LDS bytes of one block (lines or columns NL) for each kernel family
 // Pitch of an LDS transpose with R values per k: R, padded by one where R is a multiple
-// of 4 (the bank-group reasoning is at the transposes in fft_passes.h).
-__host__ __device__ constexpr int tpitch(int R) { return R % 4 == 0 ? R + 1 : R; }
+// of 4 but not a power of two (the bank-group reasoning is at the transposes in
+// fft_passes.h).
+__host__ __device__ constexpr int tpitch(int R) { return (R % 4 == 0 && (R & (R - 1)) != 0) ? R + 1 : R; }
 // Row kernels hold either NL lines or the block's transpose [k][2 NL] (k <= F/2); the
 // circulant-embedding row kernel NL lines or a transpose [k][NL] (k < F).
 inline size_t rows_lds(const FftGeo& g, int NL, size_t csz) {

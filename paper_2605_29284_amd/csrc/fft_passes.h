@@ -71,12 +71,18 @@ template <int R1, int R2, int R3> struct RowCap {
 #define KRIG_ROW_KERNEL \
   __global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(RowCap<R1, R2, R3>::waves)))
 
-// LDS transposes [k][R] with the pitch tpitch(R).  A wave's 16-byte LDS accesses go
-// eight lanes at a time over 16 bank groups of 16 bytes, so eight lanes with
-// consecutive k (one side of the transpose) fall on distinct groups when the pitch is
-// not a multiple of 4; such pitches get one slot of padding.  Lanes with consecutive c
-// (the other side) read consecutive slots.
-__device__ __forceinline__ int tpos(int k, int c, int R) { return k * tpitch(R) + c; }
+// LDS transposes [k][R].  A wave's 16-byte LDS accesses go eight lanes at a time over
+// 16 bank groups of 16 bytes.  Eight lanes with consecutive k (one side of the
+// transpose) fall on distinct groups when R is not a multiple of 4.  For R = 4, 8, 16,
+// ... the columns of row k are rotated by floor(k / p), p = 16 / R (1 from R = 16 on):
+// rows k and k + p, which start in the same group, are then shifted one group apart.
+// Other multiples of 4 get a padded pitch (tpitch).  Lanes with consecutive c (the other
+// side) stay within one row or run into the next.
+__device__ __forceinline__ int tpos(int k, int c, int R) {
+  if ((R & 3) != 0 || (R & (R - 1)) != 0) return k * tpitch(R) + c;
+  const int sh = R >= 16 ? 0 : (R == 8 ? 1 : 2);
+  return k * R + ((c + (k >> sh)) & (R - 1));
+}
 
 // Workgroups go to the 8 XCDs (each with its own L2) round-robin by linear block id.
 // xcd_block maps the hardware id to a logical id so that each XCD runs one contiguous
