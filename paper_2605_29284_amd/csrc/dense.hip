@@ -338,7 +338,9 @@ __host__ __device__ inline int tri_splits(int n, int t, int upper) {
 }
 int tri_max_splits(int n) { return tri_splits(n, 0, 1); }
 
-template <int UPPER>
+// VEC: in_fs is a multiple of 4 and in 32-byte aligned, so a lane's four input values
+// are one 32-byte load (values past n are masked to zero).
+template <int UPPER, bool VEC>
 __global__ void __launch_bounds__(64) k_tri_part(const double* __restrict__ T, int64_t ldt, int n,
                                                  const double* __restrict__ in, int64_t in_fs, int B,
                                                  double* __restrict__ part, int qmax) {
@@ -360,8 +362,15 @@ __global__ void __launch_bounds__(64) k_tri_part(const double* __restrict__ T, i
     const int k = 16 * c + 4 * g;
     x[u] = (double4_t){0.0, 0.0, 0.0, 0.0};
     if (rok && c < ce) x[u] = *reinterpret_cast<const double4_t*>(trow + k);
+    if constexpr (VEC) {
+      double4_t av = (double4_t){0.0, 0.0, 0.0, 0.0};
+      if (fok && c < ce && k < n) av = *reinterpret_cast<const double4_t*>(irow + k);
 #pragma unroll
-    for (int s = 0; s < 4; ++s) a[u][s] = (fok && c < ce && k + s < n) ? irow[k + s] : 0.0;
+      for (int s = 0; s < 4; ++s) a[u][s] = k + s < n ? av[s] : 0.0;
+    } else {
+#pragma unroll
+      for (int s = 0; s < 4; ++s) a[u][s] = (fok && c < ce && k + s < n) ? irow[k + s] : 0.0;
+    }
   }
   double4_t acc = (double4_t){0.0, 0.0, 0.0, 0.0};
 #pragma unroll
@@ -401,11 +410,18 @@ hipError_t tri_apply(const double* T, int64_t ldt, int n, int upper, const doubl
     return hipErrorInvalidValue;
   const int qmax = tri_max_splits(n), nt = (n + 15) / 16, nfz = (B + 15) / 16;
   dim3 grid(nt, qmax, nfz);
+  const bool vec = (in_fs & 3) == 0 && (reinterpret_cast<uintptr_t>(in) & 31) == 0;
   if (upper) {
-    hipLaunchKernelGGL(k_tri_part<1>, grid, dim3(64), 0, st, T, ldt, n, in, in_fs, B, part, qmax);
+    if (vec)
+      hipLaunchKernelGGL((k_tri_part<1, true>), grid, dim3(64), 0, st, T, ldt, n, in, in_fs, B, part, qmax);
+    else
+      hipLaunchKernelGGL((k_tri_part<1, false>), grid, dim3(64), 0, st, T, ldt, n, in, in_fs, B, part, qmax);
     hipLaunchKernelGGL(k_tri_sum<1>, dim3(nt, nfz), dim3(256), 0, st, part, n, B, qmax, out, out_fs);
   } else {
-    hipLaunchKernelGGL(k_tri_part<0>, grid, dim3(64), 0, st, T, ldt, n, in, in_fs, B, part, qmax);
+    if (vec)
+      hipLaunchKernelGGL((k_tri_part<0, true>), grid, dim3(64), 0, st, T, ldt, n, in, in_fs, B, part, qmax);
+    else
+      hipLaunchKernelGGL((k_tri_part<0, false>), grid, dim3(64), 0, st, T, ldt, n, in, in_fs, B, part, qmax);
     hipLaunchKernelGGL(k_tri_sum<0>, dim3(nt, nfz), dim3(256), 0, st, part, n, B, qmax, out, out_fs);
   }
   return hipGetLastError();

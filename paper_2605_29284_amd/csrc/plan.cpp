@@ -80,7 +80,8 @@ struct krig_plan_s {
   void* SA = nullptr;     // cx FP64 [B][H2][ldP]   adjoint column-pass output
   void* img = nullptr;    // FP64 [B][P1][P2]       correlation image
   double* alpha = nullptr;  // [B][n]
-  double* tmpv = nullptr;   // [B][n]
+  double* tmpv = nullptr;   // [B][ldv]  between the two triangular products
+  int64_t ldv = 0;          // n rounded up to 4: 32-byte rows for vector loads
   double* tripart = nullptr;  // partial tiles of the split triangular products
   void* part = nullptr;   // cx FP64 [ngroups][H2][F1]
   int part_groups = 0;
@@ -312,7 +313,8 @@ int ensure_ws(krig_plan p, int B) {
   if ((r = dalloc_bytes(p, &p->S1, 16 * (size_t)B * H2 * p->ldP)) != KRIG_OK) return r;
   if ((r = dalloc_bytes(p, &p->S2, 16 * (size_t)B * H2 * p->ldM)) != KRIG_OK) return r;
   if ((r = dalloc(p, &p->alpha, (size_t)B * p->n)) != KRIG_OK) return r;
-  if ((r = dalloc(p, &p->tmpv, (size_t)B * p->n)) != KRIG_OK) return r;
+  p->ldv = (p->n + 3) / 4 * 4;
+  if ((r = dalloc(p, &p->tmpv, (size_t)B * p->ldv)) != KRIG_OK) return r;
   if ((r = dalloc(p, &p->tripart, tri_part_size(p->n, B))) != KRIG_OK) return r;
   p->wsB = B;
   return KRIG_OK;
@@ -338,8 +340,8 @@ int ensure_ws_adj(krig_plan p, int B) {
 
 int do_solve(krig_plan p, int B, const double* y, double* alpha) {
   StageTimer t(p, KRIG_STAGE_SOLVE);
-  KRIG_TRY(tri_apply(p->Linv, p->ldL, p->n, 0, y, p->n, p->tmpv, p->n, B, p->tripart, p->st));
-  KRIG_TRY(tri_apply(p->LinvT, p->ldL, p->n, 1, p->tmpv, p->n, alpha, p->n, B, p->tripart, p->st));
+  KRIG_TRY(tri_apply(p->Linv, p->ldL, p->n, 0, y, p->n, p->tmpv, p->ldv, B, p->tripart, p->st));
+  KRIG_TRY(tri_apply(p->LinvT, p->ldL, p->n, 1, p->tmpv, p->ldv, alpha, p->n, B, p->tripart, p->st));
   return KRIG_OK;
 }
 
