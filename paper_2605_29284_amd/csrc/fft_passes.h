@@ -84,6 +84,22 @@ __device__ __forceinline__ int tpos(int k, int c, int R) {
   return k * R + ((c + (k >> sh)) & (R - 1));
 }
 
+// The elements idx = tid, tid + NT NL, tid + 2 NT NL, ... of a [k][2 NL] transpose as
+// (k, rl) = (idx / (2 NL), idx mod 2 NL), stepped without a division: a step adds
+// NT NL = (NT / 2) 2 NL + (NT mod 2) NL.
+template <int NT> struct TWalk {
+  int k, rl;
+  const int nl;
+  __device__ __forceinline__ TWalk(int tid, int NL) : k(tid / (2 * NL)), rl(tid % (2 * NL)), nl(NL) {}
+  __device__ __forceinline__ void next() {
+    k += NT / 2;
+    if constexpr (NT % 2 != 0) {
+      rl += nl;
+      if (rl >= 2 * nl) { rl -= 2 * nl; ++k; }
+    }
+  }
+};
+
 // Workgroups go to the 8 XCDs (each with its own L2) round-robin by linear block id.
 // xcd_block maps the hardware id to a logical id so that each XCD runs one contiguous
 // range of logical blocks; blocks that share cache lines (neighbouring row blocks of a
@@ -440,10 +456,10 @@ KRIG_ROW_KERNEL k_rows_r2c(RowsR2CArgs a) {
   }
   __syncthreads();
   cx<TS>* o = reinterpret_cast<cx<TS>*>(a.out) + (int64_t)b * a.out_fs;
-  for (int idx = threadIdx.x; idx < a.H2 * R2b; idx += blockDim.x) {
-    const int rl = idx % R2b, k = idx / R2b;
-    const int row = row0 + rl;
-    if (row < a.nrows) o[(int64_t)k * a.out_ld + row] = ccast<TS>(T[tpos(k, rl, R2b)]);
+  // element idx = k R2b + rl of the transpose goes to thread idx mod blockDim (NT NL)
+  for (TWalk<G::NT> e(threadIdx.x, NL); e.k < a.H2; e.next()) {
+    const int row = row0 + e.rl;
+    if (row < a.nrows) o[(int64_t)e.k * a.out_ld + row] = ccast<TS>(T[tpos(e.k, e.rl, R2b)]);
   }
 }
 
@@ -705,21 +721,21 @@ KRIG_ROW_KERNEL k_rows_c2r(RowsC2RArgs a) {
   {
     // a thread's share is at most IT elements (blockDim = NT * NL, H2 = F/2 + 1): all
     // its loads are issued before the first LDS store
+    // element idx = k R2b + rl goes to thread idx mod blockDim (NT NL)
     constexpr int IT = (2 * (G::F / 2 + 1) + G::NT - 1) / G::NT;
-    const int tot = a.H2 * R2b;
     cx<TS> buf[IT];
+    {
+      TWalk<G::NT> e(threadIdx.x, NL);
 #pragma unroll
-    for (int it = 0; it < IT; ++it) {
-      const int idx = threadIdx.x + it * blockDim.x;
-      const int rl = idx % R2b, k = idx / R2b;
-      const int row = row0 + rl;
-      buf[it] = (idx < tot && row < a.nrows) ? in[(int64_t)k * a.in_ld + row] : mk<TS>(0, 0);
+      for (int it = 0; it < IT; ++it, e.next()) {
+        const int row = row0 + e.rl;
+        buf[it] = (e.k < a.H2 && row < a.nrows) ? in[(int64_t)e.k * a.in_ld + row] : mk<TS>(0, 0);
+      }
     }
+    TWalk<G::NT> e(threadIdx.x, NL);
 #pragma unroll
-    for (int it = 0; it < IT; ++it) {
-      const int idx = threadIdx.x + it * blockDim.x;
-      if (idx < tot) T[tpos(idx / R2b, idx % R2b, R2b)] = ccast<TC>(buf[it]);
-    }
+    for (int it = 0; it < IT; ++it, e.next())
+      if (e.k < a.H2) T[tpos(e.k, e.rl, R2b)] = ccast<TC>(buf[it]);
   }
   __syncthreads();
   cx<TC> v[G::NIN];
@@ -778,22 +794,22 @@ __global__ void __launch_bounds__(256) k_rows_c2r_fold(RowsC2RArgs a) {
   const cx<TC>* in = reinterpret_cast<const cx<TC>*>(a.in);
   {
     constexpr int IT = (2 * (G::F / 2 + 1) + G::NT - 1) / G::NT;  // as in k_rows_c2r
-    const int tot = a.H2 * R2b;
     cx<TC> b0[IT], b1[IT];
+    {
+      TWalk<G::NT> e(threadIdx.x, NL);
 #pragma unroll
-    for (int it = 0; it < IT; ++it) {
-      const int idx = threadIdx.x + it * blockDim.x;
-      const int rl = idx % R2b, k = idx / R2b;
-      const int u = row0 + rl;
-      const bool ok = idx < tot && u < n1l;
-      b0[it] = ok ? in[(int64_t)k * a.in_ld + u] : mk<TC>(0, 0);
-      b1[it] = (ok && u > 0) ? in[(int64_t)k * a.in_ld + 2 * n1l - 1 - u] : mk<TC>(0, 0);
+      for (int it = 0; it < IT; ++it, e.next()) {
+        const int u = row0 + e.rl;
+        const bool ok = e.k < a.H2 && u < n1l;
+        b0[it] = ok ? in[(int64_t)e.k * a.in_ld + u] : mk<TC>(0, 0);
+        b1[it] = (ok && u > 0) ? in[(int64_t)e.k * a.in_ld + 2 * n1l - 1 - u] : mk<TC>(0, 0);
+      }
     }
+    TWalk<G::NT> e(threadIdx.x, NL);
 #pragma unroll
-    for (int it = 0; it < IT; ++it) {
-      const int idx = threadIdx.x + it * blockDim.x;
-      const int u = row0 + idx % R2b;
-      if (idx < tot) T[tpos(idx / R2b, idx % R2b, R2b)] = u > 0 ? b0[it] + b1[it] : b0[it];
+    for (int it = 0; it < IT; ++it, e.next()) {
+      const int u = row0 + e.rl;
+      if (e.k < a.H2) T[tpos(e.k, e.rl, R2b)] = u > 0 ? b0[it] + b1[it] : b0[it];
     }
   }
   __syncthreads();
@@ -841,18 +857,21 @@ __global__ void __launch_bounds__(256) k_rows_ce(RowsCEArgs a) {
   const cx<TS>* in = reinterpret_cast<const cx<TS>*>(a.in) + (int64_t)by * a.in_fs;
   cx<TC>* T = lds;  // [k][l]
   {
-    constexpr int IT = (G::F + G::NT - 1) / G::NT;  // blockDim = NT * NL
+    // element idx = k NL + rl goes to thread idx mod blockDim (NT NL): a thread keeps
+    // its rl and steps k by NT
+    constexpr int IT = (G::F + G::NT - 1) / G::NT;
+    const int rl = threadIdx.x % NL, k0 = threadIdx.x / NL;
+    const int r = row0 + rl;
     cx<TS> buf[IT];
 #pragma unroll
     for (int it = 0; it < IT; ++it) {
-      const int idx = threadIdx.x + it * blockDim.x;
-      const int r = row0 + idx % NL;
-      buf[it] = (idx < G::F * NL && r < a.nrows) ? in[(int64_t)(idx / NL) * a.in_ld + r] : mk<TS>(0, 0);
+      const int k = k0 + it * G::NT;
+      buf[it] = (k < G::F && r < a.nrows) ? in[(int64_t)k * a.in_ld + r] : mk<TS>(0, 0);
     }
 #pragma unroll
     for (int it = 0; it < IT; ++it) {
-      const int idx = threadIdx.x + it * blockDim.x;
-      if (idx < G::F * NL) T[tpos(idx / NL, idx % NL, NL)] = ccast<TC>(buf[it]);
+      const int k = k0 + it * G::NT;
+      if (k < G::F) T[tpos(k, rl, NL)] = ccast<TC>(buf[it]);
     }
   }
   __syncthreads();
