@@ -7,7 +7,9 @@ Matern nu = 2.5, range 0.3, nugget 0.05, 350 x 350 grid, L = 3 -- with a batch
 of B = 16 data vectors: y -> alpha (FP64 solve) -> scatter + FFT convolution ->
 y_hat, then the adjoint of an upstream gradient g = 2 m y_hat (loss sum m y_hat^2,
 m a seeded U[0,1] mask) -> dy (FP64 solve) and d lag.  Inputs are resident in
-HBM before timing.  Prints one JSON line.
+HBM before timing.  The timed steps are the call loop; the same step recorded once
+as a HIP graph and replayed is timed too (graph_ms_per_step; --graph makes it the
+timed figure).  Prints one JSON line.
 """
 from __future__ import annotations
 
@@ -191,6 +193,8 @@ def main(argv=None):
     ap.add_argument("--cpu-fields", type=int, default=16)
     ap.add_argument("--no-fp64", action="store_true")
     ap.add_argument("--no-autotune", action="store_true", help="keep plan_create's launch shapes")
+    ap.add_argument("--graph", action="store_true",
+                    help="time replays of the step recorded as a HIP graph instead of the call loop")
     ap.add_argument("--uneven", action="store_true", help="time the 64-problem uneven batch instead")
     ap.add_argument("--uneven-count", type=int, default=64)
     ap.add_argument("--calibrate-copy-mib", type=int, default=0,
@@ -252,14 +256,27 @@ def main(argv=None):
                 p.predict(y, alpha_out=bf["alpha"], saved=bf["saved"], out=bf["yhat"])
                 p.adjoint(g, alpha=bf["alpha"], saved=bf["saved"], dy_out=bf["dy"], dlag_out=bf["dlag"])
 
-    def timed(p, bf, g, steps, hot=False):
+    def timed(p, bf, g, steps, hot=False, graph=None):
         s, e = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
         torch.cuda.synchronize()
         s.record()
-        run(p, bf, g, steps, hot)
+        if graph is None:
+            run(p, bf, g, steps, hot)
+        else:
+            for _ in range(steps):
+                graph.replay()
         e.record()
         torch.cuda.synchronize()
         return s.elapsed_time(e) / steps
+
+    def record(p, bf, g, hot=False):
+        # one step's launches recorded as a HIP graph (every kernel runs on each replay;
+        # the buffers are the same ones the eager loop uses)
+        graph = torch.cuda.CUDAGraph()
+        with torch.cuda.graph(graph):
+            run(p, bf, g, 1, hot)
+        torch.cuda.synchronize()
+        return graph
 
     mask = torch.as_tensor(w.extra["mask"], device=dev)
     res = {}
@@ -269,8 +286,15 @@ def main(argv=None):
         p.predict(y, alpha_out=bf["alpha"], saved=bf["saved"], out=bf["yhat"])
         g = (2.0 * mask.to(p.tdtype) * bf["yhat"]).contiguous()  # upstream gradient, fixed over the steps
         run(p, bf, g, a.warmup)
-        ms = timed(p, bf, g, a.steps)
-        hot_ms = timed(p, bf, g, a.steps, hot=True)
+        eager_ms = timed(p, bf, g, a.steps)
+        eager_hot_ms = timed(p, bf, g, a.steps, hot=True)
+        gr, gh = record(p, bf, g), record(p, bf, g, hot=True)
+        for _ in range(a.warmup):
+            gr.replay()
+        graph_ms = timed(p, bf, g, a.steps, graph=gr)
+        graph_hot_ms = timed(p, bf, g, a.steps, hot=True, graph=gh)
+        del gr, gh
+        ms, hot_ms = (graph_ms, graph_hot_ms) if a.graph else (eager_ms, eager_hot_ms)
         # per-stage kernel times (HIP events around each launch, same stream)
         p.timing(True)
         run(p, bf, g, a.steps)
@@ -278,7 +302,7 @@ def main(argv=None):
         p.timing(False)
         run(p, bf, g, 1)
         torch.cuda.synchronize()
-        res[dtype] = dict(plan=p, ms=ms, hot_ms=hot_ms, setup_ms=setup_ms, tune_ms=tune_ms, tuned=tuned, stages=stages,
+        res[dtype] = dict(plan=p, ms=ms, graph_ms=graph_ms, hot_ms=hot_ms, setup_ms=setup_ms, tune_ms=tune_ms, tuned=tuned, stages=stages,
                           yhat=bf["yhat"].double().cpu().numpy(), dy=bf["dy"].cpu().numpy(),
                           dlag=bf["dlag"].double().cpu().numpy())
 
@@ -315,6 +339,10 @@ def main(argv=None):
         "roofline": {"bound": "hbm", "kernel": dom, "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
                      "frac": achieved / HBM_PEAK_GBS, "traffic": recorded_traffic(dom),
                      "bytes_per_launch": sb[dom], "avg_launch_ms": avg[dom]},
+        "launch": "HIP graph replay of one recorded step" if a.graph else "call loop",
+        # the same step recorded once as a HIP graph and replayed (on this stack the graph
+        # is not faster than the call loop's launches)
+        "graph_ms_per_step": r32["graph_ms"],
         "hot_path_value": npred / (r32["hot_ms"] * 1e-3),
         "setup_ms": r32["setup_ms"],
         "autotune_ms": r32["tune_ms"],

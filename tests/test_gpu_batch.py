@@ -135,3 +135,42 @@ def test_batch_guards(krig, problems):
     finally:
         bt.close()
     host(p.predict(torch.zeros(64, p.n, dtype=torch.float64, device="cuda:0")))  # grows now
+
+
+@pytest.mark.parametrize("dtype", ["f32", "f64"])
+def test_step_graph_replays(krig, dtype):
+    """predict + adjoint recorded once in a HIP graph (torch capture of the plan's
+    calls: sized workspaces, no host synchronisation or memset inside) and replayed:
+    every replay must reproduce the eager step bit for bit, with eager work on the
+    same plan between the replays."""
+    w = wl.grad_batch(B=4)
+    say("step graph replays", dtype)
+    p = krig.plan_for(w, dtype)
+    y = dev(w.y)
+    B = y.shape[0]
+    alpha = torch.empty(B, w.n, dtype=torch.float64, device="cuda:0")
+    saved = p.new_saved(B)
+    yhat = p.empty(B, w.m1, w.m2)
+    dy = torch.empty(B, w.n, dtype=torch.float64, device="cuda:0")
+    dlag = p.empty(w.m1 + w.L, w.m2 + w.L)
+    g = (2.0 * dev(w.extra["mask"], yhat.dtype) * p.predict(y)).contiguous()
+
+    def step():
+        p.predict(y, alpha_out=alpha, saved=saved, out=yhat)
+        p.adjoint(g, alpha=alpha, saved=saved, dy_out=dy, dlag_out=dlag)
+
+    step()
+    ref = [host(t) for t in (alpha, yhat, dy, dlag)]
+    graph = torch.cuda.CUDAGraph()
+    with torch.cuda.graph(graph):
+        step()
+    for rep in range(3):
+        for t in (alpha, yhat, dy, dlag):
+            t.fill_(float("nan"))  # a replay must write every output
+        torch.cuda.synchronize()
+        graph.replay()
+        torch.cuda.synchronize()
+        for name, t, r in zip(("alpha", "yhat", "dy", "dlag"), (alpha, yhat, dy, dlag), ref):
+            assert np.array_equal(host(t), r), (rep, name)
+        host(p.predict(y))  # eager work on the same plan between replays
+    del graph

@@ -268,6 +268,31 @@ def test_adjoint_grad_batch_full_size(krig):
     assert relmax(dlag, ref_dlag) < 1e-6
 
 
+@pytest.mark.parametrize("dtype", ["f32", "f64"])
+def test_adjoint_repeatable_with_stage_timing(krig, dtype):
+    """Stage timing only brackets the launches with events: dy and dlag must agree bit
+    for bit with timing on and off, on repeated and back-to-back calls too."""
+    w = wl.grad_batch(B=4)
+    say("adjoint with and without stage timing", dtype)
+    p = krig.plan_for(w, dtype)
+    y = dev(w.y)
+    alpha = torch.empty(4, w.n, dtype=torch.float64, device="cuda:0")
+    saved = p.new_saved(4)
+    yhat = p.predict(y, alpha_out=alpha, saved=saved)
+    gup = (2.0 * dev(w.extra["mask"], yhat.dtype) * yhat).contiguous()
+    p.timing(True)
+    ref = [host(t) for t in p.adjoint(gup, alpha=alpha, saved=saved)]
+    p.timing(False)
+    for rep in range(3):
+        got = [host(t) for t in p.adjoint(gup, alpha=alpha, saved=saved)]
+        for a, b in zip(got, ref):
+            assert np.array_equal(a, b), rep
+    # back-to-back calls without a host synchronisation in between
+    outs = [p.adjoint(gup, alpha=alpha, saved=saved) for _ in range(3)]
+    for dy, dlag in outs:
+        assert np.array_equal(host(dy), ref[0]) and np.array_equal(host(dlag), ref[1])
+
+
 def test_adjoint_finite_differences_f64(krig):
     # loss = sum m yhat^2 is quadratic in y and in lag: central differences are exact up to rounding
     w = wl.tiny(seed=9, m1=30, m2=26, L=3, n=40, B=1, nu=2.5, rho=0.3, tau2=0.05)
