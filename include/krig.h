@@ -156,11 +156,10 @@ int krig_scatter(krig_plan p, int32_t B, const double *d_alpha, void *d_img);
  * caller lag quadrant (m1+L) x (m2+L) in dt whose spectrum is recomputed (FP64).
  * d_saved: NULL, or a buffer of B * KRIG_INFO_SAVED_PER_FIELD complex FP64 values
  * that receives the row spectra of c* for krig_predict_adjoint.
- * Precision: the scatter, the forward row transforms and the forward column
- * transforms run in FP64 arithmetic with FP64 storage; in a KRIG_F32 plan the
- * product with the filter spectrum is rounded to FP32 and the inverse column and
- * row transforms run in FP32 (the prediction is a cancellation-heavy sum, so the
- * forward half decides the accuracy).
+ * Precision: every transform, the scatter and the filter product run in FP64
+ * arithmetic with FP64 spectra between the passes, in both dtypes (the prediction
+ * is a cancellation-heavy sum); a KRIG_F32 plan rounds d_yhat (and reads d_lag) in
+ * FP32 only.
  */
 int krig_convolve(krig_plan p, int32_t B, const double *d_alpha, const void *d_lag, void *d_yhat,
                   void *d_saved);
@@ -188,6 +187,21 @@ int krig_predict(krig_plan p, int32_t B, const double *d_y, const void *d_lag, v
  */
 int krig_predict_adjoint(krig_plan p, int32_t B, const void *d_g, const double *d_alpha,
                          const void *d_saved, const void *d_lag, double *d_dy, void *d_dlag);
+
+/*
+ * Off-grid predictions (the closing discussion of Section 6: predict on a fine mesh,
+ * then interpolate locally with polynomials).  d_yhat [B][m1][m2] dt is a mesh
+ * prediction (e.g. from krig_predict); d_pts [npts][2] FP64 holds (x, y) per point;
+ * d_out [B][npts] dt receives, per field, the tensor-product Lagrange polynomial of
+ * degree q-1 in x and in y through the q x q mesh nodes around each point: with
+ * t = (x - x0)/dx in FP64, the x nodes are sx .. sx+q-1, sx = floor(t) + 1 - ceil(q/2)
+ * clamped to [0, m1-q] (the same in y).  A point on a mesh node gets that node's value
+ * exactly.  Requires 2 <= q <= 8, q <= m1, q <= m2 and B <= 65535 (else KRIG_EINVAL).
+ * Points outside the grid's bounding box (t or u outside [0, m-1], or NaN) give NaN.
+ * FP64 arithmetic; asynchronous on the plan's stream; d_out must not overlap d_yhat.
+ */
+int krig_interp(krig_plan p, int32_t B, const void *d_yhat, int32_t npts, const double *d_pts, int32_t q,
+                void *d_out);
 
 /*
  * Conditional simulation (Section 1 steps (1)-(2); circulant embedding as in the

@@ -30,7 +30,7 @@ STATUS = {0: "KRIG_OK", -1: "KRIG_EINVAL", -2: "KRIG_EDOMAIN", -3: "KRIG_ENOTSPD
 
 EXPORTS = ["krig_plan_create", "krig_plan_destroy", "krig_plan_info", "krig_set_stream", "krig_weights",
            "krig_set_weights", "krig_lag", "krig_solve", "krig_scatter", "krig_convolve", "krig_predict",
-           "krig_predict_adjoint", "krig_csim", "krig_plan_tune", "krig_plan_autotune", "krig_predict_many", "krig_batch_create",
+           "krig_predict_adjoint", "krig_csim", "krig_interp", "krig_plan_tune", "krig_plan_autotune", "krig_predict_many", "krig_batch_create",
            "krig_batch_launch", "krig_batch_destroy", "krig_timing_enable", "krig_timing_read", "krig_strerror"]
 
 STAGES = ["ROWS_FWD", "COLS_CONV", "ROWS_INV", "ADJ_ROWS_FWD", "ADJ_COLS", "ADJ_ROWS_INV", "GATHER", "SOLVE",
@@ -80,6 +80,7 @@ def load_library(path: str = LIB_PATH) -> ctypes.CDLL:
         "krig_predict": [vp, i32, dp, dp, dp, dp, dp],
         "krig_predict_adjoint": [vp, i32, dp, dp, dp, dp, dp, dp],
         "krig_csim": [vp, i32, ctypes.c_uint64, dp, dp],
+        "krig_interp": [vp, i32, dp, i32, dp, i32, dp],
         "krig_plan_tune": [vp, i32, i64],
         "krig_plan_autotune": [vp, i32, i32],
         "krig_predict_many": [ctypes.POINTER(vp), i32, ctypes.POINTER(i32), ctypes.POINTER(vp), ctypes.POINTER(vp), vp],
@@ -296,6 +297,21 @@ class Plan:
             cnt = ctypes.c_int64()
             _check(self.lib.krig_timing_read(self.h, i, ctypes.byref(ms), ctypes.byref(cnt)), "krig_timing_read")
             out[name] = (float(ms.value), int(cnt.value))
+        return out
+
+    def interp(self, yhat, pts, q: int = 4, out=None):
+        """Off-grid predictions (krig_interp): the mesh prediction yhat [B][m1][m2]
+        (plan dtype) interpolated to pts [npts][2] (FP64) -> [B][npts] (plan dtype)."""
+        yhat = self._batch(yhat, (self.m1, self.m2), "yhat", self.tdtype)
+        B = yhat.shape[0]
+        if pts.dim() != 2 or pts.shape[1] != 2:
+            raise ValueError("pts: expected shape (npts, 2)")
+        pts = self._t(pts, self.torch.float64, tuple(pts.shape), "pts")
+        npts = pts.shape[0]
+        out = self.empty(B, npts) if out is None else self._t(out, self.tdtype, (B, npts), "out")
+        self._stream()
+        _check(self.lib.krig_interp(self.h, B, yhat.data_ptr(), npts, pts.data_ptr(), int(q), out.data_ptr()),
+               "krig_interp")
         return out
 
     def csim(self, R: int, seed: int, y):

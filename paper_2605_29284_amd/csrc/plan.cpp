@@ -15,6 +15,7 @@
 
 #include "../../include/krig.h"
 #include "dense.h"
+#include "interp.h"
 #include "fft_args.h"
 #include "fft_reg.h"
 #include "setup.h"
@@ -1053,6 +1054,29 @@ int krig_predict_adjoint(krig_plan p, int32_t B, const void* d_g, const double* 
     oc.NL = p->nl_rows64;
     KRIG_TRY((is32(p) ? set2(p).c2r_fold32 : set2(p).c2r_fold64)(oc, 1, p->st));
   }
+  return KRIG_OK;
+}
+
+int krig_interp(krig_plan p, int32_t B, const void* d_yhat, int32_t npts, const double* d_pts, int32_t q,
+                void* d_out) {
+  if (!p || B < 1 || B > 65535 || npts < 0 || !d_yhat) return KRIG_EINVAL;
+  if (q < 2 || q > 8 || q > p->g.m1 || q > p->g.m2) return KRIG_EINVAL;
+  if (npts == 0) return KRIG_OK;
+  if (!d_pts || !d_out) return KRIG_EINVAL;
+  InterpArgs a{};
+  a.yhat = d_yhat;
+  a.yhat_fs = (int64_t)p->g.m1 * p->g.m2;
+  a.m1 = p->g.m1;
+  a.m2 = p->g.m2;
+  a.x0 = p->g.x0;
+  a.y0 = p->g.y0;
+  a.dx = p->g.dx;
+  a.dy = p->g.dy;
+  a.pts = d_pts;
+  a.npts = npts;
+  a.out = d_out;
+  a.out_fs = npts;
+  KRIG_TRY(interp_points(a, B, q, is32(p), p->st));
   return KRIG_OK;
 }
 
