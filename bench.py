@@ -30,11 +30,12 @@ HBM_PEAK_GBS = 8000.0  # MI355X HBM3E, GB/s
 PROFILES = os.path.join(ROOT, "profiles")
 # sources of the FFT pass kernels: a recorded traffic figure holds only while they are unchanged
 KERNEL_SOURCES = ["fft_passes.h", "fft_args.h", "fft_reg.h", "krig_internal.h", "matern_dev.h", "philox_dev.h"]
+STAGE_SOURCES = {"INTERP": ["interp.hip", "interp.h"]}  # stages whose kernel lives elsewhere
 
 
-def kernel_source_hash():
+def kernel_source_hash(stage=None):
     h = hashlib.sha256()
-    for name in KERNEL_SOURCES:
+    for name in STAGE_SOURCES.get(stage, KERNEL_SOURCES):
         with open(os.path.join(ROOT, "paper_2605_29284_amd", "csrc", name), "rb") as f:
             h.update(f.read())
     return h.hexdigest()[:16]
@@ -52,7 +53,7 @@ def recorded_traffic(stage):
         txt = open(os.path.join(PROFILES, name)).read()
         m = re.search(r"^traffic_bytes_per_launch:\s*([0-9.eE+]+)\s*$", txt, re.M)
         h = re.search(r"^kernel_source_hash:\s*([0-9a-f]+)\s*$", txt, re.M)
-        if m and h and h.group(1) == kernel_source_hash():
+        if m and h and h.group(1) == kernel_source_hash(stage):
             return float(m.group(1))
     return None
 
@@ -183,6 +184,60 @@ def uneven(a, torch, krig, wl, dev):
     return 0
 
 
+def interp_mode(a, torch, krig, wl, dev):
+    """Off-grid predictions (krig_interp): the paper-sized mesh prediction (350x350, B fields,
+    FP32 plan) interpolated to seeded uniform points with q x q local Lagrange stencils.
+    Prints one JSON line."""
+    w = wl.grad_batch(B=a.B)
+    B, npts, q = a.B, a.interp_points, a.interp_q
+    p = krig.plan_for(w, "f32")
+    yhat = p.predict(torch.as_tensor(w.y, dtype=torch.float64, device=dev))
+    rng = np.random.default_rng(99)
+    pts_h = np.stack([w.x0 + rng.uniform(0, w.m1 - 1, npts) * w.dx, w.y0 + rng.uniform(0, w.m2 - 1, npts) * w.dy], 1)
+    pts = torch.as_tensor(pts_h, dtype=torch.float64, device=dev)
+    out = torch.empty(B, npts, dtype=torch.float32, device=dev)
+    for _ in range(a.warmup):
+        p.interp(yhat, pts, q, out=out)
+    s, e = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    torch.cuda.synchronize()
+    s.record()
+    for _ in range(a.steps):
+        p.interp(yhat, pts, q, out=out)
+    e.record()
+    torch.cuda.synchronize()
+    ms = s.elapsed_time(e) / a.steps
+    # algorithmic bytes: the points once, every output once, the mesh prediction once
+    nbytes = npts * 16 + B * npts * 4 + B * w.m1 * w.m2 * 4
+    achieved = nbytes / (ms * 1e-3) / 1e9
+    res = {"metric": "off-grid predictions/s (mesh prediction -> irregular points, local Lagrange q=%d)" % q,
+           "value": B * npts / (ms * 1e-3), "unit": "off-grid predictions/s", "n_gpus": 1, "steps": a.steps,
+           "warmup": a.warmup, "ms_per_step": ms, "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
+           "dtype": "f64", "io_dtype": "f32", "data": "synthetic",
+           "config": {"workload": "off-grid interpolation: 350x350 mesh prediction of the paper-sized field, "
+                                  "%d fields, %d seeded uniform points, %dx%d Lagrange stencils" % (B, npts, q, q),
+                      "B": B, "points": npts, "q": q, "grid": [w.m1, w.m2]},
+           "roofline": {"bound": "hbm", "kernel": "INTERP", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                        "frac": achieved / HBM_PEAK_GBS, "traffic": recorded_traffic("INTERP"),
+                        "bytes_per_launch": nbytes, "avg_launch_ms": ms}}
+    if not a.no_cpu_baseline:
+        from threadpoolctl import threadpool_limits
+
+        from oracle.interp import interp_points
+        from oracle.rapid import Grid
+        g = Grid(w.m1, w.m2, w.x0, w.y0, w.dx, w.dy, w.L)
+        Yh = yhat.double().cpu().numpy()
+        nf, npc = min(4, B), min(npts, 100_000)
+        with threadpool_limits(limits=1):
+            t0 = time.perf_counter()
+            for b in range(nf):
+                interp_points(g, Yh[b], pts_h[:npc], q)
+            dt = time.perf_counter() - t0
+        res["cpu_baseline"] = {"value": nf * npc / dt, "unit": "off-grid predictions/s", "cores": 1, "kind": "oracle",
+                               "sample": f"{nf} fields x {npc} points, one thread, {dt:.1f} s"}
+    print(json.dumps(res), flush=True)
+    return 0
+
+
 def main(argv=None):
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -197,6 +252,9 @@ def main(argv=None):
                     help="time replays of the step recorded as a HIP graph instead of the call loop")
     ap.add_argument("--uneven", action="store_true", help="time the 64-problem uneven batch instead")
     ap.add_argument("--uneven-count", type=int, default=64)
+    ap.add_argument("--interp", action="store_true", help="time off-grid predictions (krig_interp) instead")
+    ap.add_argument("--interp-points", type=int, default=1_000_000)
+    ap.add_argument("--interp-q", type=int, default=4)
     ap.add_argument("--calibrate-copy-mib", type=int, default=0,
                     help="only run a plain device copy of this many MiB (counter calibration) and exit")
     a = ap.parse_args(argv)
@@ -225,6 +283,8 @@ def main(argv=None):
         return 0
     if a.uneven:
         return uneven(a, torch, krig, wl, dev)
+    if a.interp:
+        return interp_mode(a, torch, krig, wl, dev)
     w = wl.grad_batch(B=a.B)
     B = a.B
 
