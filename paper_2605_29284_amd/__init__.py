@@ -29,7 +29,7 @@ STATUS = {0: "KRIG_OK", -1: "KRIG_EINVAL", -2: "KRIG_EDOMAIN", -3: "KRIG_ENOTSPD
           -5: "KRIG_ENOMEM", -6: "KRIG_EHIP", -7: "KRIG_EUNSUPPORTED"}
 
 EXPORTS = ["krig_plan_create", "krig_plan_destroy", "krig_plan_info", "krig_set_stream", "krig_weights",
-           "krig_set_weights", "krig_lag", "krig_solve", "krig_scatter", "krig_convolve", "krig_predict",
+           "krig_set_weights", "krig_set_kvec", "krig_lag", "krig_solve", "krig_scatter", "krig_convolve", "krig_predict",
            "krig_predict_adjoint", "krig_csim", "krig_interp", "krig_plan_tune", "krig_plan_autotune", "krig_predict_many", "krig_batch_create",
            "krig_batch_launch", "krig_batch_destroy", "krig_timing_enable", "krig_timing_read", "krig_strerror"]
 
@@ -73,6 +73,7 @@ def load_library(path: str = LIB_PATH) -> ctypes.CDLL:
         "krig_set_stream": [vp, vp],
         "krig_weights": [vp, dp, dp],
         "krig_set_weights": [vp, dp, dp],
+        "krig_set_kvec": [vp, dp],
         "krig_lag": [vp, dp],
         "krig_solve": [vp, i32, dp, dp],
         "krig_scatter": [vp, i32, dp, dp],
@@ -199,6 +200,13 @@ class Plan:
         self._t(W, self.torch.float64, (self.n, self.M), "W")
         self._stream()
         _check(self.lib.krig_set_weights(self.h, anchor.data_ptr(), W.data_ptr()), "krig_set_weights")
+
+    def set_kvec(self, kvec):
+        """Weights from caller covariance vectors k_i [n][M] FP64 (krig_set_kvec):
+        W_i = K_N^{-1} k_i with the plan's stationary K_N."""
+        kvec = self._t(kvec, self.torch.float64, (self.n, self.M), "kvec")
+        self._stream()
+        _check(self.lib.krig_set_kvec(self.h, kvec.data_ptr()), "krig_set_kvec")
 
     def lag(self):
         out = self.empty(self.m1 + self.L, self.m2 + self.L)

@@ -869,6 +869,26 @@ int krig_set_weights(krig_plan p, const int32_t* d_anchor, const double* d_W) {
   return KRIG_OK;
 }
 
+int krig_set_kvec(krig_plan p, const double* d_kvec) {
+  if (!p || !d_kvec) return KRIG_EINVAL;
+  const int n = p->n, M = p->M;
+  // Step 4 with the caller's k_i: W = (k L_N^{-T}) L_N^{-1}, the products of plan
+  // creation; Wt holds the intermediate and is rebuilt from W afterwards
+  GemmArgs ga{};
+  ga.A = d_kvec; ga.lda = M; ga.transA = 0;
+  ga.B = p->LinvN; ga.ldb = M; ga.transB = 1;
+  ga.C = p->Wt; ga.ldc = M;
+  ga.m_off = 0; ga.M_end = n; ga.n_off = 0; ga.N_end = M; ga.K = M;
+  ga.alpha = 1.0; ga.beta = 0.0; ga.lower = 0;
+  KRIG_TRY(gemm_f64(ga, p->st));
+  GemmArgs gb = ga;
+  gb.A = p->Wt; gb.transB = 0; gb.C = p->W;
+  KRIG_TRY(gemm_f64(gb, p->st));
+  KRIG_TRY(transpose_w(p->W, n, M, p->Wt, p->st));
+  KRIG_TRY(build_csr(p->g, p->anchor, p->W, n, p->cw, p->node_ptr, p->ent_site, p->ent_w, p->st));
+  return KRIG_OK;
+}
+
 int krig_lag(krig_plan p, void* d_lag) {
   if (!p || !d_lag) return KRIG_EINVAL;
   KRIG_TRY(hipMemcpyAsync(d_lag, p->lagT, p->tsz * p->n1l * p->n2l, hipMemcpyDeviceToDevice, p->st));
