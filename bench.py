@@ -238,6 +238,47 @@ def interp_mode(a, torch, krig, wl, dev):
     return 0
 
 
+def nonstat_mode(a, torch, krig, wl, dev):
+    """Nonstationary covariance vectors (krig_set_kvec) on the paper-sized field: weights
+    from caller k_i (C(p, q) = sd(p) sd(q) k(p - q)), then the convolution of B fields'
+    coefficients with them.  Prints one JSON line."""
+    from oracle.matern import Matern
+    from oracle.nonstat import kvecs_cov, scaled_cov
+    from oracle.rapid import Grid
+    w = wl.grad_batch(B=a.B)
+    g = Grid(w.m1, w.m2, w.x0, w.y0, w.dx, w.dy, w.L)
+    k = Matern(w.sigma2, w.rho, w.nu, w.tau2)
+    sd = lambda p: 1.0 + 0.3 * np.sin(3.0 * p[..., 0] + 0.5) * np.cos(2.0 * p[..., 1])
+    kv = torch.as_tensor(kvecs_cov(g, w.sites, scaled_cov(k, sd)), dtype=torch.float64, device=dev)
+    p = krig.plan_for(w, "f32")
+    alpha = torch.as_tensor(np.random.default_rng(0).standard_normal((a.B, w.n)), dtype=torch.float64, device=dev)
+    out = torch.empty(a.B, w.m1, w.m2, dtype=torch.float32, device=dev)
+
+    def timed(fn):
+        for _ in range(a.warmup):
+            fn()
+        s, e = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        torch.cuda.synchronize()
+        s.record()
+        for _ in range(a.steps):
+            fn()
+        e.record()
+        torch.cuda.synchronize()
+        return s.elapsed_time(e) / a.steps
+
+    ms_kvec = timed(lambda: p.set_kvec(kv))
+    ms_conv = timed(lambda: p.convolve(alpha, out=out))
+    res = {"metric": "nonstationary k_i: weight updates (krig_set_kvec) and predictions with them",
+           "value": a.B * w.m1 * w.m2 / (ms_conv * 1e-3), "unit": "grid predictions/s", "n_gpus": 1,
+           "steps": a.steps, "warmup": a.warmup, "ms_per_step": ms_conv, "higher_is_better": True,
+           "scaling": "weak", "vs_baseline": None, "dtype": "f64", "io_dtype": "f32", "data": "synthetic",
+           "config": {"workload": "paper-sized field (n=1368, 350x350, L=3), caller k_i from "
+                                  "sd(p) sd(q) k(p - q); B fields of coefficients", "B": a.B},
+           "set_kvec_ms": ms_kvec, "weights_per_s": w.n / (ms_kvec * 1e-3)}
+    print(json.dumps(res), flush=True)
+    return 0
+
+
 def main(argv=None):
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -253,6 +294,7 @@ def main(argv=None):
     ap.add_argument("--uneven", action="store_true", help="time the 64-problem uneven batch instead")
     ap.add_argument("--uneven-count", type=int, default=64)
     ap.add_argument("--interp", action="store_true", help="time off-grid predictions (krig_interp) instead")
+    ap.add_argument("--nonstat", action="store_true", help="time weights from caller k_i (krig_set_kvec) instead")
     ap.add_argument("--interp-points", type=int, default=1_000_000)
     ap.add_argument("--interp-q", type=int, default=4)
     ap.add_argument("--calibrate-copy-mib", type=int, default=0,
@@ -285,6 +327,8 @@ def main(argv=None):
         return uneven(a, torch, krig, wl, dev)
     if a.interp:
         return interp_mode(a, torch, krig, wl, dev)
+    if a.nonstat:
+        return nonstat_mode(a, torch, krig, wl, dev)
     w = wl.grad_batch(B=a.B)
     B = a.B
 
