@@ -218,6 +218,24 @@ int krig_interp(krig_plan p, int32_t B, const void *d_yhat, int32_t npts, const 
                 void *d_out);
 
 /*
+ * Nonstationary mixture (Section 6, discussion: a covariance that combines several
+ * stationary covariances with spatially varying weights is predicted by running the
+ * rapid predictor per stationary component and combining the results):
+ *   C(s, s') = sum_c lam_c(s) lam_c(s') k_c(s - s'),
+ *   d_yhat[b](s) = sum_c lam_c(s) * rapid_c( lam_c(s_i) alpha[b][i] )(s)  on the m1 x m2 grid.
+ * plans[c], c < C <= 8: one distinct plan per component (its kernel k_c, its weights and lag
+ * image), all built on the same sites in the same order (not checked) and the same grid
+ * nodes and dtype (checked: KRIG_EINVAL otherwise).  d_alpha [B][n] FP64: the mixture
+ * model's coefficients (the caller's solve); d_lam_sites [C][n] FP64: lam_c at the sites;
+ * d_lam_grid [C][m1][m2] FP64: lam_c at the grid nodes; d_yhat [B][m1][m2] in the plans'
+ * dtype.  The components' predictions go to each plan's workspace (grown at a new B, like
+ * the other workspaces) and are summed in component order in FP64, rounded once.  Runs
+ * on stream (NULL: plans[0]'s stream); asynchronous.
+ */
+int krig_mixture(const krig_plan *plans, int32_t C, int32_t B, const double *d_alpha,
+                 const double *d_lam_sites, const double *d_lam_grid, void *d_yhat, void *stream);
+
+/*
  * Conditional simulation (Section 1 steps (1)-(2); circulant embedding as in the
  * discussion section): R realisations on the m1 x m2 grid, d_fields [R][m1][m2] dt.
  * Realisation r: unconditional field u on the padded grid by circulant embedding

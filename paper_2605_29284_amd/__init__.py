@@ -30,7 +30,7 @@ STATUS = {0: "KRIG_OK", -1: "KRIG_EINVAL", -2: "KRIG_EDOMAIN", -3: "KRIG_ENOTSPD
 
 EXPORTS = ["krig_plan_create", "krig_plan_destroy", "krig_plan_info", "krig_set_stream", "krig_weights",
            "krig_set_weights", "krig_set_kvec", "krig_lag", "krig_solve", "krig_scatter", "krig_convolve", "krig_predict",
-           "krig_predict_adjoint", "krig_csim", "krig_interp", "krig_plan_tune", "krig_plan_autotune", "krig_predict_many", "krig_batch_create",
+           "krig_predict_adjoint", "krig_csim", "krig_interp", "krig_mixture", "krig_plan_tune", "krig_plan_autotune", "krig_predict_many", "krig_batch_create",
            "krig_batch_launch", "krig_batch_destroy", "krig_timing_enable", "krig_timing_read", "krig_strerror"]
 
 STAGES = ["ROWS_FWD", "COLS_CONV", "ROWS_INV", "ADJ_ROWS_FWD", "ADJ_COLS", "ADJ_ROWS_INV", "GATHER", "SOLVE",
@@ -82,6 +82,7 @@ def load_library(path: str = LIB_PATH) -> ctypes.CDLL:
         "krig_predict_adjoint": [vp, i32, dp, dp, dp, dp, dp, dp],
         "krig_csim": [vp, i32, ctypes.c_uint64, dp, dp],
         "krig_interp": [vp, i32, dp, i32, dp, i32, dp],
+        "krig_mixture": [ctypes.POINTER(vp), i32, i32, dp, dp, dp, dp, vp],
         "krig_plan_tune": [vp, i32, i64],
         "krig_plan_autotune": [vp, i32, i32],
         "krig_predict_many": [ctypes.POINTER(vp), i32, ctypes.POINTER(i32), ctypes.POINTER(vp), ctypes.POINTER(vp), vp],
@@ -346,6 +347,24 @@ def _many_args(plans, ys, outs):
     hy = (ctypes.c_void_p * k)(*[y.data_ptr() for y in ys])
     ho = (ctypes.c_void_p * k)(*[o.data_ptr() for o in outs])
     return k, hp, hb, hy, ho
+
+
+def mixture(plans, alpha, lam_sites, lam_grid, out=None):
+    """Nonstationary mixture prediction (krig_mixture): plans[c] is component c's plan
+    (same sites, grid and dtype); alpha [B][n] FP64, lam_sites [C][n] FP64, lam_grid
+    [C][m1][m2] FP64 -> [B][m1][m2] in the plans' dtype, on torch's current stream."""
+    p0 = plans[0]
+    C = len(plans)
+    alpha = p0._batch(alpha, (p0.n,), "alpha", p0.torch.float64)
+    B = alpha.shape[0]
+    p0._t(lam_sites, p0.torch.float64, (C, p0.n), "lam_sites")
+    p0._t(lam_grid, p0.torch.float64, (C, p0.m1, p0.m2), "lam_grid")
+    out = p0.empty(B, p0.m1, p0.m2) if out is None else p0._t(out, p0.tdtype, (B, p0.m1, p0.m2), "out")
+    hp = (ctypes.c_void_p * C)(*[p.h for p in plans])
+    st = p0.torch.cuda.current_stream(p0.device).cuda_stream
+    _check(p0.lib.krig_mixture(hp, C, B, alpha.data_ptr(), lam_sites.data_ptr(), lam_grid.data_ptr(),
+                               out.data_ptr(), st), "krig_mixture")
+    return out
 
 
 def predict_many(plans, ys, outs):

@@ -16,6 +16,7 @@
 #include "../../include/krig.h"
 #include "dense.h"
 #include "interp.h"
+#include "mixture.h"
 #include "fft_args.h"
 #include "fft_reg.h"
 #include "setup.h"
@@ -87,6 +88,8 @@ struct krig_plan_s {
   void* part = nullptr;   // cx FP64 [ngroups][H2][F1]
   int part_groups = 0;
   void* XC = nullptr;     // cx FP64 [H2][ldX]
+  void* mix = nullptr;    // dt [B][m1][m2]  this plan's component of a mixture prediction
+  int wsB_mix = 0;
   // custom-lag filter
   double* filtC = nullptr;
   double* lagC64 = nullptr;
@@ -336,6 +339,19 @@ int ensure_ws_adj(krig_plan p, int B) {
   p->part_groups = B;  // worst case G = 1
   if ((r = dalloc_bytes(p, &p->part, 16 * (size_t)p->part_groups * H2 * p->F1)) != KRIG_OK) return r;
   p->wsB_adj = B;
+  return KRIG_OK;
+}
+
+// mixture-component output for B fields
+int ensure_ws_mix(krig_plan p, int B) {
+  if (B <= p->wsB_mix) return KRIG_OK;
+  if (p->batch_refs > 0) return KRIG_EINVAL;
+  KRIG_TRY(hipStreamSynchronize(p->st));
+  dfree(p, p->mix);
+  p->mix = nullptr;
+  int r;
+  if ((r = dalloc_bytes(p, &p->mix, p->tsz * (size_t)B * p->g.m1 * p->g.m2)) != KRIG_OK) return r;
+  p->wsB_mix = B;
   return KRIG_OK;
 }
 
@@ -1336,6 +1352,45 @@ static int check_many(const krig_plan* plans, int32_t count, const int32_t* h_B,
   if (!plans || count < 1 || !h_y || !h_yhat) return KRIG_EINVAL;
   for (int i = 0; i < count; ++i)
     if (!plans[i] || !h_y[i] || !h_yhat[i] || (h_B && h_B[i] < 1)) return KRIG_EINVAL;
+  return KRIG_OK;
+}
+
+int krig_mixture(const krig_plan* plans, int32_t C, int32_t B, const double* d_alpha, const double* d_lam_sites,
+                 const double* d_lam_grid, void* d_yhat, void* stream) {
+  if (!plans || C < 1 || C > MIX_MAX || B < 1 || !d_alpha || !d_lam_sites || !d_lam_grid || !d_yhat)
+    return KRIG_EINVAL;
+  const krig_plan p0 = plans[0];
+  if (!p0) return KRIG_EINVAL;
+  for (int c = 0; c < C; ++c) {
+    const krig_plan p = plans[c];
+    if (!p || p->n != p0->n || p->dtype != p0->dtype || p->g.m1 != p0->g.m1 || p->g.m2 != p0->g.m2 ||
+        p->g.x0 != p0->g.x0 || p->g.y0 != p0->g.y0 || p->g.dx != p0->g.dx || p->g.dy != p0->g.dy)
+      return KRIG_EINVAL;
+    for (int e = 0; e < c; ++e)
+      if (plans[e] == p) return KRIG_EINVAL;  // each component needs its own workspaces
+  }
+  const hipStream_t st = stream ? (hipStream_t)stream : p0->st;
+  const int n = p0->n;
+  MixArgs m{};
+  m.lam = d_lam_grid;
+  m.C = C;
+  m.npix = (int64_t)p0->g.m1 * p0->g.m2;
+  m.B = B;
+  m.out = d_yhat;
+  for (int c = 0; c < C; ++c) {
+    const krig_plan p = plans[c];
+    int r;
+    if ((r = ensure_ws(p, B)) != KRIG_OK || (r = ensure_ws_mix(p, B)) != KRIG_OK) return r;
+    const hipStream_t old = p->st;
+    p->st = st;
+    // component c: the coefficients lam_c(s_i) alpha_i through this plan's rapid predictor
+    r = hip_status(mix_scale_coef(d_alpha, d_lam_sites + (size_t)c * n, n, B, p->alpha, st));
+    if (r == KRIG_OK) r = krig_convolve(p, B, p->alpha, nullptr, p->mix, nullptr);
+    p->st = old;
+    if (r != KRIG_OK) return r;
+    m.comp[c] = p->mix;
+  }
+  KRIG_TRY(mix_combine(m, is32(p0), st));
   return KRIG_OK;
 }
 
