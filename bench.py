@@ -279,6 +279,42 @@ def nonstat_mode(a, torch, krig, wl, dev):
     return 0
 
 
+def mixture_mode(a, torch, krig, wl, dev):
+    """Nonstationary mixture (krig_mixture) on the paper-sized field: two stationary
+    components (the field's own Matern nu = 2.5, range 0.3 and a nu = 1.5, range 0.15 one)
+    with weights cos^2 / sin^2 of x, B fields of coefficients.  Prints one JSON line."""
+    import dataclasses
+    w = wl.grad_batch(B=a.B)
+    w2 = dataclasses.replace(w, sigma2=0.5, rho=0.15, nu=1.5)
+    plans = [krig.plan_for(w, "f32"), krig.plan_for(w2, "f32")]
+    lam = [lambda p: np.cos(1.5 * p[..., 0]) ** 2 + 0.1, lambda p: np.sin(1.5 * p[..., 0]) ** 2 + 0.1]
+    X, Y = np.meshgrid(w.x0 + np.arange(w.m1) * w.dx, w.y0 + np.arange(w.m2) * w.dy, indexing="ij")
+    nodes = np.stack([X, Y], -1)
+    lam_sites = torch.as_tensor(np.stack([f(w.sites) for f in lam]), dtype=torch.float64, device=dev)
+    lam_grid = torch.as_tensor(np.stack([f(nodes) for f in lam]), dtype=torch.float64, device=dev)
+    alpha = torch.as_tensor(np.random.default_rng(0).standard_normal((a.B, w.n)), dtype=torch.float64, device=dev)
+    out = torch.empty(a.B, w.m1, w.m2, dtype=torch.float32, device=dev)
+    for _ in range(a.warmup):
+        krig.mixture(plans, alpha, lam_sites, lam_grid, out=out)
+    s, e = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    torch.cuda.synchronize()
+    s.record()
+    for _ in range(a.steps):
+        krig.mixture(plans, alpha, lam_sites, lam_grid, out=out)
+    e.record()
+    torch.cuda.synchronize()
+    ms = s.elapsed_time(e) / a.steps
+    res = {"metric": "grid predictions/s, nonstationary mixture of 2 stationary components",
+           "value": a.B * w.m1 * w.m2 / (ms * 1e-3), "unit": "grid predictions/s", "n_gpus": 1, "steps": a.steps,
+           "warmup": a.warmup, "ms_per_step": ms, "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
+           "dtype": "f64", "io_dtype": "f32", "data": "synthetic",
+           "config": {"workload": "paper-sized field (n=1368, 350x350, L=3), components Matern(nu 2.5, range 0.3) and "
+                                  "Matern(nu 1.5, range 0.15), weights cos^2 / sin^2 of x; B fields", "B": a.B,
+                      "components": 2}}
+    print(json.dumps(res), flush=True)
+    return 0
+
+
 def main(argv=None):
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -295,6 +331,7 @@ def main(argv=None):
     ap.add_argument("--uneven-count", type=int, default=64)
     ap.add_argument("--interp", action="store_true", help="time off-grid predictions (krig_interp) instead")
     ap.add_argument("--nonstat", action="store_true", help="time weights from caller k_i (krig_set_kvec) instead")
+    ap.add_argument("--mixture", action="store_true", help="time a two-component nonstationary mixture instead")
     ap.add_argument("--interp-points", type=int, default=1_000_000)
     ap.add_argument("--interp-q", type=int, default=4)
     ap.add_argument("--calibrate-copy-mib", type=int, default=0,
@@ -329,6 +366,8 @@ def main(argv=None):
         return interp_mode(a, torch, krig, wl, dev)
     if a.nonstat:
         return nonstat_mode(a, torch, krig, wl, dev)
+    if a.mixture:
+        return mixture_mode(a, torch, krig, wl, dev)
     w = wl.grad_batch(B=a.B)
     B = a.B
 
