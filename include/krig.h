@@ -203,6 +203,21 @@ int krig_predict_adjoint(krig_plan p, int32_t B, const void *d_g, const double *
                          const void *d_saved, const void *d_lag, double *d_dy, void *d_dlag);
 
 /*
+ * Universal kriging (Section 3, eqs. findbeta, findc, predictionf): data with a linear
+ * trend in np covariates, 1 <= np <= 16.  d_z [B][n] FP64 data; d_Xs [np][n] FP64 the
+ * covariates at the sites (covariate k of site i at d_Xs[k*n + i]: the columns of the
+ * paper's X, one per row); d_Xg [np][m1][m2] FP64 the covariates at the grid nodes.
+ *   beta_b = (X^T M^{-1} X)^{-1} X^T M^{-1} z_b,  c_b = M^{-1}(z_b - X beta_b),
+ *   d_yhat[b] = X_grid beta_b + the rapid prediction of c_b   ([B][m1][m2] dt).
+ * d_beta [B][np] FP64 and d_coef [B][n] FP64 may be NULL (else receive beta and c).
+ * M^{-1} is the plan's FP64 solve; the np x np system is factored on the GPU, and when
+ * X^T M^{-1} X is not numerically positive definite (covariates not independent at the
+ * sites) beta, and with it the prediction, is NaN.  B <= 65519.  Asynchronous.
+ */
+int krig_predict_universal(krig_plan p, int32_t B, const double *d_z, int32_t np, const double *d_Xs,
+                           const double *d_Xg, void *d_yhat, double *d_beta, double *d_coef);
+
+/*
  * Off-grid predictions (the closing discussion of Section 6: predict on a fine mesh,
  * then interpolate locally with polynomials).  d_yhat [B][m1][m2] dt is a mesh
  * prediction (e.g. from krig_predict); d_pts [npts][2] FP64 holds (x, y) per point;

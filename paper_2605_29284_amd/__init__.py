@@ -30,7 +30,7 @@ STATUS = {0: "KRIG_OK", -1: "KRIG_EINVAL", -2: "KRIG_EDOMAIN", -3: "KRIG_ENOTSPD
 
 EXPORTS = ["krig_plan_create", "krig_plan_destroy", "krig_plan_info", "krig_set_stream", "krig_weights",
            "krig_set_weights", "krig_set_kvec", "krig_lag", "krig_solve", "krig_scatter", "krig_convolve", "krig_predict",
-           "krig_predict_adjoint", "krig_csim", "krig_interp", "krig_mixture", "krig_plan_tune", "krig_plan_autotune", "krig_predict_many", "krig_batch_create",
+           "krig_predict_adjoint", "krig_csim", "krig_interp", "krig_mixture", "krig_predict_universal", "krig_plan_tune", "krig_plan_autotune", "krig_predict_many", "krig_batch_create",
            "krig_batch_launch", "krig_batch_destroy", "krig_timing_enable", "krig_timing_read", "krig_strerror"]
 
 STAGES = ["ROWS_FWD", "COLS_CONV", "ROWS_INV", "ADJ_ROWS_FWD", "ADJ_COLS", "ADJ_ROWS_INV", "GATHER", "SOLVE",
@@ -83,6 +83,7 @@ def load_library(path: str = LIB_PATH) -> ctypes.CDLL:
         "krig_csim": [vp, i32, ctypes.c_uint64, dp, dp],
         "krig_interp": [vp, i32, dp, i32, dp, i32, dp],
         "krig_mixture": [ctypes.POINTER(vp), i32, i32, dp, dp, dp, dp, vp],
+        "krig_predict_universal": [vp, i32, dp, i32, dp, dp, dp, dp, dp],
         "krig_plan_tune": [vp, i32, i64],
         "krig_plan_autotune": [vp, i32, i32],
         "krig_predict_many": [ctypes.POINTER(vp), i32, ctypes.POINTER(i32), ctypes.POINTER(vp), ctypes.POINTER(vp), vp],
@@ -306,6 +307,25 @@ class Plan:
             cnt = ctypes.c_int64()
             _check(self.lib.krig_timing_read(self.h, i, ctypes.byref(ms), ctypes.byref(cnt)), "krig_timing_read")
             out[name] = (float(ms.value), int(cnt.value))
+        return out
+
+    def predict_universal(self, z, Xs, Xg, out=None, beta_out=None, coef_out=None):
+        """Universal kriging (krig_predict_universal): z [B][n] FP64, covariates Xs [np][n]
+        at the sites and Xg [np][m1][m2] at the nodes (FP64) -> [B][m1][m2] (plan dtype)."""
+        z = self._batch(z, (self.n,), "z", self.torch.float64)
+        B = z.shape[0]
+        npc = Xs.shape[0] if Xs.dim() == 2 else -1
+        self._t(Xs, self.torch.float64, (npc, self.n), "Xs")
+        self._t(Xg, self.torch.float64, (npc, self.m1, self.m2), "Xg")
+        out = self.empty(B, self.m1, self.m2) if out is None else self._t(out, self.tdtype, (B, self.m1, self.m2), "out")
+        if beta_out is not None:
+            self._t(beta_out, self.torch.float64, (B, npc), "beta_out")
+        if coef_out is not None:
+            self._t(coef_out, self.torch.float64, (B, self.n), "coef_out")
+        self._stream()
+        _check(self.lib.krig_predict_universal(self.h, B, z.data_ptr(), npc, Xs.data_ptr(), Xg.data_ptr(),
+                                               out.data_ptr(), _ptr(beta_out), _ptr(coef_out)),
+               "krig_predict_universal")
         return out
 
     def interp(self, yhat, pts, q: int = 4, out=None):

@@ -17,6 +17,7 @@
 #include "dense.h"
 #include "interp.h"
 #include "mixture.h"
+#include "universal.h"
 #include "fft_args.h"
 #include "fft_reg.h"
 #include "setup.h"
@@ -90,6 +91,11 @@ struct krig_plan_s {
   void* XC = nullptr;     // cx FP64 [H2][ldX]
   void* mix = nullptr;    // dt [B][m1][m2]  this plan's component of a mixture prediction
   int wsB_mix = 0;
+  // universal kriging
+  double* uk_vx = nullptr;    // [UK_MAX][n]  M^{-1} X, one covariate per row
+  double* uk_G = nullptr;     // [UK_MAX][UK_MAX + B]  X^T M^{-1} [X | z]
+  double* uk_beta = nullptr;  // [B][UK_MAX]
+  int wsB_uk = 0;
   // custom-lag filter
   double* filtC = nullptr;
   double* lagC64 = nullptr;
@@ -352,6 +358,22 @@ int ensure_ws_mix(krig_plan p, int B) {
   int r;
   if ((r = dalloc_bytes(p, &p->mix, p->tsz * (size_t)B * p->g.m1 * p->g.m2)) != KRIG_OK) return r;
   p->wsB_mix = B;
+  return KRIG_OK;
+}
+
+// universal-kriging workspaces for B fields
+int ensure_ws_uk(krig_plan p, int B) {
+  if (B <= p->wsB_uk) return KRIG_OK;
+  if (p->batch_refs > 0) return KRIG_EINVAL;
+  KRIG_TRY(hipStreamSynchronize(p->st));
+  dfree(p, p->uk_G);
+  dfree(p, p->uk_beta);
+  p->uk_G = p->uk_beta = nullptr;
+  int r;
+  if (!p->uk_vx && (r = dalloc(p, &p->uk_vx, (size_t)UK_MAX * p->n)) != KRIG_OK) return r;
+  if ((r = dalloc(p, &p->uk_G, (size_t)UK_MAX * (UK_MAX + B))) != KRIG_OK) return r;
+  if ((r = dalloc(p, &p->uk_beta, (size_t)B * UK_MAX)) != KRIG_OK) return r;
+  p->wsB_uk = B;
   return KRIG_OK;
 }
 
@@ -1090,6 +1112,28 @@ int krig_predict_adjoint(krig_plan p, int32_t B, const void* d_g, const double* 
     oc.NL = p->nl_rows64;
     KRIG_TRY((is32(p) ? set2(p).c2r_fold32 : set2(p).c2r_fold64)(oc, 1, p->st));
   }
+  return KRIG_OK;
+}
+
+int krig_predict_universal(krig_plan p, int32_t B, const double* d_z, int32_t np, const double* d_Xs,
+                           const double* d_Xg, void* d_yhat, double* d_beta, double* d_coef) {
+  if (!p || B < 1 || B > 65535 - UK_MAX || np < 1 || np > UK_MAX || !d_z || !d_Xs || !d_Xg || !d_yhat)
+    return KRIG_EINVAL;
+  int r;
+  if ((r = ensure_ws(p, std::max<int>(B, np))) != KRIG_OK) return r;
+  if ((r = ensure_ws_uk(p, B)) != KRIG_OK) return r;
+  const int n = p->n;
+  if ((r = do_solve(p, np, d_Xs, p->uk_vx)) != KRIG_OK) return r;  // M^{-1} X
+  if ((r = do_solve(p, B, d_z, p->alpha)) != KRIG_OK) return r;    // M^{-1} z
+  KRIG_TRY(uk_gram(d_Xs, p->uk_vx, p->alpha, n, np, B, p->uk_G, p->st));
+  KRIG_TRY(uk_solve(p->uk_G, np, B, p->uk_beta, p->st));           // eq. findbeta
+  KRIG_TRY(uk_resid(p->alpha, p->uk_vx, p->uk_beta, n, np, B, p->st));  // eq. findc
+  if ((r = krig_convolve(p, B, p->alpha, nullptr, d_yhat, nullptr)) != KRIG_OK) return r;
+  KRIG_TRY(uk_trend(d_yhat, is32(p), d_Xg, p->uk_beta, (int64_t)p->g.m1 * p->g.m2, np, B, p->st));  // predictionf
+  if (d_beta)
+    KRIG_TRY(hipMemcpyAsync(d_beta, p->uk_beta, sizeof(double) * B * np, hipMemcpyDeviceToDevice, p->st));
+  if (d_coef)
+    KRIG_TRY(hipMemcpyAsync(d_coef, p->alpha, sizeof(double) * B * n, hipMemcpyDeviceToDevice, p->st));
   return KRIG_OK;
 }
 
