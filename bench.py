@@ -315,6 +315,44 @@ def mixture_mode(a, torch, krig, wl, dev):
     return 0
 
 
+def universal_mode(a, torch, krig, wl, dev):
+    """Universal kriging (krig_predict_universal) on the paper-sized field: covariates
+    (1, x, y, xy), B fields of data with a trend.  Prints one JSON line."""
+    w = wl.grad_batch(B=a.B)
+    p = krig.plan_for(w, "f32")
+    design = lambda x, y: np.stack([np.ones_like(x), x, y, x * y])
+    X, Y = np.meshgrid(w.x0 + np.arange(w.m1) * w.dx, w.y0 + np.arange(w.m2) * w.dy, indexing="ij")
+    Xs = torch.as_tensor(design(w.sites[:, 0], w.sites[:, 1]), dtype=torch.float64, device=dev)
+    Xg = torch.as_tensor(design(X, Y), dtype=torch.float64, device=dev)
+    z = torch.as_tensor(w.y + np.array([1.0, 0.5, -0.5, 0.2]) @ design(w.sites[:, 0], w.sites[:, 1]),
+                        dtype=torch.float64, device=dev)
+    out = torch.empty(a.B, w.m1, w.m2, dtype=torch.float32, device=dev)
+
+    def timed(fn):
+        for _ in range(a.warmup):
+            fn()
+        s, e = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        torch.cuda.synchronize()
+        s.record()
+        for _ in range(a.steps):
+            fn()
+        e.record()
+        torch.cuda.synchronize()
+        return s.elapsed_time(e) / a.steps
+
+    ms = timed(lambda: p.predict_universal(z, Xs, Xg, out=out))
+    ms_plain = timed(lambda: p.predict(z, out=out))
+    res = {"metric": "grid predictions/s, universal kriging (GLS trend in 4 covariates)",
+           "value": a.B * w.m1 * w.m2 / (ms * 1e-3), "unit": "grid predictions/s", "n_gpus": 1, "steps": a.steps,
+           "warmup": a.warmup, "ms_per_step": ms, "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
+           "dtype": "f64", "io_dtype": "f32", "data": "synthetic",
+           "config": {"workload": "paper-sized field (n=1368, 350x350, L=3), covariates (1, x, y, xy), B fields",
+                      "B": a.B, "covariates": 4},
+           "plain_predict_ms": ms_plain}
+    print(json.dumps(res), flush=True)
+    return 0
+
+
 def main(argv=None):
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -332,6 +370,7 @@ def main(argv=None):
     ap.add_argument("--interp", action="store_true", help="time off-grid predictions (krig_interp) instead")
     ap.add_argument("--nonstat", action="store_true", help="time weights from caller k_i (krig_set_kvec) instead")
     ap.add_argument("--mixture", action="store_true", help="time a two-component nonstationary mixture instead")
+    ap.add_argument("--universal", action="store_true", help="time universal kriging with a GLS trend instead")
     ap.add_argument("--interp-points", type=int, default=1_000_000)
     ap.add_argument("--interp-q", type=int, default=4)
     ap.add_argument("--calibrate-copy-mib", type=int, default=0,
@@ -368,6 +407,8 @@ def main(argv=None):
         return nonstat_mode(a, torch, krig, wl, dev)
     if a.mixture:
         return mixture_mode(a, torch, krig, wl, dev)
+    if a.universal:
+        return universal_mode(a, torch, krig, wl, dev)
     w = wl.grad_batch(B=a.B)
     B = a.B
 
