@@ -353,6 +353,25 @@ def universal_mode(a, torch, krig, wl, dev):
     return 0
 
 
+def device_copy_gbs(torch, dev, mib=1024, reps=10):
+    """Bandwidth of a plain device-to-device copy of `mib` MiB: (read + write bytes) / time."""
+    n = mib << 20
+    src = torch.ones(n, dtype=torch.uint8, device=dev)
+    dst = torch.empty_like(src)
+    for _ in range(2):
+        dst.copy_(src)
+    s, e = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    torch.cuda.synchronize()
+    s.record()
+    for _ in range(reps):
+        dst.copy_(src)
+    e.record()
+    torch.cuda.synchronize()
+    gbs = 2.0 * n * reps / (s.elapsed_time(e) * 1e-3) / 1e9
+    del src, dst
+    return round(gbs, 1)
+
+
 def main(argv=None):
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -492,6 +511,7 @@ def main(argv=None):
 
     r32 = res["f32"]
     p32 = r32["plan"]
+    copy_gbs = device_copy_gbs(torch, dev)
     npred = B * w.m1 * w.m2
     value = npred / (r32["ms"] * 1e-3)
     # dominant single-kernel stage and its roofline
@@ -532,6 +552,9 @@ def main(argv=None):
         "autotune_ms": r32["tune_ms"],
         "launch_shapes": r32["tuned"],
         "stage_avg_ms": {k: round(v, 5) for k, v in avg.items()},
+        "stage_calls_per_step": {k: v[1] / a.steps for k, v in r32["stages"].items() if v[1] > 0},
+        # a plain device-to-device copy on the same GPU (reads + writes), beside the HBM peak
+        "device_copy_gbs": copy_gbs,
         "stage_gbs": {k: round(sb[k] / (avg[k] * 1e-3) / 1e9, 1) for k in sb if k in avg},
     }
     if "f64" in res:

@@ -392,12 +392,12 @@ __global__ void __launch_bounds__(256) k_tri_sum(const double* __restrict__ part
   const int f = 16 * z + (lane >> 4) + 4 * j, i = 16 * t + (lane & 15);
   const int ns = tri_splits(n, t, UPPER);
   double s = 0.0;
-  for (int q0 = 0; q0 < ns; q0 += 8) {  // eight loads in flight, summed in split order
-    double v[8];
+  for (int q0 = 0; q0 < ns; q0 += 16) {  // up to 16 loads in flight (one round for n <= 2048), summed in split order
+    double v[16];
 #pragma unroll
-    for (int u = 0; u < 8; ++u) v[u] = q0 + u < ns ? part[((int64_t)(t * qmax + q0 + u) * nfz + z) * 256 + e] : 0.0;
+    for (int u = 0; u < 16; ++u) v[u] = q0 + u < ns ? part[((int64_t)(t * qmax + q0 + u) * nfz + z) * 256 + e] : 0.0;
 #pragma unroll
-    for (int u = 0; u < 8; ++u)
+    for (int u = 0; u < 16; ++u)
       if (q0 + u < ns) s += v[u];
   }
   if (f < B && i < n) out[(int64_t)f * out_fs + i] = s;
