@@ -105,7 +105,21 @@ def cpu_baseline(w, nfields: int, reps: int = 6):
         dt = time.perf_counter() - t0
     return {"value": nfields * reps * w.m1 * w.m2 / dt, "unit": "grid predictions/s", "cores": 1, "kind": "oracle",
             "sample": f"{nfields} of the {w.B} fields x {reps} passes, forward + adjoint (y -> y_hat, g -> dy, d lag) with the "
-                      f"oracle's FP64 FFT variants, one thread, {dt:.1f} s"}
+                      f"oracle's FP64 FFT variants, one thread, {dt:.1f} s", "host": host_cpu()}
+
+
+def host_cpu():
+    """Model name and logical CPU count of the host that timed the oracle."""
+    model = None
+    try:
+        with open("/proc/cpuinfo") as f:
+            for line in f:
+                if line.startswith("model name"):
+                    model = line.split(":", 1)[1].strip()
+                    break
+    except OSError:
+        pass
+    return {"cpu_model": model, "logical_cpus": os.cpu_count()}
 
 
 def uneven(a, torch, krig, wl, dev):
@@ -233,6 +247,7 @@ def interp_mode(a, torch, krig, wl, dev):
                 interp_points(g, Yh[b], pts_h[:npc], q)
             dt = time.perf_counter() - t0
         res["cpu_baseline"] = {"value": nf * npc / dt, "unit": "off-grid predictions/s", "cores": 1, "kind": "oracle",
+                               "host": host_cpu(),
                                "sample": f"{nf} fields x {npc} points, one thread, {dt:.1f} s"}
     print(json.dumps(res), flush=True)
     return 0

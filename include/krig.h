@@ -27,6 +27,9 @@
  *  - "dt" arrays (images, lag, predictions, gradients) have the plan's dtype
  *    (float for KRIG_F32, double for KRIG_F64).  Data y, coefficients alpha,
  *    gradients w.r.t. y and the weights are always FP64.
+ *  - Batch counts (B fields, R realisations, C components) must be >= 1; an empty
+ *    batch returns KRIG_EINVAL without enqueueing anything.  Point counts of
+ *    krig_interp may be 0.
  *  - All calls after krig_plan_create are asynchronous on the plan's stream
  *    (krig_set_stream), return a krig_status, never throw, and validate their
  *    arguments on the host before enqueueing anything.  A plan must not be used
@@ -136,7 +139,6 @@ int krig_weights(krig_plan p, int32_t *d_anchor, double *d_W);
  */
 int krig_set_weights(krig_plan p, const int32_t *d_anchor, const double *d_W);
 
-/* Export the lag quadrant (m1+L) x (m2+L) in dt (Step 2's filter). */
 /*
  * Nonstationary covariance vectors (Section 6, discussion): Step 3's k_i taken from a
  * caller covariance C while K_N and the lag image stay the plan's stationary ones.
@@ -151,6 +153,7 @@ int krig_set_weights(krig_plan p, const int32_t *d_anchor, const double *d_W);
  */
 int krig_set_kvec(krig_plan p, const double *d_kvec);
 
+/* Export the lag quadrant (m1+L) x (m2+L) in dt (Step 2's filter). */
 int krig_lag(krig_plan p, void *d_lag);
 
 /* Kriging coefficients alpha = (K + tau^2 I)^{-1} y for B fields (eq. findc), FP64:

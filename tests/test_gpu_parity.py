@@ -465,6 +465,13 @@ def test_error_paths(krig):
     y = host(p.predict(dev(np.array([[1.0, -2.0, 0.5, 3.0]]))))[0]
     ref = rp.predict_direct(ek.coef(np.array([1.0, -2.0, 0.5, 3.0]))).reshape(10, 10)
     assert relmax(y, ref) < 1e-12
+    # an empty batch is rejected before anything is enqueued; the plan stays usable
+    empty = dev(np.zeros((0, 4)))
+    for call in (p.solve, p.scatter, p.convolve, p.predict):
+        with pytest.raises(krig.KrigError) as e:
+            call(empty)
+        assert e.value.status == -1
+    assert np.array_equal(host(p.predict(dev(np.array([[1.0, -2.0, 0.5, 3.0]]))))[0], y)
 
 
 # ------------------------------------------------------------------------------ conditional simulation
