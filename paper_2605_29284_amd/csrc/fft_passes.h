@@ -484,7 +484,10 @@ __device__ __forceinline__ void col_fwd(const cx<TS>* src, int in_off, int in_cn
 enum { COL_CONV = 0, COL_CONV_DLAG = 1, COL_FWD_REAL = 2, COL_INV_SUM = 3, COL_CE = 4 };
 
 // The lag-gradient column pass (two forward transforms and an inverse per line) of the
-// same forms holds just over 168 VGPRs: capped at three waves per SIMD it needs no scratch.
+// same forms needs just over 168 VGPRs.  Capped at three waves per SIMD it spills a few
+// dozen bytes per lane and still runs faster than uncapped at two waves; a four-wave cap
+// (over 200 bytes of scratch) runs at half speed.  The plain convolution pass keeps the
+// default (four waves): a five-wave cap made it spill and run slower.
 template <int R1, int R2, int R3, int MODE> struct ColCap {
   static constexpr int waves = (MODE == COL_CONV_DLAG && RowCap<R1, R2, R3>::waves > 1) ? 3 : 1;
 };
