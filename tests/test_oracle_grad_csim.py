@@ -194,6 +194,28 @@ def test_ce_fields_empirical_variance():
     assert abs(c1 - k.of_dist(g.dx) / 2.0) < 0.06
 
 
+@pytest.mark.parametrize("nu, rho, Fs1, Fs2", [(1.5, 0.15, 48, 48), (0.5, 0.2, 40, 48)])
+def test_ce_fields_semivariogram(nu, rho, Fs1, Fs2):
+    # The unconditional field is stationary with covariance k, so its semivariogram is
+    # gamma(h) = (E (u(x + h) - u(x))^2) / 2 = sigma2 - k(h) along each axis.  The grid
+    # is anisotropic (dx != dy): a swapped axis or lag scale misses by 12-68 %.
+    g = Grid(12, 16, 0.0, 0.0, 1 / 11, 1 / 15, 2)
+    k = Matern(1.5, rho, nu)
+    lam, _, _ = csim.ce_eigs(g, k, Fs1, Fs2)
+    us = []
+    for p in range(400):
+        a, b = csim.ce_pair(lam, 7, p, g.P1, g.P2)
+        us += [a, b]
+    us = np.array(us)
+    for h in range(1, 5):
+        gx = 0.5 * np.mean((us[:, h:, :] - us[:, :-h, :]) ** 2)
+        gy = 0.5 * np.mean((us[:, :, h:] - us[:, :, :-h]) ** 2)
+        # 800 fields: relative standard error <= sqrt(2 / 800) = 5 % even if all pairs
+        # inside a field were fully correlated; 8 % is 1.6 of that bound
+        assert abs(gx / (1.5 - k.of_dist(h * g.dx)) - 1) < 0.08, (h, gx)
+        assert abs(gy / (1.5 - k.of_dist(h * g.dy)) - 1) < 0.08, (h, gy)
+
+
 def test_conditional_simulation_reproduces_kriging_se():
     g = grid_unit(16, 16, 2)
     k = Matern(1.0, 0.2, 1.5, 0.01)
