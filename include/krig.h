@@ -145,8 +145,9 @@ int krig_set_weights(krig_plan p, const int32_t *d_anchor, const double *d_W);
  * d_kvec [n][M] FP64: kvec[i][m] = C(g_m, s_i) for the neighbourhood nodes g_m of site i
  * (anchor from krig_weights, offsets (ox, oy) in {-L+1..L}^2, ox-major, node
  * (x0 + (i0 + ox) dx, y0 + (j0 + oy) dy)).  Replaces the weights by
- * W_i = K_N^{-1} k_i (Step 4, the products of plan creation) and rebuilds the scatter
- * structure; later krig_scatter / krig_convolve / krig_predict_adjoint use them.  The
+ * W_i = K_N^{-1} k_i (Step 4, the products of plan creation) and rewrites the scatter
+ * structure's weights (its layout depends only on the anchors, which stay the same);
+ * later krig_scatter / krig_convolve / krig_predict_adjoint use them.  The
  * coefficients of the nonstationary model are the caller's (krig_convolve takes them);
  * krig_solve / krig_predict keep solving with the plan's stationary K + tau^2 I.
  * Asynchronous on the plan's stream; d_kvec is read before the call's work completes.

@@ -923,7 +923,8 @@ int krig_set_kvec(krig_plan p, const double* d_kvec) {
   gb.A = p->Wt; gb.transB = 0; gb.C = p->W;
   KRIG_TRY(gemm_f64(gb, p->st));
   KRIG_TRY(transpose_w(p->W, n, M, p->Wt, p->st));
-  KRIG_TRY(build_csr(p->g, p->anchor, p->W, n, p->cw, p->node_ptr, p->ent_site, p->ent_w, p->st));
+  // the anchors are unchanged, so the scatter structure is too: only its weights are rewritten
+  KRIG_TRY(refill_csr_weights(p->g, p->anchor, p->W, p->node_ptr, p->ent_site, p->ent_w, p->st));
   return KRIG_OK;
 }
 

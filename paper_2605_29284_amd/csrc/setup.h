@@ -42,6 +42,11 @@ struct CsrWork {
 };
 hipError_t build_csr(const GridDev& g, const int32_t* anchor, const double* W, int n, const CsrWork& w,
                      int32_t* node_ptr, int32_t* ent_site, double* ent_w, hipStream_t st);
+// Rewrite the entry weights of an existing scatter structure from new weights W [n][M]
+// whose anchors are unchanged (the node pointers and entry sites stay as they are):
+// ent_w[e] = W[site][m] with m the offset of the entry's node from the site's anchor.
+hipError_t refill_csr_weights(const GridDev& g, const int32_t* anchor, const double* W,
+                              const int32_t* node_ptr, const int32_t* ent_site, double* ent_w, hipStream_t st);
 
 // c* image [B][P1][P2] (storage precision) = A^T alpha by segment sums (FP64 accumulation)
 hipError_t scatter_image(const GridDev& g, const int32_t* node_ptr, const int32_t* ent_site, const double* ent_w,

@@ -322,6 +322,28 @@ hipError_t build_csr(const GridDev& g, const int32_t* anchor, const double* W, i
   return hipGetLastError();
 }
 
+// one thread per padded node: its entries keep their sites and order, only the weights change
+__global__ void k_node_refill(GridDev g, const int32_t* __restrict__ anchor, const double* __restrict__ W,
+                              const int32_t* __restrict__ node_ptr, const int32_t* __restrict__ ent_site,
+                              double* __restrict__ ent_w) {
+  const int q = blockIdx.x * blockDim.x + threadIdx.x;
+  if (q >= g.P1 * g.P2) return;
+  const int p = q / g.P2, r = q % g.P2;
+  const int L2 = 2 * g.L;
+  for (int e = node_ptr[q]; e < node_ptr[q + 1]; ++e) {
+    const int i = ent_site[e];
+    const int ox = p - g.L - anchor[2 * i], oy = r - g.L - anchor[2 * i + 1];
+    ent_w[e] = W[(int64_t)i * g.M + (ox + g.L - 1) * L2 + (oy + g.L - 1)];
+  }
+}
+
+hipError_t refill_csr_weights(const GridDev& g, const int32_t* anchor, const double* W, const int32_t* node_ptr,
+                              const int32_t* ent_site, double* ent_w, hipStream_t st) {
+  const int nnode = g.P1 * g.P2;
+  hipLaunchKernelGGL(k_node_refill, dim3(nblk(nnode)), dim3(256), 0, st, g, anchor, W, node_ptr, ent_site, ent_w);
+  return hipGetLastError();
+}
+
 // ------------------------------------------------------------------------------ scatter / gather
 template <typename TS>
 __global__ void k_scatter_image(int nnode, const int32_t* __restrict__ node_ptr,

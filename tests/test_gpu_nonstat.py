@@ -58,6 +58,29 @@ def test_set_kvec_small_field(krig, dtype):
         assert relmax(yh[b], ref) < (1e-12 if dtype == "f64" else 1e-6)
 
 
+@pytest.mark.parametrize("dtype", ["f64", "f32"])
+def test_set_kvec_refill_matches_a_rebuilt_structure(krig, dtype):
+    # set_kvec rewrites only the weights of the scatter structure; a plan given the same
+    # weights through set_weights rebuilds the structure from scratch: same layout, same
+    # order, so the scatter image and the predictions agree bit for bit
+    w = wl.paper_field()
+    g = Grid(w.m1, w.m2, w.x0, w.y0, w.dx, w.dy, w.L)
+    k = Matern(w.sigma2, w.rho, w.nu, w.tau2)
+    say("set_kvec refill vs rebuilt structure, paper field", dtype)
+    p = krig.plan_for(w, dtype)
+    p.set_kvec(dev(kvecs_cov(g, w.sites, scaled_cov(k, sd))))
+    anc, W = p.weights()
+    q = krig.plan_for(w, dtype)
+    q.set_weights(anc, W)
+    alpha = dev(np.random.default_rng(5).standard_normal((3, w.n)))
+    assert np.array_equal(host(p.scatter(alpha)), host(q.scatter(alpha)))
+    assert np.array_equal(host(p.convolve(alpha)), host(q.convolve(alpha)))
+    gup = torch.ones(3, w.m1, w.m2, dtype=p.tdtype, device="cuda:0")
+    dp, _ = p.adjoint(gup, alpha=alpha, want_dlag=False)
+    dq, _ = q.adjoint(gup, alpha=alpha, want_dlag=False)
+    assert np.array_equal(host(dp), host(dq))
+
+
 def test_set_kvec_stationary_reproduces_the_plan(krig):
     w = wl.small_field()
     g = Grid(w.m1, w.m2, w.x0, w.y0, w.dx, w.dy, w.L)
