@@ -268,6 +268,33 @@ def test_adjoint_grad_batch_full_size(krig):
     assert relmax(dlag, ref_dlag) < 1e-6
 
 
+def test_grad_batch_in_the_benchmark_configuration(krig):
+    # the benchmark's step at its full size and launch configuration: 16 fields, FP32 plan,
+    # autotuned shapes, loss sum(m * yhat^2); every output against the oracle (same weights)
+    w = wl.grad_batch(B=16)
+    g, k, rp, ek = oracle_of(w)
+    p = krig.plan_for(w, "f32")
+    p.set_weights(dev(np.stack([rp.i0, rp.j0], 1), torch.int32), dev(rp.W))
+    shapes = p.autotune(16, with_adjoint=True)
+    say("grad-batch B=16 autotuned", shapes)
+    y = dev(w.y)
+    alpha = torch.empty(16, w.n, dtype=torch.float64, device="cuda:0")
+    saved = p.new_saved(16)
+    yhat = p.predict(y, alpha_out=alpha, saved=saved)
+    gup = (2.0 * dev(w.extra["mask"], torch.float32) * yhat).contiguous()
+    dy, dlag = p.adjoint(gup, alpha=alpha, saved=saved)
+    yh, dy, dlag, gh = host(yhat), host(dy), host(dlag), host(gup)
+    lag = lag_quadrant(g, k)
+    al = ek.coef(w.y)
+    cst = [rp.cstar(al[b]) for b in range(16)]
+    for b in range(16):
+        assert relmax(yh[b], rapid_fft(g, lag, cst[b])) < 1e-6, b
+    ref_dy = np.stack([ek.coef(grad_coef(rp.A, corr_image_fft(g, lag, gh[b]))) for b in range(16)])
+    ref_dlag = sum(dlag_fft(g, gh[b], cst[b]) for b in range(16))
+    assert relmax(dy, ref_dy) < 1e-8
+    assert relmax(dlag, ref_dlag) < 1e-6
+
+
 @pytest.mark.parametrize("dtype", ["f32", "f64"])
 def test_adjoint_repeatable_with_stage_timing(krig, dtype):
     """Stage timing only brackets the launches with events: dy and dlag must agree bit
