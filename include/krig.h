@@ -207,6 +207,25 @@ int krig_predict_adjoint(krig_plan p, int32_t B, const void *d_g, const double *
                          const void *d_saved, const void *d_lag, double *d_dy, void *d_dlag);
 
 /*
+ * Exact kriging prediction from coefficients (eq. predictionh): the dense cross-covariance
+ * product that the rapid method approximates, O(N n) covariance evaluations,
+ *   d_yhat[b][a][c] = sum_{i < n} k(|node(a, c) - s_i|) alpha[b][i],
+ * with the plan's sites and Matern covariance (no nugget: k is the covariance of the
+ * field g).  d_alpha [B][n] FP64 (e.g. from krig_solve), d_yhat [B][m1][m2] dt.  Each
+ * value is summed in FP64 over the sites in index order and rounded once (bitwise
+ * repeatable).  A reference for the approximation error and its cost; B <= 65535.
+ * Asynchronous on the plan's stream.
+ */
+int krig_predict_exact(krig_plan p, int32_t B, const double *d_alpha, void *d_yhat);
+
+/*
+ * The same exact prediction at arbitrary points: d_pts [npts][2] FP64 (x, y), anywhere
+ * in the plane; d_out [B][npts] FP64.  npts = 0 is a no-op.  Asynchronous.
+ */
+int krig_exact_at(krig_plan p, int32_t B, const double *d_alpha, int32_t npts, const double *d_pts,
+                  double *d_out);
+
+/*
  * Universal kriging (Section 3, eqs. findbeta, findc, predictionf): data with a linear
  * trend in np covariates, 1 <= np <= 16.  d_z [B][n] FP64 data; d_Xs [np][n] FP64 the
  * covariates at the sites (covariate k of site i at d_Xs[k*n + i]: the columns of the

@@ -30,7 +30,7 @@ STATUS = {0: "KRIG_OK", -1: "KRIG_EINVAL", -2: "KRIG_EDOMAIN", -3: "KRIG_ENOTSPD
 
 EXPORTS = ["krig_plan_create", "krig_plan_destroy", "krig_plan_info", "krig_set_stream", "krig_weights",
            "krig_set_weights", "krig_set_kvec", "krig_lag", "krig_solve", "krig_scatter", "krig_convolve", "krig_predict",
-           "krig_predict_adjoint", "krig_csim", "krig_interp", "krig_mixture", "krig_predict_universal", "krig_plan_tune", "krig_plan_autotune", "krig_predict_many", "krig_batch_create",
+           "krig_predict_adjoint", "krig_csim", "krig_interp", "krig_predict_exact", "krig_exact_at", "krig_mixture", "krig_predict_universal", "krig_plan_tune", "krig_plan_autotune", "krig_predict_many", "krig_batch_create",
            "krig_batch_launch", "krig_batch_destroy", "krig_timing_enable", "krig_timing_read", "krig_strerror"]
 
 STAGES = ["ROWS_FWD", "COLS_CONV", "ROWS_INV", "ADJ_ROWS_FWD", "ADJ_COLS", "ADJ_ROWS_INV", "GATHER", "SOLVE",
@@ -82,6 +82,8 @@ def load_library(path: str = LIB_PATH) -> ctypes.CDLL:
         "krig_predict_adjoint": [vp, i32, dp, dp, dp, dp, dp, dp],
         "krig_csim": [vp, i32, ctypes.c_uint64, dp, dp],
         "krig_interp": [vp, i32, dp, i32, dp, i32, dp],
+        "krig_predict_exact": [vp, i32, dp, dp],
+        "krig_exact_at": [vp, i32, dp, i32, dp, dp],
         "krig_mixture": [ctypes.POINTER(vp), i32, i32, dp, dp, dp, dp, vp],
         "krig_predict_universal": [vp, i32, dp, i32, dp, dp, dp, dp, dp],
         "krig_plan_tune": [vp, i32, i64],
@@ -341,6 +343,31 @@ class Plan:
         self._stream()
         _check(self.lib.krig_interp(self.h, B, yhat.data_ptr(), npts, pts.data_ptr(), int(q), out.data_ptr()),
                "krig_interp")
+        return out
+
+    def exact(self, alpha, out=None):
+        """Exact kriging prediction on the grid (krig_predict_exact): coefficients alpha
+        [B][n] FP64 -> [B][m1][m2] (plan dtype), the dense sum over the sites."""
+        alpha = self._batch(alpha, (self.n,), "alpha", self.torch.float64)
+        B = alpha.shape[0]
+        out = self.empty(B, self.m1, self.m2) if out is None else self._t(out, self.tdtype, (B, self.m1, self.m2), "out")
+        self._stream()
+        _check(self.lib.krig_predict_exact(self.h, B, alpha.data_ptr(), out.data_ptr()), "krig_predict_exact")
+        return out
+
+    def exact_at(self, alpha, pts):
+        """Exact kriging prediction at points (krig_exact_at): alpha [B][n] FP64,
+        pts [npts][2] FP64 -> [B][npts] FP64."""
+        alpha = self._batch(alpha, (self.n,), "alpha", self.torch.float64)
+        B = alpha.shape[0]
+        if pts.dim() != 2 or pts.shape[1] != 2:
+            raise ValueError("pts: expected shape (npts, 2)")
+        pts = self._t(pts, self.torch.float64, tuple(pts.shape), "pts")
+        npts = pts.shape[0]
+        out = self.empty(B, npts, dtype=self.torch.float64)
+        self._stream()
+        _check(self.lib.krig_exact_at(self.h, B, alpha.data_ptr(), npts, pts.data_ptr(), out.data_ptr()),
+               "krig_exact_at")
         return out
 
     def csim(self, R: int, seed: int, y):

@@ -61,7 +61,7 @@ def build(jobs: int = 8, verbose: bool = False) -> str:
             with open(src, "w") as f:
                 f.write(body)
         units.append(src)
-    for name in ("dense.hip", "setup.hip", "interp.hip", "mixture.hip", "universal.hip", "plan.cpp", "fft_registry.cpp"):
+    for name in ("dense.hip", "setup.hip", "exact.hip", "interp.hip", "mixture.hip", "universal.hip", "plan.cpp", "fft_registry.cpp"):
         path = os.path.join(CSRC, name)
         if os.path.exists(path):
             units.append(path)

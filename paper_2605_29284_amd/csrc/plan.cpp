@@ -15,6 +15,7 @@
 
 #include "../../include/krig.h"
 #include "dense.h"
+#include "exact.h"
 #include "interp.h"
 #include "mixture.h"
 #include "universal.h"
@@ -1159,6 +1160,35 @@ int krig_interp(krig_plan p, int32_t B, const void* d_yhat, int32_t npts, const 
   a.out_fs = npts;
   KRIG_TRY(interp_points(a, B, q, is32(p), p->st));
   return KRIG_OK;
+}
+
+static int exact_call(krig_plan p, int32_t B, const double* d_alpha, int32_t npts, const double* d_pts, void* d_out,
+                      bool f32) {
+  ExactArgs a{};
+  a.sites = p->sites;
+  a.n = p->n;
+  a.alpha = d_alpha;
+  a.alpha_fs = p->n;
+  a.pts = d_pts;
+  a.npts = npts;
+  a.g = p->g;
+  a.mt = p->mt;
+  a.out = d_out;
+  a.out_fs = d_pts ? (int64_t)npts : (int64_t)p->g.m1 * p->g.m2;
+  const hipError_t e = exact_predict(a, B, f32, p->st);
+  return e == hipSuccess ? KRIG_OK : (e == hipErrorInvalidValue ? KRIG_EINVAL : KRIG_EHIP);
+}
+
+int krig_predict_exact(krig_plan p, int32_t B, const double* d_alpha, void* d_yhat) {
+  if (!p || B < 1 || B > 65535 || !d_alpha || !d_yhat) return KRIG_EINVAL;
+  return exact_call(p, B, d_alpha, 0, nullptr, d_yhat, is32(p));
+}
+
+int krig_exact_at(krig_plan p, int32_t B, const double* d_alpha, int32_t npts, const double* d_pts, double* d_out) {
+  if (!p || B < 1 || B > 65535 || npts < 0 || !d_alpha) return KRIG_EINVAL;
+  if (npts == 0) return KRIG_OK;
+  if (!d_pts || !d_out) return KRIG_EINVAL;
+  return exact_call(p, B, d_alpha, npts, d_pts, d_out, false);
 }
 
 int krig_plan_tune(krig_plan p, int32_t key, int64_t value) {

@@ -1,0 +1,107 @@
+"""GPU: exact kriging predictions (krig_predict_exact, krig_exact_at) against the oracle."""
+import sys
+
+import numpy as np
+import pytest
+
+import workloads as wl
+from oracle.exact import ExactKriging
+from oracle.matern import Matern
+from oracle.rapid import Grid
+
+pytestmark = pytest.mark.gpu
+
+torch = pytest.importorskip("torch")
+
+EPS = np.finfo(np.float64).eps
+
+
+def say(*a):
+    print("[gpu-case]", *a, flush=True)
+    sys.stdout.flush()
+
+
+def dev(x, dtype=torch.float64):
+    return torch.as_tensor(np.ascontiguousarray(x), dtype=dtype, device="cuda:0")
+
+
+def host(t):
+    torch.cuda.synchronize()
+    return t.detach().cpu().numpy().astype(np.float64)
+
+
+def check_bound(got, pts, sites, k, alpha, f32):
+    """|got - exact| per point within the rounding bound of two n-term FP64 sums (each term
+    carries a few eps from sqrt, the division and exp): 2 (n + 16) eps sum_i |k_ji alpha_i|,
+    plus one FP32 rounding of the result for FP32 output."""
+    K = k.cross(pts, sites)
+    ref = alpha @ K.T
+    S = np.abs(alpha) @ np.abs(K).T
+    bound = 2 * (sites.shape[0] + 16) * EPS * S + (2.0 ** -24 * np.abs(ref) if f32 else 0.0)
+    assert np.all(np.abs(got - ref) <= bound), float(np.max(np.abs(got - ref) / np.maximum(bound, 1e-300)))
+
+
+@pytest.mark.parametrize("dtype", ["f64", "f32"])
+def test_exact_grid_small_field(krig, dtype):
+    w = wl.small_field()
+    g = Grid(w.m1, w.m2, w.x0, w.y0, w.dx, w.dy, w.L)
+    k = Matern(w.sigma2, w.rho, w.nu, w.tau2)
+    say("exact on the grid, small field", dtype)
+    p = krig.plan_for(w, dtype)
+    alpha = np.random.default_rng(3).standard_normal((3, w.n))
+    got = host(p.exact(dev(alpha))).reshape(3, -1)
+    check_bound(got, g.nodes(), w.sites, k, alpha, dtype == "f32")
+    assert np.array_equal(host(p.exact(dev(alpha))).reshape(3, -1), got)  # bitwise repeatable
+
+
+def test_exact_at_points_inside_and_outside(krig):
+    w = wl.small_field()
+    k = Matern(w.sigma2, w.rho, w.nu, w.tau2)
+    say("exact at points")
+    p = krig.plan_for(w, "f32")
+    rng = np.random.default_rng(4)
+    pts = np.concatenate([rng.uniform(-0.3, 1.3, (700, 2)), w.sites[:5]])  # also outside, and on sites
+    alpha = rng.standard_normal((2, w.n))
+    got = host(p.exact_at(dev(alpha), dev(pts)))
+    check_bound(got, pts, w.sites, k, alpha, False)
+    assert host(p.exact_at(dev(alpha), dev(np.zeros((0, 2))))).shape == (2, 0)
+
+
+def test_exact_paper_field_sampled(krig):
+    # the paper-sized field with 16 fields on the full grid; sampled nodes against the oracle
+    w = wl.grad_batch(B=16)
+    g = Grid(w.m1, w.m2, w.x0, w.y0, w.dx, w.dy, w.L)
+    k = Matern(w.sigma2, w.rho, w.nu, w.tau2)
+    say("exact on the paper field, B=16 f32")
+    p = krig.plan_for(w, "f32")
+    alpha = ExactKriging(w.sites, k).coef(w.y)
+    got = host(p.exact(dev(alpha))).reshape(16, -1)
+    idx = np.concatenate([np.random.default_rng(6).choice(g.m1 * g.m2, 1500, replace=False),
+                          [0, g.m2 - 1, (g.m1 - 1) * g.m2, g.m1 * g.m2 - 1]])
+    check_bound(got[:, idx], g.nodes()[idx], w.sites, k, alpha, True)
+
+
+def test_rapid_equals_exact_when_sites_are_nodes(krig):
+    # every site on a grid node: each weight vector is a unit vector, so the rapid
+    # predictor is exact kriging (the closed special case of the method)
+    m1, m2, L = 40, 36, 2
+    dx, dy = 1.0 / (m1 - 1), 1.0 / (m2 - 1)
+    rng = np.random.default_rng(7)
+    q = rng.choice(m1 * m2, 60, replace=False)
+    sites = np.stack([(q // m2) * dx, (q % m2) * dy], 1)
+    say("rapid = exact with sites on nodes")
+    p = krig.Plan(m1, m2, 0.0, 0.0, dx, dy, L, 1.0, 0.2, 1.5, 0.01, sites, "f64")
+    alpha = dev(rng.standard_normal((2, 60)))
+    rapid, exact = host(p.convolve(alpha)), host(p.exact(alpha))
+    for b in range(2):
+        assert np.abs(rapid[b] - exact[b]).max() <= 1e-12 * np.abs(exact[b]).max()
+
+
+def test_exact_argument_errors(krig):
+    w = wl.small_field()
+    p = krig.plan_for(w, "f64")
+    with pytest.raises(krig.KrigError) as e:
+        p.exact(dev(np.zeros((0, w.n))))
+    assert e.value.status == -1
+    with pytest.raises(ValueError):
+        p.exact_at(dev(np.zeros((1, w.n))), dev(np.zeros((3, 3))))
