@@ -368,6 +368,87 @@ def universal_mode(a, torch, krig, wl, dev):
     return 0
 
 
+def exact_mode(a, torch, krig, wl, dev):
+    """The rapid predictor against exact kriging (the dense O(N n) sum, krig_predict_exact)
+    on the paper-sized field with B fields, both on the GPU from the same coefficients:
+    times, speedup and the approximation error.  Prints one JSON line."""
+    w = wl.grad_batch(B=a.B)
+    p = krig.plan_for(w, "f32")
+    y = torch.as_tensor(w.y, dtype=torch.float64, device=dev)
+    alpha = p.solve(y)
+    out = torch.empty(a.B, w.m1, w.m2, dtype=torch.float32, device=dev)
+
+    def timed(fn, steps):
+        for _ in range(min(a.warmup, 3)):
+            fn()
+        s, e = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        torch.cuda.synchronize()
+        s.record()
+        for _ in range(steps):
+            fn()
+        e.record()
+        torch.cuda.synchronize()
+        return s.elapsed_time(e) / steps
+
+    rapid_ms = timed(lambda: p.convolve(alpha, out=out), a.steps)
+    rapid_full_ms = timed(lambda: p.predict(y, out=out), a.steps)
+    exact_ms = timed(lambda: p.exact(alpha, out=out), max(3, a.steps // 4))
+    solve_ms = timed(lambda: p.solve(y), a.steps)
+    rapid = p.convolve(alpha).double()
+    exact = p.exact(alpha).double()
+    torch.cuda.synchronize()
+    diff = (rapid - exact).abs()
+    scale = exact.abs().amax(dim=(1, 2))
+    npred = a.B * w.m1 * w.m2
+    res = {"metric": "grid predictions/s, rapid predictor vs exact kriging on the same GPU",
+           "value": npred / (rapid_ms * 1e-3), "unit": "grid predictions/s", "n_gpus": 1, "steps": a.steps,
+           "warmup": a.warmup, "ms_per_step": rapid_ms, "higher_is_better": True, "scaling": "weak",
+           "vs_baseline": None, "dtype": "f64", "io_dtype": "f32", "data": "synthetic",
+           "config": {"workload": "paper-sized field (n=1368 sites, 350x350, L=3, Matern nu=2.5 range 0.3), "
+                                  "B fields; rapid: scatter + FFT convolution, exact: sum over all sites",
+                      "B": a.B, "n": w.n, "grid": [w.m1, w.m2]},
+           "exact_ms": exact_ms, "exact_value": npred / (exact_ms * 1e-3),
+           "exact_pair_evals_per_s": w.m1 * w.m2 * w.n / (exact_ms * 1e-3),
+           "speedup_rapid_over_exact": exact_ms / rapid_ms,
+           "with_solve": {"solve_ms": solve_ms, "rapid_ms": rapid_full_ms, "exact_ms": solve_ms + exact_ms,
+                          "speedup": (solve_ms + exact_ms) / rapid_full_ms},
+           "approximation_error": {"max_abs_rel_to_max": float((diff.amax(dim=(1, 2)) / scale).max()),
+                                   "mean_abs": float(diff.mean()), "max_abs": float(diff.max())}}
+    if not a.no_cpu_baseline:
+        res["cpu_baseline"] = exact_cpu_baseline(w)
+    print(json.dumps(res), flush=True)
+    return 0
+
+
+def exact_cpu_baseline(w):
+    """The oracle's rapid (FFT form) and exact predictions of one field on one host core."""
+    from threadpoolctl import threadpool_limits
+
+    from oracle.exact import ExactKriging
+    from oracle.matern import Matern
+    from oracle.rapid import Grid, RapidPredictor, lag_quadrant, rapid_fft
+    g = Grid(w.m1, w.m2, w.x0, w.y0, w.dx, w.dy, w.L)
+    k = Matern(w.sigma2, w.rho, w.nu, w.tau2)
+    with threadpool_limits(limits=1):
+        rp = RapidPredictor(g, k, w.sites)
+        ek = ExactKriging(w.sites, k)
+        lag = lag_quadrant(g, k)
+        c = ek.coef(w.y[0])
+        t0 = time.perf_counter()
+        reps = 3
+        for _ in range(reps):
+            rapid_fft(g, lag, rp.cstar(c))
+        t_rapid = (time.perf_counter() - t0) / reps
+        t0 = time.perf_counter()
+        ek.predict_at(g.nodes(), c)
+        t_exact = time.perf_counter() - t0
+    return {"value": w.m1 * w.m2 / t_rapid, "unit": "grid predictions/s", "cores": 1, "kind": "oracle",
+            "sample": f"one field: the oracle's rapid prediction (FFT form, {reps} runs) and its exact prediction "
+                      f"(dense sum over the {w.n} sites, {t_exact:.1f} s)",
+            "exact_value": w.m1 * w.m2 / t_exact, "speedup_rapid_over_exact": t_exact / t_rapid,
+            "host": host_cpu()}
+
+
 def device_copy_gbs(torch, dev, mib=1024, reps=10):
     """Bandwidth of a plain device-to-device copy of `mib` MiB: (read + write bytes) / time."""
     n = mib << 20
@@ -405,6 +486,7 @@ def main(argv=None):
     ap.add_argument("--nonstat", action="store_true", help="time weights from caller k_i (krig_set_kvec) instead")
     ap.add_argument("--mixture", action="store_true", help="time a two-component nonstationary mixture instead")
     ap.add_argument("--universal", action="store_true", help="time universal kriging with a GLS trend instead")
+    ap.add_argument("--exact", action="store_true", help="time the rapid predictor against exact kriging instead")
     ap.add_argument("--interp-points", type=int, default=1_000_000)
     ap.add_argument("--interp-q", type=int, default=4)
     ap.add_argument("--calibrate-copy-mib", type=int, default=0,
@@ -443,6 +525,8 @@ def main(argv=None):
         return mixture_mode(a, torch, krig, wl, dev)
     if a.universal:
         return universal_mode(a, torch, krig, wl, dev)
+    if a.exact:
+        return exact_mode(a, torch, krig, wl, dev)
     w = wl.grad_batch(B=a.B)
     B = a.B
 
