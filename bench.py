@@ -449,6 +449,109 @@ def exact_cpu_baseline(w):
             "host": host_cpu()}
 
 
+# phi(r) = 0.7 for the closed-form smoothness levels: the factorial study fixes the
+# distance at which the correlation falls to 0.7, so range = that distance / R07[nu]
+R07 = {0.5: 0.3566749439387324, 1.5: 1.0973492107034915}
+
+
+def table_a2_model(coef, nu, L, m, tau2):
+    """Fitted log10 mean absolute error of Appendix A, Table A2 for one factor combination."""
+    t = coef["(Intercept)"]
+    if nu == 1.5:
+        t += coef["smoothness1.5"] + (coef["smoothness1.5:NN4"] if L == 4 else 0.0)
+    if L == 4:
+        t += coef["NN4"]
+    if m != 100:
+        t += coef[f"nGrid{m}"]
+    if tau2 != 0.01:
+        t += coef[f"nugget{tau2}"]
+    return t
+
+
+def accuracy_mode(a, torch, krig, wl, dev):
+    """The paper's factorial accuracy study (Section 3, Appendix A) at the levels the GPU path
+    supports, as a batch of problems on the GPU: for every combination of n, range, smoothness,
+    nugget, L and grid, seeded uniform site sets and data, the rapid prediction against exact
+    kriging (krig_exact_at) at five nodes from the centre to the corner.  The log10 mean
+    absolute error per case is compared with the fitted model of Table A2.  One JSON line."""
+    coef = {}
+    with open(os.path.join(ROOT, "tests", "golden", "tableA2_coef.txt")) as f:
+        for line in f:
+            if line.strip() and not line.startswith("#"):
+                k_, v_ = line.split()
+                coef[k_] = float(v_)
+    levels = {"n": (200, 500, 1500), "d07": (0.2, 0.4, 0.8), "nu": (0.5, 1.5), "tau2": (0.01, 0.1, 0.5),
+              "L": (2, 4), "m": (100, 350, 500)}
+    rng = np.random.default_rng(27)
+    cases = []
+    t0 = time.perf_counter()
+    for m in levels["m"]:
+        h = 1.0 / (m - 1)
+        ab = [(m // 2, m // 2), (m // 4, m // 4), (0, 0), (m // 2, 0), (m - 1, m // 2)]
+        idx = torch.as_tensor([i * m + j for i, j in ab], device=dev)
+        pts = torch.as_tensor([[i * h, j * h] for i, j in ab], dtype=torch.float64, device=dev)
+        for L in levels["L"]:
+            for nu in levels["nu"]:
+                for tau2 in levels["tau2"]:
+                    for d07 in levels["d07"]:
+                        for n in levels["n"]:
+                            rho = d07 / R07[nu]
+                            errs, failed = [], []
+                            for _ in range(a.accuracy_reps):
+                                sites = wl.sites_uniform(rng, n)
+                                y = wl.add_nugget(rng, wl.rff_draw(rng, sites, 1.0, rho, nu), tau2)
+                                try:
+                                    p = krig.Plan(m, m, 0.0, 0.0, h, h, L, 1.0, rho, nu, tau2, sites, "f64")
+                                except krig.KrigError as e:  # e.g. a non-positive pivot in K_N
+                                    failed.append(e.status)
+                                    continue
+                                al = p.solve(torch.as_tensor(y, dtype=torch.float64, device=dev))
+                                rapid = p.convolve(al).reshape(-1)[idx]
+                                exact = p.exact_at(al, pts)[0]
+                                errs.append((rapid - exact).abs().cpu().numpy())
+                                p.close()
+                            if not errs:
+                                cases.append({"n": n, "d07": d07, "nu": nu, "tau2": tau2, "L": L, "m": m,
+                                              "failed": failed})
+                                continue
+                            got = float(np.log10(np.mean(errs)))
+                            cases.append({"n": n, "d07": d07, "nu": nu, "tau2": tau2, "L": L, "m": m,
+                                          "log10_mean_abs_err": round(got, 3),
+                                          "table_a2": round(table_a2_model(coef, nu, L, m, tau2), 3)})
+    secs = time.perf_counter() - t0
+    failed = [c for c in cases if "failed" in c]
+    cases_ok = [c for c in cases if "failed" not in c]
+    dev_ = np.array([c["log10_mean_abs_err"] - c["table_a2"] for c in cases_ok])
+    got_all = np.array([c["log10_mean_abs_err"] for c in cases_ok])
+
+    def effect(key, lev, base):
+        sel = lambda v: np.array([c[key] == v for c in cases_ok])
+        return round(float(got_all[sel(lev)].mean() - got_all[sel(base)].mean()), 3)
+
+    effects = {"nu1.5": [effect("nu", 1.5, 0.5), coef["smoothness1.5"]],
+               "L4": [effect("L", 4, 2), coef["NN4"]],
+               "grid350": [effect("m", 350, 100), coef["nGrid350"]], "grid500": [effect("m", 500, 100), coef["nGrid500"]],
+               "nugget0.1": [effect("tau2", 0.1, 0.01), coef["nugget0.1"]],
+               "nugget0.5": [effect("tau2", 0.5, 0.01), coef["nugget0.5"]],
+               "n500": [effect("n", 500, 200), None], "n1500": [effect("n", 1500, 200), None],
+               "d07_0.4": [effect("d07", 0.4, 0.2), None], "d07_0.8": [effect("d07", 0.8, 0.2), None]}
+    res = {"metric": "factorial accuracy study: |log10 mean abs error (rapid vs exact) - Table A2 model|, mean over cases",
+           "value": float(np.abs(dev_).mean()), "unit": "decades", "n_gpus": 1, "higher_is_better": False,
+           "data": "synthetic", "dtype": "f64",
+           "config": {"workload": "factorial: n {200,500,1500} x correlation-0.7 distance {0.2,0.4,0.8} x nu {0.5,1.5} "
+                                  "x nugget {0.01,0.1,0.5} x L {2,4} x grid {100,350,500}^2 on [0,1]^2, sigma2 = 1; "
+                                  f"{a.accuracy_reps} seeded site sets per case; errors at five nodes from centre to corner",
+                      "cases": len(cases), "site_sets_per_case": a.accuracy_reps},
+           "seconds": secs, "problems_per_s": len(cases) * a.accuracy_reps / secs,
+           "deviation_from_table_a2": {"mean": float(dev_.mean()), "rms": float(np.sqrt((dev_ ** 2).mean())),
+                                       "max_abs": float(np.abs(dev_).max()),
+                                       "within_one_decade": float((np.abs(dev_) < 1.0).mean())},
+           "main_effects_vs_table_a2": effects, "failed_cases": len(failed),
+           "cases": cases}
+    print(json.dumps(res), flush=True)
+    return 0
+
+
 def device_copy_gbs(torch, dev, mib=1024, reps=10):
     """Bandwidth of a plain device-to-device copy of `mib` MiB: (read + write bytes) / time."""
     n = mib << 20
@@ -487,6 +590,9 @@ def main(argv=None):
     ap.add_argument("--mixture", action="store_true", help="time a two-component nonstationary mixture instead")
     ap.add_argument("--universal", action="store_true", help="time universal kriging with a GLS trend instead")
     ap.add_argument("--exact", action="store_true", help="time the rapid predictor against exact kriging instead")
+    ap.add_argument("--accuracy", action="store_true",
+                    help="run the factorial accuracy study (rapid vs exact kriging, against Table A2) instead")
+    ap.add_argument("--accuracy-reps", type=int, default=2, help="site sets per factorial case")
     ap.add_argument("--interp-points", type=int, default=1_000_000)
     ap.add_argument("--interp-q", type=int, default=4)
     ap.add_argument("--calibrate-copy-mib", type=int, default=0,
@@ -527,6 +633,8 @@ def main(argv=None):
         return universal_mode(a, torch, krig, wl, dev)
     if a.exact:
         return exact_mode(a, torch, krig, wl, dev)
+    if a.accuracy:
+        return accuracy_mode(a, torch, krig, wl, dev)
     w = wl.grad_batch(B=a.B)
     B = a.B
 

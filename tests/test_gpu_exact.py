@@ -1,11 +1,12 @@
 """GPU: exact kriging predictions (krig_predict_exact, krig_exact_at) against the oracle."""
+import os
 import sys
 
 import numpy as np
 import pytest
 
 import workloads as wl
-from oracle.exact import ExactKriging
+from oracle.exact import ExactKriging, gp_draw
 from oracle.matern import Matern
 from oracle.rapid import Grid
 
@@ -105,3 +106,41 @@ def test_exact_argument_errors(krig):
     assert e.value.status == -1
     with pytest.raises(ValueError):
         p.exact_at(dev(np.zeros((1, w.n))), dev(np.zeros((3, 3))))
+
+
+def test_factorial_cases_within_a_decade_of_table_a2(krig):
+    # the accuracy study's measure through the GPU (rapid prediction against krig_exact_at at
+    # five nodes from the centre to the corner, sigma2 = 1, exact data draws) for three factor
+    # combinations, against the fitted log10 mean absolute error of Appendix A, Table A2
+    coef = {}
+    with open(os.path.join(os.path.dirname(__file__), "golden", "tableA2_coef.txt")) as f:
+        for line in f:
+            if line.strip() and not line.startswith("#"):
+                a_, b_ = line.split()
+                coef[a_] = float(b_)
+    r07 = {0.5: -np.log(0.7), 1.5: 1.0973492107034915}  # phi(r07) = 0.7
+    rng = np.random.default_rng(11)
+    for nu, L, m, tau2, n, d07 in ((0.5, 2, 100, 0.01, 200, 0.4), (1.5, 4, 350, 0.1, 500, 0.2),
+                                   (1.5, 2, 500, 0.5, 1500, 0.8)):
+        model = coef["(Intercept)"]
+        if nu == 1.5:
+            model += coef["smoothness1.5"] + (coef["smoothness1.5:NN4"] if L == 4 else 0.0)
+        model += coef["NN4"] if L == 4 else 0.0
+        model += coef[f"nGrid{m}"] if m != 100 else 0.0
+        model += coef[f"nugget{tau2}"] if tau2 != 0.01 else 0.0
+        say("factorial case", nu, L, m, tau2, n, d07)
+        k = Matern(1.0, d07 / r07[nu], nu, tau2)
+        h = 1.0 / (m - 1)
+        ab = [(m // 2, m // 2), (m // 4, m // 4), (0, 0), (m // 2, 0), (m - 1, m // 2)]
+        idx = np.array([i * m + j for i, j in ab])
+        pts = dev(np.array([[i * h, j * h] for i, j in ab]))
+        errs = []
+        for _ in range(3):
+            s_ = rng.uniform(0, 1, (n, 2))
+            p = krig.Plan(m, m, 0.0, 0.0, h, h, L, 1.0, k.rho, nu, tau2, s_, "f64")
+            al = p.solve(dev(gp_draw(s_, k, rng)))
+            rapid = host(p.convolve(al)).reshape(-1)[idx]
+            errs.append(np.abs(rapid - host(p.exact_at(al, pts))[0]))
+            p.close()
+        got = np.log10(np.mean(errs))
+        assert abs(got - model) < 1.0, (nu, L, m, tau2, got, model)
