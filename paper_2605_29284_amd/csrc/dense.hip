@@ -122,6 +122,7 @@ hipError_t assemble_kt(const double* d_sites, int n, const MaternDev& mt, double
 __global__ void __launch_bounds__(256) k_potrf_diag(double* A, int64_t lda, int n, int k0, double* Dinv,
                                                     int* status) {
   __shared__ double a[64][65];
+  __shared__ double dinv[64];
   __shared__ int bad;
   const int tid = threadIdx.x;
   const int nb = min(64, n - k0);
@@ -134,6 +135,9 @@ __global__ void __launch_bounds__(256) k_potrf_diag(double* A, int64_t lda, int 
     a[i][j] = v;
   }
   __syncthreads();
+  // right-looking column sweep; thread (ti, tj) of a 16 x 16 grid owns rows 4ti..4ti+3 and
+  // columns 4tj..4tj+3 of the trailing update (lower triangle only)
+  const int ti = tid >> 4, tj = tid & 15;
   for (int j = 0; j < 64; ++j) {
     if (tid == 0) {
       const double d = a[j][j];
@@ -148,13 +152,22 @@ __global__ void __launch_bounds__(256) k_potrf_diag(double* A, int64_t lda, int 
       }
     }
     __syncthreads();
-    const double djj = a[j][j];
-    for (int i = j + 1 + tid; i < 64; i += 256) a[i][j] /= djj;
+    if (tid > j && tid < 64) a[tid][j] /= a[j][j];
     __syncthreads();
-    const int rem = 63 - j;  // trailing (rem x rem) lower triangle
-    for (int e = tid; e < rem * rem; e += 256) {
-      const int i = j + 1 + e / rem, c = j + 1 + e % rem;
-      if (c <= i) a[i][c] -= a[i][j] * a[c][j];
+    if (4 * ti + 3 > j && 4 * tj + 3 > j && tj <= ti) {
+      double li[4], lc[4];
+#pragma unroll
+      for (int u = 0; u < 4; ++u) {
+        li[u] = a[4 * ti + u][j];
+        lc[u] = a[4 * tj + u][j];
+      }
+#pragma unroll
+      for (int u = 0; u < 4; ++u)
+#pragma unroll
+        for (int v = 0; v < 4; ++v) {
+          const int i = 4 * ti + u, c = 4 * tj + v;
+          if (i > j && c > j && c <= i) a[i][c] -= li[u] * lc[v];
+        }
     }
     __syncthreads();
   }
@@ -163,17 +176,25 @@ __global__ void __launch_bounds__(256) k_potrf_diag(double* A, int64_t lda, int 
     const int i = e / 64, j = e % 64;
     if (i < nb && j < nb) A[(int64_t)(k0 + i) * lda + k0 + j] = (j <= i) ? a[i][j] : 0.0;
   }
-  // inverse of the lower-triangular tile, one column per thread, written straight to
-  // Dinv (row-major 64 x 64); each thread only reads back entries it wrote itself
+  // inverse of the lower-triangular tile by forward substitution, one column per thread:
+  // entry (i, j), i > j, of the inverse is kept at a[j][i] (the unused upper triangle, row j
+  // belongs to thread j alone) and the diagonal in dinv; the factor itself stays in the
+  // lower triangle, which is only read from here on
   if (tid < 64) {
     const int j = tid;
-    for (int i = 0; i < j; ++i) Dinv[i * 64 + j] = 0.0;
-    Dinv[j * 64 + j] = 1.0 / a[j][j];
+    const double djj = 1.0 / a[j][j];
+    dinv[j] = djj;
     for (int i = j + 1; i < 64; ++i) {
-      double s = 0.0;
-      for (int k = j; k < i; ++k) s += a[i][k] * Dinv[k * 64 + j];
-      Dinv[i * 64 + j] = -s / a[i][i];
+      double s = a[i][j] * djj;
+      for (int k = j + 1; k < i; ++k) s += a[i][k] * a[j][k];
+      a[j][i] = -s / a[i][i];
     }
+  }
+  __syncthreads();
+  // Dinv row-major 64 x 64 (lower), coalesced
+  for (int e = tid; e < 64 * 64; e += 256) {
+    const int i = e / 64, j = e % 64;
+    Dinv[e] = i > j ? a[j][i] : (i == j ? dinv[i] : 0.0);
   }
 }
 
