@@ -27,9 +27,10 @@
  *  - "dt" arrays (images, lag, predictions, gradients) have the plan's dtype
  *    (float for KRIG_F32, double for KRIG_F64).  Data y, coefficients alpha,
  *    gradients w.r.t. y and the weights are always FP64.
- *  - Batch counts (B fields, R realisations, C components) must be >= 1; an empty
- *    batch returns KRIG_EINVAL without enqueueing anything.  Point counts of
- *    krig_interp may be 0.
+ *  - Batch counts (B fields, R realisations) must lie in 1..65535 (one launch grid
+ *    dimension each), and C components in 1..8; anything else, an empty batch
+ *    included, returns KRIG_EINVAL without enqueueing anything.  Point counts of
+ *    krig_interp and krig_exact_at may be 0.
  *  - All calls after krig_plan_create are asynchronous on the plan's stream
  *    (krig_set_stream), return a krig_status, never throw, and validate their
  *    arguments on the host before enqueueing anything.  A plan must not be used

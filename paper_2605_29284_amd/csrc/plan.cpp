@@ -936,21 +936,21 @@ int krig_lag(krig_plan p, void* d_lag) {
 }
 
 int krig_solve(krig_plan p, int32_t B, const double* d_y, double* d_alpha) {
-  if (!p || B < 1 || !d_y || !d_alpha) return KRIG_EINVAL;
+  if (!p || B < 1 || B > 65535 || !d_y || !d_alpha) return KRIG_EINVAL;
   int r = ensure_ws(p, B);
   if (r != KRIG_OK) return r;
   return do_solve(p, B, d_y, d_alpha);
 }
 
 int krig_scatter(krig_plan p, int32_t B, const double* d_alpha, void* d_img) {
-  if (!p || B < 1 || !d_alpha || !d_img) return KRIG_EINVAL;
+  if (!p || B < 1 || B > 65535 || !d_alpha || !d_img) return KRIG_EINVAL;
   KRIG_TRY(scatter_image(p->g, p->node_ptr, p->ent_site, p->ent_w, d_alpha, p->n, B, d_img,
                          (int64_t)p->P1 * p->P2, p->dtype == KRIG_F32, p->st));
   return KRIG_OK;
 }
 
 int krig_convolve(krig_plan p, int32_t B, const double* d_alpha, const void* d_lag, void* d_yhat, void* d_saved) {
-  if (!p || B < 1 || !d_alpha || !d_yhat) return KRIG_EINVAL;
+  if (!p || B < 1 || B > 65535 || !d_alpha || !d_yhat) return KRIG_EINVAL;
   int r = ensure_ws(p, B);
   if (r != KRIG_OK) return r;
   const double* filt = nullptr;
@@ -960,7 +960,7 @@ int krig_convolve(krig_plan p, int32_t B, const double* d_alpha, const void* d_l
 
 int krig_predict(krig_plan p, int32_t B, const double* d_y, const void* d_lag, void* d_yhat, double* d_alpha_out,
                  void* d_saved) {
-  if (!p || B < 1 || !d_y || !d_yhat) return KRIG_EINVAL;
+  if (!p || B < 1 || B > 65535 || !d_y || !d_yhat) return KRIG_EINVAL;
   int r = ensure_ws(p, B);
   if (r != KRIG_OK) return r;
   double* al = d_alpha_out ? d_alpha_out : p->alpha;
@@ -972,7 +972,7 @@ int krig_predict(krig_plan p, int32_t B, const double* d_y, const void* d_lag, v
 
 int krig_predict_adjoint(krig_plan p, int32_t B, const void* d_g, const double* d_alpha, const void* d_saved,
                          const void* d_lag, double* d_dy, void* d_dlag) {
-  if (!p || B < 1 || !d_g) return KRIG_EINVAL;
+  if (!p || B < 1 || B > 65535 || !d_g) return KRIG_EINVAL;
   if (d_dlag && !d_saved && !d_alpha) return KRIG_EINVAL;
   int r = ensure_ws(p, B);
   if (r != KRIG_OK) return r;
@@ -1215,7 +1215,7 @@ int krig_plan_tune(krig_plan p, int32_t key, int64_t value) {
 }
 
 int krig_plan_autotune(krig_plan p, int32_t B, int32_t with_adjoint) {
-  if (!p || B < 1 || p->timing || p->batch_refs > 0) return KRIG_EINVAL;
+  if (!p || B < 1 || B > 65535 || p->timing || p->batch_refs > 0) return KRIG_EINVAL;
   int r;
   if ((r = ensure_ws(p, B)) != KRIG_OK) return r;
   if (with_adjoint && (r = ensure_ws_adj(p, B)) != KRIG_OK) return r;
@@ -1356,7 +1356,7 @@ int krig_timing_read(krig_plan p, int32_t stage, double* total_ms, int64_t* laun
 }
 
 int krig_csim(krig_plan p, int32_t R, uint64_t seed, const double* d_y, void* d_fields) {
-  if (!p || R < 1 || !d_y || !d_fields) return KRIG_EINVAL;
+  if (!p || R < 1 || R > 65535 || !d_y || !d_fields) return KRIG_EINVAL;
   int r;
   if (!p->lamS && (r = ce_setup(p)) != KRIG_OK) return r;
   if ((r = ensure_ws(p, R)) != KRIG_OK) return r;
@@ -1426,13 +1426,13 @@ static int check_many(const krig_plan* plans, int32_t count, const int32_t* h_B,
                       void* const* h_yhat) {
   if (!plans || count < 1 || !h_y || !h_yhat) return KRIG_EINVAL;
   for (int i = 0; i < count; ++i)
-    if (!plans[i] || !h_y[i] || !h_yhat[i] || (h_B && h_B[i] < 1)) return KRIG_EINVAL;
+    if (!plans[i] || !h_y[i] || !h_yhat[i] || (h_B && (h_B[i] < 1 || h_B[i] > 65535))) return KRIG_EINVAL;
   return KRIG_OK;
 }
 
 int krig_mixture(const krig_plan* plans, int32_t C, int32_t B, const double* d_alpha, const double* d_lam_sites,
                  const double* d_lam_grid, void* d_yhat, void* stream) {
-  if (!plans || C < 1 || C > MIX_MAX || B < 1 || !d_alpha || !d_lam_sites || !d_lam_grid || !d_yhat)
+  if (!plans || C < 1 || C > MIX_MAX || B < 1 || B > 65535 || !d_alpha || !d_lam_sites || !d_lam_grid || !d_yhat)
     return KRIG_EINVAL;
   const krig_plan p0 = plans[0];
   if (!p0) return KRIG_EINVAL;

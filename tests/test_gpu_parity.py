@@ -492,12 +492,15 @@ def test_error_paths(krig):
     y = host(p.predict(dev(np.array([[1.0, -2.0, 0.5, 3.0]]))))[0]
     ref = rp.predict_direct(ek.coef(np.array([1.0, -2.0, 0.5, 3.0]))).reshape(10, 10)
     assert relmax(y, ref) < 1e-12
-    # an empty batch is rejected before anything is enqueued; the plan stays usable
+    # an empty batch, or one beyond a launch grid dimension, is rejected before anything is
+    # enqueued; the plan stays usable
     empty = dev(np.zeros((0, 4)))
     for call in (p.solve, p.scatter, p.convolve, p.predict):
         with pytest.raises(krig.KrigError) as e:
             call(empty)
         assert e.value.status == -1
+    y1, out1 = dev(np.zeros((1, 4))), p.empty(1, 10, 10)  # valid buffers; the count is checked first
+    assert p.lib.krig_predict(p.h, 65536, y1.data_ptr(), None, out1.data_ptr(), None, None) == -1
     assert np.array_equal(host(p.predict(dev(np.array([[1.0, -2.0, 0.5, 3.0]]))))[0], y)
 
 
