@@ -15,15 +15,17 @@ typedef double double4_t __attribute__((ext_vector_type(4)));
 // ------------------------------------------------------------------------------------
 // GEMM: C = alpha * op(A) * op(B) + beta * C  (row-major, FP64, MFMA 16x16x4)
 // Block tile 64 x 64, four waves each owning a 32 x 32 quadrant (2 x 2 MFMA tiles),
-// K staged through LDS 16 at a time.  LOWER restricts the launch to tiles with
-// tile_col <= tile_row (symmetric rank-k updates).
+// K staged through two LDS buffers 16 at a time (register prefetch of the next chunk).
+// LOWER restricts the launch to tiles with tile_col <= tile_row (symmetric rank-k updates).
 // MFMA operand layout (v_mfma_f64_16x16x4f64): lane l supplies A[l%16][l/16] and
 // B[l/16][l%16]; result register r of lane l is D[l/16 + 4*r][l%16] (FP64 form: rows
 // interleave across the four lane groups, unlike the FP32 16x16 forms).
 // ------------------------------------------------------------------------------------
 __global__ void __launch_bounds__(256) k_gemm_f64(GemmArgs g) {
-  __shared__ double As[16][64 + 1];   // [k][m]
-  __shared__ double Bs[16][64 + 1];   // [k][n]
+  // two LDS buffers: chunk t is staged into buffer t&1 while the previous chunk's MFMAs run,
+  // and the next chunk's global loads are in flight in registers during chunk t's MFMAs
+  __shared__ double As[2][16][64 + 1];   // [buf][k][m]
+  __shared__ double Bs[2][16][64 + 1];   // [buf][k][n]
   const int tm = blockIdx.y, tn = blockIdx.x;
   if (g.lower && tn > tm) return;
   const int m0 = tm * 64 + g.m_off, n0 = tn * 64 + g.n_off;
@@ -34,40 +36,51 @@ __global__ void __launch_bounds__(256) k_gemm_f64(GemmArgs g) {
   for (int i = 0; i < 2; ++i)
     for (int j = 0; j < 2; ++j) acc[i][j] = (double4_t){0.0, 0.0, 0.0, 0.0};
 
+  // element e = tid + 256 q (q < 4) of a 64 x 16 chunk: its (m, k) and (n, k) positions
+  int am[4], ak[4], bn[4], bk[4];
+#pragma unroll
+  for (int q = 0; q < 4; ++q) {
+    const int e = tid + 256 * q;
+    if (g.transA) { am[q] = e % 64; ak[q] = e / 64; } else { ak[q] = e % 16; am[q] = e / 16; }
+    if (g.transB) { bk[q] = e % 16; bn[q] = e / 16; } else { bn[q] = e % 64; bk[q] = e / 64; }
+  }
+  double ra[4], rb[4];
+  auto fetch = [&](int k0) {
+#pragma unroll
+    for (int q = 0; q < 4; ++q) {
+      const int gm = m0 + am[q], gka = k0 + ak[q];
+      ra[q] = 0.0;
+      if (gm < g.M_end && gka < g.K)
+        ra[q] = g.transA ? g.A[(int64_t)gka * g.lda + gm] : g.A[(int64_t)gm * g.lda + gka];
+      const int gn = n0 + bn[q], gkb = k0 + bk[q];
+      rb[q] = 0.0;
+      if (gn < g.N_end && gkb < g.K)
+        rb[q] = g.transB ? g.B[(int64_t)gn * g.ldb + gkb] : g.B[(int64_t)gkb * g.ldb + gn];
+    }
+  };
+  fetch(0);
+  int buf = 0;
   for (int k0 = 0; k0 < g.K; k0 += 16) {
-    // stage A (64 x 16) and B (16 x 64)
-    for (int e = tid; e < 64 * 16; e += 256) {
-      int mm, kk;
-      if (g.transA) { mm = e % 64; kk = e / 64; } else { kk = e % 16; mm = e / 16; }
-      const int gm = m0 + mm, gk = k0 + kk;
-      double v = 0.0;
-      if (gm < g.M_end && gk < g.K)
-        v = g.transA ? g.A[(int64_t)gk * g.lda + gm] : g.A[(int64_t)gm * g.lda + gk];
-      As[kk][mm] = v;
+#pragma unroll
+    for (int q = 0; q < 4; ++q) {
+      As[buf][ak[q]][am[q]] = ra[q];
+      Bs[buf][bk[q]][bn[q]] = rb[q];
     }
-    for (int e = tid; e < 64 * 16; e += 256) {
-      int nn, kk;
-      if (g.transB) { kk = e % 16; nn = e / 16; } else { nn = e % 64; kk = e / 64; }
-      const int gn = n0 + nn, gk = k0 + kk;
-      double v = 0.0;
-      if (gn < g.N_end && gk < g.K)
-        v = g.transB ? g.B[(int64_t)gn * g.ldb + gk] : g.B[(int64_t)gk * g.ldb + gn];
-      Bs[kk][nn] = v;
-    }
-    __syncthreads();
+    __syncthreads();  // chunk visible; every wave is past the MFMAs that last read this buffer's twin
+    if (k0 + 16 < g.K) fetch(k0 + 16);
 #pragma unroll
     for (int kk = 0; kk < 16; kk += 4) {
       const int kq = kk + (lane >> 4);
-      double a0 = As[kq][wm + (lane & 15)];
-      double a1 = As[kq][wm + 16 + (lane & 15)];
-      double b0 = Bs[kq][wn + (lane & 15)];
-      double b1 = Bs[kq][wn + 16 + (lane & 15)];
+      double a0 = As[buf][kq][wm + (lane & 15)];
+      double a1 = As[buf][kq][wm + 16 + (lane & 15)];
+      double b0 = Bs[buf][kq][wn + (lane & 15)];
+      double b1 = Bs[buf][kq][wn + 16 + (lane & 15)];
       acc[0][0] = __builtin_amdgcn_mfma_f64_16x16x4f64(a0, b0, acc[0][0], 0, 0, 0);
       acc[0][1] = __builtin_amdgcn_mfma_f64_16x16x4f64(a0, b1, acc[0][1], 0, 0, 0);
       acc[1][0] = __builtin_amdgcn_mfma_f64_16x16x4f64(a1, b0, acc[1][0], 0, 0, 0);
       acc[1][1] = __builtin_amdgcn_mfma_f64_16x16x4f64(a1, b1, acc[1][1], 0, 0, 0);
     }
-    __syncthreads();
+    buf ^= 1;
   }
   for (int i = 0; i < 2; ++i)
     for (int j = 0; j < 2; ++j)
