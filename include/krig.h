@@ -235,8 +235,9 @@ int krig_exact_at(krig_plan p, int32_t B, const double *d_alpha, int32_t npts, c
  *   d_yhat[b] = X_grid beta_b + the rapid prediction of c_b   ([B][m1][m2] dt).
  * d_beta [B][np] FP64 and d_coef [B][n] FP64 may be NULL (else receive beta and c).
  * M^{-1} is the plan's FP64 solve; the np x np system is factored on the GPU, and when
- * X^T M^{-1} X is not numerically positive definite (covariates not independent at the
- * sites) beta, and with it the prediction, is NaN.  B <= 65519.  Asynchronous.
+ * X^T M^{-1} X is not numerically positive definite (a Cholesky pivot below 1e-8 of its
+ * diagonal entry: covariates dependent at the sites to about four digits) beta, and with
+ * it the prediction, is NaN.  B <= 65519.  Asynchronous.
  */
 int krig_predict_universal(krig_plan p, int32_t B, const double *d_z, int32_t np, const double *d_Xs,
                            const double *d_Xg, void *d_yhat, double *d_beta, double *d_coef);

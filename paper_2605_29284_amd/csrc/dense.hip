@@ -245,14 +245,19 @@ hipError_t cholesky_and_inverse(double* A, int64_t lda, int n, double* Linv, dou
       // copy back into A
       if ((e = copy_rows(work, 64, A + (int64_t)(k0 + nb) * lda + k0, lda, rows, nb, st)) != hipSuccess) return e;
     }
-    // trailing update: A22 -= L21 L21^T (lower tiles)
+    // trailing update A22 -= L21 L21^T (lower tiles).  Blocks go in pairs (outer panels of
+    // 128 columns): after the first block of a pair only the second block's columns are
+    // updated (K = 64); after the second, everything to the right at once from both
+    // blocks' columns (K = 128), which halves the trailing matrix's read-modify-write traffic.
     {
       const int rows = n - k0 - nb;
+      const bool first = (kb & 1) == 0;
+      const int kc = first ? k0 : k0 - 64;  // first column of the update's K range
       GemmArgs g{};
-      g.A = A + (int64_t)(k0 + nb) * lda + k0; g.lda = lda; g.transA = 0;
-      g.B = A + (int64_t)(k0 + nb) * lda + k0; g.ldb = lda; g.transB = 1;
+      g.A = A + (int64_t)(k0 + nb) * lda + kc; g.lda = lda; g.transA = 0;
+      g.B = A + (int64_t)(k0 + nb) * lda + kc; g.ldb = lda; g.transB = 1;
       g.C = A + (int64_t)(k0 + nb) * lda + (k0 + nb); g.ldc = lda;
-      g.m_off = 0; g.M_end = rows; g.n_off = 0; g.N_end = rows; g.K = nb;
+      g.m_off = 0; g.M_end = rows; g.n_off = 0; g.N_end = first ? min(64, rows) : rows; g.K = k0 + nb - kc;
       g.alpha = -1.0; g.beta = 1.0; g.lower = 1;
       if ((e = gemm_f64(g, st)) != hipSuccess) return e;
     }
@@ -283,12 +288,18 @@ hipError_t cholesky_and_inverse(double* A, int64_t lda, int n, double* Linv, dou
         hipSuccess)
       return e;
     if (i0 + nb >= n) break;
-    // R[i0+nb:, 0:i0+nb] += L[i0+nb:, i0:i0+nb] X[i0:i0+nb, 0:i0+nb]
+    // R[i0+nb:, 0:i0+nb] += L[i0+nb:, i0:i0+nb] X[i0:i0+nb, 0:i0+nb], with the block rows in
+    // pairs as in the factorisation: after the first of a pair only the next block row is
+    // updated (K = 64), after the second all rows below from both (K = 128; X of the first
+    // block row is zero in the second's columns)
+    const bool first = (ib & 1) == 0;
+    const int kc = first ? i0 : i0 - 64;
     GemmArgs g{};
-    g.A = A + (int64_t)(i0 + nb) * lda + i0; g.lda = lda; g.transA = 0;
-    g.B = Linv + (int64_t)i0 * lda; g.ldb = lda; g.transB = 0;
+    g.A = A + (int64_t)(i0 + nb) * lda + kc; g.lda = lda; g.transA = 0;
+    g.B = Linv + (int64_t)kc * lda; g.ldb = lda; g.transB = 0;
     g.C = Linv + (int64_t)(i0 + nb) * lda; g.ldc = lda;
-    g.m_off = 0; g.M_end = n - i0 - nb; g.n_off = 0; g.N_end = i0 + nb; g.K = nb;
+    g.m_off = 0; g.M_end = first ? min(64, n - i0 - nb) : n - i0 - nb; g.n_off = 0; g.N_end = i0 + nb;
+    g.K = i0 + nb - kc;
     g.alpha = 1.0; g.beta = 1.0; g.lower = 0;
     if ((e = gemm_f64(g, st)) != hipSuccess) return e;
   }

@@ -45,9 +45,13 @@ __global__ void __launch_bounds__(256) k_uk_solve(const double* __restrict__ G, 
     for (int i = 0; i < np; ++i)
       for (int j = 0; j <= i; ++j) Lf[i][j] = G[(int64_t)i * ld + j];
     for (int j = 0; j < np && ok; ++j) {
-      double d = Lf[j][j];
+      // a pivot below 1e-8 of its diagonal entry (covariate j reproduced by the earlier ones
+      // to about four digits in the M^{-1} inner product) counts as dependent: the sign of a
+      // rounding residue must not decide it
+      const double d0 = Lf[j][j];
+      double d = d0;
       for (int k = 0; k < j; ++k) d -= Lf[j][k] * Lf[j][k];
-      if (!(d > 0.0)) {
+      if (!(d > 1e-8 * d0)) {
         ok = 0;
         break;
       }
