@@ -219,6 +219,8 @@ __global__ void k_zero_upper(double* A, int64_t lda, int n) {
   if (j > i) A[(int64_t)i * lda + j] = 0.0;
 }
 
+constexpr int CHOL_GROUP = 4;  // 64-wide blocks per outer panel of the factorisations
+
 // Blocked Cholesky of the n x n matrix A (lower, in place) plus the inverse factor
 // Linv = L^{-1} (lower, n x n).  work: 64 x n doubles.  Dinv: nblk * 64 * 64.
 hipError_t cholesky_and_inverse(double* A, int64_t lda, int n, double* Linv, double* Dinv, double* work,
@@ -245,19 +247,23 @@ hipError_t cholesky_and_inverse(double* A, int64_t lda, int n, double* Linv, dou
       // copy back into A
       if ((e = copy_rows(work, 64, A + (int64_t)(k0 + nb) * lda + k0, lda, rows, nb, st)) != hipSuccess) return e;
     }
-    // trailing update A22 -= L21 L21^T (lower tiles).  Blocks go in pairs (outer panels of
-    // 128 columns): after the first block of a pair only the second block's columns are
-    // updated (K = 64); after the second, everything to the right at once from both
-    // blocks' columns (K = 128), which halves the trailing matrix's read-modify-write traffic.
+    // trailing update A22 -= L21 L21^T (lower tiles).  Blocks go in groups of CHOL_GROUP
+    // (outer panels of 64 CHOL_GROUP columns): within a group a block updates only the
+    // group's remaining columns (K = 64); the group's last block updates everything to
+    // the right at once from all the group's columns (K = 64 CHOL_GROUP), which divides
+    // the trailing matrix's read-modify-write traffic by CHOL_GROUP.
     {
       const int rows = n - k0 - nb;
-      const bool first = (kb & 1) == 0;
-      const int kc = first ? k0 : k0 - 64;  // first column of the update's K range
+      const int g0 = (kb - kb % CHOL_GROUP) * 64;  // first column of the group
+      const bool last = kb % CHOL_GROUP == CHOL_GROUP - 1;
+      const int kc = last ? g0 : k0;               // first column of the update's K range
       GemmArgs g{};
       g.A = A + (int64_t)(k0 + nb) * lda + kc; g.lda = lda; g.transA = 0;
       g.B = A + (int64_t)(k0 + nb) * lda + kc; g.ldb = lda; g.transB = 1;
       g.C = A + (int64_t)(k0 + nb) * lda + (k0 + nb); g.ldc = lda;
-      g.m_off = 0; g.M_end = rows; g.n_off = 0; g.N_end = first ? min(64, rows) : rows; g.K = k0 + nb - kc;
+      g.m_off = 0; g.M_end = rows; g.n_off = 0;
+      g.N_end = last ? rows : min(g0 + 64 * CHOL_GROUP - (k0 + nb), rows);
+      g.K = k0 + nb - kc;
       g.alpha = -1.0; g.beta = 1.0; g.lower = 1;
       if ((e = gemm_f64(g, st)) != hipSuccess) return e;
     }
@@ -289,16 +295,18 @@ hipError_t cholesky_and_inverse(double* A, int64_t lda, int n, double* Linv, dou
       return e;
     if (i0 + nb >= n) break;
     // R[i0+nb:, 0:i0+nb] += L[i0+nb:, i0:i0+nb] X[i0:i0+nb, 0:i0+nb], with the block rows in
-    // pairs as in the factorisation: after the first of a pair only the next block row is
-    // updated (K = 64), after the second all rows below from both (K = 128; X of the first
-    // block row is zero in the second's columns)
-    const bool first = (ib & 1) == 0;
-    const int kc = first ? i0 : i0 - 64;
+    // groups as in the factorisation: within a group a block row updates only the group's
+    // remaining block rows (K = 64); the group's last updates all rows below from the whole
+    // group (K = 64 CHOL_GROUP; X of an earlier block row is zero in later ones' columns)
+    const int g0 = (ib - ib % CHOL_GROUP) * 64;
+    const bool last = ib % CHOL_GROUP == CHOL_GROUP - 1;
+    const int kc = last ? g0 : i0;
     GemmArgs g{};
     g.A = A + (int64_t)(i0 + nb) * lda + kc; g.lda = lda; g.transA = 0;
     g.B = Linv + (int64_t)kc * lda; g.ldb = lda; g.transB = 0;
     g.C = Linv + (int64_t)(i0 + nb) * lda; g.ldc = lda;
-    g.m_off = 0; g.M_end = first ? min(64, n - i0 - nb) : n - i0 - nb; g.n_off = 0; g.N_end = i0 + nb;
+    g.m_off = 0; g.M_end = last ? n - i0 - nb : min(g0 + 64 * CHOL_GROUP - (i0 + nb), n - i0 - nb);
+    g.n_off = 0; g.N_end = i0 + nb;
     g.K = i0 + nb - kc;
     g.alpha = 1.0; g.beta = 1.0; g.lower = 0;
     if ((e = gemm_f64(g, st)) != hipSuccess) return e;
