@@ -346,9 +346,9 @@ int krig_plan_tune(krig_plan p, int32_t key, int64_t value);
  * (transform forms first, then lines per block and field grouping; candidates are
  * the powers of two up to each key's limit and the limit itself).  Each timing is
  * the median of three windows of ten calls; a candidate replaces the current value
- * only when it is more than 1% faster.  The choice is recorded in a process-wide table keyed by grid, neighbour
- * order, transform lengths and dtype; plans created later with the same key start
- * from it.  Synchronises the plan's stream.  KRIG_EINVAL while stage timing is on or
+ * only when it is more than 1% faster.  The choice is recorded in a process-wide
+ * table keyed by grid, neighbour order, transform lengths and dtype; plans created
+ * later with the same key start from it.  Synchronises the plan's stream.  KRIG_EINVAL while stage timing is on or
  * a recorded batch holds the plan.
  */
 int krig_plan_autotune(krig_plan p, int32_t B, int32_t with_adjoint);
