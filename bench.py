@@ -552,6 +552,52 @@ def accuracy_mode(a, torch, krig, wl, dev):
     return 0
 
 
+def convergence_mode(a, torch, krig, wl, dev):
+    """Section 3.2 / Table 2 on the GPU: the error Lambda of the interpolated covariance
+    (krig_kernel_at) against the exact one (krig_exact_at with a unit coefficient), as a
+    supremum over [0,1]^2 (a 121 x 121 lattice plus an 81 x 81 patch around the site), for
+    the Figure 5 set-up (range 0.25, L = 2, one site centred in the central grid box) on
+    grids of 20^2 .. 140^2; the fitted slopes against the inverse fill distance are
+    compared with the paper's.  Prints one JSON line."""
+    gold = {}
+    with open(os.path.join(ROOT, "tests", "golden", "table2_slopes.txt")) as f:
+        for line in f:
+            if line.strip() and not line.startswith("#"):
+                k_, v_ = line.split()
+                gold[float(k_)] = float(v_)
+    one = torch.ones(1, 1, dtype=torch.float64, device=dev)
+    ms = (20, 30, 40, 60, 80, 100, 140)
+    out = {}
+    t0 = time.perf_counter()
+    for nu in (0.5, 1.5, 2.5):
+        lams, inv = [], []
+        for m in ms:
+            h = 1.0 / (m - 1)
+            c = (m - 1) // 2
+            s_ = np.array([[(c + 0.5) * h, (c + 0.5) * h]])
+            p = krig.Plan(m, m, 0.0, 0.0, h, h, 2, 1.0, 0.25, nu, 0.0, s_, "f64")
+            g1 = np.linspace(0, 1, 121)
+            X, Y = np.meshgrid(g1, g1, indexing="ij")
+            g2 = np.linspace(-3 * h, 3 * h, 81)
+            U, V = np.meshgrid(g2, g2, indexing="ij")
+            pts = torch.as_tensor(np.concatenate([np.stack([X.ravel(), Y.ravel()], 1),
+                                                  s_ + np.stack([U.ravel(), V.ravel()], 1)]), device=dev)
+            lams.append((p.kernel_at(0, pts) - p.exact_at(one, pts)[0]).abs().max().item())
+            inv.append(1.0 / (0.5 * np.hypot(h, h)))
+            p.close()
+        slope = float(-np.polyfit(np.log10(inv), np.log10(lams), 1)[0])
+        out[str(nu)] = {"lambda": lams, "slope": round(slope, 3), "table2": gold[nu]}
+    res = {"metric": "Table 2 convergence: fitted order of the kernel approximation error vs 1/fill distance",
+           "value": float(np.mean([abs(v["slope"] - v["table2"]) for v in out.values()])),
+           "unit": "mean |slope - Table 2|", "n_gpus": 1, "higher_is_better": False, "data": "synthetic",
+           "dtype": "f64", "config": {"workload": "Figure 5 set-up: [0,1]^2, Matern range 0.25, L = 2, one site "
+                                                  "centred in the central box, grids " + ",".join(f"{m}^2" for m in ms),
+                                      "nu": [0.5, 1.5, 2.5]},
+           "grids": list(ms), "by_nu": out, "seconds": time.perf_counter() - t0}
+    print(json.dumps(res), flush=True)
+    return 0
+
+
 def device_copy_gbs(torch, dev, mib=1024, reps=10):
     """Bandwidth of a plain device-to-device copy of `mib` MiB: (read + write bytes) / time."""
     n = mib << 20
@@ -594,6 +640,8 @@ def main(argv=None):
     ap.add_argument("--accuracy", action="store_true",
                     help="run the factorial accuracy study (rapid vs exact kriging, against Table A2) instead")
     ap.add_argument("--accuracy-reps", type=int, default=2, help="site sets per factorial case")
+    ap.add_argument("--convergence", action="store_true",
+                    help="measure the Table 2 convergence slopes of the kernel approximation instead")
     ap.add_argument("--interp-points", type=int, default=1_000_000)
     ap.add_argument("--interp-q", type=int, default=4)
     ap.add_argument("--calibrate-copy-mib", type=int, default=0,
@@ -636,6 +684,8 @@ def main(argv=None):
         return exact_mode(a, torch, krig, wl, dev)
     if a.accuracy:
         return accuracy_mode(a, torch, krig, wl, dev)
+    if a.convergence:
+        return convergence_mode(a, torch, krig, wl, dev)
     w = wl.grad_batch(B=a.B)
     B = a.B
 

@@ -227,6 +227,17 @@ int krig_exact_at(krig_plan p, int32_t B, const double *d_alpha, int32_t npts, c
                   double *d_out);
 
 /*
+ * The rapid method's interpolated covariance of site i at arbitrary points (eq. weights;
+ * the quantity whose error Section 3.2 and Table 2 study):
+ *   d_out[j] = sum_{m < M} W[i][m] k(|p_j - g_m|),
+ * g_m the site's neighbour nodes (its anchor and the offsets of krig_weights), W[i] its
+ * current weights.  d_pts [npts][2] FP64 anywhere in the plane, d_out [npts] FP64.
+ * Reads the site's anchor back from the device first (synchronises the plan's stream);
+ * npts = 0 is a no-op; KRIG_EINVAL for i outside 0..n-1.
+ */
+int krig_kernel_at(krig_plan p, int32_t i, int32_t npts, const double *d_pts, double *d_out);
+
+/*
  * Universal kriging (Section 3, eqs. findbeta, findc, predictionf): data with a linear
  * trend in np covariates, 1 <= np <= 16.  d_z [B][n] FP64 data; d_Xs [np][n] FP64 the
  * covariates at the sites (covariate k of site i at d_Xs[k*n + i]: the columns of the

@@ -30,7 +30,7 @@ STATUS = {0: "KRIG_OK", -1: "KRIG_EINVAL", -2: "KRIG_EDOMAIN", -3: "KRIG_ENOTSPD
 
 EXPORTS = ["krig_plan_create", "krig_plan_destroy", "krig_plan_info", "krig_set_stream", "krig_weights",
            "krig_set_weights", "krig_set_kvec", "krig_lag", "krig_solve", "krig_scatter", "krig_convolve", "krig_predict",
-           "krig_predict_adjoint", "krig_csim", "krig_interp", "krig_predict_exact", "krig_exact_at", "krig_mixture", "krig_predict_universal", "krig_plan_tune", "krig_plan_autotune", "krig_predict_many", "krig_batch_create",
+           "krig_predict_adjoint", "krig_csim", "krig_interp", "krig_predict_exact", "krig_exact_at", "krig_kernel_at", "krig_mixture", "krig_predict_universal", "krig_plan_tune", "krig_plan_autotune", "krig_predict_many", "krig_batch_create",
            "krig_batch_launch", "krig_batch_destroy", "krig_timing_enable", "krig_timing_read", "krig_strerror"]
 
 STAGES = ["ROWS_FWD", "COLS_CONV", "ROWS_INV", "ADJ_ROWS_FWD", "ADJ_COLS", "ADJ_ROWS_INV", "GATHER", "SOLVE",
@@ -84,6 +84,7 @@ def load_library(path: str = LIB_PATH) -> ctypes.CDLL:
         "krig_interp": [vp, i32, dp, i32, dp, i32, dp],
         "krig_predict_exact": [vp, i32, dp, dp],
         "krig_exact_at": [vp, i32, dp, i32, dp, dp],
+        "krig_kernel_at": [vp, i32, i32, dp, dp],
         "krig_mixture": [ctypes.POINTER(vp), i32, i32, dp, dp, dp, dp, vp],
         "krig_predict_universal": [vp, i32, dp, i32, dp, dp, dp, dp, dp],
         "krig_plan_tune": [vp, i32, i64],
@@ -368,6 +369,17 @@ class Plan:
         self._stream()
         _check(self.lib.krig_exact_at(self.h, B, alpha.data_ptr(), npts, pts.data_ptr(), out.data_ptr()),
                "krig_exact_at")
+        return out
+
+    def kernel_at(self, i: int, pts):
+        """The interpolated covariance of site i at points (krig_kernel_at): pts [npts][2]
+        FP64 -> [npts] FP64."""
+        if pts.dim() != 2 or pts.shape[1] != 2:
+            raise ValueError("pts: expected shape (npts, 2)")
+        pts = self._t(pts, self.torch.float64, tuple(pts.shape), "pts")
+        out = self.empty(pts.shape[0], dtype=self.torch.float64)
+        self._stream()
+        _check(self.lib.krig_kernel_at(self.h, int(i), pts.shape[0], pts.data_ptr(), out.data_ptr()), "krig_kernel_at")
         return out
 
     def csim(self, R: int, seed: int, y):

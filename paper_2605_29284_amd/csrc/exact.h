@@ -26,4 +26,10 @@ struct ExactArgs {
 // rounded once.  hipErrorInvalidValue when B < 1 or the grid would be too large.
 hipError_t exact_predict(const ExactArgs& a, int B, bool f32, hipStream_t st);
 
+// The rapid method's interpolated covariance of one site at arbitrary points (eq. weights):
+// out[j] = sum_{m < M} W[m] k(|p_j - g_m|), g_m the site's neighbour nodes (anchor (i0, j0),
+// offsets (ox, oy) in {-L+1..L}^2, ox-major), W its M weights.  FP64.
+hipError_t kernel_approx_at(const GridDev& g, const MaternDev& mt, int i0, int j0, const double* W,
+                            const double* pts, int npts, double* out, hipStream_t st);
+
 }  // namespace krig

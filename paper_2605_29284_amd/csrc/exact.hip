@@ -106,4 +106,28 @@ hipError_t exact_predict(const ExactArgs& a, int B, bool f32, hipStream_t st) {
   return hipGetLastError();
 }
 
+__global__ void __launch_bounds__(256) k_kernel_approx(GridDev g, MaternDev mt, int i0, int j0,
+                                                       const double* __restrict__ W, const double* __restrict__ pts,
+                                                       int npts, double* __restrict__ out) {
+  const int j = blockIdx.x * blockDim.x + threadIdx.x;
+  if (j >= npts) return;
+  const double px = pts[2 * (int64_t)j], py = pts[2 * (int64_t)j + 1];
+  const int L2 = 2 * g.L;
+  double s = 0.0;
+  for (int m = 0; m < g.M; ++m) {
+    const int ox = m / L2 - g.L + 1, oy = m % L2 - g.L + 1;
+    const double ddx = px - (g.x0 + (double)(i0 + ox) * g.dx), ddy = py - (g.y0 + (double)(j0 + oy) * g.dy);
+    s += W[m] * matern_cov(sqrt(ddx * ddx + ddy * ddy), mt);
+  }
+  out[j] = s;
+}
+
+hipError_t kernel_approx_at(const GridDev& g, const MaternDev& mt, int i0, int j0, const double* W,
+                            const double* pts, int npts, double* out, hipStream_t st) {
+  if (npts <= 0) return npts == 0 ? hipSuccess : hipErrorInvalidValue;
+  hipLaunchKernelGGL(k_kernel_approx, dim3((unsigned)((npts + 255) / 256)), dim3(256), 0, st, g, mt, i0, j0, W, pts,
+                     npts, out);
+  return hipGetLastError();
+}
+
 }  // namespace krig

@@ -1191,6 +1191,17 @@ int krig_exact_at(krig_plan p, int32_t B, const double* d_alpha, int32_t npts, c
   return exact_call(p, B, d_alpha, npts, d_pts, d_out, false);
 }
 
+int krig_kernel_at(krig_plan p, int32_t i, int32_t npts, const double* d_pts, double* d_out) {
+  if (!p || i < 0 || i >= p->n || npts < 0) return KRIG_EINVAL;
+  if (npts == 0) return KRIG_OK;
+  if (!d_pts || !d_out) return KRIG_EINVAL;
+  int32_t anc[2];  // the site's anchor, from the device copy (a small synchronous read)
+  KRIG_TRY(hipMemcpyAsync(anc, p->anchor + 2 * (int64_t)i, sizeof(anc), hipMemcpyDeviceToHost, p->st));
+  KRIG_TRY(hipStreamSynchronize(p->st));
+  KRIG_TRY(kernel_approx_at(p->g, p->mt, anc[0], anc[1], p->W + (int64_t)i * p->M, d_pts, npts, d_out, p->st));
+  return KRIG_OK;
+}
+
 int krig_plan_tune(krig_plan p, int32_t key, int64_t value) {
   if (!p || value < 1 || value > 256) return KRIG_EINVAL;
   if (p->batch_refs > 0) return KRIG_EINVAL;  // a recorded graph holds the current launches
