@@ -451,14 +451,15 @@ def exact_cpu_baseline(w):
 
 # phi(r) = 0.7 for the closed-form smoothness levels: the factorial study fixes the
 # distance at which the correlation falls to 0.7, so range = that distance / R07[nu]
-R07 = {0.5: 0.3566749439387324, 1.5: 1.0973492107034915}
+R07 = {0.5: 0.3566749439387324, 1.0: 0.7766915961392014, 1.5: 1.0973492107034915}
 
 
 def table_a2_model(coef, nu, L, m, tau2):
     """Fitted log10 mean absolute error of Appendix A, Table A2 for one factor combination."""
     t = coef["(Intercept)"]
-    if nu == 1.5:
-        t += coef["smoothness1.5"] + (coef["smoothness1.5:NN4"] if L == 4 else 0.0)
+    if nu != 0.5:
+        sn = "smoothness1" if nu == 1.0 else "smoothness1.5"
+        t += coef[sn] + (coef[f"{sn}:NN4"] if L == 4 else 0.0)
     if L == 4:
         t += coef["NN4"]
     if m != 100:
@@ -480,7 +481,7 @@ def accuracy_mode(a, torch, krig, wl, dev):
             if line.strip() and not line.startswith("#"):
                 k_, v_ = line.split()
                 coef[k_] = float(v_)
-    levels = {"n": (200, 500, 1500), "d07": (0.2, 0.4, 0.8), "nu": (0.5, 1.5), "tau2": (0.01, 0.1, 0.5),
+    levels = {"n": (200, 500, 1500), "d07": (0.2, 0.4, 0.8), "nu": (0.5, 1.0, 1.5), "tau2": (0.01, 0.1, 0.5),
               "L": (2, 4), "m": (100, 350, 500)}
     rng = np.random.default_rng(27)
     cases = []
@@ -528,7 +529,7 @@ def accuracy_mode(a, torch, krig, wl, dev):
         sel = lambda v: np.array([c[key] == v for c in cases_ok])
         return round(float(got_all[sel(lev)].mean() - got_all[sel(base)].mean()), 3)
 
-    effects = {"nu1.5": [effect("nu", 1.5, 0.5), coef["smoothness1.5"]],
+    effects = {"nu1": [effect("nu", 1.0, 0.5), coef["smoothness1"]], "nu1.5": [effect("nu", 1.5, 0.5), coef["smoothness1.5"]],
                "L4": [effect("L", 4, 2), coef["NN4"]],
                "grid350": [effect("m", 350, 100), coef["nGrid350"]], "grid500": [effect("m", 500, 100), coef["nGrid500"]],
                "nugget0.1": [effect("tau2", 0.1, 0.01), coef["nugget0.1"]],
@@ -538,7 +539,7 @@ def accuracy_mode(a, torch, krig, wl, dev):
     res = {"metric": "factorial accuracy study: |log10 mean abs error (rapid vs exact) - Table A2 model|, mean over cases",
            "value": float(np.abs(dev_).mean()), "unit": "decades", "n_gpus": 1, "higher_is_better": False,
            "data": "synthetic", "dtype": "f64",
-           "config": {"workload": "factorial: n {200,500,1500} x correlation-0.7 distance {0.2,0.4,0.8} x nu {0.5,1.5} "
+           "config": {"workload": "factorial: n {200,500,1500} x correlation-0.7 distance {0.2,0.4,0.8} x nu {0.5,1,1.5} "
                                   "x nugget {0.01,0.1,0.5} x L {2,4} x grid {100,350,500}^2 on [0,1]^2, sigma2 = 1; "
                                   f"{a.accuracy_reps} seeded site sets per case; errors at five nodes from centre to corner",
                       "cases": len(cases), "site_sets_per_case": a.accuracy_reps},
@@ -569,7 +570,7 @@ def convergence_mode(a, torch, krig, wl, dev):
     ms = (20, 30, 40, 60, 80, 100, 140)
     out = {}
     t0 = time.perf_counter()
-    for nu in (0.5, 1.5, 2.5):
+    for nu in (0.5, 1.0, 1.5, 2.5):
         lams, inv = [], []
         for m in ms:
             h = 1.0 / (m - 1)
@@ -592,7 +593,7 @@ def convergence_mode(a, torch, krig, wl, dev):
            "unit": "mean |slope - Table 2|", "n_gpus": 1, "higher_is_better": False, "data": "synthetic",
            "dtype": "f64", "config": {"workload": "Figure 5 set-up: [0,1]^2, Matern range 0.25, L = 2, one site "
                                                   "centred in the central box, grids " + ",".join(f"{m}^2" for m in ms),
-                                      "nu": [0.5, 1.5, 2.5]},
+                                      "nu": [0.5, 1.0, 1.5, 2.5]},
            "grids": list(ms), "by_nu": out, "seconds": time.perf_counter() - t0}
     print(json.dumps(res), flush=True)
     return 0

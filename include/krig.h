@@ -19,7 +19,8 @@
  *    index = unpadded index + L.  Sites must satisfy 0 <= (x-x0)/dx <= m1-1 and
  *    0 <= (y-y0)/dy <= m2-1.
  *  - Covariance k(d) = sigma2 * phi(d / range), phi of eq. (Matern1) with
- *    nu in {0.5, 1.5, 2.5}.
+ *    nu in {0.5, 1, 1.5, 2.5} (nu = 1: phi(r) = r K_1(r), evaluated by quadrature to
+ *    about 1e-15 relative error; the others in closed form).
  *  - Neighbour offsets (ox, oy) in {-L+1..L}^2 of the lower-left node of the cell
  *    holding a site, listed ox-major; W[i][m] is the weight of offset m.
  *  - d_* pointers are device memory owned by the caller (contiguous, row-major);
@@ -68,7 +69,7 @@ typedef struct {
 typedef struct {
   double sigma2;        /* process variance (> 0) */
   double range;         /* divides the distance (> 0) */
-  double nu;            /* smoothness: 0.5, 1.5 or 2.5 */
+  double nu;            /* smoothness: 0.5, 1, 1.5 or 2.5 */
   double tau2;          /* nugget variance (>= 0) */
 } krig_matern;
 

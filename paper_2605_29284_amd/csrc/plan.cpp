@@ -478,6 +478,7 @@ int matern_kind(double nu) {
   if (nu == 0.5) return 0;
   if (nu == 1.5) return 1;
   if (nu == 2.5) return 2;
+  if (nu == 1.0) return 3;
   return -1;
 }
 

@@ -118,13 +118,14 @@ def test_factorial_cases_within_a_decade_of_table_a2(krig):
             if line.strip() and not line.startswith("#"):
                 a_, b_ = line.split()
                 coef[a_] = float(b_)
-    r07 = {0.5: -np.log(0.7), 1.5: 1.0973492107034915}  # phi(r07) = 0.7
+    r07 = {0.5: -np.log(0.7), 1.0: 0.7766915961392014, 1.5: 1.0973492107034915}  # phi(r07) = 0.7
     rng = np.random.default_rng(11)
     for nu, L, m, tau2, n, d07 in ((0.5, 2, 100, 0.01, 200, 0.4), (1.5, 4, 350, 0.1, 500, 0.2),
-                                   (1.5, 2, 500, 0.5, 1500, 0.8)):
+                                   (1.5, 2, 500, 0.5, 1500, 0.8), (1.0, 4, 100, 0.1, 500, 0.4)):
         model = coef["(Intercept)"]
-        if nu == 1.5:
-            model += coef["smoothness1.5"] + (coef["smoothness1.5:NN4"] if L == 4 else 0.0)
+        if nu != 0.5:
+            sn = "smoothness1" if nu == 1.0 else "smoothness1.5"
+            model += coef[sn] + (coef[f"{sn}:NN4"] if L == 4 else 0.0)
         model += coef["NN4"] if L == 4 else 0.0
         model += coef[f"nGrid{m}"] if m != 100 else 0.0
         model += coef[f"nugget{tau2}"] if tau2 != 0.01 else 0.0
@@ -171,7 +172,7 @@ def test_table2_convergence_slopes_on_the_gpu(krig):
     # Figure 5 / Table 2 set-up through the GPU: range 0.25, L = 2, one site in the centre of
     # the central box, Lambda = sup over [0,1]^2 (a 121 x 121 lattice plus an 81 x 81 patch
     # around the site) of |k_approx - k|, against the inverse fill distance; slopes within
-    # 0.2 of the paper's (nu = 1 needs the Bessel K1 covariance: not on the GPU)
+    # 0.2 of the paper's, for all four of its smoothness levels
     gold = {}
     with open(os.path.join(os.path.dirname(__file__), "golden", "table2_slopes.txt")) as f:
         for line in f:
@@ -179,7 +180,7 @@ def test_table2_convergence_slopes_on_the_gpu(krig):
                 a_, b_ = line.split()
                 gold[float(a_)] = float(b_)
     one = dev(np.ones((1, 1)))
-    for nu in (0.5, 1.5, 2.5):
+    for nu in (0.5, 1.0, 1.5, 2.5):
         say("table 2 slopes on the GPU, nu", nu)
         errs, inv = [], []
         for m in (20, 30, 40, 60, 80, 100, 140):
@@ -198,3 +199,37 @@ def test_table2_convergence_slopes_on_the_gpu(krig):
             p.close()
         slope = -np.polyfit(np.log10(inv), np.log10(errs), 1)[0]
         assert abs(slope - gold[nu]) < 0.2, (nu, slope, gold[nu], errs)
+
+
+def test_matern_nu1_values(krig):
+    # nu = 1 has no elementary form: phi(r) = r K_1(r) by quadrature on the device, against
+    # the oracle's Bessel evaluation over r from 1e-6 to 60 (exact_at with one unit coefficient)
+    say("Matern nu = 1 values")
+    k = Matern(1.7, 0.3, 1.0, 0.0)
+    site = np.array([[0.5, 0.5]])
+    p = krig.Plan(8, 8, 0.0, 0.0, 1 / 7, 1 / 7, 2, 1.7, 0.3, 1.0, 0.0, site, "f64")
+    r = np.concatenate([[0.0], np.logspace(-6, np.log10(60.0), 400)])
+    ang = np.random.default_rng(12).uniform(0, 2 * np.pi, r.size)
+    pts = site + 0.3 * r[:, None] * np.stack([np.cos(ang), np.sin(ang)], 1)
+    got = host(p.exact_at(dev(np.ones((1, 1))), dev(pts)))[0]
+    ref = k.of_dist(np.hypot(pts[:, 0] - 0.5, pts[:, 1] - 0.5))
+    assert np.all(np.abs(got - ref) <= 1e-14 * np.abs(ref) + 1e-300), float(np.max(np.abs(got - ref) / ref))
+
+
+@pytest.mark.parametrize("dtype", ["f64", "f32"])
+def test_predict_nu1_end_to_end(krig, dtype):
+    # the whole predictor with nu = 1 (lag image, K_N, weights, solve, convolution) against
+    # the oracle's direct form with its own weights
+    from oracle.rapid import RapidPredictor, rapid_direct
+    w = wl.tiny(seed=31, m1=40, m2=36, L=2, n=60, nu=1.0, rho=0.2, tau2=0.01, B=2)
+    g = Grid(w.m1, w.m2, w.x0, w.y0, w.dx, w.dy, w.L)
+    k = Matern(w.sigma2, w.rho, w.nu, w.tau2)
+    rp = RapidPredictor(g, k, w.sites)
+    ek = ExactKriging(w.sites, k)
+    say("predict nu = 1", dtype)
+    p = krig.plan_for(w, dtype)
+    got = host(p.predict(dev(w.y)))
+    for b in range(2):
+        ref = rapid_direct(g, k, rp.cstar(ek.coef(w.y[b]))).reshape(g.m1, g.m2)
+        err = np.abs(got[b] - ref).max() / np.abs(ref).max()
+        assert err < (1e-11 if dtype == "f64" else 1e-6), (b, err)

@@ -478,7 +478,7 @@ def test_error_paths(krig):
         krig.Plan(10, 10, 0.0, 0.0, 1 / 9, 1 / 9, 2, 1.0, 0.3, 1.5, 0.0, s)
     assert e.value.status == -2
     with pytest.raises(krig.KrigError) as e:
-        krig.Plan(10, 10, 0.0, 0.0, 1 / 9, 1 / 9, 2, 1.0, 0.3, 1.0, 0.0, w.sites)
+        krig.Plan(10, 10, 0.0, 0.0, 1 / 9, 1 / 9, 2, 1.0, 0.3, 2.0, 0.0, w.sites)  # no form for nu = 2
     assert e.value.status == -7
     dup = np.concatenate([w.sites, w.sites[:1]])
     with pytest.raises(krig.KrigError) as e:
