@@ -459,9 +459,9 @@ def table_a2_model(coef, nu, L, m, tau2):
     t = coef["(Intercept)"]
     if nu != 0.5:
         sn = "smoothness1" if nu == 1.0 else "smoothness1.5"
-        t += coef[sn] + (coef[f"{sn}:NN4"] if L == 4 else 0.0)
-    if L == 4:
-        t += coef["NN4"]
+        t += coef[sn] + (coef[f"{sn}:NN{L}"] if L != 2 else 0.0)
+    if L != 2:
+        t += coef[f"NN{L}"]
     if m != 100:
         t += coef[f"nGrid{m}"]
     if tau2 != 0.01:
@@ -482,7 +482,7 @@ def accuracy_mode(a, torch, krig, wl, dev):
                 k_, v_ = line.split()
                 coef[k_] = float(v_)
     levels = {"n": (200, 500, 1500), "d07": (0.2, 0.4, 0.8), "nu": (0.5, 1.0, 1.5), "tau2": (0.01, 0.1, 0.5),
-              "L": (2, 4), "m": (100, 350, 500)}
+              "L": (2, 4, 8), "m": (100, 350, 500)}
     rng = np.random.default_rng(27)
     cases = []
     t0 = time.perf_counter()
@@ -530,7 +530,7 @@ def accuracy_mode(a, torch, krig, wl, dev):
         return round(float(got_all[sel(lev)].mean() - got_all[sel(base)].mean()), 3)
 
     effects = {"nu1": [effect("nu", 1.0, 0.5), coef["smoothness1"]], "nu1.5": [effect("nu", 1.5, 0.5), coef["smoothness1.5"]],
-               "L4": [effect("L", 4, 2), coef["NN4"]],
+               "L4": [effect("L", 4, 2), coef["NN4"]], "L8": [effect("L", 8, 2), coef["NN8"]],
                "grid350": [effect("m", 350, 100), coef["nGrid350"]], "grid500": [effect("m", 500, 100), coef["nGrid500"]],
                "nugget0.1": [effect("tau2", 0.1, 0.01), coef["nugget0.1"]],
                "nugget0.5": [effect("tau2", 0.5, 0.01), coef["nugget0.5"]],
@@ -540,7 +540,7 @@ def accuracy_mode(a, torch, krig, wl, dev):
            "value": float(np.abs(dev_).mean()), "unit": "decades", "n_gpus": 1, "higher_is_better": False,
            "data": "synthetic", "dtype": "f64",
            "config": {"workload": "factorial: n {200,500,1500} x correlation-0.7 distance {0.2,0.4,0.8} x nu {0.5,1,1.5} "
-                                  "x nugget {0.01,0.1,0.5} x L {2,4} x grid {100,350,500}^2 on [0,1]^2, sigma2 = 1; "
+                                  "x nugget {0.01,0.1,0.5} x L {2,4,8} x grid {100,350,500}^2 on [0,1]^2, sigma2 = 1; "
                                   f"{a.accuracy_reps} seeded site sets per case; errors at five nodes from centre to corner",
                       "cases": len(cases), "site_sets_per_case": a.accuracy_reps},
            "seconds": secs, "problems_per_s": len(cases) * a.accuracy_reps / secs,

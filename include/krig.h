@@ -63,7 +63,7 @@ typedef struct {
   int32_t m1, m2;       /* prediction grid nodes per axis (>= 2) */
   double x0, y0;        /* first node */
   double dx, dy;        /* spacings (> 0) */
-  int32_t L;            /* neighbour order, M = (2L)^2, 1 <= L <= 4 */
+  int32_t L;            /* neighbour order, M = (2L)^2, 1 <= L <= 8 */
 } krig_grid;
 
 typedef struct {

@@ -378,6 +378,40 @@ int ensure_ws_uk(krig_plan p, int B) {
   return KRIG_OK;
 }
 
+// K_N factor and inverse factor for more than 64 neighbours (L > 4): the blocked Cholesky of
+// the kriging system applied to K_N, with the same single jitter retry as the one-tile
+// kernel (1e-14 sigma2 M on the diagonal) decided on the host; the outcome goes to
+// d_status[0] as the one-tile kernel reports it (0 clean, 1 jitter used, -pivot failed).
+int kn_factor_large(krig_plan p) {
+  const int M = p->M;
+  double *A = nullptr, *Dv = nullptr, *wk = nullptr;
+  int r;
+  if ((r = dalloc(p, &A, (size_t)M * M)) != KRIG_OK) return r;
+  if ((r = dalloc(p, &Dv, (size_t)((M + 63) / 64) * 4096)) != KRIG_OK) return r;
+  if ((r = dalloc(p, &wk, (size_t)64 * M)) != KRIG_OK) return r;
+  int status = 0;
+  for (int attempt = 0; attempt < 2; ++attempt) {
+    const double jit = attempt ? 1e-14 * p->mt.sigma2 * M : 0.0;
+    KRIG_TRY(kn_assemble(p->g, p->mt, attempt ? nullptr : p->KN, A, jit, p->st));
+    KRIG_TRY(hipMemsetAsync(p->d_status + 2, 0, sizeof(int), p->st));
+    KRIG_TRY(cholesky_and_inverse(A, M, M, p->LinvN, Dv, wk, p->d_status + 2, p->st));
+    int piv = 0;
+    KRIG_TRY(hipMemcpyAsync(&piv, p->d_status + 2, sizeof(int), hipMemcpyDeviceToHost, p->st));
+    KRIG_TRY(hipStreamSynchronize(p->st));
+    if (piv == 0) {
+      status = attempt;
+      break;
+    }
+    status = -piv;
+  }
+  KRIG_TRY(hipMemcpyAsync(p->d_status, &status, sizeof(int), hipMemcpyHostToDevice, p->st));
+  KRIG_TRY(hipStreamSynchronize(p->st));
+  dfree(p, A);
+  dfree(p, Dv);
+  dfree(p, wk);
+  return KRIG_OK;
+}
+
 int do_solve(krig_plan p, int B, const double* y, double* alpha) {
   StageTimer t(p, KRIG_STAGE_SOLVE);
   KRIG_TRY(tri_apply(p->Linv, p->ldL, p->n, 0, y, p->n, p->tmpv, p->ldv, B, p->tripart, p->st));
@@ -683,7 +717,7 @@ int krig_plan_create(krig_plan* out, const krig_grid* g, const krig_matern* k, i
   if (!out) return KRIG_EINVAL;
   *out = nullptr;
   if (!g || !k || !h_sites || n < 1) return KRIG_EINVAL;
-  if (g->m1 < 2 || g->m2 < 2 || g->L < 1 || g->L > 4 || !(g->dx > 0) || !(g->dy > 0)) return KRIG_EINVAL;
+  if (g->m1 < 2 || g->m2 < 2 || g->L < 1 || g->L > 8 || !(g->dx > 0) || !(g->dy > 0)) return KRIG_EINVAL;
   if (dtype != KRIG_F32 && dtype != KRIG_F64) return KRIG_EINVAL;
   if (!(k->sigma2 > 0) || !(k->range > 0) || !(k->tau2 >= 0)) return KRIG_EINVAL;
   const int kind = matern_kind(k->nu);
@@ -775,7 +809,10 @@ int krig_plan_create(krig_plan* out, const krig_grid* g, const krig_matern* k, i
   CK(dalloc(p, &p->kvec, (size_t)n * M));
   CK(dalloc(p, &p->W, (size_t)n * M));
   CK(dalloc(p, &p->Wt, (size_t)n * M));
-  CKH(kn_factor(p->g, p->mt, p->KN, p->LinvN, p->d_status, p->st));
+  if (M <= 64)
+    CKH(kn_factor(p->g, p->mt, p->KN, p->LinvN, p->d_status, p->st));
+  else
+    CK(kn_factor_large(p));
   CKH(site_kvec(p->g, p->mt, p->sites, n, p->anchor, p->kvec, p->st));
   {
     GemmArgs ga{};

@@ -28,6 +28,9 @@ hipError_t copy2d_f64_to(const double* src, int64_t lds_, void* dst, int64_t ldd
 // status = -(pivot+1) if the retry fails too.
 hipError_t kn_factor(const GridDev& g, const MaternDev& mt, double* KN, double* LinvN, int* status,
                      hipStream_t st);
+// K_N for more than 64 neighbours (L > 4), for the blocked factorisation: KN (may be NULL)
+// receives K_N, A receives K_N + jit I (both M x M row-major).
+hipError_t kn_assemble(const GridDev& g, const MaternDev& mt, double* KN, double* A, double jit, hipStream_t st);
 // Step 3: anchor cell (i0, j0) and k_i (n x M) of every site; sites [n][2] FP64.
 hipError_t site_kvec(const GridDev& g, const MaternDev& mt, const double* sites, int n, int32_t* anchor,
                      double* kvec, hipStream_t st);

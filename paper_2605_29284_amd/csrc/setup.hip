@@ -142,8 +142,28 @@ __global__ void __launch_bounds__(256) k_kn_factor(GridDev g, MaternDev mt, doub
   }
 }
 
+__global__ void k_kn_assemble(GridDev g, MaternDev mt, double* __restrict__ KN, double* __restrict__ A, double jit) {
+  const int M = g.M;
+  const int e = blockIdx.x * blockDim.x + threadIdx.x;
+  if (e >= M * M) return;
+  const int p = e / M, q = e % M;
+  int oxp, oyp, oxq, oyq;
+  offset_of(p, g.L, oxp, oyp);
+  offset_of(q, g.L, oxq, oyq);
+  const double hx = (double)(oxp - oxq) * g.dx, hy = (double)(oyp - oyq) * g.dy;
+  const double v = matern_cov(sqrt(hx * hx + hy * hy), mt);
+  if (KN) KN[e] = v;
+  A[e] = p == q ? v + jit : v;
+}
+
+hipError_t kn_assemble(const GridDev& g, const MaternDev& mt, double* KN, double* A, double jit, hipStream_t st) {
+  hipLaunchKernelGGL(k_kn_assemble, dim3(nblk((int64_t)g.M * g.M)), dim3(256), 0, st, g, mt, KN, A, jit);
+  return hipGetLastError();
+}
+
 hipError_t kn_factor(const GridDev& g, const MaternDev& mt, double* KN, double* LinvN, int* status,
                      hipStream_t st) {
+  if (g.M > 64) return hipErrorInvalidValue;  // one LDS tile; larger K_N go through the blocked path
   hipLaunchKernelGGL(k_kn_factor, dim3(1), dim3(256), 0, st, g, mt, KN, LinvN, status);
   return hipGetLastError();
 }
@@ -435,6 +455,17 @@ __global__ void __launch_bounds__(256) k_gather_sites(GridDev g, const int32_t* 
 }
 
 template <typename TS>
+__global__ void __launch_bounds__(256) k_gather_generic(GridDev g, const int32_t* __restrict__ anchor,
+                                                        const double* __restrict__ Wt, int n,
+                                                        const TS* __restrict__ img, int64_t img_fs, int64_t ldi,
+                                                        double* __restrict__ out, int64_t out_fs) {
+  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  const int b = blockIdx.y;
+  if (i >= n) return;
+  out[(int64_t)b * out_fs + i] = gather_one<TS>(g, anchor, Wt, n, i, img + (int64_t)b * img_fs, ldi);
+}
+
+template <typename TS>
 hipError_t gather_launch(const GridDev& g, const int32_t* anchor, const double* Wt, int n, const TS* img,
                          int64_t img_fs, int64_t ldi, int B, double* out, int64_t out_fs, hipStream_t st) {
   dim3 grid((unsigned)((4 * (int64_t)n + 255) / 256), B);
@@ -443,7 +474,10 @@ hipError_t gather_launch(const GridDev& g, const int32_t* anchor, const double* 
     case 2: hipLaunchKernelGGL((k_gather_sites<TS, 2>), grid, dim3(256), 0, st, g, anchor, Wt, n, img, img_fs, ldi, out, out_fs); break;
     case 3: hipLaunchKernelGGL((k_gather_sites<TS, 3>), grid, dim3(256), 0, st, g, anchor, Wt, n, img, img_fs, ldi, out, out_fs); break;
     case 4: hipLaunchKernelGGL((k_gather_sites<TS, 4>), grid, dim3(256), 0, st, g, anchor, Wt, n, img, img_fs, ldi, out, out_fs); break;
-    default: return hipErrorInvalidValue;
+    default:  // L > 4: one thread per site and field, neighbours sixteen at a time
+      hipLaunchKernelGGL(k_gather_generic<TS>, dim3((unsigned)((n + 255) / 256), B), dim3(256), 0, st, g, anchor, Wt,
+                         n, img, img_fs, ldi, out, out_fs);
+      break;
   }
   return hipGetLastError();
 }

@@ -268,6 +268,34 @@ def test_adjoint_grad_batch_full_size(krig):
     assert relmax(dlag, ref_dlag) < 1e-6
 
 
+@pytest.mark.parametrize("L, nu", [(5, 0.5), (8, 0.5), (8, 1.5)])
+def test_large_neighbourhoods(krig, L, nu):
+    # L > 4 (M = 100 and 256 neighbours): K_N through the blocked factorisation with its host
+    # jitter rule, the generic gather in the adjoint
+    w = wl.tiny(seed=40 + L, m1=48, m2=44, L=L, n=50, nu=nu, rho=0.2, tau2=0.01, B=2)
+    g, k, rp, ek = oracle_of(w)
+    say("large neighbourhood L =", L, "nu =", nu)
+    p = krig.plan_for(w, "f64")
+    anc, W = p.weights()
+    _, _, u, v = site_cells(g, w.sites)
+    res = np.abs(host(W) @ kn_matrix(g, k) - kvecs(g, k, u, v)).max()
+    assert res < 1e-8, res  # eq. weights, with the GPU's own K_N factor
+    p.set_weights(dev(np.stack([rp.i0, rp.j0], 1), torch.int32), dev(rp.W))
+    alpha = ek.coef(w.y)
+    y = host(p.convolve(dev(alpha)))
+    lag = lag_quadrant(g, k)
+    gup = np.random.default_rng(L).standard_normal((2, g.m1, g.m2))
+    dy, _ = p.adjoint(dev(gup), alpha=dev(alpha), want_dlag=False)
+    dy = host(dy)
+    for b in range(2):
+        cimg = rp.cstar(alpha[b])
+        ref = rapid_direct(g, k, cimg).reshape(g.m1, g.m2)
+        cancel = np.abs(cimg).sum() / np.abs(ref).max()
+        assert relmax(y[b], ref) < 1e-12 * max(1.0, cancel / 2e4), b
+        ref_dy = ek.coef(grad_coef(rp.A, corr_image_direct(g, lag, gup[b])))
+        assert relmax(dy[b], ref_dy) < 1e-10, b
+
+
 def test_grad_batch_in_the_benchmark_configuration(krig):
     # the benchmark's step at its full size and launch configuration: 16 fields, FP32 plan,
     # autotuned shapes, loss sum(m * yhat^2); every output against the oracle (same weights)
