@@ -449,8 +449,8 @@ def exact_cpu_baseline(w):
             "host": host_cpu()}
 
 
-# phi(r) = 0.7 for the closed-form smoothness levels: the factorial study fixes the
-# distance at which the correlation falls to 0.7, so range = that distance / R07[nu]
+# phi(r) = 0.7 for the smoothness levels of the factorial study (r K_1(r) for nu = 1): the
+# study fixes the distance at which the correlation falls to 0.7, so range = that distance / R07[nu]
 R07 = {0.5: 0.3566749439387324, 1.0: 0.7766915961392014, 1.5: 1.0973492107034915}
 
 
