@@ -109,6 +109,25 @@ def test_solve_matches_cholesky(krig, small, paper, which):
     assert relmax(a, ref) < 10 * cond * np.finfo(float).eps
 
 
+@pytest.mark.parametrize("n,B", [(1, 1), (37, 17), (1024, 3), (4096, 17), (4097, 2), (8200, 17)])
+def test_solve_sizes(krig, n, B):
+    """The split triangular products at one and four chunk groups per wave (below and from
+    n = 8192), a single site, ragged row tiles, field groups of 16 and an input pitch that is
+    not a multiple of 4 (n = 37, 4097).  With tau^2 = 0.5 and sigma^2 = 1, cond(M) <= (n + 0.5)
+    / 0.5 (Gershgorin), so the bound needs no SVD."""
+    say("solve sizes", n, B)
+    rng = np.random.default_rng(n)
+    sites = rng.uniform(0.0, 1.0, (n, 2))
+    k = Matern(1.0, 0.1, 1.5, 0.5)
+    p = krig.Plan(128, 128, 0.0, 0.0, 1 / 127, 1 / 127, 2, 1.0, 0.1, 1.5, 0.5, sites, "f64")
+    y = rng.standard_normal((B, n))
+    a = host(p.solve(dev(y)))
+    p.close()
+    ref = ExactKriging(sites, k).coef(y)
+    cond = (n + 0.5) / 0.5
+    assert relmax(a, ref) < 10 * cond * np.finfo(float).eps
+
+
 # ------------------------------------------------------------------------------ scatter (Steps 5-6)
 @pytest.mark.parametrize("dtype", ["f64", "f32"])
 def test_scatter_identical_weights(krig, paper, dtype):
