@@ -204,6 +204,10 @@ int krig_predict(krig_plan p, int32_t B, const double *d_y, const void *d_lag, v
  * in FP64 arithmetic and storage for both dtypes (dy is (K + tau^2 I)^{-1} applied to
  * the gathered correlation, which amplifies any FP32 rounding of that image by the
  * system's condition number); only d_g and d_dlag are in dt.
+ * With both d_dy and d_dlag given (and stage timing off), the lag-gradient tail runs on a
+ * second stream that the plan owns, forked from and joined back into the plan's stream
+ * with events inside the call (also when that stream is being captured into a graph):
+ * callers see the usual ordering on the plan's stream.
  */
 int krig_predict_adjoint(krig_plan p, int32_t B, const void *d_g, const double *d_alpha,
                          const void *d_saved, const void *d_lag, double *d_dy, void *d_dlag);

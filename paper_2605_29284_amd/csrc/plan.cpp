@@ -123,6 +123,10 @@ struct krig_plan_s {
   bool timing = false;
   int batch_refs = 0;  // recorded batches (graphs) holding pointers into the workspaces
   std::vector<hipEvent_t> ev_pool;
+  // second stream of the adjoint (lag-gradient tail beside the gather and solve), with its
+  // fork and join events; created with the adjoint workspaces
+  hipStream_t aux = nullptr;
+  hipEvent_t ev_fork = nullptr, ev_join = nullptr;
   std::vector<std::pair<hipEvent_t, hipEvent_t>> ev_pending[KRIG_STAGE_COUNT];
   std::vector<void*> allocs;
 };
@@ -333,6 +337,11 @@ int ensure_ws(krig_plan p, int B) {
 
 // adjoint workspaces for B fields
 int ensure_ws_adj(krig_plan p, int B) {
+  if (!p->aux) {  // default priority, no implicit synchronisation with the null stream
+    KRIG_TRY(hipStreamCreateWithFlags(&p->aux, hipStreamNonBlocking));
+    KRIG_TRY(hipEventCreateWithFlags(&p->ev_fork, hipEventDisableTiming));
+    KRIG_TRY(hipEventCreateWithFlags(&p->ev_join, hipEventDisableTiming));
+  }
   if (B <= p->wsB_adj) return KRIG_OK;
   if (p->batch_refs > 0) return KRIG_EINVAL;
   void* olds[] = {p->SG, p->SA, p->img, p->part};
@@ -525,6 +534,12 @@ void destroy_all(krig_plan p) {
       (void)hipEventDestroy(pr.second);
     }
   for (hipEvent_t e : p->ev_pool) (void)hipEventDestroy(e);
+  if (p->aux) {
+    (void)hipStreamSynchronize(p->aux);
+    (void)hipStreamDestroy(p->aux);
+  }
+  if (p->ev_fork) (void)hipEventDestroy(p->ev_fork);
+  if (p->ev_join) (void)hipEventDestroy(p->ev_join);
   for (void* q : p->allocs) (void)hipFree(q);
   p->allocs.clear();
   delete p;
@@ -1008,6 +1023,42 @@ int krig_predict(krig_plan p, int32_t B, const double* d_y, const void* d_lag, v
   return do_convolve(p, B, al, filt, d_yhat, d_saved ? d_saved : p->S1, nullptr, 0, 0);
 }
 
+// Lag-gradient tail: inverse transform of sum_b G_b conj(C_b) from the partial spectra
+// written by the adjoint's column pass (G groups), keeping lags -(n-1)..(n-1), then the
+// rows and the fold of the sign images into d_dlag.  Reads part, writes XC and d_dlag.
+int dlag_tail(krig_plan p, int ngroups, void* d_dlag, hipStream_t st) {
+  StageTimer t(p, KRIG_STAGE_DLAG_TAIL);
+  // the columns: inverse transform of the summed partial spectra, lags -(n-1)..(n-1)
+  ColsArgs ci{};
+  ci.H2 = p->H2;
+  ci.in = p->part;
+  ci.in_fs = (int64_t)p->H2 * p->F1;
+  ci.in_ld = p->F1;
+  ci.G = ngroups;
+  ci.out = p->XC;
+  ci.out_ld = p->ldX;
+  ci.rows = Window{0, p->n1l, p->F1 - p->n1l + 1, p->n1l - 1};
+  ci.twF = p->tw1_64;
+  ci.twI = p->tw1_64;
+  ci.NL = p->nl_cols64;
+  KRIG_TRY(set1(p).inv_sum64(ci, 1, st));
+  RowsC2RArgs oc{};
+  oc.nrows = p->n1l;
+  oc.H2 = p->H2;
+  oc.in = p->XC;
+  oc.in_fs = 0;
+  oc.in_ld = p->ldX;
+  oc.out = d_dlag;
+  oc.out_fs = 0;
+  oc.ldo = p->n2l;
+  oc.cols = Window{0, p->n2l, 0, 0};
+  oc.twF = p->tw2_64;
+  oc.scale = 1.0 / ((double)p->F1 * p->F2);
+  oc.NL = p->nl_rows64;
+  KRIG_TRY((is32(p) ? set2(p).c2r_fold32 : set2(p).c2r_fold64)(oc, 1, st));
+  return KRIG_OK;
+}
+
 int krig_predict_adjoint(krig_plan p, int32_t B, const void* d_g, const double* d_alpha, const void* d_saved,
                          const void* d_lag, double* d_dy, void* d_dlag) {
   if (!p || B < 1 || B > 65535 || !d_g) return KRIG_EINVAL;
@@ -1095,6 +1146,25 @@ int krig_predict_adjoint(krig_plan p, int32_t B, const void* d_g, const double* 
     StageTimer t(p, KRIG_STAGE_ADJ_COLS);
     KRIG_TRY(set1(p).conv64(c, B, p->st));
   }
+  // The lag-gradient tail does not depend on the gather and solve below (they read SA,
+  // img, alpha, tmpv and tripart): with both outputs asked for, it runs on the plan's
+  // second stream beside them, filling the compute units the latency-bound solve leaves
+  // idle, and joins the plan's stream before this call's work ends.
+  const bool fork = d_dlag && d_dy && !p->timing;
+  struct Join {
+    krig_plan p = nullptr;
+    ~Join() {
+      if (p) (void)hipStreamWaitEvent(p->st, p->ev_join, 0);
+    }
+  } join;
+  if (fork) {
+    KRIG_TRY(hipEventRecord(p->ev_fork, p->st));
+    KRIG_TRY(hipStreamWaitEvent(p->aux, p->ev_fork, 0));
+    const int rd = dlag_tail(p, ngroups, d_dlag, p->aux);
+    KRIG_TRY(hipEventRecord(p->ev_join, p->aux));
+    join.p = p;
+    if (rd != KRIG_OK) return rd;
+  }
   // rows back to the padded image
   RowsC2RArgs o{};
   o.nrows = p->P1;
@@ -1121,37 +1191,7 @@ int krig_predict_adjoint(krig_plan p, int32_t B, const void* d_g, const double* 
     }
     if ((r = do_solve(p, B, p->alpha, d_dy)) != KRIG_OK) return r;
   }
-  if (d_dlag) {
-    StageTimer t(p, KRIG_STAGE_DLAG_TAIL);
-    // inverse transform of sum_b G_b conj(C_b), keeping lags -(n-1)..(n-1)
-    ColsArgs ci{};
-    ci.H2 = p->H2;
-    ci.in = p->part;
-    ci.in_fs = (int64_t)p->H2 * p->F1;
-    ci.in_ld = p->F1;
-    ci.G = ngroups;
-    ci.out = p->XC;
-    ci.out_ld = p->ldX;
-    ci.rows = Window{0, p->n1l, p->F1 - p->n1l + 1, p->n1l - 1};
-    ci.twF = p->tw1_64;
-    ci.twI = p->tw1_64;
-    ci.NL = p->nl_cols64;
-    KRIG_TRY(set1(p).inv_sum64(ci, 1, p->st));
-    RowsC2RArgs oc{};
-    oc.nrows = p->n1l;
-    oc.H2 = p->H2;
-    oc.in = p->XC;
-    oc.in_fs = 0;
-    oc.in_ld = p->ldX;
-    oc.out = d_dlag;
-    oc.out_fs = 0;
-    oc.ldo = p->n2l;
-    oc.cols = Window{0, p->n2l, 0, 0};
-    oc.twF = p->tw2_64;
-    oc.scale = 1.0 / ((double)p->F1 * p->F2);
-    oc.NL = p->nl_rows64;
-    KRIG_TRY((is32(p) ? set2(p).c2r_fold32 : set2(p).c2r_fold64)(oc, 1, p->st));
-  }
+  if (d_dlag && !fork) return dlag_tail(p, ngroups, d_dlag, p->st);
   return KRIG_OK;
 }
 
