@@ -345,7 +345,9 @@ def test_grad_batch_in_the_benchmark_configuration(krig):
 @pytest.mark.parametrize("dtype", ["f32", "f64"])
 def test_adjoint_repeatable_with_stage_timing(krig, dtype):
     """Stage timing only brackets the launches with events: dy and dlag must agree bit
-    for bit with timing on and off, on repeated and back-to-back calls too."""
+    for bit with timing on and off, on repeated and back-to-back calls too.  With timing
+    off and both outputs asked for, the lag-gradient tail runs on the plan's second stream;
+    the single-output calls and the timed call run on one stream."""
     w = wl.grad_batch(B=4)
     say("adjoint with and without stage timing", dtype)
     p = krig.plan_for(w, dtype)
@@ -365,6 +367,9 @@ def test_adjoint_repeatable_with_stage_timing(krig, dtype):
     outs = [p.adjoint(gup, alpha=alpha, saved=saved) for _ in range(3)]
     for dy, dlag in outs:
         assert np.array_equal(host(dy), ref[0]) and np.array_equal(host(dlag), ref[1])
+    dy_only, _ = p.adjoint(gup, alpha=alpha, saved=saved, want_dlag=False)
+    _, dlag_only = p.adjoint(gup, alpha=alpha, saved=saved, want_dy=False)
+    assert np.array_equal(host(dy_only), ref[0]) and np.array_equal(host(dlag_only), ref[1])
 
 
 def test_adjoint_finite_differences_f64(krig):
