@@ -294,6 +294,45 @@ def nonstat_mode(a, torch, krig, wl, dev):
     return 0
 
 
+def csim_mode(a, torch, krig, wl, dev):
+    """Batched conditional simulation (krig_csim): R = 256 realisations on a 512 x 512 grid,
+    n = 5000 uniform sites, Matern nu = 1.5, range 0.1, nugget 0.01, L = 4.  Each call draws
+    R unconditional fields by circulant embedding, reads them at the sites through the
+    neighbour weights and krigs the residuals.  Plan creation and one call per step are timed
+    for the FP32 and FP64 plans.  Prints one JSON line."""
+    w = wl.csim_batch(R=256)
+    R, seed = w.extra["R"], w.extra["ce_seed"]
+    y = torch.as_tensor(w.y[0], dtype=torch.float64, device=dev)
+    per = {}
+    for dtype in ("f32", "f64"):
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        p = krig.plan_for(w, dtype)
+        torch.cuda.synchronize()
+        plan_ms = (time.perf_counter() - t0) * 1e3
+        for _ in range(min(a.warmup, 5)):
+            p.csim(R, seed, y)
+        s, e = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        torch.cuda.synchronize()
+        s.record()
+        for _ in range(a.steps):
+            p.csim(R, seed, y)
+        e.record()
+        torch.cuda.synchronize()
+        per[dtype] = {"plan_ms": plan_ms, "ms_per_call": s.elapsed_time(e) / a.steps}
+        p.close()
+    ms = per["f32"]["ms_per_call"]
+    res = {"metric": "conditional simulation: realisation grid values/s (R fields per call)",
+           "value": R * w.m1 * w.m2 / (ms * 1e-3), "unit": "grid values/s", "n_gpus": 1, "steps": a.steps,
+           "warmup": min(a.warmup, 5), "ms_per_step": ms, "higher_is_better": True,
+           "scaling": "weak", "vs_baseline": None, "dtype": "f64", "io_dtype": "f32", "data": "synthetic",
+           "config": {"workload": "csim: R=256 realisations, 512x512 grid on [0,1]^2, n=5000 uniform sites, "
+                                  "Matern nu=1.5 range 0.1 nugget 0.01, L=4 (M=64)", "R": R},
+           "per_dtype": per}
+    print(json.dumps(res), flush=True)
+    return 0
+
+
 def mixture_mode(a, torch, krig, wl, dev):
     """Nonstationary mixture (krig_mixture) on the paper-sized field: two stationary
     components (the field's own Matern nu = 2.5, range 0.3 and a nu = 1.5, range 0.15 one)
@@ -636,6 +675,7 @@ def main(argv=None):
     ap.add_argument("--interp", action="store_true", help="time off-grid predictions (krig_interp) instead")
     ap.add_argument("--nonstat", action="store_true", help="time weights from caller k_i (krig_set_kvec) instead")
     ap.add_argument("--mixture", action="store_true", help="time a two-component nonstationary mixture instead")
+    ap.add_argument("--csim", action="store_true", help="time batched conditional simulation (R = 256) instead")
     ap.add_argument("--universal", action="store_true", help="time universal kriging with a GLS trend instead")
     ap.add_argument("--exact", action="store_true", help="time the rapid predictor against exact kriging instead")
     ap.add_argument("--accuracy", action="store_true",
@@ -679,6 +719,8 @@ def main(argv=None):
         return nonstat_mode(a, torch, krig, wl, dev)
     if a.mixture:
         return mixture_mode(a, torch, krig, wl, dev)
+    if a.csim:
+        return csim_mode(a, torch, krig, wl, dev)
     if a.universal:
         return universal_mode(a, torch, krig, wl, dev)
     if a.exact:
