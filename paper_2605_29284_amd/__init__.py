@@ -276,10 +276,12 @@ class Plan:
             self._t(saved, self.torch.float64, (B, self.saved_per_field, 2), "saved")
         dy = None
         if want_dy:
-            dy = self.empty(B, self.n, dtype=self.torch.float64) if dy_out is None else dy_out
+            dy = (self.empty(B, self.n, dtype=self.torch.float64) if dy_out is None
+                  else self._t(dy_out, self.torch.float64, (B, self.n), "dy_out"))
         dlag = None
         if want_dlag:
-            dlag = self.empty(self.m1 + self.L, self.m2 + self.L) if dlag_out is None else dlag_out
+            shape = (self.m1 + self.L, self.m2 + self.L)
+            dlag = self.empty(*shape) if dlag_out is None else self._t(dlag_out, self.tdtype, shape, "dlag_out")
         self._stream()
         _check(self.lib.krig_predict_adjoint(self.h, B, g.data_ptr(), _ptr(alpha), _ptr(saved), self._lag_ptr(lag),
                                              _ptr(dy), _ptr(dlag)), "krig_predict_adjoint")

@@ -125,21 +125,27 @@ typedef hipError_t (*launch_rows_c2r_t)(const RowsC2RArgs&, int B, hipStream_t);
 typedef hipError_t (*launch_rows_ce_t)(const RowsCEArgs&, int npairs, hipStream_t);
 
 // Kernels for one transform length.  Arithmetic is FP64 in every role of the
-// prediction and its adjoint (the FP32 forms differ only in the type of the caller's
-// arrays: lag, upstream gradient, predictions, lag gradient); only the conditional-
-// simulation sampler has an FP32-arithmetic form.
+// prediction and its adjoint.  FP64 plans store FP64 spectra between the passes; FP32
+// plans store FP32 spectra where one rounding stays far below the FP32 bounds (the
+// upstream gradient's row spectra, the lag-gradient partials) and FP64 where it does not
+// (the prediction's spectra, the adjoint's correlation spectra; spec_bytes in plan.cpp).
+// Only the conditional-simulation sampler has an FP32-arithmetic form.
 struct FftSet {
   launch_rows_r2c_t r2c_csr;        // scatter + forward rows, FP64 -> FP64 spectra
-  launch_rows_r2c_t r2c_dense_f32;  // FP32 rows (upstream gradient) -> FP64 spectra
+  launch_rows_r2c_t r2c_dense_f32;  // FP32 rows (upstream gradient) -> FP32 spectra
   launch_rows_r2c_t r2c_dense_f64;  // FP64 rows -> FP64 spectra
   launch_rows_r2c_t r2c_lag;        // even-reflected lag quadrant, FP64
   launch_cols_t conv64;             // all FP64
+  launch_cols_t conv_adj_f;         // FP32 in -> FP64 out (adjoint correlation, FP32 plans)
+  launch_cols_t conv_dlag_f;        // the lag-gradient form of FP32 plans: FP32 G, FP64 saved
+                                    // spectra of c*, FP64 correlation, FP32 partials
   launch_cols_t conv_dlag64;        // all FP64, plus sum_b G_b conj(C_b) partial spectra (NL fields
                                     // of one column per block, one partial per block row)
   launch_cols_t fwd_real64;         // forward columns, store Re * scale (FP64)
   launch_cols_t inv_sum64;          // inverse columns of a sum of partial spectra (FP64)
-  launch_rows_c2r_t c2r64_32;       // inverse rows, FP64 arithmetic, FP32 output
+  launch_cols_t inv_sum_f;          //   ... of FP32 partials
   launch_rows_c2r_t c2r64;          // inverse rows, FP64
+  launch_rows_c2r_t c2r64_32;       // inverse rows, FP64 spectra -> FP32 output
   launch_rows_c2r_t c2r_fold32;     // inverse rows of the compact correlation, sign images
   launch_rows_c2r_t c2r_fold64;     //   folded, FP64 arithmetic -> FP32 / FP64 lag gradient
   launch_rows_r2c_t r2c_cov;        // covariance on the embedding torus, FP64

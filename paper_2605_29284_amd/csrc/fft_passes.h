@@ -3,7 +3,8 @@
 // per transform length F = R1 * R2 * R3 (factorisation and register layouts: see
 // fft_args.h).
 //
-// Roles (TC/TF/TI = arithmetic precision, TS/TSI/TSO/TO = storage precision):
+// Roles (TC/TF/TI = arithmetic precision; TS, TO and the column passes' Stor set =
+// storage forms, see spec_io.h):
 //  k_rows_r2c   forward transform of real rows, two rows per complex line
 //               ("two-for-one"); sources: the CSR scatter of alpha_i w_im (Steps
 //               5-6), dense rows (the adjoint's input), the even reflection of the
@@ -31,6 +32,7 @@
 #include "fft_reg.h"
 #include "matern_dev.h"
 #include "philox_dev.h"
+#include "spec_io.h"
 
 namespace krig {
 
@@ -455,11 +457,11 @@ KRIG_ROW_KERNEL k_rows_r2c(RowsR2CArgs a) {
     }
   }
   __syncthreads();
-  cx<TS>* o = reinterpret_cast<cx<TS>*>(a.out) + (int64_t)b * a.out_fs;
+  const Spec<TS> o = Spec<TS>::field(a.out, a.out_fs, b);
   // element idx = k R2b + rl of the transpose goes to thread idx mod blockDim (NT NL)
   for (TWalk<G::NT> e(threadIdx.x, NL); e.k < a.H2; e.next()) {
     const int row = row0 + e.rl;
-    if (row < a.nrows) o[(int64_t)e.k * a.out_ld + row] = ccast<TS>(T[tpos(e.k, e.rl, R2b)]);
+    if (row < a.nrows) o.st((int64_t)e.k * a.out_ld + row, T[tpos(e.k, e.rl, R2b)]);
   }
 }
 
@@ -467,7 +469,7 @@ KRIG_ROW_KERNEL k_rows_r2c(RowsR2CArgs a) {
 // column kernels (contiguous columns of frequency-major spectra)
 // ----------------------------------------------------------------------------------------
 template <typename TC, typename TS, int R1, int R2, int R3>
-__device__ __forceinline__ void col_fwd(const cx<TS>* src, int in_off, int in_cnt, bool colok, int s,
+__device__ __forceinline__ void col_fwd(const Spec<TS> src, int in_off, int in_cnt, bool colok, int s,
                                         cx<TC>* L, const TwB<TC>& tb, cx<TC> (&w)[R3]) {
   using G = Geo<R1, R2, R3>;
   cx<TC> v[G::NIN];
@@ -475,7 +477,7 @@ __device__ __forceinline__ void col_fwd(const cx<TS>* src, int in_off, int in_cn
 #pragma unroll
     for (int j = 0; j < G::NIN; ++j) {
       const int r = G::TIN * j + s - in_off;
-      v[j] = (colok && r >= 0 && r < in_cnt) ? ccast<TC>(src[r]) : mk<TC>(0, 0);
+      v[j] = (colok && r >= 0 && r < in_cnt) ? src.template ld<TC>(r) : mk<TC>(0, 0);
     }
   }
   xf_fwd<TC, R1, R2, R3, -1>(v, w, s, L, tb);
@@ -492,9 +494,11 @@ template <int R1, int R2, int R3, int MODE> struct ColCap {
   static constexpr int waves = (MODE == COL_CONV_DLAG && RowCap<R1, R2, R3>::waves > 1) ? 3 : 1;
 };
 
-template <typename TF, typename TI, typename TSI, typename TSO, int R1, int R2, int R3, int MODE>
+template <typename TF, typename TI, typename ST, int R1, int R2, int R3, int MODE>
 __global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(ColCap<R1, R2, R3, MODE>::waves)))
 k_cols(ColsArgs a) {
+  using TSI = typename ST::in;
+  using TSO = typename ST::out;
   int bx, by;
   logical_block<true>(bx, by);
   using G = Geo<R1, R2, R3>;
@@ -512,7 +516,7 @@ k_cols(ColsArgs a) {
 
   if constexpr (MODE == COL_CONV) {
     const int b = by;
-    const cx<TSI>* src = reinterpret_cast<const cx<TSI>*>(a.in) + (int64_t)b * a.in_fs + (int64_t)col * a.in_ld;
+    const Spec<TSI> src = Spec<TSI>::field(a.in, a.in_fs, b).at((int64_t)col * a.in_ld);
     // the filter values this thread needs, loaded before the transform hides their latency
     TF fv[R3];
     {
@@ -535,11 +539,11 @@ k_cols(ColsArgs a) {
     cx<TI> v[G::NIN];
     xf_inv<TI, R1, R2, R3>(wi, s, LI, tb, v);
     if (s < G::TIN && colok) {
-      cx<TSO>* dst = reinterpret_cast<cx<TSO>*>(a.out) + (int64_t)b * a.out_fs + (int64_t)col * a.out_ld;
+      const Spec<TSO> dst = Spec<TSO>::field(a.out, a.out_fs, b).at((int64_t)col * a.out_ld);
 #pragma unroll
       for (int j = 0; j < G::NIN; ++j) {
         const int d = window_dst(a.rows, G::TIN * j + s);
-        if (d >= 0) dst[d] = ccast<TSO>(v[j]);
+        if (d >= 0) dst.st(d, v[j]);
       }
     }
   } else if constexpr (MODE == COL_CONV_DLAG) {
@@ -552,8 +556,10 @@ k_cols(ColsArgs a) {
     const int b = by * NL + l0;
     const bool fok = colokb && b < a.B;
     const int bb = b < a.B ? b : 0;
-    const cx<TSI>* srcc = reinterpret_cast<const cx<TSI>*>(a.in2) + (int64_t)bb * a.in2_fs + (int64_t)colb * a.in2_ld;
-    const cx<TSI>* srcg = reinterpret_cast<const cx<TSI>*>(a.in) + (int64_t)bb * a.in_fs + (int64_t)colb * a.in_ld;
+    using TSI2 = typename ST::in2;
+    using TSP = typename ST::part;
+    const Spec<TSI2> srcc = Spec<TSI2>::field(a.in2, a.in2_fs, bb).at((int64_t)colb * a.in2_ld);
+    const Spec<TSI> srcg = Spec<TSI>::field(a.in, a.in_fs, bb).at((int64_t)colb * a.in_ld);
     TF fv[R3];  // filter values, loaded before the transforms
     {
       const TF* f = reinterpret_cast<const TF*>(a.filt) + (int64_t)(colokb ? colb : 0) * a.filt_ld;
@@ -561,7 +567,7 @@ k_cols(ColsArgs a) {
       for (int k2 = 0; k2 < R3; ++k2) fv[k2] = (s < G::TOUT && fok) ? f[s + G::TOUT * k2] : (TF)0;
     }
     cx<TC> wc[R3], wg[R3];
-    col_fwd<TC, TSI, R1, R2, R3>(srcc, a.in2_off, a.in2_cnt, fok, s, L, tb, wc);  // C-hat
+    col_fwd<TC, TSI2, R1, R2, R3>(srcc, a.in2_off, a.in2_cnt, fok, s, L, tb, wc);  // C-hat
     col_fwd<TC, TSI, R1, R2, R3>(srcg, a.in_off, a.in_cnt, fok, s, L, tb, wg);    // G-hat
     __syncthreads();
     if (s < G::TOUT) {
@@ -574,28 +580,28 @@ k_cols(ColsArgs a) {
     __syncthreads();
     if (l0 == 0 && s < G::TOUT && colokb) {
       const cx<TC>* L0 = reinterpret_cast<const cx<TC>*>(smem_raw);
-      cx<TSO>* p = reinterpret_cast<cx<TSO>*>(a.part) + (int64_t)by * a.part_fs + (int64_t)colb * a.part_ld;
+      const Spec<TSP> p = Spec<TSP>::field(a.part, a.part_fs, by).at((int64_t)colb * a.part_ld);
 #pragma unroll
       for (int k2 = 0; k2 < R3; ++k2) {
         cx<TC> acc = L0[s + G::TOUT * k2];
         for (int li = 1; li < NL; ++li) acc = acc + L0[(size_t)li * G::EX + s + G::TOUT * k2];
-        p[s + G::TOUT * k2] = ccast<TSO>(acc);
+        p.st(s + G::TOUT * k2, acc);
       }
     }
     cx<TC> v[G::NIN];
     xf_inv<TC, R1, R2, R3>(wg, s, L, tb, v);
     if (s < G::TIN && fok) {
-      cx<TSO>* dst = reinterpret_cast<cx<TSO>*>(a.out) + (int64_t)b * a.out_fs + (int64_t)colb * a.out_ld;
+      const Spec<TSO> dst = Spec<TSO>::field(a.out, a.out_fs, b).at((int64_t)colb * a.out_ld);
 #pragma unroll
       for (int j = 0; j < G::NIN; ++j) {
         const int d = window_dst(a.rows, G::TIN * j + s);
-        if (d >= 0) dst[d] = ccast<TSO>(v[j]);
+        if (d >= 0) dst.st(d, v[j]);
       }
     }
   } else if constexpr (MODE == COL_FWD_REAL) {
     // forward transform of the input columns; store Re(X) * scale (natural order)
     const int b = by;
-    const cx<TSI>* src = reinterpret_cast<const cx<TSI>*>(a.in) + (int64_t)b * a.in_fs + (int64_t)col * a.in_ld;
+    const Spec<TSI> src = Spec<TSI>::field(a.in, a.in_fs, b).at((int64_t)col * a.in_ld);
     cx<TC> w[R3];
     col_fwd<TC, TSI, R1, R2, R3>(src, a.in_off, a.in_cnt, colok, s, L, tb, w);
     if (s < G::TOUT && colok) {
@@ -634,15 +640,14 @@ k_cols(ColsArgs a) {
     cx<TC> w[R3];
     xf_fwd<TC, R1, R2, R3, -1>(v, w, s, L, tb);
     if (s < G::TOUT && colok) {
-      cx<TSO>* dst = reinterpret_cast<cx<TSO>*>(a.out) + (int64_t)by * a.out_fs + (int64_t)col * a.out_ld;
+      const Spec<TSO> dst = Spec<TSO>::field(a.out, a.out_fs, by).at((int64_t)col * a.out_ld);
 #pragma unroll
       for (int k2 = 0; k2 < R3; ++k2) {
         const int d = window_dst(a.rows, s + G::TOUT * k2);
-        if (d >= 0) dst[d] = ccast<TSO>(w[k2]);
+        if (d >= 0) dst.st(d, w[k2]);
       }
     }
   } else {  // COL_INV_SUM: inverse transform of sum_g part[g] (natural order), keep rows
-    const cx<TSI>* p = reinterpret_cast<const cx<TSI>*>(a.in) + (int64_t)col * a.in_ld;
     cx<TC> v[G::NIN];
 #pragma unroll
     for (int j = 0; j < G::NIN; ++j) v[j] = mk<TC>(0, 0);
@@ -650,29 +655,29 @@ k_cols(ColsArgs a) {
       // four partials per round: their 4 NIN loads go out together; every element is
       // still summed in the order g = 0, 1, ...
       for (int g0 = 0; g0 < a.G; g0 += 4) {
-        cx<TSI> t[4][G::NIN];
+        typename Spec<TSI>::raw t[4][G::NIN];
 #pragma unroll
         for (int u = 0; u < 4; ++u) {
-          const cx<TSI>* pg = p + (int64_t)(g0 + u < a.G ? g0 + u : g0) * a.in_fs + s;
+          const Spec<TSI> pg = Spec<TSI>::field(a.in, a.in_fs, g0 + u < a.G ? g0 + u : g0).at((int64_t)col * a.in_ld + s);
 #pragma unroll
-          for (int j = 0; j < G::NIN; ++j) t[u][j] = pg[G::TIN * j];
+          for (int j = 0; j < G::NIN; ++j) t[u][j] = pg.ldraw(G::TIN * j);
         }
 #pragma unroll
         for (int u = 0; u < 4; ++u)
           if (g0 + u < a.G) {
 #pragma unroll
-            for (int j = 0; j < G::NIN; ++j) v[j] = v[j] + ccast<TC>(t[u][j]);
+            for (int j = 0; j < G::NIN; ++j) v[j] = v[j] + Spec<TSI>::template cvt<TC>(t[u][j]);
           }
       }
     }
     cx<TC> w[R3];
     xf_fwd<TC, R1, R2, R3, 1>(v, w, s, L, tb);
     if (s < G::TOUT && colok) {
-      cx<TSO>* dst = reinterpret_cast<cx<TSO>*>(a.out) + (int64_t)col * a.out_ld;
+      const Spec<TSO> dst = Spec<TSO>::field(a.out, 0, 0).at((int64_t)col * a.out_ld);
 #pragma unroll
       for (int k2 = 0; k2 < R3; ++k2) {
         const int d = window_dst(a.rows, s + G::TOUT * k2);
-        if (d >= 0) dst[d] = ccast<TSO>(w[k2]);
+        if (d >= 0) dst.st(d, w[k2]);
       }
     }
   }
@@ -720,25 +725,25 @@ KRIG_ROW_KERNEL k_rows_c2r(RowsC2RArgs a) {
   // row-contiguous loads of the block's 2 NL rows into T[k][rl]
   const int R2b = 2 * NL;
   cx<TC>* T = lds;
-  const cx<TS>* in = reinterpret_cast<const cx<TS>*>(a.in) + (int64_t)b * a.in_fs;
+  const Spec<TS> in = Spec<TS>::field(a.in, a.in_fs, b);
   {
     // a thread's share is at most IT elements (blockDim = NT * NL, H2 = F/2 + 1): all
     // its loads are issued before the first LDS store
     // element idx = k R2b + rl goes to thread idx mod blockDim (NT NL)
     constexpr int IT = (2 * (G::F / 2 + 1) + G::NT - 1) / G::NT;
-    cx<TS> buf[IT];
+    typename Spec<TS>::raw buf[IT];
     {
       TWalk<G::NT> e(threadIdx.x, NL);
 #pragma unroll
       for (int it = 0; it < IT; ++it, e.next()) {
         const int row = row0 + e.rl;
-        buf[it] = (e.k < a.H2 && row < a.nrows) ? in[(int64_t)e.k * a.in_ld + row] : mk<TS>(0, 0);
+        buf[it] = (e.k < a.H2 && row < a.nrows) ? in.ldraw((int64_t)e.k * a.in_ld + row) : Spec<TS>::zero();
       }
     }
     TWalk<G::NT> e(threadIdx.x, NL);
 #pragma unroll
     for (int it = 0; it < IT; ++it, e.next())
-      if (e.k < a.H2) T[tpos(e.k, e.rl, R2b)] = ccast<TC>(buf[it]);
+      if (e.k < a.H2) T[tpos(e.k, e.rl, R2b)] = Spec<TS>::template cvt<TC>(buf[it]);
   }
   __syncthreads();
   cx<TC> v[G::NIN];
@@ -915,14 +920,14 @@ hipError_t launch_rows_r2c(const RowsR2CArgs& a, int B, hipStream_t st) {
   return hipGetLastError();
 }
 
-template <typename TF, typename TI, typename TSI, typename TSO, int R1, int R2, int R3, int MODE>
+template <typename TF, typename TI, typename ST, int R1, int R2, int R3, int MODE>
 hipError_t launch_cols(const ColsArgs& a, int nblk_y, hipStream_t st) {
   using G = Geo<R1, R2, R3>;
   // the lag-gradient pass: one column per block, its NL lines are fields
   dim3 grid(MODE == COL_CONV_DLAG ? a.H2 : (a.H2 + a.NL - 1) / a.NL, nblk_y);
   dim3 block(G::NT * a.NL);
   const size_t sh = cols_lds(G::g, a.NL, sizeof(cx<TF>));
-  k_cols<TF, TI, TSI, TSO, R1, R2, R3, MODE><<<grid, block, sh, st>>>(a);
+  k_cols<TF, TI, ST, R1, R2, R3, MODE><<<grid, block, sh, st>>>(a);
   return hipGetLastError();
 }
 
@@ -967,21 +972,27 @@ FftEntry make_fft_entry() {
   e.F = R1 * R2 * R3;
   e.geo = fft_geo(R1, R2, R3);
   FftSet& k = e.k;
+  using S64 = Stor<double, double, double, double>;
+  using S32 = Stor<float, float, float, float>;
   k.r2c_csr = launch_rows_r2c<double, double, double, R1, R2, R3, SRC_CSR>;
-  k.r2c_dense_f32 = launch_rows_r2c<double, float, double, R1, R2, R3, SRC_DENSE>;
   k.r2c_dense_f64 = launch_rows_r2c<double, double, double, R1, R2, R3, SRC_DENSE>;
   k.r2c_lag = launch_rows_r2c<double, double, double, R1, R2, R3, SRC_LAG>;
-  k.conv64 = launch_cols<double, double, double, double, R1, R2, R3, COL_CONV>;
-  k.conv_dlag64 = launch_cols<double, double, double, double, R1, R2, R3, COL_CONV_DLAG>;
-  k.fwd_real64 = launch_cols<double, double, double, double, R1, R2, R3, COL_FWD_REAL>;
-  k.inv_sum64 = launch_cols<double, double, double, double, R1, R2, R3, COL_INV_SUM>;
-  k.c2r64_32 = launch_rows_c2r<double, double, float, R1, R2, R3>;
+  k.conv64 = launch_cols<double, double, S64, R1, R2, R3, COL_CONV>;
+  k.conv_dlag64 = launch_cols<double, double, S64, R1, R2, R3, COL_CONV_DLAG>;
+  k.fwd_real64 = launch_cols<double, double, S64, R1, R2, R3, COL_FWD_REAL>;
+  k.inv_sum64 = launch_cols<double, double, S64, R1, R2, R3, COL_INV_SUM>;
   k.c2r64 = launch_rows_c2r<double, double, double, R1, R2, R3>;
+  k.c2r64_32 = launch_rows_c2r<double, double, float, R1, R2, R3>;
+  // FP32 plans' adjoint: FP64 arithmetic, FP32 spectra where their rounding stays harmless
+  k.r2c_dense_f32 = launch_rows_r2c<double, float, float, R1, R2, R3, SRC_DENSE>;
+  k.conv_adj_f = launch_cols<double, double, Stor<float, float, double, float>, R1, R2, R3, COL_CONV>;
+  k.conv_dlag_f = launch_cols<double, double, Stor<float, double, double, float>, R1, R2, R3, COL_CONV_DLAG>;
+  k.inv_sum_f = launch_cols<double, double, Stor<float, float, double, double>, R1, R2, R3, COL_INV_SUM>;
   k.c2r_fold32 = launch_rows_c2r_fold<double, float, R1, R2, R3>;
   k.c2r_fold64 = launch_rows_c2r_fold<double, double, R1, R2, R3>;
   k.r2c_cov = launch_rows_r2c<double, double, double, R1, R2, R3, SRC_COV>;
-  k.ce_cols32 = launch_cols<float, float, float, float, R1, R2, R3, COL_CE>;
-  k.ce_cols64 = launch_cols<double, double, double, double, R1, R2, R3, COL_CE>;
+  k.ce_cols32 = launch_cols<float, float, S32, R1, R2, R3, COL_CE>;
+  k.ce_cols64 = launch_cols<double, double, S64, R1, R2, R3, COL_CE>;
   k.ce_rows32 = launch_rows_ce<float, float, float, R1, R2, R3>;
   k.ce_rows64 = launch_rows_ce<double, double, double, R1, R2, R3>;
   return e;

@@ -58,13 +58,14 @@ struct krig_plan_s {
   double* lag64 = nullptr;
   void* lagT = nullptr;
   double* filt = nullptr;  // [H2][F1] filter spectrum / (F1 F2), FP64
-  double* KN = nullptr;
+  double* KN = nullptr;     // K_N as factored (jitter included when it was needed)
   double* LinvN = nullptr;
   int* d_status = nullptr;   // [0] K_N status, [1] M pivot
   int32_t* anchor = nullptr;
   double* kvec = nullptr;
   double* W = nullptr;
   double* Wt = nullptr;
+  double* Wr = nullptr;     // [n][M] residual of the weight refinement
   int32_t* node_ptr = nullptr;
   int32_t* ent_site = nullptr;
   double* ent_w = nullptr;
@@ -283,6 +284,23 @@ const FftSet& set2(krig_plan p) { return p->e2->k; }
 bool is32(krig_plan p) { return p->dtype == KRIG_F32; }
 size_t csz(krig_plan p) { return 2 * p->tsz; }
 
+// Bytes per complex value of each spectrum that passes between the transform kernels.
+// FP64 plans store FP64 throughout.  FP32 plans (FP64 arithmetic in every pass) store
+//  - the row spectra of the upstream gradient and the lag-gradient partial spectra in
+//    FP32 (8 bytes): one rounding there moves d y by ~1e-7 and d lag by ~1e-8 (relative
+//    max error);
+//  - the prediction's spectra in FP64 (16 bytes): one FP32 rounding of the row spectra of
+//    c* moves y_hat by up to ~3e-5 on cancellation-heavy problems (sum |c*| / max |y_hat|
+//    ~ 1e5), and one of the column pass's output by up to ~3e-6, which also lifts the
+//    rounding noise of finite differences of the predictions above 1e-4;
+//  - the adjoint's correlation spectra in FP64: d y applies (K + tau^2 I)^{-1} to them,
+//    and one FP32 rounding moves d y by ~1e-4.
+enum SpecRole { SPEC_C, SPEC_PRED, SPEC_G, SPEC_CORR, SPEC_PART };
+size_t spec_bytes(krig_plan p, SpecRole role) {
+  if (!is32(p)) return 16;
+  return (role == SPEC_G || role == SPEC_PART) ? 8 : 16;
+}
+
 // spectrum of the even-reflected lag quadrant (FP64), scaled by 1/(F1 F2)
 int make_filter(krig_plan p, const double* lag64, double* filt_out) {
   RowsR2CArgs r{};
@@ -325,8 +343,8 @@ int ensure_ws(krig_plan p, int B) {
   for (void* q : olds) dfree(p, q);
   const size_t H2 = p->H2;
   int r;
-  if ((r = dalloc_bytes(p, &p->S1, 16 * (size_t)B * H2 * p->ldP)) != KRIG_OK) return r;
-  if ((r = dalloc_bytes(p, &p->S2, 16 * (size_t)B * H2 * p->ldM)) != KRIG_OK) return r;
+  if ((r = dalloc_bytes(p, &p->S1, spec_bytes(p, SPEC_C) * (size_t)B * H2 * p->ldP)) != KRIG_OK) return r;
+  if ((r = dalloc_bytes(p, &p->S2, spec_bytes(p, SPEC_PRED) * (size_t)B * H2 * p->ldM)) != KRIG_OK) return r;
   if ((r = dalloc(p, &p->alpha, (size_t)B * p->n)) != KRIG_OK) return r;
   p->ldv = (p->n + 3) / 4 * 4;
   if ((r = dalloc(p, &p->tmpv, (size_t)B * p->ldv)) != KRIG_OK) return r;
@@ -349,11 +367,12 @@ int ensure_ws_adj(krig_plan p, int B) {
   for (void* q : olds) dfree(p, q);
   const size_t H2 = p->H2;
   int r;
-  if ((r = dalloc_bytes(p, &p->SG, 16 * (size_t)B * H2 * p->ldM)) != KRIG_OK) return r;
-  if ((r = dalloc_bytes(p, &p->SA, 16 * (size_t)B * H2 * p->ldP)) != KRIG_OK) return r;
+  if ((r = dalloc_bytes(p, &p->SG, spec_bytes(p, SPEC_G) * (size_t)B * H2 * p->ldM)) != KRIG_OK) return r;
+  if ((r = dalloc_bytes(p, &p->SA, spec_bytes(p, SPEC_CORR) * (size_t)B * H2 * p->ldP)) != KRIG_OK) return r;
   if ((r = dalloc_bytes(p, &p->img, 8 * (size_t)B * p->P1 * p->P2)) != KRIG_OK) return r;
   p->part_groups = B;  // worst case G = 1
-  if ((r = dalloc_bytes(p, &p->part, 16 * (size_t)p->part_groups * H2 * p->F1)) != KRIG_OK) return r;
+  if ((r = dalloc_bytes(p, &p->part, spec_bytes(p, SPEC_PART) * (size_t)p->part_groups * H2 * p->F1)) != KRIG_OK)
+    return r;
   p->wsB_adj = B;
   return KRIG_OK;
 }
@@ -401,7 +420,7 @@ int kn_factor_large(krig_plan p) {
   int status = 0;
   for (int attempt = 0; attempt < 2; ++attempt) {
     const double jit = attempt ? 1e-14 * p->mt.sigma2 * M : 0.0;
-    KRIG_TRY(kn_assemble(p->g, p->mt, attempt ? nullptr : p->KN, A, jit, p->st));
+    KRIG_TRY(kn_assemble(p->g, p->mt, p->KN, A, jit, p->st));
     KRIG_TRY(hipMemsetAsync(p->d_status + 2, 0, sizeof(int), p->st));
     KRIG_TRY(cholesky_and_inverse(A, M, M, p->LinvN, Dv, wk, p->d_status + 2, p->st));
     int piv = 0;
@@ -418,6 +437,41 @@ int kn_factor_large(krig_plan p) {
   dfree(p, A);
   dfree(p, Dv);
   dfree(p, wk);
+  return KRIG_OK;
+}
+
+// Step 4: W = K_N^{-1} k for all sites (d_kvec [n][M]): the two FP64 MFMA products with the
+// inverse factor, (k L_N^{-T}) L_N^{-1}, then WEIGHT_REFINE steps of iterative refinement in
+// FP64, R = k - W K_N and W += (R L_N^{-T}) L_N^{-1}.  The products alone leave a residual of
+// about cond(K_N) eps |k| (1e-9 for the paper-sized field, cond(K_N) ~ 3e13); refined, it meets
+// the backward-stable bound ~M eps |K_N| |w| of a direct solve.  Leaves Wt rebuilt from W.
+constexpr int WEIGHT_REFINE = 2;
+int weights_from_kvec(krig_plan p, const double* d_kvec) {
+  const int n = p->n, M = p->M;
+  GemmArgs ga{};  // X L_N^{-T}
+  ga.lda = M; ga.transA = 0;
+  ga.B = p->LinvN; ga.ldb = M; ga.transB = 1;
+  ga.ldc = M;
+  ga.m_off = 0; ga.M_end = n; ga.n_off = 0; ga.N_end = M; ga.K = M;
+  ga.alpha = 1.0; ga.beta = 0.0; ga.lower = 0;
+  GemmArgs gb = ga;  // Y L_N^{-1}
+  gb.transB = 0;
+  ga.A = d_kvec; ga.C = p->Wt;
+  KRIG_TRY(gemm_f64(ga, p->st));
+  gb.A = p->Wt; gb.C = p->W;
+  KRIG_TRY(gemm_f64(gb, p->st));
+  for (int it = 0; it < WEIGHT_REFINE; ++it) {
+    KRIG_TRY(hipMemcpyAsync(p->Wr, d_kvec, sizeof(double) * (size_t)n * M, hipMemcpyDeviceToDevice, p->st));
+    GemmArgs gr = ga;  // R = k - W K_N
+    gr.A = p->W; gr.B = p->KN; gr.transB = 0; gr.C = p->Wr; gr.alpha = -1.0; gr.beta = 1.0;
+    KRIG_TRY(gemm_f64(gr, p->st));
+    ga.A = p->Wr; ga.C = p->Wt;
+    KRIG_TRY(gemm_f64(ga, p->st));
+    GemmArgs gw = gb;  // W += (R L_N^{-T}) L_N^{-1}
+    gw.A = p->Wt; gw.C = p->W; gw.beta = 1.0;
+    KRIG_TRY(gemm_f64(gw, p->st));
+  }
+  KRIG_TRY(transpose_w(p->W, n, M, p->Wt, p->st));
   return KRIG_OK;
 }
 
@@ -824,25 +878,13 @@ int krig_plan_create(krig_plan* out, const krig_grid* g, const krig_matern* k, i
   CK(dalloc(p, &p->kvec, (size_t)n * M));
   CK(dalloc(p, &p->W, (size_t)n * M));
   CK(dalloc(p, &p->Wt, (size_t)n * M));
+  CK(dalloc(p, &p->Wr, (size_t)n * M));
   if (M <= 64)
     CKH(kn_factor(p->g, p->mt, p->KN, p->LinvN, p->d_status, p->st));
   else
     CK(kn_factor_large(p));
   CKH(site_kvec(p->g, p->mt, p->sites, n, p->anchor, p->kvec, p->st));
-  {
-    GemmArgs ga{};
-    ga.A = p->kvec; ga.lda = M; ga.transA = 0;
-    ga.B = p->LinvN; ga.ldb = M; ga.transB = 1;
-    ga.C = p->W; ga.ldc = M;
-    ga.m_off = 0; ga.M_end = n; ga.n_off = 0; ga.N_end = M; ga.K = M;
-    ga.alpha = 1.0; ga.beta = 0.0; ga.lower = 0;
-    CKH(gemm_f64(ga, p->st));  // T1 = k L_N^{-T}  (into W)
-    GemmArgs gb = ga;
-    gb.A = p->W; gb.transB = 0; gb.C = p->kvec;  // W = T1 L_N^{-1}  (into kvec, then swap)
-    CKH(gemm_f64(gb, p->st));
-    std::swap(p->W, p->kvec);
-  }
-  CKH(transpose_w(p->W, n, M, p->Wt, p->st));
+  CK(weights_from_kvec(p, p->kvec));
 
   // Step 5 structure
   CK(dalloc(p, &p->cw.cell_cnt, (size_t)g->m1 * g->m2));
@@ -963,20 +1005,10 @@ int krig_set_weights(krig_plan p, const int32_t* d_anchor, const double* d_W) {
 
 int krig_set_kvec(krig_plan p, const double* d_kvec) {
   if (!p || !d_kvec) return KRIG_EINVAL;
-  const int n = p->n, M = p->M;
-  // Step 4 with the caller's k_i: W = (k L_N^{-T}) L_N^{-1}, the products of plan
-  // creation; Wt holds the intermediate and is rebuilt from W afterwards
-  GemmArgs ga{};
-  ga.A = d_kvec; ga.lda = M; ga.transA = 0;
-  ga.B = p->LinvN; ga.ldb = M; ga.transB = 1;
-  ga.C = p->Wt; ga.ldc = M;
-  ga.m_off = 0; ga.M_end = n; ga.n_off = 0; ga.N_end = M; ga.K = M;
-  ga.alpha = 1.0; ga.beta = 0.0; ga.lower = 0;
-  KRIG_TRY(gemm_f64(ga, p->st));
-  GemmArgs gb = ga;
-  gb.A = p->Wt; gb.transB = 0; gb.C = p->W;
-  KRIG_TRY(gemm_f64(gb, p->st));
-  KRIG_TRY(transpose_w(p->W, n, M, p->Wt, p->st));
+  // Step 4 with the caller's k_i: W = K_N^{-1} k as at plan creation (the inverse-factor
+  // products and their refinement); Wt is rebuilt from W
+  int r = weights_from_kvec(p, d_kvec);
+  if (r != KRIG_OK) return r;
   // the anchors are unchanged, so the scatter structure is too: only its weights are rewritten
   KRIG_TRY(refill_csr_weights(p->g, p->anchor, p->W, p->node_ptr, p->ent_site, p->ent_w, p->st));
   return KRIG_OK;
@@ -1041,7 +1073,7 @@ int dlag_tail(krig_plan p, int ngroups, void* d_dlag, hipStream_t st) {
   ci.twF = p->tw1_64;
   ci.twI = p->tw1_64;
   ci.NL = p->nl_cols64;
-  KRIG_TRY(set1(p).inv_sum64(ci, 1, st));
+  KRIG_TRY((is32(p) ? set1(p).inv_sum_f : set1(p).inv_sum64)(ci, 1, st));
   RowsC2RArgs oc{};
   oc.nrows = p->n1l;
   oc.H2 = p->H2;
@@ -1068,9 +1100,10 @@ int krig_predict_adjoint(krig_plan p, int32_t B, const void* d_g, const double* 
   if ((r = ensure_ws_adj(p, B)) != KRIG_OK) return r;
   const double* filt = nullptr;
   if ((r = filter_for(p, d_lag, &filt)) != KRIG_OK) return r;
-  // The adjoint runs in FP64 whatever the plan's dtype: d alpha is multiplied by
+  // The adjoint computes in FP64 whatever the plan's dtype: d alpha is multiplied by
   // (K + tau^2 I)^{-1}, whose condition number amplifies any FP32 rounding of the
-  // correlation image far beyond the gradient tolerance.
+  // correlation far beyond the gradient tolerance, so the correlation spectra and image
+  // stay FP64 in FP32 plans (spec_bytes).
   const void* spec1 = d_saved;
   if (d_dlag && !spec1) {
     // recompute the row spectra of c* from the coefficients
@@ -1140,11 +1173,11 @@ int krig_predict_adjoint(krig_plan p, int32_t B, const void* d_g, const double* 
     c.NL = std::max(1, std::min(p->dlag_G, (int)B));  // fields (lines) per block
     ngroups = (B + c.NL - 1) / c.NL;
     StageTimer t(p, KRIG_STAGE_ADJ_COLS);
-    KRIG_TRY(set1(p).conv_dlag64(c, ngroups, p->st));
+    KRIG_TRY((is32(p) ? set1(p).conv_dlag_f : set1(p).conv_dlag64)(c, ngroups, p->st));
   } else {
     c.NL = p->nl_cols64;
     StageTimer t(p, KRIG_STAGE_ADJ_COLS);
-    KRIG_TRY(set1(p).conv64(c, B, p->st));
+    KRIG_TRY((is32(p) ? set1(p).conv_adj_f : set1(p).conv64)(c, B, p->st));
   }
   // The lag-gradient tail does not depend on the gather and solve below (they read SA,
   // img, alpha, tmpv and tripart): with both outputs asked for, it runs on the plan's

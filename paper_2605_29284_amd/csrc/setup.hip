@@ -95,8 +95,8 @@ __global__ void __launch_bounds__(256) k_kn_factor(GridDev g, MaternDev mt, doub
       offset_of(q, g.L, oxq, oyq);
       const double hx = (double)(oxp - oxq) * g.dx, hy = (double)(oyp - oyq) * g.dy;
       double v = matern_cov(sqrt(hx * hx + hy * hy), mt);
-      if (attempt == 0) KN[e] = v;
       if (p == q) v += jit;
+      KN[e] = v;  // the matrix that is factored (weight refinement takes residuals against it)
       a[p][q] = v;
     }
     __syncthreads();
@@ -152,8 +152,9 @@ __global__ void k_kn_assemble(GridDev g, MaternDev mt, double* __restrict__ KN, 
   offset_of(q, g.L, oxq, oyq);
   const double hx = (double)(oxp - oxq) * g.dx, hy = (double)(oyp - oyq) * g.dy;
   const double v = matern_cov(sqrt(hx * hx + hy * hy), mt);
-  if (KN) KN[e] = v;
-  A[e] = p == q ? v + jit : v;
+  const double a = p == q ? v + jit : v;
+  if (KN) KN[e] = a;  // the matrix that is factored
+  A[e] = a;
 }
 
 hipError_t kn_assemble(const GridDev& g, const MaternDev& mt, double* KN, double* A, double jit, hipStream_t st) {

@@ -6,6 +6,7 @@ import numpy as np
 import pytest
 
 import workloads as wl
+from parity_bars import BAR_F32, bar_for, check
 from oracle.matern import Matern
 from oracle.mixture import mixture_rapid
 from oracle.rapid import Grid, RapidPredictor
@@ -73,7 +74,7 @@ def test_mixture_matches_oracle(krig, dtype):
         ref = np.zeros((w.m1, w.m2))
         for (k, lam), rp in zip(ocomps, preds):
             ref += lam(nodes).reshape(w.m1, w.m2) * rp.predict_direct(lam(w.sites) * alpha[b]).reshape(w.m1, w.m2)
-        assert relmax(got[b], ref) < (1e-12 if dtype == "f64" else 1e-6)
+        check(f"mixture field {b} {dtype}", relmax(got[b], ref), bar_for(dtype))
     again = host(krig.mixture(plans, dev(alpha), dev(lam_sites), dev(lam_grid)))
     assert np.array_equal(got, again)
 

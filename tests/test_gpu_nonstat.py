@@ -5,6 +5,7 @@ import numpy as np
 import pytest
 
 import workloads as wl
+from parity_bars import BAR_F32, bar_for, check, weight_residual_ratio
 from oracle.matern import Matern
 from oracle.nonstat import kvecs_cov, scaled_cov, weights_from_kvec
 from oracle.rapid import Grid, cstar_image, kn_matrix, kvecs, rapid_direct, site_cells, sparse_A
@@ -47,15 +48,17 @@ def test_set_kvec_small_field(krig, dtype):
     p.set_kvec(dev(kv))
     anc, W = p.weights()
     anc, W = host(anc).astype(np.int64), host(W)
-    assert np.abs(W - weights_from_kvec(g, k, kv)).max() < 1e-9
-    assert np.abs(W @ kn_matrix(g, k) - kv).max() < 1e-12  # eq. weights with the caller's k_i
+    check(f"set_kvec small field: weights vs oracle {dtype}", np.abs(W - weights_from_kvec(g, k, kv)).max(), 1e-9)
+    # eq. weights with the caller's k_i
+    check(f"set_kvec small field: residual / backward-stable bound {dtype}",
+          weight_residual_ratio(W, kn_matrix(g, k), kv), 1.0)
     # predictions from caller coefficients use the new weights (oracle with the same W)
     alpha = np.random.default_rng(0).standard_normal((2, w.n))
     yh = host(p.convolve(dev(alpha)))
     A = sparse_A(g, anc[:, 0], anc[:, 1], W)
     for b in range(2):
         ref = rapid_direct(g, k, cstar_image(g, A, alpha[b])).reshape(g.m1, g.m2)
-        assert relmax(yh[b], ref) < (1e-12 if dtype == "f64" else 1e-6)
+        check(f"set_kvec small field: prediction field {b} {dtype}", relmax(yh[b], ref), bar_for(dtype))
 
 
 @pytest.mark.parametrize("dtype", ["f64", "f32"])
@@ -109,7 +112,9 @@ def test_set_kvec_paper_field_residual(krig):
     kv = kvecs_cov(g, w.sites, scaled_cov(k, sd))
     p.set_kvec(dev(kv))
     _, W = p.weights()
-    # K_N is ill-conditioned: the weights are checked through the interpolation residual
-    assert np.abs(host(W) @ kn_matrix(g, k) - kv).max() < 1e-7
+    # K_N is ill-conditioned: the weights are checked through the interpolation residual,
+    # against the bound of a backward-stable solve
+    check("set_kvec paper field: residual / backward-stable bound",
+          weight_residual_ratio(host(W), kn_matrix(g, k), kv), 1.0)
     with pytest.raises(TypeError):
         p.set_kvec(dev(kv, torch.float32))

@@ -5,6 +5,7 @@ import numpy as np
 import pytest
 
 import workloads as wl
+from parity_bars import BAR_F32, bar_for, check
 from oracle.exact import ExactKriging
 from oracle.matern import Matern
 from oracle.rapid import Grid, RapidPredictor
@@ -70,7 +71,7 @@ def test_universal_matches_oracle(krig, small, dtype):
         assert relmax(B_[b], bref) < 1e-9
         assert relmax(C_[b], cref) < 1e-9
         ref = universal_rapid(ek, rp, X, Xg, z[b])
-        assert relmax(got[b], ref) < (1e-10 if dtype == "f64" else 1e-6)
+        check(f"universal kriging field {b} {dtype}", relmax(got[b], ref), 1e-10 if dtype == "f64" else BAR_F32)
     again = host(p.predict_universal(dev(z), dev(X.T), dev(Xg)))
     assert np.array_equal(got, again)
 
