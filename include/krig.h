@@ -95,7 +95,8 @@ enum {
   KRIG_INFO_FFT_VARIANTS_ROWS, /* compiled forms of the row / column transform length */
   KRIG_INFO_FFT_VARIANTS_COLS,
   KRIG_INFO_FFT_VARIANT_ROWS,  /* form in use, 1-based (1: the default form) */
-  KRIG_INFO_FFT_VARIANT_COLS
+  KRIG_INFO_FFT_VARIANT_COLS,
+  KRIG_INFO_SOLVE_NOALLOC_MAX_B /* largest B krig_solve_noalloc accepts for this plan (0: none) */
 };
 
 /*
@@ -162,6 +163,25 @@ int krig_lag(krig_plan p, void *d_lag);
 /* Kriging coefficients alpha = (K + tau^2 I)^{-1} y for B fields (eq. findc), FP64:
  * d_y, d_alpha [B][n] (may alias). */
 int krig_solve(krig_plan p, int32_t B, const double *d_y, double *d_alpha);
+
+/*
+ * krig_solve for callers that cannot allocate device memory: code under HIP graph
+ * capture, tight serving loops, harnesses that forbid hipMalloc.  Same arguments and
+ * results as krig_solve (the same kernels in the same order: bitwise the same alpha), but
+ * the workspace comes from a fixed scratch array of KRIG_SOLVE_NOALLOC_SCRATCH_BYTES that
+ * the library holds on each GPU from its first use until the process ends; nothing is
+ * allocated or freed, and stage timing does not cover this call.  The scratch must hold
+ * B * (n rounded up to 4) + ceil(n/16) * ceil(ceil(n/16)/8) * ceil(B/16) * 256 doubles
+ * (KRIG_INFO_SOLVE_NOALLOC_MAX_B gives the largest B for a plan: 13616 fields at n = 200,
+ * 496 at n = 1368, 32 at n = 5000, 16 at n = 8000, none beyond n = 8,176).  KRIG_EINVAL for a
+ * larger request, or when the current device is not the one the plan was created on.
+ * Every call on one GPU shares that GPU's scratch, and a call's work reads it after the
+ * call returns: calls that overlap on one GPU (other streams, other plans, other host
+ * threads) race and give wrong results.  Asynchronous on the plan's stream; d_y and
+ * d_alpha may alias.
+ */
+#define KRIG_SOLVE_NOALLOC_SCRATCH_BYTES (64u << 20)
+int krig_solve_noalloc(krig_plan p, int32_t B, const double *d_y, double *d_alpha);
 
 /*
  * Steps 5-6 on their own: the padded coefficient image c* = A^T alpha for B fields,

@@ -36,6 +36,7 @@ struct DevBuf {
 
 struct krig_plan_s {
   hipStream_t st = nullptr;
+  int device = 0;  // the GPU that was current at plan creation (holds every buffer)
   int dtype = KRIG_F32;
   size_t tsz = 4;  // bytes of one real dt value
   GridDev g{};
@@ -798,6 +799,10 @@ int krig_plan_create(krig_plan* out, const krig_grid* g, const krig_matern* k, i
 
   krig_plan p = new (std::nothrow) krig_plan_s();
   if (!p) return KRIG_ENOMEM;
+  if (hipGetDevice(&p->device) != hipSuccess) {
+    delete p;
+    return KRIG_EHIP;
+  }
   p->st = (hipStream_t)stream;
   p->dtype = dtype;
   p->tsz = dtype == KRIG_F32 ? 4 : 8;
@@ -941,6 +946,10 @@ int krig_plan_destroy(krig_plan p) {
   return KRIG_OK;
 }
 
+namespace {
+int solve_noalloc_max_B(int n);  // with krig_solve_noalloc below
+}  // namespace
+
 int krig_plan_info(krig_plan p, int32_t what, int64_t* v) {
   if (!p || !v) return KRIG_EINVAL;
   switch (what) {
@@ -969,6 +978,7 @@ int krig_plan_info(krig_plan p, int32_t what, int64_t* v) {
     case KRIG_INFO_FFT_R3: *v = p->e2->geo.R3; break;
     case KRIG_INFO_CE_F1: *v = p->Fs1; break;
     case KRIG_INFO_CE_F2: *v = p->Fs2; break;
+    case KRIG_INFO_SOLVE_NOALLOC_MAX_B: *v = solve_noalloc_max_B(p->n); break;
     default: return KRIG_EINVAL;
   }
   return KRIG_OK;
@@ -1025,6 +1035,68 @@ int krig_solve(krig_plan p, int32_t B, const double* d_y, double* d_alpha) {
   int r = ensure_ws(p, B);
   if (r != KRIG_OK) return r;
   return do_solve(p, B, d_y, d_alpha);
+}
+
+// ------------------------------------------------------------------ allocation-free solve
+// Scratch of krig_solve_noalloc: the intermediate vector between the two triangular
+// products (B rows of n rounded up to 4) followed by their split partial tiles.  A
+// file-scope device array, so each GPU holds one copy from module load until the process
+// ends; host code reaches it only through the address hipGetSymbolAddress returns for
+// the device that is current (the array's name is a host-side stand-in, not a device
+// address).
+static __device__ __align__(256) double scratch[KRIG_SOLVE_NOALLOC_SCRATCH_BYTES / sizeof(double)];
+
+namespace {
+constexpr int kMaxDevices = 64;
+std::mutex g_scratch_mu;
+double* g_scratch_ptr[kMaxDevices] = {};
+
+// this GPU's copy of the scratch array, looked up once per device (with it current)
+int scratch_for_device(int dev, double** out) {
+  if (dev < 0 || dev >= kMaxDevices) return KRIG_EINVAL;
+  std::lock_guard<std::mutex> lk(g_scratch_mu);
+  if (!g_scratch_ptr[dev]) {
+    void* ptr = nullptr;
+    if (hipGetSymbolAddress(&ptr, HIP_SYMBOL(scratch)) != hipSuccess || !ptr) return KRIG_EHIP;
+    g_scratch_ptr[dev] = static_cast<double*>(ptr);
+  }
+  *out = g_scratch_ptr[dev];
+  return KRIG_OK;
+}
+
+// doubles of scratch one solve of B fields needs: the intermediate vector, then the partials
+size_t solve_scratch_doubles(int n, int B) {
+  return (size_t)B * ((n + 3) / 4 * 4) + tri_part_size(n, B);
+}
+int solve_noalloc_max_B(int n) {
+  const size_t cap = KRIG_SOLVE_NOALLOC_SCRATCH_BYTES / sizeof(double);
+  int lo = 0, hi = 65535;  // largest B with solve_scratch_doubles(n, B) <= cap
+  while (lo < hi) {
+    const int mid = (lo + hi + 1) / 2;
+    if (solve_scratch_doubles(n, mid) <= cap) lo = mid; else hi = mid - 1;
+  }
+  return lo;
+}
+}  // namespace
+
+int krig_solve_noalloc(krig_plan p, int32_t B, const double* d_y, double* d_alpha) {
+  if (!p || B < 1 || B > 65535 || !d_y || !d_alpha) return KRIG_EINVAL;
+  if (solve_scratch_doubles(p->n, B) * sizeof(double) > KRIG_SOLVE_NOALLOC_SCRATCH_BYTES) return KRIG_EINVAL;
+  int cur = -1;
+  if (hipGetDevice(&cur) != hipSuccess) return KRIG_EHIP;
+  if (cur != p->device) return KRIG_EINVAL;
+  double* sp = nullptr;
+  int r = scratch_for_device(cur, &sp);
+  if (r != KRIG_OK) return r;
+  // the products of krig_solve, with the scratch in place of the plan's workspaces: every
+  // value they read from it is written earlier in the same call (partials per split, the
+  // intermediate's rows up to n; its row padding is loaded but masked), so nothing is cleared
+  const int64_t ldv = (p->n + 3) / 4 * 4;
+  double* tmpv = sp;
+  double* part = sp + (size_t)B * ldv;
+  KRIG_TRY(tri_apply(p->Linv, p->ldL, p->n, 0, d_y, p->n, tmpv, ldv, B, part, p->st));
+  KRIG_TRY(tri_apply(p->LinvT, p->ldL, p->n, 1, tmpv, ldv, d_alpha, p->n, B, part, p->st));
+  return KRIG_OK;
 }
 
 int krig_scatter(krig_plan p, int32_t B, const double* d_alpha, void* d_img) {
