@@ -29,7 +29,8 @@ sys.path.insert(0, ROOT)
 HBM_PEAK_GBS = 8000.0  # MI355X HBM3E, GB/s
 PROFILES = os.path.join(ROOT, "profiles")
 # sources of the FFT pass kernels: a recorded traffic figure holds only while they are unchanged
-KERNEL_SOURCES = ["fft_passes.h", "fft_args.h", "fft_reg.h", "krig_internal.h", "matern_dev.h", "philox_dev.h"]
+KERNEL_SOURCES = ["fft_passes.h", "fft_args.h", "fft_reg.h", "krig_internal.h", "matern_dev.h", "philox_dev.h",
+                  "spec_io.h"]
 STAGE_SOURCES = {"INTERP": ["interp.hip", "interp.h"]}  # stages whose kernel lives elsewhere
 
 
@@ -58,28 +59,45 @@ def recorded_traffic(stage):
     return None
 
 
-def stage_bytes(p, B, ngroups):
-    """Algorithmic bytes per launch of each timed single-kernel stage: what the pass must
-    read and write once (FP64 spectra between the passes, the plan's dtype for the
-    caller's arrays)."""
-    t = 4 if p.dtype_code == 1 else 8      # dt value
-    z = 16                                  # FP64 complex
+def stage_bytes(p, B, model="s8d"):
+    """Algorithmic bytes per launch of each timed single-kernel stage of the grad-batch step (B
+    fields), in one of two models:
+      "s8d"  the survey's measurement model: 8-byte complex spectra and 4-byte caller arrays
+             (FP32), the filter spectrum in FP32, CSR entries of 8 bytes; the adjoint's column
+             pass reads G-hat (m1 rows), writes the correlation spectra (P1 rows) and reloads the
+             saved spectrum of c* as a full F1 x H2 spectrum per field, and writes the summed
+             lag-gradient spectrum once; the padded correlation image is FP32;
+      "build" what this build's kernels must move: FP64 spectra between the passes (FP32 for the
+             upstream gradient's row spectra and the lag-gradient partials of FP32 plans), the
+             filter in FP64, the plan's dtype for caller arrays, an FP64 correlation image.
+    Per-group partial lag-gradient spectra are an implementation choice and count once."""
     m1, m2, n, M = p.m1, p.m2, p.n, p.M
     P1, P2, F1, H2 = p.P1, p.P2, p.F1, p.info("H2")
+    if model == "s8d":
+        z = zg = zp = 8
+        t, fb, img, ent = 4, 4, 4, 8
+        adj_c = F1
+    else:
+        f32 = p.dtype_code == 1
+        z, zg, zp = 16, (8 if f32 else 16), (8 if f32 else 16)
+        t, fb, img, ent = (4 if f32 else 8), 8, 8, 12
+        adj_c = P1
     return {
-        "ROWS_FWD": B * (H2 * P1 * z + n * 8) + (P1 * P2 + 1) * 4 + n * M * 12,
-        "COLS_CONV": B * (H2 * P1 * z + H2 * m1 * z) + H2 * F1 * 8,
+        "ROWS_FWD": B * (n * 8 + H2 * P1 * z) + n * M * ent + (P1 * P2 + 1) * 4,
+        "COLS_CONV": B * (H2 * P1 * z + H2 * m1 * z) + H2 * F1 * fb,
         "ROWS_INV": B * (H2 * m1 * z + m1 * m2 * t),
-        "ADJ_ROWS_FWD": B * (m1 * m2 * t + H2 * m1 * z),
-        # the summed lag-gradient spectrum once (per-group partials are an implementation choice)
-        "ADJ_COLS": B * (H2 * m1 * z + 2 * H2 * P1 * z) + H2 * F1 * z + H2 * F1 * 8,
-        "ADJ_ROWS_INV": B * (H2 * P1 * z + P1 * P2 * 8),
-        "GATHER": B * (n * M * 8 + n * 8) + n * M * 8 + n * 8,
+        "ADJ_ROWS_FWD": B * (m1 * m2 * t + H2 * m1 * zg),
+        "ADJ_COLS": B * (H2 * m1 * zg + H2 * P1 * z + H2 * adj_c * z) + H2 * F1 * fb + H2 * F1 * zp,
+        "ADJ_ROWS_INV": B * (H2 * P1 * z + P1 * P2 * img),
+        "GATHER": B * (P1 * P2 * img + n * 8) + n * M * 8,
     }
 
 
 def cpu_baseline(w, nfields: int, reps: int = 6):
-    """The FP64 oracle (its FFT variants, single thread) on a bounded sample of fields."""
+    """The FP64 oracle (its FFT variants, single thread) on a bounded sample of fields; also
+    returns the oracle's weights and its outputs for fields 0 .. nfields-1 (y_hat, dy and the
+    summed d lag, with the upstream gradient g = 2 m y_hat rounded to FP32 so that both plans
+    can take the same g), for the error report."""
     from threadpoolctl import threadpool_limits
 
     from oracle.exact import ExactKriging
@@ -87,6 +105,7 @@ def cpu_baseline(w, nfields: int, reps: int = 6):
     from oracle.matern import Matern
     from oracle.rapid import Grid, RapidPredictor, lag_quadrant, rapid_fft
 
+    outs = {"yhat": [], "dy": [], "g": [], "dlag": 0.0}
     with threadpool_limits(limits=1):
         g = Grid(w.m1, w.m2, w.x0, w.y0, w.dx, w.dy, w.L)
         k = Matern(w.sigma2, w.rho, w.nu, w.tau2)
@@ -95,17 +114,43 @@ def cpu_baseline(w, nfields: int, reps: int = 6):
         lag = lag_quadrant(g, k)
         mask = w.extra["mask"]
         t0 = time.perf_counter()
-        for b in [f % w.B for f in range(nfields * reps)]:
+        for it, b in enumerate([f % w.B for f in range(nfields * reps)]):
             c = ek.coef(w.y[b])
             cimg = rp.cstar(c)
             yhat = rapid_fft(g, lag, cimg)
-            gup = 2.0 * mask * yhat
-            ek.coef(grad_coef(rp.A, corr_image_fft(g, lag, gup)))
-            dlag_fft(g, gup, cimg)
+            gup = (2.0 * mask * yhat).astype(np.float32).astype(np.float64)
+            dy = ek.coef(grad_coef(rp.A, corr_image_fft(g, lag, gup)))
+            dl = dlag_fft(g, gup, cimg)
+            if it < nfields:
+                outs["yhat"].append(yhat)
+                outs["dy"].append(dy)
+                outs["g"].append(gup)
+                outs["dlag"] = outs["dlag"] + dl
         dt = time.perf_counter() - t0
-    return {"value": nfields * reps * w.m1 * w.m2 / dt, "unit": "grid predictions/s", "cores": 1, "kind": "oracle",
-            "sample": f"{nfields} of the {w.B} fields x {reps} passes, forward + adjoint (y -> y_hat, g -> dy, d lag) with the "
-                      f"oracle's FP64 FFT variants, one thread, {dt:.1f} s", "host": host_cpu()}
+    res = {"value": nfields * reps * w.m1 * w.m2 / dt, "unit": "grid predictions/s", "cores": 1, "kind": "oracle",
+           "sample": f"{nfields} of the {w.B} fields x {reps} passes, forward + adjoint (y -> y_hat, g -> dy, d lag) with "
+                     f"the oracle's FP64 FFT variants, one thread, {dt:.1f} s", "host": host_cpu()}
+    return res, dict(anchor=np.stack([rp.i0, rp.j0], 1), W=rp.W, **outs)
+
+
+def oracle_errors(torch, krig, w, p, ref, dev):
+    """Relative max errors of one plan against the oracle on identical inputs: the oracle's
+    weights injected (the plan is changed: call after its timings), the same data vectors and
+    the same FP32-rounded upstream gradients.  y_hat per field (max over fields), dy over the
+    fields, d lag summed over them."""
+    nf = len(ref["yhat"])
+    p.set_weights(torch.as_tensor(ref["anchor"], dtype=torch.int32, device=dev),
+                  torch.as_tensor(ref["W"], dtype=torch.float64, device=dev))
+    y = torch.as_tensor(w.y[:nf], dtype=torch.float64, device=dev)
+    alpha = torch.empty(nf, w.n, dtype=torch.float64, device=dev)
+    saved = p.new_saved(nf)
+    yh = p.predict(y, alpha_out=alpha, saved=saved).double().cpu().numpy()
+    gup = torch.as_tensor(np.stack(ref["g"]), dtype=p.tdtype, device=dev)
+    dy, dlag = p.adjoint(gup, alpha=alpha, saved=saved)
+    dy, dlag = dy.cpu().numpy(), dlag.double().cpu().numpy()
+    rel = lambda a, b: float(np.max(np.abs(a - b)) / np.max(np.abs(b)))
+    return {"yhat": max(rel(yh[b], ref["yhat"][b]) for b in range(nf)), "dy": rel(dy, np.stack(ref["dy"])),
+            "dlag": rel(dlag, ref["dlag"])}
 
 
 def host_cpu():
@@ -305,6 +350,31 @@ def nonstat_mode(a, torch, krig, wl, dev):
     return 0
 
 
+def csim_bytes(p, R, model="s8d"):
+    """Algorithmic bytes per launch of the conditional-simulation stages (R realisations,
+    (R + 1) / 2 complex pairs).  The sampler's column pass writes, per pair, the P1 torus rows
+    the padded grid needs (Fs2 columns each) and reads sqrt(Lambda) once; its row pass reads them
+    and writes two realisations; the residual kernel reads each realisation's field at the sites'
+    neighbourhoods (at most the padded grid), the weights and data, and writes the residuals; the
+    prediction passes are those of stage_bytes with B = R, the last adding the field.  Model "s8d":
+    FP32 spectra and fields (the survey's model); "build": the plan's dtype for the sampler and the
+    fields, FP64 spectra in the prediction passes."""
+    P1, P2, n, M, m1, m2 = p.P1, p.P2, p.n, p.M, p.m1, p.m2
+    Fs1, Fs2 = p.info("CE_F1"), p.info("CE_F2")
+    npairs = (R + 1) // 2
+    f32 = p.dtype_code == 1
+    cz, t = (8, 4) if (model == "s8d" or f32) else (16, 8)
+    sb = stage_bytes(p, R, model)
+    return {
+        "CSIM_CE": npairs * Fs2 * P1 * cz + (Fs2 // 2 + 1) * Fs1 * 8,
+        "CSIM_ROWS": npairs * Fs2 * P1 * cz + R * P1 * P2 * t,
+        "GATHER": R * (min(n * M, P1 * P2) * t + n * 8) + n * M * 8 + n * 8,
+        "ROWS_FWD": sb["ROWS_FWD"],
+        "COLS_CONV": sb["COLS_CONV"],
+        "ROWS_INV": sb["ROWS_INV"] + R * m1 * m2 * t,
+    }
+
+
 def csim_mode(a, torch, krig, wl, dev):
     """Batched conditional simulation (krig_csim): R = 256 realisations on a 512 x 512 grid,
     n = 5000 uniform sites, Matern nu = 1.5, range 0.1, nugget 0.01, L = 4.  Each call draws
@@ -331,6 +401,24 @@ def csim_mode(a, torch, krig, wl, dev):
         e.record()
         torch.cuda.synchronize()
         per[dtype] = {"plan_ms": plan_ms, "ms_per_call": s.elapsed_time(e) / a.steps}
+        # per-stage kernel times (HIP events around each launch, same stream)
+        p.timing(True)
+        for _ in range(a.steps):
+            p.csim(R, seed, y)
+        st = p.timing_read()
+        p.timing(False)
+        avg = {k: v[0] / v[1] for k, v in st.items() if v[1] > 0}
+        sb, sbb = csim_bytes(p, R, "s8d"), csim_bytes(p, R, "build")
+        dom = max((k for k in sb if k in avg), key=lambda k: avg[k])
+        per[dtype]["stage_avg_ms"] = {k: round(v, 4) for k, v in avg.items()}
+        per[dtype]["stage_gbs"] = {k: round(sb[k] / (avg[k] * 1e-3) / 1e9, 1) for k in sb if k in avg}
+        per[dtype]["stage_gbs_build"] = {k: round(sbb[k] / (avg[k] * 1e-3) / 1e9, 1) for k in sbb if k in avg}
+        achieved = sb[dom] / (avg[dom] * 1e-3) / 1e9
+        per[dtype]["roofline"] = {
+            "bound": "hbm", "kernel": dom, "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
+            "frac": achieved / HBM_PEAK_GBS, "traffic": recorded_traffic("CSIM_" + dom if not dom.startswith("CSIM") else dom),
+            "bytes_per_launch": sb[dom], "bytes_model": "s8d: FP32 spectra and fields", "avg_launch_ms": avg[dom],
+            "build_bytes_per_launch": sbb[dom], "build_frac": sbb[dom] / (avg[dom] * 1e-3) / 1e9 / HBM_PEAK_GBS}
         p.close()
     ms = per["f32"]["ms_per_call"]
     res = {"metric": "conditional simulation: realisation grid values/s (R fields per call)",
@@ -339,6 +427,7 @@ def csim_mode(a, torch, krig, wl, dev):
            "scaling": "weak", "vs_baseline": None, "dtype": "f64", "io_dtype": "f32", "data": "synthetic",
            "config": {"workload": "csim: R=256 realisations, 512x512 grid on [0,1]^2, n=5000 uniform sites, "
                                   "Matern nu=1.5 range 0.1 nugget 0.01, L=4 (M=64)", "R": R},
+           "roofline": per["f32"]["roofline"],
            "per_dtype": per}
     print(json.dumps(res), flush=True)
     return 0
@@ -826,13 +915,15 @@ def main(argv=None):
     copy_gbs = device_copy_gbs(torch, dev)
     npred = B * w.m1 * w.m2
     value = npred / (r32["ms"] * 1e-3)
-    # dominant single-kernel stage and its roofline
-    G = p32.info("DLAG_GROUP")
-    ng = (B + G - 1) // G
-    sb = stage_bytes(p32, B, ng)
+    # dominant single-kernel stage and its roofline: the survey's FP32-spectra byte model, with
+    # the bytes this build's kernels move (FP64 spectra) beside it
+    sb = stage_bytes(p32, B, "s8d")
+    sbb = stage_bytes(p32, B, "build")
     avg = {k: (v[0] / v[1]) for k, v in r32["stages"].items() if v[1] > 0}
     dom = max((k for k in sb if k in avg), key=lambda k: avg[k])
     achieved = sb[dom] / (avg[dom] * 1e-3) / 1e9
+    graded = [k for k in sb if k in avg]  # scatter, transform and gather passes
+    graded_s = sum(avg[k] * r32["stages"][k][1] / a.steps for k in graded) * 1e-3
     out = {
         "metric": "grid predictions/s fwd+adjoint, FP32 vs FP64 at rel err <=1e-5; % HBM peak",
         "value": value,
@@ -844,7 +935,8 @@ def main(argv=None):
         "higher_is_better": True,
         "scaling": "weak",
         "vs_baseline": None,
-        # both plans compute in FP64; the FP32 plan's lag, g, y_hat and d lag are FP32
+        # both plans compute in FP64; the FP32 plan's lag, g, y_hat and d lag are FP32, and its
+        # adjoint stores the upstream gradient's row spectra and the lag-gradient partials in FP32
         "dtype": "f64",
         "io_dtype": "f32",
         "data": "synthetic",
@@ -854,7 +946,18 @@ def main(argv=None):
                    "B": B, "n": w.n, "grid": [w.m1, w.m2], "L": w.L, "fft": [p32.F1, p32.F2]},
         "roofline": {"bound": "hbm", "kernel": dom, "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
                      "frac": achieved / HBM_PEAK_GBS, "traffic": recorded_traffic(dom),
-                     "bytes_per_launch": sb[dom], "avg_launch_ms": avg[dom]},
+                     "bytes_per_launch": sb[dom], "bytes_model": "s8d: FP32 spectra (the survey's model)",
+                     "avg_launch_ms": avg[dom],
+                     "build_bytes_per_launch": sbb[dom],
+                     "build_frac": sbb[dom] / (avg[dom] * 1e-3) / 1e9 / HBM_PEAK_GBS,
+                     "build_bytes_model": "the bytes this build's kernels move: FP64 spectra between the passes"},
+        # every scatter, transform and gather pass of the step together (FP64 solves and the lag-gradient
+        # tail excluded): s8d bytes over their summed kernel time
+        "graded_passes": {"bytes_s8d": sum(sb[k] for k in graded), "ms": graded_s * 1e3,
+                          "gbs": sum(sb[k] for k in graded) / graded_s / 1e9,
+                          "frac": sum(sb[k] for k in graded) / graded_s / 1e9 / HBM_PEAK_GBS,
+                          "build_frac": sum(sbb[k] for k in graded) / graded_s / 1e9 / HBM_PEAK_GBS,
+                          "bytes_per_prediction_s8d": sum(sb[k] for k in graded) / npred},
         "launch": "HIP graph replay of one recorded step" if a.graph else "call loop",
         # the same step recorded once as a HIP graph and replayed (on this stack the graph
         # is not faster than the call loop's launches)
@@ -868,6 +971,7 @@ def main(argv=None):
         # a plain device-to-device copy on the same GPU (reads + writes), beside the HBM peak
         "device_copy_gbs": copy_gbs,
         "stage_gbs": {k: round(sb[k] / (avg[k] * 1e-3) / 1e9, 1) for k in sb if k in avg},
+        "stage_gbs_build": {k: round(sbb[k] / (avg[k] * 1e-3) / 1e9, 1) for k in sbb if k in avg},
     }
     if "f64" in res:
         r64 = res["f64"]
@@ -878,7 +982,14 @@ def main(argv=None):
             "yhat": max(rel(r32["yhat"][b], r64["yhat"][b]) for b in range(B)),
             "dy": rel(r32["dy"], r64["dy"]), "dlag": rel(r32["dlag"], r64["dlag"])}
     if not a.no_cpu_baseline:
-        out["cpu_baseline"] = cpu_baseline(w, a.cpu_fields)
+        out["cpu_baseline"], ref = cpu_baseline(w, a.cpu_fields)
+        # errors against the FP64 oracle on identical inputs (after all timings: the oracle's
+        # weights are injected into the plans)
+        out["max_rel_err_vs_oracle"] = {d: oracle_errors(torch, krig, w, res[d]["plan"], ref, dev) for d in res}
+        out["max_rel_err_vs_oracle"]["inputs"] = (
+            f"fields 0..{len(ref['yhat']) - 1}; the oracle's weights, data and FP32-rounded upstream gradient")
+        out["max_rel_err_vs_oracle"]["bars"] = {"f32": {"yhat": 1e-5, "dy": 1e-6, "dlag": 1e-5},
+                                                "f64": {"yhat": 1e-12}}
     print(json.dumps(out), flush=True)
     return 0
 

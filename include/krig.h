@@ -338,7 +338,8 @@ enum {
   KRIG_STAGE_GATHER,         /* adjoint: gather at the neighbours (d alpha) */
   KRIG_STAGE_SOLVE,          /* FP64 applications of the inverse Cholesky factor */
   KRIG_STAGE_DLAG_TAIL,      /* lag gradient: inverse transforms of the summed spectra + fold */
-  KRIG_STAGE_CSIM_CE,        /* conditional simulation: circulant-embedding sampler (2 passes) */
+  KRIG_STAGE_CSIM_CE,        /* conditional simulation: sampler noise and column transforms */
+  KRIG_STAGE_CSIM_ROWS,      /* conditional simulation: sampler row transforms (two realisations) */
   KRIG_STAGE_COUNT
 };
 

@@ -34,7 +34,7 @@ EXPORTS = ["krig_plan_create", "krig_plan_destroy", "krig_plan_info", "krig_set_
            "krig_batch_launch", "krig_batch_destroy", "krig_timing_enable", "krig_timing_read", "krig_strerror"]
 
 STAGES = ["ROWS_FWD", "COLS_CONV", "ROWS_INV", "ADJ_ROWS_FWD", "ADJ_COLS", "ADJ_ROWS_INV", "GATHER", "SOLVE",
-          "DLAG_TAIL", "CSIM_CE"]
+          "DLAG_TAIL", "CSIM_CE", "CSIM_ROWS"]
 
 
 class KrigError(RuntimeError):

@@ -1586,6 +1586,9 @@ int krig_csim(krig_plan p, int32_t R, uint64_t seed, const double* d_y, void* d_
     c.twF = f32 ? (const void*)p->tws1_32 : (const void*)p->tws1_64;
     c.NL = nl_cols_for(p->es1, csz(p));
     KRIG_TRY((f32 ? p->es1->k.ce_cols32 : p->es1->k.ce_cols64)(c, npairs, p->st));
+  }
+  {
+    StageTimer t(p, KRIG_STAGE_CSIM_ROWS);
     // pass 2: transforms over the torus rows -> two realisations per pair
     RowsCEArgs o{};
     o.nrows = p->P1;
