@@ -96,7 +96,8 @@ enum {
   KRIG_INFO_FFT_VARIANTS_COLS,
   KRIG_INFO_FFT_VARIANT_ROWS,  /* form in use, 1-based (1: the default form) */
   KRIG_INFO_FFT_VARIANT_COLS,
-  KRIG_INFO_SOLVE_NOALLOC_MAX_B /* largest B krig_solve_noalloc accepts for this plan (0: none) */
+  KRIG_INFO_SOLVE_NOALLOC_MAX_B, /* largest B krig_solve_noalloc accepts for this plan (0: none) */
+  KRIG_INFO_FILTER_SETUP         /* how the plan's filter spectrum was built (KRIG_FILTER_*) */
 };
 
 /*
@@ -156,6 +157,25 @@ int krig_set_weights(krig_plan p, const int32_t *d_anchor, const double *d_W);
  * Asynchronous on the plan's stream; d_kvec is read before the call's work completes.
  */
 int krig_set_kvec(krig_plan p, const double *d_kvec);
+
+/*
+ * The plan's filter spectrum (Step 2): its construction, and an optional export.
+ *  KRIG_FILTER_REFLECTED (plan_create's): the lag quadrant reflected evenly into the
+ *    F1 x F2 torus (zeros beyond the quadrant), transformed;
+ *  KRIG_FILTER_CENTERED: the alternative the remark after Step 7 describes, which avoids the
+ *    reflections at the price of one more transform: the covariance between the torus centre
+ *    node (F1/2, F2/2) and every torus node from plain coordinate differences, transformed and
+ *    divided by the transform of the centre's indicator.  It fills every lag up to half the
+ *    torus, so the spectrum differs from the reflected one; the kept predictions agree to
+ *    rounding (lags beyond the quadrant never reach them).
+ * Switching rebuilds the spectrum (FP64, on the plan's stream) for later calls that use the
+ * plan's own lag image (caller lag images are always reflected).  d_spec: NULL, or device
+ * [H2][F1] FP64 receiving the spectrum scaled by 1/(F1 F2) (frequency k2 < H2 of the row
+ * transforms major, then k1 < F1).  KRIG_EINVAL for another setup value or while a recorded
+ * batch holds the plan.
+ */
+enum { KRIG_FILTER_REFLECTED = 0, KRIG_FILTER_CENTERED = 1 };
+int krig_filter(krig_plan p, int32_t setup, double *d_spec);
 
 /* Export the lag quadrant (m1+L) x (m2+L) in dt (Step 2's filter). */
 int krig_lag(krig_plan p, void *d_lag);

@@ -18,7 +18,9 @@ P1 x P2 node set in an Fs1 x Fs2 torus with minimal-image lags
 Re Y and Im Y are two independent draws with the embedded covariance.  The
 embedding can have small negative eigenvalues when the range is large
 relative to the torus (the paper's caveat); the reading used here clamps them
-to zero when min(Lambda) >= -1e-6 max(Lambda) and rejects the size otherwise.
+to zero when min(Lambda) >= -1e-6 max(Lambda) and otherwise enlarges the torus:
+both axes move to their next even 2^a 3^b size, up to twice the first size
+(`ce_torus`); beyond that the embedding fails.
 """
 from __future__ import annotations
 
@@ -27,9 +29,14 @@ import numpy as np
 from . import philox
 from .exact import ExactKriging
 from .matern import Matern
-from .rapid import Grid, RapidPredictor, offsets, lag_quadrant, rapid_fft
+from .rapid import Grid, RapidPredictor, fft_len, offsets, lag_quadrant, rapid_fft
 
 CE_CLAMP_TOL = 1e-6
+CE_MAX_GROWTH = 2
+
+
+class CEFailure(ValueError):
+    """The circulant embedding has eigenvalues below -CE_CLAMP_TOL of the largest."""
 
 
 def ce_eigs(grid: Grid, kern: Matern, Fs1: int, Fs2: int):
@@ -49,9 +56,25 @@ def ce_eigs(grid: Grid, kern: Matern, Fs1: int, Fs2: int):
     lmax = lam.max()
     lmin = lam.min()
     if lmin < -CE_CLAMP_TOL * lmax:
-        raise ValueError("circulant embedding not non-negative definite")
+        raise CEFailure("circulant embedding not non-negative definite")
     nclamp = int(np.sum(lam < 0))
     return np.maximum(lam, 0.0), nclamp, lmin / lmax
+
+
+def ce_torus(grid: Grid, kern: Matern):
+    """The embedding torus (Fs1, Fs2): the smallest even 2^a 3^b sizes >= 2(P - 1) per axis,
+    then, while the embedding fails the clamp tolerance, both axes at their next even 2^a 3^b
+    size, up to CE_MAX_GROWTH times the first sizes.  Raises CEFailure when none qualifies."""
+    F10 = fft_len(2 * (grid.P1 - 1))
+    F20 = fft_len(2 * (grid.P2 - 1))
+    F1, F2 = F10, F20
+    while F1 <= CE_MAX_GROWTH * F10 and F2 <= CE_MAX_GROWTH * F20:
+        try:
+            ce_eigs(grid, kern, F1, F2)
+            return F1, F2
+        except CEFailure:
+            F1, F2 = fft_len(F1 + 1), fft_len(F2 + 1)
+    raise CEFailure(f"no torus up to {CE_MAX_GROWTH}x ({F10} x {F20}) embeds the covariance")
 
 
 def ce_pair(lam: np.ndarray, seed: int, pair: int, P1: int, P2: int):

@@ -268,6 +268,37 @@ def rapid_fft(grid: Grid, lag: np.ndarray, cimg: np.ndarray) -> np.ndarray:
     return Y[grid.L:grid.L + grid.m1, grid.L:grid.L + grid.m2]
 
 
+def filter_spectrum_reflected(lag: np.ndarray, F1: int, F2: int) -> np.ndarray:
+    """Step 2's filter spectrum: the 2-D DFT of the even reflection of the lag quadrant (real,
+    F1 x F2).  TEST-ONLY FFT form, as rapid_fft uses it."""
+    return np.fft.fft2(embed_even(lag, F1, F2)).real
+
+
+def filter_spectrum_centered(grid: Grid, kern: Matern, F1: int, F2: int) -> np.ndarray:
+    """The alternative filter set-up of the remark after Step 7, which avoids the reflections at
+    the price of one more FFT: evaluate the covariance between the torus centre node
+    (F1/2, F2/2) and every torus node from plain coordinate differences, take its 2-D DFT and
+    divide by the DFT of the indicator of the centre node (which removes the centre's phase).
+    Every lag up to half the torus is filled, so the middle of the filter image differs from
+    the reflected quadrant's zeros; those lags never reach a kept output (reading of Step 2)."""
+    r = (np.arange(F1) - F1 // 2) * grid.dx
+    c = (np.arange(F2) - F2 // 2) * grid.dy
+    img = kern.of_lag(r[:, None], c[None, :])
+    delta = np.zeros((F1, F2))
+    delta[F1 // 2, F2 // 2] = 1.0
+    return np.fft.fft2(img) / np.fft.fft2(delta)
+
+
+def rapid_fft_spectrum(grid: Grid, spec: np.ndarray, cimg: np.ndarray) -> np.ndarray:
+    """Step 7 with a given F1 x F2 filter spectrum (numpy FP64 FFT, TEST-ONLY): the kept
+    outputs of ifft2(spec * fft2(C~))."""
+    F1, F2 = spec.shape
+    C = np.zeros((F1, F2))
+    C[:grid.P1, :grid.P2] = cimg
+    Y = np.fft.ifft2(spec * np.fft.fft2(C)).real
+    return Y[grid.L:grid.L + grid.m1, grid.L:grid.L + grid.m2]
+
+
 class RapidPredictor:
     """Steps 1-7 for one site set: weights once, then many coefficient vectors."""
 

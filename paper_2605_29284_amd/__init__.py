@@ -22,14 +22,15 @@ KRIG_F64 = 2
 INFO = dict(N=1, M=2, P1=3, P2=4, F1=5, F2=6, H2=7, LDH=8, SAVED_PER_FIELD=9, KN_STATUS=10,
             PIVOT=11, DTYPE=12, CE_CLAMPED=13, DLAG_GROUP=14, CE_F1=15, CE_F2=16, NL_ROWS64=17,
             NL_COLS64=18, FFT_R1=19, FFT_R2=20, FFT_R3=21, FFT_VARIANTS_ROWS=22, FFT_VARIANTS_COLS=23,
-            FFT_VARIANT_ROWS=24, FFT_VARIANT_COLS=25, SOLVE_NOALLOC_MAX_B=26)
+            FFT_VARIANT_ROWS=24, FFT_VARIANT_COLS=25, SOLVE_NOALLOC_MAX_B=26, FILTER_SETUP=27)
+FILTER = dict(reflected=0, centered=1)
 TUNE = dict(DLAG_GROUP=1, NL_ROWS64=2, NL_COLS64=3, FFT_ROWS=4, FFT_COLS=5)
 
 STATUS = {0: "KRIG_OK", -1: "KRIG_EINVAL", -2: "KRIG_EDOMAIN", -3: "KRIG_ENOTSPD", -4: "KRIG_ECE",
           -5: "KRIG_ENOMEM", -6: "KRIG_EHIP", -7: "KRIG_EUNSUPPORTED"}
 
 EXPORTS = ["krig_plan_create", "krig_plan_destroy", "krig_plan_info", "krig_set_stream", "krig_weights",
-           "krig_set_weights", "krig_set_kvec", "krig_lag", "krig_solve", "krig_solve_noalloc", "krig_scatter", "krig_convolve", "krig_predict",
+           "krig_set_weights", "krig_set_kvec", "krig_lag", "krig_filter", "krig_solve", "krig_solve_noalloc", "krig_scatter", "krig_convolve", "krig_predict",
            "krig_predict_adjoint", "krig_csim", "krig_interp", "krig_predict_exact", "krig_exact_at", "krig_kernel_at", "krig_mixture", "krig_predict_universal", "krig_plan_tune", "krig_plan_autotune", "krig_predict_many", "krig_batch_create",
            "krig_batch_launch", "krig_batch_destroy", "krig_timing_enable", "krig_timing_read", "krig_strerror"]
 
@@ -75,6 +76,7 @@ def load_library(path: str = LIB_PATH) -> ctypes.CDLL:
         "krig_set_weights": [vp, dp, dp],
         "krig_set_kvec": [vp, dp],
         "krig_lag": [vp, dp],
+        "krig_filter": [vp, i32, dp],
         "krig_solve": [vp, i32, dp, dp],
         "krig_solve_noalloc": [vp, i32, dp, dp],
         "krig_scatter": [vp, i32, dp, dp],
@@ -218,6 +220,15 @@ class Plan:
         out = self.empty(self.m1 + self.L, self.m2 + self.L)
         self._stream()
         _check(self.lib.krig_lag(self.h, out.data_ptr()), "krig_lag")
+        return out
+
+    def filter(self, setup: str = None):
+        """The filter spectrum [H2][F1] FP64 (scaled by 1/(F1 F2)); setup "reflected" or "centered"
+        rebuilds it first (krig_filter)."""
+        out = self.empty(self.info("H2"), self.F1, dtype=self.torch.float64)
+        s = self.info("FILTER_SETUP") if setup is None else FILTER[setup]
+        self._stream()
+        _check(self.lib.krig_filter(self.h, s, out.data_ptr()), "krig_filter")
         return out
 
     def solve(self, y):

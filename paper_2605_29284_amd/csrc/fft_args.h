@@ -149,6 +149,8 @@ struct FftSet {
   launch_rows_c2r_t c2r_fold32;     // inverse rows of the compact correlation, sign images
   launch_rows_c2r_t c2r_fold64;     //   folded, FP64 arithmetic -> FP32 / FP64 lag gradient
   launch_rows_r2c_t r2c_cov;        // covariance on the embedding torus, FP64
+  launch_rows_r2c_t r2c_center;     // covariance about the torus centre (F1/2, F2/2), plain coordinates
+  launch_rows_r2c_t r2c_delta;      // indicator of the torus centre
   launch_cols_t ce_cols32, ce_cols64;    // sampler pass 1 (noise x sqrt(Lambda), column transforms)
   launch_rows_ce_t ce_rows32, ce_rows64; // sampler pass 2 (row transforms -> two realisations)
 };

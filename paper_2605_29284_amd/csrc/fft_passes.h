@@ -311,7 +311,7 @@ __device__ __forceinline__ void xf_inv(cx<TC> (&w)[R3], int t, cx<TC>* L, const 
 // ----------------------------------------------------------------------------------------
 // row kernels: forward (real rows -> frequency-major half spectra)
 // ----------------------------------------------------------------------------------------
-enum { SRC_CSR = 0, SRC_DENSE = 1, SRC_LAG = 2, SRC_COV = 3 };
+enum { SRC_CSR = 0, SRC_DENSE = 1, SRC_LAG = 2, SRC_COV = 3, SRC_CENTER = 4, SRC_DELTA = 5 };
 
 template <typename TC, typename TIN, typename TS, int R1, int R2, int R3, int SRC>
 KRIG_ROW_KERNEL k_rows_r2c(RowsR2CArgs a) {
@@ -387,6 +387,26 @@ KRIG_ROW_KERNEL k_rows_r2c(RowsR2CArgs a) {
           if (oka) xa = (TC)d[(int64_t)ra * a.dense_ld + cc];
           if (okb) xb = (TC)d[(int64_t)rb * a.dense_ld + cc];
         }
+      } else if constexpr (SRC == SRC_CENTER) {  // covariance about the torus centre, plain coordinates
+        const int F2 = G::F;
+        MaternDev mt;
+        mt.sigma2 = a.cov_sigma2;
+        mt.rho = a.cov_rho;
+        mt.tau2 = 0.0;
+        mt.kind = a.cov_kind;
+        const double hw = (double)(c - F2 / 2) * a.cov_dy;
+        if (oka) {
+          const double hu = (double)(ra - a.F1 / 2) * a.cov_dx;
+          xa = (TC)matern_cov(sqrt(hu * hu + hw * hw), mt);
+        }
+        if (okb) {
+          const double hu = (double)(rb - a.F1 / 2) * a.cov_dx;
+          xb = (TC)matern_cov(sqrt(hu * hu + hw * hw), mt);
+        }
+      } else if constexpr (SRC == SRC_DELTA) {  // indicator of the torus centre
+        const bool cc = c == G::F / 2;
+        xa = (TC)((cc && oka && ra == a.F1 / 2) ? 1 : 0);
+        xb = (TC)((cc && okb && rb == a.F1 / 2) ? 1 : 0);
       } else if constexpr (SRC == SRC_COV) {  // torus covariance with minimal-image lags
         const int F2 = G::F;
         MaternDev mt;
@@ -991,6 +1011,8 @@ FftEntry make_fft_entry() {
   k.c2r_fold32 = launch_rows_c2r_fold<double, float, R1, R2, R3>;
   k.c2r_fold64 = launch_rows_c2r_fold<double, double, R1, R2, R3>;
   k.r2c_cov = launch_rows_r2c<double, double, double, R1, R2, R3, SRC_COV>;
+  k.r2c_center = launch_rows_r2c<double, double, double, R1, R2, R3, SRC_CENTER>;
+  k.r2c_delta = launch_rows_r2c<double, double, double, R1, R2, R3, SRC_DELTA>;
   k.ce_cols32 = launch_cols<float, float, S32, R1, R2, R3, COL_CE>;
   k.ce_cols64 = launch_cols<double, double, S64, R1, R2, R3, COL_CE>;
   k.ce_rows32 = launch_rows_ce<float, float, float, R1, R2, R3>;

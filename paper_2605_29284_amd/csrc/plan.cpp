@@ -59,6 +59,7 @@ struct krig_plan_s {
   double* lag64 = nullptr;
   void* lagT = nullptr;
   double* filt = nullptr;  // [H2][F1] filter spectrum / (F1 F2), FP64
+  int filt_setup = KRIG_FILTER_REFLECTED;  // how filt was built
   double* KN = nullptr;     // K_N as factored (jitter included when it was needed)
   double* LinvN = nullptr;
   int* d_status = nullptr;   // [0] K_N status, [1] M pivot
@@ -332,6 +333,50 @@ int make_filter(krig_plan p, const double* lag64, double* filt_out) {
   c.scale = 1.0 / ((double)p->F1 * (double)p->F2);
   c.NL = nl_cols_for(p->e1, 16);
   KRIG_TRY(p->e1->k.fwd_real64(c, 1, p->st));
+  return KRIG_OK;
+}
+
+// The alternative set-up of the remark after Step 7 (no reflection, one more transform): the
+// covariance between the torus centre node (F1/2, F2/2) and every torus node from plain
+// coordinate differences, transformed, divided by the transform of the centre's indicator.
+// Both transforms keep the real parts: the centred image is even about the centre, so its
+// transform is the filter spectrum times the centre's real phase (-1)^(k1 + k2), which the
+// indicator's transform holds.  Every lag up to half the torus is filled (the reflected
+// construction has zeros beyond the quadrant); those lags never reach a kept output.
+int make_filter_centered(krig_plan p, double* filt_out) {
+  for (int pass = 0; pass < 2; ++pass) {
+    RowsR2CArgs r{};
+    r.nrows = p->F1;
+    r.H2 = p->H2;
+    r.out = p->phiS64;
+    r.out_fs = 0;
+    r.out_ld = p->F1;
+    r.twF = p->tw2_64;
+    r.F1 = p->F1;
+    r.cov_sigma2 = p->mt.sigma2;
+    r.cov_rho = p->mt.rho;
+    r.cov_dx = p->g.dx;
+    r.cov_dy = p->g.dy;
+    r.cov_kind = p->mt.kind;
+    r.NL = nl_rows_for(p->e2, 16);
+    KRIG_TRY((pass == 0 ? p->e2->k.r2c_center : p->e2->k.r2c_delta)(r, 1, p->st));
+    ColsArgs c{};
+    c.H2 = p->H2;
+    c.in = p->phiS64;
+    c.in_fs = 0;
+    c.in_ld = p->F1;
+    c.in_off = 0;
+    c.in_cnt = p->F1;
+    c.out = pass == 0 ? filt_out : p->filtC;  // filtC: scratch for the indicator's transform
+    c.out_fs = 0;
+    c.out_ld = p->F1;
+    c.twF = p->tw1_64;
+    c.twI = p->tw1_64;
+    c.scale = pass == 0 ? 1.0 / ((double)p->F1 * (double)p->F2) : 1.0;
+    c.NL = nl_cols_for(p->e1, 16);
+    KRIG_TRY(p->e1->k.fwd_real64(c, 1, p->st));
+  }
+  KRIG_TRY(div_f64(filt_out, p->filtC, (int64_t)p->H2 * p->F1, p->st));
   return KRIG_OK;
 }
 
@@ -979,6 +1024,7 @@ int krig_plan_info(krig_plan p, int32_t what, int64_t* v) {
     case KRIG_INFO_CE_F1: *v = p->Fs1; break;
     case KRIG_INFO_CE_F2: *v = p->Fs2; break;
     case KRIG_INFO_SOLVE_NOALLOC_MAX_B: *v = solve_noalloc_max_B(p->n); break;
+    case KRIG_INFO_FILTER_SETUP: *v = p->filt_setup; break;
     default: return KRIG_EINVAL;
   }
   return KRIG_OK;
@@ -1021,6 +1067,20 @@ int krig_set_kvec(krig_plan p, const double* d_kvec) {
   if (r != KRIG_OK) return r;
   // the anchors are unchanged, so the scatter structure is too: only its weights are rewritten
   KRIG_TRY(refill_csr_weights(p->g, p->anchor, p->W, p->node_ptr, p->ent_site, p->ent_w, p->st));
+  return KRIG_OK;
+}
+
+int krig_filter(krig_plan p, int32_t setup, double* d_spec) {
+  if (!p || (setup != KRIG_FILTER_REFLECTED && setup != KRIG_FILTER_CENTERED)) return KRIG_EINVAL;
+  if (p->batch_refs > 0) return KRIG_EINVAL;  // a recorded batch replays with the current filter
+  if (setup != p->filt_setup) {
+    const int r = setup == KRIG_FILTER_CENTERED ? make_filter_centered(p, p->filt) : make_filter(p, p->lag64, p->filt);
+    if (r != KRIG_OK) return r;
+    p->filt_setup = setup;
+  }
+  if (d_spec)
+    KRIG_TRY(hipMemcpyAsync(d_spec, p->filt, sizeof(double) * (size_t)p->H2 * p->F1, hipMemcpyDeviceToDevice,
+                            p->st));
   return KRIG_OK;
 }
 

@@ -69,5 +69,7 @@ hipError_t csim_residual(const GridDev& g, const int32_t* anchor, const double* 
 hipError_t minmax_blocks(const double* x, int64_t cnt, double* bmin, double* bmax, int* bneg, int nblocks,
                          hipStream_t st);
 hipError_t sqrt_clamp(double* x, int64_t cnt, double scale, hipStream_t st);
+// x <- x / d (the reflection-free filter set-up divides out the centre's phase)
+hipError_t div_f64(double* x, const double* d, int64_t cnt, hipStream_t st);
 
 }  // namespace krig

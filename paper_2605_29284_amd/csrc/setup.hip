@@ -577,4 +577,15 @@ hipError_t sqrt_clamp(double* x, int64_t cnt, double scale, hipStream_t st) {
   return hipGetLastError();
 }
 
+// x <- x / d, element by element
+__global__ void k_div(double* x, const double* d, int64_t cnt) {
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < cnt) x[i] = x[i] / d[i];
+}
+
+hipError_t div_f64(double* x, const double* d, int64_t cnt, hipStream_t st) {
+  hipLaunchKernelGGL(k_div, dim3(nblk(cnt)), dim3(256), 0, st, x, d, cnt);
+  return hipGetLastError();
+}
+
 }  // namespace krig

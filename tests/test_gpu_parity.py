@@ -220,6 +220,41 @@ def test_predict_paper_field_f64_identical_weights(krig, paper):
     check("predict paper field f64, identical weights", relmax(y, ref), BAR_F64)
 
 
+@pytest.mark.parametrize("which", ["small", "paper"])
+def test_reflection_free_filter_setup(krig, small, paper, which):
+    """krig_filter: the reflected filter spectrum and the reflection-free one of the remark after
+    Step 7 (covariance about the torus centre, one more transform) against the oracle's, and the
+    predictions through the latter against the oracle (direct sum on the small field, the same
+    spectrum's FFT form on the paper field); switching back restores the predictions bit for bit."""
+    from oracle.rapid import fft_len, filter_spectrum_centered, filter_spectrum_reflected, rapid_fft_spectrum
+    w, (g, k, rp, ek) = small if which == "small" else paper
+    dtype = "f64" if which == "small" else "f32"
+    say("reflection-free filter set-up", which, dtype)
+    p = krig.plan_for(w, dtype)
+    p.set_weights(dev(np.stack([rp.i0, rp.j0], 1), torch.int32), dev(rp.W))
+    F1, F2 = p.F1, p.info("F2")
+    assert (F1, F2) == (fft_len(g.m1 + g.P1 - 1), fft_len(g.m2 + g.P2 - 1))
+    H2 = F2 // 2 + 1
+    alpha = ek.coef(w.y[:1])
+    y0 = host(p.convolve(dev(alpha)))[0]
+    s_ref = filter_spectrum_reflected(lag_quadrant(g, k), F1, F2)[:, :H2].T / (F1 * F2)
+    s_cen = filter_spectrum_centered(g, k, F1, F2).real
+    assert p.info("FILTER_SETUP") == 0
+    res = [(f"filter spectrum, reflected, {which}", relmax(host(p.filter()), s_ref), 1e-13)]
+    res.append((f"filter spectrum, centred (reflection-free), {which}",
+                relmax(host(p.filter("centered")), s_cen[:, :H2].T / (F1 * F2)), 1e-13))
+    assert p.info("FILTER_SETUP") == 1
+    y1 = host(p.convolve(dev(alpha)))[0]
+    cimg = rp.cstar(alpha[0])
+    ref = rapid_direct(g, k, cimg).reshape(g.m1, g.m2) if which == "small" else rapid_fft_spectrum(g, s_cen, cimg)
+    res.append((f"prediction through the centred filter, {which} {dtype}", relmax(y1, ref), bar_for(dtype)))
+    res.append((f"centred vs reflected filter: predictions, {which} {dtype}", relmax(y1, y0), bar_for(dtype)))
+    check_all(res)
+    p.filter("reflected")
+    assert np.array_equal(host(p.convolve(dev(alpha)))[0], y0)
+    p.close()
+
+
 def test_custom_lag_equals_plan_lag(krig, small):
     w, (g, k, rp, ek) = small
     say("custom lag == plan lag")
@@ -652,6 +687,47 @@ def test_csim_realisation_parity(krig, dtype):
         check(f"csim realisation {r} {dtype}", relmax(f[r], ref), 1e-9 if dtype == "f64" else 1e-4)
     f2 = host(p.csim(R, seed, dev(w.y[0])))
     assert np.array_equal(f, f2)  # same seed, same fields
+
+
+def test_csim_torus_growth_and_embedding_failure(krig):
+    """A range near the domain size: the library enlarges the embedding torus as the oracle's
+    rule does (12 x 14 grid, range 0.2: 32^2 and 36^2 fail the clamp tolerance, 48^2 embeds) and
+    its realisations match the oracle's on that torus; with range 0.3 on an 8 x 9 grid no torus up
+    to twice the first embeds the covariance and krig_csim returns KRIG_ECE."""
+    from oracle.csim import CEFailure, ConditionalSimulator, ce_torus
+    rng = np.random.default_rng(31)
+    say("csim torus growth 12x14 range 0.2")
+    sites = np.stack([rng.uniform(0, 1, 10), rng.uniform(0, 1.1, 10)], 1)
+    w = wl.Workload("ce growth", 12, 14, 0.0, 0.0, 1 / 11, 1.1 / 13, 1, 1.0, 0.2, 1.5, 0.01, sites,
+                    rng.standard_normal((1, 10)), 31)
+    g, k, rp, ek = oracle_of(w)
+    Fs = ce_torus(g, k)
+    p = krig.plan_for(w, "f64")
+    p.set_weights(dev(np.stack([rp.i0, rp.j0], 1), torch.int32), dev(rp.W))
+    f = host(p.csim(4, 777, dev(w.y[0])))
+    assert (p.info("CE_F1"), p.info("CE_F2")) == Fs == (48, 48)
+    cs = ConditionalSimulator(g, k, sites, *Fs)
+    assert p.info("CE_CLAMPED") == cs.nclamp
+    check_all([(f"csim after torus growth, realisation {r} f64", relmax(f[r], cs.realisation(777, r, w.y[0])), 1e-9)
+               for r in range(4)])
+    p.close()
+    say("csim embedding failure 8x9 range 0.3")
+    w2 = wl.Workload("ce failure", 8, 9, 0.0, 0.0, 1 / 7, 1.1 / 8, 1, 1.0, 0.3, 2.5, 0.01, sites * [1.0, 1.0],
+                     w.y, 31)
+    g2, k2, _, _ = oracle_of(w2)
+    with pytest.raises(CEFailure):
+        ce_torus(g2, k2)
+    q = krig.plan_for(w2, "f64")
+    with pytest.raises(krig.KrigError) as e:
+        q.csim(2, 777, dev(w2.y[0]))
+    assert e.value.status == -4  # KRIG_ECE
+    assert q.info("CE_F1") == 0  # no torus was kept
+    # the plan stays usable
+    check("prediction after an embedding failure f64", relmax(host(q.predict(dev(w2.y)))[0],
+                                                             oracle_of(w2)[2].predict_direct(
+                                                                 oracle_of(w2)[3].coef(w2.y[0])).reshape(8, 9)),
+          BAR_F64 * 100)
+    q.close()
 
 
 def test_csim_batch_matches_kriging_standard_errors(krig):

@@ -8,8 +8,9 @@ from scipy import special
 from oracle import philox
 from oracle.exact import ExactKriging, gp_draw
 from oracle.matern import Matern, phi, phi_closed, phi_general
-from oracle.rapid import (Grid, RapidPredictor, conv_lag_direct, cstar_image, embed_even, fft_len, grid_unit,
-                          kn_matrix, kvecs, lag_quadrant, neighbour_weights, offsets, rapid_direct, rapid_fft,
+from oracle.rapid import (Grid, RapidPredictor, conv_lag_direct, cstar_image, embed_even, fft_len,
+                          filter_spectrum_centered, filter_spectrum_reflected, grid_unit, kn_matrix, kvecs,
+                          lag_quadrant, neighbour_weights, offsets, rapid_direct, rapid_fft, rapid_fft_spectrum,
                           site_cells, sparse_A)
 
 GOLD = os.path.join(os.path.dirname(__file__), "golden")
@@ -187,6 +188,35 @@ def test_direct_convolution_matches_brute_force_and_delta():
     sc = np.abs(y1).max()
     assert np.abs(y1 - y2).max() < 1e-13 * sc
     assert np.abs(y1 - y3).max() < 1e-13 * sc
+
+
+def test_reflection_free_filter_setup():
+    """The remark after Step 7: the filter spectrum from the covariance about the torus centre
+    and one extra FFT (the centre indicator's) instead of reflecting the lag quadrant."""
+    g, k, s, rng = _tiny_problem(2)
+    F1, F2 = fft_len(g.m1 + g.P1 - 1), fft_len(g.m2 + g.P2 - 1)
+    cen = filter_spectrum_centered(g, k, F1, F2)
+    # the centred image is even about the centre, so after the phase is divided out the
+    # spectrum is real
+    assert np.abs(cen.imag).max() < 1e-13 * np.abs(cen.real).max()
+    # it is the spectrum of the full minimal-image lag table (every lag up to half the torus)
+    full = k.of_lag(np.arange(F1 // 2 + 1)[:, None] * g.dx, np.arange(F2 // 2 + 1)[None, :] * g.dy)
+    ref = np.fft.fft2(embed_even(full, F1, F2)).real
+    assert np.abs(cen.real - ref).max() < 1e-13 * np.abs(ref).max()
+    # it differs from the reflected quadrant's spectrum (middle lags filled), yet the kept
+    # outputs are the direct sum's, as the reflected filter's are
+    refl = filter_spectrum_reflected(lag_quadrant(g, k), F1, F2)
+    assert np.abs(cen.real - refl).max() > 1e-6 * np.abs(refl).max()
+    cimg = rng.standard_normal((g.P1, g.P2))
+    y0 = rapid_direct(g, k, cimg).reshape(g.m1, g.m2)
+    sc = np.abs(y0).max()
+    assert np.abs(rapid_fft_spectrum(g, cen.real, cimg) - y0).max() < 1e-13 * sc
+    assert np.abs(rapid_fft_spectrum(g, refl, cimg) - y0).max() < 1e-13 * sc
+    # a delta at padded (3, 5) gives the shifted covariance through the centred filter too
+    d = np.zeros((g.P1, g.P2))
+    d[3, 5] = 1.0
+    a, b = np.meshgrid(np.arange(g.m1), np.arange(g.m2), indexing="ij")
+    assert np.abs(rapid_fft_spectrum(g, cen.real, d) - k.of_lag((a + g.L - 3) * g.dx, (b + g.L - 5) * g.dy)).max() < 1e-14
 
 
 def test_fft_len_and_embedding():

@@ -178,6 +178,47 @@ def test_ce_eigs_and_field_covariance():
         csim.ce_eigs(g, k, 2 * (g.P1 - 1) - 2, 36)
 
 
+def _torus_ratio_dense(g, k, Fs1, Fs2):
+    """min / max eigenvalue of the covariance of the Fs1 x Fs2 torus points with minimal-image
+    lags, from a dense symmetric eigensolver (independent of the FFT route of ce_eigs)."""
+    a, b = np.meshgrid(np.arange(Fs1), np.arange(Fs2), indexing="ij")
+    a, b = a.ravel(), b.ravel()
+    du = np.abs(a[:, None] - a[None, :])
+    dw = np.abs(b[:, None] - b[None, :])
+    du = np.minimum(du, Fs1 - du) * g.dx
+    dw = np.minimum(dw, Fs2 - dw) * g.dy
+    ev = np.linalg.eigvalsh(k.of_lag(du, dw))
+    return ev.min() / ev.max()
+
+
+def _even_23(lo, hi):
+    return sorted(v for v in {2 ** i * 3 ** j for i in range(1, 12) for j in range(0, 7)} if lo <= v <= hi)
+
+
+def test_ce_torus_grows_until_the_embedding_is_nonnegative():
+    # range 0.2 on a 12 x 14 grid (L = 1): the first torus (32 x 32) and the next (36 x 36) have
+    # eigenvalues below -1e-6 of the largest; 48 x 48 embeds the covariance
+    g = Grid(12, 14, 0.0, 0.0, 1.0 / 11, 1.1 / 13, 1)
+    k = Matern(1.0, 0.2, 1.5, 0.0)
+    Fs = csim.ce_torus(g, k)
+    assert Fs == (48, 48)
+    assert _torus_ratio_dense(g, k, 32, 32) < -1e-6 and _torus_ratio_dense(g, k, 36, 36) < -1e-6
+    assert _torus_ratio_dense(g, k, *Fs) >= -1e-6
+    # every torus the rule skipped is one of the even 2^a 3^b sizes between the first and the chosen one
+    assert _even_23(32, 48) == [32, 36, 48]
+
+
+def test_ce_torus_fails_beyond_twice_the_first_size():
+    # range 0.3 on an 8 x 9 grid (L = 1): first torus 18 x 24; every even 2^a 3^b torus up to
+    # twice that (36 x 48) has a negative eigenvalue beyond the tolerance
+    g = Grid(8, 9, 0.0, 0.0, 1.0 / 7, 1.1 / 8, 1)
+    k = Matern(1.0, 0.3, 2.5, 0.0)
+    with pytest.raises(csim.CEFailure):
+        csim.ce_torus(g, k)
+    for F1, F2 in zip(_even_23(18, 36), _even_23(24, 48)):
+        assert _torus_ratio_dense(g, k, F1, F2) < -1e-6, (F1, F2)
+
+
 def test_ce_fields_empirical_variance():
     g = grid_unit(8, 8, 2)
     k = Matern(2.0, 0.2, 0.5)
