@@ -428,10 +428,20 @@ int krig_predict_many(const krig_plan *plans, int32_t count, const int32_t *h_B,
 /*
  * The same batch recorded once as a HIP graph and replayed by one launch.
  * krig_batch_create grows every plan's workspaces for its B, then captures the
- * batch's kernel launches on `stream` (NULL: a stream of the batch's own), spread
- * over `lanes` (1..16) parallel branches so that small problems run side by side
- * (largest problem first, each to the least-loaded branch).  The device pointers in
- * h_y / h_yhat are recorded: a replay reads and writes those buffers.
+ * batch's kernel launches on `stream` (NULL: a stream of the batch's own), in one of
+ * two forms:
+ *  lanes 1..16: every problem's own launches, spread over `lanes` parallel branches so
+ *    that small problems run side by side (largest problem first, each to the
+ *    least-loaded branch);
+ *  lanes 0 (persistent): each pass of all problems in one launch per pass and kernel form
+ *    (the solve's triangular products and their sums, the scatter + forward rows, the
+ *    columns, the inverse rows; problems grouped by transform form): a grid of about one
+ *    resident round of blocks that walks the pass's (problem, tile) list, block b taking
+ *    items b, b + grid, ..., every tile computing what the problem's own launch computes
+ *    (bitwise the same predictions).  Each problem needs its own plan (KRIG_EINVAL for a
+ *    repeat).
+ * The device pointers in h_y / h_yhat are recorded: a replay reads and writes those
+ * buffers.
  * krig_batch_launch replays the graph on `stream` (NULL: the capture stream).
  * While a batch exists its plans refuse krig_plan_destroy and any call that would
  * regrow their workspaces (KRIG_EINVAL); a replay must not overlap other calls on the

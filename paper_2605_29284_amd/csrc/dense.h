@@ -42,4 +42,29 @@ inline size_t tri_part_size(int n, int B) { return (size_t)((n + 15) / 16) * tri
 hipError_t tri_apply(const double* T, int64_t ldt, int n, int upper, const double* in, int64_t in_fs, double* out,
                      int64_t out_fs, int B, double* part, hipStream_t st);
 
+// One problem of a persistent triangular product (an uneven batch): tri_apply's arguments and
+// its tile counts (nt row tiles x qs splits x nfz field groups for the products, nt x nfz for
+// the sums; kg chunk groups per wave; vec: 32-byte input vectors).
+struct TriProb {
+  const double* T;
+  int64_t ldt;
+  const double* in;
+  int64_t in_fs;
+  double* part;
+  double* out;
+  int64_t out_fs;
+  int n, B, qmax, kg, nt, qs, nfz, vec;
+  int per_z;              // product tiles per field group: the (row tile, split) pairs with chunks
+};
+TriProb tri_prob(const double* T, int64_t ldt, int n, const double* in, int64_t in_fs, double* out, int64_t out_fs,
+                 int B, double* part);
+struct TriQueue {
+  const TriProb* probs;   // device array of count problems
+  const int* first;       // [count + 1] prefix sums of their tile counts
+  int count, total;
+};
+// product tiles of problems that all have this (upper, vec, kg); then the sums (any kg, vec)
+hipError_t tri_part_queue(const TriQueue& q, int upper, int vec, int kg, hipStream_t st);
+hipError_t tri_sum_queue(const TriQueue& q, int upper, hipStream_t st);
+
 }  // namespace krig

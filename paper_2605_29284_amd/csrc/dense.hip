@@ -400,10 +400,9 @@ __host__ __device__ inline int tri_splits_kg(int n, int t, int upper, int kg) {
 // VEC: in_fs is a multiple of 4 and in 32-byte aligned, so a lane's four input values
 // are one 32-byte load (values past n are masked to zero).
 template <int UPPER, bool VEC, int KG>
-__global__ void __launch_bounds__(64) k_tri_part(const double* __restrict__ T, int64_t ldt, int n,
-                                                 const double* __restrict__ in, int64_t in_fs, int B,
-                                                 double* __restrict__ part, int qmax) {
-  const int t = blockIdx.x, q = blockIdx.y, z = blockIdx.z, nfz = gridDim.z;
+__device__ __forceinline__ void tri_part_body(const double* __restrict__ T, int64_t ldt, int n,
+                                              const double* __restrict__ in, int64_t in_fs, int B,
+                                              double* __restrict__ part, int qmax, int t, int q, int z, int nfz) {
   if (q >= tri_splits_kg(n, t, UPPER, KG)) return;  // the whole wave
   const int lane = threadIdx.x, r = lane & 15, g = lane >> 4;
   const int i0 = 16 * t, f0 = 16 * z;
@@ -445,12 +444,18 @@ __global__ void __launch_bounds__(64) k_tri_part(const double* __restrict__ T, i
   for (int j = 0; j < 4; ++j) pp[j * 64 + lane] = acc[j];
 }
 
+template <int UPPER, bool VEC, int KG>
+__global__ void __launch_bounds__(64) k_tri_part(const double* __restrict__ T, int64_t ldt, int n,
+                                                 const double* __restrict__ in, int64_t in_fs, int B,
+                                                 double* __restrict__ part, int qmax) {
+  tri_part_body<UPPER, VEC, KG>(T, ldt, n, in, in_fs, B, part, qmax, blockIdx.x, blockIdx.y, blockIdx.z, gridDim.z);
+}
+
 // out = sum of a tile's partials (split index order); element e of a partial tile is
 // MFMA result register e/64 of lane e%64: field f0 + (e%64)/16 + 4 (e/64), row i0 + e%16
 template <int UPPER>
-__global__ void __launch_bounds__(256) k_tri_sum(const double* __restrict__ part, int n, int B, int qmax,
-                                                 double* __restrict__ out, int64_t out_fs, int kg) {
-  const int t = blockIdx.x, z = blockIdx.y, nfz = gridDim.y;
+__device__ __forceinline__ void tri_sum_body(const double* __restrict__ part, int n, int B, int qmax,
+                                             double* __restrict__ out, int64_t out_fs, int kg, int t, int z, int nfz) {
   const int e = threadIdx.x, lane = e & 63, j = e >> 6;
   const int f = 16 * z + (lane >> 4) + 4 * j, i = 16 * t + (lane & 15);
   const int ns = tri_splits_kg(n, t, UPPER, kg);
@@ -466,6 +471,57 @@ __global__ void __launch_bounds__(256) k_tri_sum(const double* __restrict__ part
   if (f < B && i < n) out[(int64_t)f * out_fs + i] = s;
 }
 
+template <int UPPER>
+__global__ void __launch_bounds__(256) k_tri_sum(const double* __restrict__ part, int n, int B, int qmax,
+                                                 double* __restrict__ out, int64_t out_fs, int kg) {
+  tri_sum_body<UPPER>(part, n, B, qmax, out, out_fs, kg, blockIdx.x, blockIdx.y, gridDim.y);
+}
+
+// Persistent forms for an uneven batch: the tiles of several problems' products in one list
+// (problem i owns tiles [first[i], first[i + 1])), walked by a grid of about one resident
+// round of blocks, block b taking tiles b, b + grid, ...  A product tile is (t, q, z) =
+// (row tile, split, field group), a sum tile (t, z); each computes what the problem's own
+// launch computes.
+template <typename T> using const_as = const __attribute__((address_space(4))) T;
+
+__device__ __forceinline__ bool tri_next(const TriQueue& qa, int& iter, int& prob, int& local) {
+  // the tile index only grows, so the problem is found by stepping forward from the last one
+  const int t = blockIdx.x + (iter++) * gridDim.x;
+  if (t >= qa.total) return false;
+  while (prob + 1 < qa.count && qa.first[prob + 1] <= t) ++prob;
+  local = t - qa.first[prob];
+  return true;
+}
+
+// Only the (row tile, split) pairs that hold chunks are listed: split q covers row tiles
+// [q w, nt) of a lower product and [0, nt - q w) of an upper one (w = TRI_KS * KG chunks per
+// split), nt - q w tiles either way, field groups outermost.
+template <int UPPER, bool VEC, int KG>
+__global__ void __launch_bounds__(64) k_tri_part_queue(TriQueue qa) {
+  int prob = 0, local, iter = 0;
+  while (tri_next(qa, iter, prob, local)) {
+    const_as<TriProb>* p = (const_as<TriProb>*)(qa.probs) + prob;
+    const int nt = p->nt, w = TRI_KS * KG;
+    const int z = local / p->per_z;
+    int rem = local - z * p->per_z, q = 0;
+    while (rem >= nt - q * w) {
+      rem -= nt - q * w;
+      ++q;
+    }
+    const int t = UPPER ? rem : q * w + rem;
+    tri_part_body<UPPER, VEC, KG>(p->T, p->ldt, p->n, p->in, p->in_fs, p->B, p->part, p->qmax, t, q, z, p->nfz);
+  }
+}
+
+template <int UPPER>
+__global__ void __launch_bounds__(256) k_tri_sum_queue(TriQueue qa) {
+  int prob = 0, local, iter = 0;
+  while (tri_next(qa, iter, prob, local)) {
+    const_as<TriProb>* p = (const_as<TriProb>*)(qa.probs) + prob;
+    tri_sum_body<UPPER>(p->part, p->n, p->B, p->qmax, p->out, p->out_fs, p->kg, local % p->nt, local / p->nt, p->nfz);
+  }
+}
+
 template <int UPPER, int KG>
 void tri_part_launch(bool vec, dim3 grid, const double* T, int64_t ldt, int n, const double* in, int64_t in_fs, int B,
                      double* part, int qmax, hipStream_t st) {
@@ -473,6 +529,65 @@ void tri_part_launch(bool vec, dim3 grid, const double* T, int64_t ldt, int n, c
     hipLaunchKernelGGL((k_tri_part<UPPER, true, KG>), grid, dim3(64), 0, st, T, ldt, n, in, in_fs, B, part, qmax);
   else
     hipLaunchKernelGGL((k_tri_part<UPPER, false, KG>), grid, dim3(64), 0, st, T, ldt, n, in, in_fs, B, part, qmax);
+}
+
+TriProb tri_prob(const double* T, int64_t ldt, int n, const double* in, int64_t in_fs, double* out, int64_t out_fs,
+                 int B, double* part) {
+  TriProb p{};
+  p.T = T;
+  p.ldt = ldt;
+  p.in = in;
+  p.in_fs = in_fs;
+  p.part = part;
+  p.out = out;
+  p.out_fs = out_fs;
+  p.n = n;
+  p.B = B;
+  p.qmax = tri_max_splits(n);
+  p.kg = n >= 8192 ? 4 : 1;
+  p.nt = (n + 15) / 16;
+  p.qs = tri_splits_kg(n, 0, 1, p.kg);
+  p.nfz = (B + 15) / 16;
+  p.vec = (in_fs & 3) == 0 && (reinterpret_cast<uintptr_t>(in) & 31) == 0;
+  p.per_z = 0;
+  for (int q = 0; q < p.qs; ++q) p.per_z += p.nt - q * TRI_KS * p.kg;
+  return p;
+}
+
+static int cu_count() {
+  int dev = 0, cus = 0;
+  if (hipGetDevice(&dev) != hipSuccess || hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) !=
+                                              hipSuccess || cus < 1)
+    cus = 1;
+  return cus;
+}
+
+template <typename K>
+static int tri_resident(K kernel, int threads) {
+  int per = 0;
+  if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per, kernel, threads, 0) != hipSuccess || per < 1) per = 1;
+  return per * cu_count();
+}
+
+hipError_t tri_part_queue(const TriQueue& q, int upper, int vec, int kg, hipStream_t st) {
+#define KRIG_TRIQ(U, V, KGV)                                                                    \
+  if (upper == U && vec == V && kg == KGV) {                                                    \
+    hipLaunchKernelGGL((k_tri_part_queue<U, V, KGV>), dim3(tri_resident(k_tri_part_queue<U, V, KGV>, 64)), \
+                       dim3(64), 0, st, q);                                                     \
+    return hipGetLastError();                                                                   \
+  }
+  KRIG_TRIQ(0, true, 1) KRIG_TRIQ(0, false, 1) KRIG_TRIQ(0, true, 4) KRIG_TRIQ(0, false, 4)
+  KRIG_TRIQ(1, true, 1) KRIG_TRIQ(1, false, 1) KRIG_TRIQ(1, true, 4) KRIG_TRIQ(1, false, 4)
+#undef KRIG_TRIQ
+  return hipErrorInvalidValue;
+}
+
+hipError_t tri_sum_queue(const TriQueue& q, int upper, hipStream_t st) {
+  if (upper)
+    hipLaunchKernelGGL(k_tri_sum_queue<1>, dim3(tri_resident(k_tri_sum_queue<1>, 256)), dim3(256), 0, st, q);
+  else
+    hipLaunchKernelGGL(k_tri_sum_queue<0>, dim3(tri_resident(k_tri_sum_queue<0>, 256)), dim3(256), 0, st, q);
+  return hipGetLastError();
 }
 
 hipError_t tri_apply(const double* T, int64_t ldt, int n, int upper, const double* in, int64_t in_fs, double* out,

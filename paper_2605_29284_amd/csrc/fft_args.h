@@ -119,10 +119,22 @@ struct RowsC2RArgs {
   int NL;
 };
 
+// Persistent launch over several problems of one transform form (an uneven batch): problem
+// i's argument block is args[i] (RowsR2CArgs, ColsArgs or RowsC2RArgs, all with the same NL),
+// its tiles are [first[i], first[i + 1]) of the list, nbx[i] per field.
+struct QueueArgs {
+  const void* args;       // device array of count argument blocks
+  const int* first;       // [count + 1] prefix sums of the problems' tile counts
+  const int* nbx;         // [count] row or column blocks per field
+  int count, total;
+};
+
 typedef hipError_t (*launch_rows_r2c_t)(const RowsR2CArgs&, int B, hipStream_t);
 typedef hipError_t (*launch_cols_t)(const ColsArgs&, int nblk_y, hipStream_t);
 typedef hipError_t (*launch_rows_c2r_t)(const RowsC2RArgs&, int B, hipStream_t);
 typedef hipError_t (*launch_rows_ce_t)(const RowsCEArgs&, int npairs, hipStream_t);
+// nblocks 0: one resident round of blocks (occupancy x compute units), -d: a d-th of it
+typedef hipError_t (*launch_queue_t)(const QueueArgs&, int NL, int nblocks, hipStream_t);
 
 // Kernels for one transform length.  Arithmetic is FP64 in every role of the
 // prediction and its adjoint.  FP64 plans store FP64 spectra between the passes; FP32
@@ -151,6 +163,8 @@ struct FftSet {
   launch_rows_r2c_t r2c_cov;        // covariance on the embedding torus, FP64
   launch_rows_r2c_t r2c_center;     // covariance about the torus centre (F1/2, F2/2), plain coordinates
   launch_rows_r2c_t r2c_delta;      // indicator of the torus centre
+  // persistent forms of the prediction's passes (uneven batches)
+  launch_queue_t q_r2c_csr, q_conv64, q_c2r64, q_c2r64_32;
   launch_cols_t ce_cols32, ce_cols64;    // sampler pass 1 (noise x sqrt(Lambda), column transforms)
   launch_rows_ce_t ce_rows32, ce_rows64; // sampler pass 2 (row transforms -> two realisations)
 };

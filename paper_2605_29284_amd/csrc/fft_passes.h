@@ -313,176 +313,17 @@ __device__ __forceinline__ void xf_inv(cx<TC> (&w)[R3], int t, cx<TC>* L, const 
 // ----------------------------------------------------------------------------------------
 enum { SRC_CSR = 0, SRC_DENSE = 1, SRC_LAG = 2, SRC_COV = 3, SRC_CENTER = 4, SRC_DELTA = 5 };
 
+// Kernel bodies (fft_body_*.inc) are included inside the kernels, after the block's logical
+// coordinates (bx: row or column block, by: field or group) are set, so that one text serves a
+// plain launch (one problem, block id -> (bx, by)) and the persistent launch of an uneven batch
+// (a tile list over several problems).  Included rather than called: the call form changed the
+// register allocation of the plain kernels (two of them spilled).
+
 template <typename TC, typename TIN, typename TS, int R1, int R2, int R3, int SRC>
 KRIG_ROW_KERNEL k_rows_r2c(RowsR2CArgs a) {
   int bx, by;
   logical_block<false>(bx, by);
-  using G = Geo<R1, R2, R3>;
-  extern __shared__ __align__(16) unsigned char smem_raw[];
-  cx<TC>* lds = reinterpret_cast<cx<TC>*>(smem_raw);
-  const int s = threadIdx.x % G::NT;
-  const int l = threadIdx.x / G::NT;
-  const int NL = a.NL;
-  const int b = by;
-  const int row0 = 2 * bx * NL;
-  const int ra = row0 + 2 * l, rb = ra + 1;
-  const bool oka = ra < a.nrows, okb = rb < a.nrows;
-  const cx<TC>* twF = reinterpret_cast<const cx<TC>*>(a.twF);
-  const TwB<TC> tb = tw_bases<TC, R1, R2, R3, false>(twF, s);
-  cx<TC>* L = lds + (size_t)l * G::ROWS;
-
-  cx<TC> v[G::NIN];
-  // CSR scatter (Steps 5-6): node (r, c) = sum over its segment of alpha[site] * w, in
-  // segment order.  For each of the line's two rows the loads of its NIN nodes go out
-  // in three batches (segment bounds, first entries, their alphas) instead of one
-  // dependent chain per node; later entries of a segment (rare) follow in a loop.
-  double sc[2][G::NIN];
-  if constexpr (SRC == SRC_CSR) {
-    if (s < G::TIN) {
-      const double* al = a.alpha + (int64_t)b * a.alpha_fs;
-#pragma unroll
-      for (int h = 0; h < 2; ++h) {
-        const int rr = h ? rb : ra;
-        const bool okr = h ? okb : oka;
-        int e0[G::NIN], e1[G::NIN];
-#pragma unroll
-        for (int j = 0; j < G::NIN; ++j) {
-          const int c = G::TIN * j + s;
-          const bool ok = okr && c < a.ncols;
-          const int q = rr * a.ncols + c;
-          e0[j] = ok ? a.row_ptr[q] : 0;
-          e1[j] = ok ? a.row_ptr[q + 1] : 0;
-        }
-        int site[G::NIN];
-        double w0[G::NIN];
-#pragma unroll
-        for (int j = 0; j < G::NIN; ++j) {
-          const bool has = e0[j] < e1[j];
-          site[j] = has ? a.ent_site[e0[j]] : 0;
-          w0[j] = has ? a.ent_w[e0[j]] : 0.0;
-        }
-#pragma unroll
-        for (int j = 0; j < G::NIN; ++j) {
-          sc[h][j] = 0.0;
-          if (e0[j] < e1[j]) sc[h][j] += al[site[j]] * w0[j];
-        }
-#pragma unroll
-        for (int j = 0; j < G::NIN; ++j)
-          for (int e = e0[j] + 1; e < e1[j]; ++e) sc[h][j] += al[a.ent_site[e]] * a.ent_w[e];
-      }
-    }
-  }
-  if (s < G::TIN) {
-#pragma unroll
-    for (int j = 0; j < G::NIN; ++j) {
-      const int c = G::TIN * j + s;
-      TC xa = 0, xb = 0;
-      if constexpr (SRC == SRC_CSR) {
-        xa = (TC)sc[0][j];
-        xb = (TC)sc[1][j];
-      } else if constexpr (SRC == SRC_DENSE) {
-        const int cc = c - a.coff;
-        if (cc >= 0 && cc < a.ncols) {
-          const TIN* d = reinterpret_cast<const TIN*>(a.dense) + (int64_t)b * a.dense_fs;
-          if (oka) xa = (TC)d[(int64_t)ra * a.dense_ld + cc];
-          if (okb) xb = (TC)d[(int64_t)rb * a.dense_ld + cc];
-        }
-      } else if constexpr (SRC == SRC_CENTER) {  // covariance about the torus centre, plain coordinates
-        const int F2 = G::F;
-        MaternDev mt;
-        mt.sigma2 = a.cov_sigma2;
-        mt.rho = a.cov_rho;
-        mt.tau2 = 0.0;
-        mt.kind = a.cov_kind;
-        const double hw = (double)(c - F2 / 2) * a.cov_dy;
-        if (oka) {
-          const double hu = (double)(ra - a.F1 / 2) * a.cov_dx;
-          xa = (TC)matern_cov(sqrt(hu * hu + hw * hw), mt);
-        }
-        if (okb) {
-          const double hu = (double)(rb - a.F1 / 2) * a.cov_dx;
-          xb = (TC)matern_cov(sqrt(hu * hu + hw * hw), mt);
-        }
-      } else if constexpr (SRC == SRC_DELTA) {  // indicator of the torus centre
-        const bool cc = c == G::F / 2;
-        xa = (TC)((cc && oka && ra == a.F1 / 2) ? 1 : 0);
-        xb = (TC)((cc && okb && rb == a.F1 / 2) ? 1 : 0);
-      } else if constexpr (SRC == SRC_COV) {  // torus covariance with minimal-image lags
-        const int F2 = G::F;
-        MaternDev mt;
-        mt.sigma2 = a.cov_sigma2;
-        mt.rho = a.cov_rho;
-        mt.tau2 = 0.0;
-        mt.kind = a.cov_kind;
-        const double hw = (double)(c < F2 - c ? c : F2 - c) * a.cov_dy;
-        if (oka) {
-          const double hu = (double)(ra < a.F1 - ra ? ra : a.F1 - ra) * a.cov_dx;
-          xa = (TC)matern_cov(sqrt(hu * hu + hw * hw), mt);
-        }
-        if (okb) {
-          const double hu = (double)(rb < a.F1 - rb ? rb : a.F1 - rb) * a.cov_dx;
-          xb = (TC)matern_cov(sqrt(hu * hu + hw * hw), mt);
-        }
-      } else {  // SRC_LAG: embedding row r holds lag[min(r, F1-r)][min(c, F2-c)]
-        const int F2 = G::F;
-        const int dc = c < F2 - c ? c : F2 - c;
-        if (dc < a.n2l) {
-          if (oka) {
-            const int dr = ra < a.F1 - ra ? ra : a.F1 - ra;
-            if (dr < a.n1l) xa = (TC)a.lag[(int64_t)dr * a.n2l + dc];
-          }
-          if (okb) {
-            const int dr = rb < a.F1 - rb ? rb : a.F1 - rb;
-            if (dr < a.n1l) xb = (TC)a.lag[(int64_t)dr * a.n2l + dc];
-          }
-        }
-      }
-      v[j] = mk<TC>(xa, xb);
-    }
-  }
-  cx<TC> w[G::NOUT];
-  xf_fwd<TC, R1, R2, R3, -1>(v, w, s, L, tb);
-  __syncthreads();
-  // natural-order exchange to pair Z[k] with Z[F-k]
-  if (s < G::TOUT) {
-#pragma unroll
-    for (int k2 = 0; k2 < G::NOUT; ++k2) L[s + G::TOUT * k2] = w[k2];
-  }
-  __syncthreads();
-  constexpr int NK = (G::F / 2 + G::TOUT) / G::TOUT;  // k2 with k = s + TOUT k2 <= F/2 for some s
-  cx<TC> xa[NK], xb[NK];
-  if (s < G::TOUT) {
-#pragma unroll
-    for (int k2 = 0; k2 < NK; ++k2) {
-      const int k = s + G::TOUT * k2;
-      const cx<TC> z = w[k2];
-      const cx<TC> zc = L[(G::F - k) % G::F];
-      // Xa = (Z[k] + conj Z[F-k]) / 2,  Xb = (Z[k] - conj Z[F-k]) / (2 i)
-      xa[k2] = mk<TC>((TC)0.5 * (z.x + zc.x), (TC)0.5 * (z.y - zc.y));
-      xb[k2] = mk<TC>((TC)0.5 * (z.y + zc.y), (TC)0.5 * (zc.x - z.x));
-    }
-  }
-  __syncthreads();
-  // transpose through LDS: T[k][2l + {0,1}] over the block, then row-contiguous stores
-  cx<TC>* T = lds;
-  const int R2b = 2 * NL;
-  if (s < G::TOUT) {
-#pragma unroll
-    for (int k2 = 0; k2 < NK; ++k2) {
-      const int k = s + G::TOUT * k2;
-      if (k < a.H2) {
-        T[tpos(k, 2 * l, R2b)] = xa[k2];
-        T[tpos(k, 2 * l + 1, R2b)] = xb[k2];
-      }
-    }
-  }
-  __syncthreads();
-  const Spec<TS> o = Spec<TS>::field(a.out, a.out_fs, b);
-  // element idx = k R2b + rl of the transpose goes to thread idx mod blockDim (NT NL)
-  for (TWalk<G::NT> e(threadIdx.x, NL); e.k < a.H2; e.next()) {
-    const int row = row0 + e.rl;
-    if (row < a.nrows) o.st((int64_t)e.k * a.out_ld + row, T[tpos(e.k, e.rl, R2b)]);
-  }
+#include "fft_body_rows_r2c.inc"
 }
 
 // ----------------------------------------------------------------------------------------
@@ -514,193 +355,13 @@ template <int R1, int R2, int R3, int MODE> struct ColCap {
   static constexpr int waves = (MODE == COL_CONV_DLAG && RowCap<R1, R2, R3>::waves > 1) ? 3 : 1;
 };
 
+
 template <typename TF, typename TI, typename ST, int R1, int R2, int R3, int MODE>
 __global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(ColCap<R1, R2, R3, MODE>::waves)))
 k_cols(ColsArgs a) {
-  using TSI = typename ST::in;
-  using TSO = typename ST::out;
   int bx, by;
   logical_block<true>(bx, by);
-  using G = Geo<R1, R2, R3>;
-  using TC = TF;
-  extern __shared__ __align__(16) unsigned char smem_raw[];
-  const int NL = a.NL;
-  const int s = threadIdx.x % G::NT;
-  const int l0 = threadIdx.x / G::NT;
-  const int col = bx * NL + l0;
-  const bool colok = col < a.H2;
-  const cx<TC>* twF = reinterpret_cast<const cx<TC>*>(a.twF);
-  static_assert(std::is_same<TI, TF>::value, "one arithmetic type per column pass");
-  const TwB<TC> tb = tw_bases<TC, R1, R2, R3, (MODE == COL_CONV || MODE == COL_CONV_DLAG)>(twF, s);
-  cx<TC>* L = reinterpret_cast<cx<TC>*>(smem_raw) + (size_t)l0 * G::EX;
-
-  if constexpr (MODE == COL_CONV) {
-    const int b = by;
-    const Spec<TSI> src = Spec<TSI>::field(a.in, a.in_fs, b).at((int64_t)col * a.in_ld);
-    // the filter values this thread needs, loaded before the transform hides their latency
-    TF fv[R3];
-    {
-      const TF* f = reinterpret_cast<const TF*>(a.filt) + (int64_t)(colok ? col : 0) * a.filt_ld;
-#pragma unroll
-      for (int k2 = 0; k2 < R3; ++k2) fv[k2] = (s < G::TOUT && colok) ? f[s + G::TOUT * k2] : (TF)0;
-    }
-    cx<TI> wi[R3];
-    {
-      cx<TC> w[R3];
-      col_fwd<TC, TSI, R1, R2, R3>(src, a.in_off, a.in_cnt, colok, s, L, tb, w);
-      if (s < G::TOUT && colok) {
-#pragma unroll
-        for (int k2 = 0; k2 < R3; ++k2) w[k2] = cscale(w[k2], fv[k2]);
-      }
-#pragma unroll
-      for (int k2 = 0; k2 < R3; ++k2) wi[k2] = ccast<TI>(w[k2]);
-    }
-    cx<TI>* LI = reinterpret_cast<cx<TI>*>(smem_raw) + (size_t)l0 * G::EX;
-    cx<TI> v[G::NIN];
-    xf_inv<TI, R1, R2, R3>(wi, s, LI, tb, v);
-    if (s < G::TIN && colok) {
-      const Spec<TSO> dst = Spec<TSO>::field(a.out, a.out_fs, b).at((int64_t)col * a.out_ld);
-#pragma unroll
-      for (int j = 0; j < G::NIN; ++j) {
-        const int d = window_dst(a.rows, G::TIN * j + s);
-        if (d >= 0) dst.st(d, v[j]);
-      }
-    }
-  } else if constexpr (MODE == COL_CONV_DLAG) {
-    // one column per block (bx); line l0 takes field by * NL + l0.  The
-    // lines' products G-hat conj(C-hat) are summed through LDS in line order into the
-    // block's partial spectrum part[by]; each field's correlation with the
-    // filter goes to out as in COL_CONV.
-    const int colb = bx;
-    const bool colokb = colb < a.H2;
-    const int b = by * NL + l0;
-    const bool fok = colokb && b < a.B;
-    const int bb = b < a.B ? b : 0;
-    using TSI2 = typename ST::in2;
-    using TSP = typename ST::part;
-    const Spec<TSI2> srcc = Spec<TSI2>::field(a.in2, a.in2_fs, bb).at((int64_t)colb * a.in2_ld);
-    const Spec<TSI> srcg = Spec<TSI>::field(a.in, a.in_fs, bb).at((int64_t)colb * a.in_ld);
-    TF fv[R3];  // filter values, loaded before the transforms
-    {
-      const TF* f = reinterpret_cast<const TF*>(a.filt) + (int64_t)(colokb ? colb : 0) * a.filt_ld;
-#pragma unroll
-      for (int k2 = 0; k2 < R3; ++k2) fv[k2] = (s < G::TOUT && fok) ? f[s + G::TOUT * k2] : (TF)0;
-    }
-    cx<TC> wc[R3], wg[R3];
-    col_fwd<TC, TSI2, R1, R2, R3>(srcc, a.in2_off, a.in2_cnt, fok, s, L, tb, wc);  // C-hat
-    col_fwd<TC, TSI, R1, R2, R3>(srcg, a.in_off, a.in_cnt, fok, s, L, tb, wg);    // G-hat
-    __syncthreads();
-    if (s < G::TOUT) {
-#pragma unroll
-      for (int k2 = 0; k2 < R3; ++k2) {
-        L[s + G::TOUT * k2] = fok ? cmulc(wg[k2], wc[k2]) : mk<TC>(0, 0);
-        if (fok) wg[k2] = cscale(wg[k2], fv[k2]);
-      }
-    }
-    __syncthreads();
-    if (l0 == 0 && s < G::TOUT && colokb) {
-      const cx<TC>* L0 = reinterpret_cast<const cx<TC>*>(smem_raw);
-      const Spec<TSP> p = Spec<TSP>::field(a.part, a.part_fs, by).at((int64_t)colb * a.part_ld);
-#pragma unroll
-      for (int k2 = 0; k2 < R3; ++k2) {
-        cx<TC> acc = L0[s + G::TOUT * k2];
-        for (int li = 1; li < NL; ++li) acc = acc + L0[(size_t)li * G::EX + s + G::TOUT * k2];
-        p.st(s + G::TOUT * k2, acc);
-      }
-    }
-    cx<TC> v[G::NIN];
-    xf_inv<TC, R1, R2, R3>(wg, s, L, tb, v);
-    if (s < G::TIN && fok) {
-      const Spec<TSO> dst = Spec<TSO>::field(a.out, a.out_fs, b).at((int64_t)colb * a.out_ld);
-#pragma unroll
-      for (int j = 0; j < G::NIN; ++j) {
-        const int d = window_dst(a.rows, G::TIN * j + s);
-        if (d >= 0) dst.st(d, v[j]);
-      }
-    }
-  } else if constexpr (MODE == COL_FWD_REAL) {
-    // forward transform of the input columns; store Re(X) * scale (natural order)
-    const int b = by;
-    const Spec<TSI> src = Spec<TSI>::field(a.in, a.in_fs, b).at((int64_t)col * a.in_ld);
-    cx<TC> w[R3];
-    col_fwd<TC, TSI, R1, R2, R3>(src, a.in_off, a.in_cnt, colok, s, L, tb, w);
-    if (s < G::TOUT && colok) {
-      TSO* dst = reinterpret_cast<TSO*>(a.out) + (int64_t)b * a.out_fs + (int64_t)col * a.out_ld;
-#pragma unroll
-      for (int k2 = 0; k2 < R3; ++k2) dst[s + G::TOUT * k2] = (TSO)(w[k2].x * (TC)a.scale);
-    }
-  } else if constexpr (MODE == COL_CE) {
-    // sampler pass 1: column k2 (all ncol_full frequencies) of sqrt(Lambda/N) (xi1 + i xi2),
-    // xi from Philox counter (k1 * ncol_full + k2, pair, STREAM_CE, 0); forward transform
-    // over k1; keep rows [0, rows.na) -> out[pair][k2][r]
-    const int pair = a.pair0 + by;
-    const int kk2 = col < a.ncol_full - col ? col : a.ncol_full - col;  // Lambda is even
-    const double* lam = reinterpret_cast<const double*>(a.filt) + (int64_t)kk2 * a.filt_ld;
-    cx<TC> v[G::NIN];
-    if (s < G::TIN) {
-#pragma unroll
-      for (int j = 0; j < G::NIN; ++j) {
-        const int k1 = G::TIN * j + s;
-        cx<TC> z = mk<TC>(0, 0);
-        if (colok) {
-          u32x4 cn;
-          cn.v[0] = (uint32_t)(k1 * a.ncol_full + col);
-          cn.v[1] = (uint32_t)pair;
-          cn.v[2] = STREAM_CE;
-          cn.v[3] = 0;
-          const u32x4 r = philox4x32_10(cn, a.key0, a.key1);
-          double x0, x1;
-          box_muller_f64(r.v[0], r.v[1], x0, x1);
-          const double sl = lam[k1];
-          z = mk<TC>((TC)(sl * x0), (TC)(sl * x1));
-        }
-        v[j] = z;
-      }
-    }
-    cx<TC> w[R3];
-    xf_fwd<TC, R1, R2, R3, -1>(v, w, s, L, tb);
-    if (s < G::TOUT && colok) {
-      const Spec<TSO> dst = Spec<TSO>::field(a.out, a.out_fs, by).at((int64_t)col * a.out_ld);
-#pragma unroll
-      for (int k2 = 0; k2 < R3; ++k2) {
-        const int d = window_dst(a.rows, s + G::TOUT * k2);
-        if (d >= 0) dst.st(d, w[k2]);
-      }
-    }
-  } else {  // COL_INV_SUM: inverse transform of sum_g part[g] (natural order), keep rows
-    cx<TC> v[G::NIN];
-#pragma unroll
-    for (int j = 0; j < G::NIN; ++j) v[j] = mk<TC>(0, 0);
-    if (s < G::TIN && colok) {
-      // four partials per round: their 4 NIN loads go out together; every element is
-      // still summed in the order g = 0, 1, ...
-      for (int g0 = 0; g0 < a.G; g0 += 4) {
-        typename Spec<TSI>::raw t[4][G::NIN];
-#pragma unroll
-        for (int u = 0; u < 4; ++u) {
-          const Spec<TSI> pg = Spec<TSI>::field(a.in, a.in_fs, g0 + u < a.G ? g0 + u : g0).at((int64_t)col * a.in_ld + s);
-#pragma unroll
-          for (int j = 0; j < G::NIN; ++j) t[u][j] = pg.ldraw(G::TIN * j);
-        }
-#pragma unroll
-        for (int u = 0; u < 4; ++u)
-          if (g0 + u < a.G) {
-#pragma unroll
-            for (int j = 0; j < G::NIN; ++j) v[j] = v[j] + Spec<TSI>::template cvt<TC>(t[u][j]);
-          }
-      }
-    }
-    cx<TC> w[R3];
-    xf_fwd<TC, R1, R2, R3, 1>(v, w, s, L, tb);
-    if (s < G::TOUT && colok) {
-      const Spec<TSO> dst = Spec<TSO>::field(a.out, 0, 0).at((int64_t)col * a.out_ld);
-#pragma unroll
-      for (int k2 = 0; k2 < R3; ++k2) {
-        const int d = window_dst(a.rows, s + G::TOUT * k2);
-        if (d >= 0) dst.st(d, w[k2]);
-      }
-    }
-  }
+#include "fft_body_cols.inc"
 }
 
 // ----------------------------------------------------------------------------------------
@@ -726,70 +387,81 @@ __device__ __forceinline__ void c2r_line_input(const cx<TC>* T, int R2b, int l, 
   }
 }
 
+
 template <typename TC, typename TS, typename TO, int R1, int R2, int R3>
 KRIG_ROW_KERNEL k_rows_c2r(RowsC2RArgs a) {
   int bx, by;
   logical_block<false>(bx, by);
-  using G = Geo<R1, R2, R3>;
-  extern __shared__ __align__(16) unsigned char smem_raw[];
-  cx<TC>* lds = reinterpret_cast<cx<TC>*>(smem_raw);
-  const int s = threadIdx.x % G::NT;
-  const int l = threadIdx.x / G::NT;
-  const int NL = a.NL;
-  const int b = by;
-  const int row0 = 2 * bx * NL;
-  const int ra = row0 + 2 * l, rb = ra + 1;
-  const bool oka = ra < a.nrows, okb = rb < a.nrows;
-  const cx<TC>* twF = reinterpret_cast<const cx<TC>*>(a.twF);
-  const TwB<TC> tb = tw_bases<TC, R1, R2, R3, false>(twF, s);
-  // row-contiguous loads of the block's 2 NL rows into T[k][rl]
-  const int R2b = 2 * NL;
-  cx<TC>* T = lds;
-  const Spec<TS> in = Spec<TS>::field(a.in, a.in_fs, b);
-  {
-    // a thread's share is at most IT elements (blockDim = NT * NL, H2 = F/2 + 1): all
-    // its loads are issued before the first LDS store
-    // element idx = k R2b + rl goes to thread idx mod blockDim (NT NL)
-    constexpr int IT = (2 * (G::F / 2 + 1) + G::NT - 1) / G::NT;
-    typename Spec<TS>::raw buf[IT];
-    {
-      TWalk<G::NT> e(threadIdx.x, NL);
-#pragma unroll
-      for (int it = 0; it < IT; ++it, e.next()) {
-        const int row = row0 + e.rl;
-        buf[it] = (e.k < a.H2 && row < a.nrows) ? in.ldraw((int64_t)e.k * a.in_ld + row) : Spec<TS>::zero();
-      }
-    }
-    TWalk<G::NT> e(threadIdx.x, NL);
-#pragma unroll
-    for (int it = 0; it < IT; ++it, e.next())
-      if (e.k < a.H2) T[tpos(e.k, e.rl, R2b)] = Spec<TS>::template cvt<TC>(buf[it]);
+#include "fft_body_rows_c2r.inc"
+}
+
+// ----------------------------------------------------------------------------------------
+// Persistent launches of an uneven batch: the tiles (row or column blocks) of several
+// problems of the same transform form in one list, problem i owning tiles [first[i],
+// first[i + 1]) laid out as (bx, by) = (t mod nbx[i], t / nbx[i]) with t the tile's index
+// within the problem.  A grid of about one resident round of blocks walks the list, block b
+// taking tiles b, b + grid, b + 2 grid, ... until it is exhausted: no block waits for
+// another, so every block ends.  (An atomic counter handing out tiles measured twice as slow
+// on the batch's ~10^6 small triangular-product tiles.)  Each tile's arithmetic is that of
+// the problem's own launch, so results are bitwise the same.
+// ----------------------------------------------------------------------------------------
+// Argument blocks are read through the constant address space: they do not change while the
+// kernel runs, so the compiler may reload a field where it is used instead of holding every
+// field in registers across the tile.
+template <typename T> using const_as = const __attribute__((address_space(4))) T;
+
+template <typename ArgsT>
+__device__ __forceinline__ bool next_tile(const QueueArgs& q, int& iter, int& prob, int& bx, int& by,
+                                          const_as<ArgsT>*& a) {
+  // the tile index only grows, so the problem is found by stepping forward from the last one
+  const int t = blockIdx.x + (iter++) * gridDim.x;
+  if (t >= q.total) return false;
+  int lo = prob;
+  while (lo + 1 < q.count && q.first[lo + 1] <= t) ++lo;
+  const int local = t - q.first[lo];
+  prob = lo;
+  bx = local % q.nbx[lo];
+  by = local / q.nbx[lo];
+  a = (const_as<ArgsT>*)(q.args) + lo;
+  return true;
+}
+
+// The queue loop holds a few more registers than a plain launch: the row forms capped at five
+// waves per SIMD there run at four here (no scratch).
+template <int R1, int R2, int R3> struct QueueRowCap {
+  static constexpr int waves = RowCap<R1, R2, R3>::waves > 1 ? 4 : 1;
+};
+#define KRIG_QUEUE_ROW_KERNEL \
+  __global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(QueueRowCap<R1, R2, R3>::waves)))
+
+template <typename TC, typename TIN, typename TS, int R1, int R2, int R3, int SRC>
+KRIG_QUEUE_ROW_KERNEL k_rows_r2c_queue(QueueArgs q) {
+  int prob = 0, bx, by, iter = 0;
+  const_as<RowsR2CArgs>* ap;
+  while (next_tile(q, iter, prob, bx, by, ap)) {
+    const RowsR2CArgs& a = *(const RowsR2CArgs*)ap;
+#include "fft_body_rows_r2c.inc"
   }
-  __syncthreads();
-  cx<TC> v[G::NIN];
-  c2r_line_input<TC, R1, R2, R3>(T, R2b, l, s, a.H2, v);
-  cx<TC>* L = lds + (size_t)l * G::ROWS;
-  cx<TC> w[R3];
-  xf_fwd<TC, R1, R2, R3, 1>(v, w, s, L, tb);
-  if (s < G::TOUT) {
-    TO* oa = reinterpret_cast<TO*>(a.out) + (int64_t)b * a.out_fs + (int64_t)ra * a.ldo;
-    TO* ob = oa + a.ldo;
-    const TO* ad = reinterpret_cast<const TO*>(a.add);
-#pragma unroll
-    for (int k2 = 0; k2 < R3; ++k2) {
-      const int c = s + G::TOUT * k2;
-      const int d = window_dst(a.cols, c);
-      if (d >= 0) {
-        TO va = (TO)w[k2].x, vb = (TO)w[k2].y;
-        if (ad) {
-          const TO* abase = ad + (int64_t)b * a.add_fs + (int64_t)(ra + a.add_r0) * a.add_ld + d + a.add_c0;
-          if (oka) va += abase[0];
-          if (okb) vb += abase[a.add_ld];
-        }
-        if (oka) oa[d] = va;
-        if (okb) ob[d] = vb;
-      }
-    }
+}
+
+template <typename TF, typename TI, typename ST, int R1, int R2, int R3, int MODE>
+__global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(ColCap<R1, R2, R3, MODE>::waves)))
+k_cols_queue(QueueArgs q) {
+  int prob = 0, bx, by, iter = 0;
+  const_as<ColsArgs>* ap;
+  while (next_tile(q, iter, prob, bx, by, ap)) {
+    const ColsArgs& a = *(const ColsArgs*)ap;
+#include "fft_body_cols.inc"
+  }
+}
+
+template <typename TC, typename TS, typename TO, int R1, int R2, int R3>
+KRIG_QUEUE_ROW_KERNEL k_rows_c2r_queue(QueueArgs q) {
+  int prob = 0, bx, by, iter = 0;
+  const_as<RowsC2RArgs>* ap;
+  while (next_tile(q, iter, prob, bx, by, ap)) {
+    const RowsC2RArgs& a = *(const RowsC2RArgs*)ap;
+#include "fft_body_rows_c2r.inc"
   }
 }
 
@@ -986,6 +658,50 @@ hipError_t launch_rows_ce(const RowsCEArgs& a, int npairs, hipStream_t st) {
   return hipGetLastError();
 }
 
+// a queue launch's grid for nblocks <= 0: one resident round of blocks (occupancy per compute
+// unit x compute units) for 0, a d-th of it for -d
+template <typename K>
+int queue_grid(int nblocks, K kernel, int threads, size_t lds) {
+  int per = 0;
+  if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per, kernel, threads, lds) != hipSuccess || per < 1) per = 1;
+  int dev = 0, cus = 0;
+  if (hipGetDevice(&dev) != hipSuccess || hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) !=
+                                              hipSuccess || cus < 1)
+    cus = 1;
+  const int round = per * cus;
+  return nblocks == 0 ? round : (round / -nblocks > 1 ? round / -nblocks : 1);
+}
+
+template <typename TC, typename TIN, typename TS, int R1, int R2, int R3, int SRC>
+hipError_t launch_rows_r2c_queue(const QueueArgs& q, int NL, int nblocks, hipStream_t st) {
+  using G = Geo<R1, R2, R3>;
+  const int threads = G::NT * NL;
+  const size_t sh = rows_lds(G::g, NL, sizeof(cx<TC>));
+  if (nblocks <= 0) nblocks = queue_grid(nblocks, k_rows_r2c_queue<TC, TIN, TS, R1, R2, R3, SRC>, threads, sh);
+  k_rows_r2c_queue<TC, TIN, TS, R1, R2, R3, SRC><<<nblocks, threads, sh, st>>>(q);
+  return hipGetLastError();
+}
+
+template <typename TF, typename TI, typename ST, int R1, int R2, int R3, int MODE>
+hipError_t launch_cols_queue(const QueueArgs& q, int NL, int nblocks, hipStream_t st) {
+  using G = Geo<R1, R2, R3>;
+  const int threads = G::NT * NL;
+  const size_t sh = cols_lds(G::g, NL, sizeof(cx<TF>));
+  if (nblocks <= 0) nblocks = queue_grid(nblocks, k_cols_queue<TF, TI, ST, R1, R2, R3, MODE>, threads, sh);
+  k_cols_queue<TF, TI, ST, R1, R2, R3, MODE><<<nblocks, threads, sh, st>>>(q);
+  return hipGetLastError();
+}
+
+template <typename TC, typename TS, typename TO, int R1, int R2, int R3>
+hipError_t launch_rows_c2r_queue(const QueueArgs& q, int NL, int nblocks, hipStream_t st) {
+  using G = Geo<R1, R2, R3>;
+  const int threads = G::NT * NL;
+  const size_t sh = rows_lds(G::g, NL, sizeof(cx<TC>));
+  if (nblocks <= 0) nblocks = queue_grid(nblocks, k_rows_c2r_queue<TC, TS, TO, R1, R2, R3>, threads, sh);
+  k_rows_c2r_queue<TC, TS, TO, R1, R2, R3><<<nblocks, threads, sh, st>>>(q);
+  return hipGetLastError();
+}
+
 template <int R1, int R2, int R3>
 FftEntry make_fft_entry() {
   FftEntry e;
@@ -1012,6 +728,10 @@ FftEntry make_fft_entry() {
   k.c2r_fold64 = launch_rows_c2r_fold<double, double, R1, R2, R3>;
   k.r2c_cov = launch_rows_r2c<double, double, double, R1, R2, R3, SRC_COV>;
   k.r2c_center = launch_rows_r2c<double, double, double, R1, R2, R3, SRC_CENTER>;
+  k.q_r2c_csr = launch_rows_r2c_queue<double, double, double, R1, R2, R3, SRC_CSR>;
+  k.q_conv64 = launch_cols_queue<double, double, S64, R1, R2, R3, COL_CONV>;
+  k.q_c2r64 = launch_rows_c2r_queue<double, double, double, R1, R2, R3>;
+  k.q_c2r64_32 = launch_rows_c2r_queue<double, double, float, R1, R2, R3>;
   k.r2c_delta = launch_rows_r2c<double, double, double, R1, R2, R3, SRC_DELTA>;
   k.ce_cols32 = launch_cols<float, float, S32, R1, R2, R3, COL_CE>;
   k.ce_cols64 = launch_cols<double, double, S64, R1, R2, R3, COL_CE>;

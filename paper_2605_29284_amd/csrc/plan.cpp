@@ -4,6 +4,7 @@
 #include <hip/hip_runtime.h>
 #include <math.h>
 #include <string.h>
+#include <stdlib.h>
 
 #include <algorithm>
 #include <map>
@@ -811,6 +812,220 @@ void tuned_lookup(krig_plan p) {
 }  // namespace
 
 // =====================================================================================
+struct krig_batch_s {
+  std::vector<krig_plan> plans;
+  hipGraph_t graph = nullptr;
+  hipGraphExec_t exec = nullptr;
+  hipStream_t own = nullptr;   // capture stream created by the batch (stream NULL)
+  hipStream_t cap = nullptr;   // the capture stream
+  void* qbuf = nullptr;        // persistent form: argument blocks and tile tables
+};
+
+namespace {
+
+// The persistent form of an uneven batch.  Every pass of every problem goes into one launch
+// per pass and kernel form: the triangular products grouped by (vec, kg), their sums, then
+// the row, column and inverse-row transforms grouped by transform form (and, for the inverse
+// rows, by dtype).  Each launch is a grid of about one resident round of blocks that walks
+// the pass's (problem, tile) list.
+struct QueueLaunch {
+  int kind;                  // 0 product, 1 sum, 2 rows forward, 3 columns, 4 inverse rows
+  int upper = 0, vec = 0, kg = 1, f32 = 0, NL = 1;
+  const FftEntry* e = nullptr;
+  size_t args_off = 0, first_off = 0, nbx_off = 0;
+  int count = 0, total = 0;
+};
+
+struct QueuePlan {
+  std::vector<unsigned char> host;  // the device buffer's image
+  std::vector<QueueLaunch> launches;
+
+  template <typename T>
+  size_t put(const std::vector<T>& v) {
+    const size_t off = (host.size() + 15) / 16 * 16;
+    host.resize(off + v.size() * sizeof(T));
+    if (!v.empty()) memcpy(host.data() + off, v.data(), v.size() * sizeof(T));
+    return off;
+  }
+  template <typename T>
+  void add(int kind, const std::vector<T>& args, const std::vector<int>& tiles, const std::vector<int>& nbx,
+           QueueLaunch proto) {
+    std::vector<int> first(tiles.size() + 1, 0);
+    for (size_t i = 0; i < tiles.size(); ++i) first[i + 1] = first[i] + tiles[i];
+    proto.kind = kind;
+    proto.args_off = put(args);
+    proto.first_off = put(first);
+    proto.nbx_off = nbx.empty() ? 0 : put(nbx);
+    proto.count = (int)args.size();
+    proto.total = first.back();
+    launches.push_back(proto);
+  }
+};
+
+// Adds the launches of the problems `ids` to qp: first the solve's (products grouped by (vec,
+// kg), then sums), then the transforms'; returns the index of the first transform launch.
+size_t queue_problems(QueuePlan& qp, const std::vector<int>& ids, const krig_plan* plans, const int32_t* h_B,
+                      const double* const* h_y, void* const* h_yhat) {
+  for (int upper = 0; upper < 2; ++upper) {  // L^{-1} y -> tmpv, then L^{-T} tmpv -> alpha
+    std::map<std::pair<int, int>, std::vector<TriProb>> groups;  // (vec, kg) -> problems
+    std::vector<TriProb> all;
+    for (int i : ids) {
+      const krig_plan p = plans[i];
+      const int B = h_B ? h_B[i] : 1;
+      const TriProb tp = upper ? tri_prob(p->LinvT, p->ldL, p->n, p->tmpv, p->ldv, p->alpha, p->n, B, p->tripart)
+                               : tri_prob(p->Linv, p->ldL, p->n, h_y[i], p->n, p->tmpv, p->ldv, B, p->tripart);
+      groups[{tp.vec, tp.kg}].push_back(tp);
+      all.push_back(tp);
+    }
+    for (auto& g : groups) {
+      std::vector<int> tiles;
+      for (const TriProb& tp : g.second) tiles.push_back(tp.per_z * tp.nfz);
+      QueueLaunch ql;
+      ql.upper = upper;
+      ql.vec = g.first.first;
+      ql.kg = g.first.second;
+      qp.add(0, g.second, tiles, {}, ql);
+    }
+    std::vector<int> tiles;
+    for (const TriProb& tp : all) tiles.push_back(tp.nt * tp.nfz);
+    QueueLaunch ql;
+    ql.upper = upper;
+    if (!all.empty()) qp.add(1, all, tiles, {}, ql);
+  }
+  const size_t mid = qp.launches.size();
+  // transforms: scatter + forward rows, columns (x filter), inverse rows
+  std::map<const FftEntry*, std::vector<RowsR2CArgs>> rf;
+  std::map<const FftEntry*, std::vector<int>> rf_t, rf_n;
+  std::map<const FftEntry*, std::vector<ColsArgs>> cf;
+  std::map<const FftEntry*, std::vector<int>> cf_t, cf_n;
+  std::map<std::pair<const FftEntry*, int>, std::vector<RowsC2RArgs>> ri;
+  std::map<std::pair<const FftEntry*, int>, std::vector<int>> ri_t, ri_n;
+  for (int i : ids) {
+    const krig_plan p = plans[i];
+    const int B = h_B ? h_B[i] : 1;
+    const int nlr = nl_rows_for(p->e2, 16), nlc = nl_cols_for(p->e1, 16);
+    RowsR2CArgs r{};
+    r.nrows = p->P1;
+    r.H2 = p->H2;
+    r.out = p->S1;
+    r.out_fs = (int64_t)p->H2 * p->ldP;
+    r.out_ld = p->ldP;
+    r.twF = p->tw2_64;
+    r.row_ptr = p->node_ptr;
+    r.ent_site = p->ent_site;
+    r.ent_w = p->ent_w;
+    r.alpha = p->alpha;
+    r.alpha_fs = p->n;
+    r.ncols = p->P2;
+    r.NL = nlr;
+    const int nbr = ((p->P1 + 1) / 2 + nlr - 1) / nlr;
+    rf[p->e2].push_back(r);
+    rf_t[p->e2].push_back(nbr * B);
+    rf_n[p->e2].push_back(nbr);
+    ColsArgs c{};
+    c.H2 = p->H2;
+    c.in = p->S1;
+    c.in_fs = (int64_t)p->H2 * p->ldP;
+    c.in_ld = p->ldP;
+    c.in_off = 0;
+    c.in_cnt = p->P1;
+    c.filt = p->filt;
+    c.filt_ld = p->F1;
+    c.out = p->S2;
+    c.out_fs = (int64_t)p->H2 * p->ldM;
+    c.out_ld = p->ldM;
+    c.rows = Window{p->g.L, p->g.m1, 0, 0};
+    c.twF = p->tw1_64;
+    c.twI = p->tw1_64;
+    c.B = B;
+    c.NL = nlc;
+    const int nbc = (p->H2 + nlc - 1) / nlc;
+    cf[p->e1].push_back(c);
+    cf_t[p->e1].push_back(nbc * B);
+    cf_n[p->e1].push_back(nbc);
+    RowsC2RArgs o{};
+    o.nrows = p->g.m1;
+    o.H2 = p->H2;
+    o.in = p->S2;
+    o.in_fs = (int64_t)p->H2 * p->ldM;
+    o.in_ld = p->ldM;
+    o.out = h_yhat[i];
+    o.out_fs = (int64_t)p->g.m1 * p->g.m2;
+    o.ldo = p->g.m2;
+    o.cols = Window{p->g.L, p->g.m2, 0, 0};
+    o.twF = p->tw2_64;
+    o.NL = nlr;
+    const int nbi = ((p->g.m1 + 1) / 2 + nlr - 1) / nlr;
+    const auto key = std::make_pair(p->e2, (int)is32(p));
+    ri[key].push_back(o);
+    ri_t[key].push_back(nbi * B);
+    ri_n[key].push_back(nbi);
+  }
+  for (auto& g : rf) {
+    QueueLaunch ql;
+    ql.e = g.first;
+    ql.NL = g.second[0].NL;
+    qp.add(2, g.second, rf_t[g.first], rf_n[g.first], ql);
+  }
+  for (auto& g : cf) {
+    QueueLaunch ql;
+    ql.e = g.first;
+    ql.NL = g.second[0].NL;
+    qp.add(3, g.second, cf_t[g.first], cf_n[g.first], ql);
+  }
+  for (auto& g : ri) {
+    QueueLaunch ql;
+    ql.e = g.first.first;
+    ql.f32 = g.first.second;
+    ql.NL = g.second[0].NL;
+    qp.add(4, g.second, ri_t[g.first], ri_n[g.first], ql);
+  }
+  return mid;
+}
+
+// nblocks for the transform kernels: 0 one resident round of blocks, -d 1/d of one
+int queue_launch(const QueueLaunch& ql, unsigned char* base, int nblocks, hipStream_t st) {
+  const int* first = reinterpret_cast<const int*>(base + ql.first_off);
+  if (ql.kind <= 1) {
+    TriQueue tq{reinterpret_cast<const TriProb*>(base + ql.args_off), first, ql.count, ql.total};
+    return hip_status(ql.kind == 0 ? tri_part_queue(tq, ql.upper, ql.vec, ql.kg, st) : tri_sum_queue(tq, ql.upper, st));
+  }
+  QueueArgs qa{base + ql.args_off, first, reinterpret_cast<const int*>(base + ql.nbx_off), ql.count, ql.total};
+  const FftSet& k = ql.e->k;
+  const launch_queue_t fn = ql.kind == 2 ? k.q_r2c_csr : ql.kind == 3 ? k.q_conv64 : ql.f32 ? k.q_c2r64_32 : k.q_c2r64;
+  return hip_status(fn(qa, ql.NL, nblocks, st));
+}
+
+// All problems' passes in order on one stream: the products and sums of L^{-1}, those of
+// L^{-T}, then the transforms.  (Splitting the problems
+// into two halves staggered on two streams, one half's transforms beside the other's solve,
+// measured slower: concurrent persistent grids contend for the same compute units.)
+int batch_queue_record(krig_batch b, const krig_plan* plans, int count, const int32_t* h_B, const double* const* h_y,
+                       void* const* h_yhat, hipStream_t st) {
+  std::vector<int> ids(count);
+  for (int i = 0; i < count; ++i) ids[i] = i;
+  QueuePlan qp;
+  queue_problems(qp, ids, plans, h_B, h_y, h_yhat);
+  if (hipMalloc(&b->qbuf, qp.host.size()) != hipSuccess) return KRIG_ENOMEM;
+  KRIG_TRY(hipMemcpy(b->qbuf, qp.host.data(), qp.host.size(), hipMemcpyHostToDevice));
+  unsigned char* base = static_cast<unsigned char*>(b->qbuf);
+  KRIG_TRY(hipStreamBeginCapture(st, hipStreamCaptureModeThreadLocal));
+  int r = KRIG_OK;
+  for (size_t i = 0; i < qp.launches.size() && r == KRIG_OK; ++i) r = queue_launch(qp.launches[i], base, 0, st);
+  hipGraph_t g = nullptr;
+  const hipError_t ee = hipStreamEndCapture(st, &g);
+  if (r == KRIG_OK && ee != hipSuccess) r = KRIG_EHIP;
+  if (r != KRIG_OK) {
+    if (g) (void)hipGraphDestroy(g);
+    return r;
+  }
+  b->graph = g;
+  if (hipGraphInstantiate(&b->exec, b->graph, nullptr, nullptr, 0) != hipSuccess) return KRIG_EHIP;
+  return KRIG_OK;
+}
+
+}  // namespace
+
 extern "C" {
 
 const char* krig_strerror(int s) {
@@ -1741,15 +1956,10 @@ int krig_predict_many(const krig_plan* plans, int32_t count, const int32_t* h_B,
   return KRIG_OK;
 }
 
-struct krig_batch_s {
-  std::vector<krig_plan> plans;
-  hipGraph_t graph = nullptr;
-  hipGraphExec_t exec = nullptr;
-  hipStream_t own = nullptr;   // capture stream created by the batch (stream NULL)
-  hipStream_t cap = nullptr;   // the capture stream
-};
+
 
 static void batch_free(krig_batch b) {
+  if (b->qbuf) (void)hipFree(b->qbuf);
   if (b->exec) (void)hipGraphExecDestroy(b->exec);
   if (b->graph) (void)hipGraphDestroy(b->graph);
   if (b->own) (void)hipStreamDestroy(b->own);
@@ -1759,11 +1969,15 @@ static void batch_free(krig_batch b) {
 
 int krig_batch_create(krig_batch* out, const krig_plan* plans, int32_t count, const int32_t* h_B,
                       const double* const* h_y, void* const* h_yhat, int32_t lanes, void* stream) {
-  if (!out || lanes < 1 || lanes > 16) return KRIG_EINVAL;
+  if (!out || lanes < 0 || lanes > 16) return KRIG_EINVAL;
   int r = check_many(plans, count, h_B, h_y, h_yhat);
   if (r != KRIG_OK) return r;
   for (int i = 0; i < count; ++i)
     if (plans[i]->timing) return KRIG_EINVAL;
+  if (lanes == 0)  // the work-queue form runs all problems' passes at once: one plan each
+    for (int i = 0; i < count; ++i)
+      for (int j = 0; j < i; ++j)
+        if (plans[j] == plans[i]) return KRIG_EINVAL;
   // workspaces at their final size before anything is recorded
   for (int i = 0; i < count; ++i)
     if ((r = ensure_ws(plans[i], h_B ? h_B[i] : 1)) != KRIG_OK) return r;
@@ -1780,6 +1994,15 @@ int krig_batch_create(krig_batch* out, const krig_plan* plans, int32_t count, co
   for (int i = 0; i < count; ++i) {
     b->plans.push_back(plans[i]);
     ++plans[i]->batch_refs;
+  }
+  if (lanes == 0) {
+    r = batch_queue_record(b, plans, count, h_B, h_y, h_yhat, b->cap);
+    if (r != KRIG_OK) {
+      batch_free(b);
+      return r;
+    }
+    *out = b;
+    return KRIG_OK;
   }
   // problems to branches: the problems of one plan share its workspaces, so they stay
   // on one branch (in order); plans go largest first to the least-loaded branch

@@ -159,6 +159,33 @@ def test_batch_graph_replays(krig, problems, lanes):
         bt.close()
 
 
+def test_batch_persistent_replays(krig, problems):
+    """The work-queue (persistent) form, lanes = 0: every pass of all problems in one launch
+    per pass and kernel form; each replay must reproduce every plan's own krig_predict bit for
+    bit (problem 3 has two fields), with eager work on the plans between replays.  A plan
+    that appears twice is refused (the problems run at once, each in its plan's workspaces)."""
+    say("batch persistent form")
+    qs = problems[:-1]  # distinct plans
+    ref = reference(qs)
+    outs = [q["p"].empty(q["y"].shape[0], q["w"].m1, q["w"].m2) for q in qs]
+    bt = krig.Batch([q["p"] for q in qs], [q["y"] for q in qs], outs, lanes=0)
+    try:
+        for rep in range(3):
+            for o in outs:
+                o.fill_(float("nan"))  # a replay must write every output
+            torch.cuda.synchronize()
+            bt.launch()
+            torch.cuda.synchronize()
+            for i, (o, r) in enumerate(zip(outs, ref)):
+                assert np.array_equal(host(o), r), (rep, i)
+            host(qs[1]["p"].predict(qs[1]["y"]))
+    finally:
+        bt.close()
+    with pytest.raises(krig.KrigError) as e:
+        krig.Batch([problems[0]["p"], problems[-1]["p"]], [problems[0]["y"], problems[-1]["y"]], outs[:1] * 2, lanes=0)
+    assert e.value.status == -1
+
+
 def test_batch_guards(krig, problems):
     """While a batch exists its plans refuse destruction and workspace growth."""
     say("batch guards")
