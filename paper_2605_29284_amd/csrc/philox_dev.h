@@ -50,6 +50,17 @@ __device__ inline void box_muller_f64(uint32_t x0, uint32_t x1, double& n0, doub
   n1 = r * s;
 }
 
+// the same two normals with the logarithm, square root and sine/cosine in FP32 (the uniforms
+// are formed in FP64 and rounded once): a few ulp of FP32, for samplers that compute in FP32
+__device__ inline void box_muller_f32(uint32_t x0, uint32_t x1, float& n0, float& n1) {
+  const float u0 = (float)u01_f64(x0), u1 = (float)u01_f64(x1);
+  const float r = sqrtf(-2.0f * logf(u0));
+  float s, c;
+  sincospif(2.0f * u1, &s, &c);
+  n0 = r * c;
+  n1 = r * s;
+}
+
 enum { STREAM_CE = 0, STREAM_NUGGET = 1 };
 
 }  // namespace krig
