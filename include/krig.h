@@ -181,7 +181,9 @@ int krig_filter(krig_plan p, int32_t setup, double *d_spec);
 int krig_lag(krig_plan p, void *d_lag);
 
 /* Kriging coefficients alpha = (K + tau^2 I)^{-1} y for B fields (eq. findc), FP64:
- * d_y, d_alpha [B][n] (may alias). */
+ * d_y, d_alpha [B][n] (may alias).  Two launches, L^{-1} y into a workspace, then L^{-T}
+ * of that, with the explicit inverse Cholesky factor formed at plan creation; bitwise
+ * repeatable. */
 int krig_solve(krig_plan p, int32_t B, const double *d_y, double *d_alpha);
 
 /*
@@ -190,11 +192,11 @@ int krig_solve(krig_plan p, int32_t B, const double *d_y, double *d_alpha);
  * results as krig_solve (the same kernels in the same order: bitwise the same alpha), but
  * the workspace comes from a fixed scratch array of KRIG_SOLVE_NOALLOC_SCRATCH_BYTES that
  * the library holds on each GPU from its first use until the process ends; nothing is
- * allocated or freed, and stage timing does not cover this call.  The scratch must hold
- * B * (n rounded up to 4) + ceil(n/16) * ceil(ceil(n/16)/8) * ceil(B/16) * 256 doubles
- * (KRIG_INFO_SOLVE_NOALLOC_MAX_B gives the largest B for a plan: 13616 fields at n = 200,
- * 496 at n = 1368, 32 at n = 5000, 16 at n = 8000, none beyond n = 8,176).  KRIG_EINVAL for a
- * larger request, or when the current device is not the one the plan was created on.
+ * allocated or freed, and stage timing does not cover this call.  The scratch holds the
+ * intermediate vector between the two triangular products, B * (n rounded up to 4) doubles
+ * (KRIG_INFO_SOLVE_NOALLOC_MAX_B gives the largest B for a plan: 41943 fields at n = 200,
+ * 6132 at n = 1368, 1048 at n = 8000, 419 at n = 20000).  KRIG_EINVAL for a larger
+ * request, or when the current device is not the one the plan was created on.
  * Every call on one GPU shares that GPU's scratch, and a call's work reads it after the
  * call returns: calls that overlap on one GPU (other streams, other plans, other host
  * threads) race and give wrong results.  Asynchronous on the plan's stream; d_y and

@@ -231,9 +231,13 @@ class Plan:
         _check(self.lib.krig_filter(self.h, s, out.data_ptr()), "krig_filter")
         return out
 
-    def solve(self, y):
+    def solve(self, y, out=None):
+        """krig_solve; out may be y itself (an in-place solve)."""
         y = self._batch(y, (self.n,), "y", self.torch.float64)
-        out = self.empty(y.shape[0], self.n, dtype=self.torch.float64)
+        if out is None:
+            out = self.empty(y.shape[0], self.n, dtype=self.torch.float64)
+        else:
+            out = self._t(out, self.torch.float64, (y.shape[0], self.n), "out")
         self._stream()
         _check(self.lib.krig_solve(self.h, y.shape[0], y.data_ptr(), out.data_ptr()), "krig_solve")
         return out

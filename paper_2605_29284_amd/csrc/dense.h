@@ -35,36 +35,30 @@ hipError_t fill_f64(double* p, int64_t cnt, double v, hipStream_t st);
 hipError_t transpose_f64(const double* src, int64_t ld_src, double* dst, int64_t ld_dst, int n, hipStream_t st);
 // out[b] = T in[b] for a triangular T (upper = 0: lower, 1: upper); T row-major with a
 // pitch ldt that is a multiple of 4 and >= n rounded up to 16, 32-byte aligned, zeros
-// outside the triangle and in the padding.  hipErrorInvalidValue otherwise.
-// part: tri_part_size(n, B) doubles of workspace.
-int tri_max_splits(int n);
-inline size_t tri_part_size(int n, int B) { return (size_t)((n + 15) / 16) * tri_max_splits(n) * ((B + 15) / 16) * 256; }
+// outside the triangle and in the padding.  hipErrorInvalidValue otherwise.  One launch,
+// no workspace; in and out must not overlap.
 hipError_t tri_apply(const double* T, int64_t ldt, int n, int upper, const double* in, int64_t in_fs, double* out,
-                     int64_t out_fs, int B, double* part, hipStream_t st);
+                     int64_t out_fs, int B, hipStream_t st);
 
 // One problem of a persistent triangular product (an uneven batch): tri_apply's arguments and
-// its tile counts (nt row tiles x qs splits x nfz field groups for the products, nt x nfz for
-// the sums; kg chunk groups per wave; vec: 32-byte input vectors).
+// its tile counts (nt row tiles x nfz field groups; vec: 32-byte input vectors).
 struct TriProb {
   const double* T;
   int64_t ldt;
   const double* in;
   int64_t in_fs;
-  double* part;
   double* out;
   int64_t out_fs;
-  int n, B, qmax, kg, nt, qs, nfz, vec;
-  int per_z;              // product tiles per field group: the (row tile, split) pairs with chunks
+  int n, B, nt, nfz, vec;
 };
 TriProb tri_prob(const double* T, int64_t ldt, int n, const double* in, int64_t in_fs, double* out, int64_t out_fs,
-                 int B, double* part);
+                 int B);
 struct TriQueue {
   const TriProb* probs;   // device array of count problems
-  const int* first;       // [count + 1] prefix sums of their tile counts
+  const int* first;       // [count + 1] prefix sums of their tile counts (nt nfz each)
   int count, total;
 };
-// product tiles of problems that all have this (upper, vec, kg); then the sums (any kg, vec)
-hipError_t tri_part_queue(const TriQueue& q, int upper, int vec, int kg, hipStream_t st);
-hipError_t tri_sum_queue(const TriQueue& q, int upper, hipStream_t st);
+// the products of problems that all have this (upper, vec)
+hipError_t tri_apply_queue(const TriQueue& q, int upper, int vec, hipStream_t st);
 
 }  // namespace krig

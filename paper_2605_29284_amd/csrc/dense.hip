@@ -373,65 +373,50 @@ hipError_t transpose_f64(const double* src, int64_t ld_src, double* dst, int64_t
 // zeros outside the triangle and in the pitch padding):
 //   upper = 0:  out[b][i] = sum_{k <= i} T[i][k] in[b][k]      (T = L^{-1})
 //   upper = 1:  out[b][i] = sum_{k >= i} T[i][k] in[b][k]      (T = L^{-T})
-// Work unit (one wave): 16 output rows (row tile t) x 16 fields x KG groups of TRI_KS
-// chunks of 16 columns (KG = 1, or 4 for long rows).  A row tile's chunks are split
-// over many waves so that no compute unit
-// streams a long row block alone (a single unit's share of memory bandwidth is
-// small).  Per chunk, lane (r = l%16, g = l/16) loads T[16t+r][16c + 4g .. +3] as
-// one 32-byte vector (whole 128-byte row segments per wave) and in[f0+r][same k];
-// four MFMA 16x16x4 steps take element s of each, i.e. the K order inside a chunk
-// is permuted identically for both operands.  Each wave stores its 16 x 16 partial
-// tile; a second kernel sums a tile's partials in the order of the split index.
+// One workgroup of TRI_NW waves owns an output tile: 16 rows (row tile t) x 16 fields
+// (group z), over the tile's chunks of 16 columns inside the triangle.  Wave w takes chunks
+// w, w + TRI_NW, ... (the waves read neighbouring row segments together), TRI_KS chunks in
+// flight at a time.  Per chunk, lane (r = l%16, g = l/16) loads T[16t+r][16c + 4g .. +3] as
+// one 32-byte vector (whole 128-byte row segments per wave) and in[16z+r][same k]; four MFMA
+// 16x16x4 steps take element s of each, so the K order inside a chunk is permuted identically
+// for both operands.  The waves' partial tiles are added through LDS in wave order: one launch
+// per product, no partials in device memory, bitwise repeatable results.
 // ------------------------------------------------------------------------------------
-constexpr int TRI_KS = 8;
-
-__host__ __device__ inline int tri_splits(int n, int t, int upper) {
-  const int nch = (n + 15) / 16;
-  const int len = upper ? nch - t : t + 1;
-  return (len + TRI_KS - 1) / TRI_KS;
-}
-int tri_max_splits(int n) { return tri_splits(n, 0, 1); }
-__host__ __device__ inline int tri_splits_kg(int n, int t, int upper, int kg) {
-  const int nch = (n + 15) / 16;
-  const int len = upper ? nch - t : t + 1;
-  return (len + TRI_KS * kg - 1) / (TRI_KS * kg);
-}
+constexpr int TRI_KS = 4;   // chunks in flight per wave
+constexpr int TRI_NW = 16;  // waves per tile
 
 // VEC: in_fs is a multiple of 4 and in 32-byte aligned, so a lane's four input values
 // are one 32-byte load (values past n are masked to zero).
-template <int UPPER, bool VEC, int KG>
-__device__ __forceinline__ void tri_part_body(const double* __restrict__ T, int64_t ldt, int n,
+template <int UPPER, bool VEC>
+__device__ __forceinline__ void tri_tile_body(const double* __restrict__ T, int64_t ldt, int n,
                                               const double* __restrict__ in, int64_t in_fs, int B,
-                                              double* __restrict__ part, int qmax, int t, int q, int z, int nfz) {
-  if (q >= tri_splits_kg(n, t, UPPER, KG)) return;  // the whole wave
-  const int lane = threadIdx.x, r = lane & 15, g = lane >> 4;
+                                              double* __restrict__ out, int64_t out_fs, int t, int z,
+                                              double (*red)[256]) {
+  const int tid = threadIdx.x, w = tid >> 6, lane = tid & 63, r = lane & 15, g = lane >> 4;
   const int i0 = 16 * t, f0 = 16 * z;
   const int nch = (n + 15) / 16;
-  const int cb0 = (UPPER ? t : 0) + q * TRI_KS * KG;
-  const int ce = min(cb0 + TRI_KS * KG, UPPER ? nch : t + 1);
+  const int cbeg = UPPER ? t : 0, cend = UPPER ? nch : t + 1;
   const bool rok = i0 + r < n, fok = f0 + r < B;
   const double* trow = T + (int64_t)(rok ? i0 + r : 0) * ldt;
   const double* irow = in + (int64_t)(fok ? f0 + r : 0) * in_fs;
   double4_t acc = (double4_t){0.0, 0.0, 0.0, 0.0};
-#pragma unroll
-  for (int gg = 0; gg < KG; ++gg) {
-    const int cb = cb0 + gg * TRI_KS;
+  for (int cb = cbeg + w; cb < cend; cb += TRI_NW * TRI_KS) {
     double4_t x[TRI_KS];
     double a[TRI_KS][4];
 #pragma unroll
     for (int u = 0; u < TRI_KS; ++u) {
-      const int c = cb + u;
+      const int c = cb + u * TRI_NW;
       const int k = 16 * c + 4 * g;
       x[u] = (double4_t){0.0, 0.0, 0.0, 0.0};
-      if (rok && c < ce) x[u] = *reinterpret_cast<const double4_t*>(trow + k);
+      if (rok && c < cend) x[u] = *reinterpret_cast<const double4_t*>(trow + k);
       if constexpr (VEC) {
         double4_t av = (double4_t){0.0, 0.0, 0.0, 0.0};
-        if (fok && c < ce && k < n) av = *reinterpret_cast<const double4_t*>(irow + k);
+        if (fok && c < cend && k < n) av = *reinterpret_cast<const double4_t*>(irow + k);
 #pragma unroll
         for (int s = 0; s < 4; ++s) a[u][s] = k + s < n ? av[s] : 0.0;
       } else {
 #pragma unroll
-        for (int s = 0; s < 4; ++s) a[u][s] = (fok && c < ce && k + s < n) ? irow[k + s] : 0.0;
+        for (int s = 0; s < 4; ++s) a[u][s] = (fok && c < cend && k + s < n) ? irow[k + s] : 0.0;
       }
     }
 #pragma unroll
@@ -439,118 +424,65 @@ __device__ __forceinline__ void tri_part_body(const double* __restrict__ T, int6
 #pragma unroll
       for (int s = 0; s < 4; ++s) acc = __builtin_amdgcn_mfma_f64_16x16x4f64(a[u][s], x[u][s], acc, 0, 0, 0);
   }
-  double* pp = part + ((int64_t)(t * qmax + q) * nfz + z) * 256;
+  // element e = 64 j + lane of a partial tile is MFMA result register j of lane `lane`:
+  // field f0 + lane/16 + 4 j, row i0 + lane%16
 #pragma unroll
-  for (int j = 0; j < 4; ++j) pp[j * 64 + lane] = acc[j];
-}
-
-template <int UPPER, bool VEC, int KG>
-__global__ void __launch_bounds__(64) k_tri_part(const double* __restrict__ T, int64_t ldt, int n,
-                                                 const double* __restrict__ in, int64_t in_fs, int B,
-                                                 double* __restrict__ part, int qmax) {
-  tri_part_body<UPPER, VEC, KG>(T, ldt, n, in, in_fs, B, part, qmax, blockIdx.x, blockIdx.y, blockIdx.z, gridDim.z);
-}
-
-// out = sum of a tile's partials (split index order); element e of a partial tile is
-// MFMA result register e/64 of lane e%64: field f0 + (e%64)/16 + 4 (e/64), row i0 + e%16
-template <int UPPER>
-__device__ __forceinline__ void tri_sum_body(const double* __restrict__ part, int n, int B, int qmax,
-                                             double* __restrict__ out, int64_t out_fs, int kg, int t, int z, int nfz) {
-  const int e = threadIdx.x, lane = e & 63, j = e >> 6;
-  const int f = 16 * z + (lane >> 4) + 4 * j, i = 16 * t + (lane & 15);
-  const int ns = tri_splits_kg(n, t, UPPER, kg);
-  double s = 0.0;
-  for (int q0 = 0; q0 < ns; q0 += 16) {  // up to 16 loads in flight (one round for n <= 2048), summed in split order
-    double v[16];
+  for (int j = 0; j < 4; ++j) red[w][j * 64 + lane] = acc[j];
+  __syncthreads();
+  if (tid < 256) {
+    double s = 0.0;
 #pragma unroll
-    for (int u = 0; u < 16; ++u) v[u] = q0 + u < ns ? part[((int64_t)(t * qmax + q0 + u) * nfz + z) * 256 + e] : 0.0;
-#pragma unroll
-    for (int u = 0; u < 16; ++u)
-      if (q0 + u < ns) s += v[u];
+    for (int v = 0; v < TRI_NW; ++v) s += red[v][tid];
+    const int f = f0 + ((tid & 63) >> 4) + 4 * (tid >> 6), i = i0 + (tid & 15);
+    if (f < B && i < n) out[(int64_t)f * out_fs + i] = s;
   }
-  if (f < B && i < n) out[(int64_t)f * out_fs + i] = s;
 }
 
-template <int UPPER>
-__global__ void __launch_bounds__(256) k_tri_sum(const double* __restrict__ part, int n, int B, int qmax,
-                                                 double* __restrict__ out, int64_t out_fs, int kg) {
-  tri_sum_body<UPPER>(part, n, B, qmax, out, out_fs, kg, blockIdx.x, blockIdx.y, gridDim.y);
+template <int UPPER, bool VEC>
+__global__ void __launch_bounds__(64 * TRI_NW) k_tri_tile(const double* __restrict__ T, int64_t ldt, int n,
+                                                         const double* __restrict__ in, int64_t in_fs, int B,
+                                                         double* __restrict__ out, int64_t out_fs) {
+  __shared__ double red[TRI_NW][256];
+  tri_tile_body<UPPER, VEC>(T, ldt, n, in, in_fs, B, out, out_fs, blockIdx.x, blockIdx.y, red);
 }
 
-// Persistent forms for an uneven batch: the tiles of several problems' products in one list
+// Persistent form for an uneven batch: the tiles of several problems' products in one list
 // (problem i owns tiles [first[i], first[i + 1])), walked by a grid of about one resident
-// round of blocks, block b taking tiles b, b + grid, ...  A product tile is (t, q, z) =
-// (row tile, split, field group), a sum tile (t, z); each computes what the problem's own
-// launch computes.
+// round of workgroups, workgroup b taking tiles b, b + grid, ...  Tile (t, z) of a problem
+// computes what the problem's own launch computes.
 template <typename T> using const_as = const __attribute__((address_space(4))) T;
 
-__device__ __forceinline__ bool tri_next(const TriQueue& qa, int& iter, int& prob, int& local) {
-  // the tile index only grows, so the problem is found by stepping forward from the last one
-  const int t = blockIdx.x + (iter++) * gridDim.x;
-  if (t >= qa.total) return false;
-  while (prob + 1 < qa.count && qa.first[prob + 1] <= t) ++prob;
-  local = t - qa.first[prob];
-  return true;
-}
-
-// Only the (row tile, split) pairs that hold chunks are listed: split q covers row tiles
-// [q w, nt) of a lower product and [0, nt - q w) of an upper one (w = TRI_KS * KG chunks per
-// split), nt - q w tiles either way, field groups outermost.
-template <int UPPER, bool VEC, int KG>
-__global__ void __launch_bounds__(64) k_tri_part_queue(TriQueue qa) {
-  int prob = 0, local, iter = 0;
-  while (tri_next(qa, iter, prob, local)) {
+template <int UPPER, bool VEC>
+__global__ void __launch_bounds__(64 * TRI_NW) k_tri_tile_queue(TriQueue qa) {
+  __shared__ double red[TRI_NW][256];
+  int prob = 0, iter = 0;
+  for (;;) {
+    // the tile index only grows, so the problem is found by stepping forward from the last one
+    const int tile = blockIdx.x + (iter++) * gridDim.x;
+    if (tile >= qa.total) return;
+    while (prob + 1 < qa.count && qa.first[prob + 1] <= tile) ++prob;
     const_as<TriProb>* p = (const_as<TriProb>*)(qa.probs) + prob;
-    const int nt = p->nt, w = TRI_KS * KG;
-    const int z = local / p->per_z;
-    int rem = local - z * p->per_z, q = 0;
-    while (rem >= nt - q * w) {
-      rem -= nt - q * w;
-      ++q;
-    }
-    const int t = UPPER ? rem : q * w + rem;
-    tri_part_body<UPPER, VEC, KG>(p->T, p->ldt, p->n, p->in, p->in_fs, p->B, p->part, p->qmax, t, q, z, p->nfz);
+    const int local = tile - qa.first[prob];
+    tri_tile_body<UPPER, VEC>(p->T, p->ldt, p->n, p->in, p->in_fs, p->B, p->out, p->out_fs, local % p->nt,
+                              local / p->nt, red);
+    __syncthreads();  // red is reused by the next tile
   }
-}
-
-template <int UPPER>
-__global__ void __launch_bounds__(256) k_tri_sum_queue(TriQueue qa) {
-  int prob = 0, local, iter = 0;
-  while (tri_next(qa, iter, prob, local)) {
-    const_as<TriProb>* p = (const_as<TriProb>*)(qa.probs) + prob;
-    tri_sum_body<UPPER>(p->part, p->n, p->B, p->qmax, p->out, p->out_fs, p->kg, local % p->nt, local / p->nt, p->nfz);
-  }
-}
-
-template <int UPPER, int KG>
-void tri_part_launch(bool vec, dim3 grid, const double* T, int64_t ldt, int n, const double* in, int64_t in_fs, int B,
-                     double* part, int qmax, hipStream_t st) {
-  if (vec)
-    hipLaunchKernelGGL((k_tri_part<UPPER, true, KG>), grid, dim3(64), 0, st, T, ldt, n, in, in_fs, B, part, qmax);
-  else
-    hipLaunchKernelGGL((k_tri_part<UPPER, false, KG>), grid, dim3(64), 0, st, T, ldt, n, in, in_fs, B, part, qmax);
 }
 
 TriProb tri_prob(const double* T, int64_t ldt, int n, const double* in, int64_t in_fs, double* out, int64_t out_fs,
-                 int B, double* part) {
+                 int B) {
   TriProb p{};
   p.T = T;
   p.ldt = ldt;
   p.in = in;
   p.in_fs = in_fs;
-  p.part = part;
   p.out = out;
   p.out_fs = out_fs;
   p.n = n;
   p.B = B;
-  p.qmax = tri_max_splits(n);
-  p.kg = n >= 8192 ? 4 : 1;
   p.nt = (n + 15) / 16;
-  p.qs = tri_splits_kg(n, 0, 1, p.kg);
   p.nfz = (B + 15) / 16;
   p.vec = (in_fs & 3) == 0 && (reinterpret_cast<uintptr_t>(in) & 31) == 0;
-  p.per_z = 0;
-  for (int q = 0; q < p.qs; ++q) p.per_z += p.nt - q * TRI_KS * p.kg;
   return p;
 }
 
@@ -563,58 +495,39 @@ static int cu_count() {
 }
 
 template <typename K>
-static int tri_resident(K kernel, int threads) {
+static int tri_resident(K kernel) {
   int per = 0;
-  if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per, kernel, threads, 0) != hipSuccess || per < 1) per = 1;
+  if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per, kernel, 64 * TRI_NW, 0) != hipSuccess || per < 1) per = 1;
   return per * cu_count();
 }
 
-hipError_t tri_part_queue(const TriQueue& q, int upper, int vec, int kg, hipStream_t st) {
-#define KRIG_TRIQ(U, V, KGV)                                                                    \
-  if (upper == U && vec == V && kg == KGV) {                                                    \
-    hipLaunchKernelGGL((k_tri_part_queue<U, V, KGV>), dim3(tri_resident(k_tri_part_queue<U, V, KGV>, 64)), \
-                       dim3(64), 0, st, q);                                                     \
-    return hipGetLastError();                                                                   \
+hipError_t tri_apply_queue(const TriQueue& q, int upper, int vec, hipStream_t st) {
+#define KRIG_TRIQ(U, V)                                                                                     \
+  if (upper == U && vec == V) {                                                                             \
+    hipLaunchKernelGGL((k_tri_tile_queue<U, V>), dim3(tri_resident(k_tri_tile_queue<U, V>)), dim3(64 * TRI_NW), \
+                       0, st, q);                                                                           \
+    return hipGetLastError();                                                                               \
   }
-  KRIG_TRIQ(0, true, 1) KRIG_TRIQ(0, false, 1) KRIG_TRIQ(0, true, 4) KRIG_TRIQ(0, false, 4)
-  KRIG_TRIQ(1, true, 1) KRIG_TRIQ(1, false, 1) KRIG_TRIQ(1, true, 4) KRIG_TRIQ(1, false, 4)
+  KRIG_TRIQ(0, true) KRIG_TRIQ(0, false) KRIG_TRIQ(1, true) KRIG_TRIQ(1, false)
 #undef KRIG_TRIQ
   return hipErrorInvalidValue;
 }
 
-hipError_t tri_sum_queue(const TriQueue& q, int upper, hipStream_t st) {
-  if (upper)
-    hipLaunchKernelGGL(k_tri_sum_queue<1>, dim3(tri_resident(k_tri_sum_queue<1>, 256)), dim3(256), 0, st, q);
-  else
-    hipLaunchKernelGGL(k_tri_sum_queue<0>, dim3(tri_resident(k_tri_sum_queue<0>, 256)), dim3(256), 0, st, q);
-  return hipGetLastError();
-}
-
 hipError_t tri_apply(const double* T, int64_t ldt, int n, int upper, const double* in, int64_t in_fs, double* out,
-                     int64_t out_fs, int B, double* part, hipStream_t st) {
+                     int64_t out_fs, int B, hipStream_t st) {
   if (n <= 0 || B <= 0) return hipSuccess;
   if ((ldt & 3) || ldt < (int64_t)(n + 15) / 16 * 16 || (reinterpret_cast<uintptr_t>(T) & 31))
     return hipErrorInvalidValue;
-  // long rows: four groups of TRI_KS chunks per wave (fewer partial tiles, longer row segments
-  // per DRAM page): measured 10-16% faster from n = 10000 on, slower below n = 5000
-  const int kg = n >= 8192 ? 4 : 1;
-  const int qmax = tri_max_splits(n), nt = (n + 15) / 16, nfz = (B + 15) / 16;
-  dim3 grid(nt, tri_splits_kg(n, 0, 1, kg), nfz);
-  const bool vec = (in_fs & 3) == 0 && (reinterpret_cast<uintptr_t>(in) & 31) == 0;
-  if (upper) {
-    if (kg == 4)
-      tri_part_launch<1, 4>(vec, grid, T, ldt, n, in, in_fs, B, part, qmax, st);
-    else
-      tri_part_launch<1, 1>(vec, grid, T, ldt, n, in, in_fs, B, part, qmax, st);
-    hipLaunchKernelGGL(k_tri_sum<1>, dim3(nt, nfz), dim3(256), 0, st, part, n, B, qmax, out, out_fs, kg);
-  } else {
-    if (kg == 4)
-      tri_part_launch<0, 4>(vec, grid, T, ldt, n, in, in_fs, B, part, qmax, st);
-    else
-      tri_part_launch<0, 1>(vec, grid, T, ldt, n, in, in_fs, B, part, qmax, st);
-    hipLaunchKernelGGL(k_tri_sum<0>, dim3(nt, nfz), dim3(256), 0, st, part, n, B, qmax, out, out_fs, kg);
+  const TriProb p = tri_prob(T, ldt, n, in, in_fs, out, out_fs, B);
+  const dim3 grid(p.nt, p.nfz);
+#define KRIG_TRI(U, V)                                                                                        \
+  if (upper == U && p.vec == V) {                                                                             \
+    hipLaunchKernelGGL((k_tri_tile<U, V>), grid, dim3(64 * TRI_NW), 0, st, T, ldt, n, in, in_fs, B, out, out_fs); \
+    return hipGetLastError();                                                                                 \
   }
-  return hipGetLastError();
+  KRIG_TRI(0, true) KRIG_TRI(0, false) KRIG_TRI(1, true) KRIG_TRI(1, false)
+#undef KRIG_TRI
+  return hipErrorInvalidValue;
 }
 
 }  // namespace krig

@@ -90,7 +90,6 @@ struct krig_plan_s {
   double* alpha = nullptr;  // [B][n]
   double* tmpv = nullptr;   // [B][ldv]  between the two triangular products
   int64_t ldv = 0;          // n rounded up to 4: 32-byte rows for vector loads
-  double* tripart = nullptr;  // partial tiles of the split triangular products
   void* part = nullptr;   // cx FP64 [ngroups][H2][F1]
   int part_groups = 0;
   void* XC = nullptr;     // cx FP64 [H2][ldX]
@@ -385,7 +384,7 @@ int make_filter_centered(krig_plan p, double* filt_out) {
 int ensure_ws(krig_plan p, int B) {
   if (B <= p->wsB) return KRIG_OK;
   if (p->batch_refs > 0) return KRIG_EINVAL;  // a recorded graph uses the current buffers
-  void* olds[] = {p->S1, p->S2, p->alpha, p->tmpv, p->tripart};
+  void* olds[] = {p->S1, p->S2, p->alpha, p->tmpv};
   KRIG_TRY(hipStreamSynchronize(p->st));
   for (void* q : olds) dfree(p, q);
   const size_t H2 = p->H2;
@@ -395,7 +394,6 @@ int ensure_ws(krig_plan p, int B) {
   if ((r = dalloc(p, &p->alpha, (size_t)B * p->n)) != KRIG_OK) return r;
   p->ldv = (p->n + 3) / 4 * 4;
   if ((r = dalloc(p, &p->tmpv, (size_t)B * p->ldv)) != KRIG_OK) return r;
-  if ((r = dalloc(p, &p->tripart, tri_part_size(p->n, B))) != KRIG_OK) return r;
   p->wsB = B;
   return KRIG_OK;
 }
@@ -524,8 +522,8 @@ int weights_from_kvec(krig_plan p, const double* d_kvec) {
 
 int do_solve(krig_plan p, int B, const double* y, double* alpha) {
   StageTimer t(p, KRIG_STAGE_SOLVE);
-  KRIG_TRY(tri_apply(p->Linv, p->ldL, p->n, 0, y, p->n, p->tmpv, p->ldv, B, p->tripart, p->st));
-  KRIG_TRY(tri_apply(p->LinvT, p->ldL, p->n, 1, p->tmpv, p->ldv, alpha, p->n, B, p->tripart, p->st));
+  KRIG_TRY(tri_apply(p->Linv, p->ldL, p->n, 0, y, p->n, p->tmpv, p->ldv, B, p->st));
+  KRIG_TRY(tri_apply(p->LinvT, p->ldL, p->n, 1, p->tmpv, p->ldv, alpha, p->n, B, p->st));
   return KRIG_OK;
 }
 
@@ -824,13 +822,13 @@ struct krig_batch_s {
 namespace {
 
 // The persistent form of an uneven batch.  Every pass of every problem goes into one launch
-// per pass and kernel form: the triangular products grouped by (vec, kg), their sums, then
+// per pass and kernel form: the two triangular products grouped by input form (vec), then
 // the row, column and inverse-row transforms grouped by transform form (and, for the inverse
 // rows, by dtype).  Each launch is a grid of about one resident round of blocks that walks
 // the pass's (problem, tile) list.
 struct QueueLaunch {
-  int kind;                  // 0 product, 1 sum, 2 rows forward, 3 columns, 4 inverse rows
-  int upper = 0, vec = 0, kg = 1, f32 = 0, NL = 1;
+  int kind;                  // 0 triangular product, 2 rows forward, 3 columns, 4 inverse rows
+  int upper = 0, vec = 0, f32 = 0, NL = 1;
   const FftEntry* e = nullptr;
   size_t args_off = 0, first_off = 0, nbx_off = 0;
   int count = 0, total = 0;
@@ -867,30 +865,22 @@ struct QueuePlan {
 size_t queue_problems(QueuePlan& qp, const std::vector<int>& ids, const krig_plan* plans, const int32_t* h_B,
                       const double* const* h_y, void* const* h_yhat) {
   for (int upper = 0; upper < 2; ++upper) {  // L^{-1} y -> tmpv, then L^{-T} tmpv -> alpha
-    std::map<std::pair<int, int>, std::vector<TriProb>> groups;  // (vec, kg) -> problems
-    std::vector<TriProb> all;
+    std::map<int, std::vector<TriProb>> groups;  // vec -> problems
     for (int i : ids) {
       const krig_plan p = plans[i];
       const int B = h_B ? h_B[i] : 1;
-      const TriProb tp = upper ? tri_prob(p->LinvT, p->ldL, p->n, p->tmpv, p->ldv, p->alpha, p->n, B, p->tripart)
-                               : tri_prob(p->Linv, p->ldL, p->n, h_y[i], p->n, p->tmpv, p->ldv, B, p->tripart);
-      groups[{tp.vec, tp.kg}].push_back(tp);
-      all.push_back(tp);
+      const TriProb tp = upper ? tri_prob(p->LinvT, p->ldL, p->n, p->tmpv, p->ldv, p->alpha, p->n, B)
+                               : tri_prob(p->Linv, p->ldL, p->n, h_y[i], p->n, p->tmpv, p->ldv, B);
+      groups[tp.vec].push_back(tp);
     }
     for (auto& g : groups) {
       std::vector<int> tiles;
-      for (const TriProb& tp : g.second) tiles.push_back(tp.per_z * tp.nfz);
+      for (const TriProb& tp : g.second) tiles.push_back(tp.nt * tp.nfz);
       QueueLaunch ql;
       ql.upper = upper;
-      ql.vec = g.first.first;
-      ql.kg = g.first.second;
+      ql.vec = g.first;
       qp.add(0, g.second, tiles, {}, ql);
     }
-    std::vector<int> tiles;
-    for (const TriProb& tp : all) tiles.push_back(tp.nt * tp.nfz);
-    QueueLaunch ql;
-    ql.upper = upper;
-    if (!all.empty()) qp.add(1, all, tiles, {}, ql);
   }
   const size_t mid = qp.launches.size();
   // transforms: scatter + forward rows, columns (x filter), inverse rows
@@ -986,9 +976,9 @@ size_t queue_problems(QueuePlan& qp, const std::vector<int>& ids, const krig_pla
 // nblocks for the transform kernels: 0 one resident round of blocks, -d 1/d of one
 int queue_launch(const QueueLaunch& ql, unsigned char* base, int nblocks, hipStream_t st) {
   const int* first = reinterpret_cast<const int*>(base + ql.first_off);
-  if (ql.kind <= 1) {
+  if (ql.kind == 0) {
     TriQueue tq{reinterpret_cast<const TriProb*>(base + ql.args_off), first, ql.count, ql.total};
-    return hip_status(ql.kind == 0 ? tri_part_queue(tq, ql.upper, ql.vec, ql.kg, st) : tri_sum_queue(tq, ql.upper, st));
+    return hip_status(tri_apply_queue(tq, ql.upper, ql.vec, st));
   }
   QueueArgs qa{base + ql.args_off, first, reinterpret_cast<const int*>(base + ql.nbx_off), ql.count, ql.total};
   const FftSet& k = ql.e->k;
@@ -1314,7 +1304,7 @@ int krig_solve(krig_plan p, int32_t B, const double* d_y, double* d_alpha) {
 
 // ------------------------------------------------------------------ allocation-free solve
 // Scratch of krig_solve_noalloc: the intermediate vector between the two triangular
-// products (B rows of n rounded up to 4) followed by their split partial tiles.  A
+// products (B rows of n rounded up to 4).  A
 // file-scope device array, so each GPU holds one copy from module load until the process
 // ends; host code reaches it only through the address hipGetSymbolAddress returns for
 // the device that is current (the array's name is a host-side stand-in, not a device
@@ -1339,10 +1329,8 @@ int scratch_for_device(int dev, double** out) {
   return KRIG_OK;
 }
 
-// doubles of scratch one solve of B fields needs: the intermediate vector, then the partials
-size_t solve_scratch_doubles(int n, int B) {
-  return (size_t)B * ((n + 3) / 4 * 4) + tri_part_size(n, B);
-}
+// doubles of scratch one solve of B fields needs: the intermediate vector
+size_t solve_scratch_doubles(int n, int B) { return (size_t)B * ((n + 3) / 4 * 4); }
 int solve_noalloc_max_B(int n) {
   const size_t cap = KRIG_SOLVE_NOALLOC_SCRATCH_BYTES / sizeof(double);
   int lo = 0, hi = 65535;  // largest B with solve_scratch_doubles(n, B) <= cap
@@ -1363,14 +1351,13 @@ int krig_solve_noalloc(krig_plan p, int32_t B, const double* d_y, double* d_alph
   double* sp = nullptr;
   int r = scratch_for_device(cur, &sp);
   if (r != KRIG_OK) return r;
-  // the products of krig_solve, with the scratch in place of the plan's workspaces: every
-  // value they read from it is written earlier in the same call (partials per split, the
-  // intermediate's rows up to n; its row padding is loaded but masked), so nothing is cleared
+  // the products of krig_solve, with the scratch in place of the plan's intermediate vector:
+  // every value they read from it is written earlier in the same call (its rows up to n; the
+  // row padding is loaded but masked), so nothing is cleared
   const int64_t ldv = (p->n + 3) / 4 * 4;
   double* tmpv = sp;
-  double* part = sp + (size_t)B * ldv;
-  KRIG_TRY(tri_apply(p->Linv, p->ldL, p->n, 0, d_y, p->n, tmpv, ldv, B, part, p->st));
-  KRIG_TRY(tri_apply(p->LinvT, p->ldL, p->n, 1, tmpv, ldv, d_alpha, p->n, B, part, p->st));
+  KRIG_TRY(tri_apply(p->Linv, p->ldL, p->n, 0, d_y, p->n, tmpv, ldv, B, p->st));
+  KRIG_TRY(tri_apply(p->LinvT, p->ldL, p->n, 1, tmpv, ldv, d_alpha, p->n, B, p->st));
   return KRIG_OK;
 }
 
@@ -1527,7 +1514,7 @@ int krig_predict_adjoint(krig_plan p, int32_t B, const void* d_g, const double* 
     KRIG_TRY((is32(p) ? set1(p).conv_adj_f : set1(p).conv64)(c, B, p->st));
   }
   // The lag-gradient tail does not depend on the gather and solve below (they read SA,
-  // img, alpha, tmpv and tripart): with both outputs asked for, it runs on the plan's
+  // img, alpha and tmpv): with both outputs asked for, it runs on the plan's
   // second stream beside them, filling the compute units the latency-bound solve leaves
   // idle, and joins the plan's stream before this call's work ends.
   const bool fork = d_dlag && d_dy && !p->timing;

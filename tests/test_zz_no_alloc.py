@@ -64,7 +64,7 @@ def test_solve_noalloc_allocates_nothing_and_checks_its_limit(krig):
     p = krig.plan_for(w, "f64")
     try:
         mb = p.info("SOLVE_NOALLOC_MAX_B")
-        assert mb == 496, mb  # B (n rounded up to 4) + ceil(n/16) ceil(ceil(n/16)/8) ceil(B/16) 256 doubles <= 64 MiB
+        assert mb == 6132, mb  # B (n rounded up to 4) doubles <= 64 MiB
         y = dev(np.tile(w.y, (mb + 1, 1)))
         out = torch.empty(mb + 1, w.n, dtype=torch.float64, device="cuda:0")
         torch.cuda.synchronize()
@@ -78,5 +78,23 @@ def test_solve_noalloc_allocates_nothing_and_checks_its_limit(krig):
         got = host(out[:mb])
         ref = host(p.solve(y[:1]))
         assert np.array_equal(got[0], ref[0]) and np.array_equal(got[mb - 1], ref[0])
+    finally:
+        p.close()
+
+
+def test_solve_in_place(krig):
+    """krig_solve and krig_solve_noalloc with d_alpha == d_y (the header allows aliasing: y is
+    read by the first triangular product, alpha written by the second): the in-place results
+    must equal the out-of-place ones bit for bit, twice in a row."""
+    w = wl.paper_field()
+    say("in-place solves, paper field n=1368 B=16")
+    p = krig.plan_for(w, "f64")
+    try:
+        ref = host(p.solve(dev(w.y)))
+        for rep in range(2):
+            y = dev(w.y)
+            assert np.array_equal(host(p.solve(y, out=y)), ref), rep
+            y = dev(w.y)
+            assert np.array_equal(host(p.solve_noalloc(y, y)), ref), rep
     finally:
         p.close()
