@@ -1009,6 +1009,7 @@ def main(argv=None):
         rel = lambda x, y: float(np.max(np.abs(x - y)) / np.max(np.abs(y)))
         out["fp64_value"] = npred / (r64["ms"] * 1e-3)
         out["fp64_ms_per_step"] = r64["ms"]
+        out["fp64_stage_avg_ms"] = {k: round(v[0] / v[1], 5) for k, v in r64["stages"].items() if v[1] > 0}
         out["fp32_vs_fp64_rel_err"] = {
             "yhat": max(rel(r32["yhat"][b], r64["yhat"][b]) for b in range(B)),
             "dy": rel(r32["dy"], r64["dy"]), "dlag": rel(r32["dlag"], r64["dlag"])}

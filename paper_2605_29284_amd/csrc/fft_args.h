@@ -138,9 +138,10 @@ typedef hipError_t (*launch_queue_t)(const QueueArgs&, int NL, int nblocks, hipS
 
 // Kernels for one transform length.  Arithmetic is FP64 in every role of the
 // prediction and its adjoint.  FP64 plans store FP64 spectra between the passes; FP32
-// plans store FP32 spectra where one rounding stays far below the FP32 bounds (the
-// upstream gradient's row spectra, the lag-gradient partials) and FP64 where it does not
-// (the prediction's spectra, the adjoint's correlation spectra; spec_bytes in plan.cpp).
+// plans store FP32 spectra where one rounding stays below the FP32 bounds (the column
+// pass's output of the prediction, the upstream gradient's row spectra, the lag-gradient
+// partials) and FP64 where it does not (the row spectra of c*, the adjoint's correlation
+// spectra; spec_bytes in plan.cpp).
 // Only the conditional-simulation sampler has an FP32-arithmetic form.
 struct FftSet {
   launch_rows_r2c_t r2c_csr;        // scatter + forward rows, FP64 -> FP64 spectra
@@ -148,6 +149,7 @@ struct FftSet {
   launch_rows_r2c_t r2c_dense_f64;  // FP64 rows -> FP64 spectra
   launch_rows_r2c_t r2c_lag;        // even-reflected lag quadrant, FP64
   launch_cols_t conv64;             // all FP64
+  launch_cols_t conv_pred_f;        // FP32 plans' prediction: FP64 row spectra in, FP32 out
   launch_cols_t conv_adj_f;         // FP32 in -> FP64 out (adjoint correlation, FP32 plans)
   launch_cols_t conv_dlag_f;        // the lag-gradient form of FP32 plans: FP32 G, FP64 saved
                                     // spectra of c*, FP64 correlation, FP32 partials
@@ -157,14 +159,14 @@ struct FftSet {
   launch_cols_t inv_sum64;          // inverse columns of a sum of partial spectra (FP64)
   launch_cols_t inv_sum_f;          //   ... of FP32 partials
   launch_rows_c2r_t c2r64;          // inverse rows, FP64
-  launch_rows_c2r_t c2r64_32;       // inverse rows, FP64 spectra -> FP32 output
+  launch_rows_c2r_t c2r_f32;        // inverse rows, FP32 spectra -> FP32 output (FP64 arithmetic)
   launch_rows_c2r_t c2r_fold32;     // inverse rows of the compact correlation, sign images
   launch_rows_c2r_t c2r_fold64;     //   folded, FP64 arithmetic -> FP32 / FP64 lag gradient
   launch_rows_r2c_t r2c_cov;        // covariance on the embedding torus, FP64
   launch_rows_r2c_t r2c_center;     // covariance about the torus centre (F1/2, F2/2), plain coordinates
   launch_rows_r2c_t r2c_delta;      // indicator of the torus centre
   // persistent forms of the prediction's passes (uneven batches)
-  launch_queue_t q_r2c_csr, q_conv64, q_c2r64, q_c2r64_32;
+  launch_queue_t q_r2c_csr, q_conv64, q_c2r64, q_conv_pred_f, q_c2r_f32;
   launch_cols_t ce_cols32, ce_cols64;    // sampler pass 1 (noise x sqrt(Lambda), column transforms)
   launch_rows_ce_t ce_rows32, ce_rows64; // sampler pass 2 (row transforms -> two realisations)
 };

@@ -718,7 +718,9 @@ FftEntry make_fft_entry() {
   k.fwd_real64 = launch_cols<double, double, S64, R1, R2, R3, COL_FWD_REAL>;
   k.inv_sum64 = launch_cols<double, double, S64, R1, R2, R3, COL_INV_SUM>;
   k.c2r64 = launch_rows_c2r<double, double, double, R1, R2, R3>;
-  k.c2r64_32 = launch_rows_c2r<double, double, float, R1, R2, R3>;
+  // FP32 plans' prediction: the column pass stores its output spectra in FP32
+  k.conv_pred_f = launch_cols<double, double, Stor<double, double, float, double>, R1, R2, R3, COL_CONV>;
+  k.c2r_f32 = launch_rows_c2r<double, float, float, R1, R2, R3>;
   // FP32 plans' adjoint: FP64 arithmetic, FP32 spectra where their rounding stays harmless
   k.r2c_dense_f32 = launch_rows_r2c<double, float, float, R1, R2, R3, SRC_DENSE>;
   k.conv_adj_f = launch_cols<double, double, Stor<float, float, double, float>, R1, R2, R3, COL_CONV>;
@@ -731,7 +733,8 @@ FftEntry make_fft_entry() {
   k.q_r2c_csr = launch_rows_r2c_queue<double, double, double, R1, R2, R3, SRC_CSR>;
   k.q_conv64 = launch_cols_queue<double, double, S64, R1, R2, R3, COL_CONV>;
   k.q_c2r64 = launch_rows_c2r_queue<double, double, double, R1, R2, R3>;
-  k.q_c2r64_32 = launch_rows_c2r_queue<double, double, float, R1, R2, R3>;
+  k.q_conv_pred_f = launch_cols_queue<double, double, Stor<double, double, float, double>, R1, R2, R3, COL_CONV>;
+  k.q_c2r_f32 = launch_rows_c2r_queue<double, float, float, R1, R2, R3>;
   k.r2c_delta = launch_rows_r2c<double, double, double, R1, R2, R3, SRC_DELTA>;
   k.ce_cols32 = launch_cols<float, float, S32, R1, R2, R3, COL_CE>;
   k.ce_cols64 = launch_cols<double, double, S64, R1, R2, R3, COL_CE>;

@@ -291,16 +291,16 @@ size_t csz(krig_plan p) { return 2 * p->tsz; }
 //  - the row spectra of the upstream gradient and the lag-gradient partial spectra in
 //    FP32 (8 bytes): one rounding there moves d y by ~1e-7 and d lag by ~1e-8 (relative
 //    max error);
-//  - the prediction's spectra in FP64 (16 bytes): one FP32 rounding of the row spectra of
-//    c* moves y_hat by up to ~3e-5 on cancellation-heavy problems (sum |c*| / max |y_hat|
-//    ~ 1e5), and one of the column pass's output by up to ~3e-6, which also lifts the
-//    rounding noise of finite differences of the predictions above 1e-4;
+//  - the column pass's output of the prediction in FP32: one rounding moves y_hat by up to
+//    ~3e-6 on cancellation-heavy problems (sum |c*| / max |y_hat| ~ 1e5), ~1e-7 on the rest;
+//  - the row spectra of c* in FP64 (16 bytes): one FP32 rounding there moves y_hat by up to
+//    ~3e-5 on cancellation-heavy problems;
 //  - the adjoint's correlation spectra in FP64: d y applies (K + tau^2 I)^{-1} to them,
 //    and one FP32 rounding moves d y by ~1e-4.
 enum SpecRole { SPEC_C, SPEC_PRED, SPEC_G, SPEC_CORR, SPEC_PART };
 size_t spec_bytes(krig_plan p, SpecRole role) {
   if (!is32(p)) return 16;
-  return (role == SPEC_G || role == SPEC_PART) ? 8 : 16;
+  return (role == SPEC_PRED || role == SPEC_G || role == SPEC_PART) ? 8 : 16;
 }
 
 // spectrum of the even-reflected lag quadrant (FP64), scaled by 1/(F1 F2)
@@ -580,7 +580,7 @@ int do_convolve(krig_plan p, int B, const double* alpha, const double* filt, voi
   c.NL = p->nl_cols64;
   {
     StageTimer t(p, KRIG_STAGE_COLS_CONV);
-    KRIG_TRY(set1(p).conv64(c, B, p->st));
+    KRIG_TRY((is32(p) ? set1(p).conv_pred_f : set1(p).conv64)(c, B, p->st));
   }
 
   RowsC2RArgs o{};
@@ -602,7 +602,7 @@ int do_convolve(krig_plan p, int B, const double* alpha, const double* filt, voi
   o.NL = p->nl_rows64;
   {
     StageTimer t(p, KRIG_STAGE_ROWS_INV);
-    KRIG_TRY((is32(p) ? set2(p).c2r64_32 : set2(p).c2r64)(o, B, p->st));
+    KRIG_TRY((is32(p) ? set2(p).c2r_f32 : set2(p).c2r64)(o, B, p->st));
   }
   return KRIG_OK;
 }
@@ -886,8 +886,8 @@ size_t queue_problems(QueuePlan& qp, const std::vector<int>& ids, const krig_pla
   // transforms: scatter + forward rows, columns (x filter), inverse rows
   std::map<const FftEntry*, std::vector<RowsR2CArgs>> rf;
   std::map<const FftEntry*, std::vector<int>> rf_t, rf_n;
-  std::map<const FftEntry*, std::vector<ColsArgs>> cf;
-  std::map<const FftEntry*, std::vector<int>> cf_t, cf_n;
+  std::map<std::pair<const FftEntry*, int>, std::vector<ColsArgs>> cf;
+  std::map<std::pair<const FftEntry*, int>, std::vector<int>> cf_t, cf_n;
   std::map<std::pair<const FftEntry*, int>, std::vector<RowsC2RArgs>> ri;
   std::map<std::pair<const FftEntry*, int>, std::vector<int>> ri_t, ri_n;
   for (int i : ids) {
@@ -930,9 +930,10 @@ size_t queue_problems(QueuePlan& qp, const std::vector<int>& ids, const krig_pla
     c.B = B;
     c.NL = nlc;
     const int nbc = (p->H2 + nlc - 1) / nlc;
-    cf[p->e1].push_back(c);
-    cf_t[p->e1].push_back(nbc * B);
-    cf_n[p->e1].push_back(nbc);
+    const auto ckey = std::make_pair(p->e1, (int)is32(p));
+    cf[ckey].push_back(c);
+    cf_t[ckey].push_back(nbc * B);
+    cf_n[ckey].push_back(nbc);
     RowsC2RArgs o{};
     o.nrows = p->g.m1;
     o.H2 = p->H2;
@@ -959,7 +960,8 @@ size_t queue_problems(QueuePlan& qp, const std::vector<int>& ids, const krig_pla
   }
   for (auto& g : cf) {
     QueueLaunch ql;
-    ql.e = g.first;
+    ql.e = g.first.first;
+    ql.f32 = g.first.second;
     ql.NL = g.second[0].NL;
     qp.add(3, g.second, cf_t[g.first], cf_n[g.first], ql);
   }
@@ -982,11 +984,13 @@ int queue_launch(const QueueLaunch& ql, unsigned char* base, int nblocks, hipStr
   }
   QueueArgs qa{base + ql.args_off, first, reinterpret_cast<const int*>(base + ql.nbx_off), ql.count, ql.total};
   const FftSet& k = ql.e->k;
-  const launch_queue_t fn = ql.kind == 2 ? k.q_r2c_csr : ql.kind == 3 ? k.q_conv64 : ql.f32 ? k.q_c2r64_32 : k.q_c2r64;
+  const launch_queue_t fn = ql.kind == 2   ? k.q_r2c_csr
+                            : ql.kind == 3 ? (ql.f32 ? k.q_conv_pred_f : k.q_conv64)
+                                           : (ql.f32 ? k.q_c2r_f32 : k.q_c2r64);
   return hip_status(fn(qa, ql.NL, nblocks, st));
 }
 
-// All problems' passes in order on one stream: the products and sums of L^{-1}, those of
+// All problems' passes in order on one stream: the product of L^{-1}, that of
 // L^{-T}, then the transforms.  (Splitting the problems
 // into two halves staggered on two streams, one half's transforms beside the other's solve,
 // measured slower: concurrent persistent grids contend for the same compute units.)
