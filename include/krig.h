@@ -329,9 +329,13 @@ int krig_interp(krig_plan p, int32_t B, const void *d_yhat, int32_t npts, const 
  * nodes and dtype (checked: KRIG_EINVAL otherwise).  d_alpha [B][n] FP64: the mixture
  * model's coefficients (the caller's solve); d_lam_sites [C][n] FP64: lam_c at the sites;
  * d_lam_grid [C][m1][m2] FP64: lam_c at the grid nodes; d_yhat [B][m1][m2] in the plans'
- * dtype.  The components' predictions go to each plan's workspace (grown at a new B, like
- * the other workspaces) and are summed in component order in FP64, rounded once.  Runs
- * on stream (NULL: plans[0]'s stream); asynchronous.
+ * dtype.  When all plans have the same neighbour order L (the same transform geometry), the
+ * scaling lam_c(s_i) alpha_i rides in each component's scatter and one inverse-row pass
+ * transforms every component's rows and adds lam_c times them in FP64 in component order,
+ * rounded once to the dtype.  Otherwise each component's prediction goes to its plan's
+ * workspace (grown at a new B, like the other workspaces, and rounded to the dtype) and a
+ * combine pass sums them in component order in FP64, rounded once.  Runs on stream (NULL:
+ * plans[0]'s stream); asynchronous.
  */
 int krig_mixture(const krig_plan *plans, int32_t C, int32_t B, const double *d_alpha,
                  const double *d_lam_sites, const double *d_lam_grid, void *d_yhat, void *stream);

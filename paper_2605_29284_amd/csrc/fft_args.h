@@ -43,6 +43,7 @@ struct RowsR2CArgs {
   const double* ent_w;      // [nnz]
   const double* alpha;      // [B][n]
   int64_t alpha_fs;
+  const double* alpha_scale;  // [n] per-site factor of alpha (the scaled scatter only)
   // dense source: in[b][r][c] (row-major) placed at column offset coff
   const void* dense;        // TIN
   int64_t dense_fs, dense_ld;
@@ -119,6 +120,19 @@ struct RowsC2RArgs {
   int NL;
 };
 
+// Inverse rows of a spatially weighted mixture: out[b][r][c] = sum_{k < C} lam[k][r][c] *
+// (inverse rows of component k's spectra)[b][r][c], accumulated in FP64 in component order
+// and rounded once.  The components share the geometry of r (their spectra differ only in
+// their base pointer); r.in and r.add are not used.
+constexpr int MIX_COMP_MAX = 8;
+struct MixRowsArgs {
+  RowsC2RArgs r;
+  const void* in[MIX_COMP_MAX];   // component k's spectra, laid out as r.in_fs / r.in_ld
+  const double* lam;              // lam[k * lam_cs + r * lam_ld + c]
+  int64_t lam_cs, lam_ld;
+  int C;
+};
+
 // Persistent launch over several problems of one transform form (an uneven batch): problem
 // i's argument block is args[i] (RowsR2CArgs, ColsArgs or RowsC2RArgs, all with the same NL),
 // its tiles are [first[i], first[i + 1]) of the list, nbx[i] per field.
@@ -132,6 +146,7 @@ struct QueueArgs {
 typedef hipError_t (*launch_rows_r2c_t)(const RowsR2CArgs&, int B, hipStream_t);
 typedef hipError_t (*launch_cols_t)(const ColsArgs&, int nblk_y, hipStream_t);
 typedef hipError_t (*launch_rows_c2r_t)(const RowsC2RArgs&, int B, hipStream_t);
+typedef hipError_t (*launch_rows_c2r_mix_t)(const MixRowsArgs&, int B, hipStream_t);
 typedef hipError_t (*launch_rows_ce_t)(const RowsCEArgs&, int npairs, hipStream_t);
 // nblocks 0: one resident round of blocks (occupancy x compute units), -d: a d-th of it
 typedef hipError_t (*launch_queue_t)(const QueueArgs&, int NL, int nblocks, hipStream_t);
@@ -145,6 +160,7 @@ typedef hipError_t (*launch_queue_t)(const QueueArgs&, int NL, int nblocks, hipS
 // Only the conditional-simulation sampler has an FP32-arithmetic form.
 struct FftSet {
   launch_rows_r2c_t r2c_csr;        // scatter + forward rows, FP64 -> FP64 spectra
+  launch_rows_r2c_t r2c_csr_scaled; //   ... of alpha[b][i] * alpha_scale[i] (mixture components)
   launch_rows_r2c_t r2c_dense_f32;  // FP32 rows (upstream gradient) -> FP32 spectra
   launch_rows_r2c_t r2c_dense_f64;  // FP64 rows -> FP64 spectra
   launch_rows_r2c_t r2c_lag;        // even-reflected lag quadrant, FP64
@@ -160,6 +176,8 @@ struct FftSet {
   launch_cols_t inv_sum_f;          //   ... of FP32 partials
   launch_rows_c2r_t c2r64;          // inverse rows, FP64
   launch_rows_c2r_t c2r_f32;        // inverse rows, FP32 spectra -> FP32 output (FP64 arithmetic)
+  launch_rows_c2r_mix_t c2r_mix64;  // weighted sum of components' inverse rows, FP64
+  launch_rows_c2r_mix_t c2r_mix_f32;//   ... FP32 spectra and output (FP64 arithmetic)
   launch_rows_c2r_t c2r_fold32;     // inverse rows of the compact correlation, sign images
   launch_rows_c2r_t c2r_fold64;     //   folded, FP64 arithmetic -> FP32 / FP64 lag gradient
   launch_rows_r2c_t r2c_cov;        // covariance on the embedding torus, FP64

@@ -311,7 +311,7 @@ __device__ __forceinline__ void xf_inv(cx<TC> (&w)[R3], int t, cx<TC>* L, const 
 // ----------------------------------------------------------------------------------------
 // row kernels: forward (real rows -> frequency-major half spectra)
 // ----------------------------------------------------------------------------------------
-enum { SRC_CSR = 0, SRC_DENSE = 1, SRC_LAG = 2, SRC_COV = 3, SRC_CENTER = 4, SRC_DELTA = 5 };
+enum { SRC_CSR = 0, SRC_DENSE = 1, SRC_LAG = 2, SRC_COV = 3, SRC_CENTER = 4, SRC_DELTA = 5, SRC_CSR_SCALED = 6 };
 
 // Kernel bodies (fft_body_*.inc) are included inside the kernels, after the block's logical
 // coordinates (bx: row or column block, by: field or group) are set, so that one text serves a
@@ -393,6 +393,107 @@ KRIG_ROW_KERNEL k_rows_c2r(RowsC2RArgs a) {
   int bx, by;
   logical_block<false>(bx, by);
 #include "fft_body_rows_c2r.inc"
+}
+
+// Inverse rows of a weighted mixture (MixRowsArgs): per component the rows of
+// k_rows_c2r, then lam_k times the kept values added in FP64 in component order; one rounding
+// to TO at the end.  The component's spectra pointer is selected with constant indices (no
+// dynamic indexing of the argument block).
+__device__ __forceinline__ const void* mix_in(const MixRowsArgs& m, int k) {
+  switch (k) {
+    case 0: return m.in[0];
+    case 1: return m.in[1];
+    case 2: return m.in[2];
+    case 3: return m.in[3];
+    case 4: return m.in[4];
+    case 5: return m.in[5];
+    case 6: return m.in[6];
+    default: return m.in[7];
+  }
+}
+
+// A loop over components lets the compiler hoist everything that depends only on the thread's
+// coordinates (twiddle bases and powers, LDS and load addresses) out of it and hold it all in
+// registers (about 250 VGPRs); the coordinates and the twiddle pointer are therefore passed
+// through an empty asm per component, which makes them opaque, and each component recomputes
+// its addresses (133 VGPRs, three waves per SIMD, no scratch; no wave cap).
+template <typename TC, typename TS, typename TO, int R1, int R2, int R3>
+__global__ void __launch_bounds__(256) k_rows_c2r_mix(MixRowsArgs m) {
+  using G = Geo<R1, R2, R3>;
+  const RowsC2RArgs& a = m.r;
+  int bx, by;
+  logical_block<false>(bx, by);
+  extern __shared__ __align__(16) unsigned char smem_raw[];
+  cx<TC>* lds = reinterpret_cast<cx<TC>*>(smem_raw);
+  const int tid0 = threadIdx.x;
+  const int NL = a.NL;
+  const int b = by;
+  const int row0 = 2 * bx * NL;
+  const int R2b = 2 * NL;
+  cx<TC>* T = lds;
+  double acc_a[R3], acc_b[R3];
+#pragma unroll
+  for (int k2 = 0; k2 < R3; ++k2) acc_a[k2] = acc_b[k2] = 0.0;
+#pragma unroll 1
+  for (int k = 0; k < m.C; ++k) {
+    if (k > 0) __syncthreads();  // every line is done with the previous component's LDS
+    const Spec<TS> in = Spec<TS>::field(mix_in(m, k), a.in_fs, b);
+    const cx<TC>* twF = reinterpret_cast<const cx<TC>*>(a.twF);
+    int tid = tid0;
+    asm volatile("" : "+s"(twF), "+v"(tid));
+    const int s = tid % G::NT, l = tid / G::NT;
+    const int ra = row0 + 2 * l, rb = ra + 1;
+    const bool oka = ra < a.nrows, okb = rb < a.nrows;
+    cx<TC>* L = lds + (size_t)l * G::ROWS;
+    const TwB<TC> tb = tw_bases<TC, R1, R2, R3, false>(twF, s);
+    {
+      constexpr int IT = (2 * (G::F / 2 + 1) + G::NT - 1) / G::NT;  // as in k_rows_c2r
+      typename Spec<TS>::raw buf[IT];
+      {
+        TWalk<G::NT> e(tid, NL);
+#pragma unroll
+        for (int it = 0; it < IT; ++it, e.next()) {
+          const int row = row0 + e.rl;
+          buf[it] = (e.k < a.H2 && row < a.nrows) ? in.ldraw((int64_t)e.k * a.in_ld + row) : Spec<TS>::zero();
+        }
+      }
+      TWalk<G::NT> e(tid, NL);
+#pragma unroll
+      for (int it = 0; it < IT; ++it, e.next())
+        if (e.k < a.H2) T[tpos(e.k, e.rl, R2b)] = Spec<TS>::template cvt<TC>(buf[it]);
+    }
+    __syncthreads();
+    cx<TC> v[G::NIN];
+    c2r_line_input<TC, R1, R2, R3>(T, R2b, l, s, a.H2, v);
+    cx<TC> w[R3];
+    xf_fwd<TC, R1, R2, R3, 1>(v, w, s, L, tb);
+    if (s < G::TOUT) {
+      const double* lk = m.lam + (int64_t)k * m.lam_cs;
+#pragma unroll
+      for (int k2 = 0; k2 < R3; ++k2) {
+        const int d = window_dst(a.cols, s + G::TOUT * k2);
+        if (d >= 0) {
+          if (oka) acc_a[k2] += lk[(int64_t)ra * m.lam_ld + d] * (double)w[k2].x;
+          if (okb) acc_b[k2] += lk[(int64_t)rb * m.lam_ld + d] * (double)w[k2].y;
+        }
+      }
+    }
+  }
+  const int s = tid0 % G::NT, l = tid0 / G::NT;
+  const int ra = row0 + 2 * l, rb = ra + 1;
+  const bool oka = ra < a.nrows, okb = rb < a.nrows;
+  if (s < G::TOUT) {
+    TO* oa = reinterpret_cast<TO*>(a.out) + (int64_t)b * a.out_fs + (int64_t)ra * a.ldo;
+    TO* ob = oa + a.ldo;
+#pragma unroll
+    for (int k2 = 0; k2 < R3; ++k2) {
+      const int d = window_dst(a.cols, s + G::TOUT * k2);
+      if (d >= 0) {
+        if (oka) oa[d] = (TO)acc_a[k2];
+        if (okb) ob[d] = (TO)acc_b[k2];
+      }
+    }
+  }
 }
 
 // ----------------------------------------------------------------------------------------
@@ -635,6 +736,19 @@ hipError_t launch_rows_c2r(const RowsC2RArgs& a, int B, hipStream_t st) {
   return hipGetLastError();
 }
 
+template <typename TC, typename TS, typename TO, int R1, int R2, int R3>
+hipError_t launch_rows_c2r_mix(const MixRowsArgs& m, int B, hipStream_t st) {
+  using G = Geo<R1, R2, R3>;
+  const RowsC2RArgs& a = m.r;
+  if (a.H2 != G::F / 2 + 1 || a.NL < 1 || m.C < 1 || m.C > MIX_COMP_MAX) return hipErrorInvalidValue;
+  const int npairs = (a.nrows + 1) / 2;
+  dim3 grid((npairs + a.NL - 1) / a.NL, B);
+  dim3 block(G::NT * a.NL);
+  const size_t sh = rows_lds(G::g, a.NL, sizeof(cx<TC>));
+  k_rows_c2r_mix<TC, TS, TO, R1, R2, R3><<<grid, block, sh, st>>>(m);
+  return hipGetLastError();
+}
+
 template <typename TC, typename TO, int R1, int R2, int R3>
 hipError_t launch_rows_c2r_fold(const RowsC2RArgs& a, int B, hipStream_t st) {
   using G = Geo<R1, R2, R3>;
@@ -711,6 +825,7 @@ FftEntry make_fft_entry() {
   using S64 = Stor<double, double, double, double>;
   using S32 = Stor<float, float, float, float>;
   k.r2c_csr = launch_rows_r2c<double, double, double, R1, R2, R3, SRC_CSR>;
+  k.r2c_csr_scaled = launch_rows_r2c<double, double, double, R1, R2, R3, SRC_CSR_SCALED>;
   k.r2c_dense_f64 = launch_rows_r2c<double, double, double, R1, R2, R3, SRC_DENSE>;
   k.r2c_lag = launch_rows_r2c<double, double, double, R1, R2, R3, SRC_LAG>;
   k.conv64 = launch_cols<double, double, S64, R1, R2, R3, COL_CONV>;
@@ -721,6 +836,8 @@ FftEntry make_fft_entry() {
   // FP32 plans' prediction: the column pass stores its output spectra in FP32
   k.conv_pred_f = launch_cols<double, double, Stor<double, double, float, double>, R1, R2, R3, COL_CONV>;
   k.c2r_f32 = launch_rows_c2r<double, float, float, R1, R2, R3>;
+  k.c2r_mix64 = launch_rows_c2r_mix<double, double, double, R1, R2, R3>;
+  k.c2r_mix_f32 = launch_rows_c2r_mix<double, float, float, R1, R2, R3>;
   // FP32 plans' adjoint: FP64 arithmetic, FP32 spectra where their rounding stays harmless
   k.r2c_dense_f32 = launch_rows_r2c<double, float, float, R1, R2, R3, SRC_DENSE>;
   k.conv_adj_f = launch_cols<double, double, Stor<float, float, double, float>, R1, R2, R3, COL_CONV>;

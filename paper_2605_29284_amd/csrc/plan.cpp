@@ -540,8 +540,9 @@ int filter_for(krig_plan p, const void* d_lag, const double** out) {
   return KRIG_OK;
 }
 
-int do_convolve(krig_plan p, int B, const double* alpha, const double* filt, void* yhat, void* spec1,
-                const void* add, int64_t add_fs, int add_ld) {
+// Argument blocks of the prediction's three passes (Steps 5-7): scatter + forward rows of
+// alpha into spec1, columns (x filter) into S2, inverse rows of S2 into yhat.
+RowsR2CArgs rows_fwd_args(krig_plan p, const double* alpha, void* spec1) {
   RowsR2CArgs r{};
   r.nrows = p->P1;
   r.H2 = p->H2;
@@ -556,11 +557,10 @@ int do_convolve(krig_plan p, int B, const double* alpha, const double* filt, voi
   r.alpha_fs = p->n;
   r.ncols = p->P2;
   r.NL = p->nl_rows64;
-  {
-    StageTimer t(p, KRIG_STAGE_ROWS_FWD);
-    KRIG_TRY(set2(p).r2c_csr(r, B, p->st));
-  }
+  return r;
+}
 
+ColsArgs cols_conv_args(krig_plan p, const void* spec1, const double* filt, int B) {
   ColsArgs c{};
   c.H2 = p->H2;
   c.in = spec1;
@@ -578,11 +578,10 @@ int do_convolve(krig_plan p, int B, const double* alpha, const double* filt, voi
   c.twI = p->tw1_64;
   c.B = B;
   c.NL = p->nl_cols64;
-  {
-    StageTimer t(p, KRIG_STAGE_COLS_CONV);
-    KRIG_TRY((is32(p) ? set1(p).conv_pred_f : set1(p).conv64)(c, B, p->st));
-  }
+  return c;
+}
 
+RowsC2RArgs rows_inv_args(krig_plan p, void* yhat) {
   RowsC2RArgs o{};
   o.nrows = p->g.m1;
   o.H2 = p->H2;
@@ -593,13 +592,27 @@ int do_convolve(krig_plan p, int B, const double* alpha, const double* filt, voi
   o.out_fs = (int64_t)p->g.m1 * p->g.m2;
   o.ldo = p->g.m2;
   o.cols = Window{p->g.L, p->g.m2, 0, 0};
+  o.twF = p->tw2_64;  // FP64 arithmetic; the FP32 form reads FP32 spectra and writes FP32
+  o.NL = p->nl_rows64;
+  return o;
+}
+
+int do_convolve(krig_plan p, int B, const double* alpha, const double* filt, void* yhat, void* spec1,
+                const void* add, int64_t add_fs, int add_ld) {
+  {
+    StageTimer t(p, KRIG_STAGE_ROWS_FWD);
+    KRIG_TRY(set2(p).r2c_csr(rows_fwd_args(p, alpha, spec1), B, p->st));
+  }
+  {
+    StageTimer t(p, KRIG_STAGE_COLS_CONV);
+    KRIG_TRY((is32(p) ? set1(p).conv_pred_f : set1(p).conv64)(cols_conv_args(p, spec1, filt, B), B, p->st));
+  }
+  RowsC2RArgs o = rows_inv_args(p, yhat);
   o.add = add;
   o.add_fs = add_fs;
   o.add_ld = add_ld;
   o.add_r0 = p->g.L;
   o.add_c0 = p->g.L;
-  o.twF = p->tw2_64;  // FP64 arithmetic; the FP32 form only writes FP32
-  o.NL = p->nl_rows64;
   {
     StageTimer t(p, KRIG_STAGE_ROWS_INV);
     KRIG_TRY((is32(p) ? set2(p).c2r_f32 : set2(p).c2r64)(o, B, p->st));
@@ -894,57 +907,20 @@ size_t queue_problems(QueuePlan& qp, const std::vector<int>& ids, const krig_pla
     const krig_plan p = plans[i];
     const int B = h_B ? h_B[i] : 1;
     const int nlr = nl_rows_for(p->e2, 16), nlc = nl_cols_for(p->e1, 16);
-    RowsR2CArgs r{};
-    r.nrows = p->P1;
-    r.H2 = p->H2;
-    r.out = p->S1;
-    r.out_fs = (int64_t)p->H2 * p->ldP;
-    r.out_ld = p->ldP;
-    r.twF = p->tw2_64;
-    r.row_ptr = p->node_ptr;
-    r.ent_site = p->ent_site;
-    r.ent_w = p->ent_w;
-    r.alpha = p->alpha;
-    r.alpha_fs = p->n;
-    r.ncols = p->P2;
+    RowsR2CArgs r = rows_fwd_args(p, p->alpha, p->S1);
     r.NL = nlr;
     const int nbr = ((p->P1 + 1) / 2 + nlr - 1) / nlr;
     rf[p->e2].push_back(r);
     rf_t[p->e2].push_back(nbr * B);
     rf_n[p->e2].push_back(nbr);
-    ColsArgs c{};
-    c.H2 = p->H2;
-    c.in = p->S1;
-    c.in_fs = (int64_t)p->H2 * p->ldP;
-    c.in_ld = p->ldP;
-    c.in_off = 0;
-    c.in_cnt = p->P1;
-    c.filt = p->filt;
-    c.filt_ld = p->F1;
-    c.out = p->S2;
-    c.out_fs = (int64_t)p->H2 * p->ldM;
-    c.out_ld = p->ldM;
-    c.rows = Window{p->g.L, p->g.m1, 0, 0};
-    c.twF = p->tw1_64;
-    c.twI = p->tw1_64;
-    c.B = B;
+    ColsArgs c = cols_conv_args(p, p->S1, p->filt, B);
     c.NL = nlc;
     const int nbc = (p->H2 + nlc - 1) / nlc;
     const auto ckey = std::make_pair(p->e1, (int)is32(p));
     cf[ckey].push_back(c);
     cf_t[ckey].push_back(nbc * B);
     cf_n[ckey].push_back(nbc);
-    RowsC2RArgs o{};
-    o.nrows = p->g.m1;
-    o.H2 = p->H2;
-    o.in = p->S2;
-    o.in_fs = (int64_t)p->H2 * p->ldM;
-    o.in_ld = p->ldM;
-    o.out = h_yhat[i];
-    o.out_fs = (int64_t)p->g.m1 * p->g.m2;
-    o.ldo = p->g.m2;
-    o.cols = Window{p->g.L, p->g.m2, 0, 0};
-    o.twF = p->tw2_64;
+    RowsC2RArgs o = rows_inv_args(p, h_yhat[i]);
     o.NL = nlr;
     const int nbi = ((p->g.m1 + 1) / 2 + nlr - 1) / nlr;
     const auto key = std::make_pair(p->e2, (int)is32(p));
@@ -1909,6 +1885,39 @@ int krig_mixture(const krig_plan* plans, int32_t C, int32_t B, const double* d_a
   }
   const hipStream_t st = stream ? (hipStream_t)stream : p0->st;
   const int n = p0->n;
+  // Components with the same neighbour order share every transform geometry: the scaling of
+  // the coefficients by lam_c(s_i) rides in each component's scatter, and one inverse-row
+  // launch transforms all components' rows and adds lam_c times them in FP64 (no component
+  // images, no combine pass).  Otherwise each component is predicted into its plan's
+  // workspace and a combine pass adds them.
+  bool fused = true;
+  for (int c = 1; c < C; ++c) {
+    const krig_plan p = plans[c];
+    fused = fused && p->g.L == p0->g.L && p->e1 == p0->e1 && p->e2 == p0->e2 && p->P1 == p0->P1 &&
+            p->P2 == p0->P2 && p->ldP == p0->ldP && p->ldM == p0->ldM && p->H2 == p0->H2;
+  }
+  if (fused) {
+    static_assert(MIX_MAX <= MIX_COMP_MAX, "mixture components");
+    MixRowsArgs m{};
+    m.r = rows_inv_args(p0, d_yhat);
+    m.r.in = nullptr;
+    m.lam = d_lam_grid;
+    m.lam_cs = (int64_t)p0->g.m1 * p0->g.m2;
+    m.lam_ld = p0->g.m2;
+    m.C = C;
+    for (int c = 0; c < C; ++c) {
+      const krig_plan p = plans[c];
+      int r;
+      if ((r = ensure_ws(p, B)) != KRIG_OK) return r;
+      RowsR2CArgs ra = rows_fwd_args(p, d_alpha, p->S1);
+      ra.alpha_scale = d_lam_sites + (size_t)c * n;
+      KRIG_TRY(set2(p).r2c_csr_scaled(ra, B, st));
+      KRIG_TRY((is32(p) ? set1(p).conv_pred_f : set1(p).conv64)(cols_conv_args(p, p->S1, p->filt, B), B, st));
+      m.in[c] = p->S2;
+    }
+    KRIG_TRY((is32(p0) ? set2(p0).c2r_mix_f32 : set2(p0).c2r_mix64)(m, B, st));
+    return KRIG_OK;
+  }
   MixArgs m{};
   m.lam = d_lam_grid;
   m.C = C;

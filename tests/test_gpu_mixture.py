@@ -42,18 +42,22 @@ def lam2(p):
     return np.sin(2.0 * p[..., 0]) ** 2 + 0.1
 
 
-def components(w):
-    """The workload's own kernel and a second, smoother and shorter-range one (L = 2)."""
-    w2 = dataclasses.replace(w, sigma2=0.5, rho=0.6 * w.rho, nu=2.5, L=2)
+def components(w, shared):
+    """The workload's own kernel and a second, smoother and shorter-range one: with the same
+    neighbour order L (one transform geometry: the fused path, the coefficient scaling in the
+    scatter and the weighted sum in one inverse-row pass) or with L + 1 (separate component
+    images and a combine pass)."""
+    w2 = dataclasses.replace(w, sigma2=0.5, rho=0.6 * w.rho, nu=2.5, L=w.L if shared else w.L + 1)
     return [(w, lam1), (w2, lam2)]
 
 
+@pytest.mark.parametrize("shared", [True, False], ids=["same-L", "different-L"])
 @pytest.mark.parametrize("dtype", ["f64", "f32"])
-def test_mixture_matches_oracle(krig, dtype):
+def test_mixture_matches_oracle(krig, dtype, shared):
     w = wl.small_field()
     g = Grid(w.m1, w.m2, w.x0, w.y0, w.dx, w.dy, w.L)
-    say("mixture of two components, small field", dtype)
-    comps = components(w)
+    say("mixture of two components, small field", dtype, "same L" if shared else "different L")
+    comps = components(w, shared)
     plans, ocomps, preds = [], [], []
     for wc, lam in comps:
         k = Matern(wc.sigma2, wc.rho, wc.nu, wc.tau2)
@@ -74,7 +78,7 @@ def test_mixture_matches_oracle(krig, dtype):
         ref = np.zeros((w.m1, w.m2))
         for (k, lam), rp in zip(ocomps, preds):
             ref += lam(nodes).reshape(w.m1, w.m2) * rp.predict_direct(lam(w.sites) * alpha[b]).reshape(w.m1, w.m2)
-        check(f"mixture field {b} {dtype}", relmax(got[b], ref), bar_for(dtype))
+        check(f"mixture field {b} {dtype} {'same' if shared else 'different'} L", relmax(got[b], ref), bar_for(dtype))
     again = host(krig.mixture(plans, dev(alpha), dev(lam_sites), dev(lam_grid)))
     assert np.array_equal(got, again)
 
