@@ -68,24 +68,24 @@ def stage_bytes(p, B, model="s8d"):
              saved spectrum of c* as a full F1 x H2 spectrum per field, and writes the summed
              lag-gradient spectrum once; the padded correlation image is FP32;
       "build" what this build's kernels must move: FP64 spectra between the passes (FP32 for the
-             upstream gradient's row spectra and the lag-gradient partials of FP32 plans), the
-             filter in FP64, the plan's dtype for caller arrays, an FP64 correlation image.
+             prediction's column-pass output in FP32 plans), the filter in FP64, the plan's dtype
+             for caller arrays, an FP64 correlation image.
     Per-group partial lag-gradient spectra are an implementation choice and count once."""
     m1, m2, n, M = p.m1, p.m2, p.n, p.M
     P1, P2, F1, H2 = p.P1, p.P2, p.F1, p.info("H2")
     if model == "s8d":
-        z = zg = zp = 8
+        z = zs = zg = zp = 8
         t, fb, img, ent = 4, 4, 4, 8
         adj_c = F1
     else:
         f32 = p.dtype_code == 1
-        z, zg, zp = 16, (8 if f32 else 16), (8 if f32 else 16)
+        z, zs, zg, zp = 16, (8 if f32 else 16), 16, 16
         t, fb, img, ent = (4 if f32 else 8), 8, 8, 12
         adj_c = P1
     return {
         "ROWS_FWD": B * (n * 8 + H2 * P1 * z) + n * M * ent + (P1 * P2 + 1) * 4,
-        "COLS_CONV": B * (H2 * P1 * z + H2 * m1 * z) + H2 * F1 * fb,
-        "ROWS_INV": B * (H2 * m1 * z + m1 * m2 * t),
+        "COLS_CONV": B * (H2 * P1 * z + H2 * m1 * zs) + H2 * F1 * fb,
+        "ROWS_INV": B * (H2 * m1 * zs + m1 * m2 * t),
         "ADJ_ROWS_FWD": B * (m1 * m2 * t + H2 * m1 * zg),
         "ADJ_COLS": B * (H2 * m1 * zg + H2 * P1 * z + H2 * adj_c * z) + H2 * F1 * fb + H2 * F1 * zp,
         "ADJ_ROWS_INV": B * (H2 * P1 * z + P1 * P2 * img),
@@ -389,7 +389,7 @@ def csim_bytes(p, R, model="s8d"):
     neighbourhoods (at most the padded grid), the weights and data, and writes the residuals; the
     prediction passes are those of stage_bytes with B = R, the last adding the field.  Model "s8d":
     FP32 spectra and fields (the survey's model); "build": the plan's dtype for the sampler and the
-    fields, FP64 spectra in the prediction passes."""
+    fields, the prediction passes' spectra as stage_bytes counts them."""
     P1, P2, n, M, m1, m2 = p.P1, p.P2, p.n, p.M, p.m1, p.m2
     Fs1, Fs2 = p.info("CE_F1"), p.info("CE_F2")
     npairs = (R + 1) // 2

@@ -153,27 +153,21 @@ typedef hipError_t (*launch_queue_t)(const QueueArgs&, int NL, int nblocks, hipS
 
 // Kernels for one transform length.  Arithmetic is FP64 in every role of the
 // prediction and its adjoint.  FP64 plans store FP64 spectra between the passes; FP32
-// plans store FP32 spectra where one rounding stays below the FP32 bounds (the column
-// pass's output of the prediction, the upstream gradient's row spectra, the lag-gradient
-// partials) and FP64 where it does not (the row spectra of c*, the adjoint's correlation
-// spectra; spec_bytes in plan.cpp).
+// plans store the column pass's output of the prediction in FP32 and every other spectrum
+// in FP64 (spec_bytes in plan.cpp gives the reasons).
 // Only the conditional-simulation sampler has an FP32-arithmetic form.
 struct FftSet {
   launch_rows_r2c_t r2c_csr;        // scatter + forward rows, FP64 -> FP64 spectra
   launch_rows_r2c_t r2c_csr_scaled; //   ... of alpha[b][i] * alpha_scale[i] (mixture components)
-  launch_rows_r2c_t r2c_dense_f32;  // FP32 rows (upstream gradient) -> FP32 spectra
+  launch_rows_r2c_t r2c_dense_f32;  // FP32 rows (upstream gradient) -> FP64 spectra
   launch_rows_r2c_t r2c_dense_f64;  // FP64 rows -> FP64 spectra
   launch_rows_r2c_t r2c_lag;        // even-reflected lag quadrant, FP64
   launch_cols_t conv64;             // all FP64
   launch_cols_t conv_pred_f;        // FP32 plans' prediction: FP64 row spectra in, FP32 out
-  launch_cols_t conv_adj_f;         // FP32 in -> FP64 out (adjoint correlation, FP32 plans)
-  launch_cols_t conv_dlag_f;        // the lag-gradient form of FP32 plans: FP32 G, FP64 saved
-                                    // spectra of c*, FP64 correlation, FP32 partials
   launch_cols_t conv_dlag64;        // all FP64, plus sum_b G_b conj(C_b) partial spectra (NL fields
                                     // of one column per block, one partial per block row)
   launch_cols_t fwd_real64;         // forward columns, store Re * scale (FP64)
   launch_cols_t inv_sum64;          // inverse columns of a sum of partial spectra (FP64)
-  launch_cols_t inv_sum_f;          //   ... of FP32 partials
   launch_rows_c2r_t c2r64;          // inverse rows, FP64
   launch_rows_c2r_t c2r_f32;        // inverse rows, FP32 spectra -> FP32 output (FP64 arithmetic)
   launch_rows_c2r_mix_t c2r_mix64;  // weighted sum of components' inverse rows, FP64

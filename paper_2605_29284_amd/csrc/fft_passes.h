@@ -838,11 +838,8 @@ FftEntry make_fft_entry() {
   k.c2r_f32 = launch_rows_c2r<double, float, float, R1, R2, R3>;
   k.c2r_mix64 = launch_rows_c2r_mix<double, double, double, R1, R2, R3>;
   k.c2r_mix_f32 = launch_rows_c2r_mix<double, float, float, R1, R2, R3>;
-  // FP32 plans' adjoint: FP64 arithmetic, FP32 spectra where their rounding stays harmless
-  k.r2c_dense_f32 = launch_rows_r2c<double, float, float, R1, R2, R3, SRC_DENSE>;
-  k.conv_adj_f = launch_cols<double, double, Stor<float, float, double, float>, R1, R2, R3, COL_CONV>;
-  k.conv_dlag_f = launch_cols<double, double, Stor<float, double, double, float>, R1, R2, R3, COL_CONV_DLAG>;
-  k.inv_sum_f = launch_cols<double, double, Stor<float, float, double, double>, R1, R2, R3, COL_INV_SUM>;
+  // FP32 plans' adjoint: the FP32 upstream gradient into FP64 spectra
+  k.r2c_dense_f32 = launch_rows_r2c<double, float, double, R1, R2, R3, SRC_DENSE>;
   k.c2r_fold32 = launch_rows_c2r_fold<double, float, R1, R2, R3>;
   k.c2r_fold64 = launch_rows_c2r_fold<double, double, R1, R2, R3>;
   k.r2c_cov = launch_rows_r2c<double, double, double, R1, R2, R3, SRC_COV>;

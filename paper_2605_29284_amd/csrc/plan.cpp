@@ -287,20 +287,22 @@ bool is32(krig_plan p) { return p->dtype == KRIG_F32; }
 size_t csz(krig_plan p) { return 2 * p->tsz; }
 
 // Bytes per complex value of each spectrum that passes between the transform kernels.
-// FP64 plans store FP64 throughout.  FP32 plans (FP64 arithmetic in every pass) store
-//  - the row spectra of the upstream gradient and the lag-gradient partial spectra in
-//    FP32 (8 bytes): one rounding there moves d y by ~1e-7 and d lag by ~1e-8 (relative
-//    max error);
-//  - the column pass's output of the prediction in FP32: one rounding moves y_hat by up to
-//    ~3e-6 on cancellation-heavy problems (sum |c*| / max |y_hat| ~ 1e5), ~1e-7 on the rest;
-//  - the row spectra of c* in FP64 (16 bytes): one FP32 rounding there moves y_hat by up to
-//    ~3e-5 on cancellation-heavy problems;
-//  - the adjoint's correlation spectra in FP64: d y applies (K + tau^2 I)^{-1} to them,
-//    and one FP32 rounding moves d y by ~1e-4.
+// FP64 plans store FP64 throughout.  FP32 plans (FP64 arithmetic in every pass) store the
+// column pass's output of the prediction in FP32 (8 bytes): one rounding there moves y_hat
+// by up to ~3e-6 on cancellation-heavy problems (sum |c*| / max |y_hat| ~ 1e5), ~1e-7 on the
+// rest, and halves that pass's writes and the inverse rows' reads.  Everything else stays
+// FP64:
+//  - the row spectra of c*: one FP32 rounding there moves y_hat by up to ~3e-5 on
+//    cancellation-heavy problems;
+//  - the adjoint's correlation spectra: d y applies (K + tau^2 I)^{-1} to them, and one FP32
+//    rounding moves d y by ~1e-4;
+//  - the upstream gradient's row spectra and the lag-gradient partials: FP32 storage there was
+//    harmless (~1e-7 in d y) but measured 1 us per step slower, since the conversions add to
+//    the lag-gradient column pass's FP64 arithmetic, which bounds it, while its bytes do not.
 enum SpecRole { SPEC_C, SPEC_PRED, SPEC_G, SPEC_CORR, SPEC_PART };
 size_t spec_bytes(krig_plan p, SpecRole role) {
   if (!is32(p)) return 16;
-  return (role == SPEC_PRED || role == SPEC_G || role == SPEC_PART) ? 8 : 16;
+  return role == SPEC_PRED ? 8 : 16;
 }
 
 // spectrum of the even-reflected lag quadrant (FP64), scaled by 1/(F1 F2)
@@ -1387,7 +1389,7 @@ int dlag_tail(krig_plan p, int ngroups, void* d_dlag, hipStream_t st) {
   ci.twF = p->tw1_64;
   ci.twI = p->tw1_64;
   ci.NL = p->nl_cols64;
-  KRIG_TRY((is32(p) ? set1(p).inv_sum_f : set1(p).inv_sum64)(ci, 1, st));
+  KRIG_TRY(set1(p).inv_sum64(ci, 1, st));
   RowsC2RArgs oc{};
   oc.nrows = p->n1l;
   oc.H2 = p->H2;
@@ -1487,11 +1489,11 @@ int krig_predict_adjoint(krig_plan p, int32_t B, const void* d_g, const double* 
     c.NL = std::max(1, std::min(p->dlag_G, (int)B));  // fields (lines) per block
     ngroups = (B + c.NL - 1) / c.NL;
     StageTimer t(p, KRIG_STAGE_ADJ_COLS);
-    KRIG_TRY((is32(p) ? set1(p).conv_dlag_f : set1(p).conv_dlag64)(c, ngroups, p->st));
+    KRIG_TRY(set1(p).conv_dlag64(c, ngroups, p->st));
   } else {
     c.NL = p->nl_cols64;
     StageTimer t(p, KRIG_STAGE_ADJ_COLS);
-    KRIG_TRY((is32(p) ? set1(p).conv_adj_f : set1(p).conv64)(c, B, p->st));
+    KRIG_TRY(set1(p).conv64(c, B, p->st));
   }
   // The lag-gradient tail does not depend on the gather and solve below (they read SA,
   // img, alpha and tmpv): with both outputs asked for, it runs on the plan's
