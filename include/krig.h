@@ -219,10 +219,11 @@ int krig_scatter(krig_plan p, int32_t B, const double *d_alpha, void *d_img);
  * d_saved: NULL, or a buffer of B * KRIG_INFO_SAVED_PER_FIELD complex FP64 values
  * that receives the row spectra of c* for krig_predict_adjoint.
  * Precision: every transform, the scatter and the filter product run in FP64
- * arithmetic with FP64 spectra between the passes, in both dtypes (the prediction is a
- * cancellation-heavy sum: one FP32 rounding of the row spectra of c* moves y_hat by up
- * to ~3e-5 when sum |c*| / max |y_hat| ~ 1e5); a KRIG_F32 plan reads d_lag and writes
- * d_yhat in FP32.
+ * arithmetic in both dtypes (the prediction is a cancellation-heavy sum: one FP32
+ * rounding of the row spectra of c* moves y_hat by up to ~3e-5 when
+ * sum |c*| / max |y_hat| ~ 1e5, so those stay FP64).  A KRIG_F32 plan stores the column
+ * pass's output spectra in FP32 (up to ~3e-6 relative on such problems, ~1e-7 on the
+ * rest), reads d_lag and writes d_yhat in FP32; a KRIG_F64 plan keeps FP64 throughout.
  */
 int krig_convolve(krig_plan p, int32_t B, const double *d_alpha, const void *d_lag, void *d_yhat,
                   void *d_saved);
@@ -244,11 +245,9 @@ int krig_predict(krig_plan p, int32_t B, const double *d_y, const void *d_lag, v
  *                               coefficients: d_saved from krig_predict, or
  *                               d_alpha [B][n] FP64 to recompute c*).
  * A and the coefficients are held fixed with respect to the lag.  The adjoint runs
- * in FP64 arithmetic for both dtypes.  A KRIG_F32 plan stores the row spectra of g
- * and the lag-gradient partial spectra in FP32 (about 1e-7 relative in dy, 1e-8 in
- * d lag); the correlation spectra and image stay FP64 (dy is (K + tau^2 I)^{-1}
- * applied to the gathered correlation, which amplifies any FP32 rounding of it by the
- * system's condition number).  d_g and d_dlag are in dt.
+ * in FP64 arithmetic with FP64 spectra and correlation image for both dtypes (dy is
+ * (K + tau^2 I)^{-1} applied to the gathered correlation, which amplifies any FP32
+ * rounding of it by the system's condition number).  d_g and d_dlag are in dt.
  * With both d_dy and d_dlag given (and stage timing off), the lag-gradient tail runs on a
  * second stream that the plan owns, forked from and joined back into the plan's stream
  * with events inside the call (also when that stream is being captured into a graph):
