@@ -375,19 +375,20 @@ hipError_t transpose_f64(const double* src, int64_t ld_src, double* dst, int64_t
 //   upper = 1:  out[b][i] = sum_{k >= i} T[i][k] in[b][k]      (T = L^{-T})
 // One workgroup of TRI_NW waves owns an output tile: 16 rows (row tile t) x 16 fields
 // (group z), over the tile's chunks of 16 columns inside the triangle.  Wave w takes chunks
-// w, w + TRI_NW, ... (the waves read neighbouring row segments together), TRI_KS chunks in
-// flight at a time.  Per chunk, lane (r = l%16, g = l/16) loads T[16t+r][16c + 4g .. +3] as
+// w, w + TRI_NW, ... (the waves read neighbouring row segments together), KS chunks in
+// flight at a time (six in a plain launch: 96 chunks per round trip covers n <= 1536 in one;
+// five in the persistent form, whose loop holds more registers).  KS does not change the
+// order in which a wave adds its chunks, so both forms give the same bits.  Per chunk, lane (r = l%16, g = l/16) loads T[16t+r][16c + 4g .. +3] as
 // one 32-byte vector (whole 128-byte row segments per wave) and in[16z+r][same k]; four MFMA
 // 16x16x4 steps take element s of each, so the K order inside a chunk is permuted identically
 // for both operands.  The waves' partial tiles are added through LDS in wave order: one launch
 // per product, no partials in device memory, bitwise repeatable results.
 // ------------------------------------------------------------------------------------
-constexpr int TRI_KS = 4;   // chunks in flight per wave
 constexpr int TRI_NW = 16;  // waves per tile
 
 // VEC: in_fs is a multiple of 4 and in 32-byte aligned, so a lane's four input values
 // are one 32-byte load (values past n are masked to zero).
-template <int UPPER, bool VEC>
+template <int UPPER, bool VEC, int KS>
 __device__ __forceinline__ void tri_tile_body(const double* __restrict__ T, int64_t ldt, int n,
                                               const double* __restrict__ in, int64_t in_fs, int B,
                                               double* __restrict__ out, int64_t out_fs, int t, int z,
@@ -400,11 +401,11 @@ __device__ __forceinline__ void tri_tile_body(const double* __restrict__ T, int6
   const double* trow = T + (int64_t)(rok ? i0 + r : 0) * ldt;
   const double* irow = in + (int64_t)(fok ? f0 + r : 0) * in_fs;
   double4_t acc = (double4_t){0.0, 0.0, 0.0, 0.0};
-  for (int cb = cbeg + w; cb < cend; cb += TRI_NW * TRI_KS) {
-    double4_t x[TRI_KS];
-    double a[TRI_KS][4];
+  for (int cb = cbeg + w; cb < cend; cb += TRI_NW * KS) {
+    double4_t x[KS];
+    double a[KS][4];
 #pragma unroll
-    for (int u = 0; u < TRI_KS; ++u) {
+    for (int u = 0; u < KS; ++u) {
       const int c = cb + u * TRI_NW;
       const int k = 16 * c + 4 * g;
       x[u] = (double4_t){0.0, 0.0, 0.0, 0.0};
@@ -420,7 +421,7 @@ __device__ __forceinline__ void tri_tile_body(const double* __restrict__ T, int6
       }
     }
 #pragma unroll
-    for (int u = 0; u < TRI_KS; ++u)
+    for (int u = 0; u < KS; ++u)
 #pragma unroll
       for (int s = 0; s < 4; ++s) acc = __builtin_amdgcn_mfma_f64_16x16x4f64(a[u][s], x[u][s], acc, 0, 0, 0);
   }
@@ -443,7 +444,7 @@ __global__ void __launch_bounds__(64 * TRI_NW) k_tri_tile(const double* __restri
                                                          const double* __restrict__ in, int64_t in_fs, int B,
                                                          double* __restrict__ out, int64_t out_fs) {
   __shared__ double red[TRI_NW][256];
-  tri_tile_body<UPPER, VEC>(T, ldt, n, in, in_fs, B, out, out_fs, blockIdx.x, blockIdx.y, red);
+  tri_tile_body<UPPER, VEC, 6>(T, ldt, n, in, in_fs, B, out, out_fs, blockIdx.x, blockIdx.y, red);
 }
 
 // Persistent form for an uneven batch: the tiles of several problems' products in one list
@@ -463,7 +464,7 @@ __global__ void __launch_bounds__(64 * TRI_NW) k_tri_tile_queue(TriQueue qa) {
     while (prob + 1 < qa.count && qa.first[prob + 1] <= tile) ++prob;
     const_as<TriProb>* p = (const_as<TriProb>*)(qa.probs) + prob;
     const int local = tile - qa.first[prob];
-    tri_tile_body<UPPER, VEC>(p->T, p->ldt, p->n, p->in, p->in_fs, p->B, p->out, p->out_fs, local % p->nt,
+    tri_tile_body<UPPER, VEC, 5>(p->T, p->ldt, p->n, p->in, p->in_fs, p->B, p->out, p->out_fs, local % p->nt,
                               local / p->nt, red);
     __syncthreads();  // red is reused by the next tile
   }
