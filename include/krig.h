@@ -97,7 +97,8 @@ enum {
   KRIG_INFO_FFT_VARIANT_ROWS,  /* form in use, 1-based (1: the default form) */
   KRIG_INFO_FFT_VARIANT_COLS,
   KRIG_INFO_SOLVE_NOALLOC_MAX_B, /* largest B krig_solve_noalloc accepts for this plan (0: none) */
-  KRIG_INFO_FILTER_SETUP         /* how the plan's filter spectrum was built (KRIG_FILTER_*) */
+  KRIG_INFO_FILTER_SETUP,        /* how the plan's filter spectrum was built (KRIG_FILTER_*) */
+  KRIG_INFO_COLS_PAIR            /* KRIG_TUNE_COLS_PAIR's current value (1: column form) */
 };
 
 /*
@@ -392,6 +393,12 @@ int krig_timing_read(krig_plan p, int32_t stage, double *total_ms, int64_t *laun
  *     transform length to use, 1-based (1: the default; count via
  *     KRIG_INFO_FFT_VARIANTS_*).  Resets that side's lines per block (and the field
  *     grouping, for columns) to the form's defaults.  Outputs change by rounding.
+ *   KRIG_TUNE_COLS_PAIR: 1 (default): the convolution column pass in the column form;
+ *     k + 1 (k = 1..4): the paired form with k columns per block, where the column length
+ *     F1 is twice a compiled length that runs on 64 threads (F1 = 768, 1024).  Each column
+ *     is then one wave: two half-length transforms (even and odd samples) and a radix-2
+ *     butterfly, with no block barrier.  KRIG_EINVAL where F1 has no paired form.  The
+ *     prediction and the correlation of the adjoint change by rounding.
  * Returns KRIG_EINVAL for an unknown key, a value outside those limits, or while a
  * recorded batch (krig_batch) holds the plan.
  */
@@ -400,7 +407,8 @@ typedef enum {
   KRIG_TUNE_NL_ROWS64,
   KRIG_TUNE_NL_COLS64,
   KRIG_TUNE_FFT_ROWS,
-  KRIG_TUNE_FFT_COLS
+  KRIG_TUNE_FFT_COLS,
+  KRIG_TUNE_COLS_PAIR
 } krig_tune_key;
 int krig_plan_tune(krig_plan p, int32_t key, int64_t value);
 

@@ -181,6 +181,11 @@ struct FftSet {
   launch_queue_t q_r2c_csr, q_conv64, q_c2r64, q_conv_pred_f, q_c2r_f32;
   launch_cols_t ce_cols32, ce_cols64;    // sampler pass 1 (noise x sqrt(Lambda), column transforms)
   launch_rows_ce_t ce_rows32, ce_rows64; // sampler pass 2 (row transforms -> two realisations)
+  // paired columns of twice this length (one wave per column, no block barriers), FP64 or
+  // FP32 output spectra; set only for three-pass lengths on exactly 64 threads
+  launch_cols_t pair_conv64 = nullptr, pair_conv_pred_f = nullptr;
+  launch_queue_t q_pair_conv64 = nullptr, q_pair_conv_pred_f = nullptr;
+  int pair_ex = 0;  // LDS slots per column of the paired kernels
 };
 
 __host__ __device__ constexpr int odd_up(int x) { return x | 1; }

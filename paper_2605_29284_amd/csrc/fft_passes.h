@@ -151,26 +151,41 @@ template <typename TC> struct TwB {
   cx<float> d1, d2, d3, d4;  // relative rounding of f1, f2, i3, i4b
 };
 
-// Threads outside a pass's range read entry 0, which is exactly 1 (d = 0).
-template <typename TC, int R1, int R2, int R3, bool INV>
+// Threads outside a pass's range read entry 0, which is exactly 1 (d = 0).  S > 1 reads
+// the powers of W_F from the table of length S F (entry S j = W_(S F)^(S j) = W_F^j).
+template <typename TC, int R1, int R2, int R3, bool INV, int S = 1>
 __device__ __forceinline__ TwB<TC> tw_bases(const cx<TC>* tw, int t) {
   using G = Geo<R1, R2, R3>;
-  const cx<float>* td = reinterpret_cast<const cx<float>*>(tw + G::F);
-  const int j1 = (G::THREE && t < G::TIN) ? t : 0;
-  const int j2 = t < G::T2 ? R1 * (t % R3) : 0;
-  const int j3 = (INV && t < G::TOUT) ? R1 * (t / R1) : 0;
-  const int j4 = (INV && G::THREE && t < G::T2) ? R3 * (t / R3) : 0;
+  const cx<float>* td = reinterpret_cast<const cx<float>*>(tw + S * G::F);
+  const int j1 = S * ((G::THREE && t < G::TIN) ? t : 0);
+  const int j2 = S * (t < G::T2 ? R1 * (t % R3) : 0);
+  const int j3 = S * ((INV && t < G::TOUT) ? R1 * (t / R1) : 0);
+  const int j4 = S * ((INV && G::THREE && t < G::T2) ? R3 * (t / R3) : 0);
   TwB<TC> b;
   b.f1 = tw[j1];
   b.f2 = tw[j2];
   b.i3 = tw[j3];
-  b.i4a = tw[(INV && G::THREE && t < G::T2) ? (t / R3) * (t % R3) : 0];
+  b.i4a = tw[S * ((INV && G::THREE && t < G::T2) ? (t / R3) * (t % R3) : 0)];
   b.i4b = tw[j4];
   b.d1 = td[j1];
   b.d2 = td[j2];
   b.d3 = td[j3];
   b.d4 = td[j4];
   return b;
+}
+
+// The lines of a block share its barrier (a line may span two waves); a line that is exactly
+// one wave (the paired column kernels) needs only its own LDS accesses ordered: a wave's LDS
+// operations execute in issue order, and the fences keep the compiler from moving them.
+template <bool WAVE>
+__device__ __forceinline__ void sync_lines() {
+  if constexpr (WAVE) {
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+    __builtin_amdgcn_wave_barrier();
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+  } else {
+    __syncthreads();
+  }
 }
 
 // p (1 + k d): removes the rounding d of k table-entry factors from the product p.
@@ -190,11 +205,11 @@ __device__ __forceinline__ cx<TC> tw_fix(cx<TC> p, cx<float> d, int k) {
 //  pass 3: thread (k1, s'), t = s' R1 + k1: DFT_R3 over s -> X[k1 + R1 s' + R1 R2 k2]
 //          = X[t + TOUT k2]
 // ----------------------------------------------------------------------------------------
-template <typename TC, int R1, int R2, int R3, int DIR>
+template <typename TC, int R1, int R2, int R3, int DIR, bool WAVE = false>
 __device__ __forceinline__ void xf_fwd(cx<TC> (&v)[(Geo<R1, R2, R3>::NIN)], cx<TC> (&w)[R3], int t, cx<TC>* L,
                                        const TwB<TC>& tb) {
   using G = Geo<R1, R2, R3>;
-  __syncthreads();
+  sync_lines<WAVE>();
   cx<TC> u[R2];
   if constexpr (G::THREE) {
     if (t < G::TIN) {
@@ -211,13 +226,13 @@ __device__ __forceinline__ void xf_fwd(cx<TC> (&v)[(Geo<R1, R2, R3>::NIN)], cx<T
         L[k1 * G::P1 + t] = a;
       }
     }
-    __syncthreads();
+    sync_lines<WAVE>();
     if (t < G::T2) {
       const int k1 = t / R3, s = t % R3;
 #pragma unroll
       for (int n1 = 0; n1 < R2; ++n1) u[n1] = L[k1 * G::P1 + R3 * n1 + s];
     }
-    __syncthreads();
+    sync_lines<WAVE>();
   } else {
 #pragma unroll
     for (int n1 = 0; n1 < R2; ++n1) u[n1] = v[n1];
@@ -238,7 +253,7 @@ __device__ __forceinline__ void xf_fwd(cx<TC> (&v)[(Geo<R1, R2, R3>::NIN)], cx<T
       Lk[s * G::ON2 + q] = a;
     }
   }
-  __syncthreads();
+  sync_lines<WAVE>();
   if (t < G::TOUT) {
     const int k1 = t % R1, sp = t / R1;
     const cx<TC>* Lk = L + k1 * G::RS;
@@ -251,11 +266,11 @@ __device__ __forceinline__ void xf_fwd(cx<TC> (&v)[(Geo<R1, R2, R3>::NIN)], cx<T
 // Inverse transform from the output layout (thread t < TOUT holds X[t + TOUT k2])
 // back to the input layout (thread t < TIN ends with x[t + TIN j] in v[j]): the
 // passes of xf_fwd in reverse with conjugate twiddles.
-template <typename TC, int R1, int R2, int R3>
+template <typename TC, int R1, int R2, int R3, bool WAVE = false>
 __device__ __forceinline__ void xf_inv(cx<TC> (&w)[R3], int t, cx<TC>* L, const TwB<TC>& tb,
                                        cx<TC> (&v)[(Geo<R1, R2, R3>::NIN)]) {
   using G = Geo<R1, R2, R3>;
-  __syncthreads();
+  sync_lines<WAVE>();
   if (t < G::TOUT) {
     const int k1 = t % R1, sp = t / R1;
     DFT<R3, 1, TC>::run(w);
@@ -272,7 +287,7 @@ __device__ __forceinline__ void xf_inv(cx<TC> (&w)[R3], int t, cx<TC>* L, const 
       Lk[n2 * G::ON2 + sp] = a;
     }
   }
-  __syncthreads();
+  sync_lines<WAVE>();
   cx<TC> u[R2];
   if (t < G::T2) {
     const int k1 = t / R3, n2 = t % R3;
@@ -280,7 +295,7 @@ __device__ __forceinline__ void xf_inv(cx<TC> (&w)[R3], int t, cx<TC>* L, const 
     for (int q = 0; q < R2; ++q) u[q] = L[k1 * G::RS + n2 * G::ON2 + q];
   }
   if constexpr (G::THREE) {
-    __syncthreads();
+    sync_lines<WAVE>();
     if (t < G::T2) {
       const int k1 = t / R3, n2 = t % R3;
       DFT<R2, 1, TC>::run(u);
@@ -293,7 +308,7 @@ __device__ __forceinline__ void xf_inv(cx<TC> (&w)[R3], int t, cx<TC>* L, const 
         L[k1 * G::P1 + m] = cmulc(u[n1], wm);
       }
     }
-    __syncthreads();
+    sync_lines<WAVE>();
     if (t < G::TIN) {
 #pragma unroll
       for (int k1 = 0; k1 < R1; ++k1) v[k1] = L[k1 * G::P1 + t];
@@ -362,6 +377,16 @@ k_cols(ColsArgs a) {
   int bx, by;
   logical_block<true>(bx, by);
 #include "fft_body_cols.inc"
+}
+
+// Paired column kernel: columns of length 2 F (F = R1 R2 R3 on at most 64 threads), one wave
+// per column, two half-length transforms and a radix-2 butterfly, no block barriers
+// (fft_body_cols_pair.inc).  The convolution form only.
+template <typename TF, typename TI, typename ST, int R1, int R2, int R3>
+__global__ void __launch_bounds__(256) k_cols_pair(ColsArgs a) {
+  int bx, by;
+  logical_block<true>(bx, by);
+#include "fft_body_cols_pair.inc"
 }
 
 // ----------------------------------------------------------------------------------------
@@ -556,6 +581,16 @@ k_cols_queue(QueueArgs q) {
   }
 }
 
+template <typename TF, typename TI, typename ST, int R1, int R2, int R3>
+__global__ void __launch_bounds__(256) k_cols_pair_queue(QueueArgs q) {
+  int prob = 0, bx, by, iter = 0;
+  const_as<ColsArgs>* ap;
+  while (next_tile(q, iter, prob, bx, by, ap)) {
+    const ColsArgs& a = *(const ColsArgs*)ap;
+#include "fft_body_cols_pair.inc"
+  }
+}
+
 template <typename TC, typename TS, typename TO, int R1, int R2, int R3>
 KRIG_QUEUE_ROW_KERNEL k_rows_c2r_queue(QueueArgs q) {
   int prob = 0, bx, by, iter = 0;
@@ -724,6 +759,17 @@ hipError_t launch_cols(const ColsArgs& a, int nblk_y, hipStream_t st) {
   return hipGetLastError();
 }
 
+// paired columns: NL columns (waves) per block, NL <= 4
+template <typename TF, typename TI, typename ST, int R1, int R2, int R3>
+hipError_t launch_cols_pair(const ColsArgs& a, int nblk_y, hipStream_t st) {
+  using G = Geo<R1, R2, R3>;
+  if (a.NL < 1 || a.NL > 4) return hipErrorInvalidValue;
+  dim3 grid((a.H2 + a.NL - 1) / a.NL, nblk_y);
+  const size_t sh = (size_t)a.NL * G::EX * sizeof(cx<TF>);
+  k_cols_pair<TF, TI, ST, R1, R2, R3><<<grid, dim3(64 * a.NL), sh, st>>>(a);
+  return hipGetLastError();
+}
+
 template <typename TC, typename TS, typename TO, int R1, int R2, int R3>
 hipError_t launch_rows_c2r(const RowsC2RArgs& a, int B, hipStream_t st) {
   using G = Geo<R1, R2, R3>;
@@ -806,6 +852,17 @@ hipError_t launch_cols_queue(const QueueArgs& q, int NL, int nblocks, hipStream_
   return hipGetLastError();
 }
 
+template <typename TF, typename TI, typename ST, int R1, int R2, int R3>
+hipError_t launch_cols_pair_queue(const QueueArgs& q, int NL, int nblocks, hipStream_t st) {
+  using G = Geo<R1, R2, R3>;
+  if (NL < 1 || NL > 4) return hipErrorInvalidValue;
+  const int threads = 64 * NL;
+  const size_t sh = (size_t)NL * G::EX * sizeof(cx<TF>);
+  if (nblocks <= 0) nblocks = queue_grid(nblocks, k_cols_pair_queue<TF, TI, ST, R1, R2, R3>, threads, sh);
+  k_cols_pair_queue<TF, TI, ST, R1, R2, R3><<<nblocks, threads, sh, st>>>(q);
+  return hipGetLastError();
+}
+
 template <typename TC, typename TS, typename TO, int R1, int R2, int R3>
 hipError_t launch_rows_c2r_queue(const QueueArgs& q, int NL, int nblocks, hipStream_t st) {
   using G = Geo<R1, R2, R3>;
@@ -854,6 +911,16 @@ FftEntry make_fft_entry() {
   k.ce_cols64 = launch_cols<double, double, S64, R1, R2, R3, COL_CE>;
   k.ce_rows32 = launch_rows_ce<float, float, float, R1, R2, R3>;
   k.ce_rows64 = launch_rows_ce<double, double, double, R1, R2, R3>;
+  // columns of twice this length, one wave per column (three-pass lengths on exactly 64 threads)
+  if constexpr (Geo<R1, R2, R3>::THREE && Geo<R1, R2, R3>::NT == 64) {
+    using S64P = Stor<double, double, double, double>;
+    using S32P = Stor<double, double, float, double>;
+    k.pair_conv64 = launch_cols_pair<double, double, S64P, R1, R2, R3>;
+    k.pair_conv_pred_f = launch_cols_pair<double, double, S32P, R1, R2, R3>;
+    k.q_pair_conv64 = launch_cols_pair_queue<double, double, S64P, R1, R2, R3>;
+    k.q_pair_conv_pred_f = launch_cols_pair_queue<double, double, S32P, R1, R2, R3>;
+    k.pair_ex = Geo<R1, R2, R3>::EX;
+  }
   return e;
 }
 

@@ -48,6 +48,8 @@ struct krig_plan_s {
   int ldX = 0;  // ... with 2 (m1 + L) - 1 rows
   int n1l = 0, n2l = 0;
   const FftEntry* e1 = nullptr;  // columns (length F1)
+  const FftEntry* e1h = nullptr; // the length F1 / 2 whose paired column kernels serve F1, if any
+  int cols_pair = 0;             // 0: the column passes' own form; k >= 1: paired, k columns per block
   const FftEntry* e2 = nullptr;  // rows (length F2)
   int var_cols = 0, var_rows = 0;  // which compiled form of F1 / F2 (0: the default)
   // twiddles exp(-2 pi i j / F)
@@ -283,6 +285,14 @@ int make_twiddles(krig_plan p, int F, double** d64, float** d32) {
 
 const FftSet& set1(krig_plan p) { return p->e1->k; }
 const FftSet& set2(krig_plan p) { return p->e2->k; }
+
+// The convolution column pass (forward, filter product, inverse; FP32 output spectra for the
+// prediction of FP32 plans when f32out): the column form of e1, or the paired form of e1h.
+launch_cols_t conv_cols_fn(krig_plan p, bool f32out) {
+  if (p->cols_pair) return f32out ? p->e1h->k.pair_conv_pred_f : p->e1h->k.pair_conv64;
+  return f32out ? set1(p).conv_pred_f : set1(p).conv64;
+}
+int conv_cols_nl(krig_plan p) { return p->cols_pair ? p->cols_pair : p->nl_cols64; }
 bool is32(krig_plan p) { return p->dtype == KRIG_F32; }
 size_t csz(krig_plan p) { return 2 * p->tsz; }
 
@@ -579,7 +589,7 @@ ColsArgs cols_conv_args(krig_plan p, const void* spec1, const double* filt, int 
   c.twF = p->tw1_64;  // FP64 column transforms for both dtypes
   c.twI = p->tw1_64;
   c.B = B;
-  c.NL = p->nl_cols64;
+  c.NL = conv_cols_nl(p);
   return c;
 }
 
@@ -607,7 +617,7 @@ int do_convolve(krig_plan p, int B, const double* alpha, const double* filt, voi
   }
   {
     StageTimer t(p, KRIG_STAGE_COLS_CONV);
-    KRIG_TRY((is32(p) ? set1(p).conv_pred_f : set1(p).conv64)(cols_conv_args(p, spec1, filt, B), B, p->st));
+    KRIG_TRY(conv_cols_fn(p, is32(p))(cols_conv_args(p, spec1, filt, B), B, p->st));
   }
   RowsC2RArgs o = rows_inv_args(p, yhat);
   o.add = add;
@@ -796,7 +806,7 @@ struct TuneKey {
   }
 };
 struct TuneRec {
-  int var_rows, var_cols, nl_rows64, nl_cols64, dlag_G;
+  int var_rows, var_cols, nl_rows64, nl_cols64, dlag_G, cols_pair;
 };
 std::mutex& tune_mutex() {
   static std::mutex m;
@@ -820,6 +830,7 @@ void tuned_lookup(krig_plan p) {
   p->nl_rows64 = r.nl_rows64;
   p->nl_cols64 = r.nl_cols64;
   p->dlag_G = r.dlag_G;
+  p->cols_pair = p->e1h ? r.cols_pair : 0;
 }
 
 }  // namespace
@@ -843,7 +854,7 @@ namespace {
 // the pass's (problem, tile) list.
 struct QueueLaunch {
   int kind;                  // 0 triangular product, 2 rows forward, 3 columns, 4 inverse rows
-  int upper = 0, vec = 0, f32 = 0, NL = 1;
+  int upper = 0, vec = 0, f32 = 0, pair = 0, NL = 1;
   const FftEntry* e = nullptr;
   size_t args_off = 0, first_off = 0, nbx_off = 0;
   int count = 0, total = 0;
@@ -916,9 +927,11 @@ size_t queue_problems(QueuePlan& qp, const std::vector<int>& ids, const krig_pla
     rf_t[p->e2].push_back(nbr * B);
     rf_n[p->e2].push_back(nbr);
     ColsArgs c = cols_conv_args(p, p->S1, p->filt, B);
-    c.NL = nlc;
-    const int nbc = (p->H2 + nlc - 1) / nlc;
-    const auto ckey = std::make_pair(p->e1, (int)is32(p));
+    const int nlq = p->cols_pair ? p->cols_pair : nlc;
+    c.NL = nlq;
+    const int nbc = (p->H2 + nlq - 1) / nlq;
+    // the paired form is keyed by its half-length entry and flagged in the second member
+    const auto ckey = std::make_pair(p->cols_pair ? p->e1h : p->e1, (int)is32(p) + (p->cols_pair ? 2 : 0));
     cf[ckey].push_back(c);
     cf_t[ckey].push_back(nbc * B);
     cf_n[ckey].push_back(nbc);
@@ -939,7 +952,8 @@ size_t queue_problems(QueuePlan& qp, const std::vector<int>& ids, const krig_pla
   for (auto& g : cf) {
     QueueLaunch ql;
     ql.e = g.first.first;
-    ql.f32 = g.first.second;
+    ql.f32 = g.first.second & 1;
+    ql.pair = g.first.second >> 1;
     ql.NL = g.second[0].NL;
     qp.add(3, g.second, cf_t[g.first], cf_n[g.first], ql);
   }
@@ -963,7 +977,8 @@ int queue_launch(const QueueLaunch& ql, unsigned char* base, int nblocks, hipStr
   QueueArgs qa{base + ql.args_off, first, reinterpret_cast<const int*>(base + ql.nbx_off), ql.count, ql.total};
   const FftSet& k = ql.e->k;
   const launch_queue_t fn = ql.kind == 2   ? k.q_r2c_csr
-                            : ql.kind == 3 ? (ql.f32 ? k.q_conv_pred_f : k.q_conv64)
+                            : ql.kind == 3 ? (ql.pair ? (ql.f32 ? k.q_pair_conv_pred_f : k.q_pair_conv64)
+                                                      : (ql.f32 ? k.q_conv_pred_f : k.q_conv64))
                                            : (ql.f32 ? k.q_c2r_f32 : k.q_c2r64);
   return hip_status(fn(qa, ql.NL, nblocks, st));
 }
@@ -1066,6 +1081,10 @@ int krig_plan_create(krig_plan* out, const krig_grid* g, const krig_matern* k, i
   }
   p->e1 = find_fft(p->F1);
   p->e2 = find_fft(p->F2);
+  if (p->F1 % 2 == 0) {  // the paired column form: half the length on one wave per column
+    const FftEntry* h = find_fft(p->F1 / 2);
+    if (h && h->F == p->F1 / 2 && h->k.pair_conv64) p->e1h = h;
+  }
   p->H2 = p->F2 / 2 + 1;
   p->ldP = pitch16(p->P1);
   p->ldM = pitch16(g->m1);
@@ -1205,6 +1224,7 @@ int krig_plan_info(krig_plan p, int32_t what, int64_t* v) {
     case KRIG_INFO_FFT_VARIANTS_COLS: *v = fft_variants(p->F1, nullptr, 0); break;
     case KRIG_INFO_FFT_VARIANT_ROWS: *v = p->var_rows + 1; break;
     case KRIG_INFO_FFT_VARIANT_COLS: *v = p->var_cols + 1; break;
+    case KRIG_INFO_COLS_PAIR: *v = p->cols_pair + 1; break;
     case KRIG_INFO_FFT_R1: *v = p->e2->geo.R1; break;
     case KRIG_INFO_FFT_R2: *v = p->e2->geo.R2; break;
     case KRIG_INFO_FFT_R3: *v = p->e2->geo.R3; break;
@@ -1491,9 +1511,9 @@ int krig_predict_adjoint(krig_plan p, int32_t B, const void* d_g, const double* 
     StageTimer t(p, KRIG_STAGE_ADJ_COLS);
     KRIG_TRY(set1(p).conv_dlag64(c, ngroups, p->st));
   } else {
-    c.NL = p->nl_cols64;
+    c.NL = conv_cols_nl(p);
     StageTimer t(p, KRIG_STAGE_ADJ_COLS);
-    KRIG_TRY(set1(p).conv64(c, B, p->st));
+    KRIG_TRY(conv_cols_fn(p, false)(c, B, p->st));
   }
   // The lag-gradient tail does not depend on the gather and solve below (they read SA,
   // img, alpha and tmpv): with both outputs asked for, it runs on the plan's
@@ -1648,6 +1668,14 @@ int krig_plan_tune(krig_plan p, int32_t key, int64_t value) {
       return KRIG_OK;
     case KRIG_TUNE_FFT_ROWS:
     case KRIG_TUNE_FFT_COLS: return set_variant(p, key == KRIG_TUNE_FFT_ROWS, (int)value - 1);
+    case KRIG_TUNE_COLS_PAIR:
+      if (v == 1) {
+        p->cols_pair = 0;
+        return KRIG_OK;
+      }
+      if (!p->e1h || v - 1 > 4 || (size_t)(v - 1) * p->e1h->k.pair_ex * 16 > 64 * 1024) return KRIG_EINVAL;
+      p->cols_pair = v - 1;
+      return KRIG_OK;
     default: return KRIG_EINVAL;
   }
 }
@@ -1707,13 +1735,15 @@ int krig_plan_autotune(krig_plan p, int32_t B, int32_t with_adjoint) {
       case KRIG_TUNE_FFT_COLS: return p->var_cols + 1;
       case KRIG_TUNE_NL_ROWS64: return p->nl_rows64;
       case KRIG_TUNE_NL_COLS64: return p->nl_cols64;
+      case KRIG_TUNE_COLS_PAIR: return p->cols_pair + 1;
       default: return p->dlag_G;
     }
   };
   const int keys[] = {KRIG_TUNE_FFT_ROWS, KRIG_TUNE_FFT_COLS, KRIG_TUNE_NL_ROWS64, KRIG_TUNE_NL_COLS64,
-                      KRIG_TUNE_DLAG_GROUP};
+                      KRIG_TUNE_COLS_PAIR, KRIG_TUNE_DLAG_GROUP};
   for (int key : keys) {
     if (key == KRIG_TUNE_DLAG_GROUP && !with_adjoint) continue;
+    if (key == KRIG_TUNE_COLS_PAIR && !p->e1h) continue;
     std::vector<int> cand;
     if (key == KRIG_TUNE_FFT_ROWS || key == KRIG_TUNE_FFT_COLS) {
       const int k = fft_variants(key == KRIG_TUNE_FFT_ROWS ? p->F2 : p->F1, nullptr, 0);
@@ -1763,7 +1793,7 @@ int krig_plan_autotune(krig_plan p, int32_t B, int32_t with_adjoint) {
   cleanup();
   {
     std::lock_guard<std::mutex> lk(tune_mutex());
-    tune_table()[tune_key(p)] = TuneRec{p->var_rows, p->var_cols, p->nl_rows64, p->nl_cols64, p->dlag_G};
+    tune_table()[tune_key(p)] = TuneRec{p->var_rows, p->var_cols, p->nl_rows64, p->nl_cols64, p->dlag_G, p->cols_pair};
   }
   return KRIG_OK;
 }
@@ -1914,7 +1944,7 @@ int krig_mixture(const krig_plan* plans, int32_t C, int32_t B, const double* d_a
       RowsR2CArgs ra = rows_fwd_args(p, d_alpha, p->S1);
       ra.alpha_scale = d_lam_sites + (size_t)c * n;
       KRIG_TRY(set2(p).r2c_csr_scaled(ra, B, st));
-      KRIG_TRY((is32(p) ? set1(p).conv_pred_f : set1(p).conv64)(cols_conv_args(p, p->S1, p->filt, B), B, st));
+      KRIG_TRY(conv_cols_fn(p, is32(p))(cols_conv_args(p, p->S1, p->filt, B), B, st));
       m.in[c] = p->S2;
     }
     KRIG_TRY((is32(p0) ? set2(p0).c2r_mix_f32 : set2(p0).c2r_mix64)(m, B, st));

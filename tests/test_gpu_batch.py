@@ -186,6 +186,35 @@ def test_batch_persistent_replays(krig, problems):
     assert e.value.status == -1
 
 
+def test_batch_persistent_paired_columns(krig):
+    """Plans on the paired column form (F1 = 768 and 1024) in the persistent form reproduce
+    their own krig_predict bit for bit (the queue walks the paired kernel's columns)."""
+    ws = [wl.grad_batch(B=2), wl.tiny(seed=21, m1=450, m2=40, L=3, n=300, B=3, nu=1.5, rho=0.2, tau2=0.05)]
+    plans, ys, outs = [], [], []
+    for w, v in zip(ws, (3, 5)):
+        p = krig.plan_for(w, "f64")
+        p.tune("COLS_PAIR", v)
+        plans.append(p)
+        ys.append(dev(w.y))
+        outs.append(p.empty(w.y.shape[0], w.m1, w.m2))
+    say("batch persistent form, paired columns", [p.F1 for p in plans])
+    ref = reference([dict(p=p, y=y) for p, y in zip(plans, ys)])
+    bt = krig.Batch(plans, ys, outs, lanes=0)
+    try:
+        for rep in range(2):
+            for o in outs:
+                o.fill_(float("nan"))
+            torch.cuda.synchronize()
+            bt.launch()
+            torch.cuda.synchronize()
+            for i, (o, r) in enumerate(zip(outs, ref)):
+                assert np.array_equal(host(o), r), (rep, i)
+    finally:
+        bt.close()
+        for p in plans:
+            p.close()
+
+
 def test_batch_guards(krig, problems):
     """While a batch exists its plans refuse destruction and workspace growth."""
     say("batch guards")

@@ -616,6 +616,52 @@ def test_fft_variants_match_oracle(krig, paper):
         p.tune(side, 1)
 
 
+@pytest.mark.parametrize("dtype", ["f64", "f32"])
+def test_paired_columns_match_oracle(krig, paper, dtype):
+    """The paired column form (KRIG_TUNE_COLS_PAIR: a column of length F1 = 2H is one wave, two
+    length-H transforms and a radix-2 butterfly) against the oracle's FFT form of eq.
+    Convolution, oracle weights and coefficients injected, at F1 = 768 (the paper field) and
+    F1 = 1024 (a 450 x 40 grid, L = 3); every block width gives the same bits, and the
+    adjoint's dy-only correlation (the same pass) stays within rounding of the column form."""
+    w0, (g0, k0, rp0, ek0) = paper
+    w1 = wl.tiny(seed=21, m1=450, m2=40, L=3, n=300, B=1, nu=1.5, rho=0.2, tau2=0.05)
+    cases = [(w0, g0, k0, rp0, ek0)]
+    g1 = Grid(w1.m1, w1.m2, w1.x0, w1.y0, w1.dx, w1.dy, w1.L)
+    k1 = Matern(w1.sigma2, w1.rho, w1.nu, w1.tau2)
+    cases.append((w1, g1, k1, RapidPredictor(g1, k1, w1.sites), ExactKriging(w1.sites, k1)))
+    for w, g, k, rp, ek in cases:
+        p = krig.plan_for(w, dtype)
+        assert p.F1 in (768, 1024), p.F1
+        say("paired columns", p.F1, dtype)
+        p.set_weights(dev(np.stack([rp.i0, rp.j0], 1), torch.int32), dev(rp.W))
+        alpha = ek.coef(w.y)
+        cimg = rp.cstar(alpha[0])
+        ref = rapid_fft(g, lag_quadrant(g, k), cimg)
+        cancel = np.abs(cimg).sum() / np.abs(ref).max()
+        gup = dev(np.random.default_rng(5).standard_normal((1, w.m1, w.m2)), p.tdtype)
+        base_dy = host(p.adjoint(gup, alpha=dev(alpha), want_dlag=False)[0])
+        outs = []
+        for v in (2, 3, 4, 5):  # 1 .. 4 columns per block
+            p.tune("COLS_PAIR", v)
+            assert p.info("COLS_PAIR") == v
+            outs.append(host(p.convolve(dev(alpha)))[0])
+            dy = host(p.adjoint(gup, alpha=dev(alpha), want_dlag=False)[0])
+            # dy carries the transforms' rounding times cond(K + tau^2 I)
+            assert relmax(dy, base_dy) < (1e-10 if dtype == "f64" else 1e-6), (p.F1, v)
+        for o in outs[1:]:
+            assert np.array_equal(o, outs[0]), p.F1
+        label = f"paired columns F1={p.F1}"
+        check(f"{label} {dtype}", relmax(outs[0], ref), bar_for(dtype, label), f"cancellation {cancel:.3g}")
+        p.tune("COLS_PAIR", 1)
+        assert p.info("COLS_PAIR") == 1
+        for v in (0, 6):
+            with pytest.raises(krig.KrigError):
+                p.tune("COLS_PAIR", v)
+    q = krig.plan_for(wl.small_field(), dtype)  # F1 = 144: no paired form
+    with pytest.raises(krig.KrigError):
+        q.tune("COLS_PAIR", 2)
+
+
 def test_autotune(krig, small):
     """The autotuner keeps results within the plan's tolerance and later plans of the
     same shape start from its choice."""
