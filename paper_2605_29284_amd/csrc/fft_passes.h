@@ -153,25 +153,49 @@ template <typename TC> struct TwB {
 
 // Threads outside a pass's range read entry 0, which is exactly 1 (d = 0).  S > 1 reads
 // the powers of W_F from the table of length S F (entry S j = W_(S F)^(S j) = W_F^j).
+// t2: the thread's index in the middle pass (t itself, or its remapped index: see xf_fwd).
 template <typename TC, int R1, int R2, int R3, bool INV, int S = 1>
-__device__ __forceinline__ TwB<TC> tw_bases(const cx<TC>* tw, int t) {
+__device__ __forceinline__ TwB<TC> tw_bases(const cx<TC>* tw, int t, int t2) {
   using G = Geo<R1, R2, R3>;
   const cx<float>* td = reinterpret_cast<const cx<float>*>(tw + S * G::F);
   const int j1 = S * ((G::THREE && t < G::TIN) ? t : 0);
-  const int j2 = S * (t < G::T2 ? R1 * (t % R3) : 0);
+  const int j2 = S * (t2 < G::T2 ? R1 * (t2 % R3) : 0);
   const int j3 = S * ((INV && t < G::TOUT) ? R1 * (t / R1) : 0);
-  const int j4 = S * ((INV && G::THREE && t < G::T2) ? R3 * (t / R3) : 0);
+  const int j4 = S * ((INV && G::THREE && t2 < G::T2) ? R3 * (t2 / R3) : 0);
   TwB<TC> b;
   b.f1 = tw[j1];
   b.f2 = tw[j2];
   b.i3 = tw[j3];
-  b.i4a = tw[S * ((INV && G::THREE && t < G::T2) ? (t / R3) * (t % R3) : 0)];
+  b.i4a = tw[S * ((INV && G::THREE && t2 < G::T2) ? (t2 / R3) * (t2 % R3) : 0)];
   b.i4b = tw[j4];
   b.d1 = td[j1];
   b.d2 = td[j2];
   b.d3 = td[j3];
   b.d4 = td[j4];
   return b;
+}
+template <typename TC, int R1, int R2, int R3, bool INV, int S = 1>
+__device__ __forceinline__ TwB<TC> tw_bases(const cx<TC>* tw, int t) {
+  return tw_bases<TC, R1, R2, R3, INV, S>(tw, t, t);
+}
+
+// The middle pass of a three-pass transform runs on T2 of a line's NT threads and only
+// exchanges through LDS between block barriers, so any thread of the block may do it for any
+// line.  Remapped, block thread T works on line T / T2 as its thread T mod T2: the busy
+// threads fill whole waves and the rest (NL (NT - T2) threads, e.g. one wave of three at
+// length 768 = 8 x 12 x 8 with two lines) skip the pass instead of issuing it half masked.
+// Returns the line for the middle pass (NL or more: none); t2 receives the index.
+template <int R1, int R2, int R3>
+__device__ __forceinline__ int mid_line(int T, int NL, int& t2) {
+  using G = Geo<R1, R2, R3>;
+  if constexpr (G::THREE) {
+    const int l2 = T / G::T2;
+    t2 = l2 < NL ? T % G::T2 : G::T2;
+    return l2;
+  } else {
+    t2 = T % G::NT;  // two-stage forms take their middle input from registers: no remap
+    return T / G::NT;
+  }
 }
 
 // The lines of a block share its barrier (a line may span two waves); a line that is exactly
@@ -205,9 +229,11 @@ __device__ __forceinline__ cx<TC> tw_fix(cx<TC> p, cx<float> d, int k) {
 //  pass 3: thread (k1, s'), t = s' R1 + k1: DFT_R3 over s -> X[k1 + R1 s' + R1 R2 k2]
 //          = X[t + TOUT k2]
 // ----------------------------------------------------------------------------------------
+// t2, L2: the thread's middle-pass index and the LDS slots of the line it does that pass for
+// (mid_line), or t and L.
 template <typename TC, int R1, int R2, int R3, int DIR, bool WAVE = false>
 __device__ __forceinline__ void xf_fwd(cx<TC> (&v)[(Geo<R1, R2, R3>::NIN)], cx<TC> (&w)[R3], int t, cx<TC>* L,
-                                       const TwB<TC>& tb) {
+                                       const TwB<TC>& tb, int t2, cx<TC>* L2) {
   using G = Geo<R1, R2, R3>;
   sync_lines<WAVE>();
   cx<TC> u[R2];
@@ -227,20 +253,20 @@ __device__ __forceinline__ void xf_fwd(cx<TC> (&v)[(Geo<R1, R2, R3>::NIN)], cx<T
       }
     }
     sync_lines<WAVE>();
-    if (t < G::T2) {
-      const int k1 = t / R3, s = t % R3;
+    if (t2 < G::T2) {
+      const int k1 = t2 / R3, s = t2 % R3;
 #pragma unroll
-      for (int n1 = 0; n1 < R2; ++n1) u[n1] = L[k1 * G::P1 + R3 * n1 + s];
+      for (int n1 = 0; n1 < R2; ++n1) u[n1] = L2[k1 * G::P1 + R3 * n1 + s];
     }
     sync_lines<WAVE>();
   } else {
 #pragma unroll
     for (int n1 = 0; n1 < R2; ++n1) u[n1] = v[n1];
   }
-  if (t < G::T2) {
-    const int k1 = t / R3, s = t % R3;
+  if (t2 < G::T2) {
+    const int k1 = t2 / R3, s = t2 % R3;
     DFT<R2, DIR, TC>::run(u);
-    cx<TC>* Lk = L + k1 * G::RS;
+    cx<TC>* Lk = L2 + k1 * G::RS;
     cx<TC> wq = tb.f2;  // W^(R1 s q)
 #pragma unroll
     for (int q = 0; q < R2; ++q) {
@@ -263,12 +289,18 @@ __device__ __forceinline__ void xf_fwd(cx<TC> (&v)[(Geo<R1, R2, R3>::NIN)], cx<T
   }
 }
 
+template <typename TC, int R1, int R2, int R3, int DIR, bool WAVE = false>
+__device__ __forceinline__ void xf_fwd(cx<TC> (&v)[(Geo<R1, R2, R3>::NIN)], cx<TC> (&w)[R3], int t, cx<TC>* L,
+                                       const TwB<TC>& tb) {
+  xf_fwd<TC, R1, R2, R3, DIR, WAVE>(v, w, t, L, tb, t, L);
+}
+
 // Inverse transform from the output layout (thread t < TOUT holds X[t + TOUT k2])
 // back to the input layout (thread t < TIN ends with x[t + TIN j] in v[j]): the
 // passes of xf_fwd in reverse with conjugate twiddles.
 template <typename TC, int R1, int R2, int R3, bool WAVE = false>
 __device__ __forceinline__ void xf_inv(cx<TC> (&w)[R3], int t, cx<TC>* L, const TwB<TC>& tb,
-                                       cx<TC> (&v)[(Geo<R1, R2, R3>::NIN)]) {
+                                       cx<TC> (&v)[(Geo<R1, R2, R3>::NIN)], int t2, cx<TC>* L2) {
   using G = Geo<R1, R2, R3>;
   sync_lines<WAVE>();
   if (t < G::TOUT) {
@@ -289,15 +321,17 @@ __device__ __forceinline__ void xf_inv(cx<TC> (&w)[R3], int t, cx<TC>* L, const 
   }
   sync_lines<WAVE>();
   cx<TC> u[R2];
-  if (t < G::T2) {
-    const int k1 = t / R3, n2 = t % R3;
+  // the middle pass reads (and, three-pass, writes) the remapped line; a two-stage form
+  // keeps its values in the thread's own registers (t2 = t there)
+  if (t2 < G::T2) {
+    const int k1 = t2 / R3, n2 = t2 % R3;
 #pragma unroll
-    for (int q = 0; q < R2; ++q) u[q] = L[k1 * G::RS + n2 * G::ON2 + q];
+    for (int q = 0; q < R2; ++q) u[q] = L2[k1 * G::RS + n2 * G::ON2 + q];
   }
   if constexpr (G::THREE) {
     sync_lines<WAVE>();
-    if (t < G::T2) {
-      const int k1 = t / R3, n2 = t % R3;
+    if (t2 < G::T2) {
+      const int k1 = t2 / R3, n2 = t2 % R3;
       DFT<R2, 1, TC>::run(u);
       cx<TC> wm = tb.i4a;  // W^(m k1), m = R3 n1 + n2
 #pragma unroll
@@ -305,7 +339,7 @@ __device__ __forceinline__ void xf_inv(cx<TC> (&w)[R3], int t, cx<TC>* L, const 
         const int m = R3 * n1 + n2;
         if (n1 > 0) wm = cmul(wm, tb.i4b);
         if (n1 > 0 && n1 % 4 == 0) wm = tw_fix(wm, tb.d4, 4);
-        L[k1 * G::P1 + m] = cmulc(u[n1], wm);
+        L2[k1 * G::P1 + m] = cmulc(u[n1], wm);
       }
     }
     sync_lines<WAVE>();
@@ -315,12 +349,18 @@ __device__ __forceinline__ void xf_inv(cx<TC> (&w)[R3], int t, cx<TC>* L, const 
       DFT<R1, 1, TC>::run(v);
     }
   } else {
-    if (t < G::T2) {
+    if (t2 < G::T2) {
       DFT<R2, 1, TC>::run(u);
 #pragma unroll
       for (int n1 = 0; n1 < R2; ++n1) v[n1] = u[n1];
     }
   }
+}
+
+template <typename TC, int R1, int R2, int R3, bool WAVE = false>
+__device__ __forceinline__ void xf_inv(cx<TC> (&w)[R3], int t, cx<TC>* L, const TwB<TC>& tb,
+                                       cx<TC> (&v)[(Geo<R1, R2, R3>::NIN)]) {
+  xf_inv<TC, R1, R2, R3, WAVE>(w, t, L, tb, v, t, L);
 }
 
 // ----------------------------------------------------------------------------------------
@@ -346,7 +386,7 @@ KRIG_ROW_KERNEL k_rows_r2c(RowsR2CArgs a) {
 // ----------------------------------------------------------------------------------------
 template <typename TC, typename TS, int R1, int R2, int R3>
 __device__ __forceinline__ void col_fwd(const Spec<TS> src, int in_off, int in_cnt, bool colok, int s,
-                                        cx<TC>* L, const TwB<TC>& tb, cx<TC> (&w)[R3]) {
+                                        cx<TC>* L, const TwB<TC>& tb, cx<TC> (&w)[R3], int t2, cx<TC>* L2) {
   using G = Geo<R1, R2, R3>;
   cx<TC> v[G::NIN];
   if (s < G::TIN) {
@@ -356,7 +396,7 @@ __device__ __forceinline__ void col_fwd(const Spec<TS> src, int in_off, int in_c
       v[j] = (colok && r >= 0 && r < in_cnt) ? src.template ld<TC>(r) : mk<TC>(0, 0);
     }
   }
-  xf_fwd<TC, R1, R2, R3, -1>(v, w, s, L, tb);
+  xf_fwd<TC, R1, R2, R3, -1>(v, w, s, L, tb, t2, L2);
 }
 
 enum { COL_CONV = 0, COL_CONV_DLAG = 1, COL_FWD_REAL = 2, COL_INV_SUM = 3, COL_CE = 4 };
