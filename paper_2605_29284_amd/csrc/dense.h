@@ -40,8 +40,12 @@ hipError_t transpose_f64(const double* src, int64_t ld_src, double* dst, int64_t
 hipError_t tri_apply(const double* T, int64_t ldt, int n, int upper, const double* in, int64_t in_fs, double* out,
                      int64_t out_fs, int B, hipStream_t st);
 
+// Products with at most this many 16-row x 16-field tiles take 8 x 8 tiles (tri_form8).
+constexpr int TRI_FORM8_MAX_TILES = 160;
+bool tri_form8(int n, int B);
+
 // One problem of a persistent triangular product (an uneven batch): tri_apply's arguments and
-// its tile counts (nt row tiles x nfz field groups; vec: 32-byte input vectors).
+// its tile counts (nt row tiles x nfz field groups of the tile form; vec: 32-byte input vectors).
 struct TriProb {
   const double* T;
   int64_t ldt;
@@ -49,7 +53,7 @@ struct TriProb {
   int64_t in_fs;
   double* out;
   int64_t out_fs;
-  int n, B, nt, nfz, vec;
+  int n, B, nt, nfz, vec, form8;
 };
 TriProb tri_prob(const double* T, int64_t ldt, int n, const double* in, int64_t in_fs, double* out, int64_t out_fs,
                  int B);
@@ -58,7 +62,7 @@ struct TriQueue {
   const int* first;       // [count + 1] prefix sums of their tile counts (nt nfz each)
   int count, total;
 };
-// the products of problems that all have this (upper, vec)
-hipError_t tri_apply_queue(const TriQueue& q, int upper, int vec, hipStream_t st);
+// the products of problems that all have this (upper, vec, form8)
+hipError_t tri_apply_queue(const TriQueue& q, int upper, int vec, int form8, hipStream_t st);
 
 }  // namespace krig

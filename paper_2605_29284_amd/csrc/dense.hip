@@ -383,6 +383,16 @@ hipError_t transpose_f64(const double* src, int64_t ld_src, double* dst, int64_t
 // 16x16x4 steps take element s of each, so the K order inside a chunk is permuted identically
 // for both operands.  The waves' partial tiles are added through LDS in wave order: one launch
 // per product, no partials in device memory, bitwise repeatable results.
+//
+// Short products (few 16 x 16 tiles for the compute units) take 8-row x 8-field tiles instead
+// (tri_form8).  A workgroup's time there is its heaviest tile streaming its K range through one
+// compute unit, (rows + fields) x K x 8 bytes; the 8 x 8 form halves that.  Its chunks are 32
+// columns wide and the MFMA's 16 x 16 operands hold two K ranges side by side: operand rows and
+// columns 0-7 take columns 32c .. 32c+15 of the tile's 8 fields and 8 rows, rows and columns 8-15
+// columns 32c+16 .. 32c+31 of the same ones.  The two diagonal 8 x 8 blocks of the result are
+// the two ranges' partial sums (the off-diagonal blocks mix ranges and are dropped), added with
+// the waves' partials in a fixed order.  The heaviest tiles are dispatched first.  Four 32-column
+// chunks in flight per wave cover rows of up to 2048 columns in one memory round trip.
 // ------------------------------------------------------------------------------------
 constexpr int TRI_NW = 16;  // waves per tile
 
@@ -439,6 +449,71 @@ __device__ __forceinline__ void tri_tile_body(const double* __restrict__ T, int6
   }
 }
 
+// the 8-row x 8-field form: rows 8t .. 8t+7, fields 8z .. 8z+7, chunks of 32 columns
+template <int UPPER, bool VEC, int KS>
+__device__ __forceinline__ void tri_tile8_body(const double* __restrict__ T, int64_t ldt, int n,
+                                               const double* __restrict__ in, int64_t in_fs, int B,
+                                               double* __restrict__ out, int64_t out_fs, int t, int z,
+                                               double (*red)[256]) {
+  const int tid = threadIdx.x, w = tid >> 6, lane = tid & 63, r = lane & 15, g = lane >> 4;
+  const int rr = r & 7, h = r >> 3;  // row / field within the tile, K range of the chunk
+  const int i0 = 8 * t, f0 = 8 * z;
+  const int cbeg = UPPER ? i0 / 32 : 0, cend = UPPER ? (n + 31) / 32 : (i0 + 39) / 32;
+  const bool rok = i0 + rr < n, fok = f0 + rr < B;
+  const double* trow = T + (int64_t)(rok ? i0 + rr : 0) * ldt;
+  const double* irow = in + (int64_t)(fok ? f0 + rr : 0) * in_fs;
+  double4_t acc = (double4_t){0.0, 0.0, 0.0, 0.0};
+  for (int cb = cbeg + w; cb < cend; cb += TRI_NW * KS) {
+    double4_t x[KS];
+    double a[KS][4];
+#pragma unroll
+    for (int u = 0; u < KS; ++u) {
+      const int c = cb + u * TRI_NW;
+      const int k = 32 * c + 16 * h + 4 * g;
+      const bool ok = c < cend && k < n;  // k + 3 stays inside the pitch (n rounded up to 16)
+      x[u] = (double4_t){0.0, 0.0, 0.0, 0.0};
+      if (rok && ok) x[u] = *reinterpret_cast<const double4_t*>(trow + k);
+      if constexpr (VEC) {
+        double4_t av = (double4_t){0.0, 0.0, 0.0, 0.0};
+        if (fok && ok) av = *reinterpret_cast<const double4_t*>(irow + k);
+#pragma unroll
+        for (int s = 0; s < 4; ++s) a[u][s] = k + s < n ? av[s] : 0.0;
+      } else {
+#pragma unroll
+        for (int s = 0; s < 4; ++s) a[u][s] = (fok && ok && k + s < n) ? irow[k + s] : 0.0;
+      }
+    }
+#pragma unroll
+    for (int u = 0; u < KS; ++u)
+#pragma unroll
+      for (int s = 0; s < 4; ++s) acc = __builtin_amdgcn_mfma_f64_16x16x4f64(a[u][s], x[u][s], acc, 0, 0, 0);
+  }
+  // result register j of lane (r, g) is operand row g + 4 j (field f0 + (g + 4j) % 8, range
+  // (g + 4j) / 8 = j / 2) times operand column r (row i0 + r % 8, range r / 8): lanes of range h
+  // keep registers 2h and 2h + 1, entry h * 64 + 8 f + i of the wave's partial
+  red[w][h * 64 + 8 * g + rr] = acc[2 * h];
+  red[w][h * 64 + 8 * (g + 4) + rr] = acc[2 * h + 1];
+  __syncthreads();
+  if (tid < 64) {
+    double s = 0.0;
+#pragma unroll
+    for (int v = 0; v < TRI_NW; ++v) s += red[v][tid] + red[v][64 + tid];
+    const int f = f0 + (tid >> 3), i = i0 + (tid & 7);
+    if (f < B && i < n) out[(int64_t)f * out_fs + i] = s;
+  }
+}
+
+// whether a product of n rows and B fields takes the 8 x 8 tile form
+bool tri_form8(int n, int B) { return (int64_t)((n + 15) / 16) * ((B + 15) / 16) <= TRI_FORM8_MAX_TILES; }
+
+// tile b of a launch in dispatch order -> (row tile, field group): heaviest row tiles first,
+// field groups of one row tile next to each other
+__device__ __forceinline__ void tri_tile_of(int b, int upper, int nt, int nfz, int* t, int* z) {
+  const int tr = b / nfz;
+  *z = b - tr * nfz;
+  *t = upper ? tr : nt - 1 - tr;
+}
+
 template <int UPPER, bool VEC>
 __global__ void __launch_bounds__(64 * TRI_NW) k_tri_tile(const double* __restrict__ T, int64_t ldt, int n,
                                                          const double* __restrict__ in, int64_t in_fs, int B,
@@ -447,13 +522,23 @@ __global__ void __launch_bounds__(64 * TRI_NW) k_tri_tile(const double* __restri
   tri_tile_body<UPPER, VEC, 6>(T, ldt, n, in, in_fs, B, out, out_fs, blockIdx.x, blockIdx.y, red);
 }
 
+template <int UPPER, bool VEC>
+__global__ void __launch_bounds__(64 * TRI_NW) k_tri_tile8(const double* __restrict__ T, int64_t ldt, int n,
+                                                          const double* __restrict__ in, int64_t in_fs, int B,
+                                                          double* __restrict__ out, int64_t out_fs, int nt, int nfz) {
+  __shared__ double red[TRI_NW][256];
+  int t, z;
+  tri_tile_of(blockIdx.x, UPPER, nt, nfz, &t, &z);
+  tri_tile8_body<UPPER, VEC, 4>(T, ldt, n, in, in_fs, B, out, out_fs, t, z, red);
+}
+
 // Persistent form for an uneven batch: the tiles of several problems' products in one list
 // (problem i owns tiles [first[i], first[i + 1])), walked by a grid of about one resident
 // round of workgroups, workgroup b taking tiles b, b + grid, ...  Tile (t, z) of a problem
 // computes what the problem's own launch computes.
 template <typename T> using const_as = const __attribute__((address_space(4))) T;
 
-template <int UPPER, bool VEC>
+template <int UPPER, bool VEC, bool F8>
 __global__ void __launch_bounds__(64 * TRI_NW) k_tri_tile_queue(TriQueue qa) {
   __shared__ double red[TRI_NW][256];
   int prob = 0, iter = 0;
@@ -464,8 +549,14 @@ __global__ void __launch_bounds__(64 * TRI_NW) k_tri_tile_queue(TriQueue qa) {
     while (prob + 1 < qa.count && qa.first[prob + 1] <= tile) ++prob;
     const_as<TriProb>* p = (const_as<TriProb>*)(qa.probs) + prob;
     const int local = tile - qa.first[prob];
-    tri_tile_body<UPPER, VEC, 5>(p->T, p->ldt, p->n, p->in, p->in_fs, p->B, p->out, p->out_fs, local % p->nt,
-                              local / p->nt, red);
+    if constexpr (F8) {
+      int t, z;
+      tri_tile_of(local, UPPER, p->nt, p->nfz, &t, &z);
+      tri_tile8_body<UPPER, VEC, 4>(p->T, p->ldt, p->n, p->in, p->in_fs, p->B, p->out, p->out_fs, t, z, red);
+    } else {
+      tri_tile_body<UPPER, VEC, 5>(p->T, p->ldt, p->n, p->in, p->in_fs, p->B, p->out, p->out_fs, local % p->nt,
+                                local / p->nt, red);
+    }
     __syncthreads();  // red is reused by the next tile
   }
 }
@@ -481,8 +572,9 @@ TriProb tri_prob(const double* T, int64_t ldt, int n, const double* in, int64_t 
   p.out_fs = out_fs;
   p.n = n;
   p.B = B;
-  p.nt = (n + 15) / 16;
-  p.nfz = (B + 15) / 16;
+  p.form8 = tri_form8(n, B);
+  p.nt = p.form8 ? (n + 7) / 8 : (n + 15) / 16;
+  p.nfz = p.form8 ? (B + 7) / 8 : (B + 15) / 16;
   p.vec = (in_fs & 3) == 0 && (reinterpret_cast<uintptr_t>(in) & 31) == 0;
   return p;
 }
@@ -502,14 +594,15 @@ static int tri_resident(K kernel) {
   return per * cu_count();
 }
 
-hipError_t tri_apply_queue(const TriQueue& q, int upper, int vec, hipStream_t st) {
-#define KRIG_TRIQ(U, V)                                                                                     \
-  if (upper == U && vec == V) {                                                                             \
-    hipLaunchKernelGGL((k_tri_tile_queue<U, V>), dim3(tri_resident(k_tri_tile_queue<U, V>)), dim3(64 * TRI_NW), \
-                       0, st, q);                                                                           \
+hipError_t tri_apply_queue(const TriQueue& q, int upper, int vec, int form8, hipStream_t st) {
+#define KRIG_TRIQ(U, V, F)                                                                                  \
+  if (upper == U && vec == V && form8 == F) {                                                               \
+    hipLaunchKernelGGL((k_tri_tile_queue<U, V, F>), dim3(tri_resident(k_tri_tile_queue<U, V, F>)),            \
+                       dim3(64 * TRI_NW), 0, st, q);                                                        \
     return hipGetLastError();                                                                               \
   }
-  KRIG_TRIQ(0, true) KRIG_TRIQ(0, false) KRIG_TRIQ(1, true) KRIG_TRIQ(1, false)
+  KRIG_TRIQ(0, true, 0) KRIG_TRIQ(0, false, 0) KRIG_TRIQ(1, true, 0) KRIG_TRIQ(1, false, 0)
+  KRIG_TRIQ(0, true, 1) KRIG_TRIQ(0, false, 1) KRIG_TRIQ(1, true, 1) KRIG_TRIQ(1, false, 1)
 #undef KRIG_TRIQ
   return hipErrorInvalidValue;
 }
@@ -520,10 +613,14 @@ hipError_t tri_apply(const double* T, int64_t ldt, int n, int upper, const doubl
   if ((ldt & 3) || ldt < (int64_t)(n + 15) / 16 * 16 || (reinterpret_cast<uintptr_t>(T) & 31))
     return hipErrorInvalidValue;
   const TriProb p = tri_prob(T, ldt, n, in, in_fs, out, out_fs, B);
-  const dim3 grid(p.nt, p.nfz);
 #define KRIG_TRI(U, V)                                                                                        \
   if (upper == U && p.vec == V) {                                                                             \
-    hipLaunchKernelGGL((k_tri_tile<U, V>), grid, dim3(64 * TRI_NW), 0, st, T, ldt, n, in, in_fs, B, out, out_fs); \
+    if (p.form8)                                                                                              \
+      hipLaunchKernelGGL((k_tri_tile8<U, V>), dim3(p.nt * p.nfz), dim3(64 * TRI_NW), 0, st, T, ldt, n, in,     \
+                         in_fs, B, out, out_fs, p.nt, p.nfz);                                                  \
+    else                                                                                                      \
+      hipLaunchKernelGGL((k_tri_tile<U, V>), dim3(p.nt, p.nfz), dim3(64 * TRI_NW), 0, st, T, ldt, n, in, in_fs, \
+                         B, out, out_fs);                                                                     \
     return hipGetLastError();                                                                                 \
   }
   KRIG_TRI(0, true) KRIG_TRI(0, false) KRIG_TRI(1, true) KRIG_TRI(1, false)

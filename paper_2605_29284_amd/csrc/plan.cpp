@@ -854,7 +854,7 @@ namespace {
 // the pass's (problem, tile) list.
 struct QueueLaunch {
   int kind;                  // 0 triangular product, 2 rows forward, 3 columns, 4 inverse rows
-  int upper = 0, vec = 0, f32 = 0, pair = 0, NL = 1;
+  int upper = 0, vec = 0, form8 = 0, f32 = 0, pair = 0, NL = 1;
   const FftEntry* e = nullptr;
   size_t args_off = 0, first_off = 0, nbx_off = 0;
   int count = 0, total = 0;
@@ -886,25 +886,27 @@ struct QueuePlan {
   }
 };
 
-// Adds the launches of the problems `ids` to qp: first the solve's (products grouped by (vec,
-// kg), then sums), then the transforms'; returns the index of the first transform launch.
+// Adds the launches of the problems `ids` to qp: first the solve's (products grouped by input
+// vector width and tile form), then the transforms'; returns the index of the first transform
+// launch.
 size_t queue_problems(QueuePlan& qp, const std::vector<int>& ids, const krig_plan* plans, const int32_t* h_B,
                       const double* const* h_y, void* const* h_yhat) {
   for (int upper = 0; upper < 2; ++upper) {  // L^{-1} y -> tmpv, then L^{-T} tmpv -> alpha
-    std::map<int, std::vector<TriProb>> groups;  // vec -> problems
+    std::map<std::pair<int, int>, std::vector<TriProb>> groups;  // (vec, tile form) -> problems
     for (int i : ids) {
       const krig_plan p = plans[i];
       const int B = h_B ? h_B[i] : 1;
       const TriProb tp = upper ? tri_prob(p->LinvT, p->ldL, p->n, p->tmpv, p->ldv, p->alpha, p->n, B)
                                : tri_prob(p->Linv, p->ldL, p->n, h_y[i], p->n, p->tmpv, p->ldv, B);
-      groups[tp.vec].push_back(tp);
+      groups[{tp.vec, tp.form8}].push_back(tp);
     }
     for (auto& g : groups) {
       std::vector<int> tiles;
       for (const TriProb& tp : g.second) tiles.push_back(tp.nt * tp.nfz);
       QueueLaunch ql;
       ql.upper = upper;
-      ql.vec = g.first;
+      ql.vec = g.first.first;
+      ql.form8 = g.first.second;
       qp.add(0, g.second, tiles, {}, ql);
     }
   }
@@ -972,7 +974,7 @@ int queue_launch(const QueueLaunch& ql, unsigned char* base, int nblocks, hipStr
   const int* first = reinterpret_cast<const int*>(base + ql.first_off);
   if (ql.kind == 0) {
     TriQueue tq{reinterpret_cast<const TriProb*>(base + ql.args_off), first, ql.count, ql.total};
-    return hip_status(tri_apply_queue(tq, ql.upper, ql.vec, st));
+    return hip_status(tri_apply_queue(tq, ql.upper, ql.vec, ql.form8, st));
   }
   QueueArgs qa{base + ql.args_off, first, reinterpret_cast<const int*>(base + ql.nbx_off), ql.count, ql.total};
   const FftSet& k = ql.e->k;
