@@ -185,8 +185,8 @@ int krig_lag(krig_plan p, void *d_lag);
  * d_y, d_alpha [B][n] (may alias).  Two launches, L^{-1} y into a workspace, then L^{-T}
  * of that, with the explicit inverse Cholesky factor formed at plan creation; bitwise
  * repeatable for a given (n, B).  The products' tile shape depends on n and B (8 x 8 tiles
- * when there are few 16 x 16 ones), so one field's alpha can differ in its last bits between
- * calls with different B. */
+ * for B <= 8 or when there are few 16 x 16 ones), so one field's alpha can differ in its last
+ * bits between calls with different B. */
 int krig_solve(krig_plan p, int32_t B, const double *d_y, double *d_alpha);
 
 /*

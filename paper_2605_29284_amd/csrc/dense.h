@@ -40,9 +40,17 @@ hipError_t transpose_f64(const double* src, int64_t ld_src, double* dst, int64_t
 hipError_t tri_apply(const double* T, int64_t ldt, int n, int upper, const double* in, int64_t in_fs, double* out,
                      int64_t out_fs, int B, hipStream_t st);
 
-// Products with at most this many 16-row x 16-field tiles take 8 x 8 tiles (tri_form8).
-constexpr int TRI_FORM8_MAX_TILES = 160;
-bool tri_form8(int n, int B);
+// Tile forms of the triangular products (tri_form): 16-row x 16-field tiles; 8 x 8 tiles for
+// products of up to 8 fields or with at most TRI_FORM8_MAX_TILES 16 x 16 tiles; 64 x 64 block
+// tiles for products of TRI_BLOCK_MIN_FIELDS fields or more with at least TRI_BLOCK_MIN_TILES
+// of them (a block's chunks are a serial chain: fewer blocks leave compute units idle) when T has
+// a zero pad column (ldt > n).  A product's bits depend on its form.
+enum { TRI_FORM16 = 0, TRI_FORM8 = 1, TRI_FORM_BLOCK = 2 };
+constexpr int TRI_FORM8_MAX_TILES = 128;
+constexpr int TRI_BLOCK_MIN_FIELDS = 64;
+constexpr int TRI_BLOCK_MIN_TILES = 256;
+constexpr int TRI_BLOCK_DEPTH = 4;  // chunks in flight per block
+int tri_form(int n, int B);
 
 // One problem of a persistent triangular product (an uneven batch): tri_apply's arguments and
 // its tile counts (nt row tiles x nfz field groups of the tile form; vec: 32-byte input vectors).
@@ -53,7 +61,7 @@ struct TriProb {
   int64_t in_fs;
   double* out;
   int64_t out_fs;
-  int n, B, nt, nfz, vec, form8;
+  int n, B, nt, nfz, vec, form;
 };
 TriProb tri_prob(const double* T, int64_t ldt, int n, const double* in, int64_t in_fs, double* out, int64_t out_fs,
                  int B);
@@ -62,7 +70,9 @@ struct TriQueue {
   const int* first;       // [count + 1] prefix sums of their tile counts (nt nfz each)
   int count, total;
 };
-// the products of problems that all have this (upper, vec, form8)
-hipError_t tri_apply_queue(const TriQueue& q, int upper, int vec, int form8, hipStream_t st);
+// one problem's product in its own launch (what tri_apply launches)
+hipError_t tri_apply_prob(const TriProb& p, int upper, hipStream_t st);
+// the products of problems that all have this (upper, vec, form), form TRI_FORM16 or TRI_FORM8
+hipError_t tri_apply_queue(const TriQueue& q, int upper, int vec, int form, hipStream_t st);
 
 }  // namespace krig

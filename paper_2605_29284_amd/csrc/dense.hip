@@ -385,7 +385,7 @@ hipError_t transpose_f64(const double* src, int64_t ld_src, double* dst, int64_t
 // per product, no partials in device memory, bitwise repeatable results.
 //
 // Short products (few 16 x 16 tiles for the compute units) take 8-row x 8-field tiles instead
-// (tri_form8).  A workgroup's time there is its heaviest tile streaming its K range through one
+// (TRI_FORM8).  A workgroup's time there is its heaviest tile streaming its K range through one
 // compute unit, (rows + fields) x K x 8 bytes; the 8 x 8 form halves that.  Its chunks are 32
 // columns wide and the MFMA's 16 x 16 operands hold two K ranges side by side: operand rows and
 // columns 0-7 take columns 32c .. 32c+15 of the tile's 8 fields and 8 rows, rows and columns 8-15
@@ -503,8 +503,16 @@ __device__ __forceinline__ void tri_tile8_body(const double* __restrict__ T, int
   }
 }
 
-// whether a product of n rows and B fields takes the 8 x 8 tile form
-bool tri_form8(int n, int B) { return (int64_t)((n + 15) / 16) * ((B + 15) / 16) <= TRI_FORM8_MAX_TILES; }
+// the tile form of a product of n rows and B fields: 8 x 8 for up to 8 fields (a 16-field tile
+// would stream twice the rows for the same fields) or few 16 x 16 tiles; 64 x 64 blocks for many
+// fields and many tiles; else 16 x 16
+int tri_form(int n, int B) {
+  const int64_t tiles16 = (int64_t)((n + 15) / 16) * ((B + 15) / 16);
+  if (B <= 8 || tiles16 <= TRI_FORM8_MAX_TILES) return TRI_FORM8;
+  const int64_t blocks = (int64_t)((n + 63) / 64) * ((B + 63) / 64);
+  if (B >= TRI_BLOCK_MIN_FIELDS && blocks >= TRI_BLOCK_MIN_TILES) return TRI_FORM_BLOCK;
+  return TRI_FORM16;
+}
 
 // tile b of a launch in dispatch order -> (row tile, field group): heaviest row tiles first,
 // field groups of one row tile next to each other
@@ -530,6 +538,101 @@ __global__ void __launch_bounds__(64 * TRI_NW) k_tri_tile8(const double* __restr
   int t, z;
   tri_tile_of(blockIdx.x, UPPER, nt, nfz, &t, &z);
   tri_tile8_body<UPPER, VEC, 4>(T, ldt, n, in, in_fs, B, out, out_fs, t, z, red);
+}
+
+// A workgroup barrier for LDS data only: this wave's LDS accesses complete, then the barrier.
+// __syncthreads also waits for every outstanding global load (its workgroup fence), which would
+// drain the chunks a pipelined loop keeps in flight.  The memory clobber keeps the compiler from
+// moving memory accesses across it.
+__device__ __forceinline__ void lds_barrier() { asm volatile("s_waitcnt lgkmcnt(0)\n\ts_barrier" ::: "memory"); }
+
+// Many fields and many tiles (the bandwidth regime): 64-row x 64-field block tiles, K staged
+// through LDS 16 columns at a time, four waves each owning a 32 x 32 quadrant (2 x 2 MFMA tiles),
+// as in the GEMM above.  A 16 x 16 tile reads (16 + 16) K doubles per 256 outputs; this one
+// (64 + 64) K per 4096, a quarter of the cache traffic.  A block's chunks are a serial chain, so
+// they go in groups of G = TRI_BLOCK_DEPTH: a group is stored to LDS, the next group's loads are
+// issued, and the group's MFMAs run while they are in flight (one chunk ahead left every step
+// waiting a memory latency).  Each tile's K range is its part of the
+// triangle (rounded out to whole chunks; T is zero outside the triangle), the heaviest tiles
+// first.
+template <int UPPER>
+__global__ void __launch_bounds__(256) k_tri_block(const double* __restrict__ T, int64_t ldt, int n,
+                                                   const double* __restrict__ in, int64_t in_fs, int B,
+                                                   double* __restrict__ out, int64_t out_fs, int ntn, int nfm) {
+  constexpr int G = TRI_BLOCK_DEPTH;
+  __shared__ double Is[G][16][64 + 1];  // [chunk of the group][k][field]
+  __shared__ double Ts[G][16][64 + 1];  // [chunk of the group][k][row]
+  const int tr = blockIdx.x / nfm, tm = blockIdx.x - tr * nfm;
+  const int tn = UPPER ? tr : ntn - 1 - tr;
+  const int f0 = 64 * tm, i0 = 64 * tn;
+  const int kbeg = UPPER ? i0 : 0, kend = UPPER ? n : min(n, i0 + 64);
+  const int tid = threadIdx.x, wave = tid >> 6, lane = tid & 63;
+  const int wm = (wave >> 1) * 32, wn = (wave & 1) * 32;
+  double4_t acc[2][2];
+#pragma unroll
+  for (int i = 0; i < 2; ++i)
+#pragma unroll
+    for (int j = 0; j < 2; ++j) acc[i][j] = (double4_t){0.0, 0.0, 0.0, 0.0};
+  // element e = tid + 256 q of a 64 x 16 chunk: row (field or T row) e / 16, column e % 16, so
+  // 16 lanes read one 128-byte row segment
+  const int ek = tid & 15, er = tid >> 4;
+  double ra[G][4], rb[G][4];  // slot u holds chunk c0 + u of the next group
+  // The loop has no branches and no value selects: the chunks run in whole groups of G and every
+  // load is issued, from a clamped address.  Rows past n and fields past B read row n - 1 or
+  // field B - 1: they only reach outputs that are not stored.  A column past the tile's range
+  // (the triangle's edge, n, or chunks past the end) meets a zero of T: the strict triangle, or
+  // the pitch padding (ldt > n, columns clamped to ldt - 1); its input value is any finite one
+  // (column clamped to n - 1).  Conditional loads, or zeroing loaded values, made the compiler
+  // wait for every outstanding load before each LDS store.
+  auto fetch = [&](int c, double (&a)[4], double (&b)[4]) {
+    const int k = kbeg + 16 * c + ek;
+    const int kt = k < ldt ? k : (int)ldt - 1, ki = k < n ? k : n - 1;
+#pragma unroll
+    for (int q = 0; q < 4; ++q) {
+      const int f = f0 + er + 16 * q, i = i0 + er + 16 * q;
+      a[q] = in[(int64_t)(f < B ? f : B - 1) * in_fs + ki];
+      b[q] = T[(int64_t)(i < n ? i : n - 1) * ldt + kt];
+    }
+  };
+  const int nch = (kend - kbeg + 15) / 16;
+#pragma unroll
+  for (int u = 0; u < G; ++u) fetch(u, ra[u], rb[u]);
+  for (int c0 = 0; c0 < nch; c0 += G) {
+#pragma unroll
+    for (int u = 0; u < G; ++u)
+#pragma unroll
+      for (int q = 0; q < 4; ++q) {
+        Is[u][ek][er + 16 * q] = ra[u][q];
+        Ts[u][ek][er + 16 * q] = rb[u][q];
+      }
+    lds_barrier();  // the group is visible
+#pragma unroll
+    for (int u = 0; u < G; ++u) fetch(c0 + G + u, ra[u], rb[u]);
+#pragma unroll
+    for (int u = 0; u < G; ++u)
+#pragma unroll
+      for (int kk = 0; kk < 16; kk += 4) {
+        const int kq = kk + (lane >> 4);
+        const double a0 = Is[u][kq][wm + (lane & 15)], a1 = Is[u][kq][wm + 16 + (lane & 15)];
+        const double b0 = Ts[u][kq][wn + (lane & 15)], b1 = Ts[u][kq][wn + 16 + (lane & 15)];
+        acc[0][0] = __builtin_amdgcn_mfma_f64_16x16x4f64(a0, b0, acc[0][0], 0, 0, 0);
+        acc[0][1] = __builtin_amdgcn_mfma_f64_16x16x4f64(a0, b1, acc[0][1], 0, 0, 0);
+        acc[1][0] = __builtin_amdgcn_mfma_f64_16x16x4f64(a1, b0, acc[1][0], 0, 0, 0);
+        acc[1][1] = __builtin_amdgcn_mfma_f64_16x16x4f64(a1, b1, acc[1][1], 0, 0, 0);
+      }
+    lds_barrier();  // every wave is done with the group before the next one is stored
+  }
+  // result register r of lane l in quadrant tile (i, j): field f0 + wm + 16 i + l / 16 + 4 r,
+  // row i0 + wn + 16 j + l % 16
+#pragma unroll
+  for (int i = 0; i < 2; ++i)
+#pragma unroll
+    for (int j = 0; j < 2; ++j)
+#pragma unroll
+      for (int r = 0; r < 4; ++r) {
+        const int f = f0 + wm + 16 * i + (lane >> 4) + 4 * r, row = i0 + wn + 16 * j + (lane & 15);
+        if (f < B && row < n) out[(int64_t)f * out_fs + row] = acc[i][j][r];
+      }
 }
 
 // Persistent form for an uneven batch: the tiles of several problems' products in one list
@@ -572,9 +675,11 @@ TriProb tri_prob(const double* T, int64_t ldt, int n, const double* in, int64_t 
   p.out_fs = out_fs;
   p.n = n;
   p.B = B;
-  p.form8 = tri_form8(n, B);
-  p.nt = p.form8 ? (n + 7) / 8 : (n + 15) / 16;
-  p.nfz = p.form8 ? (B + 7) / 8 : (B + 15) / 16;
+  p.form = tri_form(n, B);
+  if (p.form == TRI_FORM_BLOCK && ldt <= n) p.form = TRI_FORM16;  // the block form needs a zero pad column
+  const int rows = p.form == TRI_FORM8 ? 8 : p.form == TRI_FORM_BLOCK ? 64 : 16;
+  p.nt = (n + rows - 1) / rows;
+  p.nfz = (B + rows - 1) / rows;
   p.vec = (in_fs & 3) == 0 && (reinterpret_cast<uintptr_t>(in) & 31) == 0;
   return p;
 }
@@ -594,7 +699,9 @@ static int tri_resident(K kernel) {
   return per * cu_count();
 }
 
-hipError_t tri_apply_queue(const TriQueue& q, int upper, int vec, int form8, hipStream_t st) {
+hipError_t tri_apply_queue(const TriQueue& q, int upper, int vec, int form, hipStream_t st) {
+  const int form8 = form == TRI_FORM8;
+  if (form != TRI_FORM8 && form != TRI_FORM16) return hipErrorInvalidValue;
 #define KRIG_TRIQ(U, V, F)                                                                                  \
   if (upper == U && vec == V && form8 == F) {                                                               \
     hipLaunchKernelGGL((k_tri_tile_queue<U, V, F>), dim3(tri_resident(k_tri_tile_queue<U, V, F>)),            \
@@ -612,15 +719,27 @@ hipError_t tri_apply(const double* T, int64_t ldt, int n, int upper, const doubl
   if (n <= 0 || B <= 0) return hipSuccess;
   if ((ldt & 3) || ldt < (int64_t)(n + 15) / 16 * 16 || (reinterpret_cast<uintptr_t>(T) & 31))
     return hipErrorInvalidValue;
-  const TriProb p = tri_prob(T, ldt, n, in, in_fs, out, out_fs, B);
+  return tri_apply_prob(tri_prob(T, ldt, n, in, in_fs, out, out_fs, B), upper, st);
+}
+
+hipError_t tri_apply_prob(const TriProb& p, int upper, hipStream_t st) {
+  if (p.form == TRI_FORM_BLOCK) {
+    if (upper)
+      hipLaunchKernelGGL(k_tri_block<1>, dim3(p.nt * p.nfz), dim3(256), 0, st, p.T, p.ldt, p.n, p.in, p.in_fs, p.B,
+                         p.out, p.out_fs, p.nt, p.nfz);
+    else
+      hipLaunchKernelGGL(k_tri_block<0>, dim3(p.nt * p.nfz), dim3(256), 0, st, p.T, p.ldt, p.n, p.in, p.in_fs, p.B,
+                         p.out, p.out_fs, p.nt, p.nfz);
+    return hipGetLastError();
+  }
 #define KRIG_TRI(U, V)                                                                                        \
   if (upper == U && p.vec == V) {                                                                             \
-    if (p.form8)                                                                                              \
-      hipLaunchKernelGGL((k_tri_tile8<U, V>), dim3(p.nt * p.nfz), dim3(64 * TRI_NW), 0, st, T, ldt, n, in,     \
-                         in_fs, B, out, out_fs, p.nt, p.nfz);                                                  \
+    if (p.form == TRI_FORM8)                                                                                  \
+      hipLaunchKernelGGL((k_tri_tile8<U, V>), dim3(p.nt * p.nfz), dim3(64 * TRI_NW), 0, st, p.T, p.ldt, p.n,   \
+                         p.in, p.in_fs, p.B, p.out, p.out_fs, p.nt, p.nfz);                                    \
     else                                                                                                      \
-      hipLaunchKernelGGL((k_tri_tile<U, V>), dim3(p.nt, p.nfz), dim3(64 * TRI_NW), 0, st, T, ldt, n, in, in_fs, \
-                         B, out, out_fs);                                                                     \
+      hipLaunchKernelGGL((k_tri_tile<U, V>), dim3(p.nt, p.nfz), dim3(64 * TRI_NW), 0, st, p.T, p.ldt, p.n,     \
+                         p.in, p.in_fs, p.B, p.out, p.out_fs);                                                 \
     return hipGetLastError();                                                                                 \
   }
   KRIG_TRI(0, true) KRIG_TRI(0, false) KRIG_TRI(1, true) KRIG_TRI(1, false)

@@ -78,7 +78,7 @@ struct krig_plan_s {
   double* Lfac = nullptr;  // Cholesky factor of K + tau^2 I
   double* Linv = nullptr;  // its inverse
   double* LinvT = nullptr;  // and the transpose of that
-  int64_t ldL = 0;  // pitch of Lfac, Linv, LinvT (n rounded up to 16)
+  int64_t ldL = 0;  // pitch of Lfac, Linv, LinvT (n + 1 rounded up to 16: at least one zero pad column)
   double* Dinv = nullptr;
   double* work = nullptr;
   int kn_status = 0, pivot = 0;
@@ -854,7 +854,8 @@ namespace {
 // the pass's (problem, tile) list.
 struct QueueLaunch {
   int kind;                  // 0 triangular product, 2 rows forward, 3 columns, 4 inverse rows
-  int upper = 0, vec = 0, form8 = 0, f32 = 0, pair = 0, NL = 1;
+  int upper = 0, vec = 0, form = 0, f32 = 0, pair = 0, NL = 1;
+  std::vector<TriProb> direct;  // block-tile products: one launch per problem, from the host
   const FftEntry* e = nullptr;
   size_t args_off = 0, first_off = 0, nbx_off = 0;
   int count = 0, total = 0;
@@ -898,7 +899,7 @@ size_t queue_problems(QueuePlan& qp, const std::vector<int>& ids, const krig_pla
       const int B = h_B ? h_B[i] : 1;
       const TriProb tp = upper ? tri_prob(p->LinvT, p->ldL, p->n, p->tmpv, p->ldv, p->alpha, p->n, B)
                                : tri_prob(p->Linv, p->ldL, p->n, h_y[i], p->n, p->tmpv, p->ldv, B);
-      groups[{tp.vec, tp.form8}].push_back(tp);
+      groups[{tp.vec, tp.form}].push_back(tp);
     }
     for (auto& g : groups) {
       std::vector<int> tiles;
@@ -906,7 +907,8 @@ size_t queue_problems(QueuePlan& qp, const std::vector<int>& ids, const krig_pla
       QueueLaunch ql;
       ql.upper = upper;
       ql.vec = g.first.first;
-      ql.form8 = g.first.second;
+      ql.form = g.first.second;
+      if (ql.form == TRI_FORM_BLOCK) ql.direct = g.second;
       qp.add(0, g.second, tiles, {}, ql);
     }
   }
@@ -973,8 +975,12 @@ size_t queue_problems(QueuePlan& qp, const std::vector<int>& ids, const krig_pla
 int queue_launch(const QueueLaunch& ql, unsigned char* base, int nblocks, hipStream_t st) {
   const int* first = reinterpret_cast<const int*>(base + ql.first_off);
   if (ql.kind == 0) {
+    if (ql.form == TRI_FORM_BLOCK) {  // 256-thread workgroups: each problem's own launch
+      for (const TriProb& tp : ql.direct) KRIG_TRY(tri_apply_prob(tp, ql.upper, st));
+      return KRIG_OK;
+    }
     TriQueue tq{reinterpret_cast<const TriProb*>(base + ql.args_off), first, ql.count, ql.total};
-    return hip_status(tri_apply_queue(tq, ql.upper, ql.vec, ql.form8, st));
+    return hip_status(tri_apply_queue(tq, ql.upper, ql.vec, ql.form, st));
   }
   QueueArgs qa{base + ql.args_off, first, reinterpret_cast<const int*>(base + ql.nbx_off), ql.count, ql.total};
   const FftSet& k = ql.e->k;
@@ -1157,7 +1163,7 @@ int krig_plan_create(krig_plan* out, const krig_grid* g, const krig_matern* k, i
   CKH(build_csr(p->g, p->anchor, p->W, n, p->cw, p->node_ptr, p->ent_site, p->ent_w, p->st));
 
   // kriging system: M = K + tau^2 I, Cholesky, inverse factor
-  p->ldL = (n + 15) / 16 * 16;
+  p->ldL = (n + 16) / 16 * 16;
   CK(dalloc(p, &p->Lfac, (size_t)n * p->ldL));
   CK(dalloc(p, &p->Linv, (size_t)n * p->ldL));
   CK(dalloc(p, &p->LinvT, (size_t)n * p->ldL));

@@ -215,6 +215,42 @@ def test_batch_persistent_paired_columns(krig):
             p.close()
 
 
+@pytest.mark.parametrize("lanes", [0, 2])
+def test_batch_tile_forms(krig, lanes):
+    """Problems whose solves take each tile form of the triangular products (8 x 8: n = 700 with
+    16 fields; 16 x 16: n = 2100 with 17 and n = 700 with 64; 64 x 64 blocks: n = 4100 with 260
+    fields, which the persistent form launches per problem) reproduce their own krig_predict bit
+    for bit in the persistent form and over graph branches."""
+    rng = np.random.default_rng(17)
+    shapes = [(700, 16), (2100, 17), (700, 64), (4100, 260)]
+    plans, ys, outs = [], [], []
+    try:
+        for i, (n, B) in enumerate(shapes):
+            sites = rng.uniform(0.0, 1.0, (n, 2))
+            p = krig.Plan(96, 80, 0.0, 0.0, 1 / 95, 1 / 79, 2, 1.0, 0.15, 1.5, 0.05, sites,
+                          "f64" if i % 2 else "f32")
+            plans.append(p)
+            ys.append(dev(rng.standard_normal((B, n))))
+            outs.append(p.empty(B, 96, 80))
+        say("batch tile forms, lanes", lanes, shapes)
+        ref = reference([dict(p=p, y=y) for p, y in zip(plans, ys)])
+        bt = krig.Batch(plans, ys, outs, lanes=lanes)
+        try:
+            for rep in range(2):
+                for o in outs:
+                    o.fill_(float("nan"))
+                torch.cuda.synchronize()
+                bt.launch()
+                torch.cuda.synchronize()
+                for i, (o, r) in enumerate(zip(outs, ref)):
+                    assert np.array_equal(host(o), r), (rep, i)
+        finally:
+            bt.close()
+    finally:
+        for p in plans:
+            p.close()
+
+
 def test_batch_guards(krig, problems):
     """While a batch exists its plans refuse destruction and workspace growth."""
     say("batch guards")

@@ -110,12 +110,15 @@ def test_solve_matches_cholesky(krig, small, paper, which):
     assert relmax(a, ref) < 10 * cond * np.finfo(float).eps
 
 
-@pytest.mark.parametrize("n,B", [(1, 1), (37, 17), (1024, 3), (4096, 17), (4097, 2), (8200, 17)])
+@pytest.mark.parametrize("n,B", [(1, 1), (37, 17), (1024, 3), (4096, 17), (4097, 2), (8200, 17), (700, 64),
+                                 (4100, 260)])
 def test_solve_sizes(krig, n, B):
-    """The split triangular products at one and four chunk groups per wave (below and from
-    n = 8192), a single site, ragged row tiles, field groups of 16 and an input pitch that is
-    not a multiple of 4 (n = 37, 4097).  With tau^2 = 0.5 and sigma^2 = 1, cond(M) <= (n + 0.5)
-    / 0.5 (Gershgorin), so the bound needs no SVD."""
+    """The triangular products in each tile form: 8 x 8 tiles (a single site; n = 37, B = 17:
+    ragged row and field tiles and an input pitch that is not a multiple of 4; B <= 8 up to
+    n = 4097), 16 x 16 tiles (n = 4096 and 8200 with 17 fields: a ragged second field group,
+    rows of more than one round of chunks; n = 700 with 64 fields, too few blocks for the block
+    form) and 64 x 64 block tiles (n = 4100, B = 260: ragged rows and fields).  With tau^2 = 0.5
+    and sigma^2 = 1, cond(M) <= (n + 0.5) / 0.5 (Gershgorin), so the bound needs no SVD."""
     say("solve sizes", n, B)
     rng = np.random.default_rng(n)
     sites = rng.uniform(0.0, 1.0, (n, 2))
