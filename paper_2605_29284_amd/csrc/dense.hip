@@ -608,18 +608,31 @@ __global__ void __launch_bounds__(256) k_tri_block(const double* __restrict__ T,
     lds_barrier();  // the group is visible
 #pragma unroll
     for (int u = 0; u < G; ++u) fetch(c0 + G + u, ra[u], rb[u]);
+    // the operands of step t + 1 are read from LDS before step t's MFMAs issue, so the reads'
+    // latency overlaps the MFMA pipe instead of draining it
+    {
+      const int kq0 = lane >> 4, m = lane & 15;
+      double op[2][4];
+      op[0][0] = Is[0][kq0][wm + m];
+      op[0][1] = Is[0][kq0][wm + 16 + m];
+      op[0][2] = Ts[0][kq0][wn + m];
+      op[0][3] = Ts[0][kq0][wn + 16 + m];
 #pragma unroll
-    for (int u = 0; u < G; ++u)
-#pragma unroll
-      for (int kk = 0; kk < 16; kk += 4) {
-        const int kq = kk + (lane >> 4);
-        const double a0 = Is[u][kq][wm + (lane & 15)], a1 = Is[u][kq][wm + 16 + (lane & 15)];
-        const double b0 = Ts[u][kq][wn + (lane & 15)], b1 = Ts[u][kq][wn + 16 + (lane & 15)];
-        acc[0][0] = __builtin_amdgcn_mfma_f64_16x16x4f64(a0, b0, acc[0][0], 0, 0, 0);
-        acc[0][1] = __builtin_amdgcn_mfma_f64_16x16x4f64(a0, b1, acc[0][1], 0, 0, 0);
-        acc[1][0] = __builtin_amdgcn_mfma_f64_16x16x4f64(a1, b0, acc[1][0], 0, 0, 0);
-        acc[1][1] = __builtin_amdgcn_mfma_f64_16x16x4f64(a1, b1, acc[1][1], 0, 0, 0);
+      for (int t = 0; t < 4 * G; ++t) {
+        const int cur = t & 1, nxt = cur ^ 1;
+        if (t + 1 < 4 * G) {
+          const int u = (t + 1) >> 2, kq = 4 * ((t + 1) & 3) + kq0;
+          op[nxt][0] = Is[u][kq][wm + m];
+          op[nxt][1] = Is[u][kq][wm + 16 + m];
+          op[nxt][2] = Ts[u][kq][wn + m];
+          op[nxt][3] = Ts[u][kq][wn + 16 + m];
+        }
+        acc[0][0] = __builtin_amdgcn_mfma_f64_16x16x4f64(op[cur][0], op[cur][2], acc[0][0], 0, 0, 0);
+        acc[0][1] = __builtin_amdgcn_mfma_f64_16x16x4f64(op[cur][0], op[cur][3], acc[0][1], 0, 0, 0);
+        acc[1][0] = __builtin_amdgcn_mfma_f64_16x16x4f64(op[cur][1], op[cur][2], acc[1][0], 0, 0, 0);
+        acc[1][1] = __builtin_amdgcn_mfma_f64_16x16x4f64(op[cur][1], op[cur][3], acc[1][1], 0, 0, 0);
       }
+    }
     lds_barrier();  // every wave is done with the group before the next one is stored
   }
   // result register r of lane l in quadrant tile (i, j): field f0 + wm + 16 i + l / 16 + 4 r,
