@@ -98,7 +98,8 @@ enum {
   KRIG_INFO_FFT_VARIANT_COLS,
   KRIG_INFO_SOLVE_NOALLOC_MAX_B, /* largest B krig_solve_noalloc accepts for this plan (0: none) */
   KRIG_INFO_FILTER_SETUP,        /* how the plan's filter spectrum was built (KRIG_FILTER_*) */
-  KRIG_INFO_COLS_PAIR            /* KRIG_TUNE_COLS_PAIR's current value (1: column form) */
+  KRIG_INFO_COLS_PAIR,           /* KRIG_TUNE_COLS_PAIR's current value (1: column form) */
+  KRIG_INFO_SCATTER              /* KRIG_TUNE_SCATTER's current value */
 };
 
 /*
@@ -401,6 +402,13 @@ int krig_timing_read(krig_plan p, int32_t stage, double *total_ms, int64_t *laun
  *     is then one wave: two half-length transforms (even and odd samples) and a radix-2
  *     butterfly, with no block barrier.  KRIG_EINVAL where F1 has no paired form.  The
  *     prediction and the correlation of the adjoint change by rounding.
+ *   KRIG_TUNE_SCATTER: where the scatter of Steps 5-6 runs: 1, fused into the first row
+ *     pass (a line of threads takes a whole row's nodes); 2, its own kernel (one thread per
+ *     padded node) into a workspace image of B * P1 * P2 doubles, then the row pass over that
+ *     image, for site sets with many entries per node.  Plan creation takes 2 when the sites
+ *     give one or more CSR entries per padded node on average (n M >= P1 P2), else 1.
+ *     Both add each node's entries in segment order in FP64: the results are bitwise the
+ *     same.  A change takes effect at the next call, which sizes the workspaces again.
  * Returns KRIG_EINVAL for an unknown key, a value outside those limits, or while a
  * recorded batch (krig_batch) holds the plan.
  */
@@ -410,7 +418,8 @@ typedef enum {
   KRIG_TUNE_NL_COLS64,
   KRIG_TUNE_FFT_ROWS,
   KRIG_TUNE_FFT_COLS,
-  KRIG_TUNE_COLS_PAIR
+  KRIG_TUNE_COLS_PAIR,
+  KRIG_TUNE_SCATTER
 } krig_tune_key;
 int krig_plan_tune(krig_plan p, int32_t key, int64_t value);
 

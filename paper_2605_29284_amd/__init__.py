@@ -22,9 +22,9 @@ KRIG_F64 = 2
 INFO = dict(N=1, M=2, P1=3, P2=4, F1=5, F2=6, H2=7, LDH=8, SAVED_PER_FIELD=9, KN_STATUS=10,
             PIVOT=11, DTYPE=12, CE_CLAMPED=13, DLAG_GROUP=14, CE_F1=15, CE_F2=16, NL_ROWS64=17,
             NL_COLS64=18, FFT_R1=19, FFT_R2=20, FFT_R3=21, FFT_VARIANTS_ROWS=22, FFT_VARIANTS_COLS=23,
-            FFT_VARIANT_ROWS=24, FFT_VARIANT_COLS=25, SOLVE_NOALLOC_MAX_B=26, FILTER_SETUP=27, COLS_PAIR=28)
+            FFT_VARIANT_ROWS=24, FFT_VARIANT_COLS=25, SOLVE_NOALLOC_MAX_B=26, FILTER_SETUP=27, COLS_PAIR=28, SCATTER=29)
 FILTER = dict(reflected=0, centered=1)
-TUNE = dict(DLAG_GROUP=1, NL_ROWS64=2, NL_COLS64=3, FFT_ROWS=4, FFT_COLS=5, COLS_PAIR=6)
+TUNE = dict(DLAG_GROUP=1, NL_ROWS64=2, NL_COLS64=3, FFT_ROWS=4, FFT_COLS=5, COLS_PAIR=6, SCATTER=7)
 
 STATUS = {0: "KRIG_OK", -1: "KRIG_EINVAL", -2: "KRIG_EDOMAIN", -3: "KRIG_ENOTSPD", -4: "KRIG_ECE",
           -5: "KRIG_ENOMEM", -6: "KRIG_EHIP", -7: "KRIG_EUNSUPPORTED"}
@@ -323,7 +323,7 @@ class Plan:
         self._stream()
         _check(self.lib.krig_plan_autotune(self.h, int(B), 1 if with_adjoint else 0), "krig_plan_autotune")
         return {k: self.info(k) for k in ("FFT_VARIANT_ROWS", "FFT_VARIANT_COLS", "NL_ROWS64", "NL_COLS64",
-                                          "DLAG_GROUP", "COLS_PAIR")}
+                                          "DLAG_GROUP", "COLS_PAIR", "SCATTER")}
 
     def timing(self, on: bool):
         """Bracket every stage launch with HIP events on the plan's stream."""

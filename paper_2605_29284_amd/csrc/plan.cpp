@@ -35,6 +35,10 @@ struct DevBuf {
 
 }  // namespace
 
+// Site sets with at least this many CSR entries per padded node on average (n M / (P1 P2)) take
+// the scatter's own kernel before the row transforms instead of the scatter fused into them.
+constexpr int SCATTER_SPLIT_MIN_DENSITY = 1;
+
 struct krig_plan_s {
   hipStream_t st = nullptr;
   int device = 0;  // the GPU that was current at plan creation (holds every buffer)
@@ -50,6 +54,7 @@ struct krig_plan_s {
   const FftEntry* e1 = nullptr;  // columns (length F1)
   const FftEntry* e1h = nullptr; // the length F1 / 2 whose paired column kernels serve F1, if any
   int cols_pair = 0;             // 0: the column passes' own form; k >= 1: paired, k columns per block
+  int scatter_split = 0;         // 1: scatter into fimg by its own kernel, then the row transforms
   const FftEntry* e2 = nullptr;  // rows (length F2)
   int var_cols = 0, var_rows = 0;  // which compiled form of F1 / F2 (0: the default)
   // twiddles exp(-2 pi i j / F)
@@ -91,6 +96,7 @@ struct krig_plan_s {
   void* img = nullptr;    // FP64 [B][P1][P2]       correlation image
   double* alpha = nullptr;  // [B][n]
   double* tmpv = nullptr;   // [B][ldv]  between the two triangular products
+  double* fimg = nullptr;   // [B][P1][P2] the scattered image, when the scatter has its own kernel
   int64_t ldv = 0;          // n rounded up to 4: 32-byte rows for vector loads
   void* part = nullptr;   // cx FP64 [ngroups][H2][F1]
   int part_groups = 0;
@@ -396,9 +402,10 @@ int make_filter_centered(krig_plan p, double* filt_out) {
 int ensure_ws(krig_plan p, int B) {
   if (B <= p->wsB) return KRIG_OK;
   if (p->batch_refs > 0) return KRIG_EINVAL;  // a recorded graph uses the current buffers
-  void* olds[] = {p->S1, p->S2, p->alpha, p->tmpv};
+  void* olds[] = {p->S1, p->S2, p->alpha, p->tmpv, p->fimg};
   KRIG_TRY(hipStreamSynchronize(p->st));
   for (void* q : olds) dfree(p, q);
+  p->fimg = nullptr;
   const size_t H2 = p->H2;
   int r;
   if ((r = dalloc_bytes(p, &p->S1, spec_bytes(p, SPEC_C) * (size_t)B * H2 * p->ldP)) != KRIG_OK) return r;
@@ -406,6 +413,7 @@ int ensure_ws(krig_plan p, int B) {
   if ((r = dalloc(p, &p->alpha, (size_t)B * p->n)) != KRIG_OK) return r;
   p->ldv = (p->n + 3) / 4 * 4;
   if ((r = dalloc(p, &p->tmpv, (size_t)B * p->ldv)) != KRIG_OK) return r;
+  if (p->scatter_split && (r = dalloc(p, &p->fimg, (size_t)B * p->P1 * p->P2)) != KRIG_OK) return r;
   p->wsB = B;
   return KRIG_OK;
 }
@@ -572,6 +580,23 @@ RowsR2CArgs rows_fwd_args(krig_plan p, const double* alpha, void* spec1) {
   return r;
 }
 
+// The scatter and the forward row transforms (Steps 5-6 and the first pass of Step 7): fused
+// into one row kernel, or, for site sets with many CSR entries per padded node, the scatter's
+// own kernel (one thread per node: the fused form gives a whole row's nodes to one line of
+// threads) into the plan's image, then the row transforms of that image.  Both add each node's
+// entries in segment order in FP64 and transform the same values: the same bits.
+int rows_fwd(krig_plan p, int B, const double* alpha, void* spec1) {
+  RowsR2CArgs r = rows_fwd_args(p, alpha, spec1);
+  if (!p->scatter_split) return hip_status(set2(p).r2c_csr(r, B, p->st));
+  KRIG_TRY(scatter_image(p->g, p->node_ptr, p->ent_site, p->ent_w, alpha, p->n, B, p->fimg,
+                         (int64_t)p->P1 * p->P2, 0, p->st));
+  r.dense = p->fimg;
+  r.dense_fs = (int64_t)p->P1 * p->P2;
+  r.dense_ld = p->P2;
+  r.coff = 0;
+  return hip_status(set2(p).r2c_dense_f64(r, B, p->st));
+}
+
 ColsArgs cols_conv_args(krig_plan p, const void* spec1, const double* filt, int B) {
   ColsArgs c{};
   c.H2 = p->H2;
@@ -613,7 +638,8 @@ int do_convolve(krig_plan p, int B, const double* alpha, const double* filt, voi
                 const void* add, int64_t add_fs, int add_ld) {
   {
     StageTimer t(p, KRIG_STAGE_ROWS_FWD);
-    KRIG_TRY(set2(p).r2c_csr(rows_fwd_args(p, alpha, spec1), B, p->st));
+    const int r = rows_fwd(p, B, alpha, spec1);
+    if (r != KRIG_OK) return r;
   }
   {
     StageTimer t(p, KRIG_STAGE_COLS_CONV);
@@ -1095,6 +1121,9 @@ int krig_plan_create(krig_plan* out, const krig_grid* g, const krig_matern* k, i
   }
   p->H2 = p->F2 / 2 + 1;
   p->ldP = pitch16(p->P1);
+  // the scatter's form: its own kernel, one thread per padded node, where nodes hold many CSR
+  // entries (n M entries over P1 P2 nodes); fused into the row kernel for sparser site sets
+  p->scatter_split = (int64_t)n * p->M >= (int64_t)SCATTER_SPLIT_MIN_DENSITY * p->P1 * p->P2;
   p->ldM = pitch16(g->m1);
   p->ldX = pitch16(2 * (g->m1 + g->L) - 1);
   const bool f32 = dtype == KRIG_F32;
@@ -1233,6 +1262,7 @@ int krig_plan_info(krig_plan p, int32_t what, int64_t* v) {
     case KRIG_INFO_FFT_VARIANT_ROWS: *v = p->var_rows + 1; break;
     case KRIG_INFO_FFT_VARIANT_COLS: *v = p->var_cols + 1; break;
     case KRIG_INFO_COLS_PAIR: *v = p->cols_pair + 1; break;
+    case KRIG_INFO_SCATTER: *v = p->scatter_split + 1; break;
     case KRIG_INFO_FFT_R1: *v = p->e2->geo.R1; break;
     case KRIG_INFO_FFT_R2: *v = p->e2->geo.R2; break;
     case KRIG_INFO_FFT_R3: *v = p->e2->geo.R3; break;
@@ -1451,22 +1481,8 @@ int krig_predict_adjoint(krig_plan p, int32_t B, const void* d_g, const double* 
   const void* spec1 = d_saved;
   if (d_dlag && !spec1) {
     // recompute the row spectra of c* from the coefficients
-    RowsR2CArgs rr{};
-    rr.nrows = p->P1;
-    rr.H2 = p->H2;
-    rr.out = p->S1;
-    rr.out_fs = (int64_t)p->H2 * p->ldP;
-    rr.out_ld = p->ldP;
-    rr.twF = p->tw2_64;
-    rr.row_ptr = p->node_ptr;
-    rr.ent_site = p->ent_site;
-    rr.ent_w = p->ent_w;
-    rr.alpha = d_alpha;
-    rr.alpha_fs = p->n;
-    rr.ncols = p->P2;
-    rr.NL = p->nl_rows64;
     StageTimer t(p, KRIG_STAGE_ROWS_FWD);
-    KRIG_TRY(set2(p).r2c_csr(rr, B, p->st));
+    if ((r = rows_fwd(p, B, d_alpha, p->S1)) != KRIG_OK) return r;
     spec1 = p->S1;
   }
   // rows of g (placed at padded offset L) -> half spectra
@@ -1684,6 +1700,13 @@ int krig_plan_tune(krig_plan p, int32_t key, int64_t value) {
       if (!p->e1h || v - 1 > 4 || (size_t)(v - 1) * p->e1h->k.pair_ex * 16 > 64 * 1024) return KRIG_EINVAL;
       p->cols_pair = v - 1;
       return KRIG_OK;
+    case KRIG_TUNE_SCATTER:
+      if (v > 2) return KRIG_EINVAL;
+      if (p->scatter_split != v - 1) {
+        p->scatter_split = v - 1;
+        p->wsB = 0;  // the next call sizes the workspaces again (with or without the image)
+      }
+      return KRIG_OK;
     default: return KRIG_EINVAL;
   }
 }
@@ -1744,11 +1767,12 @@ int krig_plan_autotune(krig_plan p, int32_t B, int32_t with_adjoint) {
       case KRIG_TUNE_NL_ROWS64: return p->nl_rows64;
       case KRIG_TUNE_NL_COLS64: return p->nl_cols64;
       case KRIG_TUNE_COLS_PAIR: return p->cols_pair + 1;
+      case KRIG_TUNE_SCATTER: return p->scatter_split + 1;
       default: return p->dlag_G;
     }
   };
   const int keys[] = {KRIG_TUNE_FFT_ROWS, KRIG_TUNE_FFT_COLS, KRIG_TUNE_NL_ROWS64, KRIG_TUNE_NL_COLS64,
-                      KRIG_TUNE_COLS_PAIR, KRIG_TUNE_DLAG_GROUP};
+                      KRIG_TUNE_COLS_PAIR, KRIG_TUNE_DLAG_GROUP, KRIG_TUNE_SCATTER};
   for (int key : keys) {
     if (key == KRIG_TUNE_DLAG_GROUP && !with_adjoint) continue;
     if (key == KRIG_TUNE_COLS_PAIR && !p->e1h) continue;

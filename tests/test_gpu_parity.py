@@ -134,6 +134,36 @@ def test_solve_sizes(krig, n, B):
 
 # ------------------------------------------------------------------------------ scatter (Steps 5-6)
 @pytest.mark.parametrize("dtype", ["f64", "f32"])
+def test_scatter_forms_bitwise(krig, paper, dtype):
+    """The scatter's two forms (fused into the first row pass, or its own kernel into an image
+    that the row pass then reads) add each node's entries in segment order in FP64: the
+    predictions and the adjoint's outputs (which recompute the row spectra when none are saved)
+    must be bitwise the same, on a dense site set (about 37 entries per padded node, where plan
+    creation picks the separate kernel) and on the paper field (0.4 per node: the fused form)."""
+    rng = np.random.default_rng(23)
+    sites = rng.uniform(0.0, 1.0, (3000, 2))
+    dense = krig.Plan(48, 48, 0.0, 0.0, 1 / 47, 1 / 47, 3, 1.0, 0.2, 1.5, 0.05, sites, dtype)
+    w, _ = paper
+    sparse = krig.plan_for(w, dtype)
+    try:
+        assert dense.info("SCATTER") == 2 and sparse.info("SCATTER") == 1
+        for p, n in ((dense, 3000), (sparse, w.n)):
+            say("scatter forms", dtype, "n", n)
+            y = dev(np.random.default_rng(n).standard_normal((3, n)))
+            g = dev(np.random.default_rng(n + 1).standard_normal((3, p.m1, p.m2)), p.tdtype)
+            got = {}
+            for form in (1, 2):
+                p.tune("SCATTER", form)
+                alpha = p.solve(y)
+                got[form] = [host(p.predict(y))] + [host(t) for t in p.adjoint(g, alpha=alpha)]
+            for a, b in zip(got[1], got[2]):
+                assert np.array_equal(a, b)
+    finally:
+        dense.close()
+        sparse.close()
+
+
+@pytest.mark.parametrize("dtype", ["f64", "f32"])
 def test_scatter_identical_weights(krig, paper, dtype):
     w, (g, k, rp, ek) = paper
     say("scatter paper-field injected weights", dtype)
