@@ -179,6 +179,7 @@ struct FftSet {
   launch_rows_r2c_t r2c_delta;      // indicator of the torus centre
   // persistent forms of the prediction's passes (uneven batches)
   launch_queue_t q_r2c_csr, q_conv64, q_c2r64, q_conv_pred_f, q_c2r_f32;
+  launch_queue_t q_r2c_dense;  // forward rows of FP64 images (problems whose scatter runs apart)
   launch_cols_t ce_cols32, ce_cols64;    // sampler pass 1 (noise x sqrt(Lambda), column transforms)
   launch_rows_ce_t ce_rows32, ce_rows64; // sampler pass 2 (row transforms -> two realisations)
   // paired columns of twice this length (one wave per column, no block barriers), FP64 or

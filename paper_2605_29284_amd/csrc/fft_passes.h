@@ -942,6 +942,7 @@ FftEntry make_fft_entry() {
   k.r2c_cov = launch_rows_r2c<double, double, double, R1, R2, R3, SRC_COV>;
   k.r2c_center = launch_rows_r2c<double, double, double, R1, R2, R3, SRC_CENTER>;
   k.q_r2c_csr = launch_rows_r2c_queue<double, double, double, R1, R2, R3, SRC_CSR>;
+  k.q_r2c_dense = launch_rows_r2c_queue<double, double, double, R1, R2, R3, SRC_DENSE>;
   k.q_conv64 = launch_cols_queue<double, double, S64, R1, R2, R3, COL_CONV>;
   k.q_c2r64 = launch_rows_c2r_queue<double, double, double, R1, R2, R3>;
   k.q_conv_pred_f = launch_cols_queue<double, double, Stor<double, double, float, double>, R1, R2, R3, COL_CONV>;

@@ -879,9 +879,11 @@ namespace {
 // rows, by dtype).  Each launch is a grid of about one resident round of blocks that walks
 // the pass's (problem, tile) list.
 struct QueueLaunch {
-  int kind;                  // 0 triangular product, 2 rows forward, 3 columns, 4 inverse rows
-  int upper = 0, vec = 0, form = 0, f32 = 0, pair = 0, NL = 1;
+  int kind;                  // 0 triangular product, 2 rows forward, 3 columns, 4 inverse rows,
+                             // 5 scatters of the problems whose scatter runs apart (direct)
+  int upper = 0, vec = 0, form = 0, f32 = 0, pair = 0, dense = 0, NL = 1;
   std::vector<TriProb> direct;  // block-tile products: one launch per problem, from the host
+  std::vector<std::pair<krig_plan, int>> scat;  // kind 5: (plan, B), each its own scatter launch
   const FftEntry* e = nullptr;
   size_t args_off = 0, first_off = 0, nbx_off = 0;
   int count = 0, total = 0;
@@ -939,9 +941,18 @@ size_t queue_problems(QueuePlan& qp, const std::vector<int>& ids, const krig_pla
     }
   }
   const size_t mid = qp.launches.size();
-  // transforms: scatter + forward rows, columns (x filter), inverse rows
-  std::map<const FftEntry*, std::vector<RowsR2CArgs>> rf;
-  std::map<const FftEntry*, std::vector<int>> rf_t, rf_n;
+  // the scatters that run apart (dense site sets), before the row passes that read their images
+  {
+    QueueLaunch ql;
+    ql.kind = 5;
+    for (int i : ids)
+      if (plans[i]->scatter_split) ql.scat.push_back({plans[i], h_B ? h_B[i] : 1});
+    if (!ql.scat.empty()) qp.launches.push_back(ql);
+  }
+  // transforms: scatter + forward rows (or rows of the scattered image), columns (x filter),
+  // inverse rows
+  std::map<std::pair<const FftEntry*, int>, std::vector<RowsR2CArgs>> rf;
+  std::map<std::pair<const FftEntry*, int>, std::vector<int>> rf_t, rf_n;
   std::map<std::pair<const FftEntry*, int>, std::vector<ColsArgs>> cf;
   std::map<std::pair<const FftEntry*, int>, std::vector<int>> cf_t, cf_n;
   std::map<std::pair<const FftEntry*, int>, std::vector<RowsC2RArgs>> ri;
@@ -952,10 +963,17 @@ size_t queue_problems(QueuePlan& qp, const std::vector<int>& ids, const krig_pla
     const int nlr = nl_rows_for(p->e2, 16), nlc = nl_cols_for(p->e1, 16);
     RowsR2CArgs r = rows_fwd_args(p, p->alpha, p->S1);
     r.NL = nlr;
+    if (p->scatter_split) {  // the rows of the image the kind-5 launch scatters (as rows_fwd)
+      r.dense = p->fimg;
+      r.dense_fs = (int64_t)p->P1 * p->P2;
+      r.dense_ld = p->P2;
+      r.coff = 0;
+    }
     const int nbr = ((p->P1 + 1) / 2 + nlr - 1) / nlr;
-    rf[p->e2].push_back(r);
-    rf_t[p->e2].push_back(nbr * B);
-    rf_n[p->e2].push_back(nbr);
+    const auto rkey = std::make_pair(p->e2, p->scatter_split);
+    rf[rkey].push_back(r);
+    rf_t[rkey].push_back(nbr * B);
+    rf_n[rkey].push_back(nbr);
     ColsArgs c = cols_conv_args(p, p->S1, p->filt, B);
     const int nlq = p->cols_pair ? p->cols_pair : nlc;
     c.NL = nlq;
@@ -975,7 +993,8 @@ size_t queue_problems(QueuePlan& qp, const std::vector<int>& ids, const krig_pla
   }
   for (auto& g : rf) {
     QueueLaunch ql;
-    ql.e = g.first;
+    ql.e = g.first.first;
+    ql.dense = g.first.second;
     ql.NL = g.second[0].NL;
     qp.add(2, g.second, rf_t[g.first], rf_n[g.first], ql);
   }
@@ -999,6 +1018,14 @@ size_t queue_problems(QueuePlan& qp, const std::vector<int>& ids, const krig_pla
 
 // nblocks for the transform kernels: 0 one resident round of blocks, -d 1/d of one
 int queue_launch(const QueueLaunch& ql, unsigned char* base, int nblocks, hipStream_t st) {
+  if (ql.kind == 5) {
+    for (const auto& sj : ql.scat) {
+      const krig_plan p = sj.first;
+      KRIG_TRY(scatter_image(p->g, p->node_ptr, p->ent_site, p->ent_w, p->alpha, p->n, sj.second, p->fimg,
+                             (int64_t)p->P1 * p->P2, 0, st));
+    }
+    return KRIG_OK;
+  }
   const int* first = reinterpret_cast<const int*>(base + ql.first_off);
   if (ql.kind == 0) {
     if (ql.form == TRI_FORM_BLOCK) {  // 256-thread workgroups: each problem's own launch
@@ -1010,7 +1037,7 @@ int queue_launch(const QueueLaunch& ql, unsigned char* base, int nblocks, hipStr
   }
   QueueArgs qa{base + ql.args_off, first, reinterpret_cast<const int*>(base + ql.nbx_off), ql.count, ql.total};
   const FftSet& k = ql.e->k;
-  const launch_queue_t fn = ql.kind == 2   ? k.q_r2c_csr
+  const launch_queue_t fn = ql.kind == 2   ? (ql.dense ? k.q_r2c_dense : k.q_r2c_csr)
                             : ql.kind == 3 ? (ql.pair ? (ql.f32 ? k.q_pair_conv_pred_f : k.q_pair_conv64)
                                                       : (ql.f32 ? k.q_conv_pred_f : k.q_conv64))
                                            : (ql.f32 ? k.q_c2r_f32 : k.q_c2r64);

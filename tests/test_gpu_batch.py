@@ -220,7 +220,9 @@ def test_batch_tile_forms(krig, lanes):
     """Problems whose solves take each tile form of the triangular products (8 x 8: n = 700 with
     16 fields; 16 x 16: n = 2100 with 17 and n = 700 with 64; 64 x 64 blocks: n = 4100 with 260
     fields, which the persistent form launches per problem) reproduce their own krig_predict bit
-    for bit in the persistent form and over graph branches."""
+    for bit in the persistent form and over graph branches.  The site sets are dense enough for
+    the scatter's own kernel (1.3 to 7.8 CSR entries per padded node); the first problem is set
+    to the fused scatter, so both scatter forms share the batch."""
     rng = np.random.default_rng(17)
     shapes = [(700, 16), (2100, 17), (700, 64), (4100, 260)]
     plans, ys, outs = [], [], []
@@ -232,6 +234,8 @@ def test_batch_tile_forms(krig, lanes):
             plans.append(p)
             ys.append(dev(rng.standard_normal((B, n))))
             outs.append(p.empty(B, 96, 80))
+        assert all(p.info("SCATTER") == 2 for p in plans)
+        plans[0].tune("SCATTER", 1)
         say("batch tile forms, lanes", lanes, shapes)
         ref = reference([dict(p=p, y=y) for p, y in zip(plans, ys)])
         bt = krig.Batch(plans, ys, outs, lanes=lanes)
