@@ -403,12 +403,14 @@ int krig_timing_read(krig_plan p, int32_t stage, double *total_ms, int64_t *laun
  *     butterfly, with no block barrier.  KRIG_EINVAL where F1 has no paired form.  The
  *     prediction and the correlation of the adjoint change by rounding.
  *   KRIG_TUNE_SCATTER: where the scatter of Steps 5-6 runs: 1, fused into the first row
- *     pass (a line of threads takes a whole row's nodes); 2, its own kernel (one thread per
- *     padded node) into a workspace image of B * P1 * P2 doubles, then the row pass over that
- *     image, for site sets with many entries per node.  Plan creation takes 2 when the sites
- *     give one or more CSR entries per padded node on average (n M >= P1 P2), else 1.
- *     Both add each node's entries in segment order in FP64: the results are bitwise the
- *     same.  A change takes effect at the next call, which sizes the workspaces again.
+ *     pass (a line of threads takes a whole row's nodes); 2, in calls of fewer than 64 fields,
+ *     its own kernel (one thread per padded node) into a workspace image of B * P1 * P2
+ *     doubles, then the row pass over that image, for site sets with many entries per node
+ *     (calls of 64 fields or more keep the fused form).  Plan creation takes 2 when the sites
+ *     give one or more CSR entries per padded node on average (n M >= P1 P2), else 1.  Both
+ *     add each node's entries in segment order in FP64: the results are bitwise the same.
+ *     A change takes effect at the next call (the first call that takes the scatter apart
+ *     allocates the image).
  * Returns KRIG_EINVAL for an unknown key, a value outside those limits, or while a
  * recorded batch (krig_batch) holds the plan.
  */

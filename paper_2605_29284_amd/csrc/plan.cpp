@@ -36,8 +36,12 @@ struct DevBuf {
 }  // namespace
 
 // Site sets with at least this many CSR entries per padded node on average (n M / (P1 P2)) take
-// the scatter's own kernel before the row transforms instead of the scatter fused into them.
+// the scatter's own kernel before the row transforms instead of the scatter fused into them, in
+// calls of fewer than SCATTER_SPLIT_MAX_B fields: with many fields the fused form has threads
+// enough, and the image's write and read cost more than they save (256 fields on a 520 x 520
+// padded grid: 2.38 against 2.24 ms per convolution).
 constexpr int SCATTER_SPLIT_MIN_DENSITY = 1;
+constexpr int SCATTER_SPLIT_MAX_B = 64;
 
 struct krig_plan_s {
   hipStream_t st = nullptr;
@@ -96,7 +100,9 @@ struct krig_plan_s {
   void* img = nullptr;    // FP64 [B][P1][P2]       correlation image
   double* alpha = nullptr;  // [B][n]
   double* tmpv = nullptr;   // [B][ldv]  between the two triangular products
-  double* fimg = nullptr;   // [B][P1][P2] the scattered image, when the scatter has its own kernel
+  double* fimg = nullptr;   // [min(B, 63)][P1][P2] the scattered image, when the scatter has its own kernel
+  int fimgB = 0;            // fields the image holds
+  bool fimg_needed = false; // a call took the scatter apart: keep the image when the workspaces grow
   int64_t ldv = 0;          // n rounded up to 4: 32-byte rows for vector loads
   void* part = nullptr;   // cx FP64 [ngroups][H2][F1]
   int part_groups = 0;
@@ -399,13 +405,23 @@ int make_filter_centered(krig_plan p, double* filt_out) {
 }
 
 // forward workspaces (prediction and solves) for B fields
+bool use_split(krig_plan p, int B) { return p->scatter_split && B < SCATTER_SPLIT_MAX_B; }
+// whether a call of B fields takes the scatter apart now: its form says so and the image is there
+// (a workspace sized for more fields than the split takes has none until such a call sizes it)
+bool split_now(krig_plan p, int B) { return use_split(p, B) && p->fimg && B <= p->fimgB; }
+
 int ensure_ws(krig_plan p, int B) {
-  if (B <= p->wsB) return KRIG_OK;
+  // with the workspaces big enough, a missing image only means the fused scatter (the same
+  // bits); it is allocated unless a recorded batch holds the buffers
+  if (B <= p->wsB && (!use_split(p, B) || (p->fimg && B <= p->fimgB) || p->batch_refs > 0)) return KRIG_OK;
   if (p->batch_refs > 0) return KRIG_EINVAL;  // a recorded graph uses the current buffers
+  const bool img = p->scatter_split && (use_split(p, B) || p->fimg_needed);
+  B = std::max(B, p->wsB);  // never shrink what earlier calls sized
   void* olds[] = {p->S1, p->S2, p->alpha, p->tmpv, p->fimg};
   KRIG_TRY(hipStreamSynchronize(p->st));
   for (void* q : olds) dfree(p, q);
   p->fimg = nullptr;
+  p->fimgB = 0;
   const size_t H2 = p->H2;
   int r;
   if ((r = dalloc_bytes(p, &p->S1, spec_bytes(p, SPEC_C) * (size_t)B * H2 * p->ldP)) != KRIG_OK) return r;
@@ -413,7 +429,13 @@ int ensure_ws(krig_plan p, int B) {
   if ((r = dalloc(p, &p->alpha, (size_t)B * p->n)) != KRIG_OK) return r;
   p->ldv = (p->n + 3) / 4 * 4;
   if ((r = dalloc(p, &p->tmpv, (size_t)B * p->ldv)) != KRIG_OK) return r;
-  if (p->scatter_split && (r = dalloc(p, &p->fimg, (size_t)B * p->P1 * p->P2)) != KRIG_OK) return r;
+  // the scatter's image, for the calls that take the scatter apart (fewer than SCATTER_SPLIT_MAX_B
+  // fields): allocated with the first such call
+  if (img) {
+    p->fimgB = std::min(B, SCATTER_SPLIT_MAX_B - 1);
+    if ((r = dalloc(p, &p->fimg, (size_t)p->fimgB * p->P1 * p->P2)) != KRIG_OK) return r;
+  }
+  p->fimg_needed = p->fimg != nullptr;
   p->wsB = B;
   return KRIG_OK;
 }
@@ -587,7 +609,7 @@ RowsR2CArgs rows_fwd_args(krig_plan p, const double* alpha, void* spec1) {
 // entries in segment order in FP64 and transform the same values: the same bits.
 int rows_fwd(krig_plan p, int B, const double* alpha, void* spec1) {
   RowsR2CArgs r = rows_fwd_args(p, alpha, spec1);
-  if (!p->scatter_split) return hip_status(set2(p).r2c_csr(r, B, p->st));
+  if (!split_now(p, B)) return hip_status(set2(p).r2c_csr(r, B, p->st));
   KRIG_TRY(scatter_image(p->g, p->node_ptr, p->ent_site, p->ent_w, alpha, p->n, B, p->fimg,
                          (int64_t)p->P1 * p->P2, 0, p->st));
   r.dense = p->fimg;
@@ -946,7 +968,7 @@ size_t queue_problems(QueuePlan& qp, const std::vector<int>& ids, const krig_pla
     QueueLaunch ql;
     ql.kind = 5;
     for (int i : ids)
-      if (plans[i]->scatter_split) ql.scat.push_back({plans[i], h_B ? h_B[i] : 1});
+      if (split_now(plans[i], h_B ? h_B[i] : 1)) ql.scat.push_back({plans[i], h_B ? h_B[i] : 1});
     if (!ql.scat.empty()) qp.launches.push_back(ql);
   }
   // transforms: scatter + forward rows (or rows of the scattered image), columns (x filter),
@@ -963,14 +985,15 @@ size_t queue_problems(QueuePlan& qp, const std::vector<int>& ids, const krig_pla
     const int nlr = nl_rows_for(p->e2, 16), nlc = nl_cols_for(p->e1, 16);
     RowsR2CArgs r = rows_fwd_args(p, p->alpha, p->S1);
     r.NL = nlr;
-    if (p->scatter_split) {  // the rows of the image the kind-5 launch scatters (as rows_fwd)
+    const bool split = split_now(p, B);
+    if (split) {  // the rows of the image the kind-5 launch scatters (as rows_fwd)
       r.dense = p->fimg;
       r.dense_fs = (int64_t)p->P1 * p->P2;
       r.dense_ld = p->P2;
       r.coff = 0;
     }
     const int nbr = ((p->P1 + 1) / 2 + nlr - 1) / nlr;
-    const auto rkey = std::make_pair(p->e2, p->scatter_split);
+    const auto rkey = std::make_pair(p->e2, (int)split);
     rf[rkey].push_back(r);
     rf_t[rkey].push_back(nbr * B);
     rf_n[rkey].push_back(nbr);
@@ -1729,10 +1752,7 @@ int krig_plan_tune(krig_plan p, int32_t key, int64_t value) {
       return KRIG_OK;
     case KRIG_TUNE_SCATTER:
       if (v > 2) return KRIG_EINVAL;
-      if (p->scatter_split != v - 1) {
-        p->scatter_split = v - 1;
-        p->wsB = 0;  // the next call sizes the workspaces again (with or without the image)
-      }
+      p->scatter_split = v - 1;  // the next call that takes the scatter apart sizes its image
       return KRIG_OK;
     default: return KRIG_EINVAL;
   }

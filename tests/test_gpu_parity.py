@@ -163,6 +163,26 @@ def test_scatter_forms_bitwise(krig, paper, dtype):
         sparse.close()
 
 
+def test_scatter_split_by_batch_size(krig):
+    """The scatter's own kernel serves calls of fewer than 64 fields; larger calls keep the fused
+    form and no image.  Calls of 80, then 2 (allocates the image), then 80 and 5 fields on one
+    dense plan must give bitwise what a plan on the fused form gives for the same fields."""
+    rng = np.random.default_rng(29)
+    sites = rng.uniform(0.0, 1.0, (2500, 2))
+    args = (40, 40, 0.0, 0.0, 1 / 39, 1 / 39, 3, 1.0, 0.2, 2.5, 0.05, sites, "f64")
+    p, q = krig.Plan(*args), krig.Plan(*args)
+    try:
+        q.tune("SCATTER", 1)
+        assert p.info("SCATTER") == 2
+        y = rng.standard_normal((80, 2500))
+        for B in (80, 2, 80, 5):
+            say("scatter split by batch size, B", B)
+            assert np.array_equal(host(p.predict(dev(y[:B]))), host(q.predict(dev(y[:B]))))
+    finally:
+        p.close()
+        q.close()
+
+
 @pytest.mark.parametrize("dtype", ["f64", "f32"])
 def test_scatter_identical_weights(krig, paper, dtype):
     w, (g, k, rp, ek) = paper
