@@ -78,7 +78,8 @@ struct krig_plan_s {
   int32_t* anchor = nullptr;
   double* kvec = nullptr;
   double* W = nullptr;
-  double* Wt = nullptr;
+  double* Wt = nullptr;     // [M][n] transposed weights, columns in the gather order
+  int32_t* gorder = nullptr; // [n] the gather order: sites sorted by anchor cell
   double* Wr = nullptr;     // [n][M] residual of the weight refinement
   int32_t* node_ptr = nullptr;
   int32_t* ent_site = nullptr;
@@ -558,7 +559,21 @@ int weights_from_kvec(krig_plan p, const double* d_kvec) {
     gw.A = p->Wt; gw.C = p->W; gw.beta = 1.0;
     KRIG_TRY(gemm_f64(gw, p->st));
   }
-  KRIG_TRY(transpose_w(p->W, n, M, p->Wt, p->st));
+  KRIG_TRY(transpose_w(p->W, n, M, p->gorder, p->Wt, p->st));
+  return KRIG_OK;
+}
+
+// The gathers' site order: sites sorted by anchor cell (row-major over the cells; ties keep site
+// order), so that a wave's sites read neighbouring image windows.  From host anchors [n][2].
+int set_gather_order(krig_plan p, const int32_t* h_anchor) {
+  std::vector<int32_t> ord(p->n);
+  for (int i = 0; i < p->n; ++i) ord[i] = i;
+  const int64_t m2 = p->g.m2;
+  std::stable_sort(ord.begin(), ord.end(), [&](int32_t a, int32_t b) {
+    return (int64_t)h_anchor[2 * a] * m2 + h_anchor[2 * a + 1] < (int64_t)h_anchor[2 * b] * m2 + h_anchor[2 * b + 1];
+  });
+  KRIG_TRY(hipMemcpyAsync(p->gorder, ord.data(), sizeof(int32_t) * p->n, hipMemcpyHostToDevice, p->st));
+  KRIG_TRY(hipStreamSynchronize(p->st));  // ord is freed on return
   return KRIG_OK;
 }
 
@@ -1221,12 +1236,19 @@ int krig_plan_create(krig_plan* out, const krig_grid* g, const krig_matern* k, i
   CK(dalloc(p, &p->kvec, (size_t)n * M));
   CK(dalloc(p, &p->W, (size_t)n * M));
   CK(dalloc(p, &p->Wt, (size_t)n * M));
+  CK(dalloc(p, &p->gorder, (size_t)n));
   CK(dalloc(p, &p->Wr, (size_t)n * M));
   if (M <= 64)
     CKH(kn_factor(p->g, p->mt, p->KN, p->LinvN, p->d_status, p->st));
   else
     CK(kn_factor_large(p));
   CKH(site_kvec(p->g, p->mt, p->sites, n, p->anchor, p->kvec, p->st));
+  {
+    std::vector<int32_t> ha(2 * (size_t)n);
+    CKH(hipMemcpyAsync(ha.data(), p->anchor, ha.size() * sizeof(int32_t), hipMemcpyDeviceToHost, p->st));
+    CKH(hipStreamSynchronize(p->st));
+    CK(set_gather_order(p, ha.data()));
+  }
   CK(weights_from_kvec(p, p->kvec));
 
   // Step 5 structure
@@ -1349,7 +1371,9 @@ int krig_set_weights(krig_plan p, const int32_t* d_anchor, const double* d_W) {
     if (h[2 * i] < 0 || h[2 * i] >= p->g.m1 || h[2 * i + 1] < 0 || h[2 * i + 1] >= p->g.m2) return KRIG_EDOMAIN;
   KRIG_TRY(hipMemcpyAsync(p->anchor, d_anchor, h.size() * sizeof(int32_t), hipMemcpyDeviceToDevice, p->st));
   KRIG_TRY(hipMemcpyAsync(p->W, d_W, sizeof(double) * p->n * p->M, hipMemcpyDeviceToDevice, p->st));
-  KRIG_TRY(transpose_w(p->W, p->n, p->M, p->Wt, p->st));
+  const int r = set_gather_order(p, h.data());
+  if (r != KRIG_OK) return r;
+  KRIG_TRY(transpose_w(p->W, p->n, p->M, p->gorder, p->Wt, p->st));
   KRIG_TRY(build_csr(p->g, p->anchor, p->W, p->n, p->cw, p->node_ptr, p->ent_site, p->ent_w, p->st));
   return KRIG_OK;
 }
@@ -1629,7 +1653,7 @@ int krig_predict_adjoint(krig_plan p, int32_t B, const void* d_g, const double* 
   if (d_dy) {
     {
       StageTimer t(p, KRIG_STAGE_GATHER);
-      KRIG_TRY(gather_sites(p->g, p->anchor, p->Wt, p->n, p->img, (int64_t)p->P1 * p->P2, p->P2, B, 0, p->alpha,
+      KRIG_TRY(gather_sites(p->g, p->anchor, p->Wt, p->gorder, p->n, p->img, (int64_t)p->P1 * p->P2, p->P2, B, 0, p->alpha,
                             p->n, p->st));
     }
     if ((r = do_solve(p, B, p->alpha, d_dy)) != KRIG_OK) return r;
@@ -1962,7 +1986,7 @@ int krig_csim(krig_plan p, int32_t R, uint64_t seed, const double* d_y, void* d_
   // residual of the data against the simulated data at the sites
   {
     StageTimer t(p, KRIG_STAGE_GATHER);
-    KRIG_TRY(csim_residual(p->g, p->anchor, p->Wt, p->n, p->csU, (int64_t)p->P1 * p->P2, p->P2, R, f32, d_y,
+    KRIG_TRY(csim_residual(p->g, p->anchor, p->Wt, p->gorder, p->n, p->csU, (int64_t)p->P1 * p->P2, p->P2, R, f32, d_y,
                            sqrt(p->mt.tau2), seed, 0, p->csRes, p->n, p->st));
   }
   if ((r = do_solve(p, R, p->csRes, p->csAl)) != KRIG_OK) return r;

@@ -34,8 +34,10 @@ hipError_t kn_assemble(const GridDev& g, const MaternDev& mt, double* KN, double
 // Step 3: anchor cell (i0, j0) and k_i (n x M) of every site; sites [n][2] FP64.
 hipError_t site_kvec(const GridDev& g, const MaternDev& mt, const double* sites, int n, int32_t* anchor,
                      double* kvec, hipStream_t st);
-// W [n][M] -> Wt [M][n]
-hipError_t transpose_w(const double* W, int n, int M, double* Wt, hipStream_t st);
+// W [n][M] -> Wt [M][n] in gather order: Wt[m][s] = W[order[s]][m] (order NULL: the identity).
+// The gathers walk sites in that order (slot s holds site order[s]): with the sites sorted by
+// anchor cell, neighbouring lanes read neighbouring image windows and share cache lines.
+hipError_t transpose_w(const double* W, int n, int M, const int32_t* order, double* Wt, hipStream_t st);
 
 // Step 5 structure: CSR over the padded grid (deterministic, no float atomics).
 //  cell_cnt [m1*m2], cell_ptr [m1*m2+1], cell_sites [n], node_ptr [P1*P2+1],
@@ -55,14 +57,16 @@ hipError_t refill_csr_weights(const GridDev& g, const int32_t* anchor, const dou
 hipError_t scatter_image(const GridDev& g, const int32_t* node_ptr, const int32_t* ent_site, const double* ent_w,
                          const double* alpha, int64_t alpha_fs, int B, void* img, int64_t img_fs, int to_f32,
                          hipStream_t st);
-// out[b][i] = sum_m Wt[m][i] img[b][(i0+L+ox_m) * ldi + j0+L+oy_m] (FP64 accumulation);
-// optional: out[b][i] = sub[b][i] - (that + noise_scale * N(0,1) Philox noise).
-hipError_t gather_sites(const GridDev& g, const int32_t* anchor, const double* Wt, int n, const void* img,
-                        int64_t img_fs, int64_t ldi, int B, int from_f32, double* out, int64_t out_fs,
-                        hipStream_t st);
-hipError_t csim_residual(const GridDev& g, const int32_t* anchor, const double* Wt, int n, const void* img,
-                         int64_t img_fs, int64_t ldi, int R, int from_f32, const double* y, double noise_sd,
-                         uint64_t seed, int r0, double* out, int64_t out_fs, hipStream_t st);
+// out[b][i] = sum_m W[i][m] img[b][(i0+L+ox_m) * ldi + j0+L+oy_m] (FP64 accumulation, in the
+// order of m), with Wt the transposed weights in the gather order `order` (transpose_w; NULL:
+// the identity); the sites are visited in that order, each writing its own output.
+// csim_residual: out[r][i] = y[i] - (that + noise_sd * N(0,1) Philox noise of (i, r0 + r)).
+hipError_t gather_sites(const GridDev& g, const int32_t* anchor, const double* Wt, const int32_t* order, int n,
+                        const void* img, int64_t img_fs, int64_t ldi, int B, int from_f32, double* out,
+                        int64_t out_fs, hipStream_t st);
+hipError_t csim_residual(const GridDev& g, const int32_t* anchor, const double* Wt, const int32_t* order, int n,
+                         const void* img, int64_t img_fs, int64_t ldi, int R, int from_f32, const double* y,
+                         double noise_sd, uint64_t seed, int r0, double* out, int64_t out_fs, hipStream_t st);
 
 // circulant-embedding eigenvalues: per-block min / max / negative count (the host
 // finishes the reduction), then x <- sqrt(max(x, 0) * scale)

@@ -198,14 +198,16 @@ hipError_t site_kvec(const GridDev& g, const MaternDev& mt, const double* sites,
   return hipGetLastError();
 }
 
-__global__ void k_transpose_w(const double* __restrict__ W, int n, int M, double* __restrict__ Wt) {
+__global__ void k_transpose_w(const double* __restrict__ W, int n, int M, const int32_t* __restrict__ order,
+                              double* __restrict__ Wt) {
   const int64_t idx = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (idx >= (int64_t)n * M) return;
-  const int i = (int)(idx % n), m = (int)(idx / n);
+  const int s = (int)(idx % n), m = (int)(idx / n);
+  const int i = order ? order[s] : s;
   Wt[idx] = W[(int64_t)i * M + m];
 }
-hipError_t transpose_w(const double* W, int n, int M, double* Wt, hipStream_t st) {
-  hipLaunchKernelGGL(k_transpose_w, dim3(nblk((int64_t)n * M)), dim3(256), 0, st, W, n, M, Wt);
+hipError_t transpose_w(const double* W, int n, int M, const int32_t* order, double* Wt, hipStream_t st) {
+  hipLaunchKernelGGL(k_transpose_w, dim3(nblk((int64_t)n * M)), dim3(256), 0, st, W, n, M, order, Wt);
   return hipGetLastError();
 }
 
@@ -393,9 +395,10 @@ hipError_t scatter_image(const GridDev& g, const int32_t* node_ptr, const int32_
   return hipGetLastError();
 }
 
+// site i in gather slot s (its transposed weights are column s of Wt)
 template <typename TS>
-__device__ inline double gather_one(const GridDev& g, const int32_t* anchor, const double* Wt, int n, int i,
-                                    const TS* im, int64_t ldi) {
+__device__ inline double gather_one(const GridDev& g, const int32_t* anchor, const double* Wt, int n, int s,
+                                    int i, const TS* im, int64_t ldi) {
   const int i0 = anchor[2 * i], j0 = anchor[2 * i + 1];
   const int L2 = 2 * g.L;
   double acc = 0.0;
@@ -409,7 +412,7 @@ __device__ inline double gather_one(const GridDev& g, const int32_t* anchor, con
       iv[u] = 0.0;
       if (m < g.M) {
         const int ox = m / L2 - g.L + 1, oy = m % L2 - g.L + 1;
-        wv[u] = Wt[(int64_t)m * n + i];
+        wv[u] = Wt[(int64_t)m * n + s];
         iv[u] = (double)im[(int64_t)(i0 + g.L + ox) * ldi + (j0 + g.L + oy)];
       }
     }
@@ -427,22 +430,24 @@ __device__ inline double gather_one(const GridDev& g, const int32_t* anchor, con
 // (q0 + q1) + (q2 + q3).
 template <typename TS, int L>
 __global__ void __launch_bounds__(256) k_gather_sites(GridDev g, const int32_t* __restrict__ anchor,
-                                                      const double* __restrict__ Wt, int n,
+                                                      const double* __restrict__ Wt,
+                                                      const int32_t* __restrict__ order, int n,
                                                       const TS* __restrict__ img, int64_t img_fs, int64_t ldi,
                                                       double* __restrict__ out, int64_t out_fs) {
   constexpr int L2 = 2 * L, PER = L * L;
   const int t = blockIdx.x * blockDim.x + threadIdx.x;
-  const int i = t >> 2, q = t & 3;
+  const int s = t >> 2, q = t & 3;  // gather slot, quarter of the neighbourhood
   const int b = blockIdx.y;
-  const bool ok = i < n;  // all four lanes of a site agree; no early exit before the shuffles
-  const int ii = ok ? i : 0;
+  const bool ok = s < n;  // all four lanes of a site agree; no early exit before the shuffles
+  const int ss = ok ? s : 0;
+  const int ii = order ? order[ss] : ss;
   const TS* base = img + (int64_t)b * img_fs + (int64_t)(anchor[2 * ii] + L) * ldi + (anchor[2 * ii + 1] + L);
   double wv[PER], iv[PER];
 #pragma unroll
   for (int u = 0; u < PER; ++u) {
     const int m = q + 4 * u;  // q is a lane value: the offsets below are q-dependent but cheap
     const int ox = m / L2 - L + 1, oy = m % L2 - L + 1;
-    wv[u] = ok ? Wt[(int64_t)m * n + ii] : 0.0;
+    wv[u] = ok ? Wt[(int64_t)m * n + ss] : 0.0;
     iv[u] = ok ? (double)base[(int64_t)ox * ldi + oy] : 0.0;
   }
   double acc = 0.0;
@@ -452,54 +457,59 @@ __global__ void __launch_bounds__(256) k_gather_sites(GridDev g, const int32_t* 
   const double pair = (q & 1) ? o1 + acc : acc + o1;  // (q0 + q1) or (q2 + q3), on both lanes of a pair
   const double o2 = __shfl_xor(pair, 2);
   const double tot = (q & 2) ? o2 + pair : pair + o2;
-  if (ok && q == 0) out[(int64_t)b * out_fs + i] = tot;
+  if (ok && q == 0) out[(int64_t)b * out_fs + ii] = tot;
 }
 
 template <typename TS>
 __global__ void __launch_bounds__(256) k_gather_generic(GridDev g, const int32_t* __restrict__ anchor,
-                                                        const double* __restrict__ Wt, int n,
+                                                        const double* __restrict__ Wt,
+                                                        const int32_t* __restrict__ order, int n,
                                                         const TS* __restrict__ img, int64_t img_fs, int64_t ldi,
                                                         double* __restrict__ out, int64_t out_fs) {
-  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  const int s = blockIdx.x * blockDim.x + threadIdx.x;
   const int b = blockIdx.y;
-  if (i >= n) return;
-  out[(int64_t)b * out_fs + i] = gather_one<TS>(g, anchor, Wt, n, i, img + (int64_t)b * img_fs, ldi);
+  if (s >= n) return;
+  const int i = order ? order[s] : s;
+  out[(int64_t)b * out_fs + i] = gather_one<TS>(g, anchor, Wt, n, s, i, img + (int64_t)b * img_fs, ldi);
 }
 
 template <typename TS>
-hipError_t gather_launch(const GridDev& g, const int32_t* anchor, const double* Wt, int n, const TS* img,
-                         int64_t img_fs, int64_t ldi, int B, double* out, int64_t out_fs, hipStream_t st) {
+hipError_t gather_launch(const GridDev& g, const int32_t* anchor, const double* Wt, const int32_t* order, int n,
+                         const TS* img, int64_t img_fs, int64_t ldi, int B, double* out, int64_t out_fs,
+                         hipStream_t st) {
   dim3 grid((unsigned)((4 * (int64_t)n + 255) / 256), B);
   switch (g.L) {
-    case 1: hipLaunchKernelGGL((k_gather_sites<TS, 1>), grid, dim3(256), 0, st, g, anchor, Wt, n, img, img_fs, ldi, out, out_fs); break;
-    case 2: hipLaunchKernelGGL((k_gather_sites<TS, 2>), grid, dim3(256), 0, st, g, anchor, Wt, n, img, img_fs, ldi, out, out_fs); break;
-    case 3: hipLaunchKernelGGL((k_gather_sites<TS, 3>), grid, dim3(256), 0, st, g, anchor, Wt, n, img, img_fs, ldi, out, out_fs); break;
-    case 4: hipLaunchKernelGGL((k_gather_sites<TS, 4>), grid, dim3(256), 0, st, g, anchor, Wt, n, img, img_fs, ldi, out, out_fs); break;
+    case 1: hipLaunchKernelGGL((k_gather_sites<TS, 1>), grid, dim3(256), 0, st, g, anchor, Wt, order, n, img, img_fs, ldi, out, out_fs); break;
+    case 2: hipLaunchKernelGGL((k_gather_sites<TS, 2>), grid, dim3(256), 0, st, g, anchor, Wt, order, n, img, img_fs, ldi, out, out_fs); break;
+    case 3: hipLaunchKernelGGL((k_gather_sites<TS, 3>), grid, dim3(256), 0, st, g, anchor, Wt, order, n, img, img_fs, ldi, out, out_fs); break;
+    case 4: hipLaunchKernelGGL((k_gather_sites<TS, 4>), grid, dim3(256), 0, st, g, anchor, Wt, order, n, img, img_fs, ldi, out, out_fs); break;
     default:  // L > 4: one thread per site and field, neighbours sixteen at a time
       hipLaunchKernelGGL(k_gather_generic<TS>, dim3((unsigned)((n + 255) / 256), B), dim3(256), 0, st, g, anchor, Wt,
-                         n, img, img_fs, ldi, out, out_fs);
+                         order, n, img, img_fs, ldi, out, out_fs);
       break;
   }
   return hipGetLastError();
 }
 
-hipError_t gather_sites(const GridDev& g, const int32_t* anchor, const double* Wt, int n, const void* img,
-                        int64_t img_fs, int64_t ldi, int B, int from_f32, double* out, int64_t out_fs,
-                        hipStream_t st) {
-  if (from_f32) return gather_launch<float>(g, anchor, Wt, n, (const float*)img, img_fs, ldi, B, out, out_fs, st);
-  return gather_launch<double>(g, anchor, Wt, n, (const double*)img, img_fs, ldi, B, out, out_fs, st);
+hipError_t gather_sites(const GridDev& g, const int32_t* anchor, const double* Wt, const int32_t* order, int n,
+                        const void* img, int64_t img_fs, int64_t ldi, int B, int from_f32, double* out,
+                        int64_t out_fs, hipStream_t st) {
+  if (from_f32)
+    return gather_launch<float>(g, anchor, Wt, order, n, (const float*)img, img_fs, ldi, B, out, out_fs, st);
+  return gather_launch<double>(g, anchor, Wt, order, n, (const double*)img, img_fs, ldi, B, out, out_fs, st);
 }
 
 // residual of conditional simulation: out[r][i] = y[i] - (u_r(s_i) + sd * xi_{r,i})
 template <typename TS>
 __global__ void k_csim_residual(GridDev g, const int32_t* __restrict__ anchor, const double* __restrict__ Wt,
-                                int n, const TS* __restrict__ img, int64_t img_fs, int64_t ldi,
-                                const double* __restrict__ y, double sd, uint32_t k0, uint32_t k1, int r0,
-                                double* __restrict__ out, int64_t out_fs) {
-  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+                                const int32_t* __restrict__ order, int n, const TS* __restrict__ img,
+                                int64_t img_fs, int64_t ldi, const double* __restrict__ y, double sd, uint32_t k0,
+                                uint32_t k1, int r0, double* __restrict__ out, int64_t out_fs) {
+  const int s = blockIdx.x * blockDim.x + threadIdx.x;
   const int r = blockIdx.y;
-  if (i >= n) return;
-  const double us = gather_one<TS>(g, anchor, Wt, n, i, img + (int64_t)r * img_fs, ldi);
+  if (s >= n) return;
+  const int i = order ? order[s] : s;
+  const double us = gather_one<TS>(g, anchor, Wt, n, s, i, img + (int64_t)r * img_fs, ldi);
   u32x4 c;
   c.v[0] = (uint32_t)i;
   c.v[1] = (uint32_t)(r0 + r);
@@ -510,17 +520,17 @@ __global__ void k_csim_residual(GridDev g, const int32_t* __restrict__ anchor, c
   box_muller_f64(w.v[0], w.v[1], n0, n1);
   out[(int64_t)r * out_fs + i] = y[i] - (us + sd * n0);
 }
-hipError_t csim_residual(const GridDev& g, const int32_t* anchor, const double* Wt, int n, const void* img,
-                         int64_t img_fs, int64_t ldi, int R, int from_f32, const double* y, double noise_sd,
-                         uint64_t seed, int r0, double* out, int64_t out_fs, hipStream_t st) {
+hipError_t csim_residual(const GridDev& g, const int32_t* anchor, const double* Wt, const int32_t* order, int n,
+                         const void* img, int64_t img_fs, int64_t ldi, int R, int from_f32, const double* y,
+                         double noise_sd, uint64_t seed, int r0, double* out, int64_t out_fs, hipStream_t st) {
   dim3 grid(nblk(n), R);
   const uint32_t k0 = (uint32_t)(seed & 0xFFFFFFFFu), k1 = (uint32_t)(seed >> 32);
   if (from_f32)
-    hipLaunchKernelGGL(k_csim_residual<float>, grid, dim3(256), 0, st, g, anchor, Wt, n, (const float*)img, img_fs,
-                       ldi, y, noise_sd, k0, k1, r0, out, out_fs);
-  else
-    hipLaunchKernelGGL(k_csim_residual<double>, grid, dim3(256), 0, st, g, anchor, Wt, n, (const double*)img,
+    hipLaunchKernelGGL(k_csim_residual<float>, grid, dim3(256), 0, st, g, anchor, Wt, order, n, (const float*)img,
                        img_fs, ldi, y, noise_sd, k0, k1, r0, out, out_fs);
+  else
+    hipLaunchKernelGGL(k_csim_residual<double>, grid, dim3(256), 0, st, g, anchor, Wt, order, n,
+                       (const double*)img, img_fs, ldi, y, noise_sd, k0, k1, r0, out, out_fs);
   return hipGetLastError();
 }
 
