@@ -791,7 +791,7 @@ def device_copy_gbs(torch, dev, mib=1024, reps=10):
 def main(argv=None):
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
-    ap.add_argument("--steps", type=int, default=20)
+    ap.add_argument("--steps", type=int, default=200)
     ap.add_argument("--warmup", type=int, default=200,
                     help="untimed steps first; about 40 ms of sustained work settles the GPU clocks")
     ap.add_argument("--B", type=int, default=16)
