@@ -180,12 +180,20 @@ def uneven(a, torch, krig, wl, dev):
                                   "[500, 20000], L in {2,3,4}, nu in {0.5,1.5,2.5}, range U[0.05,0.3], nugget 0.01",
                       "problems": len(ws), "grid_points": npred, "n_max": max(w.sites.shape[0] for w in ws)}}
     res = {}
+    # algorithmic bytes of one pass (one field per problem): the two FP64 triangles of every
+    # solve (n^2 / 2 doubles each) and the prediction's three transform passes in the survey's
+    # FP32-spectra model
+    tri_bytes, conv_bytes = 0, 0
     for dtype in (("f32",) if a.no_fp64 else ("f32", "f64")):
         torch.cuda.synchronize()
         t0 = time.perf_counter()
         plans = []
         for i, w in enumerate(ws):
             plans.append(krig.plan_for(w, dtype))
+            if dtype == "f32":
+                sb = stage_bytes(plans[-1], 1, "s8d")
+                tri_bytes += 8 * w.sites.shape[0] ** 2
+                conv_bytes += sb["ROWS_FWD"] + sb["COLS_CONV"] + sb["ROWS_INV"]
             if i % 8 == 7:
                 torch.cuda.synchronize()
                 print(f"[uneven] {dtype}: {i + 1} plans, {time.perf_counter() - t0:.1f} s", file=sys.stderr, flush=True)
@@ -268,6 +276,15 @@ def uneven(a, torch, krig, wl, dev):
                                                          "f64": r64["persistent_bitwise_equal"]},
                 "eager_ms_per_step": {"f32": r32["ms_eager"], "f64": r64["ms_eager"]},
                 "fp32_vs_fp64_rel_err": err,
+                # whole pass against HBM: the triangles dominate (every problem's factor is read
+                # once per solve, and the working set is far beyond the 256 MB last-level cache)
+                "roofline": {"bound": "hbm", "kernel": "whole pass (every problem's FP64 triangular products "
+                                                       "and transforms)",
+                             "achieved": (tri_bytes + conv_bytes) / (best(r32) * 1e-3) / 1e9, "peak": HBM_PEAK_GBS,
+                             "unit": "GB/s", "frac": (tri_bytes + conv_bytes) / (best(r32) * 1e-3) / 1e9 / HBM_PEAK_GBS,
+                             "traffic": None, "bytes_per_pass": tri_bytes + conv_bytes, "triangle_bytes": tri_bytes,
+                             "bytes_model": "two FP64 triangles of n^2/2 per solve; transforms in the FP32-spectra "
+                                            "model"},
                 "setup_s": {"f32": r32["setup_s"], "f64": r64["setup_s"]},
                 "autotune_s": {"f32": r32["tune_s"], "f64": r64["tune_s"]}})
     print(json.dumps(out), flush=True)
