@@ -434,8 +434,9 @@ int krig_plan_tune(krig_plan p, int32_t key, int64_t value);
  * the median of three windows of ten calls; a candidate replaces the current value
  * only when it is more than 1% faster.  The choice is recorded in a process-wide
  * table keyed by grid, neighbour order, transform lengths and dtype; plans created
- * later with the same key start from it.  Synchronises the plan's stream.  KRIG_EINVAL while stage timing is on or
- * a recorded batch holds the plan.
+ * later with the same key start from it (the scatter form only when they also have the
+ * same number of sites, since it follows the site density).  Synchronises the plan's
+ * stream.  KRIG_EINVAL while stage timing is on or a recorded batch holds the plan.
  */
 int krig_plan_autotune(krig_plan p, int32_t B, int32_t with_adjoint);
 

@@ -870,6 +870,7 @@ struct TuneKey {
 };
 struct TuneRec {
   int var_rows, var_cols, nl_rows64, nl_cols64, dlag_G, cols_pair;
+  int n, scatter_split;  // the scatter form depends on the site density: kept for plans of the same n
 };
 std::mutex& tune_mutex() {
   static std::mutex m;
@@ -894,6 +895,7 @@ void tuned_lookup(krig_plan p) {
   p->nl_cols64 = r.nl_cols64;
   p->dlag_G = r.dlag_G;
   p->cols_pair = p->e1h ? r.cols_pair : 0;
+  if (r.n == p->n) p->scatter_split = r.scatter_split;
 }
 
 }  // namespace
@@ -1896,7 +1898,8 @@ int krig_plan_autotune(krig_plan p, int32_t B, int32_t with_adjoint) {
   cleanup();
   {
     std::lock_guard<std::mutex> lk(tune_mutex());
-    tune_table()[tune_key(p)] = TuneRec{p->var_rows, p->var_cols, p->nl_rows64, p->nl_cols64, p->dlag_G, p->cols_pair};
+    tune_table()[tune_key(p)] =
+        TuneRec{p->var_rows, p->var_cols, p->nl_rows64, p->nl_cols64, p->dlag_G, p->cols_pair, p->n, p->scatter_split};
   }
   return KRIG_OK;
 }
