@@ -80,6 +80,7 @@ struct krig_plan_s {
   double* W = nullptr;
   double* Wt = nullptr;     // [M][n] transposed weights, columns in the gather order
   int32_t* gorder = nullptr; // [n] the gather order: sites sorted by anchor cell
+  int32_t* ganchor = nullptr; // [n][2] the anchors in that order (slot s: anchor of gorder[s])
   double* Wr = nullptr;     // [n][M] residual of the weight refinement
   int32_t* node_ptr = nullptr;
   int32_t* ent_site = nullptr;
@@ -564,7 +565,9 @@ int weights_from_kvec(krig_plan p, const double* d_kvec) {
 }
 
 // The gathers' site order: sites sorted by anchor cell (row-major over the cells; ties keep site
-// order), so that a wave's sites read neighbouring image windows.  From host anchors [n][2].
+// order), so that a wave's sites read neighbouring image windows, and the anchors in that order,
+// so that a gather reads its slot's anchor without first loading the site index.  From host
+// anchors [n][2].
 int set_gather_order(krig_plan p, const int32_t* h_anchor) {
   std::vector<int32_t> ord(p->n);
   for (int i = 0; i < p->n; ++i) ord[i] = i;
@@ -572,8 +575,14 @@ int set_gather_order(krig_plan p, const int32_t* h_anchor) {
   std::stable_sort(ord.begin(), ord.end(), [&](int32_t a, int32_t b) {
     return (int64_t)h_anchor[2 * a] * m2 + h_anchor[2 * a + 1] < (int64_t)h_anchor[2 * b] * m2 + h_anchor[2 * b + 1];
   });
+  std::vector<int32_t> ga(2 * (size_t)p->n);
+  for (int s = 0; s < p->n; ++s) {
+    ga[2 * s] = h_anchor[2 * ord[s]];
+    ga[2 * s + 1] = h_anchor[2 * ord[s] + 1];
+  }
   KRIG_TRY(hipMemcpyAsync(p->gorder, ord.data(), sizeof(int32_t) * p->n, hipMemcpyHostToDevice, p->st));
-  KRIG_TRY(hipStreamSynchronize(p->st));  // ord is freed on return
+  KRIG_TRY(hipMemcpyAsync(p->ganchor, ga.data(), sizeof(int32_t) * ga.size(), hipMemcpyHostToDevice, p->st));
+  KRIG_TRY(hipStreamSynchronize(p->st));  // ord and ga are freed on return
   return KRIG_OK;
 }
 
@@ -1239,6 +1248,7 @@ int krig_plan_create(krig_plan* out, const krig_grid* g, const krig_matern* k, i
   CK(dalloc(p, &p->W, (size_t)n * M));
   CK(dalloc(p, &p->Wt, (size_t)n * M));
   CK(dalloc(p, &p->gorder, (size_t)n));
+  CK(dalloc(p, &p->ganchor, 2 * (size_t)n));
   CK(dalloc(p, &p->Wr, (size_t)n * M));
   if (M <= 64)
     CKH(kn_factor(p->g, p->mt, p->KN, p->LinvN, p->d_status, p->st));
@@ -1655,7 +1665,7 @@ int krig_predict_adjoint(krig_plan p, int32_t B, const void* d_g, const double* 
   if (d_dy) {
     {
       StageTimer t(p, KRIG_STAGE_GATHER);
-      KRIG_TRY(gather_sites(p->g, p->anchor, p->Wt, p->gorder, p->n, p->img, (int64_t)p->P1 * p->P2, p->P2, B, 0, p->alpha,
+      KRIG_TRY(gather_sites(p->g, p->ganchor, p->Wt, p->gorder, p->n, p->img, (int64_t)p->P1 * p->P2, p->P2, B, 0, p->alpha,
                             p->n, p->st));
     }
     if ((r = do_solve(p, B, p->alpha, d_dy)) != KRIG_OK) return r;
@@ -1989,7 +1999,7 @@ int krig_csim(krig_plan p, int32_t R, uint64_t seed, const double* d_y, void* d_
   // residual of the data against the simulated data at the sites
   {
     StageTimer t(p, KRIG_STAGE_GATHER);
-    KRIG_TRY(csim_residual(p->g, p->anchor, p->Wt, p->gorder, p->n, p->csU, (int64_t)p->P1 * p->P2, p->P2, R, f32, d_y,
+    KRIG_TRY(csim_residual(p->g, p->ganchor, p->Wt, p->gorder, p->n, p->csU, (int64_t)p->P1 * p->P2, p->P2, R, f32, d_y,
                            sqrt(p->mt.tau2), seed, 0, p->csRes, p->n, p->st));
   }
   if ((r = do_solve(p, R, p->csRes, p->csAl)) != KRIG_OK) return r;

@@ -59,7 +59,9 @@ hipError_t scatter_image(const GridDev& g, const int32_t* node_ptr, const int32_
                          hipStream_t st);
 // out[b][i] = sum_m W[i][m] img[b][(i0+L+ox_m) * ldi + j0+L+oy_m] (FP64 accumulation, in the
 // order of m), with Wt the transposed weights in the gather order `order` (transpose_w; NULL:
-// the identity); the sites are visited in that order, each writing its own output.
+// the identity); the sites are visited in that order, each writing its own output.  `anchor`
+// holds the anchors (i0, j0) in the same order: slot s reads anchor[2s], anchor[2s + 1] and
+// writes site order[s].
 // csim_residual: out[r][i] = y[i] - (that + noise_sd * N(0,1) Philox noise of (i, r0 + r)).
 hipError_t gather_sites(const GridDev& g, const int32_t* anchor, const double* Wt, const int32_t* order, int n,
                         const void* img, int64_t img_fs, int64_t ldi, int B, int from_f32, double* out,

@@ -398,8 +398,8 @@ hipError_t scatter_image(const GridDev& g, const int32_t* node_ptr, const int32_
 // site i in gather slot s (its transposed weights are column s of Wt)
 template <typename TS>
 __device__ inline double gather_one(const GridDev& g, const int32_t* anchor, const double* Wt, int n, int s,
-                                    int i, const TS* im, int64_t ldi) {
-  const int i0 = anchor[2 * i], j0 = anchor[2 * i + 1];
+                                    const TS* im, int64_t ldi) {
+  const int i0 = anchor[2 * s], j0 = anchor[2 * s + 1];
   const int L2 = 2 * g.L;
   double acc = 0.0;
   // loads of sixteen neighbours are issued together; the sum runs in the order of m
@@ -440,8 +440,8 @@ __global__ void __launch_bounds__(256) k_gather_sites(GridDev g, const int32_t* 
   const int b = blockIdx.y;
   const bool ok = s < n;  // all four lanes of a site agree; no early exit before the shuffles
   const int ss = ok ? s : 0;
-  const int ii = order ? order[ss] : ss;
-  const TS* base = img + (int64_t)b * img_fs + (int64_t)(anchor[2 * ii] + L) * ldi + (anchor[2 * ii + 1] + L);
+  const int ii = order ? order[ss] : ss;  // needed only for the store
+  const TS* base = img + (int64_t)b * img_fs + (int64_t)(anchor[2 * ss] + L) * ldi + (anchor[2 * ss + 1] + L);
   double wv[PER], iv[PER];
 #pragma unroll
   for (int u = 0; u < PER; ++u) {
@@ -470,7 +470,7 @@ __global__ void __launch_bounds__(256) k_gather_generic(GridDev g, const int32_t
   const int b = blockIdx.y;
   if (s >= n) return;
   const int i = order ? order[s] : s;
-  out[(int64_t)b * out_fs + i] = gather_one<TS>(g, anchor, Wt, n, s, i, img + (int64_t)b * img_fs, ldi);
+  out[(int64_t)b * out_fs + i] = gather_one<TS>(g, anchor, Wt, n, s, img + (int64_t)b * img_fs, ldi);
 }
 
 template <typename TS>
@@ -509,7 +509,7 @@ __global__ void k_csim_residual(GridDev g, const int32_t* __restrict__ anchor, c
   const int r = blockIdx.y;
   if (s >= n) return;
   const int i = order ? order[s] : s;
-  const double us = gather_one<TS>(g, anchor, Wt, n, s, i, img + (int64_t)r * img_fs, ldi);
+  const double us = gather_one<TS>(g, anchor, Wt, n, s, img + (int64_t)r * img_fs, ldi);
   u32x4 c;
   c.v[0] = (uint32_t)i;
   c.v[1] = (uint32_t)(r0 + r);
