@@ -201,7 +201,7 @@ struct FftGeo {
   int NT;           // threads per line
   int ON2;          // odd stride between the R3 rows of an inner exchange
   int RS;           // odd size of one inner exchange region
-  int P1;           // row stride of the pass-1 exchange (M + 1)
+  int P1;           // row stride of the pass-1 exchange (at least M, = R3 mod 16)
   int EX;           // LDS slots per line for the exchanges
   int ROWS;         // row kernels: exchanges, natural-order pairing or transpose
 };
@@ -221,7 +221,10 @@ __host__ __device__ constexpr FftGeo fft_geo(int R1, int R2, int R3) {
   g.NT = imax(imax(g.TIN, g.T2), g.TOUT);
   g.ON2 = odd_up(R2);
   g.RS = odd_up(R3 * g.ON2);
-  g.P1 = g.M + 1;
+  // P1 = R3 (mod 16): the middle pass's lane t2 = (k1, s) = (t2 / R3, t2 mod R3) reads slot
+  // k1 P1 + R3 n1 + s, which is t2 mod 16 plus a constant, so sixteen consecutive lanes use
+  // sixteen different bank groups of 16 bytes (M + 1 put two rows one slot apart)
+  g.P1 = g.M + ((g.R3 - g.M) % 16 + 16) % 16;
   g.EX = R1 > 1 ? imax(R1 * g.P1, R1 * g.RS) : g.RS;
   g.ROWS = imax(g.EX, g.F + 2);
   return g;
