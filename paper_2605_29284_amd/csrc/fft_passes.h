@@ -402,8 +402,8 @@ __device__ __forceinline__ void col_fwd(const Spec<TS> src, int in_off, int in_c
 enum { COL_CONV = 0, COL_CONV_DLAG = 1, COL_FWD_REAL = 2, COL_INV_SUM = 3, COL_CE = 4 };
 
 // The lag-gradient column pass (two forward transforms and an inverse per line) of the
-// same forms needs just over 168 VGPRs.  Capped at three waves per SIMD it spills a few
-// dozen bytes per lane and still runs faster than uncapped at two waves; a four-wave cap
+// same forms needs 160 VGPRs: three waves per SIMD without scratch (it loads its filter values
+// and inverse twiddle bases late for that), faster than uncapped at two waves; a four-wave cap
 // (over 200 bytes of scratch) runs at half speed.  The plain convolution pass keeps the
 // default (four waves): a five-wave cap made it spill and run slower.
 template <int R1, int R2, int R3, int MODE> struct ColCap {
